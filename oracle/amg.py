@@ -1,0 +1,458 @@
+"""Sec. 3.2 of the paper: the multigrid-reduction hierarchy (AMGR) built on
+the shared inner block A_inn, and its V-cycle (Alg. 3).
+
+Readings taken where the paper names a method without defining it (each is
+listed with its reason in the design notes):
+  * strength: classical, S_i = {j != i : -a_ij >= theta * max_{l != i} -a_il},
+    symmetrised to the graph T = S u S^T (Alg. 2, first two steps);
+  * "maximum independent set" = the lexicographically-first maximal
+    independent set under hash priorities (Alg. 2, fourth step);
+  * level 0 (the reduction): independent set of T^d taken inside the inner
+    (non-interface) nodes, coarse set = MIS u interface (Alg. 2, last step);
+    levels >= 1: independent set of T (distance 1) with PMIS-style priorities
+    (number of strong dependants, then hash);
+  * interpolation: the ideal interpolation -A_FF^{-1} A_FC truncated after a
+    few Jacobi steps, with symbolic patterns, rows rescaled to the direct
+    interpolation row sum; P = [W; I] (eq. (3.11));
+  * smoother: static-pattern FSAI, block-diagonal over F/C at level 0
+    (eq. (3.12)), damped by 4/(3 lambda_max(G A G^T));
+  * reduced operator A_c = P^T A P (eq. (3.13)), symbolic pattern;
+  * coarsest level: dense Cholesky.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .splitmix import splitmix64, unit_centered
+
+
+# ---------------------------------------------------------------------------
+# sparse helpers (structure-preserving)
+# ---------------------------------------------------------------------------
+
+def _ones_like(A: sp.csr_matrix) -> sp.csr_matrix:
+    return sp.csr_matrix((np.ones(A.nnz), A.indices.copy(), A.indptr.copy()), shape=A.shape)
+
+
+def _keys(A: sp.csr_matrix) -> np.ndarray:
+    rows = np.repeat(np.arange(A.shape[0], dtype=np.int64), np.diff(A.indptr))
+    return rows * np.int64(A.shape[1]) + A.indices.astype(np.int64)
+
+
+def embed(values: sp.csr_matrix, pattern: sp.csr_matrix) -> sp.csr_matrix:
+    """Return a matrix with the structure of ``pattern`` holding the entries
+    of ``values`` (absent entries become explicit zeros).  Requires
+    structure(values) to be a subset of structure(pattern)."""
+    values = values.tocsr()
+    values.sort_indices()
+    pattern = pattern.tocsr()
+    pattern.sort_indices()
+    kp = _keys(pattern)
+    kv = _keys(values)
+    pos = np.searchsorted(kp, kv)
+    if kv.size and (pos.max() >= kp.size or np.any(kp[pos] != kv)):
+        raise AssertionError("values outside the symbolic pattern")
+    data = np.zeros(pattern.nnz)
+    data[pos] = values.data
+    return sp.csr_matrix((data, pattern.indices.copy(), pattern.indptr.copy()), shape=pattern.shape)
+
+
+def sym_matmul(A: sp.csr_matrix, B: sp.csr_matrix) -> sp.csr_matrix:
+    """A @ B with the *structural* pattern (every reachable (i, j) is kept,
+    exact cancellations included as explicit zeros)."""
+    pat = (_ones_like(A) @ _ones_like(B)).tocsr()
+    val = (A @ B).tocsr()
+    return embed(val, pat)
+
+
+def sym_add(A: sp.csr_matrix, B: sp.csr_matrix) -> sp.csr_matrix:
+    pat = (_ones_like(A) + _ones_like(B)).tocsr()
+    val = (A + B).tocsr()
+    val.eliminate_zeros()
+    return embed(val, pat)
+
+
+def lookup(A: sp.csr_matrix, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
+    """A[rows, cols] elementwise (0 where not stored); A sorted CSR."""
+    k = _keys(A)
+    q = rows.astype(np.int64) * np.int64(A.shape[1]) + cols.astype(np.int64)
+    pos = np.searchsorted(k, q)
+    pos = np.minimum(pos, k.size - 1)
+    hit = k[pos] == q
+    out = np.where(hit, A.data[pos], 0.0)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2 steps 1-2: strength of connection and the filtered graph T
+# ---------------------------------------------------------------------------
+
+def strength(A: sp.csr_matrix, theta: float) -> sp.csr_matrix:
+    """Classical strength: j in S_i iff j != i and -a_ij >= theta*max_{l!=i}(-a_il);
+    S_i is empty when that maximum is <= 0.  Returns a 0/1 CSR matrix S
+    with S[i, j] = 1 for j in S_i.  theta*max is one FP64 multiply and the
+    comparison is exact."""
+    A = A.tocsr()
+    n = A.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(A.indptr))
+    off = A.indices != rows
+    neg = -A.data
+    negoff = np.where(off, neg, -np.inf)
+    mx = np.full(n, -np.inf)
+    np.maximum.at(mx, rows, negoff)
+    thr = theta * mx
+    strong = off & (mx[rows] > 0) & (neg >= thr[rows])
+    S = sp.csr_matrix((np.ones(int(strong.sum())), (rows[strong], A.indices[strong])), shape=(n, n))
+    S.sort_indices()
+    return S
+
+
+def symmetrise(S: sp.csr_matrix) -> sp.csr_matrix:
+    """T = S u S^T as a 0/1 matrix."""
+    T = (_ones_like(S) + _ones_like(S).T).tocsr()
+    T.data[:] = 1.0
+    T.sort_indices()
+    return T
+
+
+def distance_graph(T: sp.csr_matrix, d: int) -> sp.csr_matrix:
+    """Symbolic power: i ~ j iff 1 <= dist_T(i, j) <= d (Alg. 2, step 3)."""
+    n = T.shape[0]
+    I = sp.identity(n, format="csr")
+    R = (I + _ones_like(T)).tocsr()
+    Rk = R.copy()
+    for _ in range(d - 1):
+        Rk = (Rk @ R).tocsr()
+    Rk.data[:] = 1.0
+    Rk = Rk - sp.diags(Rk.diagonal())
+    Rk = Rk.tocsr()
+    Rk.eliminate_zeros()
+    Rk.sort_indices()
+    return Rk
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2 step 4: independent sets
+# ---------------------------------------------------------------------------
+
+def mis_greedy(G: sp.csr_matrix, rank: np.ndarray) -> np.ndarray:
+    """Lexicographically-first maximal independent set of graph G under
+    decreasing ``rank`` (distinct integers): scan the nodes by decreasing rank
+    and take a node when none of its neighbours has been taken.  Pure Python
+    loop; for small graphs."""
+    n = G.shape[0]
+    taken = np.zeros(n, dtype=bool)
+    for i in np.argsort(-np.asarray(rank, dtype=np.int64), kind="stable"):
+        nb = G.indices[G.indptr[i]:G.indptr[i + 1]]
+        if not taken[nb].any():
+            taken[i] = True
+    return taken
+
+
+def mis_rounds(G: sp.csr_matrix, rank: np.ndarray) -> np.ndarray:
+    """The same set by rounds: every undecided node whose rank beats all its
+    undecided neighbours is taken, then its undecided neighbours are removed.
+    Adjacency stays that of the fixed graph G (removal does not shorten or
+    lengthen any distance)."""
+    n = G.shape[0]
+    rank = np.asarray(rank, dtype=np.int64)
+    state = np.zeros(n, dtype=np.int8)      # 0 undecided, 1 taken, -1 removed
+    rows = np.repeat(np.arange(n), np.diff(G.indptr))
+    cols = G.indices
+    while np.any(state == 0):
+        und = state == 0
+        live = und[rows] & und[cols]
+        best = np.full(n, -1, dtype=np.int64)
+        np.maximum.at(best, rows[live], rank[cols[live]])
+        sel = und & (rank > best)
+        state[sel] = 1
+        nb = cols[sel[rows]]
+        nb = nb[state[nb] == 0]
+        state[nb] = -1
+    return state == 1
+
+
+def priorities_level0(n: int, seed: int) -> np.ndarray:
+    """Hash priorities pi_i = splitmix64(seed xor i)."""
+    return splitmix64(np.uint64(seed) ^ np.arange(n, dtype=np.uint64))
+
+
+def priorities_coarse(S: sp.csr_matrix, level: int, seed: int) -> np.ndarray:
+    """PMIS-style priorities: (#{j : i in S_j}, splitmix64(seed xor (level<<40)
+    xor i)) compared lexicographically; returned as dense ranks (int64)."""
+    n = S.shape[0]
+    lam = np.asarray(_ones_like(S).sum(axis=0)).ravel().astype(np.int64)
+    h = splitmix64(np.uint64(seed) ^ (np.uint64(level) << np.uint64(40)) ^ np.arange(n, dtype=np.uint64))
+    order = np.lexsort((h, lam))            # increasing (lam, h)
+    rank = np.empty(n, dtype=np.int64)
+    rank[order] = np.arange(n)
+    return rank
+
+
+def coarsen_level0(A: sp.csr_matrix, interface: np.ndarray, theta: float, d: int, seed: int,
+                   method: str = "rounds") -> np.ndarray:
+    """Alg. 2 (populated coarsening at interpolation distance d): coarse set
+    = MIS(T^d restricted to inner nodes) disjoint-union interface.  Returns a
+    boolean C mask."""
+    n = A.shape[0]
+    S = strength(A, theta)
+    T = symmetrise(S)
+    inner = np.flatnonzero(~interface)
+    Tin = T[inner][:, inner].tocsr()
+    Gd = distance_graph(Tin, d)
+    pri = priorities_level0(n, seed)[inner]
+    rank = np.empty(inner.size, dtype=np.int64)
+    rank[np.argsort(pri)] = np.arange(inner.size)
+    mis = mis_greedy(Gd, rank) if method == "greedy" else mis_rounds(Gd, rank)
+    C = interface.copy()
+    C[inner[mis]] = True
+    return C
+
+
+def coarsen_standard(A: sp.csr_matrix, level: int, theta: float, seed: int,
+                     method: str = "rounds") -> np.ndarray:
+    """Levels below the reduction: C = MIS of T (distance 1)."""
+    S = strength(A, theta)
+    T = symmetrise(S)
+    rank = priorities_coarse(S, level, seed)
+    return mis_greedy(T, rank) if method == "greedy" else mis_rounds(T, rank)
+
+
+# ---------------------------------------------------------------------------
+# interpolation, P = [W; I] (eq. (3.11))
+# ---------------------------------------------------------------------------
+
+def interpolation(A: sp.csr_matrix, C: np.ndarray, steps: int) -> sp.csr_matrix:
+    """Jacobi-truncated ideal interpolation (parity reading of the cited long
+    distance schemes): W1 = -D^{-1} A_FC, W_{t+1} = -D^{-1}(A_FC + O W_t) with
+    D = diag(A_FF), O = A_FF - D, symbolic patterns.  Each F row with nonzero
+    sum is rescaled to rho_i = -sum_{l != i} a_il / a_ii.  Returns P (n x n_c),
+    coarse unknowns numbered by increasing fine index."""
+    A = A.tocsr()
+    n = A.shape[0]
+    F = ~C
+    fidx = np.flatnonzero(F)
+    cidx = np.flatnonzero(C)
+    nc = cidx.size
+    AF = A[fidx].tocsr()
+    AFF = AF[:, fidx].tocsr()
+    AFC = AF[:, cidx].tocsr()
+    AFF.sort_indices()
+    AFC.sort_indices()
+    Dv = AFF.diagonal()
+    Dinv = sp.diags(1.0 / Dv)
+    # O = A_FF without its diagonal (structure of the off-diagonal part)
+    rows = np.repeat(np.arange(fidx.size), np.diff(AFF.indptr))
+    keep = AFF.indices != rows
+    O = sp.csr_matrix((AFF.data[keep], (rows[keep], AFF.indices[keep])), shape=AFF.shape)
+    O.sort_indices()
+    W = embed(-(Dinv @ AFC), AFC)
+    for _ in range(steps - 1):
+        inner = sym_add(AFC, sym_matmul(O, W))
+        W = embed(-(Dinv @ inner), inner)
+    # row rescaling to the direct-interpolation row sum
+    diagA = A.diagonal()
+    rowsA = np.repeat(np.arange(n), np.diff(A.indptr))
+    offsum = np.zeros(n)
+    np.add.at(offsum, rowsA[A.indices != rowsA], A.data[A.indices != rowsA])
+    rho = -offsum[fidx] / diagA[fidx]
+    wsum = np.asarray(W.sum(axis=1)).ravel()
+    scale = np.where(wsum != 0.0, rho / np.where(wsum != 0.0, wsum, 1.0), 1.0)
+    W = sp.csr_matrix((W.data * np.repeat(scale, np.diff(W.indptr)), W.indices, W.indptr), shape=W.shape)
+    # assemble P in fine-row order
+    cnum = -np.ones(n, dtype=np.int64)
+    cnum[cidx] = np.arange(nc)
+    prow = []
+    pcol = []
+    pval = []
+    Wr = np.repeat(fidx, np.diff(W.indptr))
+    prow.append(Wr)
+    pcol.append(W.indices.astype(np.int64))
+    pval.append(W.data)
+    prow.append(cidx)
+    pcol.append(np.arange(nc))
+    pval.append(np.ones(nc))
+    prow = np.concatenate(prow)
+    pcol = np.concatenate(pcol)
+    pval = np.concatenate(pval)
+    order = np.lexsort((pcol, prow))
+    counts = np.bincount(prow, minlength=n)
+    indptr = np.concatenate([[0], np.cumsum(counts)])
+    P = sp.csr_matrix((pval[order], pcol[order], indptr), shape=(n, nc))
+    return P
+
+
+def galerkin(A: sp.csr_matrix, P: sp.csr_matrix) -> sp.csr_matrix:
+    """Reduced operator A_c = P^T A P (eq. (3.13)), symbolic pattern,
+    computed as R (A P) with R = P^T."""
+    R = P.T.tocsr()
+    R.sort_indices()
+    AP = sym_matmul(A, P)
+    return sym_matmul(R, AP)
+
+
+# ---------------------------------------------------------------------------
+# FSAI smoother (eq. (2.15) factor; block form eq. (3.12))
+# ---------------------------------------------------------------------------
+
+def fsai_pattern(S: sp.csr_matrix, block: np.ndarray):
+    """Row patterns J_i = {j < i : j in S_i, block_j == block_i} + [i], sorted."""
+    n = S.shape[0]
+    pats = []
+    for i in range(n):
+        nb = S.indices[S.indptr[i]:S.indptr[i + 1]]
+        nb = nb[(nb < i) & (block[nb] == block[i])]
+        pats.append(np.concatenate([np.sort(nb), [i]]).astype(np.int64))
+    return pats
+
+
+def fsai(A: sp.csr_matrix, S: sp.csr_matrix, block: np.ndarray) -> sp.csr_matrix:
+    """Static-pattern factorised sparse approximate inverse: for each row i,
+    solve A[J_i, J_i] g = e_last and scale g by 1/sqrt(g_last), so that
+    G A G^T has unit diagonal and G^T G ~ A^{-1}.  Rows are grouped by
+    pattern size and solved with batched dense solves."""
+    A = A.tocsr()
+    A.sort_indices()
+    n = A.shape[0]
+    # vectorised pattern construction
+    rows = np.repeat(np.arange(n), np.diff(S.indptr))
+    cols = S.indices
+    keep = (cols < rows) & (block[cols] == block[rows])
+    pr = np.concatenate([rows[keep], np.arange(n)])
+    pc = np.concatenate([cols[keep], np.arange(n)])
+    order = np.lexsort((pc, pr))
+    pr, pc = pr[order], pc[order]
+    counts = np.bincount(pr, minlength=n)
+    indptr = np.concatenate([[0], np.cumsum(counts)])
+    gval = np.empty(pr.size)
+    for k in np.unique(counts):
+        rws = np.flatnonzero(counts == k)
+        J = pc[indptr[rws][:, None] + np.arange(k)[None, :]]       # (nr, k), last = i
+        M = lookup(A, np.repeat(J, k, axis=1).ravel(), np.tile(J, (1, k)).ravel()).reshape(-1, k, k)
+        e = np.zeros((rws.size, k))
+        e[:, -1] = 1.0
+        g = np.linalg.solve(M, e[:, :, None])[:, :, 0]
+        g = g / np.sqrt(g[:, -1:])
+        gval[indptr[rws][:, None] + np.arange(k)[None, :]] = g
+    G = sp.csr_matrix((gval, pc, indptr), shape=(n, n))
+    return G
+
+
+def damping(A: sp.csr_matrix, G: sp.csr_matrix, seed: int, iters: int = 20) -> float:
+    """omega = 4 / (3 lam), lam from `iters` power iterations on G A G^T started
+    at v_i = splitmix64(seed xor i)/2^64 - 1/2; lam is the Rayleigh quotient
+    v^T (G A G^T) v of the last normalised iterate."""
+    n = A.shape[0]
+    v = unit_centered(np.uint64(seed) ^ np.arange(n, dtype=np.uint64))
+    v = v / np.linalg.norm(v)
+    lam = 0.0
+    GT = G.T.tocsr()
+    for _ in range(iters):
+        w = G @ (A @ (GT @ v))
+        lam = float(v @ w)
+        v = w / np.linalg.norm(w)
+    return 4.0 / (3.0 * lam)
+
+
+# ---------------------------------------------------------------------------
+# hierarchy and V-cycle (Alg. 3)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Level:
+    A: sp.csr_matrix
+    C: Optional[np.ndarray] = None
+    P: Optional[sp.csr_matrix] = None
+    R: Optional[sp.csr_matrix] = None
+    G: Optional[sp.csr_matrix] = None
+    omega: float = 0.0
+
+
+@dataclasses.dataclass
+class Hierarchy:
+    levels: List[Level]
+    coarse_factor: tuple = None        # cho_factor of the coarsest matrix
+
+    @property
+    def nlev(self):
+        return len(self.levels)
+
+    def stats(self):
+        rows = [L.A.shape[0] for L in self.levels]
+        nnz = [L.A.nnz for L in self.levels]
+        return dict(rows=rows, nnz=nnz, op_complexity=sum(nnz) / nnz[0],
+                    c_rat=(rows[1] / rows[0]) if len(rows) > 1 else 1.0,
+                    avg_nnzr=(nnz[1] / rows[1]) if len(rows) > 1 else nnz[0] / rows[0])
+
+
+@dataclasses.dataclass
+class AMGOptions:
+    theta: float = 0.25
+    dist: int = 2
+    jacobi0: int = 2          # interpolation steps at the reduction level
+    jacobi: int = 1           # interpolation steps below it
+    coarse_max: int = 1024
+    max_levels: int = 20
+    max_ratio: float = 0.8
+    seed: int = 240705930
+    mis_method: str = "rounds"
+
+
+def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions) -> Hierarchy:
+    """AMGR on the shared inner block: level 0 is the multigrid reduction of
+    Sec. 3.2 (Alg. 2 coarsening with the interface forced coarse, P = [W; I],
+    block-FSAI smoother), levels below are standard AMG on the reduced
+    operator, the last level is solved densely."""
+    levels = []
+    A = Ainn.tocsr()
+    A.sort_indices()
+    lev = 0
+    while True:
+        L = Level(A=A)
+        levels.append(L)
+        n = A.shape[0]
+        if n <= opt.coarse_max or lev == opt.max_levels - 1:
+            break
+        if lev == 0:
+            C = coarsen_level0(A, interface, opt.theta, opt.dist, opt.seed, opt.mis_method)
+            steps = opt.jacobi0
+        else:
+            C = coarsen_standard(A, lev, opt.theta, opt.seed, opt.mis_method)
+            steps = opt.jacobi
+        nc = int(C.sum())
+        if nc == 0 or nc > opt.max_ratio * n:
+            break
+        S = strength(A, opt.theta)
+        block = C.astype(np.int64) if lev == 0 else np.zeros(n, dtype=np.int64)
+        L.C = C
+        L.G = fsai(A, S, block)
+        L.omega = damping(A, L.G, opt.seed)
+        L.P = interpolation(A, C, steps)
+        L.R = L.P.T.tocsr()
+        L.R.sort_indices()
+        A = galerkin(A, L.P)
+        lev += 1
+    Ad = levels[-1].A.toarray()
+    factor = sla.cho_factor(Ad, lower=True)
+    return Hierarchy(levels=levels, coarse_factor=factor)
+
+
+def vcycle(H: Hierarchy, y: np.ndarray, lev: int = 0) -> np.ndarray:
+    """Alg. 3 with nu1 = nu2 = 1 and smoother M = omega G^T G:
+    s = M y; r = y - A s; h_c = V(R r); s += P h_c; s += M (y - A s).
+    ``y`` may hold several columns."""
+    if lev == H.nlev - 1:
+        return sla.cho_solve(H.coarse_factor, y)
+    L = H.levels[lev]
+    GT = L.G.T
+    s = L.omega * (GT @ (L.G @ y))
+    r = y - L.A @ s
+    hc = vcycle(H, L.R @ r, lev + 1)
+    s = s + L.P @ hc
+    s = s + L.omega * (GT @ (L.G @ (y - L.A @ s)))
+    return s
