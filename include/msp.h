@@ -1,0 +1,160 @@
+/*
+ * msp.h -- mirror-symmetric Poisson solver for AMD Instinct MI355X (gfx950).
+ *
+ * C interface of the library that solves A x = b for a symmetric positive
+ * definite matrix A whose unknowns carry s mirror symmetries, following
+ * arXiv 2407.05930 ("A multigrid reduction framework for domains with
+ * symmetries"):
+ *
+ *   setup (Sec. 2, eqs. (2.4)-(2.6) and the text after them): the caller
+ *     passes the full matrix and the symmetry map; the library extracts the
+ *     base-mesh blocks H_j, checks the block structure "block (a,b) of A =
+ *     H_{a xor b}" bit for bit, keeps only the shared inner block
+ *     A_inn = H_0 plus the per-subsystem outer part (eq. (2.11)), and builds
+ *     one preconditioner shared by all 2^s subsystems: the multigrid
+ *     reduction hierarchy of Sec. 3.2 (Alg. 2, eqs. (3.11)-(3.13)) on A_inn,
+ *     or the FSAI of A_inn (eq. (2.15)), optionally with per-subsystem
+ *     low-rank corrections (LRCAMG(k), eq. (2.27); LRCFSAI(k), eq. (2.20)).
+ *   solve (Alg. 1): bhat = Q_s b, decoupled PCG on every subsystem and
+ *     right-hand side with the shared preconditioner applied to all
+ *     2^s * m columns at once (SpMM, eqs. (2.7)-(2.8)), x = Q_s xhat.
+ *
+ * Conventions
+ *   - Matrices are CSR with 64-bit row pointers and 32-bit column indices,
+ *     FP64 values, 0-based.  Rows need not be sorted; duplicates are an error.
+ *   - The symmetry map is img[i * 2^s + a] = row of image a of base cell i,
+ *     for 0 <= i < n_b = n / 2^s and 0 <= a < 2^s.  Bit t of a means
+ *     "reflected about mirror plane t"; images compose by XOR; a = 0 is the
+ *     base mesh.  It must be a permutation of 0..n-1.
+ *   - Right-hand sides and solutions are n x m column-major arrays
+ *     (element (row g, rhs j) at [j * n + g]).  2^s * m must not exceed 64.
+ *   - Every function returns an msp_status; no C++ exception crosses the
+ *     interface.  msp_last_error() returns a thread-local message for the
+ *     last failing call on that thread.
+ *   - The caller owns every array it passes; setup copies what it needs.
+ *     A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef MSP_H
+#define MSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSP_OK = 0,
+    MSP_NOT_CONVERGED = 1,       /* maxit reached; x holds the last iterate */
+    MSP_ERR_ARG = -1,            /* bad argument (null, size, layout) */
+    MSP_ERR_NOT_SYMMETRIC = -2,  /* A != A^T, or A inconsistent with the map */
+    MSP_ERR_BAD_MAP = -3,        /* map is not a permutation */
+    MSP_ERR_BREAKDOWN = -4,      /* PCG: p^T A p <= 0 or a non-finite value */
+    MSP_ERR_HIP = -5,            /* HIP runtime error */
+    MSP_ERR_OOM = -6,            /* host or device allocation failed */
+    MSP_ERR_NOT_SPD = -7,        /* a dense Cholesky factorisation failed */
+    MSP_ERR_UNSUPPORTED = -8     /* input outside what this build handles */
+} msp_status;
+
+enum { MSP_FP64 = 0, MSP_MIXED_FP32 = 1, MSP_MIXED_FP32_BF16G = 2 };
+enum { MSP_PC_AMGR = 0, MSP_PC_FSAI = 1, MSP_PC_NONE = 2 };
+
+typedef struct msp_ctx msp_ctx;
+
+/* Full matrix A (host memory). */
+typedef struct {
+    int64_t n;
+    const int64_t* rowptr;   /* n + 1 */
+    const int32_t* col;      /* rowptr[n] */
+    const double* val;       /* rowptr[n] */
+} msp_csr;
+
+/* Symmetry map (host memory). */
+typedef struct {
+    int32_t s;               /* number of mirror symmetries, 0..6 */
+    int64_t n_b;             /* base-mesh unknowns, n = n_b << s */
+    const int64_t* img;      /* n_b * 2^s */
+} msp_symmap;
+
+typedef struct {
+    int32_t precision;   /* MSP_FP64 | MSP_MIXED_FP32 | MSP_MIXED_FP32_BF16G */
+    int32_t pc;          /* MSP_PC_AMGR | MSP_PC_FSAI | MSP_PC_NONE */
+    int32_t lrc_k;       /* low-rank correction rank per subsystem, >= 0 */
+    int32_t dist;        /* interpolation distance d of Alg. 2 (>= 1) */
+    double theta;        /* strength threshold */
+    int32_t jacobi0;     /* interpolation smoothing steps at the reduction level */
+    int32_t jacobi;      /* interpolation smoothing steps below it */
+    int32_t coarse_max;  /* a level with at most this many rows is solved densely */
+    int32_t max_levels;
+    double max_ratio;    /* stop coarsening when n_{l+1} > max_ratio * n_l */
+    double tol;          /* per right-hand side, ||b - A x|| <= tol ||b|| */
+    int32_t maxit;
+    int32_t device;      /* HIP device ordinal; -1 = host-only setup (no solve) */
+    uint64_t seed;       /* seed of the hash priorities and start vectors */
+} msp_opts;
+
+typedef struct {
+    int32_t iters;               /* PCG iterations of the slowest column */
+    int32_t status;
+    double relres[64];           /* recursive-residual bound per RHS (m <= 64) */
+    int32_t nlev;
+    int64_t rows[32];
+    int64_t nnz[32];
+    double op_complexity;        /* sum_l nnz(A_l) / nnz(A_0) */
+    double c_rat;                /* n_1 / n_0 */
+    double avg_nnzr;             /* nnz(A_1) / n_1 */
+    double t_setup_s;
+    double t_solve_s;
+} msp_stats;
+
+/* Fill *o with the defaults: FP64, AMGR, k = 0, d = 2, theta = 0.25,
+   jacobi0 = 2, jacobi = 1, coarse_max = 1024, max_levels = 20,
+   max_ratio = 0.8, tol = 1e-10, maxit = 1000, device = 0, seed = 240705930. */
+int msp_default_opts(msp_opts* o);
+
+/* Build a context from A and its symmetry map.  Validates the map
+   (MSP_ERR_BAD_MAP) and the exact block structure and symmetry
+   (MSP_ERR_NOT_SYMMETRIC); outer blocks H_j, j != 0, must be diagonal
+   (two-point stencils; otherwise MSP_ERR_UNSUPPORTED).  With device >= 0 the
+   hierarchy is uploaded to that GPU and low-rank corrections are computed
+   there.  On success *out owns all library memory until msp_free. */
+int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ctx** out);
+
+/* Solve for m right-hand sides held in device memory (d_b, d_x: n x m
+   column-major FP64, on the context's device), enqueued on hip_stream (NULL
+   = the default stream).  Returns when the solve has finished.
+   st may be NULL. */
+int msp_solve_device(msp_ctx* c, int32_t m, const double* d_b, double* d_x, void* hip_stream,
+                     msp_stats* st);
+
+/* Same with host arrays (copies in and out). */
+int msp_solve(msp_ctx* c, int32_t m, const double* b, double* x, msp_stats* st);
+
+/* Hierarchy introspection (works for host-only contexts). */
+int msp_get_stats(const msp_ctx* c, msp_stats* st);
+int msp_num_levels(const msp_ctx* c, int32_t* nlev);
+/* Sizes of level lev: rows, nnz(A_lev), nnz(P_lev), nnz(G_lev) (0 on the
+   coarsest level, which has no P and G). */
+int msp_level_sizes(const msp_ctx* c, int32_t lev, int64_t* n, int64_t* nnz_A, int64_t* nnz_P,
+                    int64_t* nnz_G);
+/* Copy level lev into caller arrays sized from msp_level_sizes.  Any
+   pointer may be NULL to skip that part.  cf[i] = 1 for coarse rows;
+   P is n x n_{lev+1}; G is the lower-triangular smoother factor;
+   omega its damping.  Rows are sorted by column. */
+int msp_export_level(const msp_ctx* c, int32_t lev, int8_t* cf, int64_t* A_rp, int32_t* A_ci,
+                     double* A_v, int64_t* P_rp, int32_t* P_ci, double* P_v, int64_t* G_rp,
+                     int32_t* G_ci, double* G_v, double* omega);
+/* Outer part: sigma[i * 2^s + a] (diagonal of A_out,a) and the interface
+   mask (1 for base cells coupled to another image). */
+int msp_export_outer(const msp_ctx* c, double* sigma, int8_t* interface_mask);
+/* Low-rank corrections: number kept per subsystem (kept[a]) and the Ritz
+   values found (ritz[a * k + t], k = lrc_k, ascending). */
+int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz);
+
+void msp_free(msp_ctx* c);
+const char* msp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSP_H */

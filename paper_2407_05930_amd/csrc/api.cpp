@@ -1,0 +1,556 @@
+// C interface, device context and the solve driver (Alg. 1 with per-column
+// PCG; the shared preconditioner applied to every column at once).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace msp {
+
+static thread_local std::string g_last_error;
+
+#define HIPCHECK(expr)                                                                                 \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            throw msp::Error(e_ == hipErrorOutOfMemory ? MSP_ERR_OOM : MSP_ERR_HIP,                    \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                            \
+    } while (0)
+
+// Device CSR: 32-bit row pointers and columns, FP64 and (mixed modes) FP32 values.
+struct DevCsr {
+    int64_t nr = 0, nc = 0, nnz = 0;
+    int32_t* rp = nullptr;
+    int32_t* ci = nullptr;
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+};
+
+struct DevLevel {
+    DevCsr A, P, R, G, GT;
+    double omega = 0.0;
+    int64_t n = 0;
+};
+
+// Column-count-dependent workspace.
+struct Work {
+    int C = 0;
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *zold = nullptr;
+    std::vector<void*> vy, vs, vr, vt;    // per level, element type of the V-cycle
+    double* partial = nullptr;
+    int nb_dot = 0;
+    double* scal = nullptr;   // 10 arrays of 64
+    int* iscal = nullptr;     // active[64], iters[64], flags[2]
+    int* h_flags = nullptr;   // pinned host copy of flags
+    int* h_iters = nullptr;
+    double* h_scal = nullptr;
+};
+
+enum { SC_RR = 0, SC_RZ, SC_PQ, SC_RHO, SC_ALPHA, SC_BETA, SC_THR, SC_RNORM, SC_BN2, SC_RZOLD, SC_COUNT };
+
+}  // namespace msp
+
+struct msp_ctx {
+    msp_opts o{};
+    msp::SymParts sym;
+    msp::HostHierarchy hier;
+    msp::Csr Gf;              // FSAI of A_inn (pc = FSAI)
+    msp_stats stats{};
+    bool on_device = false;
+    int device = -1;
+    std::vector<void*> allocs;
+    int64_t* d_img = nullptr;
+    double* d_sigma = nullptr;
+    msp::DevCsr dAinn, dGf, dGfT;
+    std::vector<msp::DevLevel> dl;
+    double* d_cinv = nullptr;
+    int64_t nL = 0;
+    msp::Work w;
+    // low-rank corrections
+    int lrc_k = 0;
+    std::vector<int32_t> lrc_kept;
+    std::vector<double> lrc_ritz;
+
+    ~msp_ctx() {
+        if (on_device) {
+            (void)hipSetDevice(device);
+            for (void* p : allocs) (void)hipFree(p);
+            if (w.h_flags) (void)hipHostFree(w.h_flags);
+            if (w.h_iters) (void)hipHostFree(w.h_iters);
+            if (w.h_scal) (void)hipHostFree(w.h_scal);
+        }
+    }
+
+    template <typename T>
+    T* dalloc(int64_t count) {
+        if (count <= 0) count = 1;
+        void* p = nullptr;
+        HIPCHECK(hipMalloc(&p, sizeof(T) * static_cast<size_t>(count)));
+        allocs.push_back(p);
+        return static_cast<T*>(p);
+    }
+    template <typename T>
+    T* upload(const T* h, int64_t count) {
+        T* d = dalloc<T>(count);
+        if (count > 0) HIPCHECK(hipMemcpy(d, h, sizeof(T) * static_cast<size_t>(count), hipMemcpyHostToDevice));
+        return d;
+    }
+};
+
+namespace msp {
+
+static DevCsr upload_csr(msp_ctx* c, const Csr& M, bool fp32) {
+    DevCsr D;
+    D.nr = M.nr;
+    D.nc = M.nc;
+    D.nnz = M.nnz();
+    if (D.nnz >= (int64_t(1) << 31)) throw Error(MSP_ERR_UNSUPPORTED, "matrix too large for 32-bit indices");
+    std::vector<int32_t> rp(M.nr + 1);
+    for (int64_t i = 0; i <= M.nr; ++i) rp[i] = static_cast<int32_t>(M.rp[i]);
+    D.rp = c->upload(rp.data(), M.nr + 1);
+    D.ci = c->upload(M.ci.data(), D.nnz);
+    D.v64 = c->upload(M.v.data(), D.nnz);
+    if (fp32) {
+        std::vector<float> f(M.v.begin(), M.v.end());
+        D.v32 = c->upload(f.data(), D.nnz);
+    }
+    return D;
+}
+
+template <typename T>
+static const T* vals(const DevCsr& M);
+template <>
+const double* vals<double>(const DevCsr& M) { return M.v64; }
+template <>
+const float* vals<float>(const DevCsr& M) { return M.v32; }
+
+template <typename T>
+static void spmm(hipStream_t st, int C, const DevCsr& M, const T* X, T* Y, const T* Z, T alpha, T beta,
+                 const double* sigma = nullptr, int S = 1, int m = 1) {
+    HIPCHECK(launch_spmm<T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m));
+}
+
+static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
+
+static void ensure_work(msp_ctx* c, int C) {
+    Work& w = c->w;
+    if (w.C == C) return;
+    if (w.C != 0) throw Error(MSP_ERR_UNSUPPORTED, "column count changed; create a new context");
+    const int64_t nb = c->sym.n_b;
+    w.C = C;
+    w.x = c->dalloc<double>(nb * C);
+    w.r = c->dalloc<double>(nb * C);
+    w.z = c->dalloc<double>(nb * C);
+    w.p = c->dalloc<double>(nb * C);
+    w.q = c->dalloc<double>(nb * C);
+    w.zold = c->dalloc<double>(nb * C);
+    const size_t es = mixed(c) ? sizeof(float) : sizeof(double);
+    const size_t L = c->dl.size() + 1;
+    w.vy.assign(L, nullptr);
+    w.vs.assign(L, nullptr);
+    w.vr.assign(L, nullptr);
+    w.vt.assign(L, nullptr);
+    for (size_t l = 0; l < c->hier.lev.size(); ++l) {
+        const int64_t n = c->hier.lev[l].A.nr;
+        w.vy[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+        w.vs[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+        w.vr[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+        w.vt[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+    }
+    w.nb_dot = 1024;
+    w.partial = c->dalloc<double>(static_cast<int64_t>(w.nb_dot) * 64);
+    w.scal = c->dalloc<double>(SC_COUNT * 64);
+    w.iscal = c->dalloc<int>(64 * 2 + 2);
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_flags), 2 * sizeof(int), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_iters), 64 * sizeof(int), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_scal), SC_COUNT * 64 * sizeof(double),
+                           hipHostMallocDefault));
+}
+
+// One V(1,1) cycle of Alg. 3 on level l: s = M_l^{-1} y, all C columns.
+template <typename T>
+static void vcycle(msp_ctx* c, hipStream_t st, size_t l, const T* y, T* s) {
+    Work& w = c->w;
+    const int C = w.C;
+    if (l + 1 == c->hier.lev.size()) {
+        HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s));
+        return;
+    }
+    const DevLevel& L = c->dl[l];
+    T* r = static_cast<T*>(w.vr[l]);
+    T* t = static_cast<T*>(w.vt[l]);
+    T* yc = static_cast<T*>(w.vy[l + 1]);
+    T* sc = static_cast<T*>(w.vs[l + 1]);
+    const T om = static_cast<T>(L.omega);
+    spmm<T>(st, C, L.G, y, t, nullptr, T(1), T(0));          // pre-smooth from zero: s = w G^T G y
+    spmm<T>(st, C, L.GT, t, s, nullptr, om, T(0));
+    spmm<T>(st, C, L.A, s, r, y, T(-1), T(1));              // r = y - A s
+    spmm<T>(st, C, L.R, r, yc, nullptr, T(1), T(0));        // r_c = P^T r
+    vcycle<T>(c, st, l + 1, yc, sc);                        // coarse correction
+    spmm<T>(st, C, L.P, sc, s, s, T(1), T(1));              // s += P h_c
+    spmm<T>(st, C, L.A, s, r, y, T(-1), T(1));              // post-smooth: s += w G^T G (y - A s)
+    spmm<T>(st, C, L.G, r, t, nullptr, T(1), T(0));
+    spmm<T>(st, C, L.GT, t, s, s, om, T(1));
+}
+
+// z = M^{-1} r on all columns (shared preconditioner).
+static void precondition(msp_ctx* c, hipStream_t st, const double* r, double* z) {
+    Work& w = c->w;
+    const int C = w.C;
+    const int64_t nb = c->sym.n_b;
+    if (c->o.pc == MSP_PC_AMGR) {
+        if (mixed(c)) {
+            float* y0 = static_cast<float*>(w.vy[0]);
+            float* s0 = static_cast<float*>(w.vs[0]);
+            HIPCHECK((launch_cast<float, double>(st, nb * C, r, y0)));
+            vcycle<float>(c, st, 0, y0, s0);
+            HIPCHECK((launch_cast<double, float>(st, nb * C, s0, z)));
+        } else {
+            vcycle<double>(c, st, 0, r, z);
+        }
+    } else if (c->o.pc == MSP_PC_FSAI) {
+        double* t = w.zold;   // scratch (FSAI mode never needs the flexible copy)
+        spmm<double>(st, C, c->dGf, r, t, nullptr, 1.0, 0.0);
+        spmm<double>(st, C, c->dGfT, t, z, nullptr, 1.0, 0.0);
+    } else {
+        HIPCHECK(hipMemcpyAsync(z, r, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
+    }
+}
+
+static void upload_all(msp_ctx* c) {
+    HIPCHECK(hipSetDevice(c->device));
+    const bool f32 = mixed(c);
+    c->d_img = c->upload(c->sym.img.data(), static_cast<int64_t>(c->sym.img.size()));
+    c->d_sigma = c->upload(c->sym.sigma.data(), static_cast<int64_t>(c->sym.sigma.size()));
+    c->dAinn = upload_csr(c, c->sym.Ainn, false);
+    if (c->o.pc == MSP_PC_AMGR) {
+        c->dl.resize(c->hier.lev.size() - 1);
+        for (size_t l = 0; l + 1 < c->hier.lev.size(); ++l) {
+            const HostLevel& H = c->hier.lev[l];
+            DevLevel& D = c->dl[l];
+            D.n = H.A.nr;
+            D.A = upload_csr(c, H.A, f32);
+            D.P = upload_csr(c, H.P, f32);
+            D.R = upload_csr(c, H.R, f32);
+            D.G = upload_csr(c, H.G, f32);
+            D.GT = upload_csr(c, H.GT, f32);
+            D.omega = H.omega;
+        }
+        c->nL = c->hier.lev.back().A.nr;
+        c->d_cinv = c->upload(c->hier.coarse_inv.data(), static_cast<int64_t>(c->hier.coarse_inv.size()));
+    } else if (c->o.pc == MSP_PC_FSAI) {
+        c->dGf = upload_csr(c, c->Gf, false);
+        c->dGfT = upload_csr(c, transpose(c->Gf), false);
+    }
+    c->on_device = true;
+}
+
+static int next_pow2(int x) {
+    int c = 1;
+    while (c < x) c <<= 1;
+    return c;
+}
+
+static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipStream_t st, msp_stats* out) {
+    if (!c->on_device) throw Error(MSP_ERR_ARG, "context was set up without a device");
+    if (m <= 0 || !d_b || !d_x) throw Error(MSP_ERR_ARG, "need m > 0 and device arrays");
+    HIPCHECK(hipSetDevice(c->device));
+    const int S = 1 << c->sym.s;
+    const int ncol = S * m;
+    if (ncol > 64) throw Error(MSP_ERR_UNSUPPORTED, "2^s * m must not exceed 64");
+    const int C = next_pow2(ncol);
+    ensure_work(c, C);
+    Work& w = c->w;
+    const int64_t nb = c->sym.n_b, n = c->sym.n;
+    double* sc = w.scal;
+    double *rr = sc + SC_RR * 64, *rz = sc + SC_RZ * 64, *pq = sc + SC_PQ * 64, *rho = sc + SC_RHO * 64,
+           *alpha = sc + SC_ALPHA * 64, *beta = sc + SC_BETA * 64, *thr = sc + SC_THR * 64,
+           *rnorm = sc + SC_RNORM * 64, *bn2 = sc + SC_BN2 * 64, *rzold = sc + SC_RZOLD * 64;
+    int* active = w.iscal;
+    int* iters = w.iscal + 64;
+    int* flags = w.iscal + 128;
+    const bool flexible = mixed(c) && c->o.pc == MSP_PC_AMGR;
+    const auto t0 = std::chrono::steady_clock::now();
+
+    HIPCHECK(launch_colnorm2(st, n, m, d_b, bn2));
+    HIPCHECK(launch_thresholds(st, C, S, m, c->o.tol, bn2, thr));
+    HIPCHECK(launch_fill<double>(st, nb * C, w.r, 0.0));
+    HIPCHECK(launch_fill<double>(st, nb * C, w.x, 0.0));
+    HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, w.r));   // bhat = Q_s b
+    precondition(c, st, w.r, w.z);
+    HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.r, w.partial, w.nb_dot, rr));
+    HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.z, w.partial, w.nb_dot, rz));
+    HIPCHECK(launch_pcg_init(st, C, rr, rz, thr, active, rho, iters, flags, rnorm));
+    HIPCHECK(hipMemcpyAsync(w.p, w.z, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
+    HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    int nactive = w.h_flags[1];
+    int it = 0;
+    int status = MSP_OK;
+    while (nactive > 0 && it < c->o.maxit) {
+        spmm<double>(st, C, c->dAinn, w.p, w.q, nullptr, 1.0, 0.0, c->d_sigma, S, m);   // q = Ahat p
+        HIPCHECK(launch_dot<double>(st, C, nb, w.p, w.q, w.partial, w.nb_dot, pq));
+        HIPCHECK(launch_pcg_alpha(st, C, pq, active, rho, alpha, flags));
+        HIPCHECK(launch_pcg_update(st, C, nb, w.x, w.r, w.p, w.q, alpha));
+        HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.r, w.partial, w.nb_dot, rr));
+        HIPCHECK(launch_pcg_check(st, C, rr, thr, active, iters, flags, rnorm));
+        HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        ++it;
+        if (w.h_flags[0]) {
+            status = MSP_ERR_BREAKDOWN;
+            break;
+        }
+        nactive = w.h_flags[1];
+        if (nactive == 0) break;
+        if (flexible) HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.z, w.partial, w.nb_dot, rzold));
+        precondition(c, st, w.r, w.z);
+        HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.z, w.partial, w.nb_dot, rz));
+        HIPCHECK(launch_pcg_beta(st, C, rz, rzold, active, rho, beta, flexible ? 1 : 0));
+        HIPCHECK(launch_pcg_pupdate(st, C, nb, w.p, w.z, beta, active));
+    }
+    if (status == MSP_OK && nactive > 0) status = MSP_NOT_CONVERGED;
+    HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, w.x, d_x));   // x = Q_s xhat
+    HIPCHECK(hipMemcpyAsync(w.h_iters, iters, 64 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(w.h_scal, sc, SC_COUNT * 64 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    const auto t1 = std::chrono::steady_clock::now();
+    msp_stats& S_ = c->stats;
+    S_.iters = 0;
+    for (int q = 0; q < ncol; ++q) S_.iters = std::max(S_.iters, w.h_iters[q]);
+    for (int j = 0; j < 64; ++j) S_.relres[j] = 0.0;
+    for (int j = 0; j < m && j < 64; ++j) {
+        double s2 = 0.0;
+        for (int a = 0; a < S; ++a) {
+            const double v = w.h_scal[SC_RNORM * 64 + a * m + j];
+            s2 += v * v;
+        }
+        const double bn = std::sqrt(w.h_scal[SC_BN2 * 64 + j]);
+        S_.relres[j] = bn > 0 ? std::sqrt(s2) / bn : 0.0;
+    }
+    S_.status = status;
+    S_.t_solve_s = std::chrono::duration<double>(t1 - t0).count();
+    if (out) *out = S_;
+    if (status == MSP_ERR_BREAKDOWN) throw Error(MSP_ERR_BREAKDOWN, "PCG breakdown: p^T A p <= 0 or not finite");
+    return status;
+}
+
+static void fill_stats(msp_ctx* c) {
+    msp_stats& st = c->stats;
+    const auto& L = c->hier.lev;
+    st.nlev = static_cast<int32_t>(L.size());
+    double tot = 0.0;
+    for (size_t l = 0; l < L.size() && l < 32; ++l) {
+        st.rows[l] = L[l].A.nr;
+        st.nnz[l] = L[l].A.nnz();
+        tot += static_cast<double>(L[l].A.nnz());
+    }
+    const double nnz0 = L.empty() ? 1.0 : static_cast<double>(std::max<int64_t>(1, L[0].A.nnz()));
+    st.op_complexity = tot / nnz0;
+    if (L.size() > 1) {
+        st.c_rat = static_cast<double>(L[1].A.nr) / static_cast<double>(L[0].A.nr);
+        st.avg_nnzr = static_cast<double>(L[1].A.nnz()) / static_cast<double>(std::max<int64_t>(1, L[1].A.nr));
+    } else {
+        st.c_rat = 1.0;
+        st.avg_nnzr = L.empty() ? 0.0 : static_cast<double>(L[0].A.nnz()) / static_cast<double>(L[0].A.nr);
+    }
+}
+
+void build_lrc(msp_ctx* c);   // low-rank corrections (below)
+
+}  // namespace msp
+
+// ====================================================================== C ABI
+
+using msp::Error;
+
+template <typename F>
+static int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        msp::g_last_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        msp::g_last_error = "host allocation failed";
+        return MSP_ERR_OOM;
+    } catch (const std::exception& e) {
+        msp::g_last_error = e.what();
+        return MSP_ERR_ARG;
+    } catch (...) {
+        msp::g_last_error = "unknown error";
+        return MSP_ERR_ARG;
+    }
+}
+
+extern "C" {
+
+int msp_default_opts(msp_opts* o) {
+    if (!o) return MSP_ERR_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = MSP_FP64;
+    o->pc = MSP_PC_AMGR;
+    o->lrc_k = 0;
+    o->dist = 2;
+    o->theta = 0.25;
+    o->jacobi0 = 2;
+    o->jacobi = 1;
+    o->coarse_max = 1024;
+    o->max_levels = 20;
+    o->max_ratio = 0.8;
+    o->tol = 1e-10;
+    o->maxit = 1000;
+    o->device = 0;
+    o->seed = 240705930ull;
+    return MSP_OK;
+}
+
+int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ctx** out) {
+    return guarded([&]() -> int {
+        if (!out || !o) throw Error(MSP_ERR_ARG, "null output or options");
+        *out = nullptr;
+        if (o->precision < MSP_FP64 || o->precision > MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_ARG, "precision");
+        if (o->pc < MSP_PC_AMGR || o->pc > MSP_PC_NONE) throw Error(MSP_ERR_ARG, "pc");
+        if (o->lrc_k < 0 || o->dist < 1 || o->jacobi0 < 1 || o->jacobi < 1 || o->coarse_max < 1 ||
+            o->max_levels < 1 || !(o->theta >= 0.0) || !(o->tol > 0.0) || o->maxit < 0)
+            throw Error(MSP_ERR_ARG, "invalid option value");
+        if (o->lrc_k > 0 && o->pc == MSP_PC_NONE) throw Error(MSP_ERR_ARG, "low-rank corrections need a preconditioner");
+        const auto t0 = std::chrono::steady_clock::now();
+        std::unique_ptr<msp_ctx> c(new msp_ctx());
+        c->o = *o;
+        c->device = o->device;
+        c->lrc_k = o->lrc_k;
+        c->sym = msp::extract_blocks(A, map);
+        if (o->pc == MSP_PC_AMGR) {
+            c->hier = msp::build_hierarchy(c->sym.Ainn, c->sym.iface, *o);
+        } else {
+            c->hier.lev.emplace_back();
+            c->hier.lev.back().A = c->sym.Ainn;
+            if (o->pc == MSP_PC_FSAI) c->Gf = msp::fsai_full_lower(c->sym.Ainn);
+        }
+        msp::fill_stats(c.get());
+        if (o->device >= 0) {
+            int ndev = 0;
+            HIPCHECK(hipGetDeviceCount(&ndev));
+            if (o->device >= ndev) throw Error(MSP_ERR_ARG, "device ordinal out of range");
+            msp::upload_all(c.get());
+            if (c->lrc_k > 0) msp::build_lrc(c.get());
+            HIPCHECK(hipDeviceSynchronize());
+        }
+        const auto t1 = std::chrono::steady_clock::now();
+        c->stats.t_setup_s = std::chrono::duration<double>(t1 - t0).count();
+        *out = c.release();
+        return MSP_OK;
+    });
+}
+
+int msp_solve_device(msp_ctx* c, int32_t m, const double* d_b, double* d_x, void* hip_stream, msp_stats* st) {
+    return guarded([&]() -> int {
+        if (!c) throw Error(MSP_ERR_ARG, "null context");
+        return msp::solve_device(c, m, d_b, d_x, static_cast<hipStream_t>(hip_stream), st);
+    });
+}
+
+int msp_solve(msp_ctx* c, int32_t m, const double* b, double* x, msp_stats* st) {
+    return guarded([&]() -> int {
+        if (!c || !b || !x || m <= 0) throw Error(MSP_ERR_ARG, "null argument or m <= 0");
+        if (!c->on_device) throw Error(MSP_ERR_ARG, "context was set up without a device");
+        HIPCHECK(hipSetDevice(c->device));
+        const size_t bytes = sizeof(double) * static_cast<size_t>(c->sym.n) * static_cast<size_t>(m);
+        double *db = nullptr, *dx = nullptr;
+        HIPCHECK(hipMalloc(&db, bytes));
+        if (hipMalloc(&dx, bytes) != hipSuccess) {
+            (void)hipFree(db);
+            throw Error(MSP_ERR_OOM, "device allocation failed");
+        }
+        int rc;
+        try {
+            HIPCHECK(hipMemcpy(db, b, bytes, hipMemcpyHostToDevice));
+            rc = msp::solve_device(c, m, db, dx, nullptr, st);
+            HIPCHECK(hipMemcpy(x, dx, bytes, hipMemcpyDeviceToHost));
+        } catch (...) {
+            (void)hipFree(db);
+            (void)hipFree(dx);
+            throw;
+        }
+        (void)hipFree(db);
+        (void)hipFree(dx);
+        return rc;
+    });
+}
+
+int msp_get_stats(const msp_ctx* c, msp_stats* st) {
+    if (!c || !st) return MSP_ERR_ARG;
+    *st = c->stats;
+    return MSP_OK;
+}
+
+int msp_num_levels(const msp_ctx* c, int32_t* nlev) {
+    if (!c || !nlev) return MSP_ERR_ARG;
+    *nlev = static_cast<int32_t>(c->hier.lev.size());
+    return MSP_OK;
+}
+
+int msp_level_sizes(const msp_ctx* c, int32_t lev, int64_t* n, int64_t* nnz_A, int64_t* nnz_P, int64_t* nnz_G) {
+    if (!c || lev < 0 || lev >= static_cast<int32_t>(c->hier.lev.size())) return MSP_ERR_ARG;
+    const auto& L = c->hier.lev[lev];
+    if (n) *n = L.A.nr;
+    if (nnz_A) *nnz_A = L.A.nnz();
+    if (nnz_P) *nnz_P = L.P.nnz();
+    if (nnz_G) *nnz_G = L.G.nnz();
+    return MSP_OK;
+}
+
+static void copy_csr(const msp::Csr& M, int64_t* rp, int32_t* ci, double* v) {
+    if (rp && !M.rp.empty()) std::copy(M.rp.begin(), M.rp.end(), rp);
+    if (ci) std::copy(M.ci.begin(), M.ci.end(), ci);
+    if (v) std::copy(M.v.begin(), M.v.end(), v);
+}
+
+int msp_export_level(const msp_ctx* c, int32_t lev, int8_t* cf, int64_t* A_rp, int32_t* A_ci, double* A_v,
+                     int64_t* P_rp, int32_t* P_ci, double* P_v, int64_t* G_rp, int32_t* G_ci, double* G_v,
+                     double* omega) {
+    if (!c || lev < 0 || lev >= static_cast<int32_t>(c->hier.lev.size())) return MSP_ERR_ARG;
+    const auto& L = c->hier.lev[lev];
+    if (cf) std::copy(L.cf.begin(), L.cf.end(), cf);
+    copy_csr(L.A, A_rp, A_ci, A_v);
+    copy_csr(L.P, P_rp, P_ci, P_v);
+    copy_csr(L.G, G_rp, G_ci, G_v);
+    if (omega) *omega = L.omega;
+    return MSP_OK;
+}
+
+int msp_export_outer(const msp_ctx* c, double* sigma, int8_t* iface) {
+    if (!c) return MSP_ERR_ARG;
+    if (sigma) std::copy(c->sym.sigma.begin(), c->sym.sigma.end(), sigma);
+    if (iface) std::copy(c->sym.iface.begin(), c->sym.iface.end(), iface);
+    return MSP_OK;
+}
+
+int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz) {
+    if (!c) return MSP_ERR_ARG;
+    if (kept) std::copy(c->lrc_kept.begin(), c->lrc_kept.end(), kept);
+    if (ritz) std::copy(c->lrc_ritz.begin(), c->lrc_ritz.end(), ritz);
+    return MSP_OK;
+}
+
+void msp_free(msp_ctx* c) { delete c; }
+
+const char* msp_last_error(void) { return msp::g_last_error.c_str(); }
+
+}  // extern "C"
+
+namespace msp {
+void build_lrc(msp_ctx* c) {
+    (void)c;
+    throw Error(MSP_ERR_UNSUPPORTED, "low-rank corrections are not available in this build yet");
+}
+}  // namespace msp

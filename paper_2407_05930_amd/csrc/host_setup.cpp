@@ -1,0 +1,676 @@
+// Host-side setup: block extraction and validation (Sec. 2) and the shared
+// multigrid-reduction hierarchy on A_inn (Sec. 3.2, Alg. 2, eqs. (3.11)-(3.13)).
+//
+// Pattern-deciding arithmetic (strength thresholds, symbolic products) is
+// compiled without floating-point contraction so that each decision is one
+// IEEE multiply followed by an exact comparison.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <utility>
+
+#include "internal.hpp"
+
+namespace msp {
+
+// ------------------------------------------------------------------ hashing
+
+uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double unit_centered(uint64_t x) {
+    return static_cast<double>(splitmix64(x)) / 18446744073709551616.0 - 0.5;
+}
+
+static int popcount_parity(uint32_t x) { return __builtin_popcount(x) & 1; }
+
+// ------------------------------------------------------------------ sparse kernels
+
+Csr transpose(const Csr& A) {
+    Csr T;
+    T.nr = A.nc;
+    T.nc = A.nr;
+    T.rp.assign(T.nr + 1, 0);
+    const int64_t nnz = A.nnz();
+    for (int64_t k = 0; k < nnz; ++k) T.rp[A.ci[k] + 1]++;
+    for (int64_t i = 0; i < T.nr; ++i) T.rp[i + 1] += T.rp[i];
+    T.ci.resize(nnz);
+    T.v.resize(nnz);
+    std::vector<int64_t> pos(T.rp.begin(), T.rp.end() - 1);
+    for (int64_t i = 0; i < A.nr; ++i)
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            const int64_t p = pos[A.ci[k]]++;
+            T.ci[p] = static_cast<int32_t>(i);
+            T.v[p] = A.v[k];
+        }
+    return T;   // rows of T come out sorted because rows of A are visited in order
+}
+
+Csr spgemm(const Csr& A, const Csr& B) {
+    Csr C;
+    C.nr = A.nr;
+    C.nc = B.nc;
+    C.rp.assign(C.nr + 1, 0);
+    std::vector<int64_t> mark(B.nc, -1);
+    std::vector<double> acc(B.nc, 0.0);
+    std::vector<int32_t> cols;
+    for (int64_t i = 0; i < A.nr; ++i) {
+        cols.clear();
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            const int32_t j = A.ci[k];
+            const double a = A.v[k];
+            for (int64_t q = B.rp[j]; q < B.rp[j + 1]; ++q) {
+                const int32_t c = B.ci[q];
+                if (mark[c] != i) {
+                    mark[c] = i;
+                    acc[c] = 0.0;
+                    cols.push_back(c);
+                }
+                acc[c] += a * B.v[q];
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        for (int32_t c : cols) {
+            C.ci.push_back(c);
+            C.v.push_back(acc[c]);
+        }
+        C.rp[i + 1] = static_cast<int64_t>(C.ci.size());
+    }
+    return C;
+}
+
+static void spmv(const Csr& A, const double* x, double* y) {
+    for (int64_t i = 0; i < A.nr; ++i) {
+        double s = 0.0;
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * x[A.ci[k]];
+        y[i] = s;
+    }
+}
+
+// ------------------------------------------------------------------ block extraction
+
+SymParts extract_blocks(const msp_csr* A, const msp_symmap* map) {
+    if (!A || !map || !A->rowptr || !A->col || !A->val || !map->img)
+        throw Error(MSP_ERR_ARG, "null matrix or map");
+    if (map->s < 0 || map->s > 6) throw Error(MSP_ERR_ARG, "s must be in 0..6");
+    const int s = map->s;
+    const int S = 1 << s;
+    const int64_t n = A->n;
+    if (n <= 0 || map->n_b <= 0 || (map->n_b << s) != n)
+        throw Error(MSP_ERR_ARG, "n must equal n_b * 2^s and be positive");
+    if (n >= (int64_t(1) << 31)) throw Error(MSP_ERR_UNSUPPORTED, "n must fit in int32");
+    const int64_t n_b = map->n_b;
+    const int64_t* rp = A->rowptr;
+    if (rp[0] != 0) throw Error(MSP_ERR_ARG, "rowptr[0] must be 0");
+    for (int64_t g = 0; g < n; ++g)
+        if (rp[g + 1] < rp[g]) throw Error(MSP_ERR_ARG, "rowptr must be non-decreasing");
+    const int64_t nnz = rp[n];
+    for (int64_t k = 0; k < nnz; ++k)
+        if (A->col[k] < 0 || A->col[k] >= n) throw Error(MSP_ERR_ARG, "column index out of range");
+
+    // map: permutation, inverse
+    std::vector<int32_t> inv_i(n, -1);
+    std::vector<int8_t> inv_a(n, 0);
+    for (int64_t i = 0; i < n_b; ++i)
+        for (int a = 0; a < S; ++a) {
+            const int64_t g = map->img[i * S + a];
+            if (g < 0 || g >= n || inv_i[g] >= 0) throw Error(MSP_ERR_BAD_MAP, "symmetry map is not a permutation");
+            inv_i[g] = static_cast<int32_t>(i);
+            inv_a[g] = static_cast<int8_t>(a);
+        }
+
+    // sorted, zero-free copy of every row
+    Csr As;
+    As.nr = As.nc = n;
+    As.rp.assign(n + 1, 0);
+    As.ci.reserve(nnz);
+    As.v.reserve(nnz);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t g = 0; g < n; ++g) {
+        row.clear();
+        for (int64_t k = rp[g]; k < rp[g + 1]; ++k)
+            if (A->val[k] != 0.0 || std::isnan(A->val[k])) row.emplace_back(A->col[k], A->val[k]);
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) { return x.first < y.first; });
+        for (size_t q = 1; q < row.size(); ++q)
+            if (row[q].first == row[q - 1].first) throw Error(MSP_ERR_ARG, "duplicate entry in a row");
+        for (auto& e : row) {
+            As.ci.push_back(e.first);
+            As.v.push_back(e.second);
+        }
+        As.rp[g + 1] = static_cast<int64_t>(As.ci.size());
+    }
+    // exact symmetry
+    for (int64_t g = 0; g < n; ++g)
+        for (int64_t k = As.rp[g]; k < As.rp[g + 1]; ++k) {
+            const int32_t h = As.ci[k];
+            const int32_t* b = As.ci.data() + As.rp[h];
+            const int32_t* e = As.ci.data() + As.rp[h + 1];
+            const int32_t* f = std::lower_bound(b, e, static_cast<int32_t>(g));
+            if (f == e || *f != g || !(As.v[f - As.ci.data()] == As.v[k]))
+                throw Error(MSP_ERR_NOT_SYMMETRIC, "matrix is not exactly symmetric");
+        }
+
+    // block structure: row of image a of base cell i, read as (j = a xor b, l)
+    SymParts P;
+    P.s = s;
+    P.n = n;
+    P.n_b = n_b;
+    P.img.assign(map->img, map->img + n_b * S);
+    P.sigma.assign(n_b * S, 0.0);
+    P.iface.assign(n_b, 0);
+    P.Ainn.nr = P.Ainn.nc = n_b;
+    P.Ainn.rp.assign(n_b + 1, 0);
+    struct Ent { int32_t j; int32_t l; double v; };
+    std::vector<Ent> canon, cur;
+    auto row_entries = [&](int64_t g, int a, std::vector<Ent>& out) {
+        out.clear();
+        for (int64_t k = As.rp[g]; k < As.rp[g + 1]; ++k) {
+            const int32_t h = As.ci[k];
+            out.push_back({a ^ inv_a[h], inv_i[h], As.v[k]});
+        }
+        std::sort(out.begin(), out.end(), [](const Ent& x, const Ent& y) {
+            return x.j != y.j ? x.j < y.j : x.l < y.l;
+        });
+    };
+    std::vector<double> hdiag(S);
+    for (int64_t i = 0; i < n_b; ++i) {
+        row_entries(map->img[i * S], 0, canon);
+        for (int a = 1; a < S; ++a) {
+            row_entries(map->img[i * S + a], a, cur);
+            bool same = cur.size() == canon.size();
+            for (size_t q = 0; same && q < cur.size(); ++q)
+                same = cur[q].j == canon[q].j && cur[q].l == canon[q].l && cur[q].v == canon[q].v;
+            if (!same)
+                throw Error(MSP_ERR_NOT_SYMMETRIC,
+                            "matrix does not have the mirrored block structure of the map");
+        }
+        std::fill(hdiag.begin(), hdiag.end(), 0.0);
+        for (const Ent& e : canon) {
+            if (e.j == 0) {
+                P.Ainn.ci.push_back(e.l);
+                P.Ainn.v.push_back(e.v);
+            } else {
+                if (e.l != i)
+                    throw Error(MSP_ERR_UNSUPPORTED,
+                                "outer blocks H_j (j != 0) must be diagonal (two-point stencils)");
+                hdiag[e.j] = e.v;
+                P.iface[i] = 1;
+            }
+        }
+        P.Ainn.rp[i + 1] = static_cast<int64_t>(P.Ainn.ci.size());
+        for (int a = 0; a < S; ++a) {
+            double acc = 0.0;
+            for (int j = 1; j < S; ++j) {
+                const double t = popcount_parity(static_cast<uint32_t>(a & j)) ? -hdiag[j] : hdiag[j];
+                acc = acc + t;
+            }
+            P.sigma[i * S + a] = acc;
+        }
+    }
+    return P;
+}
+
+// ------------------------------------------------------------------ strength and graphs
+
+struct Graph {
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+};
+
+// S_i = {j != i : -a_ij >= theta * max_{l != i} -a_il}, empty if that max <= 0.
+static Graph strength(const Csr& A, double theta) {
+    Graph S;
+    S.rp.assign(A.nr + 1, 0);
+    for (int64_t i = 0; i < A.nr; ++i) {
+        double mx = -INFINITY;
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            if (A.ci[k] != i) mx = std::max(mx, -A.v[k]);
+        if (mx > 0.0) {
+            const double thr = theta * mx;
+            for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+                if (A.ci[k] != i && -A.v[k] >= thr) S.ci.push_back(A.ci[k]);
+        }
+        S.rp[i + 1] = static_cast<int64_t>(S.ci.size());
+    }
+    return S;
+}
+
+static Graph symmetrise(const Graph& S, int64_t n) {
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
+            cnt[i + 1]++;
+            cnt[S.ci[k] + 1]++;
+        }
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> adj(cnt[n]);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
+            adj[pos[i]++] = S.ci[k];
+            adj[pos[S.ci[k]]++] = static_cast<int32_t>(i);
+        }
+    Graph T;
+    T.rp.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        auto b = adj.begin() + cnt[i], e = adj.begin() + cnt[i + 1];
+        std::sort(b, e);
+        auto u = std::unique(b, e);
+        T.ci.insert(T.ci.end(), b, u);
+        T.rp[i + 1] = static_cast<int64_t>(T.ci.size());
+    }
+    return T;
+}
+
+// Lexicographically-first maximal independent set at distance d in the graph
+// T restricted to candidate nodes: scan candidates in the given order and
+// take a node when no taken node lies within d hops through candidates.
+static std::vector<int8_t> mis_scan(const Graph& T, const std::vector<int8_t>& cand,
+                                    const std::vector<int32_t>& order, int d) {
+    const int64_t n = static_cast<int64_t>(cand.size());
+    std::vector<int8_t> taken(n, 0);
+    std::vector<int32_t> stamp(n, -1), frontier, next;
+    for (int32_t u : order) {
+        bool blocked = false;
+        frontier.assign(1, u);
+        stamp[u] = u;
+        for (int depth = 0; depth < d && !blocked; ++depth) {
+            next.clear();
+            for (int32_t x : frontier) {
+                for (int64_t k = T.rp[x]; k < T.rp[x + 1]; ++k) {
+                    const int32_t y = T.ci[k];
+                    if (!cand[y] || stamp[y] == u) continue;
+                    stamp[y] = u;
+                    if (taken[y]) {
+                        blocked = true;
+                        break;
+                    }
+                    next.push_back(y);
+                }
+                if (blocked) break;
+            }
+            frontier.swap(next);
+        }
+        if (!blocked) taken[u] = 1;
+    }
+    return taken;
+}
+
+// ------------------------------------------------------------------ interpolation
+
+// Jacobi-truncated ideal interpolation with symbolic patterns and row sums
+// rescaled to -sum_{l != i} a_il / a_ii; P = [W; I] in fine-row order with
+// coarse unknowns numbered by increasing fine index.
+static Csr interpolation(const Csr& A, const std::vector<int8_t>& cf, int steps) {
+    const int64_t n = A.nr;
+    std::vector<int32_t> cnum(n, -1), fnum(n, -1);
+    int32_t nc = 0, nf = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (cf[i]) cnum[i] = nc++;
+        else fnum[i] = nf++;
+    }
+    std::vector<int64_t> fidx;
+    fidx.reserve(nf);
+    for (int64_t i = 0; i < n; ++i)
+        if (!cf[i]) fidx.push_back(i);
+    // W rows over F, columns = coarse numbers
+    Csr W;
+    W.nr = nf;
+    W.nc = nc;
+    auto build_step = [&](const Csr* Wprev) {
+        Csr Wn;
+        Wn.nr = nf;
+        Wn.nc = nc;
+        Wn.rp.assign(nf + 1, 0);
+        std::vector<int64_t> mark(nc, -1);
+        std::vector<double> acc(nc, 0.0), afc(nc, 0.0);
+        std::vector<int8_t> has_afc(nc, 0), has_acc(nc, 0);
+        std::vector<int32_t> cols;
+        for (int32_t r = 0; r < nf; ++r) {
+            const int64_t i = fidx[r];
+            cols.clear();
+            double dii = 0.0;
+            // A_FC entries of the row and O W (Gustavson over ascending f)
+            for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                const int32_t c = A.ci[k];
+                if (c == i) {
+                    dii = A.v[k];
+                    continue;
+                }
+                if (cf[c]) {
+                    const int32_t q = cnum[c];
+                    if (mark[q] != r) {
+                        mark[q] = r;
+                        has_afc[q] = has_acc[q] = 0;
+                        cols.push_back(q);
+                    }
+                    afc[q] = A.v[k];
+                    has_afc[q] = 1;
+                } else if (Wprev) {
+                    const int32_t f = fnum[c];
+                    const double a = A.v[k];
+                    for (int64_t p = Wprev->rp[f]; p < Wprev->rp[f + 1]; ++p) {
+                        const int32_t q = Wprev->ci[p];
+                        if (mark[q] != r) {
+                            mark[q] = r;
+                            has_afc[q] = has_acc[q] = 0;
+                            cols.push_back(q);
+                        }
+                        if (!has_acc[q]) {
+                            acc[q] = 0.0;
+                            has_acc[q] = 1;
+                        }
+                        acc[q] += a * Wprev->v[p];
+                    }
+                }
+            }
+            std::sort(cols.begin(), cols.end());
+            const double dinv = 1.0 / dii;
+            for (int32_t q : cols) {
+                double t;
+                if (has_afc[q] && has_acc[q]) t = afc[q] + acc[q];
+                else if (has_afc[q]) t = afc[q];
+                else t = acc[q];
+                Wn.ci.push_back(q);
+                Wn.v.push_back(-(dinv * t));
+            }
+            Wn.rp[r + 1] = static_cast<int64_t>(Wn.ci.size());
+        }
+        return Wn;
+    };
+    W = build_step(nullptr);
+    for (int t = 1; t < steps; ++t) {
+        Csr Wn = build_step(&W);
+        W.rp.swap(Wn.rp);
+        W.ci.swap(Wn.ci);
+        W.v.swap(Wn.v);
+    }
+    // rescale rows to rho_i = -sum_{l != i} a_il / a_ii
+    for (int32_t r = 0; r < nf; ++r) {
+        const int64_t i = fidx[r];
+        double off = 0.0, dii = 0.0;
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            if (A.ci[k] == i) dii = A.v[k];
+            else off += A.v[k];
+        }
+        const double rho = -off / dii;
+        double ws = 0.0;
+        for (int64_t p = W.rp[r]; p < W.rp[r + 1]; ++p) ws += W.v[p];
+        if (ws != 0.0) {
+            const double sc = rho / ws;
+            for (int64_t p = W.rp[r]; p < W.rp[r + 1]; ++p) W.v[p] = W.v[p] * sc;
+        }
+    }
+    Csr P;
+    P.nr = n;
+    P.nc = nc;
+    P.rp.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        if (cf[i]) {
+            P.ci.push_back(cnum[i]);
+            P.v.push_back(1.0);
+        } else {
+            const int32_t r = fnum[i];
+            for (int64_t p = W.rp[r]; p < W.rp[r + 1]; ++p) {
+                P.ci.push_back(W.ci[p]);
+                P.v.push_back(W.v[p]);
+            }
+        }
+        P.rp[i + 1] = static_cast<int64_t>(P.ci.size());
+    }
+    return P;
+}
+
+// ------------------------------------------------------------------ FSAI and damping
+
+// Dense Cholesky of an SPD k x k row-major matrix in place (lower factor).
+static bool cholesky(int k, double* M) {
+    for (int j = 0; j < k; ++j) {
+        double d = M[j * k + j];
+        for (int p = 0; p < j; ++p) d -= M[j * k + p] * M[j * k + p];
+        if (!(d > 0.0)) return false;
+        d = std::sqrt(d);
+        M[j * k + j] = d;
+        for (int i = j + 1; i < k; ++i) {
+            double s = M[i * k + j];
+            for (int p = 0; p < j; ++p) s -= M[i * k + p] * M[j * k + p];
+            M[i * k + j] = s / d;
+        }
+    }
+    return true;
+}
+
+static double lookup(const Csr& A, int64_t i, int32_t j) {
+    const int32_t* b = A.ci.data() + A.rp[i];
+    const int32_t* e = A.ci.data() + A.rp[i + 1];
+    const int32_t* f = std::lower_bound(b, e, j);
+    return (f != e && *f == j) ? A.v[f - A.ci.data()] : 0.0;
+}
+
+// Static-pattern FSAI: row i pattern = given lower neighbours (ascending) + i;
+// A[J,J] g = e_last solved by Cholesky, g scaled by 1/sqrt(g_last).
+static Csr fsai_rows(const Csr& A, const std::vector<std::vector<int32_t>>& lower) {
+    Csr G;
+    G.nr = G.nc = A.nr;
+    G.rp.assign(A.nr + 1, 0);
+    std::vector<double> M, g;
+    std::vector<int32_t> J;
+    for (int64_t i = 0; i < A.nr; ++i) {
+        J = lower[i];
+        J.push_back(static_cast<int32_t>(i));
+        const int k = static_cast<int>(J.size());
+        M.assign(static_cast<size_t>(k) * k, 0.0);
+        for (int p = 0; p < k; ++p)
+            for (int q = 0; q < k; ++q) M[p * k + q] = lookup(A, J[p], J[q]);
+        if (!cholesky(k, M.data())) throw Error(MSP_ERR_NOT_SPD, "FSAI: local matrix not SPD");
+        // solve L L^T g = e_last: L y = e_last has y = e_last / L_kk, then L^T g = y
+        g.assign(k, 0.0);
+        g[k - 1] = 1.0 / M[(k - 1) * k + (k - 1)];
+        for (int p = k - 1; p >= 0; --p) {
+            double s = g[p];
+            for (int q = p + 1; q < k; ++q) s -= M[q * k + p] * g[q];
+            g[p] = s / M[p * k + p];
+        }
+        const double sc = 1.0 / std::sqrt(g[k - 1]);
+        for (int p = 0; p < k; ++p) {
+            G.ci.push_back(J[p]);
+            G.v.push_back(g[p] * sc);
+        }
+        G.rp[i + 1] = static_cast<int64_t>(G.ci.size());
+    }
+    return G;
+}
+
+Csr fsai_full_lower(const Csr& A) {
+    std::vector<std::vector<int32_t>> lower(A.nr);
+    for (int64_t i = 0; i < A.nr; ++i)
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            if (A.ci[k] < i) lower[i].push_back(A.ci[k]);
+    return fsai_rows(A, lower);
+}
+
+// omega = 4 / (3 lam), lam = v^T G A G^T v after 20 power iterations from
+// v_i = splitmix64(seed xor i)/2^64 - 1/2 (normalised).
+static double damping(const Csr& A, const Csr& G, const Csr& GT, uint64_t seed) {
+    const int64_t n = A.nr;
+    std::vector<double> v(n), t1(n), t2(n), w(n);
+    double nrm = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        v[i] = unit_centered(seed ^ static_cast<uint64_t>(i));
+        nrm += v[i] * v[i];
+    }
+    nrm = std::sqrt(nrm);
+    for (auto& x : v) x /= nrm;
+    double lam = 0.0;
+    for (int it = 0; it < 20; ++it) {
+        spmv(GT, v.data(), t1.data());
+        spmv(A, t1.data(), t2.data());
+        spmv(G, t2.data(), w.data());
+        double vw = 0.0, ww = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            vw += v[i] * w[i];
+            ww += w[i] * w[i];
+        }
+        lam = vw;
+        const double wn = std::sqrt(ww);
+        for (int64_t i = 0; i < n; ++i) v[i] = w[i] / wn;
+    }
+    return 4.0 / (3.0 * lam);
+}
+
+// ------------------------------------------------------------------ dense eigen (Jacobi)
+
+void sym_eig(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& V) {
+    V.assign(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += A[i * n + j] * A[i * n + j];
+                if (i != j) off += A[i * n + j] * A[i * n + j];
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                const double app = A[p * n + p], aqq = A[q * n + q];
+                const double tau = (aqq - app) / (2.0 * apq);
+                const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - s * vkq;
+                    V[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    std::vector<int> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return A[x * n + x] < A[y * n + y]; });
+    w.resize(n);
+    std::vector<double> Vs(static_cast<size_t>(n) * n);
+    for (int c = 0; c < n; ++c) {
+        w[c] = A[idx[c] * n + idx[c]];
+        for (int k = 0; k < n; ++k) Vs[k * n + c] = V[k * n + idx[c]];
+    }
+    V.swap(Vs);
+}
+
+// ------------------------------------------------------------------ hierarchy
+
+HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o) {
+    HostHierarchy H;
+    Csr A = Ainn;
+    int lev = 0;
+    const uint64_t seed = o.seed;
+    while (true) {
+        H.lev.emplace_back();
+        HostLevel& L = H.lev.back();
+        const int64_t n = A.nr;
+        if (n <= o.coarse_max || lev == o.max_levels - 1) {
+            L.A = std::move(A);
+            break;
+        }
+        Graph S = strength(A, o.theta);
+        Graph T = symmetrise(S, n);
+        std::vector<int8_t> cf(n, 0), cand(n, 1);
+        std::vector<int32_t> order;
+        int d;
+        if (lev == 0) {
+            // Alg. 2: MIS of T^d over inner nodes, then interface forced coarse
+            for (int64_t i = 0; i < n; ++i) {
+                cand[i] = iface[i] ? 0 : 1;
+                if (cand[i]) order.push_back(static_cast<int32_t>(i));
+            }
+            std::vector<uint64_t> pri(n);
+            for (int64_t i = 0; i < n; ++i) pri[i] = splitmix64(seed ^ static_cast<uint64_t>(i));
+            std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return pri[x] > pri[y]; });
+            d = o.dist;
+        } else {
+            // standard level: priority (number of strong dependants, hash)
+            std::vector<int64_t> lam(n, 0);
+            for (int64_t k = 0; k < S.rp[n]; ++k) lam[S.ci[k]]++;
+            std::vector<uint64_t> h(n);
+            for (int64_t i = 0; i < n; ++i)
+                h[i] = splitmix64(seed ^ (static_cast<uint64_t>(lev) << 40) ^ static_cast<uint64_t>(i));
+            order.resize(n);
+            std::iota(order.begin(), order.end(), 0);
+            std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+                return lam[x] != lam[y] ? lam[x] > lam[y] : h[x] > h[y];
+            });
+            d = 1;
+        }
+        std::vector<int8_t> mis = mis_scan(T, cand, order, d);
+        int64_t nc = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            cf[i] = (mis[i] || (lev == 0 && iface[i])) ? 1 : 0;
+            nc += cf[i];
+        }
+        if (nc == 0 || static_cast<double>(nc) > o.max_ratio * static_cast<double>(n)) {
+            L.A = std::move(A);
+            break;
+        }
+        // smoother: FSAI on the strong lower pattern, block-diagonal F/C at level 0
+        std::vector<std::vector<int32_t>> lower(n);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
+                const int32_t j = S.ci[k];
+                if (j < i && (lev != 0 || cf[j] == cf[i])) lower[i].push_back(j);
+            }
+        L.G = fsai_rows(A, lower);
+        L.GT = transpose(L.G);
+        L.omega = damping(A, L.G, L.GT, seed);
+        L.P = interpolation(A, cf, lev == 0 ? o.jacobi0 : o.jacobi);
+        L.R = transpose(L.P);
+        L.cf = std::move(cf);
+        Csr AP = spgemm(A, L.P);
+        Csr Ac = spgemm(L.R, AP);
+        L.A = std::move(A);
+        A = std::move(Ac);
+        ++lev;
+    }
+    // dense inverse of the coarsest operator
+    const HostLevel& Lc = H.lev.back();
+    const int64_t nc = Lc.A.nr;
+    if (nc > 16384) throw Error(MSP_ERR_UNSUPPORTED, "coarsest level too large for a dense solve");
+    std::vector<double> M(nc * nc, 0.0);
+    for (int64_t i = 0; i < nc; ++i)
+        for (int64_t k = Lc.A.rp[i]; k < Lc.A.rp[i + 1]; ++k) M[i * nc + Lc.A.ci[k]] = Lc.A.v[k];
+    if (!cholesky(static_cast<int>(nc), M.data())) throw Error(MSP_ERR_NOT_SPD, "coarsest level is not SPD");
+    // inverse: solve L Y = I, then L^T X = Y, column by column
+    H.coarse_inv.assign(nc * nc, 0.0);
+    std::vector<double> y(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+        for (int64_t i = 0; i < nc; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int64_t p = c; p < i; ++p) s -= M[i * nc + p] * y[p];
+            y[i] = (i < c) ? 0.0 : s / M[i * nc + i];
+        }
+        for (int64_t i = nc - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int64_t p = i + 1; p < nc; ++p) s -= M[p * nc + i] * H.coarse_inv[p * nc + c];
+            H.coarse_inv[i * nc + c] = s / M[i * nc + i];
+        }
+    }
+    return H;
+}
+
+}  // namespace msp

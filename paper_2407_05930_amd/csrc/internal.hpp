@@ -1,0 +1,68 @@
+// Internal data structures of the mirror-symmetric Poisson library.
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "msp.h"
+
+namespace msp {
+
+// Error carried to the C boundary as (status, message).
+struct Error : std::runtime_error {
+    int status;
+    Error(int st, const std::string& msg) : std::runtime_error(msg), status(st) {}
+};
+
+// Host CSR, sorted columns, 64-bit row pointers.
+struct Csr {
+    int64_t nr = 0, nc = 0;
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> v;
+    int64_t nnz() const { return rp.empty() ? 0 : rp[nr]; }
+};
+
+Csr transpose(const Csr& A);
+// Product with the structural pattern (explicit zeros kept); each value is
+// sum_k A_ik B_kj accumulated in increasing k (Gustavson order).
+Csr spgemm(const Csr& A, const Csr& B);
+
+// One level of the shared hierarchy (host copy).
+struct HostLevel {
+    Csr A;
+    std::vector<int8_t> cf;   // 1 = coarse (empty on the coarsest level)
+    Csr P, R, G, GT;
+    double omega = 0.0;
+};
+
+struct HostHierarchy {
+    std::vector<HostLevel> lev;
+    std::vector<double> coarse_inv;   // dense inverse of the coarsest A, row-major
+};
+
+// Result of block extraction (Sec. 2).
+struct SymParts {
+    int s = 0;
+    int64_t n = 0, n_b = 0;
+    Csr Ainn;                       // H_0
+    std::vector<double> sigma;      // n_b * 2^s, diagonal of A_out,a
+    std::vector<int8_t> iface;      // n_b
+    std::vector<int64_t> img;       // n_b * 2^s
+};
+
+SymParts extract_blocks(const msp_csr* A, const msp_symmap* map);
+HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o);
+// Static FSAI on the full lower pattern of A (the stand-alone FSAI of A_inn).
+Csr fsai_full_lower(const Csr& A);
+
+uint64_t splitmix64(uint64_t x);
+double unit_centered(uint64_t x);
+
+// Dense symmetric eigen-decomposition (cyclic Jacobi), row-major n x n input;
+// eigenvalues ascending, eigenvectors as columns of V (row-major).
+void sym_eig(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& V);
+
+}  // namespace msp

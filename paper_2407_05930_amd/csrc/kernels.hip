@@ -1,0 +1,529 @@
+// HIP kernels for gfx950 (CDNA4, wave64).
+//
+// Multivectors are n x C row-major (the C columns of one row are contiguous;
+// C is the padded column count 2^s * m rounded up to a power of two).  A row
+// is handled by LPR = C / VW lanes, each lane owning VW consecutive columns,
+// so one wavefront covers 64 / LPR rows and every matrix entry (column index
+// and value) is read once for all C columns (the SpMM of eq. (2.8)).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace msp {
+
+constexpr int kBlock = 256;
+
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) Pack {
+    T e[VW];
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ Pack<T, VW> ld(const T* p) {
+    return *reinterpret_cast<const Pack<T, VW>*>(p);
+}
+template <typename T, int VW>
+__device__ __forceinline__ void st(T* p, const Pack<T, VW>& v) {
+    *reinterpret_cast<Pack<T, VW>*>(p) = v;
+}
+
+// vector width per lane: 16-byte accesses where the row is wide enough
+template <typename T, int C>
+struct Lanes {
+    static constexpr int VW = (16 / (int)sizeof(T)) < C ? (16 / (int)sizeof(T)) : C;
+    static constexpr int LPR = C / VW;
+    static constexpr int RPB = kBlock / LPR;
+};
+
+// ------------------------------------------------------------------ SpMM
+// Y = alpha * (A X + diag-outer(X)) + beta * Z, where the outer term adds
+// sigma[row * S + col / m] * X[row, col] (the per-subsystem outer diagonal of
+// eq. (2.11), one value per subsystem, broadcast over its m columns).
+// Y may alias Z (each lane reads its own Z elements before writing them).
+template <typename T, int C>
+__global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci,
+                                                 const T* __restrict__ va, const T* __restrict__ X,
+                                                 T* Y, const T* Z, T alpha, T beta,
+                                                 const double* __restrict__ sigma, int S, int m) {
+    using L = Lanes<T, C>;
+    constexpr int VW = L::VW;
+    const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
+    const int lane = threadIdx.x % L::LPR;
+    if (row >= n) return;
+    T acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = T(0);
+    const int32_t k0 = rp[row], k1 = rp[row + 1];
+    for (int32_t k = k0; k < k1; ++k) {
+        const int32_t c = ci[k];
+        const T a = va[k];
+        const Pack<T, VW> x = ld<T, VW>(X + (int64_t)c * C + lane * VW);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] += a * x.e[e];
+    }
+    if (sigma) {
+        const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const int a = (lane * VW + e) / m;
+            if (a < S) acc[e] += (T)sigma[row * S + a] * x.e[e];
+        }
+    }
+    Pack<T, VW> out;
+    if (Z) {
+        const Pack<T, VW> z = ld<T, VW>(Z + row * C + lane * VW);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) out.e[e] = alpha * acc[e] + beta * z.e[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) out.e[e] = alpha * acc[e];
+    }
+    st<T, VW>(Y + row * C + lane * VW, out);
+}
+
+// ------------------------------------------------------------------ per-column dots
+// partial[block * C + c] = sum over this block's rows of X[row, c] * Y[row, c]
+// (FP64 accumulation); rows are visited grid-stride, the in-block reduction
+// runs over row slots in a fixed order, so results are deterministic.
+template <typename T, int C>
+__global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const T* __restrict__ X,
+                                                const T* __restrict__ Y, double* __restrict__ partial) {
+    using L = Lanes<T, C>;
+    constexpr int VW = L::VW;
+    __shared__ double sm[kBlock * VW];
+    const int slot = threadIdx.x / L::LPR;
+    const int lane = threadIdx.x % L::LPR;
+    double acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * L::RPB + slot; row < n; row += (int64_t)gridDim.x * L::RPB) {
+        const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
+        const Pack<T, VW> y = ld<T, VW>(Y + row * C + lane * VW);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] += (double)x.e[e] * (double)y.e[e];
+    }
+#pragma unroll
+    for (int e = 0; e < VW; ++e) sm[threadIdx.x * VW + e] = acc[e];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        double s = 0.0;
+        for (int r = 0; r < L::RPB; ++r) s += sm[r * C + threadIdx.x];
+        partial[(int64_t)blockIdx.x * C + threadIdx.x] = s;
+    }
+}
+
+// Sum the partials of nb blocks per column in a fixed order: out[c].
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(int nb, const double* __restrict__ partial,
+                                                            double* __restrict__ out) {
+    constexpr int P = kBlock / C;
+    __shared__ double sm[kBlock];
+    const int c = threadIdx.x % C;
+    const int part = threadIdx.x / C;
+    double s = 0.0;
+    for (int b = part; b < nb; b += P) s += partial[(int64_t)b * C + c];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        double t = 0.0;
+        for (int p = 0; p < P; ++p) t += sm[p * C + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+// ------------------------------------------------------------------ PCG scalar steps (one block)
+// Column state: active[c] (0/1), rho[c], alpha[c], beta[c], iters[c],
+// thr[c] (stop once ||r_c|| <= thr[c]); flags[0] = breakdown, flags[1] = #active.
+
+__global__ void k_pcg_init(int C, const double* __restrict__ rr, const double* __restrict__ rz,
+                           const double* __restrict__ thr, int* active, double* rho, int* iters,
+                           int* flags, double* rnorm) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < C) {
+        const double nr = sqrt(rr[c]);
+        rnorm[c] = nr;
+        const int a = nr > thr[c] ? 1 : 0;
+        active[c] = a;
+        rho[c] = rz[c];
+        iters[c] = 0;
+        if (a) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        flags[0] = 0;
+        flags[1] = cnt;
+    }
+}
+
+__global__ void k_pcg_alpha(int C, const double* __restrict__ pq, const int* __restrict__ active,
+                            const double* __restrict__ rho, double* alpha, int* flags) {
+    const int c = threadIdx.x;
+    if (c < C) {
+        double a = 0.0;
+        if (active[c]) {
+            const double d = pq[c];
+            if (!(d > 0.0) || !isfinite(d) || !isfinite(rho[c])) flags[0] = 1;
+            else a = rho[c] / d;
+        }
+        alpha[c] = a;
+    }
+}
+
+__global__ void k_pcg_check(int C, const double* __restrict__ rr, const double* __restrict__ thr,
+                            int* active, int* iters, int* flags, double* rnorm) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < C && active[c]) {
+        iters[c] += 1;
+        const double nr = sqrt(rr[c]);
+        rnorm[c] = nr;
+        if (!isfinite(nr)) flags[0] = 1;
+        if (nr > thr[c]) atomicAdd(&cnt, 1);
+        else active[c] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) flags[1] = cnt;
+}
+
+// standard beta = <r,z>_new / <r,z>_old; flexible: (<r,z>_new - <r,z_old>) / <r,z>_old
+__global__ void k_pcg_beta(int C, const double* __restrict__ rz, const double* __restrict__ rzold,
+                           const int* __restrict__ active, double* rho, double* beta, int flexible) {
+    const int c = threadIdx.x;
+    if (c < C) {
+        double b = 0.0;
+        if (active[c]) {
+            const double num = flexible ? rz[c] - rzold[c] : rz[c];
+            b = num / rho[c];
+            rho[c] = rz[c];
+        }
+        beta[c] = b;
+    }
+}
+
+// x += alpha p, r -= alpha q (per column alpha; zero for frozen columns)
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                       const double* __restrict__ p, const double* __restrict__ q,
+                                                       const double* __restrict__ alpha) {
+    using L = Lanes<double, C>;
+    constexpr int VW = L::VW;
+    const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
+    const int lane = threadIdx.x % L::LPR;
+    if (row >= n) return;
+    const int64_t o = row * C + lane * VW;
+    Pack<double, VW> xv = ld<double, VW>(x + o), rv = ld<double, VW>(r + o);
+    const Pack<double, VW> pv = ld<double, VW>(p + o), qv = ld<double, VW>(q + o);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+        const double a = alpha[lane * VW + e];
+        xv.e[e] += a * pv.e[e];
+        rv.e[e] -= a * qv.e[e];
+    }
+    st<double, VW>(x + o, xv);
+    st<double, VW>(r + o, rv);
+}
+
+// p = z + beta p on active columns
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_pcg_pupdate(int64_t n, double* __restrict__ p,
+                                                        const double* __restrict__ z,
+                                                        const double* __restrict__ beta,
+                                                        const int* __restrict__ active) {
+    using L = Lanes<double, C>;
+    constexpr int VW = L::VW;
+    const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
+    const int lane = threadIdx.x % L::LPR;
+    if (row >= n) return;
+    const int64_t o = row * C + lane * VW;
+    Pack<double, VW> pv = ld<double, VW>(p + o);
+    const Pack<double, VW> zv = ld<double, VW>(z + o);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+        const int c = lane * VW + e;
+        if (active[c]) pv.e[e] = zv.e[e] + beta[c] * pv.e[e];
+    }
+    st<double, VW>(p + o, pv);
+}
+
+// ------------------------------------------------------------------ Q_s (Alg. 1, eq. (2.9))
+// Q_s = 2^{-s/2} Had (x) I: a Walsh-Hadamard butterfly over the 2^s images of
+// each base cell, fused with the layout change between the caller's n x m
+// column-major vectors and the n_b x C multivector (column a*m + j).
+template <int S>
+__device__ __forceinline__ void fwht(double* v) {
+#pragma unroll
+    for (int h = 1; h < S; h <<= 1)
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if ((i & h) == 0) {
+                const double u = v[i], w = v[i + h];
+                v[i] = u + w;
+                v[i + h] = u - w;
+            }
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_qs_forward(int64_t n_b, int m, int C, int64_t n,
+                                                       const int64_t* __restrict__ img,
+                                                       const double* __restrict__ b, double* __restrict__ out,
+                                                       double scale) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_b * m) return;
+    const int64_t i = t / m;
+    const int j = (int)(t % m);
+    double v[S];
+#pragma unroll
+    for (int a = 0; a < S; ++a) v[a] = b[img[i * S + a] + (int64_t)j * n];
+    fwht<S>(v);
+#pragma unroll
+    for (int a = 0; a < S; ++a) out[i * C + a * m + j] = scale * v[a];
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_qs_backward(int64_t n_b, int m, int C, int64_t n,
+                                                        const int64_t* __restrict__ img,
+                                                        const double* __restrict__ xh, double* __restrict__ x,
+                                                        double scale) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_b * m) return;
+    const int64_t i = t / m;
+    const int j = (int)(t % m);
+    double v[S];
+#pragma unroll
+    for (int a = 0; a < S; ++a) v[a] = xh[i * C + a * m + j];
+    fwht<S>(v);
+#pragma unroll
+    for (int a = 0; a < S; ++a) x[img[i * S + a] + (int64_t)j * n] = scale * v[a];
+}
+
+// per-RHS squared norms of the caller's b: out[j] (one block per RHS, fixed order)
+__global__ __launch_bounds__(kBlock) void k_colnorm2(int64_t n, const double* __restrict__ b,
+                                                     double* __restrict__ out) {
+    __shared__ double sm[kBlock];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int64_t g = threadIdx.x; g < n; g += kBlock) {
+        const double v = b[g + (int64_t)j * n];
+        s += v * v;
+    }
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = sm[0];
+}
+
+// thresholds per column a*m + j: tol * ||b_j|| / sqrt(2^s); padded columns -1
+__global__ void k_thresholds(int C, int S, int m, double tol, const double* __restrict__ bn2,
+                             double* __restrict__ thr) {
+    const int c = threadIdx.x;
+    if (c < C) thr[c] = (c < S * m) ? tol * sqrt(bn2[c % m]) / sqrt((double)S) : -1.0;
+}
+
+// ------------------------------------------------------------------ dense coarsest level
+// out[i, :] = sum_k Minv[i, k] * y[k, :] in FP64 (inputs/outputs of type T)
+template <typename T, int C>
+__global__ __launch_bounds__(kBlock) void k_dense(int64_t nL, const double* __restrict__ Minv,
+                                                  const T* __restrict__ y, T* __restrict__ out) {
+    using L = Lanes<T, C>;
+    constexpr int VW = L::VW;
+    const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
+    const int lane = threadIdx.x % L::LPR;
+    if (row >= nL) return;
+    double acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = 0.0;
+    const double* mr = Minv + row * nL;
+    for (int64_t k = 0; k < nL; ++k) {
+        const double a = mr[k];
+        const Pack<T, VW> x = ld<T, VW>(y + k * C + lane * VW);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] += a * (double)x.e[e];
+    }
+    Pack<T, VW> o;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) o.e[e] = (T)acc[e];
+    st<T, VW>(out + row * C + lane * VW, o);
+}
+
+// ------------------------------------------------------------------ elementwise
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t len, T* __restrict__ p, T v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) p[i] = v;
+}
+
+template <typename TO, typename TI>
+__global__ __launch_bounds__(kBlock) void k_cast(int64_t len, const TI* __restrict__ a, TO* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) b[i] = (TO)a[i];
+}
+
+// ------------------------------------------------------------------ host launchers
+
+static inline unsigned blocks_for(int64_t work, int per_block) {
+    return (unsigned)((work + per_block - 1) / per_block);
+}
+
+#define MSP_DISPATCH_C(C, ...)                                   \
+    switch (C) {                                                 \
+        case 1: { constexpr int CC = 1; __VA_ARGS__; } break;    \
+        case 2: { constexpr int CC = 2; __VA_ARGS__; } break;    \
+        case 4: { constexpr int CC = 4; __VA_ARGS__; } break;    \
+        case 8: { constexpr int CC = 8; __VA_ARGS__; } break;    \
+        case 16: { constexpr int CC = 16; __VA_ARGS__; } break;  \
+        case 32: { constexpr int CC = 32; __VA_ARGS__; } break;  \
+        case 64: { constexpr int CC = 64; __VA_ARGS__; } break;  \
+        default: return hipErrorInvalidValue;                    \
+    }
+
+template <typename T>
+hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const T* va,
+                       const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m) {
+    if (n <= 0) return hipSuccess;
+    MSP_DISPATCH_C(C, {
+        using L = Lanes<T, CC>;
+        hipLaunchKernelGGL((k_spmm<T, CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp, ci, va, X, Y,
+                           Z, alpha, beta, sigma, S, m);
+    });
+    return hipGetLastError();
+}
+template hipError_t launch_spmm<double>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const double*,
+                                        const double*, double*, const double*, double, double, const double*, int,
+                                        int);
+template hipError_t launch_spmm<float>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const float*,
+                                       const float*, float*, const float*, float, float, const double*, int, int);
+
+template <typename T>
+hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
+                      double* out) {
+    MSP_DISPATCH_C(C, {
+        hipLaunchKernelGGL((k_dot<T, CC>), dim3(nb), dim3(kBlock), 0, st, n, X, Y, partial);
+        hipLaunchKernelGGL((k_reduce_partials<CC>), dim3(1), dim3(kBlock), 0, st, nb, partial, out);
+    });
+    return hipGetLastError();
+}
+template hipError_t launch_dot<double>(hipStream_t, int, int64_t, const double*, const double*, double*, int,
+                                       double*);
+template hipError_t launch_dot<float>(hipStream_t, int, int64_t, const float*, const float*, double*, int,
+                                      double*);
+
+hipError_t launch_pcg_init(hipStream_t st, int C, const double* rr, const double* rz, const double* thr,
+                           int* active, double* rho, int* iters, int* flags, double* rnorm) {
+    hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(64), 0, st, C, rr, rz, thr, active, rho, iters, flags, rnorm);
+    return hipGetLastError();
+}
+hipError_t launch_pcg_alpha(hipStream_t st, int C, const double* pq, const int* active, const double* rho,
+                            double* alpha, int* flags) {
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(64), 0, st, C, pq, active, rho, alpha, flags);
+    return hipGetLastError();
+}
+hipError_t launch_pcg_check(hipStream_t st, int C, const double* rr, const double* thr, int* active, int* iters,
+                            int* flags, double* rnorm) {
+    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(64), 0, st, C, rr, thr, active, iters, flags, rnorm);
+    return hipGetLastError();
+}
+hipError_t launch_pcg_beta(hipStream_t st, int C, const double* rz, const double* rzold, const int* active,
+                           double* rho, double* beta, int flexible) {
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, st, C, rz, rzold, active, rho, beta, flexible);
+    return hipGetLastError();
+}
+hipError_t launch_pcg_update(hipStream_t st, int C, int64_t n, double* x, double* r, const double* p,
+                             const double* q, const double* alpha) {
+    MSP_DISPATCH_C(C, {
+        using L = Lanes<double, CC>;
+        hipLaunchKernelGGL((k_pcg_update<CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, x, r, p, q,
+                           alpha);
+    });
+    return hipGetLastError();
+}
+hipError_t launch_pcg_pupdate(hipStream_t st, int C, int64_t n, double* p, const double* z, const double* beta,
+                              const int* active) {
+    MSP_DISPATCH_C(C, {
+        using L = Lanes<double, CC>;
+        hipLaunchKernelGGL((k_pcg_pupdate<CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, p, z, beta,
+                           active);
+    });
+    return hipGetLastError();
+}
+
+#define MSP_DISPATCH_S(S, ...)                                   \
+    switch (S) {                                                 \
+        case 1: { constexpr int SS = 1; __VA_ARGS__; } break;    \
+        case 2: { constexpr int SS = 2; __VA_ARGS__; } break;    \
+        case 4: { constexpr int SS = 4; __VA_ARGS__; } break;    \
+        case 8: { constexpr int SS = 8; __VA_ARGS__; } break;    \
+        case 16: { constexpr int SS = 16; __VA_ARGS__; } break;  \
+        case 32: { constexpr int SS = 32; __VA_ARGS__; } break;  \
+        case 64: { constexpr int SS = 64; __VA_ARGS__; } break;  \
+        default: return hipErrorInvalidValue;                    \
+    }
+
+hipError_t launch_qs_forward(hipStream_t st, int S, int64_t n_b, int m, int C, int64_t n, const int64_t* img,
+                             const double* b, double* out) {
+    const double scale = 1.0 / std::sqrt((double)S);
+    MSP_DISPATCH_S(S, {
+        hipLaunchKernelGGL((k_qs_forward<SS>), dim3(blocks_for(n_b * m, kBlock)), dim3(kBlock), 0, st, n_b, m, C,
+                           n, img, b, out, scale);
+    });
+    return hipGetLastError();
+}
+hipError_t launch_qs_backward(hipStream_t st, int S, int64_t n_b, int m, int C, int64_t n, const int64_t* img,
+                              const double* xh, double* x) {
+    const double scale = 1.0 / std::sqrt((double)S);
+    MSP_DISPATCH_S(S, {
+        hipLaunchKernelGGL((k_qs_backward<SS>), dim3(blocks_for(n_b * m, kBlock)), dim3(kBlock), 0, st, n_b, m, C,
+                           n, img, xh, x, scale);
+    });
+    return hipGetLastError();
+}
+hipError_t launch_colnorm2(hipStream_t st, int64_t n, int m, const double* b, double* out) {
+    hipLaunchKernelGGL(k_colnorm2, dim3(m), dim3(kBlock), 0, st, n, b, out);
+    return hipGetLastError();
+}
+hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, const double* bn2, double* thr) {
+    hipLaunchKernelGGL(k_thresholds, dim3(1), dim3(64), 0, st, C, S, m, tol, bn2, thr);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out) {
+    MSP_DISPATCH_C(C, {
+        using L = Lanes<T, CC>;
+        hipLaunchKernelGGL((k_dense<T, CC>), dim3(blocks_for(nL, L::RPB)), dim3(kBlock), 0, st, nL, Minv, y, out);
+    });
+    return hipGetLastError();
+}
+template hipError_t launch_dense<double>(hipStream_t, int, int64_t, const double*, const double*, double*);
+template hipError_t launch_dense<float>(hipStream_t, int, int64_t, const double*, const float*, float*);
+
+template <typename T>
+hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {
+    if (len <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(len, kBlock)), dim3(kBlock), 0, st, len, p, v);
+    return hipGetLastError();
+}
+template hipError_t launch_fill<double>(hipStream_t, int64_t, double*, double);
+template hipError_t launch_fill<float>(hipStream_t, int64_t, float*, float);
+
+template <typename TO, typename TI>
+hipError_t launch_cast(hipStream_t st, int64_t len, const TI* a, TO* b) {
+    if (len <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_cast<TO, TI>), dim3(blocks_for(len, kBlock)), dim3(kBlock), 0, st, len, a, b);
+    return hipGetLastError();
+}
+template hipError_t launch_cast<float, double>(hipStream_t, int64_t, const double*, float*);
+template hipError_t launch_cast<double, float>(hipStream_t, int64_t, const float*, double*);
+
+}  // namespace msp

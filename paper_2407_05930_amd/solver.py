@@ -1,0 +1,165 @@
+"""Python front end of the C interface: ``Solver(A, img, ...)`` then
+``solve(b)``.  Marshalling only; every step of the solve runs in the
+library's HIP kernels.  Device arrays are torch tensors."""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def default_opts() -> _lib.msp_opts:
+    o = _lib.msp_opts()
+    check(lib.msp_default_opts(ctypes.byref(o)))
+    return o
+
+
+def make_opts(**kw) -> _lib.msp_opts:
+    o = default_opts()
+    for key, val in kw.items():
+        if key == "precision":
+            val = _lib.PRECISION[val] if isinstance(val, str) else val
+        elif key == "pc":
+            val = _lib.PC[val] if isinstance(val, str) else val
+        elif key == "k":
+            key = "lrc_k"
+        if not hasattr(o, key):
+            raise TypeError(f"unknown option {key}")
+        setattr(o, key, val)
+    return o
+
+
+class Solver:
+    """Setup from the full symmetric matrix ``A`` (scipy CSR or anything with
+    indptr/indices/data) and the symmetry map ``img`` (n_b x 2^s, row of
+    image a of base cell i); options as in ``msp_opts`` (``k`` = LRC rank,
+    ``precision`` in {"fp64", "mixed", "mixed_bf16g"}, ``pc`` in
+    {"amgr", "fsai", "none"}, ``device`` = -1 for a host-only setup)."""
+
+    def __init__(self, A, img, **opts):
+        img = np.ascontiguousarray(img, dtype=np.int64)
+        if img.ndim != 2:
+            raise ValueError("img must be (n_b, 2^s)")
+        n_b, S = img.shape
+        s = S.bit_length() - 1
+        if 1 << s != S:
+            raise ValueError("img must have 2^s columns")
+        indptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        indices = np.ascontiguousarray(A.indices, dtype=np.int32)
+        data = np.ascontiguousarray(A.data, dtype=np.float64)
+        n = indptr.size - 1
+        self.n, self.n_b, self.s = n, n_b, s
+        csr = _lib.msp_csr(n, _ptr(indptr, ctypes.c_int64), _ptr(indices, ctypes.c_int32),
+                           _ptr(data, ctypes.c_double))
+        smap = _lib.msp_symmap(s, n_b, _ptr(img, ctypes.c_int64))
+        self.opts = make_opts(**opts)
+        self._ctx = ctypes.c_void_p()
+        check(lib.msp_setup(ctypes.byref(csr), ctypes.byref(smap), ctypes.byref(self.opts),
+                            ctypes.byref(self._ctx)))
+        self.last = _lib.msp_stats()
+
+    # ------------------------------------------------------------------ solves
+    def solve(self, b, stream=None):
+        """Solve A x = b for a torch tensor b on the context's GPU, shape (n,)
+        or (n, m), float64.  Returns x with b's shape.  ``stream`` is a
+        torch.cuda.Stream (default: the current stream)."""
+        import torch
+        vec = b.dim() == 1
+        B = b.reshape(self.n, -1)
+        m = B.shape[1]
+        bt = B.t().contiguous()                       # (m, n) = n x m column-major
+        if bt.dtype != torch.float64 or not bt.is_cuda:
+            raise ValueError("b must be a float64 CUDA tensor")
+        xt = torch.empty_like(bt)
+        st = stream if stream is not None else torch.cuda.current_stream(bt.device)
+        rc = check(lib.msp_solve_device(self._ctx, m, ctypes.c_void_p(bt.data_ptr()),
+                                        ctypes.c_void_p(xt.data_ptr()), ctypes.c_void_p(st.cuda_stream),
+                                        ctypes.byref(self.last)))
+        self.status = rc
+        x = xt.t()
+        return x.reshape(-1) if vec else x.contiguous()
+
+    def solve_host(self, b: np.ndarray) -> np.ndarray:
+        vec = b.ndim == 1
+        B = np.asarray(b, dtype=np.float64).reshape(self.n, -1)
+        m = B.shape[1]
+        bt = np.ascontiguousarray(B.T)
+        xt = np.empty_like(bt)
+        rc = check(lib.msp_solve(self._ctx, m, bt.ctypes.data_as(ctypes.c_void_p),
+                                 xt.ctypes.data_as(ctypes.c_void_p), ctypes.byref(self.last)))
+        self.status = rc
+        return xt.T.reshape(-1) if vec else np.ascontiguousarray(xt.T)
+
+    # ------------------------------------------------------------------ introspection
+    @property
+    def stats(self):
+        st = _lib.msp_stats()
+        check(lib.msp_get_stats(self._ctx, ctypes.byref(st)))
+        return st
+
+    def num_levels(self) -> int:
+        v = ctypes.c_int32()
+        check(lib.msp_num_levels(self._ctx, ctypes.byref(v)))
+        return v.value
+
+    def export_level(self, lev: int) -> dict:
+        """Host copy of level ``lev``: cf mask, A, P, G (scipy CSR), omega."""
+        import scipy.sparse as sp
+        n, nA, nP, nG = (ctypes.c_int64() for _ in range(4))
+        check(lib.msp_level_sizes(self._ctx, lev, ctypes.byref(n), ctypes.byref(nA), ctypes.byref(nP),
+                                  ctypes.byref(nG)))
+        n, nA, nP, nG = n.value, nA.value, nP.value, nG.value
+        cf = np.zeros(n, dtype=np.int8)
+        Arp, Aci, Av = np.zeros(n + 1, np.int64), np.zeros(nA, np.int32), np.zeros(nA)
+        has_p = nP > 0
+        Prp, Pci, Pv = np.zeros(n + 1, np.int64), np.zeros(nP, np.int32), np.zeros(nP)
+        Grp, Gci, Gv = np.zeros(n + 1, np.int64), np.zeros(nG, np.int32), np.zeros(nG)
+        om = ctypes.c_double()
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        check(lib.msp_export_level(self._ctx, lev, vp(cf), vp(Arp), vp(Aci), vp(Av),
+                                   vp(Prp) if has_p else None, vp(Pci) if has_p else None,
+                                   vp(Pv) if has_p else None, vp(Grp) if nG else None,
+                                   vp(Gci) if nG else None, vp(Gv) if nG else None, ctypes.byref(om)))
+        out = dict(A=sp.csr_matrix((Av, Aci, Arp), shape=(n, n)), omega=om.value)
+        if has_p:
+            nc = int(cf.sum())
+            out["cf"] = cf.astype(bool)
+            out["P"] = sp.csr_matrix((Pv, Pci, Prp), shape=(n, nc))
+            out["G"] = sp.csr_matrix((Gv, Gci, Grp), shape=(n, n))
+        return out
+
+    def export_outer(self):
+        S = 1 << self.s
+        sigma = np.zeros(self.n_b * S)
+        iface = np.zeros(self.n_b, dtype=np.int8)
+        check(lib.msp_export_outer(self._ctx, sigma.ctypes.data_as(ctypes.c_void_p),
+                                   iface.ctypes.data_as(ctypes.c_void_p)))
+        return sigma.reshape(self.n_b, S), iface.astype(bool)
+
+    def export_lrc(self):
+        S = 1 << self.s
+        k = self.opts.lrc_k
+        kept = np.zeros(S, dtype=np.int32)
+        ritz = np.zeros(S * max(k, 1))
+        check(lib.msp_export_lrc(self._ctx, kept.ctypes.data_as(ctypes.c_void_p),
+                                 ritz.ctypes.data_as(ctypes.c_void_p)))
+        return kept, ritz.reshape(S, max(k, 1))[:, :k]
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib.msp_free(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

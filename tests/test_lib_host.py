@@ -1,0 +1,119 @@
+"""Host-side checks of the native library (no GPU needed): exported
+symbols, input validation, and bit-exact parity of the setup (block
+extraction, Alg. 2 coarsening, interpolation/FSAI patterns) with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from gen import make_problem
+from oracle import amg, krylov
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2407_05930_amd import _lib
+    return _lib
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "msp.h")).read()
+    names = set(re.findall(r"\b(msp_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 12
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2407_05930_amd", "libmsp.so"))
+    for nm in sorted(names):
+        assert hasattr(lib, nm), nm
+
+
+def _setup(p, **kw):
+    from paper_2407_05930_amd import Solver
+    return Solver(p.A, p.img, device=-1, **kw)
+
+
+@pytest.mark.parametrize("case", [
+    dict(N=(64, 64), s=1, kw=dict(), opt=dict(coarse_max=64)),
+    dict(N=(32, 32, 32), s=3, kw=dict(jitter=0.2, kappa="lognormal"), opt=dict(coarse_max=64)),
+    dict(N=(48, 48, 48), s=2, kw=dict(y_stretch=1.5), opt=dict()),
+    dict(N=(24, 16, 20), s=3, kw=dict(y_stretch=1.5), opt=dict(coarse_max=32, dist=3, jacobi0=3)),
+])
+def test_hierarchy_bit_exact_with_oracle(case):
+    p = make_problem(case["N"], s=case["s"], seed=1, **case["kw"])
+    sv = _setup(p, **case["opt"])
+    oo = {k: v for k, v in case["opt"].items()}
+    if "dist" in oo:
+        oo["dist"] = oo["dist"]
+    ctx = krylov.setup(p.A, p.img, amg.AMGOptions(**oo))
+    H = ctx["hier"]
+    assert sv.num_levels() == H.nlev
+    for lev in range(H.nlev):
+        e = sv.export_level(lev)
+        L = H.levels[lev]
+        assert np.array_equal(e["A"].indptr, L.A.indptr)
+        assert np.array_equal(e["A"].indices, L.A.indices)
+        assert np.abs(e["A"].data - L.A.data).max() <= 1e-12 * np.abs(L.A.data).max()
+        if L.C is not None:
+            assert np.array_equal(e["cf"], L.C)
+            for key in ("P", "G"):
+                M1, M2 = e[key], getattr(L, key)
+                assert np.array_equal(M1.indptr, M2.indptr) and np.array_equal(M1.indices, M2.indices)
+                assert np.abs(M1.data - M2.data).max() <= 1e-12 * np.abs(M2.data).max()
+            assert abs(e["omega"] - L.omega) <= 1e-10 * L.omega
+    sigma, iface = sv.export_outer()
+    assert np.array_equal(iface, ctx["interface"])
+    S = 1 << p.s
+    for a in range(S):
+        assert np.abs(sigma[:, a] - ctx["outs"][a].diagonal()).max() <= 1e-15 * np.abs(p.A.data).max()
+    st = sv.stats
+    assert st.nlev == H.nlev
+    assert abs(st.op_complexity - H.stats()["op_complexity"]) < 1e-12
+
+
+def test_setup_rejects_bad_inputs():
+    from paper_2407_05930_amd import Solver, MspError
+    p = make_problem((8, 8), s=1, seed=2, y_stretch=1.5)
+    img = p.img.copy()
+    img[0, 0] = img[1, 0]                       # not a permutation
+    with pytest.raises(MspError) as e:
+        Solver(p.A, img, device=-1)
+    assert e.value.status == -3
+    img = p.img.copy()
+    img[[0, 1], 1] = img[[1, 0], 1]             # permutation, but not the mirror map
+    with pytest.raises(MspError) as e:
+        Solver(p.A, img, device=-1)
+    assert e.value.status == -2
+    A = p.A.tolil()
+    A[0, 1] += 1e-3                             # breaks exact symmetry
+    with pytest.raises(MspError) as e:
+        Solver(A.tocsr(), p.img, device=-1)
+    assert e.value.status == -2
+    with pytest.raises(MspError) as e:
+        Solver(p.A, p.img, device=-1, tol=-1.0)
+    assert e.value.status == -1
+
+
+def test_setup_rejects_non_diagonal_outer_blocks():
+    """A 9-point-like coupling across the mirror plane makes H_1 non-diagonal."""
+    from paper_2407_05930_amd import Solver, MspError
+    p = make_problem((6, 6), s=1, seed=2, ordering="mirrored")
+    A = p.A.tolil()
+    n_b = p.n_b
+    # couple base cell 0 with image 1 of base cell 1 (and mirrored partners)
+    for (i, j) in [(0, n_b + 1), (n_b + 1, 0), (n_b + 0, 1), (1, n_b + 0)]:
+        A[i, j] = -0.01
+    A = A.tocsr()
+    with pytest.raises(MspError) as e:
+        Solver(A, p.img, device=-1)
+    assert e.value.status == -8
+
+
+def test_host_only_context_cannot_solve():
+    from paper_2407_05930_amd import Solver, MspError
+    p = make_problem((8, 8), s=1, seed=2)
+    sv = Solver(p.A, p.img, device=-1)
+    with pytest.raises(MspError) as e:
+        sv.solve_host(p.b)
+    assert e.value.status == -1
