@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the mirror-symmetric Poisson solve on one MI355X.
+
+Workload (default): 128^3 cell-centred Poisson on the unit cube, y stretched
+by tanh (gamma = 1.5), homogeneous Dirichlet walls, s = 3 mirror symmetries
+(8 decoupled subsystems), 4 seeded uniform[-1, 1] right-hand sides solved
+together (32 SpMM columns), low-rank corrections of rank k per subsystem,
+tolerance 1e-10 relative residual per right-hand side.
+
+A step is one complete solve (Q_s transforms, PCG to tolerance with the shared
+V-cycle and corrections, back transform) with the right-hand sides already
+resident in GPU memory.  The headline value is the solve time of the mixed
+solver (FP32 V-cycle, FP64 outer PCG); the plain FP64 solve is timed beside
+it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solve time to 1e-10 rel-res, 128^3 s=3; mixed vs FP64 plain; V-cycle HBM GB/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_solves(sv, b, steps, warmup, torch):
+    for _ in range(warmup):
+        sv.solve(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x = sv.solve(b)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) / steps, x
+
+
+def dominant_kernel(sv, b):
+    """Kind with the largest total time over one fully instrumented solve."""
+    sv.reset_timing()
+    sv.set_timing(True)
+    sv.solve(b)
+    sv.set_timing(False)
+    tm = sv.timing()
+    sv.reset_timing()
+    kind = max(tm, key=lambda k: tm[k][1])
+    total = sum(v[1] for v in tm.values())
+    return kind, tm, total
+
+
+def cpu_baseline(problem, iters_gpu, k):
+    """The FP64 oracle on the host: setup plus a bounded sample of PCG
+    iterations on the same workload, extrapolated to the GPU's iteration
+    count.  One thread (SciPy's sparse products are single-threaded; BLAS is
+    pinned to one thread)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import amg, krylov
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ctx = krylov.setup(problem.A, problem.img, amg.AMGOptions(), k=0)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        krylov.solve(ctx, problem.b, tol=1e-10, maxit=1)
+        t1 = time.perf_counter()
+        krylov.solve(ctx, problem.b, tol=1e-10, maxit=3)
+        t2 = time.perf_counter()
+    per_it = ((t2 - t1) - (t1 - t0)) / 2.0
+    est = (t1 - t0) + per_it * max(iters_gpu - 1, 0)
+    sample = (f"oracle setup ({t_setup:.1f} s, k=0) then PCG runs of 1 and 3 iterations on the full workload; "
+              f"{per_it:.2f} s/iteration extrapolated to the GPU FP64 iteration count ({iters_gpu}); "
+              f"low-rank corrections (k={k}) not included in the oracle sample")
+    return dict(value=round(est, 3), unit="s", cores=1, kind="oracle", sample=sample,
+                setup_s=round(t_setup, 2), s_per_iteration=round(per_it, 3))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="channel3d_128_s3")
+    ap.add_argument("--k", type=int, default=8, help="low-rank correction rank per subsystem")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): this solver has no "
+              "multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from gen import config_problem
+    from paper_2407_05930_amd import Solver
+
+    rank = int(os.environ.get("RANK", "0"))
+    log(f"building workload {args.workload}")
+    p = config_problem(args.workload)
+    b = torch.from_numpy(p.b).cuda()
+    k = args.k
+    res = {}
+    for prec in ("fp64", "mixed"):
+        log(f"setup {prec} k={k}")
+        try:
+            sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=k)
+        except Exception as e:   # low-rank corrections may be unavailable in this build
+            log(f"  k={k} unavailable ({e}); using k=0")
+            k = 0
+            sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=0)
+        t_setup = sv.stats.t_setup_s
+        log(f"timing {prec}: warmup {args.warmup}, steps {args.steps}")
+        t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
+        iters = sv.last.iters
+        relres = [float(v) for v in sv.last.relres[: p.b.shape[1]]]
+        xs = x.cpu().numpy()
+        true_rr = np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)
+        res[prec] = dict(sv=sv, t=t, iters=iters, relres=relres, true_relres=true_rr.tolist(), t_setup=t_setup,
+                         x=xs)
+        log(f"  {prec}: {t * 1e3:.2f} ms/solve, {iters} iterations, true rel res {true_rr.max():.2e}")
+
+    # roofline of the dominant kernel of the headline (mixed) solve, measured
+    # with HIP events on the solve's stream during the timed steps
+    svm = res["mixed"]["sv"]
+    kind, tm_all, total_ms = dominant_kernel(svm, b)
+    svm.set_timing(True, kind)
+    t_head, _ = timed_solves(svm, b, args.steps, 0, torch)
+    svm.set_timing(False, kind)
+    cnt, ms, by = svm.timing()[kind]
+    avg_ms = ms / cnt
+    bytes_per_launch = by / cnt
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    breakdown = {Solver.kind_name(kk): dict(launches=v[0], ms=round(v[1], 3),
+                                            GBs=round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None)
+                 for kk, v in sorted(tm_all.items(), key=lambda kv: -kv[1][1])}
+    # V-cycle aggregate GB/s: all level kernels and the dense coarsest solve
+    vc_ms = sum(v[1] for kk, v in tm_all.items() if kk >= 16 or kk == 6)
+    vc_by = sum(v[2] for kk, v in tm_all.items() if kk >= 16 or kk == 6)
+
+    t_mixed = res["mixed"]["t"]
+    t_fp64 = res["fp64"]["t"]
+    out = {
+        "metric": METRIC,
+        "value": round(t_mixed, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_mixed * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": list(p.N), "s": p.s, "rhs": int(p.b.shape[1]),
+                   "subsystem_columns": int((1 << p.s) * p.b.shape[1]), "lrc_k": k, "tol": 1e-10,
+                   "precision": "mixed (FP32 V-cycle, FP64 PCG)", "unknowns": int(p.n)},
+        "fp64_solve_s": round(t_fp64, 6),
+        "mixed_speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
+        "iters": {"fp64": res["fp64"]["iters"], "mixed": res["mixed"]["iters"]},
+        "true_relres_max": {kk: max(v["true_relres"]) for kk, v in res.items()},
+        "mixed_vs_fp64_rel_diff": float(np.linalg.norm(res["mixed"]["x"] - res["fp64"]["x"])
+                                        / np.linalg.norm(res["fp64"]["x"])),
+        "setup_s": {kk: round(v["t_setup"], 3) for kk, v in res.items()},
+        "vcycle_GBs": round(vc_by / (vc_ms * 1e-3) / 1e9, 1) if vc_ms > 0 else None,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": Solver.kind_name(kind), "avg_ms": round(avg_ms, 5),
+                     "algorithmic_bytes_per_launch": int(bytes_per_launch), "launches": cnt},
+        "kernel_breakdown_mixed": breakdown,
+        "timed_solve_with_kernel_events_s": round(t_head, 6),
+    }
+    if not args.no_cpu_baseline and rank == 0:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(p, res["fp64"]["iters"], k)
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -151,6 +151,21 @@ int msp_export_outer(const msp_ctx* c, double* sigma, int8_t* interface_mask);
    values found (ritz[a * k + t], k = lrc_k, ascending). */
 int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz);
 
+/* Optional per-kernel timers.  Launch classes ("kinds"):
+     0 operator (A_inn + outer diagonal) SpMM, 1 per-column dots,
+     2 x/r update, 3 p update, 4 Q_s butterflies, 5 precision casts,
+     6 dense coarsest solve, 7 FSAI preconditioner products,
+     8 low-rank corrections,
+     16 + 8*l + {0: A_l, 1: G_l, 2: G_l^T, 3: R_l = P_l^T, 4: P_l} (V-cycle level l).
+   While a kind is on, each of its launches is bracketed by HIP events on
+   the solve's stream; totals are folded in when the solve returns.
+   msp_set_timing(c, -1, on) switches every kind.  total_bytes sums the
+   algorithmic bytes of the timed launches (each operand read or written
+   once). */
+int msp_set_timing(msp_ctx* c, int32_t kind, int32_t on);
+int msp_reset_timing(msp_ctx* c);
+int msp_get_timing(const msp_ctx* c, int32_t kind, int64_t* count, double* total_ms, double* total_bytes);
+
 void msp_free(msp_ctx* c);
 const char* msp_last_error(void);
 

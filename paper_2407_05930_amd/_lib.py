@@ -73,6 +73,10 @@ SIGNATURES = {
                                         _P(ctypes.c_double)]),
     "msp_export_outer": (ctypes.c_int, [_vp, _vp, _vp]),
     "msp_export_lrc": (ctypes.c_int, [_vp, _vp, _vp]),
+    "msp_set_timing": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "msp_reset_timing": (ctypes.c_int, [_vp]),
+    "msp_get_timing": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_double),
+                                      _P(ctypes.c_double)]),
     "msp_free": (None, [_vp]),
     "msp_last_error": (ctypes.c_char_p, []),
 }

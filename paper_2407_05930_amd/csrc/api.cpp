@@ -56,6 +56,36 @@ struct Work {
 
 enum { SC_RR = 0, SC_RZ, SC_PQ, SC_RHO, SC_ALPHA, SC_BETA, SC_THR, SC_RNORM, SC_BN2, SC_RZOLD, SC_COUNT };
 
+// Launch classes for the optional per-kernel timers (msp_set_timing).
+enum {
+    KD_OP = 0,        // q = (A_inn + outer diagonal) p
+    KD_DOT = 1,       // per-column dot products (partials + reduction)
+    KD_UPDATE = 2,    // x += alpha p, r -= alpha q
+    KD_PUPDATE = 3,   // p = z + beta p
+    KD_QS = 4,        // Q_s butterflies
+    KD_CAST = 5,      // precision casts at the preconditioner boundary
+    KD_DENSE = 6,     // coarsest-level dense solve
+    KD_FSAI = 7,      // FSAI preconditioner products
+    KD_LRC = 8,       // low-rank corrections
+    KD_LEVEL = 16,    // + 8 * level + {0: A, 1: G, 2: G^T, 3: R, 4: P}
+    KD_COUNT = 16 + 8 * 20
+};
+
+struct PendingTime {
+    int kind;
+    double bytes;
+    hipEvent_t e0, e1;
+};
+
+struct Timers {
+    std::vector<char> on = std::vector<char>(KD_COUNT, 0);
+    std::vector<int64_t> count = std::vector<int64_t>(KD_COUNT, 0);
+    std::vector<double> ms = std::vector<double>(KD_COUNT, 0.0);
+    std::vector<double> bytes = std::vector<double>(KD_COUNT, 0.0);
+    std::vector<PendingTime> pending;
+    std::vector<hipEvent_t> pool;
+};
+
 }  // namespace msp
 
 struct msp_ctx {
@@ -78,10 +108,16 @@ struct msp_ctx {
     int lrc_k = 0;
     std::vector<int32_t> lrc_kept;
     std::vector<double> lrc_ritz;
+    msp::Timers tm;
 
     ~msp_ctx() {
         if (on_device) {
             (void)hipSetDevice(device);
+            for (auto& p : tm.pending) {
+                (void)hipEventDestroy(p.e0);
+                (void)hipEventDestroy(p.e1);
+            }
+            for (auto e : tm.pool) (void)hipEventDestroy(e);
             for (void* p : allocs) (void)hipFree(p);
             if (w.h_flags) (void)hipHostFree(w.h_flags);
             if (w.h_iters) (void)hipHostFree(w.h_iters);
@@ -132,10 +168,64 @@ const double* vals<double>(const DevCsr& M) { return M.v64; }
 template <>
 const float* vals<float>(const DevCsr& M) { return M.v32; }
 
+static hipEvent_t take_event(msp_ctx* c) {
+    if (!c->tm.pool.empty()) {
+        hipEvent_t e = c->tm.pool.back();
+        c->tm.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    return e;
+}
+
+// Run `launch` bracketed by events on `st` when timers for `kind` are on.
+template <typename F>
+static void timed(msp_ctx* c, int kind, double bytes, hipStream_t st, F&& launch) {
+    if (kind < 0 || kind >= KD_COUNT || !c->tm.on[kind]) {
+        launch();
+        return;
+    }
+    PendingTime p{kind, bytes, take_event(c), take_event(c)};
+    HIPCHECK(hipEventRecord(p.e0, st));
+    launch();
+    HIPCHECK(hipEventRecord(p.e1, st));
+    c->tm.pending.push_back(p);
+}
+
+// Fold finished event pairs into the per-kind totals (after a stream sync).
+static void resolve_timers(msp_ctx* c) {
+    for (auto& p : c->tm.pending) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, p.e0, p.e1));
+        c->tm.count[p.kind] += 1;
+        c->tm.ms[p.kind] += ms;
+        c->tm.bytes[p.kind] += p.bytes;
+        c->tm.pool.push_back(p.e0);
+        c->tm.pool.push_back(p.e1);
+    }
+    c->tm.pending.clear();
+}
+
+// Algorithmic bytes of Y = alpha (M X) + beta Z: the matrix once, X once,
+// Y written once, Z read once if present, the outer diagonal once.
 template <typename T>
-static void spmm(hipStream_t st, int C, const DevCsr& M, const T* X, T* Y, const T* Z, T alpha, T beta,
-                 const double* sigma = nullptr, int S = 1, int m = 1) {
-    HIPCHECK(launch_spmm<T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m));
+static double spmm_bytes(const DevCsr& M, int C, bool z, bool sig, int S) {
+    const double w = sizeof(T);
+    double b = static_cast<double>(M.nnz) * (w + 4.0) + 4.0 * static_cast<double>(M.nr + 1);
+    b += static_cast<double>(M.nc) * C * w + static_cast<double>(M.nr) * C * w;
+    if (z) b += static_cast<double>(M.nr) * C * w;
+    if (sig) b += static_cast<double>(M.nr) * S * 8.0;
+    return b;
+}
+
+template <typename T>
+static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, const T* X, T* Y, const T* Z,
+                 T alpha, T beta, const double* sigma = nullptr, int S = 1, int m = 1) {
+    const double bytes = c->tm.on[kind] ? spmm_bytes<T>(M, C, Z != nullptr, sigma != nullptr, S) : 0.0;
+    timed(c, kind, bytes, st, [&] {
+        HIPCHECK(launch_spmm<T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m));
+    });
 }
 
 static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
@@ -181,7 +271,8 @@ static void vcycle(msp_ctx* c, hipStream_t st, size_t l, const T* y, T* s) {
     Work& w = c->w;
     const int C = w.C;
     if (l + 1 == c->hier.lev.size()) {
-        HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s));
+        const double bytes = 8.0 * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
+        timed(c, KD_DENSE, bytes, st, [&] { HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s)); });
         return;
     }
     const DevLevel& L = c->dl[l];
@@ -190,15 +281,22 @@ static void vcycle(msp_ctx* c, hipStream_t st, size_t l, const T* y, T* s) {
     T* yc = static_cast<T*>(w.vy[l + 1]);
     T* sc = static_cast<T*>(w.vs[l + 1]);
     const T om = static_cast<T>(L.omega);
-    spmm<T>(st, C, L.G, y, t, nullptr, T(1), T(0));          // pre-smooth from zero: s = w G^T G y
-    spmm<T>(st, C, L.GT, t, s, nullptr, om, T(0));
-    spmm<T>(st, C, L.A, s, r, y, T(-1), T(1));              // r = y - A s
-    spmm<T>(st, C, L.R, r, yc, nullptr, T(1), T(0));        // r_c = P^T r
-    vcycle<T>(c, st, l + 1, yc, sc);                        // coarse correction
-    spmm<T>(st, C, L.P, sc, s, s, T(1), T(1));              // s += P h_c
-    spmm<T>(st, C, L.A, s, r, y, T(-1), T(1));              // post-smooth: s += w G^T G (y - A s)
-    spmm<T>(st, C, L.G, r, t, nullptr, T(1), T(0));
-    spmm<T>(st, C, L.GT, t, s, s, om, T(1));
+    const int kb = KD_LEVEL + 8 * static_cast<int>(l);
+    spmm<T>(c, kb + 1, st, C, L.G, y, t, nullptr, T(1), T(0));     // pre-smooth from zero: s = w G^T G y
+    spmm<T>(c, kb + 2, st, C, L.GT, t, s, nullptr, om, T(0));
+    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // r = y - A s
+    spmm<T>(c, kb + 3, st, C, L.R, r, yc, nullptr, T(1), T(0));    // r_c = P^T r
+    vcycle<T>(c, st, l + 1, yc, sc);                               // coarse correction
+    spmm<T>(c, kb + 4, st, C, L.P, sc, s, s, T(1), T(1));          // s += P h_c
+    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // post-smooth: s += w G^T G (y - A s)
+    spmm<T>(c, kb + 1, st, C, L.G, r, t, nullptr, T(1), T(0));
+    spmm<T>(c, kb + 2, st, C, L.GT, t, s, s, om, T(1));
+}
+
+// out[c] = <X_c, Y_c> for the C columns of two n_b x C multivectors.
+static void dot(msp_ctx* c, hipStream_t st, int C, int64_t nb, const double* X, const double* Y, double* out) {
+    timed(c, KD_DOT, 16.0 * nb * C, st,
+          [&] { HIPCHECK(launch_dot<double>(st, C, nb, X, Y, c->w.partial, c->w.nb_dot, out)); });
 }
 
 // z = M^{-1} r on all columns (shared preconditioner).
@@ -210,16 +308,16 @@ static void precondition(msp_ctx* c, hipStream_t st, const double* r, double* z)
         if (mixed(c)) {
             float* y0 = static_cast<float*>(w.vy[0]);
             float* s0 = static_cast<float*>(w.vs[0]);
-            HIPCHECK((launch_cast<float, double>(st, nb * C, r, y0)));
+            timed(c, KD_CAST, 12.0 * nb * C, st, [&] { HIPCHECK((launch_cast<float, double>(st, nb * C, r, y0))); });
             vcycle<float>(c, st, 0, y0, s0);
-            HIPCHECK((launch_cast<double, float>(st, nb * C, s0, z)));
+            timed(c, KD_CAST, 12.0 * nb * C, st, [&] { HIPCHECK((launch_cast<double, float>(st, nb * C, s0, z))); });
         } else {
             vcycle<double>(c, st, 0, r, z);
         }
     } else if (c->o.pc == MSP_PC_FSAI) {
         double* t = w.zold;   // scratch (FSAI mode never needs the flexible copy)
-        spmm<double>(st, C, c->dGf, r, t, nullptr, 1.0, 0.0);
-        spmm<double>(st, C, c->dGfT, t, z, nullptr, 1.0, 0.0);
+        spmm<double>(c, KD_FSAI, st, C, c->dGf, r, t, nullptr, 1.0, 0.0);
+        spmm<double>(c, KD_FSAI, st, C, c->dGfT, t, z, nullptr, 1.0, 0.0);
     } else {
         HIPCHECK(hipMemcpyAsync(z, r, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
     }
@@ -284,10 +382,11 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
     HIPCHECK(launch_thresholds(st, C, S, m, c->o.tol, bn2, thr));
     HIPCHECK(launch_fill<double>(st, nb * C, w.r, 0.0));
     HIPCHECK(launch_fill<double>(st, nb * C, w.x, 0.0));
-    HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, w.r));   // bhat = Q_s b
+    timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // bhat = Q_s b
+          [&] { HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, w.r)); });
     precondition(c, st, w.r, w.z);
-    HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.r, w.partial, w.nb_dot, rr));
-    HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.z, w.partial, w.nb_dot, rz));
+    dot(c, st, C, nb, w.r, w.r, rr);
+    dot(c, st, C, nb, w.r, w.z, rz);
     HIPCHECK(launch_pcg_init(st, C, rr, rz, thr, active, rho, iters, flags, rnorm));
     HIPCHECK(hipMemcpyAsync(w.p, w.z, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
     HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -296,11 +395,12 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
     int it = 0;
     int status = MSP_OK;
     while (nactive > 0 && it < c->o.maxit) {
-        spmm<double>(st, C, c->dAinn, w.p, w.q, nullptr, 1.0, 0.0, c->d_sigma, S, m);   // q = Ahat p
-        HIPCHECK(launch_dot<double>(st, C, nb, w.p, w.q, w.partial, w.nb_dot, pq));
+        spmm<double>(c, KD_OP, st, C, c->dAinn, w.p, w.q, nullptr, 1.0, 0.0, c->d_sigma, S, m);   // q = Ahat p
+        dot(c, st, C, nb, w.p, w.q, pq);
         HIPCHECK(launch_pcg_alpha(st, C, pq, active, rho, alpha, flags));
-        HIPCHECK(launch_pcg_update(st, C, nb, w.x, w.r, w.p, w.q, alpha));
-        HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.r, w.partial, w.nb_dot, rr));
+        timed(c, KD_UPDATE, 48.0 * nb * C, st,
+              [&] { HIPCHECK(launch_pcg_update(st, C, nb, w.x, w.r, w.p, w.q, alpha)); });
+        dot(c, st, C, nb, w.r, w.r, rr);
         HIPCHECK(launch_pcg_check(st, C, rr, thr, active, iters, flags, rnorm));
         HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
@@ -311,18 +411,21 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
         }
         nactive = w.h_flags[1];
         if (nactive == 0) break;
-        if (flexible) HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.z, w.partial, w.nb_dot, rzold));
+        if (flexible) dot(c, st, C, nb, w.r, w.z, rzold);
         precondition(c, st, w.r, w.z);
-        HIPCHECK(launch_dot<double>(st, C, nb, w.r, w.z, w.partial, w.nb_dot, rz));
+        dot(c, st, C, nb, w.r, w.z, rz);
         HIPCHECK(launch_pcg_beta(st, C, rz, rzold, active, rho, beta, flexible ? 1 : 0));
-        HIPCHECK(launch_pcg_pupdate(st, C, nb, w.p, w.z, beta, active));
+        timed(c, KD_PUPDATE, 24.0 * nb * C, st,
+              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, w.p, w.z, beta, active)); });
     }
     if (status == MSP_OK && nactive > 0) status = MSP_NOT_CONVERGED;
-    HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, w.x, d_x));   // x = Q_s xhat
+    timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // x = Q_s xhat
+          [&] { HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, w.x, d_x)); });
     HIPCHECK(hipMemcpyAsync(w.h_iters, iters, 64 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipMemcpyAsync(w.h_scal, sc, SC_COUNT * 64 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     const auto t1 = std::chrono::steady_clock::now();
+    resolve_timers(c);
     msp_stats& S_ = c->stats;
     S_.iters = 0;
     for (int q = 0; q < ncol; ++q) S_.iters = std::max(S_.iters, w.h_iters[q]);
@@ -539,6 +642,29 @@ int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz) {
     if (!c) return MSP_ERR_ARG;
     if (kept) std::copy(c->lrc_kept.begin(), c->lrc_kept.end(), kept);
     if (ritz) std::copy(c->lrc_ritz.begin(), c->lrc_ritz.end(), ritz);
+    return MSP_OK;
+}
+
+int msp_set_timing(msp_ctx* c, int32_t kind, int32_t on) {
+    if (!c || kind < -1 || kind >= msp::KD_COUNT) return MSP_ERR_ARG;
+    if (kind == -1) std::fill(c->tm.on.begin(), c->tm.on.end(), static_cast<char>(on ? 1 : 0));
+    else c->tm.on[kind] = on ? 1 : 0;
+    return MSP_OK;
+}
+
+int msp_reset_timing(msp_ctx* c) {
+    if (!c) return MSP_ERR_ARG;
+    std::fill(c->tm.count.begin(), c->tm.count.end(), 0);
+    std::fill(c->tm.ms.begin(), c->tm.ms.end(), 0.0);
+    std::fill(c->tm.bytes.begin(), c->tm.bytes.end(), 0.0);
+    return MSP_OK;
+}
+
+int msp_get_timing(const msp_ctx* c, int32_t kind, int64_t* count, double* total_ms, double* total_bytes) {
+    if (!c || kind < 0 || kind >= msp::KD_COUNT) return MSP_ERR_ARG;
+    if (count) *count = c->tm.count[kind];
+    if (total_ms) *total_ms = c->tm.ms[kind];
+    if (total_bytes) *total_bytes = c->tm.bytes[kind];
     return MSP_OK;
 }
 

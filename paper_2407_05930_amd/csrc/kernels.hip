@@ -324,11 +324,11 @@ __global__ __launch_bounds__(kBlock) void k_colnorm2(int64_t n, const double* __
     if (threadIdx.x == 0) out[j] = sm[0];
 }
 
-// thresholds per column a*m + j: tol * ||b_j|| / sqrt(2^s); padded columns -1
+// thresholds per column a*m + j: tol * ||b_j|| / sqrt(2^s); padded columns never start
 __global__ void k_thresholds(int C, int S, int m, double tol, const double* __restrict__ bn2,
                              double* __restrict__ thr) {
     const int c = threadIdx.x;
-    if (c < C) thr[c] = (c < S * m) ? tol * sqrt(bn2[c % m]) / sqrt((double)S) : -1.0;
+    if (c < C) thr[c] = (c < S * m) ? tol * sqrt(bn2[c % m]) / sqrt((double)S) : INFINITY;
 }
 
 // ------------------------------------------------------------------ dense coarsest level

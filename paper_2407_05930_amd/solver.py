@@ -153,6 +153,33 @@ class Solver:
                                  ritz.ctypes.data_as(ctypes.c_void_p)))
         return kept, ritz.reshape(S, max(k, 1))[:, :k]
 
+    # ------------------------------------------------------------------ timers
+    KIND_NAMES = {0: "operator", 1: "dot", 2: "update", 3: "p_update", 4: "qs", 5: "cast", 6: "dense_coarse",
+                  7: "fsai", 8: "lrc"}
+
+    @staticmethod
+    def kind_name(kind: int) -> str:
+        if kind < 16:
+            return Solver.KIND_NAMES.get(kind, f"kind{kind}")
+        lev, op = divmod(kind - 16, 8)
+        return f"L{lev}.{['A', 'G', 'GT', 'R', 'P', '?', '?', '?'][op]}"
+
+    def set_timing(self, on: bool = True, kind: int = -1):
+        check(lib.msp_set_timing(self._ctx, kind, 1 if on else 0))
+
+    def reset_timing(self):
+        check(lib.msp_reset_timing(self._ctx))
+
+    def timing(self) -> dict:
+        """{kind: (count, total_ms, total_bytes)} for kinds with launches."""
+        out = {}
+        for kind in range(16 + 8 * 20):
+            cnt, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            check(lib.msp_get_timing(self._ctx, kind, ctypes.byref(cnt), ctypes.byref(ms), ctypes.byref(by)))
+            if cnt.value:
+                out[kind] = (cnt.value, ms.value, by.value)
+        return out
+
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx.value:
             lib.msp_free(self._ctx)
