@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -28,6 +29,7 @@ static thread_local std::string g_last_error;
 // Device CSR: 32-bit row pointers and columns, FP64 and (mixed modes) FP32 values.
 struct DevCsr {
     int64_t nr = 0, nc = 0, nnz = 0;
+    int split = 1;           // lane groups per row (long rows are split)
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
     double* v64 = nullptr;
@@ -43,6 +45,7 @@ struct DevLevel {
 // Column-count-dependent workspace.
 struct Work {
     int C = 0;
+    int m = 1;                // columns per subsystem of the current solve
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *zold = nullptr;
     std::vector<void*> vy, vs, vr, vt;    // per level, element type of the V-cycle
     double* partial = nullptr;
@@ -103,9 +106,15 @@ struct msp_ctx {
     std::vector<msp::DevLevel> dl;
     double* d_cinv = nullptr;
     int64_t nL = 0;
-    msp::Work w;
-    // low-rank corrections
+    std::map<int, std::unique_ptr<msp::Work>> works;   // by padded column count
+    // low-rank corrections: U (n_b x S*k, FP64 or FP32), coefficients (S*k)
     int lrc_k = 0;
+    void* d_U = nullptr;
+    bool U32 = false;
+    double* d_lrc_coef = nullptr;
+    double* d_lrc_part = nullptr;
+    double* d_lrc_W = nullptr;
+    int lrc_nb = 0;
     std::vector<int32_t> lrc_kept;
     std::vector<double> lrc_ritz;
     msp::Timers tm;
@@ -119,9 +128,11 @@ struct msp_ctx {
             }
             for (auto e : tm.pool) (void)hipEventDestroy(e);
             for (void* p : allocs) (void)hipFree(p);
-            if (w.h_flags) (void)hipHostFree(w.h_flags);
-            if (w.h_iters) (void)hipHostFree(w.h_iters);
-            if (w.h_scal) (void)hipHostFree(w.h_scal);
+            for (auto& kv : works) {
+                if (kv.second->h_flags) (void)hipHostFree(kv.second->h_flags);
+                if (kv.second->h_iters) (void)hipHostFree(kv.second->h_iters);
+                if (kv.second->h_scal) (void)hipHostFree(kv.second->h_scal);
+            }
         }
     }
 
@@ -132,6 +143,13 @@ struct msp_ctx {
         HIPCHECK(hipMalloc(&p, sizeof(T) * static_cast<size_t>(count)));
         allocs.push_back(p);
         return static_cast<T*>(p);
+    }
+    void dfree(void* p) {
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) {
+            allocs.erase(it);
+            (void)hipFree(p);
+        }
     }
     template <typename T>
     T* upload(const T* h, int64_t count) {
@@ -154,6 +172,10 @@ static DevCsr upload_csr(msp_ctx* c, const Csr& M, bool fp32) {
     D.rp = c->upload(rp.data(), M.nr + 1);
     D.ci = c->upload(M.ci.data(), D.nnz);
     D.v64 = c->upload(M.v.data(), D.nnz);
+    // share long rows between lane groups: about 4 entries per group
+    const double avg = M.nr > 0 ? static_cast<double>(D.nnz) / static_cast<double>(M.nr) : 0.0;
+    D.split = 1;
+    while (D.split < 64 && 4.0 * D.split * 2 <= avg) D.split *= 2;
     if (fp32) {
         std::vector<float> f(M.v.begin(), M.v.end());
         D.v32 = c->upload(f.data(), D.nnz);
@@ -224,16 +246,21 @@ static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, c
                  T alpha, T beta, const double* sigma = nullptr, int S = 1, int m = 1) {
     const double bytes = c->tm.on[kind] ? spmm_bytes<T>(M, C, Z != nullptr, sigma != nullptr, S) : 0.0;
     timed(c, kind, bytes, st, [&] {
-        HIPCHECK(launch_spmm<T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m));
+        if (M.split > 1 && !sigma)
+            HIPCHECK(launch_spmm_split<T>(st, C, M.split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta));
+        else
+            HIPCHECK(launch_spmm<T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m));
     });
 }
 
 static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
 
-static void ensure_work(msp_ctx* c, int C) {
-    Work& w = c->w;
-    if (w.C == C) return;
-    if (w.C != 0) throw Error(MSP_ERR_UNSUPPORTED, "column count changed; create a new context");
+// Workspace for C padded columns (allocated on first use, kept with the context).
+static Work& work(msp_ctx* c, int C) {
+    auto it = c->works.find(C);
+    if (it != c->works.end()) return *it->second;
+    std::unique_ptr<Work> wp(new Work());
+    Work& w = *wp;
     const int64_t nb = c->sym.n_b;
     w.C = C;
     w.x = c->dalloc<double>(nb * C);
@@ -243,17 +270,19 @@ static void ensure_work(msp_ctx* c, int C) {
     w.q = c->dalloc<double>(nb * C);
     w.zold = c->dalloc<double>(nb * C);
     const size_t es = mixed(c) ? sizeof(float) : sizeof(double);
-    const size_t L = c->dl.size() + 1;
+    const size_t L = c->hier.lev.size();
     w.vy.assign(L, nullptr);
     w.vs.assign(L, nullptr);
     w.vr.assign(L, nullptr);
     w.vt.assign(L, nullptr);
-    for (size_t l = 0; l < c->hier.lev.size(); ++l) {
-        const int64_t n = c->hier.lev[l].A.nr;
-        w.vy[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
-        w.vs[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
-        w.vr[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
-        w.vt[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+    if (c->o.pc == MSP_PC_AMGR) {
+        for (size_t l = 0; l < L; ++l) {
+            const int64_t n = c->hier.lev[l].A.nr;
+            w.vy[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+            w.vs[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+            w.vr[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+            w.vt[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+        }
     }
     w.nb_dot = 1024;
     w.partial = c->dalloc<double>(static_cast<int64_t>(w.nb_dot) * 64);
@@ -263,12 +292,13 @@ static void ensure_work(msp_ctx* c, int C) {
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_iters), 64 * sizeof(int), hipHostMallocDefault));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_scal), SC_COUNT * 64 * sizeof(double),
                            hipHostMallocDefault));
+    c->works[C] = std::move(wp);
+    return w;
 }
 
 // One V(1,1) cycle of Alg. 3 on level l: s = M_l^{-1} y, all C columns.
 template <typename T>
-static void vcycle(msp_ctx* c, hipStream_t st, size_t l, const T* y, T* s) {
-    Work& w = c->w;
+static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T* s) {
     const int C = w.C;
     if (l + 1 == c->hier.lev.size()) {
         const double bytes = 8.0 * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
@@ -286,7 +316,7 @@ static void vcycle(msp_ctx* c, hipStream_t st, size_t l, const T* y, T* s) {
     spmm<T>(c, kb + 2, st, C, L.GT, t, s, nullptr, om, T(0));
     spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // r = y - A s
     spmm<T>(c, kb + 3, st, C, L.R, r, yc, nullptr, T(1), T(0));    // r_c = P^T r
-    vcycle<T>(c, st, l + 1, yc, sc);                               // coarse correction
+    vcycle<T>(c, w, st, l + 1, yc, sc);                            // coarse correction
     spmm<T>(c, kb + 4, st, C, L.P, sc, s, s, T(1), T(1));          // s += P h_c
     spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // post-smooth: s += w G^T G (y - A s)
     spmm<T>(c, kb + 1, st, C, L.G, r, t, nullptr, T(1), T(0));
@@ -294,14 +324,33 @@ static void vcycle(msp_ctx* c, hipStream_t st, size_t l, const T* y, T* s) {
 }
 
 // out[c] = <X_c, Y_c> for the C columns of two n_b x C multivectors.
-static void dot(msp_ctx* c, hipStream_t st, int C, int64_t nb, const double* X, const double* Y, double* out) {
+static void dot(msp_ctx* c, Work& w, hipStream_t st, const double* X, const double* Y, double* out) {
+    const int64_t nb = c->sym.n_b;
+    const int C = w.C;
     timed(c, KD_DOT, 16.0 * nb * C, st,
-          [&] { HIPCHECK(launch_dot<double>(st, C, nb, X, Y, c->w.partial, c->w.nb_dot, out)); });
+          [&] { HIPCHECK(launch_dot<double>(st, C, nb, X, Y, w.partial, w.nb_dot, out)); });
 }
 
-// z = M^{-1} r on all columns (shared preconditioner).
-static void precondition(msp_ctx* c, hipStream_t st, const double* r, double* z) {
-    Work& w = c->w;
+// z += U_a diag(coef_a) U_a^T r_a for every subsystem a (low-rank corrections).
+static void lrc_apply(msp_ctx* c, Work& w, hipStream_t st, const double* r, double* z) {
+    const int64_t nb = c->sym.n_b;
+    const int S = 1 << c->sym.s, k = c->lrc_k;
+    const double bytes = 2.0 * nb * S * k * (c->U32 ? 4.0 : 8.0) + 3.0 * 8.0 * nb * w.C;
+    timed(c, KD_LRC, bytes, st, [&] {
+        if (c->U32)
+            HIPCHECK(launch_lrc_apply<float>(st, nb, S, k, w.m, w.C, static_cast<const float*>(c->d_U), r, z,
+                                             c->d_lrc_coef, c->d_lrc_part, c->lrc_nb, c->d_lrc_W));
+        else
+            HIPCHECK(launch_lrc_apply<double>(st, nb, S, k, w.m, w.C, static_cast<const double*>(c->d_U), r, z,
+                                              c->d_lrc_coef, c->d_lrc_part, c->lrc_nb, c->d_lrc_W));
+    });
+}
+
+// The shared preconditioner without corrections: the V-cycle (AMGR), G^T G
+// (FSAI) or the identity.  For FSAI with corrections the correction acts on
+// t = G r before the G^T product: z = G^T (t + V Theta V^T t).
+static void precondition_base(msp_ctx* c, Work& w, hipStream_t st, const double* r, double* z,
+                              bool with_lrc_fsai) {
     const int C = w.C;
     const int64_t nb = c->sym.n_b;
     if (c->o.pc == MSP_PC_AMGR) {
@@ -309,18 +358,30 @@ static void precondition(msp_ctx* c, hipStream_t st, const double* r, double* z)
             float* y0 = static_cast<float*>(w.vy[0]);
             float* s0 = static_cast<float*>(w.vs[0]);
             timed(c, KD_CAST, 12.0 * nb * C, st, [&] { HIPCHECK((launch_cast<float, double>(st, nb * C, r, y0))); });
-            vcycle<float>(c, st, 0, y0, s0);
+            vcycle<float>(c, w, st, 0, y0, s0);
             timed(c, KD_CAST, 12.0 * nb * C, st, [&] { HIPCHECK((launch_cast<double, float>(st, nb * C, s0, z))); });
         } else {
-            vcycle<double>(c, st, 0, r, z);
+            vcycle<double>(c, w, st, 0, r, z);
         }
     } else if (c->o.pc == MSP_PC_FSAI) {
-        double* t = w.zold;   // scratch (FSAI mode never needs the flexible copy)
+        double* t = w.zold;   // scratch (the FSAI mode keeps no flexible copy)
         spmm<double>(c, KD_FSAI, st, C, c->dGf, r, t, nullptr, 1.0, 0.0);
+        if (with_lrc_fsai && c->d_U) {
+            // t += V Theta V^T t: apply in place through a copy of t held in z
+            HIPCHECK(hipMemcpyAsync(z, t, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
+            lrc_apply(c, w, st, z, t);
+        }
         spmm<double>(c, KD_FSAI, st, C, c->dGfT, t, z, nullptr, 1.0, 0.0);
     } else {
         HIPCHECK(hipMemcpyAsync(z, r, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
     }
+}
+
+// z = M^{-1} r on all columns: the shared preconditioner plus the
+// per-subsystem low-rank corrections.
+static void precondition(msp_ctx* c, Work& w, hipStream_t st, const double* r, double* z) {
+    precondition_base(c, w, st, r, z, true);
+    if (c->d_U && c->o.pc == MSP_PC_AMGR) lrc_apply(c, w, st, r, z);
 }
 
 static void upload_all(msp_ctx* c) {
@@ -365,8 +426,8 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
     const int ncol = S * m;
     if (ncol > 64) throw Error(MSP_ERR_UNSUPPORTED, "2^s * m must not exceed 64");
     const int C = next_pow2(ncol);
-    ensure_work(c, C);
-    Work& w = c->w;
+    Work& w = work(c, C);
+    w.m = m;
     const int64_t nb = c->sym.n_b, n = c->sym.n;
     double* sc = w.scal;
     double *rr = sc + SC_RR * 64, *rz = sc + SC_RZ * 64, *pq = sc + SC_PQ * 64, *rho = sc + SC_RHO * 64,
@@ -384,9 +445,9 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
     HIPCHECK(launch_fill<double>(st, nb * C, w.x, 0.0));
     timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // bhat = Q_s b
           [&] { HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, w.r)); });
-    precondition(c, st, w.r, w.z);
-    dot(c, st, C, nb, w.r, w.r, rr);
-    dot(c, st, C, nb, w.r, w.z, rz);
+    precondition(c, w, st, w.r, w.z);
+    dot(c, w, st, w.r, w.r, rr);
+    dot(c, w, st, w.r, w.z, rz);
     HIPCHECK(launch_pcg_init(st, C, rr, rz, thr, active, rho, iters, flags, rnorm));
     HIPCHECK(hipMemcpyAsync(w.p, w.z, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
     HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -396,11 +457,11 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
     int status = MSP_OK;
     while (nactive > 0 && it < c->o.maxit) {
         spmm<double>(c, KD_OP, st, C, c->dAinn, w.p, w.q, nullptr, 1.0, 0.0, c->d_sigma, S, m);   // q = Ahat p
-        dot(c, st, C, nb, w.p, w.q, pq);
+        dot(c, w, st, w.p, w.q, pq);
         HIPCHECK(launch_pcg_alpha(st, C, pq, active, rho, alpha, flags));
         timed(c, KD_UPDATE, 48.0 * nb * C, st,
               [&] { HIPCHECK(launch_pcg_update(st, C, nb, w.x, w.r, w.p, w.q, alpha)); });
-        dot(c, st, C, nb, w.r, w.r, rr);
+        dot(c, w, st, w.r, w.r, rr);
         HIPCHECK(launch_pcg_check(st, C, rr, thr, active, iters, flags, rnorm));
         HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
@@ -411,9 +472,9 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
         }
         nactive = w.h_flags[1];
         if (nactive == 0) break;
-        if (flexible) dot(c, st, C, nb, w.r, w.z, rzold);
-        precondition(c, st, w.r, w.z);
-        dot(c, st, C, nb, w.r, w.z, rz);
+        if (flexible) dot(c, w, st, w.r, w.z, rzold);
+        precondition(c, w, st, w.r, w.z);
+        dot(c, w, st, w.r, w.z, rz);
         HIPCHECK(launch_pcg_beta(st, C, rz, rzold, active, rho, beta, flexible ? 1 : 0));
         timed(c, KD_PUPDATE, 24.0 * nb * C, st,
               [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, w.p, w.z, beta, active)); });
@@ -675,8 +736,152 @@ const char* msp_last_error(void) { return msp::g_last_error.c_str(); }
 }  // extern "C"
 
 namespace msp {
+
+// Low-rank corrections (Sec. 2.1 eq. (2.20), Sec. 2.2 eq. (2.27)), eigenpairs by
+// Lanczos with full reorthogonalisation, run for all 2^s subsystems at once as
+// the columns of one multivector:
+//   AMGR: operator M^{-1} A_a in the A_a inner product (M^{-1} = the shared
+//         V-cycle); corrections u_t (A_a-orthonormal Ritz vectors) with
+//         coefficient 1 - lam_t for the k smallest Ritz values below 1.
+//   FSAI: operator G A_a G^T, Euclidean; corrections v_t with coefficient
+//         1/lam_t - 1, applied between the G and G^T products.
+// Start vector v_i = splitmix64(seed ^ i ^ 0x1CC)/2^64 - 1/2 (all subsystems),
+// max(4k, 40) steps (at most n_b).
 void build_lrc(msp_ctx* c) {
-    (void)c;
-    throw Error(MSP_ERR_UNSUPPORTED, "low-rank corrections are not available in this build yet");
+    const int S = 1 << c->sym.s;
+    const int k = c->lrc_k;
+    const int64_t n = c->sym.n_b;
+    const int K = static_cast<int>(std::min<int64_t>(std::max(4 * k, 40), n));
+    const int C = next_pow2(S);
+    const bool amg = c->o.pc == MSP_PC_AMGR;
+    Work& w = work(c, C);
+    w.m = 1;
+    hipStream_t st = nullptr;
+    const int64_t len = n * C;
+    double* V = c->dalloc<double>(static_cast<int64_t>(K) * len);
+    double* BV = amg ? c->dalloc<double>(static_cast<int64_t>(K) * len) : V;
+    double* hcoef = c->dalloc<double>(static_cast<int64_t>(K) * 64);
+    double* dvec = c->dalloc<double>(64);
+    double* wv = w.x;    // w
+    double* bw = w.q;    // B w
+    double* tmp = w.p;
+    std::vector<double> h(64), hv(len);
+
+    auto applyB = [&](const double* x, double* y) {   // y = A_a x per column
+        spmm<double>(c, KD_OP, st, C, c->dAinn, x, y, nullptr, 1.0, 0.0, c->d_sigma, S, 1);
+    };
+    auto op = [&](const double* v, const double* bv, double* out) {
+        if (amg) {
+            precondition_base(c, w, st, bv, out, false);
+        } else {
+            spmm<double>(c, KD_FSAI, st, C, c->dGfT, v, tmp, nullptr, 1.0, 0.0);
+            applyB(tmp, w.z);
+            spmm<double>(c, KD_FSAI, st, C, c->dGf, w.z, out, nullptr, 1.0, 0.0);
+        }
+    };
+    auto coldots = [&](const double* X, const double* Y, double* out_host) {
+        dot(c, w, st, X, Y, dvec);
+        HIPCHECK(hipMemcpyAsync(out_host, dvec, C * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+    };
+    auto scale_into = [&](double* dst, const double* src, const std::vector<double>& f) {
+        HIPCHECK(hipMemcpyAsync(dvec, f.data(), C * sizeof(double), hipMemcpyHostToDevice, st));
+        if (dst != src) HIPCHECK(hipMemcpyAsync(dst, src, len * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHECK(launch_scale_cols<double>(st, len, C, dst, dvec));
+    };
+
+    // start vector, replicated over the subsystem columns (padded columns zero)
+    for (int64_t i = 0; i < n; ++i) {
+        const double v = unit_centered(c->o.seed ^ static_cast<uint64_t>(i) ^ 0x1CCull);
+        for (int a = 0; a < C; ++a) hv[i * C + a] = a < S ? v : 0.0;
+    }
+    HIPCHECK(hipMemcpy(V, hv.data(), len * sizeof(double), hipMemcpyHostToDevice));
+    if (amg) applyB(V, BV);
+    coldots(V, BV, h.data());
+    std::vector<double> f(C, 0.0);
+    for (int a = 0; a < S; ++a) f[a] = 1.0 / std::sqrt(h[a]);
+    scale_into(V, V, f);
+    if (amg) scale_into(BV, BV, f);
+
+    std::vector<std::vector<double>> alpha(S), beta(S);
+    std::vector<int> nsteps(S, 0);
+    std::vector<char> live(S, 1);
+    std::vector<double> al(64), b2(64);
+    for (int j = 0; j < K; ++j) {
+        double* Vj = V + static_cast<int64_t>(j) * len;
+        double* BVj = BV + static_cast<int64_t>(j) * len;
+        op(Vj, BVj, wv);
+        coldots(wv, BVj, al.data());
+        // classical Gram-Schmidt, twice, against every basis vector so far
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i = 0; i <= j; ++i)
+                dot(c, w, st, wv, BV + static_cast<int64_t>(i) * len, hcoef + static_cast<int64_t>(i) * 64);
+            for (int i = 0; i <= j; ++i)
+                HIPCHECK(launch_axpy_cols(st, len, C, wv, V + static_cast<int64_t>(i) * len,
+                                          hcoef + static_cast<int64_t>(i) * 64));
+        }
+        if (amg) applyB(wv, bw);
+        coldots(wv, amg ? bw : wv, b2.data());
+        for (int a = 0; a < S; ++a) {
+            if (!live[a]) continue;
+            alpha[a].push_back(al[a]);
+            nsteps[a] = j + 1;
+            const double b = std::sqrt(std::max(b2[a], 0.0));
+            if (j == K - 1 || b <= 1e-13 * std::fabs(al[a])) {
+                live[a] = 0;
+                f[a] = 0.0;
+            } else {
+                beta[a].push_back(b);
+                f[a] = 1.0 / b;
+            }
+        }
+        if (j + 1 < K) {
+            scale_into(V + static_cast<int64_t>(j + 1) * len, wv, f);
+            if (amg) scale_into(BV + static_cast<int64_t>(j + 1) * len, bw, f);
+        }
+    }
+
+    // Ritz pairs per subsystem: k smallest, keep those below 1
+    std::vector<double> cm(static_cast<size_t>(S) * K * k, 0.0), coef(static_cast<size_t>(S) * k, 0.0);
+    c->lrc_ritz.assign(static_cast<size_t>(S) * k, 0.0);
+    c->lrc_kept.assign(S, 0);
+    for (int a = 0; a < S; ++a) {
+        const int m = nsteps[a];
+        std::vector<double> T(static_cast<size_t>(m) * m, 0.0), ev, Q;
+        for (int i = 0; i < m; ++i) {
+            T[i * m + i] = alpha[a][i];
+            if (i + 1 < m) T[i * m + i + 1] = T[(i + 1) * m + i] = beta[a][i];
+        }
+        sym_eig(m, T, ev, Q);
+        for (int t = 0; t < k && t < m; ++t) {
+            const double lam = ev[t];
+            c->lrc_ritz[a * k + t] = lam;
+            if (!(lam < 1.0) || !(lam > 0.0)) continue;
+            coef[a * k + t] = amg ? 1.0 - lam : 1.0 / lam - 1.0;
+            c->lrc_kept[a] += 1;
+            for (int j = 0; j < m; ++j) cm[(static_cast<size_t>(a) * K + j) * k + t] = Q[j * m + t];
+        }
+    }
+    double* dcm = c->upload(cm.data(), static_cast<int64_t>(cm.size()));
+    c->U32 = mixed(c);
+    if (c->U32) {
+        float* U = c->dalloc<float>(n * S * k);
+        HIPCHECK(launch_lrc_combine<float>(st, n, S, k, K, C, V, dcm, U));
+        c->d_U = U;
+    } else {
+        double* U = c->dalloc<double>(n * S * k);
+        HIPCHECK(launch_lrc_combine<double>(st, n, S, k, K, C, V, dcm, U));
+        c->d_U = U;
+    }
+    c->d_lrc_coef = c->upload(coef.data(), static_cast<int64_t>(coef.size()));
+    c->lrc_nb = 512;
+    c->d_lrc_part = c->dalloc<double>(static_cast<int64_t>(c->lrc_nb) * S * k * 64);
+    c->d_lrc_W = c->dalloc<double>(static_cast<int64_t>(S) * k * 64);
+    HIPCHECK(hipStreamSynchronize(st));
+    c->dfree(dcm);
+    c->dfree(hcoef);
+    if (amg) c->dfree(BV);
+    c->dfree(V);
 }
+
 }  // namespace msp

@@ -85,6 +85,60 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
     st<T, VW>(Y + row * C + lane * VW, out);
 }
 
+// Split-row SpMM for long rows (coarse levels): each row is shared by G lane
+// groups (G * LPR threads); group g accumulates entries k0 + g, k0 + g + G, ...
+// and the G partial rows are summed in LDS in a fixed order.
+template <typename T, int C, int G>
+__global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci,
+                                                       const T* __restrict__ va, const T* __restrict__ X,
+                                                       T* Y, const T* Z, T alpha, T beta) {
+    using L = Lanes<T, C>;
+    constexpr int VW = L::VW;
+    constexpr int TPR = G * L::LPR;             // threads per row
+    constexpr int RPB = kBlock / TPR;           // rows per block
+    __shared__ T sm[kBlock * VW];
+    const int slot = threadIdx.x / TPR;
+    const int g = (threadIdx.x % TPR) / L::LPR;
+    const int lane = threadIdx.x % L::LPR;
+    const int64_t row = (int64_t)blockIdx.x * RPB + slot;
+    T acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = T(0);
+    if (row < n) {
+        const int32_t k1 = rp[row + 1];
+        for (int32_t k = rp[row] + g; k < k1; k += G) {
+            const int32_t c = ci[k];
+            const T a = va[k];
+            const Pack<T, VW> x = ld<T, VW>(X + (int64_t)c * C + lane * VW);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[e] += a * x.e[e];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < VW; ++e) sm[threadIdx.x * VW + e] = acc[e];
+    __syncthreads();
+    if (g == 0 && row < n) {
+        // sm index of (slot, group q, lane, e) = ((slot * G + q) * LPR + lane) * VW + e
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] = T(0);
+        for (int q = 0; q < G; ++q) {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[e] += sm[((slot * G + q) * L::LPR + lane) * VW + e];
+        }
+        Pack<T, VW> out;
+        if (Z) {
+            const Pack<T, VW> z = ld<T, VW>(Z + row * C + lane * VW);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) out.e[e] = alpha * acc[e] + beta * z.e[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) out.e[e] = alpha * acc[e];
+        }
+        st<T, VW>(Y + row * C + lane * VW, out);
+    }
+}
+
 // ------------------------------------------------------------------ per-column dots
 // partial[block * C + c] = sum over this block's rows of X[row, c] * Y[row, c]
 // (FP64 accumulation); rows are visited grid-stride, the in-block reduction
@@ -332,29 +386,43 @@ __global__ void k_thresholds(int C, int S, int m, double tol, const double* __re
 }
 
 // ------------------------------------------------------------------ dense coarsest level
-// out[i, :] = sum_k Minv[i, k] * y[k, :] in FP64 (inputs/outputs of type T)
+// out[i, :] = sum_k Minv[i, k] * y[k, :] in FP64 (inputs/outputs of type T).
+// One block per row: the 256 / LPR lane groups split k and their partial
+// rows are summed in LDS in a fixed order.
 template <typename T, int C>
 __global__ __launch_bounds__(kBlock) void k_dense(int64_t nL, const double* __restrict__ Minv,
                                                   const T* __restrict__ y, T* __restrict__ out) {
     using L = Lanes<T, C>;
     constexpr int VW = L::VW;
-    const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
+    constexpr int G = kBlock / L::LPR;
+    __shared__ double sm[kBlock * VW];
+    const int64_t row = blockIdx.x;
+    const int g = threadIdx.x / L::LPR;
     const int lane = threadIdx.x % L::LPR;
-    if (row >= nL) return;
     double acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = 0.0;
     const double* mr = Minv + row * nL;
-    for (int64_t k = 0; k < nL; ++k) {
+    for (int64_t k = g; k < nL; k += G) {
         const double a = mr[k];
         const Pack<T, VW> x = ld<T, VW>(y + k * C + lane * VW);
 #pragma unroll
         for (int e = 0; e < VW; ++e) acc[e] += a * (double)x.e[e];
     }
-    Pack<T, VW> o;
 #pragma unroll
-    for (int e = 0; e < VW; ++e) o.e[e] = (T)acc[e];
-    st<T, VW>(out + row * C + lane * VW, o);
+    for (int e = 0; e < VW; ++e) sm[threadIdx.x * VW + e] = acc[e];
+    __syncthreads();
+    if (g == 0) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] = 0.0;
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[e] += sm[(q * L::LPR + lane) * VW + e];
+        Pack<T, VW> o;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) o.e[e] = (T)acc[e];
+        st<T, VW>(out + row * C + lane * VW, o);
+    }
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -368,6 +436,91 @@ template <typename TO, typename TI>
 __global__ __launch_bounds__(kBlock) void k_cast(int64_t len, const TI* __restrict__ a, TO* __restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < len) b[i] = (TO)a[i];
+}
+
+// ------------------------------------------------------------------ column-wise vector ops
+// X[:, c] *= f[c]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_cols(int64_t len, int C, T* __restrict__ X,
+                                                       const double* __restrict__ f) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) X[i] = (T)((double)X[i] * f[i % C]);
+}
+
+// Y[:, c] -= h[c] * X[:, c]
+__global__ __launch_bounds__(kBlock) void k_axpy_cols(int64_t len, int C, double* __restrict__ Y,
+                                                      const double* __restrict__ X, const double* __restrict__ h) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) Y[i] -= h[i % C] * X[i];
+}
+
+// ------------------------------------------------------------------ low-rank corrections
+// U is n x (S * k) row-major: U[i, a*k + t] is entry i of correction vector t
+// of subsystem a.  Subsystem a owns multivector columns a*m .. a*m + m - 1.
+
+// U[i, a*k + t] = sum_j V_j[i, a] * cm[(a*K + j)*k + t] (Ritz vectors from the
+// Lanczos basis V_j, stored n x C with C >= S, one column per subsystem).
+template <typename TU>
+__global__ __launch_bounds__(kBlock) void k_lrc_combine(int64_t n, int S, int k, int K, int C,
+                                                        const double* __restrict__ V,
+                                                        const double* __restrict__ cm, TU* __restrict__ U) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= n * S * k) return;
+    const int64_t i = idx / (S * k);
+    const int at = (int)(idx % (S * k));
+    const int a = at / k, t = at % k;
+    double s = 0.0;
+    for (int j = 0; j < K; ++j) s += V[((int64_t)j * n + i) * C + a] * cm[((int64_t)a * K + j) * k + t];
+    U[idx] = (TU)s;
+}
+
+// partial[b, o] = sum over block b's rows of U[i, a*k+t] * R[i, a*m+j],
+// o = (a*k + t)*m + j.  Rows are split into gridDim.x contiguous chunks.
+template <typename TU>
+__global__ __launch_bounds__(kBlock) void k_lrc_project(int64_t n, int S, int k, int m, int C,
+                                                        const TU* __restrict__ U, const double* __restrict__ R,
+                                                        double* __restrict__ partial) {
+    const int O = S * k * m;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk;
+    const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+    for (int o = threadIdx.x; o < O; o += kBlock) {
+        const int j = o % m;
+        const int at = o / m;
+        const int a = at / k;
+        double s = 0.0;
+        for (int64_t i = r0; i < r1; ++i)
+            s += (double)U[i * (S * k) + at] * R[i * C + a * m + j];
+        partial[(int64_t)blockIdx.x * O + o] = s;
+    }
+}
+
+// W[o] = coef[a*k + t] * sum_b partial[b, o]  (fixed order over b)
+__global__ __launch_bounds__(kBlock) void k_lrc_finish(int nb, int O, int k, int m,
+                                                       const double* __restrict__ partial,
+                                                       const double* __restrict__ coef, double* __restrict__ W) {
+    const int o = blockIdx.x * kBlock + threadIdx.x;
+    if (o >= O) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * O + o];
+    W[o] = coef[o / m] * s;
+}
+
+// Z[i, a*m+j] += sum_t U[i, a*k+t] * W[(a*k+t)*m + j] for columns < S*m
+template <typename TU>
+__global__ __launch_bounds__(kBlock) void k_lrc_expand(int64_t n, int S, int k, int m, int C,
+                                                       const TU* __restrict__ U, const double* __restrict__ W,
+                                                       double* __restrict__ Z) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= n * C) return;
+    const int64_t i = idx / C;
+    const int col = (int)(idx % C);
+    if (col >= S * m) return;
+    const int a = col / m, j = col % m;
+    double s = 0.0;
+    const TU* u = U + i * (S * k) + a * k;
+    for (int t = 0; t < k; ++t) s += (double)u[t] * W[(a * k + t) * m + j];
+    Z[idx] += s;
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -399,6 +552,42 @@ hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, cons
     });
     return hipGetLastError();
 }
+template <typename T, int CC, int G>
+static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const T* va, const T* X,
+                         T* Y, const T* Z, T alpha, T beta) {
+    constexpr int TPR = G * Lanes<T, CC>::LPR;
+    if constexpr (TPR <= kBlock) {
+        constexpr int RPB = kBlock / TPR;
+        hipLaunchKernelGGL((k_spmm_split<T, CC, G>), dim3(blocks_for(n, RPB)), dim3(kBlock), 0, st, n, rp, ci, va,
+                           X, Y, Z, alpha, beta);
+    }
+}
+
+template <typename T>
+hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
+                             const T* va, const T* X, T* Y, const T* Z, T alpha, T beta) {
+    if (n <= 0) return hipSuccess;
+    MSP_DISPATCH_C(C, {
+        constexpr int LPR = Lanes<T, CC>::LPR;
+        const int gmax = kBlock / LPR;
+        const int g = G < gmax ? G : gmax;
+        switch (g) {
+            case 2: launch_split<T, CC, 2>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 4: launch_split<T, CC, 4>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 8: launch_split<T, CC, 8>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 16: launch_split<T, CC, 16>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 32: launch_split<T, CC, 32>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 64: launch_split<T, CC, 64>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            default: launch_split<T, CC, 1>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+        }
+    });
+    return hipGetLastError();
+}
+template hipError_t launch_spmm_split<double>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,
+                                              const double*, const double*, double*, const double*, double, double);
+template hipError_t launch_spmm_split<float>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,
+                                             const float*, const float*, float*, const float*, float, float);
+
 template hipError_t launch_spmm<double>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const double*,
                                         const double*, double*, const double*, double, double, const double*, int,
                                         int);
@@ -501,7 +690,7 @@ template <typename T>
 hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out) {
     MSP_DISPATCH_C(C, {
         using L = Lanes<T, CC>;
-        hipLaunchKernelGGL((k_dense<T, CC>), dim3(blocks_for(nL, L::RPB)), dim3(kBlock), 0, st, nL, Minv, y, out);
+        hipLaunchKernelGGL((k_dense<T, CC>), dim3((unsigned)nL), dim3(kBlock), 0, st, nL, Minv, y, out);
     });
     return hipGetLastError();
 }
@@ -516,6 +705,48 @@ hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {
 }
 template hipError_t launch_fill<double>(hipStream_t, int64_t, double*, double);
 template hipError_t launch_fill<float>(hipStream_t, int64_t, float*, float);
+
+template <typename T>
+hipError_t launch_scale_cols(hipStream_t st, int64_t len, int C, T* X, const double* f) {
+    if (len <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_scale_cols<T>), dim3(blocks_for(len, kBlock)), dim3(kBlock), 0, st, len, C, X, f);
+    return hipGetLastError();
+}
+template hipError_t launch_scale_cols<double>(hipStream_t, int64_t, int, double*, const double*);
+
+hipError_t launch_axpy_cols(hipStream_t st, int64_t len, int C, double* Y, const double* X, const double* h) {
+    if (len <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy_cols, dim3(blocks_for(len, kBlock)), dim3(kBlock), 0, st, len, C, Y, X, h);
+    return hipGetLastError();
+}
+
+template <typename TU>
+hipError_t launch_lrc_combine(hipStream_t st, int64_t n, int S, int k, int K, int C, const double* V,
+                              const double* cm, TU* U) {
+    hipLaunchKernelGGL((k_lrc_combine<TU>), dim3(blocks_for(n * S * k, kBlock)), dim3(kBlock), 0, st, n, S, k, K,
+                       C, V, cm, U);
+    return hipGetLastError();
+}
+template hipError_t launch_lrc_combine<double>(hipStream_t, int64_t, int, int, int, int, const double*,
+                                               const double*, double*);
+template hipError_t launch_lrc_combine<float>(hipStream_t, int64_t, int, int, int, int, const double*,
+                                              const double*, float*);
+
+template <typename TU>
+hipError_t launch_lrc_apply(hipStream_t st, int64_t n, int S, int k, int m, int C, const TU* U, const double* R,
+                            double* Z, const double* coef, double* partial, int nb, double* W) {
+    const int O = S * k * m;
+    hipLaunchKernelGGL((k_lrc_project<TU>), dim3(nb), dim3(kBlock), 0, st, n, S, k, m, C, U, R, partial);
+    hipLaunchKernelGGL(k_lrc_finish, dim3(blocks_for(O, kBlock)), dim3(kBlock), 0, st, nb, O, k, m, partial, coef,
+                       W);
+    hipLaunchKernelGGL((k_lrc_expand<TU>), dim3(blocks_for(n * C, kBlock)), dim3(kBlock), 0, st, n, S, k, m, C, U,
+                       W, Z);
+    return hipGetLastError();
+}
+template hipError_t launch_lrc_apply<double>(hipStream_t, int64_t, int, int, int, int, const double*, const double*,
+                                             double*, const double*, double*, int, double*);
+template hipError_t launch_lrc_apply<float>(hipStream_t, int64_t, int, int, int, int, const float*, const double*,
+                                            double*, const double*, double*, int, double*);
 
 template <typename TO, typename TI>
 hipError_t launch_cast(hipStream_t st, int64_t len, const TI* a, TO* b) {

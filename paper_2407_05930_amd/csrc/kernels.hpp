@@ -11,6 +11,10 @@ namespace msp {
 template <typename T>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const T* va,
                        const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m);
+// Same product for long rows: G lane groups share each row (G a power of two).
+template <typename T>
+hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
+                             const T* va, const T* X, T* Y, const T* Z, T alpha, T beta);
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
                       double* out);
@@ -41,5 +45,20 @@ template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v);
 template <typename TO, typename TI>
 hipError_t launch_cast(hipStream_t st, int64_t len, const TI* a, TO* b);
+
+// column-wise: X[:, c] *= f[c]; Y[:, c] -= h[c] X[:, c]  (len = rows * C)
+template <typename T>
+hipError_t launch_scale_cols(hipStream_t st, int64_t len, int C, T* X, const double* f);
+hipError_t launch_axpy_cols(hipStream_t st, int64_t len, int C, double* Y, const double* X, const double* h);
+
+// Low-rank corrections; U is n x (S*k): U[i, a*k+t].
+// combine: U[i, a*k+t] = sum_j V_j[i, a] cm[(a*K + j)*k + t]  (V: K blocks of n x C)
+template <typename TU>
+hipError_t launch_lrc_combine(hipStream_t st, int64_t n, int S, int k, int K, int C, const double* V,
+                              const double* cm, TU* U);
+// apply: Z[:, a*m+j] += U_a diag(coef_a) U_a^T R[:, a*m+j]  (partial: nb * S*k*m, W: S*k*m scratch)
+template <typename TU>
+hipError_t launch_lrc_apply(hipStream_t st, int64_t n, int S, int k, int m, int C, const TU* U, const double* R,
+                            double* Z, const double* coef, double* partial, int nb, double* W);
 
 }  // namespace msp

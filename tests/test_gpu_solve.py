@@ -127,3 +127,36 @@ def test_full_size_channel_config_properties():
              sv.stats.t_setup_s)
         assert np.all(rr <= 2e-10)
         sv.close()
+
+
+@pytest.mark.parametrize("pc,k", [("amgr", 4), ("amgr", 8), ("fsai", 8)])
+def test_lrc_matches_oracle(pc, k):
+    """Low-rank corrected solves: Ritz values of the device Lanczos match the
+    oracle's; iteration counts within one; solutions within 1e-9."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("lrc", pc, k)
+    p = make_problem((16, 16, 16), s=3, m=2, seed=9, y_stretch=1.5)
+    opt = dict(coarse_max=48)
+    ctx = krylov.setup(p.A, p.img, amg.AMGOptions(**opt) if pc == "amgr" else None, precond=pc, k=k)
+    ref = krylov.solve(ctx, p.b, tol=1e-10)
+    sv = Solver(p.A, p.img, tol=1e-10, pc=pc, k=k, **(opt if pc == "amgr" else {}))
+    kept, ritz = sv.export_lrc()
+    for a in range(8):
+        assert np.abs(ritz[a] - ctx["lrc"].ritz[a]).max() <= 1e-8 * max(1.0, np.abs(ctx["lrc"].ritz[a]).max())
+        assert kept[a] == ctx["lrc"].U[a].shape[1]
+    x = sv.solve(torch.from_numpy(p.b).cuda()).cpu().numpy()
+    _say("its gpu", sv.last.iters, "oracle", ref.iters.max())
+    assert abs(sv.last.iters - int(ref.iters.max())) <= 1
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-9
+
+
+def test_lrc_mixed_precision_reaches_tolerance():
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    p = make_problem((24, 24, 24), s=3, m=2, seed=4, y_stretch=1.5)
+    sv = Solver(p.A, p.img, tol=1e-10, precision="mixed", k=8, coarse_max=64)
+    x = sv.solve(torch.from_numpy(p.b).cuda()).cpu().numpy()
+    rr = krylov.true_relres(p.A, x, p.b)
+    _say("mixed lrc its", sv.last.iters, rr)
+    assert np.all(rr <= 1.5e-10)
