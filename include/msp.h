@@ -156,7 +156,8 @@ int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz);
      2 x/r update, 3 p update, 4 Q_s butterflies, 5 precision casts,
      6 dense coarsest solve, 7 FSAI preconditioner products,
      8 low-rank corrections,
-     16 + 8*l + {0: A_l, 1: G_l, 2: G_l^T, 3: R_l = P_l^T, 4: P_l} (V-cycle level l).
+     16 + 8*l + {0: A_l, 1: M_l = omega_l G_l^T G_l, 3: R_l = P_l^T, 4: P_l}
+     (V-cycle level l).
    While a kind is on, each of its launches is bracketed by HIP events on
    the solve's stream; totals are folded in when the solve returns.
    msp_set_timing(c, -1, on) switches every kind.  total_bytes sums the

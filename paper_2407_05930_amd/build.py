@@ -30,6 +30,7 @@ SOURCES = [
     ("api.cpp", []),
     ("lrc.cpp", []),
     ("kernels.hip", DEVICE),
+    ("pcg.hip", DEVICE),
 ]
 
 

@@ -13,6 +13,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "pcg.hpp"
 
 namespace msp {
 
@@ -30,6 +31,7 @@ static thread_local std::string g_last_error;
 struct DevCsr {
     int64_t nr = 0, nc = 0, nnz = 0;
     int split = 1;           // lane groups per row (long rows are split)
+    int tuned[2][7] = {};    // autotuned split by [FP32?][log2 C]; 0 = not tuned
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
     double* v64 = nullptr;
@@ -37,7 +39,7 @@ struct DevCsr {
 };
 
 struct DevLevel {
-    DevCsr A, P, R, G, GT;
+    DevCsr A, P, R, M;
     double omega = 0.0;
     int64_t n = 0;
 };
@@ -47,9 +49,11 @@ struct Work {
     int C = 0;
     int m = 1;                // columns per subsystem of the current solve
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *zold = nullptr;
-    std::vector<void*> vy, vs, vr, vt;    // per level, element type of the V-cycle
+    std::vector<void*> vy, vs, vr;        // per level, element type of the V-cycle
     double* partial = nullptr;
     int nb_dot = 0;
+    // partials of the fused PCG kernels: two column sets and the low-rank projections
+    double *pp1 = nullptr, *pp2 = nullptr, *plrc = nullptr;
     double* scal = nullptr;   // 10 arrays of 64
     int* iscal = nullptr;     // active[64], iters[64], flags[2]
     int* h_flags = nullptr;   // pinned host copy of flags
@@ -241,16 +245,80 @@ static double spmm_bytes(const DevCsr& M, int C, bool z, bool sig, int S) {
     return b;
 }
 
+static int log2i(int C) {
+    int l = 0;
+    while ((1 << l) < C) ++l;
+    return l;
+}
+
+// One SpMM launch with an explicit lane-group split (1 = one group per row).
+template <typename T>
+static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const T* X, T* Y, const T* Z, T alpha,
+                        T beta, const double* sigma, int S, int m) {
+    if (split > 1 && !sigma)
+        HIPCHECK(launch_spmm_split<T>(st, C, split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta));
+    else
+        HIPCHECK(launch_spmm<T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m));
+}
+
 template <typename T>
 static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, const T* X, T* Y, const T* Z,
                  T alpha, T beta, const double* sigma = nullptr, int S = 1, int m = 1) {
     const double bytes = c->tm.on[kind] ? spmm_bytes<T>(M, C, Z != nullptr, sigma != nullptr, S) : 0.0;
-    timed(c, kind, bytes, st, [&] {
-        if (M.split > 1 && !sigma)
-            HIPCHECK(launch_spmm_split<T>(st, C, M.split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta));
-        else
-            HIPCHECK(launch_spmm<T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m));
-    });
+    const int tuned = M.tuned[sizeof(T) == 4 ? 1 : 0][log2i(C)];
+    const int split = tuned ? tuned : M.split;
+    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, X, Y, Z, alpha, beta, sigma, S, m); });
+}
+
+// Autotuner: for every V-cycle matrix, time the candidate lane-group splits
+// (1, 2, 4, ... up to the block's capacity and about half the mean row
+// length) on this column count and keep the fastest.  Runs once per context
+// and column count, on scratch multivectors cleared first.
+template <typename T>
+static void autotune_level_splits(msp_ctx* c, Work& w) {
+    hipStream_t st = nullptr;
+    const int C = w.C;
+    const int lpr = C * static_cast<int>(sizeof(T)) >= 16 ? C / (16 / static_cast<int>(sizeof(T))) : 1;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    for (size_t l = 0; l < c->hier.lev.size(); ++l) {
+        const int64_t n = c->hier.lev[l].A.nr;
+        HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vy[l]), T(0)));
+        HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vs[l]), T(0)));
+        HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vr[l]), T(0)));
+    }
+    for (size_t l = 0; l < c->dl.size(); ++l) {
+        DevLevel& L = c->dl[l];
+        struct Job { DevCsr* M; const T* X; T* Y; };
+        T* vs = static_cast<T*>(w.vs[l]);
+        T* vr = static_cast<T*>(w.vr[l]);
+        Job jobs[4] = {{&L.A, vs, vr}, {&L.M, vr, vs}, {&L.R, vr, static_cast<T*>(w.vy[l + 1])},
+                       {&L.P, static_cast<T*>(w.vs[l + 1]), vs}};
+        for (Job& jb : jobs) {
+            const double avg = jb.M->nr ? static_cast<double>(jb.M->nnz) / static_cast<double>(jb.M->nr) : 0.0;
+            int best = 1;
+            float best_ms = 1e30f;
+            for (int g = 1; g <= 64 && g * lpr <= 256; g *= 2) {   // 256 threads per block
+                if (g > 1 && g > std::max(1.0, avg / 2.0)) break;
+                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, T(1), T(0), nullptr, 1, 1);
+                HIPCHECK(hipEventRecord(e0, st));
+                for (int rep = 0; rep < 3; ++rep)
+                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, T(1), T(0), nullptr, 1, 1);
+                HIPCHECK(hipEventRecord(e1, st));
+                HIPCHECK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = g;
+                }
+            }
+            jb.M->tuned[sizeof(T) == 4 ? 1 : 0][log2i(C)] = best;
+        }
+    }
+    HIPCHECK(hipEventDestroy(e0));
+    HIPCHECK(hipEventDestroy(e1));
 }
 
 static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
@@ -274,18 +342,19 @@ static Work& work(msp_ctx* c, int C) {
     w.vy.assign(L, nullptr);
     w.vs.assign(L, nullptr);
     w.vr.assign(L, nullptr);
-    w.vt.assign(L, nullptr);
     if (c->o.pc == MSP_PC_AMGR) {
         for (size_t l = 0; l < L; ++l) {
             const int64_t n = c->hier.lev[l].A.nr;
             w.vy[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
             w.vs[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
             w.vr[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
-            w.vt[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
         }
     }
-    w.nb_dot = 1024;
+    w.nb_dot = 512;
     w.partial = c->dalloc<double>(static_cast<int64_t>(w.nb_dot) * 64);
+    w.pp1 = c->dalloc<double>(static_cast<int64_t>(kPcgMaxBlocks) * 64);
+    w.pp2 = c->dalloc<double>(static_cast<int64_t>(kPcgMaxBlocks) * 64);
+    if (c->lrc_k > 0) w.plrc = c->dalloc<double>(static_cast<int64_t>(kPcgMaxBlocks) * 64 * c->lrc_k);
     w.scal = c->dalloc<double>(SC_COUNT * 64);
     w.iscal = c->dalloc<int>(64 * 2 + 2);
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_flags), 2 * sizeof(int), hipHostMallocDefault));
@@ -293,6 +362,10 @@ static Work& work(msp_ctx* c, int C) {
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_scal), SC_COUNT * 64 * sizeof(double),
                            hipHostMallocDefault));
     c->works[C] = std::move(wp);
+    if (c->o.pc == MSP_PC_AMGR && !c->dl.empty()) {
+        if (mixed(c)) autotune_level_splits<float>(c, w);
+        else autotune_level_splits<double>(c, w);
+    }
     return w;
 }
 
@@ -307,20 +380,16 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     }
     const DevLevel& L = c->dl[l];
     T* r = static_cast<T*>(w.vr[l]);
-    T* t = static_cast<T*>(w.vt[l]);
     T* yc = static_cast<T*>(w.vy[l + 1]);
     T* sc = static_cast<T*>(w.vs[l + 1]);
-    const T om = static_cast<T>(L.omega);
     const int kb = KD_LEVEL + 8 * static_cast<int>(l);
-    spmm<T>(c, kb + 1, st, C, L.G, y, t, nullptr, T(1), T(0));     // pre-smooth from zero: s = w G^T G y
-    spmm<T>(c, kb + 2, st, C, L.GT, t, s, nullptr, om, T(0));
+    spmm<T>(c, kb + 1, st, C, L.M, y, s, nullptr, T(1), T(0));     // pre-smooth from zero: s = M y, M = w G^T G
     spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // r = y - A s
     spmm<T>(c, kb + 3, st, C, L.R, r, yc, nullptr, T(1), T(0));    // r_c = P^T r
     vcycle<T>(c, w, st, l + 1, yc, sc);                            // coarse correction
     spmm<T>(c, kb + 4, st, C, L.P, sc, s, s, T(1), T(1));          // s += P h_c
-    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // post-smooth: s += w G^T G (y - A s)
-    spmm<T>(c, kb + 1, st, C, L.G, r, t, nullptr, T(1), T(0));
-    spmm<T>(c, kb + 2, st, C, L.GT, t, s, s, om, T(1));
+    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // post-smooth: s += M (y - A s)
+    spmm<T>(c, kb + 1, st, C, L.M, r, s, s, T(1), T(1));
 }
 
 // out[c] = <X_c, Y_c> for the C columns of two n_b x C multivectors.
@@ -399,8 +468,7 @@ static void upload_all(msp_ctx* c) {
             D.A = upload_csr(c, H.A, f32);
             D.P = upload_csr(c, H.P, f32);
             D.R = upload_csr(c, H.R, f32);
-            D.G = upload_csr(c, H.G, f32);
-            D.GT = upload_csr(c, H.GT, f32);
+            D.M = upload_csr(c, H.M, f32);
             D.omega = H.omega;
         }
         c->nL = c->hier.lev.back().A.nr;
@@ -443,26 +511,86 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
     HIPCHECK(launch_thresholds(st, C, S, m, c->o.tol, bn2, thr));
     HIPCHECK(launch_fill<double>(st, nb * C, w.r, 0.0));
     HIPCHECK(launch_fill<double>(st, nb * C, w.x, 0.0));
+    HIPCHECK(hipMemsetAsync(flags, 0, 2 * sizeof(int), st));
     timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // bhat = Q_s b
           [&] { HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, w.r)); });
-    precondition(c, w, st, w.r, w.z);
-    dot(c, w, st, w.r, w.r, rr);
-    dot(c, w, st, w.r, w.z, rz);
-    HIPCHECK(launch_pcg_init(st, C, rr, rz, thr, active, rho, iters, flags, rnorm));
+
+    const int nbp = pcg_grid(C, nb);
+    const bool lrc_amg = c->d_U && c->o.pc == MSP_PC_AMGR;
+    const int kl = lrc_amg ? c->lrc_k : 0;
+    const int O = S * kl * m;
+    const double wu = c->U32 ? 4.0 : 8.0;
+    const double vb = 8.0 * nb * C;   // bytes of one FP64 multivector pass
+    // <r,r>, U^T r and (initial) active flags; then z = M^{-1} r and rho = <r,z>
+    auto update_dots = [&](bool upd) {
+        const double bytes = (upd ? 6.0 : 1.0) * vb + (flexible && upd ? vb : 0.0) + (kl ? nb * S * kl * wu : 0.0);
+        timed(c, KD_UPDATE, bytes, st, [&] {
+            if (c->U32 || !c->d_U)
+                HIPCHECK(launch_update_dots<float>(st, C, nbp, upd, flexible && upd, kl, nb, w.x, w.r, w.p, w.q, alpha,
+                                                   w.z, static_cast<const float*>(c->d_U), S, m, w.pp1, w.pp2,
+                                                   w.plrc));
+            else
+                HIPCHECK(launch_update_dots<double>(st, C, nbp, upd, flexible && upd, kl, nb, w.x, w.r, w.p, w.q,
+                                                    alpha, w.z, static_cast<const double*>(c->d_U), S, m, w.pp1,
+                                                    w.pp2, w.plrc));
+        });
+        HIPCHECK(launch_fin_check(st, C, nbp, !upd, flexible && upd, O, m, w.pp1, w.pp2, w.plrc, thr, c->d_lrc_coef,
+                                  active, iters, flags, rnorm, rzold, c->d_lrc_W));
+    };
+    auto precond_dot = [&](bool init) {
+        const float* s32 = nullptr;
+        if (c->o.pc == MSP_PC_AMGR && mixed(c)) {
+            float* y0 = static_cast<float*>(w.vy[0]);
+            float* s0 = static_cast<float*>(w.vs[0]);
+            timed(c, KD_CAST, 12.0 * nb * C, st,
+                  [&] { HIPCHECK((launch_cast<float, double>(st, nb * C, w.r, y0))); });
+            vcycle<float>(c, w, st, 0, y0, s0);
+            s32 = s0;
+        } else {
+            precondition_base(c, w, st, w.r, w.z, true);
+        }
+        const double bytes = (s32 ? 4.0 : 8.0) * nb * C + 2.0 * vb + (kl ? nb * S * kl * wu : 0.0);
+        timed(c, KD_CAST, bytes, st, [&] {
+            if (s32) {
+                if (c->U32 || !c->d_U)
+                    HIPCHECK((launch_zfinish<float, float>(st, C, nbp, nb, s32, w.z, w.r,
+                                                           static_cast<const float*>(lrc_amg ? c->d_U : nullptr),
+                                                           c->d_lrc_W, S, kl, m, w.pp1)));
+                else
+                    HIPCHECK((launch_zfinish<float, double>(st, C, nbp, nb, s32, w.z, w.r,
+                                                            static_cast<const double*>(lrc_amg ? c->d_U : nullptr),
+                                                            c->d_lrc_W, S, kl, m, w.pp1)));
+            } else {
+                if (c->U32 || !c->d_U)
+                    HIPCHECK((launch_zfinish<double, float>(st, C, nbp, nb, w.z, w.z, w.r,
+                                                            static_cast<const float*>(lrc_amg ? c->d_U : nullptr),
+                                                            c->d_lrc_W, S, kl, m, w.pp1)));
+                else
+                    HIPCHECK((launch_zfinish<double, double>(st, C, nbp, nb, w.z, w.z, w.r,
+                                                             static_cast<const double*>(lrc_amg ? c->d_U : nullptr),
+                                                             c->d_lrc_W, S, kl, m, w.pp1)));
+            }
+        });
+        HIPCHECK(launch_fin_beta(st, C, nbp, init, flexible, w.pp1, active, rzold, rho, beta, rz));
+    };
+
+    update_dots(false);
+    precond_dot(true);
     HIPCHECK(hipMemcpyAsync(w.p, w.z, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
     HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     int nactive = w.h_flags[1];
     int it = 0;
     int status = MSP_OK;
-    while (nactive > 0 && it < c->o.maxit) {
-        spmm<double>(c, KD_OP, st, C, c->dAinn, w.p, w.q, nullptr, 1.0, 0.0, c->d_sigma, S, m);   // q = Ahat p
-        dot(c, w, st, w.p, w.q, pq);
-        HIPCHECK(launch_pcg_alpha(st, C, pq, active, rho, alpha, flags));
-        timed(c, KD_UPDATE, 48.0 * nb * C, st,
-              [&] { HIPCHECK(launch_pcg_update(st, C, nb, w.x, w.r, w.p, w.q, alpha)); });
-        dot(c, w, st, w.r, w.r, rr);
-        HIPCHECK(launch_pcg_check(st, C, rr, thr, active, iters, flags, rnorm));
+    if (w.h_flags[0]) status = MSP_ERR_BREAKDOWN;
+    while (status == MSP_OK && nactive > 0 && it < c->o.maxit) {
+        const double opb = spmm_bytes<double>(c->dAinn, C, false, true, S) + vb;
+        timed(c, KD_OP, opb, st, [&] {   // q = Ahat p and <p, q>
+            HIPCHECK(launch_op_dot(st, C, nbp, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, c->d_sigma, S, m, w.p, w.q,
+                                   w.pp1));
+        });
+        HIPCHECK(launch_fin_alpha(st, C, nbp, w.pp1, active, rho, alpha, pq, flags));
+        update_dots(true);
         HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
         ++it;
@@ -472,10 +600,7 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
         }
         nactive = w.h_flags[1];
         if (nactive == 0) break;
-        if (flexible) dot(c, w, st, w.r, w.z, rzold);
-        precondition(c, w, st, w.r, w.z);
-        dot(c, w, st, w.r, w.z, rz);
-        HIPCHECK(launch_pcg_beta(st, C, rz, rzold, active, rho, beta, flexible ? 1 : 0));
+        precond_dot(false);
         timed(c, KD_PUPDATE, 24.0 * nb * C, st,
               [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, w.p, w.z, beta, active)); });
     }
@@ -587,6 +712,7 @@ int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ct
             o->max_levels < 1 || !(o->theta >= 0.0) || !(o->tol > 0.0) || o->maxit < 0)
             throw Error(MSP_ERR_ARG, "invalid option value");
         if (o->lrc_k > 0 && o->pc == MSP_PC_NONE) throw Error(MSP_ERR_ARG, "low-rank corrections need a preconditioner");
+        if (o->lrc_k > 16) throw Error(MSP_ERR_UNSUPPORTED, "low-rank correction rank above 16");
         const auto t0 = std::chrono::steady_clock::now();
         std::unique_ptr<msp_ctx> c(new msp_ctx());
         c->o = *o;

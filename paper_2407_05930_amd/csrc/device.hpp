@@ -1,0 +1,102 @@
+// Device-side helpers shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace msp {
+
+constexpr int kBlock = 256;
+
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) Pack {
+    T e[VW];
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ Pack<T, VW> ld(const T* p) {
+    return *reinterpret_cast<const Pack<T, VW>*>(p);
+}
+template <typename T, int VW>
+__device__ __forceinline__ void st(T* p, const Pack<T, VW>& v) {
+    *reinterpret_cast<Pack<T, VW>*>(p) = v;
+}
+
+// Lane layout of an n x C row-major multivector: each row is handled by
+// LPR = C / VW lanes with VW consecutive columns per lane (16-byte accesses
+// where the row is wide enough); a 256-thread block covers RPB rows.
+template <typename T, int C>
+struct Lanes {
+    static constexpr int VW = (16 / (int)sizeof(T)) < C ? (16 / (int)sizeof(T)) : C;
+    static constexpr int LPR = C / VW;
+    static constexpr int RPB = kBlock / LPR;
+};
+
+// acc[e] += sum over k = k0, k0+step, ... < k1 of va[k] * X[ci[k], lane*VW + e],
+// accumulated in that order with four entries' loads in flight at a time.
+template <typename T, int C, int VW>
+__device__ __forceinline__ void row_accumulate(int32_t k0, int32_t k1, int step, const int32_t* __restrict__ ci,
+                                               const T* __restrict__ va, const T* __restrict__ X, int lane,
+                                               T* acc) {
+    int32_t k = k0;
+    for (; k + 3 * step < k1; k += 4 * step) {
+        const int32_t c0 = ci[k], c1 = ci[k + step], c2 = ci[k + 2 * step], c3 = ci[k + 3 * step];
+        const T a0 = va[k], a1 = va[k + step], a2 = va[k + 2 * step], a3 = va[k + 3 * step];
+        const Pack<T, VW> x0 = ld<T, VW>(X + (int64_t)c0 * C + lane * VW);
+        const Pack<T, VW> x1 = ld<T, VW>(X + (int64_t)c1 * C + lane * VW);
+        const Pack<T, VW> x2 = ld<T, VW>(X + (int64_t)c2 * C + lane * VW);
+        const Pack<T, VW> x3 = ld<T, VW>(X + (int64_t)c3 * C + lane * VW);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            acc[e] += a0 * x0.e[e];
+            acc[e] += a1 * x1.e[e];
+            acc[e] += a2 * x2.e[e];
+            acc[e] += a3 * x3.e[e];
+        }
+    }
+    for (; k < k1; k += step) {
+        const Pack<T, VW> x = ld<T, VW>(X + (int64_t)ci[k] * C + lane * VW);
+        const T a = va[k];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] += a * x.e[e];
+    }
+}
+
+static inline unsigned blocks_for(int64_t work, int per_block) {
+    return (unsigned)((work + per_block - 1) / per_block);
+}
+
+// Sum per-thread column partials (VW columns per lane) over the row slots of
+// the block in a fixed order; thread c < C writes the block total of column c
+// to out[c].  sm must hold kBlock * VW doubles.  Contains __syncthreads().
+template <int C, int VW>
+__device__ __forceinline__ void block_column_sums(const double* acc, double* sm, double* out) {
+    constexpr int LPR = C / VW;
+    constexpr int RPB = kBlock / LPR;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) sm[threadIdx.x * VW + e] = acc[e];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        double s = 0.0;
+        for (int r = 0; r < RPB; ++r) s += sm[r * C + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Tree sum of partial[b * O + o] over b < nb for one output o per block
+// (fixed order); result valid in thread 0.
+__device__ __forceinline__ double block_sum_partials(int nb, int O, int o, const double* partial, double* sm) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += partial[(int64_t)b * O + o];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    return sm[0];
+}
+
+}  // namespace msp

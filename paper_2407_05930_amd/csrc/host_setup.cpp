@@ -638,6 +638,8 @@ HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface,
         L.G = fsai_rows(A, lower);
         L.GT = transpose(L.G);
         L.omega = damping(A, L.G, L.GT, seed);
+        L.M = spgemm(L.GT, L.G);
+        for (double& v : L.M.v) v *= L.omega;
         L.P = interpolation(A, cf, lev == 0 ? o.jacobi0 : o.jacobi);
         L.R = transpose(L.P);
         L.cf = std::move(cf);

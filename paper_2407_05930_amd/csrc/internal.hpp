@@ -35,6 +35,7 @@ struct HostLevel {
     Csr A;
     std::vector<int8_t> cf;   // 1 = coarse (empty on the coarsest level)
     Csr P, R, G, GT;
+    Csr M;                    // smoother omega * G^T G, formed explicitly
     double omega = 0.0;
 };
 

@@ -10,33 +10,10 @@
 #include <cmath>
 #include <cstdint>
 
+#include "device.hpp"
 #include "kernels.hpp"
 
 namespace msp {
-
-constexpr int kBlock = 256;
-
-template <typename T, int VW>
-struct alignas(sizeof(T) * VW) Pack {
-    T e[VW];
-};
-
-template <typename T, int VW>
-__device__ __forceinline__ Pack<T, VW> ld(const T* p) {
-    return *reinterpret_cast<const Pack<T, VW>*>(p);
-}
-template <typename T, int VW>
-__device__ __forceinline__ void st(T* p, const Pack<T, VW>& v) {
-    *reinterpret_cast<Pack<T, VW>*>(p) = v;
-}
-
-// vector width per lane: 16-byte accesses where the row is wide enough
-template <typename T, int C>
-struct Lanes {
-    static constexpr int VW = (16 / (int)sizeof(T)) < C ? (16 / (int)sizeof(T)) : C;
-    static constexpr int LPR = C / VW;
-    static constexpr int RPB = kBlock / LPR;
-};
 
 // ------------------------------------------------------------------ SpMM
 // Y = alpha * (A X + diag-outer(X)) + beta * Z, where the outer term adds
@@ -57,14 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
     T acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = T(0);
-    const int32_t k0 = rp[row], k1 = rp[row + 1];
-    for (int32_t k = k0; k < k1; ++k) {
-        const int32_t c = ci[k];
-        const T a = va[k];
-        const Pack<T, VW> x = ld<T, VW>(X + (int64_t)c * C + lane * VW);
-#pragma unroll
-        for (int e = 0; e < VW; ++e) acc[e] += a * x.e[e];
-    }
+    row_accumulate<T, C, VW>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc);
     if (sigma) {
         const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
 #pragma unroll
@@ -105,16 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
     T acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = T(0);
-    if (row < n) {
-        const int32_t k1 = rp[row + 1];
-        for (int32_t k = rp[row] + g; k < k1; k += G) {
-            const int32_t c = ci[k];
-            const T a = va[k];
-            const Pack<T, VW> x = ld<T, VW>(X + (int64_t)c * C + lane * VW);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) acc[e] += a * x.e[e];
-        }
-    }
+    if (row < n) row_accumulate<T, C, VW>(rp[row] + g, rp[row + 1], G, ci, va, X, lane, acc);
 #pragma unroll
     for (int e = 0; e < VW; ++e) sm[threadIdx.x * VW + e] = acc[e];
     __syncthreads();
@@ -170,23 +131,12 @@ __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const T* __restrict__
     }
 }
 
-// Sum the partials of nb blocks per column in a fixed order: out[c].
-template <int C>
-__global__ __launch_bounds__(kBlock) void k_reduce_partials(int nb, const double* __restrict__ partial,
+// out[o] = sum over nb blocks of partial[b * O + o]; one block per output o.
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(int nb, int O, const double* __restrict__ partial,
                                                             double* __restrict__ out) {
-    constexpr int P = kBlock / C;
     __shared__ double sm[kBlock];
-    const int c = threadIdx.x % C;
-    const int part = threadIdx.x / C;
-    double s = 0.0;
-    for (int b = part; b < nb; b += P) s += partial[(int64_t)b * C + c];
-    sm[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < C) {
-        double t = 0.0;
-        for (int p = 0; p < P; ++p) t += sm[p * C + threadIdx.x];
-        out[threadIdx.x] = t;
-    }
+    const double s = block_sum_partials(nb, O, blockIdx.x, partial, sm);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 // ------------------------------------------------------------------ PCG scalar steps (one block)
@@ -525,9 +475,6 @@ __global__ __launch_bounds__(kBlock) void k_lrc_expand(int64_t n, int S, int k, 
 
 // ------------------------------------------------------------------ host launchers
 
-static inline unsigned blocks_for(int64_t work, int per_block) {
-    return (unsigned)((work + per_block - 1) / per_block);
-}
 
 #define MSP_DISPATCH_C(C, ...)                                   \
     switch (C) {                                                 \
@@ -599,7 +546,7 @@ hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, 
                       double* out) {
     MSP_DISPATCH_C(C, {
         hipLaunchKernelGGL((k_dot<T, CC>), dim3(nb), dim3(kBlock), 0, st, n, X, Y, partial);
-        hipLaunchKernelGGL((k_reduce_partials<CC>), dim3(1), dim3(kBlock), 0, st, nb, partial, out);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(CC), dim3(kBlock), 0, st, nb, CC, partial, out);
     });
     return hipGetLastError();
 }

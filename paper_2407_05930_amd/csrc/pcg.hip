@@ -1,0 +1,418 @@
+// Fused kernels of the per-column PCG (Alg. 1, decoupled solves) on n_b x C
+// FP64 multivectors.  Every dot product is produced inside the kernel that
+// writes one of its operands (per-block column partials), and a small
+// finishing kernel with one block per output sums the partials in a fixed
+// order and takes the per-column scalar step (alpha, convergence check,
+// beta), so a PCG iteration is:
+//   op_dot -> fin_alpha -> update_dots -> fin_check -> [V-cycle] ->
+//   zfinish -> fin_beta -> pupdate.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "device.hpp"
+#include "pcg.hpp"
+
+namespace msp {
+
+template <int C>
+using DL = Lanes<double, C>;
+
+// q = (A_inn + diag-outer) p; partial[b, c] = this block's sum of p[:, c] q[:, c]
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci, const double* __restrict__ va,
+                                                   const double* __restrict__ sigma, int S, int m,
+                                                   const double* __restrict__ p, double* __restrict__ q,
+                                                   double* __restrict__ partial) {
+    constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
+    __shared__ double sm[kBlock * VW];
+    const int slot = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+    const int64_t ntiles = (n + RPB - 1) / RPB;
+    double dacc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) dacc[e] = 0.0;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row = tile * RPB + slot;
+        if (row >= n) continue;
+        double acc[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] = 0.0;
+        row_accumulate<double, C, VW>(rp[row], rp[row + 1], 1, ci, va, p, lane, acc);
+        const Pack<double, VW> pr = ld<double, VW>(p + row * C + lane * VW);
+        Pack<double, VW> out;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const int a = (lane * VW + e) / m;
+            if (a < S) acc[e] += sigma[row * S + a] * pr.e[e];
+            out.e[e] = acc[e];
+            dacc[e] += pr.e[e] * acc[e];
+        }
+        st<double, VW>(q + row * C + lane * VW, out);
+    }
+    block_column_sums<C, VW>(dacc, sm, partial + (int64_t)blockIdx.x * C);
+}
+
+// alpha[c] = rho[c] / <p,q>[c] on active columns (breakdown flag otherwise);
+// resets the active-column counter flags[1] for this iteration's check.
+__global__ __launch_bounds__(kBlock) void k_fin_alpha(int nb, int C, const double* __restrict__ partial,
+                                                      const int* __restrict__ active, const double* __restrict__ rho,
+                                                      double* __restrict__ alpha, double* __restrict__ pq, int* flags) {
+    __shared__ double sm[kBlock];
+    const int c = blockIdx.x;
+    const double s = block_sum_partials(nb, C, c, partial, sm);
+    if (threadIdx.x == 0) {
+        pq[c] = s;
+        double a = 0.0;
+        if (active[c]) {
+            if (!(s > 0.0) || !isfinite(s) || !isfinite(rho[c])) atomicOr(&flags[0], 1);
+            else a = rho[c] / s;
+        }
+        alpha[c] = a;
+        if (c == 0) flags[1] = 0;
+    }
+}
+
+// UPD: x += alpha p, r -= alpha q.  Then per-block partials of <r,r>
+// (partial_rr), of <r,z> with the current z when FLEX (partial_rz), and of
+// the low-rank projections U_a^T r_a when KMAX > 0:
+// partial_lrc[b, (a*k + t)*m + j] = sum_rows U[i, a*k+t] r[i, a*m+j].
+template <int C, bool UPD, bool FLEX, int KMAX, typename TU>
+__global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                        const double* __restrict__ p, const double* __restrict__ q,
+                                                        const double* __restrict__ alpha,
+                                                        const double* __restrict__ z, const TU* __restrict__ U,
+                                                        int S, int k, int m, double* __restrict__ partial_rr,
+                                                        double* __restrict__ partial_rz,
+                                                        double* __restrict__ partial_lrc) {
+    constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
+    constexpr int KA = KMAX > 0 ? KMAX : 1;
+    __shared__ double sm[kBlock * VW];
+    __shared__ double tot[C];
+    const int slot = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+    const int64_t ntiles = (n + RPB - 1) / RPB;
+    double a_rr[VW], a_rz[VW], a_l[VW][KA];
+    double al[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+        a_rr[e] = a_rz[e] = 0.0;
+        al[e] = UPD ? alpha[lane * VW + e] : 0.0;
+#pragma unroll
+        for (int t = 0; t < KA; ++t) a_l[e][t] = 0.0;
+    }
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row = tile * RPB + slot;
+        if (row >= n) continue;
+        const int64_t o = row * C + lane * VW;
+        Pack<double, VW> rv = ld<double, VW>(r + o);
+        if (UPD) {
+            Pack<double, VW> xv = ld<double, VW>(x + o);
+            const Pack<double, VW> pv = ld<double, VW>(p + o), qv = ld<double, VW>(q + o);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                xv.e[e] += al[e] * pv.e[e];
+                rv.e[e] -= al[e] * qv.e[e];
+            }
+            st<double, VW>(x + o, xv);
+            st<double, VW>(r + o, rv);
+        }
+#pragma unroll
+        for (int e = 0; e < VW; ++e) a_rr[e] += rv.e[e] * rv.e[e];
+        if (FLEX) {
+            const Pack<double, VW> zv = ld<double, VW>(z + o);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) a_rz[e] += rv.e[e] * zv.e[e];
+        }
+        if (KMAX > 0) {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                const int col = lane * VW + e;
+                const int a = col / m;
+                if (a < S) {
+                    const TU* u = U + row * (S * k) + a * k;
+                    if ((k & 3) == 0) {
+#pragma unroll
+                        for (int t = 0; t < KA; t += 4)
+                            if (t < k) {
+                                const Pack<TU, 4> u4 = ld<TU, 4>(u + t);
+#pragma unroll
+                                for (int q = 0; q < 4 && t + q < KA; ++q) a_l[e][t + q] += (double)u4.e[q] * rv.e[e];
+                            }
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < KA; ++t)
+                            if (t < k) a_l[e][t] += (double)u[t] * rv.e[e];
+                    }
+                }
+            }
+        }
+    }
+    block_column_sums<C, VW>(a_rr, sm, partial_rr + (int64_t)blockIdx.x * C);
+    if (FLEX) block_column_sums<C, VW>(a_rz, sm, partial_rz + (int64_t)blockIdx.x * C);
+    if (KMAX > 0) {
+        const int O = S * k * m;
+        for (int t = 0; t < k && t < KA; ++t) {
+            double v[VW];
+#pragma unroll
+            for (int e = 0; e < VW; ++e) v[e] = a_l[e][t];
+            block_column_sums<C, VW>(v, sm, tot);
+            if (threadIdx.x < S * m) {
+                const int col = threadIdx.x, a = col / m, j = col % m;
+                partial_lrc[(int64_t)blockIdx.x * O + (a * k + t) * m + j] = tot[col];
+            }
+        }
+    }
+}
+
+// Blocks [0, C): <r,r> -> convergence check (INIT: set the active flags);
+// blocks [C, 2C) when FLEX: <r, z_old>; the next S*k*m blocks when LRC:
+// W[o] = coef[o / m] * U^T r.
+__global__ __launch_bounds__(kBlock) void k_fin_check(int nb, int C, int init, int flex, int O, int m,
+                                                      const double* __restrict__ partial_rr,
+                                                      const double* __restrict__ partial_rz,
+                                                      const double* __restrict__ partial_lrc,
+                                                      const double* __restrict__ thr, const double* __restrict__ coef,
+                                                      int* active, int* iters, int* flags, double* rnorm,
+                                                      double* rzold, double* W) {
+    __shared__ double sm[kBlock];
+    int b = blockIdx.x;
+    if (b < C) {
+        const double s = block_sum_partials(nb, C, b, partial_rr, sm);
+        if (threadIdx.x == 0) {
+            const double nr = sqrt(s);
+            if (init) {
+                rnorm[b] = nr;
+                iters[b] = 0;
+                const int a = nr > thr[b] ? 1 : 0;
+                active[b] = a;
+                if (a) atomicAdd(&flags[1], 1);
+            } else if (active[b]) {
+                iters[b] += 1;
+                rnorm[b] = nr;
+                if (!isfinite(nr)) atomicOr(&flags[0], 1);
+                if (nr > thr[b]) atomicAdd(&flags[1], 1);
+                else active[b] = 0;
+            }
+        }
+        return;
+    }
+    b -= C;
+    if (flex) {
+        if (b < C) {
+            const double s = block_sum_partials(nb, C, b, partial_rz, sm);
+            if (threadIdx.x == 0) rzold[b] = s;
+            return;
+        }
+        b -= C;
+    }
+    if (b < O) {
+        const double s = block_sum_partials(nb, O, b, partial_lrc, sm);
+        if (threadIdx.x == 0) W[b] = coef[b / m] * s;
+    }
+}
+
+// z = s (cast to FP64; s may alias z) + sum_t U[i, a*k+t] W[(a*k+t)*m + j]
+// (the expansion of the low-rank correction); partial[b, c] = sum r z.
+template <int C, typename TS, bool LRC, typename TU>
+__global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, double* z, const double* __restrict__ r,
+                                                    const TU* __restrict__ U, const double* __restrict__ W, int S,
+                                                    int k, int m, double* __restrict__ partial) {
+    constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
+    __shared__ double sm[kBlock * VW];
+    __shared__ double wl[LRC ? 64 * 16 : 1];
+    const int slot = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+    const int64_t ntiles = (n + RPB - 1) / RPB;
+    if (LRC) {
+        for (int o = threadIdx.x; o < S * k * m; o += kBlock) wl[o] = W[o];
+        __syncthreads();
+    }
+    double acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = 0.0;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row = tile * RPB + slot;
+        if (row >= n) continue;
+        const int64_t o = row * C + lane * VW;
+        Pack<double, VW> zv;
+        const Pack<TS, VW> sv = ld<TS, VW>(s + o);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) zv.e[e] = (double)sv.e[e];
+        if (LRC) {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                const int col = lane * VW + e;
+                const int a = col / m, j = col % m;
+                if (a < S) {
+                    const TU* u = U + row * (S * k) + a * k;
+                    const double* w = wl + (a * k) * m + j;
+                    double t2 = 0.0;
+                    int t = 0;
+                    for (; t + 4 <= k; t += 4) {
+                        const Pack<TU, 4> u4 = ld<TU, 4>(u + t);
+                        t2 += (double)u4.e[0] * w[t * m];
+                        t2 += (double)u4.e[1] * w[(t + 1) * m];
+                        t2 += (double)u4.e[2] * w[(t + 2) * m];
+                        t2 += (double)u4.e[3] * w[(t + 3) * m];
+                    }
+                    for (; t < k; ++t) t2 += (double)u[t] * w[t * m];
+                    zv.e[e] += t2;
+                }
+            }
+        }
+        st<double, VW>(z + o, zv);
+        const Pack<double, VW> rv = ld<double, VW>(r + o);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] += rv.e[e] * zv.e[e];
+    }
+    block_column_sums<C, VW>(acc, sm, partial + (int64_t)blockIdx.x * C);
+}
+
+// beta (standard: <r,z>/rho; flexible: (<r,z> - <r,z_old>)/rho), rho = <r,z>
+// on active columns.  INIT: rho = <r,z> for every column.
+__global__ __launch_bounds__(kBlock) void k_fin_beta(int nb, int C, int init, int flex,
+                                                     const double* __restrict__ partial, const int* __restrict__ active,
+                                                     const double* __restrict__ rzold, double* rho, double* beta,
+                                                     double* rz) {
+    __shared__ double sm[kBlock];
+    const int c = blockIdx.x;
+    const double s = block_sum_partials(nb, C, c, partial, sm);
+    if (threadIdx.x == 0) {
+        rz[c] = s;
+        if (init) {
+            rho[c] = s;
+            beta[c] = 0.0;
+        } else if (active[c]) {
+            const double num = flex ? s - rzold[c] : s;
+            beta[c] = num / rho[c];
+            rho[c] = s;
+        } else {
+            beta[c] = 0.0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+#define MSP_DISPATCH_C(C, ...)                                   \
+    switch (C) {                                                 \
+        case 1: { constexpr int CC = 1; __VA_ARGS__; } break;    \
+        case 2: { constexpr int CC = 2; __VA_ARGS__; } break;    \
+        case 4: { constexpr int CC = 4; __VA_ARGS__; } break;    \
+        case 8: { constexpr int CC = 8; __VA_ARGS__; } break;    \
+        case 16: { constexpr int CC = 16; __VA_ARGS__; } break;  \
+        case 32: { constexpr int CC = 32; __VA_ARGS__; } break;  \
+        case 64: { constexpr int CC = 64; __VA_ARGS__; } break;  \
+        default: return hipErrorInvalidValue;                    \
+    }
+
+template <int C>
+static unsigned grid_for(int64_t n, int nbmax) {
+    const int64_t tiles = (n + DL<C>::RPB - 1) / DL<C>::RPB;
+    return (unsigned)(tiles < nbmax ? tiles : nbmax);
+}
+
+int pcg_grid(int C, int64_t n) {
+    switch (C) {
+        case 1: return grid_for<1>(n, kPcgMaxBlocks);
+        case 2: return grid_for<2>(n, kPcgMaxBlocks);
+        case 4: return grid_for<4>(n, kPcgMaxBlocks);
+        case 8: return grid_for<8>(n, kPcgMaxBlocks);
+        case 16: return grid_for<16>(n, kPcgMaxBlocks);
+        case 32: return grid_for<32>(n, kPcgMaxBlocks);
+        default: return grid_for<64>(n, kPcgMaxBlocks);
+    }
+}
+
+hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
+                         const double* va, const double* sigma, int S, int m, const double* p, double* q,
+                         double* partial) {
+    MSP_DISPATCH_C(C, {
+        hipLaunchKernelGGL((k_op_dot<CC>), dim3(nb), dim3(kBlock), 0, st, n, rp, ci, va, sigma, S, m, p, q, partial);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial, const int* active,
+                            const double* rho, double* alpha, double* pq, int* flags) {
+    hipLaunchKernelGGL(k_fin_alpha, dim3(C), dim3(kBlock), 0, st, nb, C, partial, active, rho, alpha, pq, flags);
+    return hipGetLastError();
+}
+
+template <int CC, bool UPD, bool FLEX, int KMAX, typename TU>
+static void upd_launch(hipStream_t st, int nb, int64_t n, double* x, double* r, const double* p, const double* q,
+                       const double* alpha, const double* z, const TU* U, int S, int k, int m, double* prr,
+                       double* prz, double* plrc) {
+    hipLaunchKernelGGL((k_update_dots<CC, UPD, FLEX, KMAX, TU>), dim3(nb), dim3(kBlock), 0, st, n, x, r, p, q, alpha,
+                       z, U, S, k, m, prr, prz, plrc);
+}
+
+template <typename TU>
+hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* x,
+                              double* r, const double* p, const double* q, const double* alpha, const double* z,
+                              const TU* U, int S, int m, double* prr, double* prz, double* plrc) {
+    if (k > 16) return hipErrorInvalidValue;
+    MSP_DISPATCH_C(C, {
+        if (k > 8) {
+            if (upd && flex) upd_launch<CC, true, true, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+            else if (upd) upd_launch<CC, true, false, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+            else upd_launch<CC, false, false, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+        } else if (k > 0) {
+            if (upd && flex) upd_launch<CC, true, true, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+            else if (upd) upd_launch<CC, true, false, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+            else upd_launch<CC, false, false, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+        } else {
+            if (upd && flex) upd_launch<CC, true, true, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+            else if (upd) upd_launch<CC, true, false, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+            else upd_launch<CC, false, false, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+        }
+    });
+    return hipGetLastError();
+}
+template hipError_t launch_update_dots<float>(hipStream_t, int, int, bool, bool, int, int64_t, double*, double*,
+                                              const double*, const double*, const double*, const double*,
+                                              const float*, int, int, double*, double*, double*);
+template hipError_t launch_update_dots<double>(hipStream_t, int, int, bool, bool, int, int64_t, double*, double*,
+                                               const double*, const double*, const double*, const double*,
+                                               const double*, int, int, double*, double*, double*);
+
+hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
+                            const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
+                            int* iters, int* flags, double* rnorm, double* rzold, double* W) {
+    const unsigned blocks = (unsigned)(C + (flex ? C : 0) + O);
+    hipLaunchKernelGGL(k_fin_check, dim3(blocks), dim3(kBlock), 0, st, nb, C, init ? 1 : 0, flex ? 1 : 0, O, m, prr,
+                       prz, plrc, thr, coef, active, iters, flags, rnorm, rzold, W);
+    return hipGetLastError();
+}
+
+template <typename TS, typename TU>
+hipError_t launch_zfinish(hipStream_t st, int C, int nb, int64_t n, const TS* s, double* z, const double* r,
+                          const TU* U, const double* W, int S, int k, int m, double* partial) {
+    MSP_DISPATCH_C(C, {
+        if (U && k > 0)
+            hipLaunchKernelGGL((k_zfinish<CC, TS, true, TU>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k, m,
+                               partial);
+        else
+            hipLaunchKernelGGL((k_zfinish<CC, TS, false, TU>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k,
+                               m, partial);
+    });
+    return hipGetLastError();
+}
+template hipError_t launch_zfinish<float, float>(hipStream_t, int, int, int64_t, const float*, double*,
+                                                 const double*, const float*, const double*, int, int, int, double*);
+template hipError_t launch_zfinish<double, double>(hipStream_t, int, int, int64_t, const double*, double*,
+                                                   const double*, const double*, const double*, int, int, int,
+                                                   double*);
+template hipError_t launch_zfinish<double, float>(hipStream_t, int, int, int64_t, const double*, double*,
+                                                  const double*, const float*, const double*, int, int, int, double*);
+template hipError_t launch_zfinish<float, double>(hipStream_t, int, int, int64_t, const float*, double*,
+                                                  const double*, const double*, const double*, int, int, int, double*);
+
+hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
+                           const int* active, const double* rzold, double* rho, double* beta, double* rz) {
+    hipLaunchKernelGGL(k_fin_beta, dim3(C), dim3(kBlock), 0, st, nb, C, init ? 1 : 0, flex ? 1 : 0, partial, active,
+                       rzold, rho, beta, rz);
+    return hipGetLastError();
+}
+
+}  // namespace msp

@@ -1,0 +1,32 @@
+// Launchers of the fused PCG kernels (pcg.hip).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace msp {
+
+constexpr int kPcgMaxBlocks = 2048;   // grid of the dot-producing kernels (grid-stride over row tiles)
+
+int pcg_grid(int C, int64_t n);
+
+hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
+                         const double* va, const double* sigma, int S, int m, const double* p, double* q,
+                         double* partial);
+hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial, const int* active,
+                            const double* rho, double* alpha, double* pq, int* flags);
+template <typename TU>
+hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* x,
+                              double* r, const double* p, const double* q, const double* alpha, const double* z,
+                              const TU* U, int S, int m, double* prr, double* prz, double* plrc);
+hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
+                            const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
+                            int* iters, int* flags, double* rnorm, double* rzold, double* W);
+template <typename TS, typename TU>
+hipError_t launch_zfinish(hipStream_t st, int C, int nb, int64_t n, const TS* s, double* z, const double* r,
+                          const TU* U, const double* W, int S, int k, int m, double* partial);
+hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
+                           const int* active, const double* rzold, double* rho, double* beta, double* rz);
+
+}  // namespace msp
