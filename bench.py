@@ -58,6 +58,27 @@ def dominant_kernel(sv, b):
     return kind, tm, total
 
 
+KIND_KERNEL = {"update": "k_update_dots", "operator": "k_op_dot", "cast": "k_zfinish"}
+
+
+def committed_traffic(kind_name):
+    """Calibrated HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current library source."""
+    import glob
+    from paper_2407_05930_amd.profiling import source_hash
+    want = KIND_KERNEL.get(kind_name)
+    if not want:
+        return None
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
+        try:
+            info = json.load(open(path))
+        except Exception:
+            continue
+        if want in info.get("kernel", "") and info.get("source_hash") == source_hash():
+            return int(info["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(problem, iters_gpu, k):
     """The FP64 oracle on the host: setup plus a bounded sample of PCG
     iterations on the same workload, extrapolated to the GPU's iteration
@@ -91,6 +112,8 @@ def main():
     ap.add_argument("--workload", default="channel3d_128_s3")
     ap.add_argument("--k", type=int, default=8, help="low-rank correction rank per subsystem")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference for the traffic counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -104,6 +127,13 @@ def main():
     from paper_2407_05930_amd import Solver
 
     rank = int(os.environ.get("RANK", "0"))
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {src.numel() * 8} bytes read, {dst.numel() * 8} bytes written")
+        del src, dst
     log(f"building workload {args.workload}")
     p = config_problem(args.workload)
     b = torch.from_numpy(p.b).cuda()
@@ -173,7 +203,7 @@ def main():
         "setup_s": {kk: round(v["t_setup"], 3) for kk, v in res.items()},
         "vcycle_GBs": round(vc_by / (vc_ms * 1e-3) / 1e9, 1) if vc_ms > 0 else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(Solver.kind_name(kind)),
                      "kernel": Solver.kind_name(kind), "avg_ms": round(avg_ms, 5),
                      "algorithmic_bytes_per_launch": int(bytes_per_launch), "launches": cnt},
         "kernel_breakdown_mixed": breakdown,

@@ -507,7 +507,7 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
     const bool flexible = mixed(c) && c->o.pc == MSP_PC_AMGR;
     const auto t0 = std::chrono::steady_clock::now();
 
-    HIPCHECK(launch_colnorm2(st, n, m, d_b, bn2));
+    HIPCHECK(launch_colnorm2(st, n, m, d_b, w.pp1, std::min<int64_t>(512, (n + 255) / 256), bn2));
     HIPCHECK(launch_thresholds(st, C, S, m, c->o.tol, bn2, thr));
     HIPCHECK(launch_fill<double>(st, nb * C, w.r, 0.0));
     HIPCHECK(launch_fill<double>(st, nb * C, w.x, 0.0));

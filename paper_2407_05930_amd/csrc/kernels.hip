@@ -309,13 +309,14 @@ __global__ __launch_bounds__(kBlock) void k_qs_backward(int64_t n_b, int m, int 
     for (int a = 0; a < S; ++a) x[img[i * S + a] + (int64_t)j * n] = scale * v[a];
 }
 
-// per-RHS squared norms of the caller's b: out[j] (one block per RHS, fixed order)
-__global__ __launch_bounds__(kBlock) void k_colnorm2(int64_t n, const double* __restrict__ b,
-                                                     double* __restrict__ out) {
+// per-RHS squared norms of the caller's b: block (x, j) sums a grid-stride
+// share of column j and writes partial[x * m + j]; fixed-order tree in the block.
+__global__ __launch_bounds__(kBlock) void k_colnorm2(int64_t n, int m, const double* __restrict__ b,
+                                                     double* __restrict__ partial) {
     __shared__ double sm[kBlock];
-    const int j = blockIdx.x;
+    const int j = blockIdx.y;
     double s = 0.0;
-    for (int64_t g = threadIdx.x; g < n; g += kBlock) {
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n; g += (int64_t)gridDim.x * kBlock) {
         const double v = b[g + (int64_t)j * n];
         s += v * v;
     }
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_colnorm2(int64_t n, const double* __
         if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[j] = sm[0];
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * m + j] = sm[0];
 }
 
 // thresholds per column a*m + j: tol * ||b_j|| / sqrt(2^s); padded columns never start
@@ -624,8 +625,10 @@ hipError_t launch_qs_backward(hipStream_t st, int S, int64_t n_b, int m, int C, 
     });
     return hipGetLastError();
 }
-hipError_t launch_colnorm2(hipStream_t st, int64_t n, int m, const double* b, double* out) {
-    hipLaunchKernelGGL(k_colnorm2, dim3(m), dim3(kBlock), 0, st, n, b, out);
+hipError_t launch_colnorm2(hipStream_t st, int64_t n, int m, const double* b, double* partial, int nb,
+                           double* out) {
+    hipLaunchKernelGGL(k_colnorm2, dim3(nb, m), dim3(kBlock), 0, st, n, m, b, partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(m), dim3(kBlock), 0, st, nb, m, partial, out);
     return hipGetLastError();
 }
 hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, const double* bn2, double* thr) {

@@ -36,7 +36,9 @@ hipError_t launch_qs_forward(hipStream_t st, int S, int64_t n_b, int m, int C, i
                              const double* b, double* out);
 hipError_t launch_qs_backward(hipStream_t st, int S, int64_t n_b, int m, int C, int64_t n, const int64_t* img,
                               const double* xh, double* x);
-hipError_t launch_colnorm2(hipStream_t st, int64_t n, int m, const double* b, double* out);
+// out[j] = ||b_j||^2 for the m columns of an n x m column-major array (partial: nb * m scratch)
+hipError_t launch_colnorm2(hipStream_t st, int64_t n, int m, const double* b, double* partial, int nb,
+                           double* out);
 hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, const double* bn2, double* thr);
 
 template <typename T>
