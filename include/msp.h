@@ -167,6 +167,51 @@ int msp_set_timing(msp_ctx* c, int32_t kind, int32_t on);
 int msp_reset_timing(msp_ctx* c);
 int msp_get_timing(const msp_ctx* c, int32_t kind, int64_t* count, double* total_ms, double* total_bytes);
 
+/* ---------------------------------------------------------------------------
+ * Finite-volume operator and adjoint gradient (differentiable solves).
+ *
+ * The two-point-flux Poisson matrix -div(kappa grad p) is described by the
+ * faces of the base mesh (one kappa per base cell, mirrored to every image):
+ *   interior face (base cells a, b):  T = |S| / (d_a/kappa_a + d_b/kappa_b)
+ *   Dirichlet wall face of cell a:    T = |S| kappa_a / d_a
+ *   mirror-plane face of cell a:      T = |S| kappa_a / (2 d_a), coupling
+ *                                     image c with image c xor 2^axis
+ *   A_ii = sum of the cell's T, A_ij = -T.
+ * For L(p) with p = A^{-1} f and lambda = A^{-T} dL/dp = A^{-1} dL/dp,
+ *   dL/df = lambda,  dL/dkappa_i = - lambda^T (dA/dkappa_i) p
+ *                               = sum_faces g_f dT_f/dkappa_i,
+ *   g_f = -(lambda_u - lambda_v)(p_u - p_v)  (interior and mirror faces),
+ *   g_f = -lambda_u p_u                      (wall faces),
+ * summed over the images of base cell i and over right-hand sides.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    int64_t nf;              /* number of faces touching base cells */
+    const int64_t* cell_a;   /* base cell of the face */
+    const int64_t* cell_b;   /* other base cell (interior faces), else -1 */
+    const int8_t* kind;      /* 0 interior, 1 Dirichlet wall, 2 mirror plane */
+    const int8_t* axis;      /* mirror faces: the symmetry bit it couples */
+    const double* area;      /* |S_f| */
+    const double* dist_a;    /* distance cell_a centroid -> face centroid */
+    const double* dist_b;    /* same for cell_b (interior faces) */
+} msp_faces;
+
+typedef struct msp_fv msp_fv;   /* opaque; owned by the library until msp_fv_free */
+
+/* Copy the face description and the symmetry map; with device >= 0 also
+   upload them for msp_fv_kappa_grad. */
+int msp_fv_create(const msp_faces* F, const msp_symmap* map, int32_t device, msp_fv** out);
+/* Number of nonzeros of the assembled full matrix. */
+int msp_fv_nnz(const msp_fv* f, int64_t* nnz);
+/* Assemble the full n x n matrix for kappa_base (host, n_b) in the ordering of
+   the map: rowptr (n + 1), col and val (nnz) are caller arrays; columns sorted. */
+int msp_fv_assemble(const msp_fv* f, const double* kappa_base, int64_t* rowptr, int32_t* col, double* val);
+/* d_grad[i] = dL/dkappa_i for base cell i (device arrays: kappa n_b; lambda and
+   p n x m column-major; grad n_b), one thread per base cell gathering over its
+   own faces (no atomics), enqueued on hip_stream. */
+int msp_fv_kappa_grad(msp_fv* f, const double* d_kappa_base, int32_t m, const double* d_lambda, const double* d_p,
+                      double* d_grad, void* hip_stream);
+void msp_fv_free(msp_fv* f);
+
 void msp_free(msp_ctx* c);
 const char* msp_last_error(void);
 

@@ -58,6 +58,13 @@ class msp_stats(ctypes.Structure):
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
 
 
+class msp_faces(ctypes.Structure):
+    _fields_ = [("nf", ctypes.c_int64), ("cell_a", ctypes.POINTER(ctypes.c_int64)),
+                ("cell_b", ctypes.POINTER(ctypes.c_int64)), ("kind", ctypes.POINTER(ctypes.c_int8)),
+                ("axis", ctypes.POINTER(ctypes.c_int8)), ("area", ctypes.POINTER(ctypes.c_double)),
+                ("dist_a", ctypes.POINTER(ctypes.c_double)), ("dist_b", ctypes.POINTER(ctypes.c_double))]
+
+
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
 SIGNATURES = {
@@ -77,6 +84,11 @@ SIGNATURES = {
     "msp_reset_timing": (ctypes.c_int, [_vp]),
     "msp_get_timing": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_double),
                                       _P(ctypes.c_double)]),
+    "msp_fv_create": (ctypes.c_int, [_P(msp_faces), _P(msp_symmap), ctypes.c_int32, _P(_vp)]),
+    "msp_fv_nnz": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
+    "msp_fv_assemble": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "msp_fv_kappa_grad": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]),
+    "msp_fv_free": (None, [_vp]),
     "msp_free": (None, [_vp]),
     "msp_last_error": (ctypes.c_char_p, []),
 }

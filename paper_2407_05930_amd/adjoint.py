@@ -1,0 +1,143 @@
+"""Differentiable solves: p = A(kappa)^{-1} f with a hand-written adjoint.
+
+``FVOperator`` wraps the library's finite-volume operator (assembly of the
+two-point-flux matrix from base-mesh faces and the kappa-gradient kernel);
+``PoissonSolve`` is a torch.autograd.Function whose backward solves
+A lambda = dL/dp with the same symmetric reduced solve (A = A^T, Q_s = Q_s^T)
+and returns dL/df = lambda and dL/dkappa from face products.  Marshalling
+only: assembly, setup, solves and the gradient run in libmsp.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import _lib
+from ._lib import check, lib
+from .solver import Solver
+
+
+def _p(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+class FVOperator:
+    """Base-mesh face geometry (any object with cell_a, cell_b, kind, axis,
+    area, dist_a, dist_b arrays) and the symmetry map img (n_b x 2^s)."""
+
+    def __init__(self, faces, img, device: int = 0):
+        self._keep = dict(
+            ca=np.ascontiguousarray(faces.cell_a, dtype=np.int64), cb=np.ascontiguousarray(faces.cell_b, dtype=np.int64),
+            kind=np.ascontiguousarray(faces.kind, dtype=np.int8), axis=np.ascontiguousarray(faces.axis, dtype=np.int8),
+            area=np.ascontiguousarray(faces.area, dtype=np.float64),
+            da=np.ascontiguousarray(faces.dist_a, dtype=np.float64),
+            db=np.ascontiguousarray(faces.dist_b, dtype=np.float64))
+        k = self._keep
+        F = _lib.msp_faces(k["ca"].size, _p(k["ca"], ctypes.c_int64), _p(k["cb"], ctypes.c_int64),
+                           _p(k["kind"], ctypes.c_int8), _p(k["axis"], ctypes.c_int8), _p(k["area"], ctypes.c_double),
+                           _p(k["da"], ctypes.c_double), _p(k["db"], ctypes.c_double))
+        self.img = np.ascontiguousarray(img, dtype=np.int64)
+        self.n_b, S = self.img.shape
+        self.s = S.bit_length() - 1
+        self.n = self.n_b * S
+        smap = _lib.msp_symmap(self.s, self.n_b, _p(self.img, ctypes.c_int64))
+        self._h = ctypes.c_void_p()
+        check(lib.msp_fv_create(ctypes.byref(F), ctypes.byref(smap), device, ctypes.byref(self._h)))
+
+    def assemble(self, kappa_base: np.ndarray) -> sp.csr_matrix:
+        kap = np.ascontiguousarray(kappa_base, dtype=np.float64)
+        nnz = ctypes.c_int64()
+        check(lib.msp_fv_nnz(self._h, ctypes.byref(nnz)))
+        rp = np.empty(self.n + 1, np.int64)
+        ci = np.empty(nnz.value, np.int32)
+        va = np.empty(nnz.value)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        check(lib.msp_fv_assemble(self._h, vp(kap), vp(rp), vp(ci), vp(va)))
+        return sp.csr_matrix((va, ci, rp), shape=(self.n, self.n))
+
+    def kappa_grad(self, kappa, lam, p, stream=None):
+        """dL/dkappa (torch, n_b) from lambda and p (torch, (n,) or (n, m))."""
+        import torch
+        lam2 = lam.reshape(self.n, -1).t().contiguous()
+        p2 = p.reshape(self.n, -1).t().contiguous()
+        kap = kappa.contiguous().to(torch.float64)
+        out = torch.empty(self.n_b, dtype=torch.float64, device=lam.device)
+        st = stream if stream is not None else torch.cuda.current_stream(lam.device)
+        check(lib.msp_fv_kappa_grad(self._h, ctypes.c_void_p(kap.data_ptr()), lam2.shape[0],
+                                    ctypes.c_void_p(lam2.data_ptr()), ctypes.c_void_p(p2.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib.msp_fv_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DifferentiablePoisson:
+    """Holds the operator and a solver for the last kappa seen."""
+
+    def __init__(self, faces, img, device: int = 0, **solver_opts):
+        self.op = FVOperator(faces, img, device)
+        self.opts = dict(solver_opts, device=device)
+        self._kappa = None
+        self.solver = None
+
+    def solver_for(self, kappa):
+        kap = kappa.detach().cpu().numpy()
+        if self._kappa is None or not np.array_equal(kap, self._kappa):
+            A = self.op.assemble(kap)
+            if self.solver is not None:
+                self.solver.close()
+            self.solver = Solver(A, self.op.img, **self.opts)
+            self._kappa = kap.copy()
+        return self.solver
+
+    def __call__(self, f, kappa):
+        return PoissonSolve.apply(f, kappa, self)
+
+
+def _torch_function():
+    import torch
+
+    class PoissonSolve(torch.autograd.Function):
+        """p = A(kappa)^{-1} f; backward: lambda = A^{-1} g, dL/df = lambda,
+        dL/dkappa = face-product gradient (library kernel)."""
+
+        @staticmethod
+        def forward(ctx, f, kappa, dp):
+            sv = dp.solver_for(kappa)
+            p = sv.solve(f.contiguous())
+            ctx.dp = dp
+            ctx.sv = sv
+            ctx.save_for_backward(p, kappa)
+            return p
+
+        @staticmethod
+        def backward(ctx, g):
+            p, kappa = ctx.saved_tensors
+            lam = ctx.sv.solve(g.contiguous())
+            gk = ctx.dp.op.kappa_grad(kappa, lam, p) if ctx.needs_input_grad[1] else None
+            return lam, gk, None
+
+    return PoissonSolve
+
+
+class _Lazy:
+    _fn = None
+
+    def __getattr__(self, name):
+        if _Lazy._fn is None:
+            _Lazy._fn = _torch_function()
+        return getattr(_Lazy._fn, name)
+
+
+PoissonSolve = _Lazy()

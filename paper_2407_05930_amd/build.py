@@ -28,7 +28,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 SOURCES = [
     ("host_setup.cpp", ["-ffp-contract=off"]),
     ("api.cpp", []),
-    ("lrc.cpp", []),
+    ("fv.cpp", []),
     ("kernels.hip", DEVICE),
     ("pcg.hip", DEVICE),
 ]

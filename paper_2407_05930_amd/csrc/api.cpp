@@ -654,6 +654,8 @@ static void fill_stats(msp_ctx* c) {
 }
 
 void build_lrc(msp_ctx* c);   // low-rank corrections (below)
+void fv_kappa_grad(msp_fv* f, const double* d_kap, int m, const double* d_lam, const double* d_p, double* d_grad,
+                   hipStream_t st);   // fv.cpp
 
 }  // namespace msp
 
@@ -854,6 +856,40 @@ int msp_get_timing(const msp_ctx* c, int32_t kind, int64_t* count, double* total
     if (total_bytes) *total_bytes = c->tm.bytes[kind];
     return MSP_OK;
 }
+
+int msp_fv_create(const msp_faces* F, const msp_symmap* map, int32_t device, msp_fv** out) {
+    return guarded([&]() -> int {
+        if (!out) throw Error(MSP_ERR_ARG, "null output");
+        *out = nullptr;
+        msp::fv_create(F, map, device, out);
+        return MSP_OK;
+    });
+}
+
+int msp_fv_nnz(const msp_fv* f, int64_t* nnz) {
+    if (!f || !nnz) return MSP_ERR_ARG;
+    *nnz = msp::fv_nnz(f);
+    return MSP_OK;
+}
+
+int msp_fv_assemble(const msp_fv* f, const double* kappa_base, int64_t* rowptr, int32_t* col, double* val) {
+    return guarded([&]() -> int {
+        if (!f) throw Error(MSP_ERR_ARG, "null operator");
+        msp::fv_assemble(f, kappa_base, rowptr, col, val);
+        return MSP_OK;
+    });
+}
+
+int msp_fv_kappa_grad(msp_fv* f, const double* d_kappa_base, int32_t m, const double* d_lambda, const double* d_p,
+                      double* d_grad, void* hip_stream) {
+    return guarded([&]() -> int {
+        if (!f) throw Error(MSP_ERR_ARG, "null operator");
+        msp::fv_kappa_grad(f, d_kappa_base, m, d_lambda, d_p, d_grad, static_cast<hipStream_t>(hip_stream));
+        return MSP_OK;
+    });
+}
+
+void msp_fv_free(msp_fv* f) { msp::fv_free(f); }
 
 void msp_free(msp_ctx* c) { delete c; }
 

@@ -59,6 +59,12 @@ HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface,
 // Static FSAI on the full lower pattern of A (the stand-alone FSAI of A_inn).
 Csr fsai_full_lower(const Csr& A);
 
+// finite-volume operator (fv.cpp)
+void fv_create(const msp_faces* F, const msp_symmap* map, int device, msp_fv** out);
+int64_t fv_nnz(const msp_fv* f);
+void fv_assemble(const msp_fv* f, const double* kappa_base, int64_t* rp, int32_t* ci, double* va);
+void fv_free(msp_fv* f);
+
 uint64_t splitmix64(uint64_t x);
 double unit_centered(uint64_t x);
 

@@ -474,6 +474,64 @@ __global__ __launch_bounds__(kBlock) void k_lrc_expand(int64_t n, int S, int k, 
     Z[idx] += s;
 }
 
+// ------------------------------------------------------------------ adjoint gradient
+// grad[i] = sum over the faces of base cell i, the images a and the right-hand
+// sides j of g_f dT_f/dkappa_i, with g_f = -(lam_u - lam_v)(p_u - p_v) for
+// interior and mirror faces and -lam_u p_u for wall faces (lam, p: n x m
+// column-major in the caller's ordering).  One thread per base cell, faces in
+// a fixed order: deterministic, no atomics.
+__global__ __launch_bounds__(kBlock) void k_kappa_grad(int64_t n_b, int S, int64_t n, int m,
+                                                       const int64_t* __restrict__ cfp,
+                                                       const int32_t* __restrict__ cfi,
+                                                       const int64_t* __restrict__ img,
+                                                       const int64_t* __restrict__ ca, const int64_t* __restrict__ cb,
+                                                       const int8_t* __restrict__ kind,
+                                                       const int8_t* __restrict__ axis,
+                                                       const double* __restrict__ area,
+                                                       const double* __restrict__ da, const double* __restrict__ db,
+                                                       const double* __restrict__ kap,
+                                                       const double* __restrict__ lam, const double* __restrict__ p,
+                                                       double* __restrict__ grad) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_b) return;
+    const double ki = kap[i];
+    double acc = 0.0;
+    for (int64_t e = cfp[i]; e < cfp[i + 1]; ++e) {
+        const int64_t q = cfi[e];
+        const int K = kind[q];
+        if (K == 0) {
+            const bool first = ca[q] == i;
+            const int64_t o = first ? cb[q] : ca[q];
+            const double di = first ? da[q] : db[q], dout = first ? db[q] : da[q];
+            const double T = area[q] / (di / ki + dout / kap[o]);
+            const double dT = T * T * di / (area[q] * ki * ki);
+            for (int a = 0; a < S; ++a)
+                for (int j = 0; j < m; ++j) {
+                    const int64_t u = img[i * S + a] + (int64_t)j * n, v = img[o * S + a] + (int64_t)j * n;
+                    acc += -(lam[u] - lam[v]) * (p[u] - p[v]) * dT;
+                }
+        } else if (K == 1) {
+            const double dT = area[q] / da[q];
+            for (int a = 0; a < S; ++a)
+                for (int j = 0; j < m; ++j) {
+                    const int64_t u = img[i * S + a] + (int64_t)j * n;
+                    acc += -lam[u] * p[u] * dT;
+                }
+        } else {
+            const int bit = 1 << axis[q];
+            const double dT = area[q] / (2.0 * da[q]);
+            for (int a = 0; a < S; ++a) {
+                if (a & bit) continue;   // each mirror pair once
+                for (int j = 0; j < m; ++j) {
+                    const int64_t u = img[i * S + a] + (int64_t)j * n, v = img[i * S + (a ^ bit)] + (int64_t)j * n;
+                    acc += -(lam[u] - lam[v]) * (p[u] - p[v]) * dT;
+                }
+            }
+        }
+    }
+    grad[i] = acc;
+}
+
 // ------------------------------------------------------------------ host launchers
 
 
@@ -655,6 +713,15 @@ hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {
 }
 template hipError_t launch_fill<double>(hipStream_t, int64_t, double*, double);
 template hipError_t launch_fill<float>(hipStream_t, int64_t, float*, float);
+
+hipError_t launch_kappa_grad(hipStream_t st, int64_t n_b, int S, int64_t n, int m, const int64_t* cfp,
+                            const int32_t* cfi, const int64_t* img, const int64_t* ca, const int64_t* cb,
+                            const int8_t* kind, const int8_t* axis, const double* area, const double* da,
+                            const double* db, const double* kap, const double* lam, const double* p, double* grad) {
+    hipLaunchKernelGGL(k_kappa_grad, dim3(blocks_for(n_b, kBlock)), dim3(kBlock), 0, st, n_b, S, n, m, cfp, cfi, img,
+                       ca, cb, kind, axis, area, da, db, kap, lam, p, grad);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_scale_cols(hipStream_t st, int64_t len, int C, T* X, const double* f) {

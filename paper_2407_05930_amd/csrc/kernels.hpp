@@ -48,6 +48,12 @@ hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v);
 template <typename TO, typename TI>
 hipError_t launch_cast(hipStream_t st, int64_t len, const TI* a, TO* b);
 
+// dL/dkappa per base cell from face products (see msp_fv_kappa_grad)
+hipError_t launch_kappa_grad(hipStream_t st, int64_t n_b, int S, int64_t n, int m, const int64_t* cfp,
+                            const int32_t* cfi, const int64_t* img, const int64_t* ca, const int64_t* cb,
+                            const int8_t* kind, const int8_t* axis, const double* area, const double* da,
+                            const double* db, const double* kap, const double* lam, const double* p, double* grad);
+
 // column-wise: X[:, c] *= f[c]; Y[:, c] -= h[c] X[:, c]  (len = rows * C)
 template <typename T>
 hipError_t launch_scale_cols(hipStream_t st, int64_t len, int C, T* X, const double* f);

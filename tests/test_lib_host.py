@@ -117,3 +117,16 @@ def test_host_only_context_cannot_solve():
     with pytest.raises(MspError) as e:
         sv.solve_host(p.b)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(jitter=0.2, kappa="lognormal"), dict(y_stretch=1.5)])
+def test_library_assembly_matches_generator(kw):
+    """The library's finite-volume assembly (host C++) reproduces the
+    generator's matrix, in the generator's natural ordering."""
+    from paper_2407_05930_amd.adjoint import FVOperator
+    p = make_problem((10, 8, 6), s=3 if "jitter" in kw else 2, seed=4, **kw)
+    op = FVOperator(p.faces, p.img, device=-1)
+    A = op.assemble(p.kappa_base)
+    assert A.shape == p.A.shape
+    assert np.array_equal(A.indptr, p.A.indptr) and np.array_equal(A.indices, p.A.indices)
+    assert np.abs(A.data - p.A.data).max() <= 1e-15 * np.abs(p.A.data).max()
