@@ -168,6 +168,31 @@ int msp_reset_timing(msp_ctx* c);
 int msp_get_timing(const msp_ctx* c, int32_t kind, int64_t* count, double* total_ms, double* total_bytes);
 
 /* ---------------------------------------------------------------------------
+ * Batched solves: many independent systems (different sizes, symmetries and
+ * right-hand-side counts) solved together.  Setup builds one context per
+ * system (host parts in parallel threads).  Solve starts every system on its
+ * own stream, then replays one captured HIP graph holding K PCG iterations of
+ * every system in parallel branches (default K = 4) until all columns of all
+ * systems have converged; columns that converge earlier are frozen on the
+ * device (their updates are zero), so the extra iterations of a chunk leave
+ * their solutions unchanged.  The graph is re-captured when the vector of m
+ * changes.  SpMM lane-group splits are autotuned per matrix and column count.
+ * --------------------------------------------------------------------------- */
+typedef struct msp_batch msp_batch;   /* opaque; owned by the library until msp_batch_free */
+
+/* nsys systems: A[i], maps[i] (host), common options (device >= 0). */
+int msp_batch_setup(int32_t nsys, const msp_csr* A, const msp_symmap* maps, const msp_opts* o, msp_batch** out);
+/* m[i] right-hand sides of system i; d_b[i], d_x[i]: device n_i x m[i]
+   column-major; work ordered after hip_stream and before it continues;
+   st: nsys statistics records or NULL.  Returns the worst status. */
+int msp_batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b, double* const* d_x, void* hip_stream,
+                    msp_stats* st);
+int msp_batch_size(const msp_batch* bt, int32_t* nsys);
+/* Iterations per graph replay (1..64). */
+int msp_batch_set_chunk(msp_batch* bt, int32_t iterations);
+void msp_batch_free(msp_batch* bt);
+
+/* ---------------------------------------------------------------------------
  * Finite-volume operator and adjoint gradient (differentiable solves).
  *
  * The two-point-flux Poisson matrix -div(kappa grad p) is described by the

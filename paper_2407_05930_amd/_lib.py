@@ -84,6 +84,11 @@ SIGNATURES = {
     "msp_reset_timing": (ctypes.c_int, [_vp]),
     "msp_get_timing": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_double),
                                       _P(ctypes.c_double)]),
+    "msp_batch_setup": (ctypes.c_int, [ctypes.c_int32, _P(msp_csr), _P(msp_symmap), _P(msp_opts), _P(_vp)]),
+    "msp_batch_solve": (ctypes.c_int, [_vp, _P(ctypes.c_int32), _P(_vp), _P(_vp), _vp, _P(msp_stats)]),
+    "msp_batch_size": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
+    "msp_batch_set_chunk": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "msp_batch_free": (None, [_vp]),
     "msp_fv_create": (ctypes.c_int, [_P(msp_faces), _P(msp_symmap), ctypes.c_int32, _P(_vp)]),
     "msp_fv_nnz": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "msp_fv_assemble": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),

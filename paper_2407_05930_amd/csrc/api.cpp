@@ -3,12 +3,14 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -36,6 +38,7 @@ struct DevCsr {
     int32_t* ci = nullptr;
     double* v64 = nullptr;
     float* v32 = nullptr;
+    Bf16* v16 = nullptr;      // bfloat16 values (smoother in the BF16 variant)
 };
 
 struct DevLevel {
@@ -165,7 +168,15 @@ struct msp_ctx {
 
 namespace msp {
 
-static DevCsr upload_csr(msp_ctx* c, const Csr& M, bool fp32) {
+// round-to-nearest-even binary32 -> bfloat16 (finite inputs)
+static Bf16 to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return Bf16{static_cast<uint16_t>(r >> 16)};
+}
+
+static DevCsr upload_csr(msp_ctx* c, const Csr& M, bool fp32, bool bf16 = false) {
     DevCsr D;
     D.nr = M.nr;
     D.nc = M.nc;
@@ -183,6 +194,11 @@ static DevCsr upload_csr(msp_ctx* c, const Csr& M, bool fp32) {
     if (fp32) {
         std::vector<float> f(M.v.begin(), M.v.end());
         D.v32 = c->upload(f.data(), D.nnz);
+        if (bf16) {
+            std::vector<Bf16> h(f.size());
+            for (size_t q = 0; q < f.size(); ++q) h[q] = to_bf16(f[q]);
+            D.v16 = c->upload(h.data(), D.nnz);
+        }
     }
     return D;
 }
@@ -238,7 +254,8 @@ static void resolve_timers(msp_ctx* c) {
 template <typename T>
 static double spmm_bytes(const DevCsr& M, int C, bool z, bool sig, int S) {
     const double w = sizeof(T);
-    double b = static_cast<double>(M.nnz) * (w + 4.0) + 4.0 * static_cast<double>(M.nr + 1);
+    const double wv = (sizeof(T) == 4 && M.v16) ? 2.0 : w;
+    double b = static_cast<double>(M.nnz) * (wv + 4.0) + 4.0 * static_cast<double>(M.nr + 1);
     b += static_cast<double>(M.nc) * C * w + static_cast<double>(M.nr) * C * w;
     if (z) b += static_cast<double>(M.nr) * C * w;
     if (sig) b += static_cast<double>(M.nr) * S * 8.0;
@@ -251,14 +268,26 @@ static int log2i(int C) {
     return l;
 }
 
-// One SpMM launch with an explicit lane-group split (1 = one group per row).
+// One SpMM launch with an explicit lane-group split (1 = one group per row);
+// FP32 products use the bfloat16 values when the matrix carries them.
 template <typename T>
 static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const T* X, T* Y, const T* Z, T alpha,
                         T beta, const double* sigma, int S, int m) {
+    if constexpr (sizeof(T) == 4) {
+        if (M.v16) {
+            if (split > 1 && !sigma)
+                HIPCHECK((launch_spmm_split<float, Bf16>(st, C, split, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha,
+                                                         beta)));
+            else
+                HIPCHECK((launch_spmm<float, Bf16>(st, C, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta, sigma, S,
+                                                   m)));
+            return;
+        }
+    }
     if (split > 1 && !sigma)
-        HIPCHECK(launch_spmm_split<T>(st, C, split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta));
+        HIPCHECK((launch_spmm_split<T, T>(st, C, split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta)));
     else
-        HIPCHECK(launch_spmm<T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m));
+        HIPCHECK((launch_spmm<T, T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m)));
 }
 
 template <typename T>
@@ -468,7 +497,7 @@ static void upload_all(msp_ctx* c) {
             D.A = upload_csr(c, H.A, f32);
             D.P = upload_csr(c, H.P, f32);
             D.R = upload_csr(c, H.R, f32);
-            D.M = upload_csr(c, H.M, f32);
+            D.M = upload_csr(c, H.M, f32, c->o.precision == MSP_MIXED_FP32_BF16G);
             D.omega = H.omega;
         }
         c->nL = c->hier.lev.back().A.nr;
@@ -486,148 +515,203 @@ static int next_pow2(int x) {
     return c;
 }
 
-static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipStream_t st, msp_stats* out) {
-    if (!c->on_device) throw Error(MSP_ERR_ARG, "context was set up without a device");
-    if (m <= 0 || !d_b || !d_x) throw Error(MSP_ERR_ARG, "need m > 0 and device arrays");
-    HIPCHECK(hipSetDevice(c->device));
-    const int S = 1 << c->sym.s;
-    const int ncol = S * m;
-    if (ncol > 64) throw Error(MSP_ERR_UNSUPPORTED, "2^s * m must not exceed 64");
-    const int C = next_pow2(ncol);
-    Work& w = work(c, C);
-    w.m = m;
-    const int64_t nb = c->sym.n_b, n = c->sym.n;
-    double* sc = w.scal;
-    double *rr = sc + SC_RR * 64, *rz = sc + SC_RZ * 64, *pq = sc + SC_PQ * 64, *rho = sc + SC_RHO * 64,
-           *alpha = sc + SC_ALPHA * 64, *beta = sc + SC_BETA * 64, *thr = sc + SC_THR * 64,
-           *rnorm = sc + SC_RNORM * 64, *bn2 = sc + SC_BN2 * 64, *rzold = sc + SC_RZOLD * 64;
-    int* active = w.iscal;
-    int* iters = w.iscal + 64;
-    int* flags = w.iscal + 128;
-    const bool flexible = mixed(c) && c->o.pc == MSP_PC_AMGR;
-    const auto t0 = std::chrono::steady_clock::now();
+// One solve split into phases so that iterations can be enqueued without
+// host synchronisation (and captured into a graph for batched solves):
+//   begin:  norms, thresholds, Q_s forward, initial residual checks, z, rho, p
+//   half_a: q = A p, alpha, x/r update, convergence check   (flags)
+//   half_b: z = M^{-1} r (+ corrections), beta, p update
+//   finish: Q_s backward, statistics
+// Frozen columns are masked on the device (alpha = beta = 0), so extra
+// iterations after convergence leave x unchanged.
+struct SolvePlan {
+    msp_ctx* c;
+    Work* w;
+    hipStream_t st;
+    int m, S, C, nbp, kl, O;
+    int64_t nb, n;
+    bool flexible, lrc_amg;
+    double *rr, *rz, *pq, *rho, *alpha, *beta, *thr, *rnorm, *bn2, *rzold;
+    int *active, *iters, *flags;
 
-    HIPCHECK(launch_colnorm2(st, n, m, d_b, w.pp1, std::min<int64_t>(512, (n + 255) / 256), bn2));
-    HIPCHECK(launch_thresholds(st, C, S, m, c->o.tol, bn2, thr));
-    HIPCHECK(launch_fill<double>(st, nb * C, w.r, 0.0));
-    HIPCHECK(launch_fill<double>(st, nb * C, w.x, 0.0));
-    HIPCHECK(hipMemsetAsync(flags, 0, 2 * sizeof(int), st));
-    timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // bhat = Q_s b
-          [&] { HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, w.r)); });
+    SolvePlan(msp_ctx* c_, int m_, hipStream_t st_) : c(c_), st(st_), m(m_) {
+        if (!c->on_device) throw Error(MSP_ERR_ARG, "context was set up without a device");
+        if (m <= 0) throw Error(MSP_ERR_ARG, "need m > 0");
+        HIPCHECK(hipSetDevice(c->device));
+        S = 1 << c->sym.s;
+        const int ncol = S * m;
+        if (ncol > 64) throw Error(MSP_ERR_UNSUPPORTED, "2^s * m must not exceed 64");
+        C = next_pow2(ncol);
+        w = &work(c, C);
+        w->m = m;
+        nb = c->sym.n_b;
+        n = c->sym.n;
+        double* sc = w->scal;
+        rr = sc + SC_RR * 64; rz = sc + SC_RZ * 64; pq = sc + SC_PQ * 64; rho = sc + SC_RHO * 64;
+        alpha = sc + SC_ALPHA * 64; beta = sc + SC_BETA * 64; thr = sc + SC_THR * 64;
+        rnorm = sc + SC_RNORM * 64; bn2 = sc + SC_BN2 * 64; rzold = sc + SC_RZOLD * 64;
+        active = w->iscal;
+        iters = w->iscal + 64;
+        flags = w->iscal + 128;
+        flexible = mixed(c) && c->o.pc == MSP_PC_AMGR;
+        nbp = pcg_grid(C, nb);
+        lrc_amg = c->d_U && c->o.pc == MSP_PC_AMGR;
+        kl = lrc_amg ? c->lrc_k : 0;
+        O = S * kl * m;
+    }
 
-    const int nbp = pcg_grid(C, nb);
-    const bool lrc_amg = c->d_U && c->o.pc == MSP_PC_AMGR;
-    const int kl = lrc_amg ? c->lrc_k : 0;
-    const int O = S * kl * m;
-    const double wu = c->U32 ? 4.0 : 8.0;
-    const double vb = 8.0 * nb * C;   // bytes of one FP64 multivector pass
-    // <r,r>, U^T r and (initial) active flags; then z = M^{-1} r and rho = <r,z>
-    auto update_dots = [&](bool upd) {
-        const double bytes = (upd ? 6.0 : 1.0) * vb + (flexible && upd ? vb : 0.0) + (kl ? nb * S * kl * wu : 0.0);
+    double vb() const { return 8.0 * nb * C; }   // bytes of one FP64 multivector pass
+
+    // <r,r>, U^T r and the convergence check (initial: the active flags)
+    void update_dots(bool upd) {
+        Work& W = *w;
+        const double wu = c->U32 ? 4.0 : 8.0;
+        const double bytes = (upd ? 6.0 : 1.0) * vb() + (flexible && upd ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0);
         timed(c, KD_UPDATE, bytes, st, [&] {
             if (c->U32 || !c->d_U)
-                HIPCHECK(launch_update_dots<float>(st, C, nbp, upd, flexible && upd, kl, nb, w.x, w.r, w.p, w.q, alpha,
-                                                   w.z, static_cast<const float*>(c->d_U), S, m, w.pp1, w.pp2,
-                                                   w.plrc));
+                HIPCHECK(launch_update_dots<float>(st, C, nbp, upd, flexible && upd, kl, nb, W.x, W.r, W.p, W.q, alpha,
+                                                   W.z, static_cast<const float*>(c->d_U), S, m, W.pp1, W.pp2,
+                                                   W.plrc));
             else
-                HIPCHECK(launch_update_dots<double>(st, C, nbp, upd, flexible && upd, kl, nb, w.x, w.r, w.p, w.q,
-                                                    alpha, w.z, static_cast<const double*>(c->d_U), S, m, w.pp1,
-                                                    w.pp2, w.plrc));
+                HIPCHECK(launch_update_dots<double>(st, C, nbp, upd, flexible && upd, kl, nb, W.x, W.r, W.p, W.q,
+                                                    alpha, W.z, static_cast<const double*>(c->d_U), S, m, W.pp1,
+                                                    W.pp2, W.plrc));
         });
-        HIPCHECK(launch_fin_check(st, C, nbp, !upd, flexible && upd, O, m, w.pp1, w.pp2, w.plrc, thr, c->d_lrc_coef,
+        HIPCHECK(launch_fin_check(st, C, nbp, !upd, flexible && upd, O, m, W.pp1, W.pp2, W.plrc, thr, c->d_lrc_coef,
                                   active, iters, flags, rnorm, rzold, c->d_lrc_W));
-    };
-    auto precond_dot = [&](bool init) {
+    }
+
+    // z = M^{-1} r (+ low-rank corrections), <r,z>, beta and rho
+    void precond_dot(bool init) {
+        Work& W = *w;
         const float* s32 = nullptr;
         if (c->o.pc == MSP_PC_AMGR && mixed(c)) {
-            float* y0 = static_cast<float*>(w.vy[0]);
-            float* s0 = static_cast<float*>(w.vs[0]);
+            float* y0 = static_cast<float*>(W.vy[0]);
+            float* s0 = static_cast<float*>(W.vs[0]);
             timed(c, KD_CAST, 12.0 * nb * C, st,
-                  [&] { HIPCHECK((launch_cast<float, double>(st, nb * C, w.r, y0))); });
-            vcycle<float>(c, w, st, 0, y0, s0);
+                  [&] { HIPCHECK((launch_cast<float, double>(st, nb * C, W.r, y0))); });
+            vcycle<float>(c, W, st, 0, y0, s0);
             s32 = s0;
         } else {
-            precondition_base(c, w, st, w.r, w.z, true);
+            precondition_base(c, W, st, W.r, W.z, true);
         }
-        const double bytes = (s32 ? 4.0 : 8.0) * nb * C + 2.0 * vb + (kl ? nb * S * kl * wu : 0.0);
+        const double wu = c->U32 ? 4.0 : 8.0;
+        const double bytes = (s32 ? 4.0 : 8.0) * nb * C + 2.0 * vb() + (kl ? nb * S * kl * wu : 0.0);
+        const void* U = lrc_amg ? c->d_U : nullptr;
         timed(c, KD_CAST, bytes, st, [&] {
             if (s32) {
                 if (c->U32 || !c->d_U)
-                    HIPCHECK((launch_zfinish<float, float>(st, C, nbp, nb, s32, w.z, w.r,
-                                                           static_cast<const float*>(lrc_amg ? c->d_U : nullptr),
-                                                           c->d_lrc_W, S, kl, m, w.pp1)));
+                    HIPCHECK((launch_zfinish<float, float>(st, C, nbp, nb, s32, W.z, W.r, static_cast<const float*>(U),
+                                                           c->d_lrc_W, S, kl, m, W.pp1)));
                 else
-                    HIPCHECK((launch_zfinish<float, double>(st, C, nbp, nb, s32, w.z, w.r,
-                                                            static_cast<const double*>(lrc_amg ? c->d_U : nullptr),
-                                                            c->d_lrc_W, S, kl, m, w.pp1)));
+                    HIPCHECK((launch_zfinish<float, double>(st, C, nbp, nb, s32, W.z, W.r,
+                                                            static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
+                                                            W.pp1)));
             } else {
                 if (c->U32 || !c->d_U)
-                    HIPCHECK((launch_zfinish<double, float>(st, C, nbp, nb, w.z, w.z, w.r,
-                                                            static_cast<const float*>(lrc_amg ? c->d_U : nullptr),
-                                                            c->d_lrc_W, S, kl, m, w.pp1)));
+                    HIPCHECK((launch_zfinish<double, float>(st, C, nbp, nb, W.z, W.z, W.r,
+                                                            static_cast<const float*>(U), c->d_lrc_W, S, kl, m,
+                                                            W.pp1)));
                 else
-                    HIPCHECK((launch_zfinish<double, double>(st, C, nbp, nb, w.z, w.z, w.r,
-                                                             static_cast<const double*>(lrc_amg ? c->d_U : nullptr),
-                                                             c->d_lrc_W, S, kl, m, w.pp1)));
+                    HIPCHECK((launch_zfinish<double, double>(st, C, nbp, nb, W.z, W.z, W.r,
+                                                             static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
+                                                             W.pp1)));
             }
         });
-        HIPCHECK(launch_fin_beta(st, C, nbp, init, flexible, w.pp1, active, rzold, rho, beta, rz));
-    };
+        HIPCHECK(launch_fin_beta(st, C, nbp, init, flexible, W.pp1, active, rzold, rho, beta, rz));
+    }
 
-    update_dots(false);
-    precond_dot(true);
-    HIPCHECK(hipMemcpyAsync(w.p, w.z, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
-    HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    int nactive = w.h_flags[1];
-    int it = 0;
-    int status = MSP_OK;
-    if (w.h_flags[0]) status = MSP_ERR_BREAKDOWN;
-    while (status == MSP_OK && nactive > 0 && it < c->o.maxit) {
-        const double opb = spmm_bytes<double>(c->dAinn, C, false, true, S) + vb;
+    void begin(const double* d_b) {
+        Work& W = *w;
+        HIPCHECK(launch_colnorm2(st, n, m, d_b, W.pp1, std::min<int64_t>(512, (n + 255) / 256), bn2));
+        HIPCHECK(launch_thresholds(st, C, S, m, c->o.tol, bn2, thr));
+        HIPCHECK(launch_fill<double>(st, nb * C, W.r, 0.0));
+        HIPCHECK(launch_fill<double>(st, nb * C, W.x, 0.0));
+        HIPCHECK(launch_fill<int>(st, 2, flags, 0));
+        timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // bhat = Q_s b
+              [&] { HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, W.r)); });
+        update_dots(false);
+        precond_dot(true);
+        HIPCHECK(hipMemcpyAsync(W.p, W.z, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
+    }
+
+    void half_a() {
+        Work& W = *w;
+        const double opb = spmm_bytes<double>(c->dAinn, C, false, true, S) + vb();
         timed(c, KD_OP, opb, st, [&] {   // q = Ahat p and <p, q>
-            HIPCHECK(launch_op_dot(st, C, nbp, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, c->d_sigma, S, m, w.p, w.q,
-                                   w.pp1));
+            HIPCHECK(launch_op_dot(st, C, nbp, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, c->d_sigma, S, m, W.p, W.q,
+                                   W.pp1));
         });
-        HIPCHECK(launch_fin_alpha(st, C, nbp, w.pp1, active, rho, alpha, pq, flags));
+        HIPCHECK(launch_fin_alpha(st, C, nbp, W.pp1, active, rho, alpha, pq, flags));
         update_dots(true);
-        HIPCHECK(hipMemcpyAsync(w.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    }
+
+    void half_b() {
+        Work& W = *w;
+        precond_dot(false);
+        timed(c, KD_PUPDATE, 24.0 * nb * C, st,
+              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, W.p, W.z, beta, active)); });
+    }
+
+    void read_flags() {
+        HIPCHECK(hipMemcpyAsync(w->h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
+    }
+
+    // Q_s backward and statistics (status: MSP_OK / MSP_NOT_CONVERGED / breakdown)
+    int finish(double* d_x, int status, double seconds, msp_stats* out) {
+        Work& W = *w;
+        timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // x = Q_s xhat
+              [&] { HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, W.x, d_x)); });
+        HIPCHECK(hipMemcpyAsync(W.h_iters, iters, 64 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipMemcpyAsync(W.h_scal, W.scal, SC_COUNT * 64 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipMemcpyAsync(W.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        resolve_timers(c);
+        if (status == MSP_OK && W.h_flags[0]) status = MSP_ERR_BREAKDOWN;
+        if (status == MSP_OK && W.h_flags[1] > 0) status = MSP_NOT_CONVERGED;
+        msp_stats& R = c->stats;
+        R.iters = 0;
+        for (int q = 0; q < S * m; ++q) R.iters = std::max(R.iters, W.h_iters[q]);
+        for (int j = 0; j < 64; ++j) R.relres[j] = 0.0;
+        for (int j = 0; j < m && j < 64; ++j) {
+            double s2 = 0.0;
+            for (int a = 0; a < S; ++a) {
+                const double v = W.h_scal[SC_RNORM * 64 + a * m + j];
+                s2 += v * v;
+            }
+            const double bn = std::sqrt(W.h_scal[SC_BN2 * 64 + j]);
+            R.relres[j] = bn > 0 ? std::sqrt(s2) / bn : 0.0;
+        }
+        R.status = status;
+        R.t_solve_s = seconds;
+        if (out) *out = R;
+        return status;
+    }
+};
+
+static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipStream_t st, msp_stats* out) {
+    if (!d_b || !d_x) throw Error(MSP_ERR_ARG, "need device arrays");
+    SolvePlan P(c, m, st);
+    const auto t0 = std::chrono::steady_clock::now();
+    P.begin(d_b);
+    P.read_flags();
+    int status = P.w->h_flags[0] ? MSP_ERR_BREAKDOWN : MSP_OK;
+    int nactive = P.w->h_flags[1];
+    int it = 0;
+    while (status == MSP_OK && nactive > 0 && it < c->o.maxit) {
+        P.half_a();
+        P.read_flags();
         ++it;
-        if (w.h_flags[0]) {
+        if (P.w->h_flags[0]) {
             status = MSP_ERR_BREAKDOWN;
             break;
         }
-        nactive = w.h_flags[1];
+        nactive = P.w->h_flags[1];
         if (nactive == 0) break;
-        precond_dot(false);
-        timed(c, KD_PUPDATE, 24.0 * nb * C, st,
-              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, w.p, w.z, beta, active)); });
+        P.half_b();
     }
-    if (status == MSP_OK && nactive > 0) status = MSP_NOT_CONVERGED;
-    timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // x = Q_s xhat
-          [&] { HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, w.x, d_x)); });
-    HIPCHECK(hipMemcpyAsync(w.h_iters, iters, 64 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(w.h_scal, sc, SC_COUNT * 64 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    const auto t1 = std::chrono::steady_clock::now();
-    resolve_timers(c);
-    msp_stats& S_ = c->stats;
-    S_.iters = 0;
-    for (int q = 0; q < ncol; ++q) S_.iters = std::max(S_.iters, w.h_iters[q]);
-    for (int j = 0; j < 64; ++j) S_.relres[j] = 0.0;
-    for (int j = 0; j < m && j < 64; ++j) {
-        double s2 = 0.0;
-        for (int a = 0; a < S; ++a) {
-            const double v = w.h_scal[SC_RNORM * 64 + a * m + j];
-            s2 += v * v;
-        }
-        const double bn = std::sqrt(w.h_scal[SC_BN2 * 64 + j]);
-        S_.relres[j] = bn > 0 ? std::sqrt(s2) / bn : 0.0;
-    }
-    S_.status = status;
-    S_.t_solve_s = std::chrono::duration<double>(t1 - t0).count();
-    if (out) *out = S_;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    status = P.finish(d_x, status, secs, out);
     if (status == MSP_ERR_BREAKDOWN) throw Error(MSP_ERR_BREAKDOWN, "PCG breakdown: p^T A p <= 0 or not finite");
     return status;
 }
@@ -682,6 +766,208 @@ static int guarded(F&& f) {
     }
 }
 
+static void check_opts(const msp_opts* o) {
+    if (!o) throw Error(MSP_ERR_ARG, "null options");
+    if (o->precision < MSP_FP64 || o->precision > MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_ARG, "precision");
+    if (o->pc < MSP_PC_AMGR || o->pc > MSP_PC_NONE) throw Error(MSP_ERR_ARG, "pc");
+    if (o->lrc_k < 0 || o->dist < 1 || o->jacobi0 < 1 || o->jacobi < 1 || o->coarse_max < 1 || o->max_levels < 1 ||
+        !(o->theta >= 0.0) || !(o->tol > 0.0) || o->maxit < 0)
+        throw Error(MSP_ERR_ARG, "invalid option value");
+    if (o->lrc_k > 0 && o->pc == MSP_PC_NONE) throw Error(MSP_ERR_ARG, "low-rank corrections need a preconditioner");
+    if (o->lrc_k > 16) throw Error(MSP_ERR_UNSUPPORTED, "low-rank correction rank above 16");
+}
+
+// Host part of the setup: blocks, validation, hierarchy (no HIP calls).
+static std::unique_ptr<msp_ctx> setup_host(const msp_csr* A, const msp_symmap* map, const msp_opts* o) {
+    std::unique_ptr<msp_ctx> c(new msp_ctx());
+    c->o = *o;
+    c->device = o->device;
+    c->lrc_k = o->lrc_k;
+    c->sym = msp::extract_blocks(A, map);
+    if (o->pc == MSP_PC_AMGR) {
+        c->hier = msp::build_hierarchy(c->sym.Ainn, c->sym.iface, *o);
+    } else {
+        c->hier.lev.emplace_back();
+        c->hier.lev.back().A = c->sym.Ainn;
+        if (o->pc == MSP_PC_FSAI) c->Gf = msp::fsai_full_lower(c->sym.Ainn);
+    }
+    msp::fill_stats(c.get());
+    return c;
+}
+
+// Device part: upload and low-rank corrections.
+static void setup_device(msp_ctx* c) {
+    int ndev = 0;
+    HIPCHECK(hipGetDeviceCount(&ndev));
+    if (c->o.device >= ndev) throw Error(MSP_ERR_ARG, "device ordinal out of range");
+    msp::upload_all(c);
+    if (c->lrc_k > 0) msp::build_lrc(c);
+    HIPCHECK(hipDeviceSynchronize());
+}
+
+// ====================================================================== batched solves
+
+struct msp_batch {
+    std::vector<msp_ctx*> sys;
+    std::vector<hipStream_t> streams;
+    hipStream_t main = nullptr;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
+    // graph of K iterations of every system, cached for one vector of m
+    std::vector<int> graph_m;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int K = 4;
+    int** d_flag_ptrs = nullptr;
+    int* d_flags = nullptr;
+    int* h_flags = nullptr;
+    ~msp_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : joins) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto s : streams) (void)hipStreamDestroy(s);
+        if (main) (void)hipStreamDestroy(main);
+        if (d_flag_ptrs) (void)hipFree(d_flag_ptrs);
+        if (d_flags) (void)hipFree(d_flags);
+        if (h_flags) (void)hipHostFree(h_flags);
+        for (auto c : sys) delete c;
+    }
+};
+
+namespace msp {
+
+static void batch_setup(int nsys, const msp_csr* A, const msp_symmap* maps, const msp_opts* o, msp_batch** out) {
+    if (nsys <= 0 || !A || !maps || !out) throw Error(MSP_ERR_ARG, "bad batch arguments");
+    check_opts(o);
+    if (o->device < 0) throw Error(MSP_ERR_ARG, "batched solves need a device");
+    std::unique_ptr<msp_batch> bt(new msp_batch());
+    bt->sys.assign(nsys, nullptr);
+    // host setups in parallel (each context is independent)
+    std::vector<std::unique_ptr<msp_ctx>> hosts(nsys);
+    std::vector<std::string> errs(nsys);
+    std::vector<int> codes(nsys, MSP_OK);
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::atomic<int> next(0);
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth; ++t)
+        pool.emplace_back([&]() {
+            for (int i = next++; i < nsys; i = next++) {
+                try {
+                    hosts[i] = setup_host(&A[i], &maps[i], o);
+                } catch (const Error& e) {
+                    codes[i] = e.status;
+                    errs[i] = e.what();
+                } catch (const std::exception& e) {
+                    codes[i] = MSP_ERR_ARG;
+                    errs[i] = e.what();
+                }
+            }
+        });
+    for (auto& th : pool) th.join();
+    for (int i = 0; i < nsys; ++i)
+        if (codes[i] != MSP_OK) throw Error(codes[i], "system " + std::to_string(i) + ": " + errs[i]);
+    HIPCHECK(hipSetDevice(o->device));
+    for (int i = 0; i < nsys; ++i) {
+        setup_device(hosts[i].get());
+        bt->sys[i] = hosts[i].release();
+    }
+    bt->streams.resize(nsys);
+    bt->joins.resize(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        HIPCHECK(hipStreamCreateWithFlags(&bt->streams[i], hipStreamNonBlocking));
+        HIPCHECK(hipEventCreateWithFlags(&bt->joins[i], hipEventDisableTiming));
+    }
+    HIPCHECK(hipStreamCreateWithFlags(&bt->main, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming));
+    HIPCHECK(hipMalloc(&bt->d_flag_ptrs, sizeof(int*) * nsys));
+    HIPCHECK(hipMalloc(&bt->d_flags, sizeof(int) * 2 * nsys));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&bt->h_flags), sizeof(int) * 2 * nsys, hipHostMallocDefault));
+    *out = bt.release();
+}
+
+// Solve every system: eager start per system on its own stream, then graph
+// replays of K iterations of all systems (one branch per system) until every
+// column of every system has converged, then the back transforms.
+static int batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b, double* const* d_x,
+                       hipStream_t user, msp_stats* st) {
+    const int nsys = static_cast<int>(bt->sys.size());
+    if (!m || !d_b || !d_x) throw Error(MSP_ERR_ARG, "null batch arrays");
+    HIPCHECK(hipSetDevice(bt->sys[0]->device));
+    std::vector<std::unique_ptr<SolvePlan>> plans(nsys);
+    for (int i = 0; i < nsys; ++i) {
+        if (!d_b[i] || !d_x[i]) throw Error(MSP_ERR_ARG, "null device array in batch");
+        std::fill(bt->sys[i]->tm.on.begin(), bt->sys[i]->tm.on.end(), 0);
+        plans[i].reset(new SolvePlan(bt->sys[i], m[i], bt->streams[i]));
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    HIPCHECK(hipEventRecord(bt->fork, user));
+    for (int i = 0; i < nsys; ++i) {
+        HIPCHECK(hipStreamWaitEvent(bt->streams[i], bt->fork, 0));
+        plans[i]->begin(d_b[i]);
+    }
+    // device pointers of every system's flags
+    std::vector<int*> ptrs(nsys);
+    for (int i = 0; i < nsys; ++i) ptrs[i] = plans[i]->flags;
+    HIPCHECK(hipMemcpy(bt->d_flag_ptrs, ptrs.data(), sizeof(int*) * nsys, hipMemcpyHostToDevice));
+    for (int i = 0; i < nsys; ++i) HIPCHECK(hipStreamSynchronize(bt->streams[i]));
+    std::vector<int> mv(m, m + nsys);
+    if (!bt->exec || mv != bt->graph_m) {
+        if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+        if (bt->graph) (void)hipGraphDestroy(bt->graph);
+        bt->exec = nullptr;
+        bt->graph = nullptr;
+        HIPCHECK(hipStreamBeginCapture(bt->main, hipStreamCaptureModeRelaxed));
+        HIPCHECK(hipEventRecord(bt->fork, bt->main));
+        for (int i = 0; i < nsys; ++i) {
+            HIPCHECK(hipStreamWaitEvent(bt->streams[i], bt->fork, 0));
+            for (int k = 0; k < bt->K; ++k) {
+                plans[i]->half_a();
+                plans[i]->half_b();
+            }
+            HIPCHECK(hipEventRecord(bt->joins[i], bt->streams[i]));
+            HIPCHECK(hipStreamWaitEvent(bt->main, bt->joins[i], 0));
+        }
+        HIPCHECK(launch_gather_flags(bt->main, nsys, bt->d_flag_ptrs, bt->d_flags));
+        HIPCHECK(hipStreamEndCapture(bt->main, &bt->graph));
+        HIPCHECK(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+        bt->graph_m = mv;
+    }
+    int maxit = 0;
+    for (auto c : bt->sys) maxit = std::max(maxit, c->o.maxit);
+    std::vector<int> status(nsys, MSP_OK);
+    HIPCHECK(launch_gather_flags(bt->main, nsys, bt->d_flag_ptrs, bt->d_flags));
+    HIPCHECK(hipMemcpyAsync(bt->h_flags, bt->d_flags, sizeof(int) * 2 * nsys, hipMemcpyDeviceToHost, bt->main));
+    HIPCHECK(hipStreamSynchronize(bt->main));
+    for (int it = 0; it < maxit; it += bt->K) {
+        bool any = false, broke = false;
+        for (int i = 0; i < nsys; ++i) {
+            any |= bt->h_flags[2 * i + 1] > 0;
+            broke |= bt->h_flags[2 * i] != 0;
+        }
+        if (!any || broke) break;
+        HIPCHECK(hipGraphLaunch(bt->exec, bt->main));
+        HIPCHECK(hipMemcpyAsync(bt->h_flags, bt->d_flags, sizeof(int) * 2 * nsys, hipMemcpyDeviceToHost, bt->main));
+        HIPCHECK(hipStreamSynchronize(bt->main));
+    }
+    HIPCHECK(hipEventRecord(bt->fork, bt->main));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = MSP_OK;
+    for (int i = 0; i < nsys; ++i) {
+        HIPCHECK(hipStreamWaitEvent(bt->streams[i], bt->fork, 0));
+        const int rc = plans[i]->finish(d_x[i], MSP_OK, secs, st ? &st[i] : nullptr);
+        if (rc < worst || (worst == MSP_OK && rc != MSP_OK)) worst = rc;
+    }
+    for (int i = 0; i < nsys; ++i) {
+        HIPCHECK(hipEventRecord(bt->joins[i], bt->streams[i]));
+        HIPCHECK(hipStreamWaitEvent(user, bt->joins[i], 0));
+    }
+    if (worst == MSP_ERR_BREAKDOWN) throw Error(MSP_ERR_BREAKDOWN, "PCG breakdown in a batched system");
+    return worst;
+}
+
+}  // namespace msp
+
 extern "C" {
 
 int msp_default_opts(msp_opts* o) {
@@ -706,37 +992,12 @@ int msp_default_opts(msp_opts* o) {
 
 int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ctx** out) {
     return guarded([&]() -> int {
-        if (!out || !o) throw Error(MSP_ERR_ARG, "null output or options");
+        if (!out) throw Error(MSP_ERR_ARG, "null output");
         *out = nullptr;
-        if (o->precision < MSP_FP64 || o->precision > MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_ARG, "precision");
-        if (o->pc < MSP_PC_AMGR || o->pc > MSP_PC_NONE) throw Error(MSP_ERR_ARG, "pc");
-        if (o->lrc_k < 0 || o->dist < 1 || o->jacobi0 < 1 || o->jacobi < 1 || o->coarse_max < 1 ||
-            o->max_levels < 1 || !(o->theta >= 0.0) || !(o->tol > 0.0) || o->maxit < 0)
-            throw Error(MSP_ERR_ARG, "invalid option value");
-        if (o->lrc_k > 0 && o->pc == MSP_PC_NONE) throw Error(MSP_ERR_ARG, "low-rank corrections need a preconditioner");
-        if (o->lrc_k > 16) throw Error(MSP_ERR_UNSUPPORTED, "low-rank correction rank above 16");
+        check_opts(o);
         const auto t0 = std::chrono::steady_clock::now();
-        std::unique_ptr<msp_ctx> c(new msp_ctx());
-        c->o = *o;
-        c->device = o->device;
-        c->lrc_k = o->lrc_k;
-        c->sym = msp::extract_blocks(A, map);
-        if (o->pc == MSP_PC_AMGR) {
-            c->hier = msp::build_hierarchy(c->sym.Ainn, c->sym.iface, *o);
-        } else {
-            c->hier.lev.emplace_back();
-            c->hier.lev.back().A = c->sym.Ainn;
-            if (o->pc == MSP_PC_FSAI) c->Gf = msp::fsai_full_lower(c->sym.Ainn);
-        }
-        msp::fill_stats(c.get());
-        if (o->device >= 0) {
-            int ndev = 0;
-            HIPCHECK(hipGetDeviceCount(&ndev));
-            if (o->device >= ndev) throw Error(MSP_ERR_ARG, "device ordinal out of range");
-            msp::upload_all(c.get());
-            if (c->lrc_k > 0) msp::build_lrc(c.get());
-            HIPCHECK(hipDeviceSynchronize());
-        }
+        std::unique_ptr<msp_ctx> c = setup_host(A, map, o);
+        if (o->device >= 0) setup_device(c.get());
         const auto t1 = std::chrono::steady_clock::now();
         c->stats.t_setup_s = std::chrono::duration<double>(t1 - t0).count();
         *out = c.release();
@@ -833,6 +1094,39 @@ int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz) {
     if (ritz) std::copy(c->lrc_ritz.begin(), c->lrc_ritz.end(), ritz);
     return MSP_OK;
 }
+
+int msp_batch_setup(int32_t nsys, const msp_csr* A, const msp_symmap* maps, const msp_opts* o, msp_batch** out) {
+    return guarded([&]() -> int {
+        if (out) *out = nullptr;
+        msp::batch_setup(nsys, A, maps, o, out);
+        return MSP_OK;
+    });
+}
+
+int msp_batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b, double* const* d_x, void* hip_stream,
+                    msp_stats* st) {
+    return guarded([&]() -> int {
+        if (!bt) throw Error(MSP_ERR_ARG, "null batch");
+        return msp::batch_solve(bt, m, d_b, d_x, static_cast<hipStream_t>(hip_stream), st);
+    });
+}
+
+int msp_batch_size(const msp_batch* bt, int32_t* nsys) {
+    if (!bt || !nsys) return MSP_ERR_ARG;
+    *nsys = static_cast<int32_t>(bt->sys.size());
+    return MSP_OK;
+}
+
+int msp_batch_set_chunk(msp_batch* bt, int32_t iterations) {
+    if (!bt || iterations < 1 || iterations > 64) return MSP_ERR_ARG;
+    if (bt->K != iterations) {
+        bt->K = iterations;
+        bt->graph_m.clear();
+    }
+    return MSP_OK;
+}
+
+void msp_batch_free(msp_batch* bt) { delete bt; }
 
 int msp_set_timing(msp_ctx* c, int32_t kind, int32_t on) {
     if (!c || kind < -1 || kind >= msp::KD_COUNT) return MSP_ERR_ARG;

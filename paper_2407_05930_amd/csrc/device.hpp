@@ -5,7 +5,21 @@
 
 #include <cstdint>
 
+#include "kernels.hpp"
+
 namespace msp {
+
+// matrix value -> arithmetic type
+template <typename T>
+__device__ __forceinline__ T cvt(T v) {
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T cvt(Bf16 v);
+template <>
+__device__ __forceinline__ float cvt<float>(Bf16 v) {
+    return __uint_as_float(static_cast<uint32_t>(v.bits) << 16);
+}
 
 constexpr int kBlock = 256;
 
@@ -35,14 +49,15 @@ struct Lanes {
 
 // acc[e] += sum over k = k0, k0+step, ... < k1 of va[k] * X[ci[k], lane*VW + e],
 // accumulated in that order with four entries' loads in flight at a time.
-template <typename T, int C, int VW>
+template <typename T, int C, int VW, typename TV = T>
 __device__ __forceinline__ void row_accumulate(int32_t k0, int32_t k1, int step, const int32_t* __restrict__ ci,
-                                               const T* __restrict__ va, const T* __restrict__ X, int lane,
+                                               const TV* __restrict__ va, const T* __restrict__ X, int lane,
                                                T* acc) {
     int32_t k = k0;
     for (; k + 3 * step < k1; k += 4 * step) {
         const int32_t c0 = ci[k], c1 = ci[k + step], c2 = ci[k + 2 * step], c3 = ci[k + 3 * step];
-        const T a0 = va[k], a1 = va[k + step], a2 = va[k + 2 * step], a3 = va[k + 3 * step];
+        const T a0 = cvt<T>(va[k]), a1 = cvt<T>(va[k + step]), a2 = cvt<T>(va[k + 2 * step]),
+                a3 = cvt<T>(va[k + 3 * step]);
         const Pack<T, VW> x0 = ld<T, VW>(X + (int64_t)c0 * C + lane * VW);
         const Pack<T, VW> x1 = ld<T, VW>(X + (int64_t)c1 * C + lane * VW);
         const Pack<T, VW> x2 = ld<T, VW>(X + (int64_t)c2 * C + lane * VW);
@@ -57,7 +72,7 @@ __device__ __forceinline__ void row_accumulate(int32_t k0, int32_t k1, int step,
     }
     for (; k < k1; k += step) {
         const Pack<T, VW> x = ld<T, VW>(X + (int64_t)ci[k] * C + lane * VW);
-        const T a = va[k];
+        const T a = cvt<T>(va[k]);
 #pragma unroll
         for (int e = 0; e < VW; ++e) acc[e] += a * x.e[e];
     }

@@ -20,10 +20,10 @@ namespace msp {
 // sigma[row * S + col / m] * X[row, col] (the per-subsystem outer diagonal of
 // eq. (2.11), one value per subsystem, broadcast over its m columns).
 // Y may alias Z (each lane reads its own Z elements before writing them).
-template <typename T, int C>
+template <typename T, typename TV, int C>
 __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ ci,
-                                                 const T* __restrict__ va, const T* __restrict__ X,
+                                                 const TV* __restrict__ va, const T* __restrict__ X,
                                                  T* Y, const T* Z, T alpha, T beta,
                                                  const double* __restrict__ sigma, int S, int m) {
     using L = Lanes<T, C>;
@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
     T acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = T(0);
-    row_accumulate<T, C, VW>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc);
+    row_accumulate<T, C, VW, TV>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc);
     if (sigma) {
         const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
 #pragma unroll
@@ -58,10 +58,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
 // Split-row SpMM for long rows (coarse levels): each row is shared by G lane
 // groups (G * LPR threads); group g accumulates entries k0 + g, k0 + g + G, ...
 // and the G partial rows are summed in LDS in a fixed order.
-template <typename T, int C, int G>
+template <typename T, typename TV, int C, int G>
 __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
-                                                       const T* __restrict__ va, const T* __restrict__ X,
+                                                       const TV* __restrict__ va, const T* __restrict__ X,
                                                        T* Y, const T* Z, T alpha, T beta) {
     using L = Lanes<T, C>;
     constexpr int VW = L::VW;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
     T acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = T(0);
-    if (row < n) row_accumulate<T, C, VW>(rp[row] + g, rp[row + 1], G, ci, va, X, lane, acc);
+    if (row < n) row_accumulate<T, C, VW, TV>(rp[row] + g, rp[row + 1], G, ci, va, X, lane, acc);
 #pragma unroll
     for (int e = 0; e < VW; ++e) sm[threadIdx.x * VW + e] = acc[e];
     __syncthreads();
@@ -532,6 +532,15 @@ __global__ __launch_bounds__(kBlock) void k_kappa_grad(int64_t n_b, int S, int64
     grad[i] = acc;
 }
 
+// out[2i], out[2i+1] = breakdown flag and active-column count of system i
+__global__ void k_gather_flags(int nsys, int* const* __restrict__ ptrs, int* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nsys) {
+        out[2 * i] = ptrs[i][0];
+        out[2 * i + 1] = ptrs[i][1];
+    }
+}
+
 // ------------------------------------------------------------------ host launchers
 
 
@@ -547,58 +556,58 @@ __global__ __launch_bounds__(kBlock) void k_kappa_grad(int64_t n_b, int S, int64
         default: return hipErrorInvalidValue;                    \
     }
 
-template <typename T>
-hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const T* va,
+template <typename T, typename TV>
+hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
                        const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m) {
     if (n <= 0) return hipSuccess;
     MSP_DISPATCH_C(C, {
         using L = Lanes<T, CC>;
-        hipLaunchKernelGGL((k_spmm<T, CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp, ci, va, X, Y,
-                           Z, alpha, beta, sigma, S, m);
+        hipLaunchKernelGGL((k_spmm<T, TV, CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp, ci, va, X,
+                           Y, Z, alpha, beta, sigma, S, m);
     });
     return hipGetLastError();
 }
-template <typename T, int CC, int G>
-static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const T* va, const T* X,
+
+template <typename T, typename TV, int CC, int G>
+static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va, const T* X,
                          T* Y, const T* Z, T alpha, T beta) {
     constexpr int TPR = G * Lanes<T, CC>::LPR;
     if constexpr (TPR <= kBlock) {
         constexpr int RPB = kBlock / TPR;
-        hipLaunchKernelGGL((k_spmm_split<T, CC, G>), dim3(blocks_for(n, RPB)), dim3(kBlock), 0, st, n, rp, ci, va,
-                           X, Y, Z, alpha, beta);
+        hipLaunchKernelGGL((k_spmm_split<T, TV, CC, G>), dim3(blocks_for(n, RPB)), dim3(kBlock), 0, st, n, rp, ci,
+                           va, X, Y, Z, alpha, beta);
     }
 }
 
-template <typename T>
+template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
-                             const T* va, const T* X, T* Y, const T* Z, T alpha, T beta) {
+                             const TV* va, const T* X, T* Y, const T* Z, T alpha, T beta) {
     if (n <= 0) return hipSuccess;
     MSP_DISPATCH_C(C, {
         constexpr int LPR = Lanes<T, CC>::LPR;
         const int gmax = kBlock / LPR;
         const int g = G < gmax ? G : gmax;
         switch (g) {
-            case 2: launch_split<T, CC, 2>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 4: launch_split<T, CC, 4>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 8: launch_split<T, CC, 8>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 16: launch_split<T, CC, 16>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 32: launch_split<T, CC, 32>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 64: launch_split<T, CC, 64>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            default: launch_split<T, CC, 1>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 2: launch_split<T, TV, CC, 2>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 4: launch_split<T, TV, CC, 4>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 8: launch_split<T, TV, CC, 8>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 16: launch_split<T, TV, CC, 16>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 32: launch_split<T, TV, CC, 32>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 64: launch_split<T, TV, CC, 64>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            default: launch_split<T, TV, CC, 1>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
         }
     });
     return hipGetLastError();
 }
-template hipError_t launch_spmm_split<double>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,
-                                              const double*, const double*, double*, const double*, double, double);
-template hipError_t launch_spmm_split<float>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,
-                                             const float*, const float*, float*, const float*, float, float);
 
-template hipError_t launch_spmm<double>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const double*,
-                                        const double*, double*, const double*, double, double, const double*, int,
-                                        int);
-template hipError_t launch_spmm<float>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const float*,
-                                       const float*, float*, const float*, float, float, const double*, int, int);
+#define MSP_SPMM_INST(T, TV)                                                                                         \
+    template hipError_t launch_spmm<T, TV>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const TV*,     \
+                                           const T*, T*, const T*, T, T, const double*, int, int);                   \
+    template hipError_t launch_spmm_split<T, TV>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,     \
+                                                 const TV*, const T*, T*, const T*, T, T);
+MSP_SPMM_INST(double, double)
+MSP_SPMM_INST(float, float)
+MSP_SPMM_INST(float, Bf16)
 
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
@@ -713,6 +722,12 @@ hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {
 }
 template hipError_t launch_fill<double>(hipStream_t, int64_t, double*, double);
 template hipError_t launch_fill<float>(hipStream_t, int64_t, float*, float);
+template hipError_t launch_fill<int>(hipStream_t, int64_t, int*, int);
+
+hipError_t launch_gather_flags(hipStream_t st, int nsys, int* const* ptrs, int* out) {
+    hipLaunchKernelGGL(k_gather_flags, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, ptrs, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_kappa_grad(hipStream_t st, int64_t n_b, int S, int64_t n, int m, const int64_t* cfp,
                             const int32_t* cfi, const int64_t* img, const int64_t* ca, const int64_t* cb,

@@ -8,13 +8,20 @@
 
 namespace msp {
 
-template <typename T>
-hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const T* va,
+// bfloat16 storage (upper 16 bits of an IEEE binary32), used for matrix values
+struct Bf16 {
+    uint16_t bits;
+};
+
+// Y = alpha (A X [+ outer diagonal]) + beta Z with matrix values of type TV
+// (TV = T, or Bf16 with T = float) and multivectors of type T.
+template <typename T, typename TV>
+hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
                        const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m);
 // Same product for long rows: G lane groups share each row (G a power of two).
-template <typename T>
+template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
-                             const T* va, const T* X, T* Y, const T* Z, T alpha, T beta);
+                             const TV* va, const T* X, T* Y, const T* Z, T alpha, T beta);
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
                       double* out);
@@ -47,6 +54,9 @@ template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v);
 template <typename TO, typename TI>
 hipError_t launch_cast(hipStream_t st, int64_t len, const TI* a, TO* b);
+
+// flags of every system of a batch into one array (2 ints per system)
+hipError_t launch_gather_flags(hipStream_t st, int nsys, int* const* ptrs, int* out);
 
 // dL/dkappa per base cell from face products (see msp_fv_kappa_grad)
 hipError_t launch_kappa_grad(hipStream_t st, int64_t n_b, int S, int64_t n, int m, const int64_t* cfp,

@@ -190,3 +190,70 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class BatchSolver:
+    """Many independent systems solved together (one captured HIP graph per
+    chunk of iterations).  ``systems`` is a list of (A, img) pairs; options as
+    for Solver (shared by all systems)."""
+
+    def __init__(self, systems, **opts):
+        self.n = []
+        self._keep = []
+        csrs = (_lib.msp_csr * len(systems))()
+        maps = (_lib.msp_symmap * len(systems))()
+        for i, (A, img) in enumerate(systems):
+            img = np.ascontiguousarray(img, dtype=np.int64)
+            n_b, S = img.shape
+            s = S.bit_length() - 1
+            indptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+            indices = np.ascontiguousarray(A.indices, dtype=np.int32)
+            data = np.ascontiguousarray(A.data, dtype=np.float64)
+            self._keep.append((img, indptr, indices, data))
+            n = indptr.size - 1
+            self.n.append(n)
+            csrs[i] = _lib.msp_csr(n, _ptr(indptr, ctypes.c_int64), _ptr(indices, ctypes.c_int32),
+                                   _ptr(data, ctypes.c_double))
+            maps[i] = _lib.msp_symmap(s, n_b, _ptr(img, ctypes.c_int64))
+        self.opts = make_opts(**opts)
+        self._h = ctypes.c_void_p()
+        check(lib.msp_batch_setup(len(systems), csrs, maps, ctypes.byref(self.opts), ctypes.byref(self._h)))
+        self._keep = None
+        self.stats = (_lib.msp_stats * len(systems))()
+
+    def set_chunk(self, iterations: int):
+        check(lib.msp_batch_set_chunk(self._h, iterations))
+
+    def solve(self, bs, stream=None):
+        """bs: list of float64 CUDA tensors (n_i,) or (n_i, m_i).  Returns the
+        list of solutions with the same shapes."""
+        import torch
+        k = len(bs)
+        ms = (ctypes.c_int32 * k)()
+        pb = (ctypes.c_void_p * k)()
+        px = (ctypes.c_void_p * k)()
+        bts, xts, shapes = [], [], []
+        for i, b in enumerate(bs):
+            shapes.append(b.dim() == 1)
+            B = b.reshape(self.n[i], -1)
+            bt = B.t().contiguous()
+            xt = torch.empty_like(bt)
+            bts.append(bt)
+            xts.append(xt)
+            ms[i] = bt.shape[0]
+            pb[i] = bt.data_ptr()
+            px[i] = xt.data_ptr()
+        st = stream if stream is not None else torch.cuda.current_stream(bs[0].device)
+        self.status = check(lib.msp_batch_solve(self._h, ms, pb, px, ctypes.c_void_p(st.cuda_stream), self.stats))
+        return [x.t().reshape(-1) if vec else x.t().contiguous() for x, vec in zip(xts, shapes)]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib.msp_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -160,3 +160,45 @@ def test_lrc_mixed_precision_reaches_tolerance():
     rr = krylov.true_relres(p.A, x, p.b)
     _say("mixed lrc its", sv.last.iters, rr)
     assert np.all(rr <= 1.5e-10)
+
+
+def test_bf16_smoother_variant_reaches_tolerance():
+    """FP32 V-cycle with the smoother values stored in bfloat16: the flexible
+    outer PCG still reaches 1e-10; error against the oracle is stated."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    p = make_problem((24, 24, 24), s=3, m=1, seed=4, jitter=0.2, kappa="lognormal")
+    ctx = krylov.setup(p.A, p.img, amg.AMGOptions(coarse_max=64))
+    ref = krylov.solve(ctx, p.b, tol=1e-12)
+    sv = Solver(p.A, p.img, tol=1e-10, precision="mixed_bf16g", k=16, coarse_max=64)
+    x = sv.solve(torch.from_numpy(p.b).cuda()).cpu().numpy()
+    rr = krylov.true_relres(p.A, x, p.b)
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    _say("bf16 its", sv.last.iters, "relres", rr, "err", err)
+    assert np.all(rr <= 1.5e-10)
+    assert err <= 1e-7
+
+
+def test_batched_graph_solve_matches_single_solves():
+    """Uneven systems (sizes, s, m) solved in one batch with captured graph
+    chunks: every system reaches tolerance and matches its own single solve."""
+    torch = _torch()
+    from paper_2407_05930_amd import BatchSolver, Solver
+    probs = [make_problem((N, N, N), s=s, m=m, seed=30 + i) for i, (N, s, m) in
+             enumerate([(16, 1, 3), (24, 3, 2), (20, 2, 1), (12, 3, 8), (18, 1, 5)])]
+    opts = dict(tol=1e-10, precision="mixed", coarse_max=48)
+    bs = BatchSolver([(p.A, p.img) for p in probs], **opts)
+    bs.set_chunk(3)
+    xs = bs.solve([torch.from_numpy(p.b).cuda() for p in probs])
+    for i, (p, x) in enumerate(zip(probs, xs)):
+        xh = x.cpu().numpy()
+        rr = krylov.true_relres(p.A, xh, p.b)
+        assert np.all(rr <= 1.5e-10), (i, rr)
+        sv = Solver(p.A, p.img, **opts)
+        x1 = sv.solve(torch.from_numpy(p.b).cuda()).cpu().numpy()
+        assert np.linalg.norm(xh - x1) <= 1e-12 * np.linalg.norm(x1), i
+        assert bs.stats[i].iters == sv.last.iters
+    # a second call reuses the captured graph
+    xs2 = bs.solve([torch.from_numpy(p.b).cuda() for p in probs])
+    for x, x2 in zip(xs, xs2):
+        assert torch.equal(x, x2)
