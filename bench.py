@@ -104,6 +104,100 @@ def cpu_baseline(problem, iters_gpu, k):
                 setup_s=round(t_setup, 2), s_per_iteration=round(per_it, 3))
 
 
+def bench_jitter(args, torch, np):
+    """192^3 jittered octant, lognormal kappa, s = 3, k = 16: FP64 vs mixed
+    (FP32 V-cycle) vs mixed with bfloat16 smoother values."""
+    from gen import config_problem
+    from paper_2407_05930_amd import Solver
+    log("building workload jitter3d_192_s3")
+    p = config_problem("jitter3d_192_s3")
+    b = torch.from_numpy(p.b).cuda()
+    out = {}
+    for prec in ("fp64", "mixed", "mixed_bf16g"):
+        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=args.k)
+        t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
+        xs = x.cpu().numpy()
+        rr = float(np.max(np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)))
+        out[prec] = dict(solve_s=round(t, 6), iters=sv.last.iters, true_relres=rr, setup_s=round(sv.stats.t_setup_s, 3))
+        if prec == "fp64":
+            x64 = xs
+        else:
+            out[prec]["rel_diff_vs_fp64"] = float(np.linalg.norm(xs - x64) / np.linalg.norm(x64))
+        log(f"  {prec}: {t * 1e3:.2f} ms, {sv.last.iters} its, relres {rr:.2e}")
+        sv.close()
+    return {"metric": "solve time to 1e-10 rel-res, 192^3 jittered s=3, k=16", "value": out["mixed_bf16g"]["solve_s"],
+            "unit": "s", "higher_is_better": False, "dtype": "f64+f32+bf16",
+            "config": {"workload": "jitter3d_192_s3", "grid": list(p.N), "s": 3, "rhs": 1, "lrc_k": args.k,
+                       "unknowns": int(p.n)}, "variants": out}
+
+
+def bench_batch(args, torch, np):
+    """64 uneven cubic Dirichlet systems (N in even 32..96, s in 1..3, m in
+    1..8) solved by one batch: graph chunks of iterations over all systems."""
+    from gen import batch_problems
+    from paper_2407_05930_amd import BatchSolver
+    log("building 64 systems")
+    probs = batch_problems(64)
+    bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
+    t0 = time.perf_counter()
+    bsol = BatchSolver([(pr.A, pr.img) for pr in probs], tol=1e-10, precision="mixed")
+    t_setup = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        bsol.solve(bs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        xs = bsol.solve(bs)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    worst = 0.0
+    for pr, x in zip(probs, xs):
+        xh = x.cpu().numpy()
+        worst = max(worst, float(np.max(np.linalg.norm(pr.b - pr.A @ xh, axis=0) / np.linalg.norm(pr.b, axis=0))))
+    its = [bsol.stats[i].iters for i in range(len(probs))]
+    unk = sum(pr.n * pr.b.shape[1] for pr in probs)
+    return {"metric": "batched solve time to 1e-10 rel-res, 64 uneven systems", "value": round(t, 6), "unit": "s",
+            "higher_is_better": False, "dtype": "f64+f32",
+            "config": {"workload": "batch64", "systems": len(probs), "unknowns": int(sum(pr.n for pr in probs)),
+                       "rhs_total": int(sum(pr.b.shape[1] for pr in probs))},
+            "iters_min_max": [min(its), max(its)], "true_relres_max": worst, "setup_s": round(t_setup, 2),
+            "unknown_rhs_per_s": round(unk / t, 1)}
+
+
+def bench_adjoint(args, torch, np):
+    """256^3, s = 3, lognormal kappa: forward solve and adjoint (dL/df,
+    dL/dkappa) through torch.autograd, FP64."""
+    from gen import config_problem
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    log("building workload adjoint3d_256_s3 (geometry only)")
+    pr = config_problem("adjoint3d_256_s3", assemble=False)
+    t0 = time.perf_counter()
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-10)
+    f = torch.from_numpy(pr.b).cuda()
+    pst = torch.from_numpy(pr.p_target[:, None]).cuda()
+    kap = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
+    dp.solver_for(kap)
+    t_setup = time.perf_counter() - t0
+    times = []
+    for it in range(args.warmup + args.steps):
+        kap.grad = None
+        fr = f.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = dp(fr, kap)
+        loss = 0.5 * ((p - pst) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            times.append(time.perf_counter() - t0)
+    t = sum(times) / len(times)
+    return {"metric": "forward + adjoint solve time, 256^3 s=3 lognormal kappa", "value": round(t, 6), "unit": "s",
+            "higher_is_better": False, "dtype": "f64",
+            "config": {"workload": "adjoint3d_256_s3", "grid": list(pr.N), "s": 3, "unknowns": int(pr.n)},
+            "iters": dp.solver.last.iters, "setup_s": round(t_setup, 2), "loss": float(loss.item()),
+            "grad_kappa_norm": float(kap.grad.norm().item()), "grad_f_norm": float(fr.grad.norm().item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +221,12 @@ def main():
     from paper_2407_05930_amd import Solver
 
     rank = int(os.environ.get("RANK", "0"))
+    other = {"jitter3d_192_s3": bench_jitter, "batch64": bench_batch, "adjoint3d_256_s3": bench_adjoint}
+    if args.workload in other:
+        res = other[args.workload](args, torch, np)
+        res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "vs_baseline": None})
+        print(json.dumps(res), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -317,7 +317,7 @@ def assemble_full(H: dict, n_b: int, s: int) -> sp.csr_matrix:
 def make_problem(N: Sequence[int], s: int, m: int = 1, seed: int = 0,
                  y_stretch: Optional[float] = None, jitter: Optional[float] = None,
                  kappa: str = "one", ordering: str = "natural",
-                 with_target: bool = False) -> Problem:
+                 with_target: bool = False, assemble: bool = True) -> Problem:
     """Build one seeded problem.
 
     N          cells per axis (2 or 3 axes)
@@ -329,6 +329,8 @@ def make_problem(N: Sequence[int], s: int, m: int = 1, seed: int = 0,
                base mesh, mirrored; or None
     kappa      "one" or "lognormal" (lognormal(0,1) per base cell, mirrored)
     ordering   "natural" (lexicographic full grid) or "mirrored" (block order)
+    assemble   False skips the full matrix (A = None): geometry, map and
+               right-hand sides only
     """
     N = tuple(int(v) for v in N)
     D = len(N)
@@ -349,23 +351,26 @@ def make_problem(N: Sequence[int], s: int, m: int = 1, seed: int = 0,
         kb = rng.lognormal(0.0, 1.0, size=n_b)
     else:
         raise ValueError(kappa)
-    T = transmissibility(faces, kb)
-    H = base_blocks(faces, T, n_b, s)
-    A_mir = assemble_full(H, n_b, s)
+    if assemble:
+        T = transmissibility(faces, kb)
+        H = base_blocks(faces, T, n_b, s)
+        A_mir = assemble_full(H, n_b, s)
     nat = _natural_index(N, s, B, n_b)          # (S, n_b)
     nat_of_mir = nat.reshape(-1)                # mirrored row -> natural index
     b_nat = rng.uniform(-1.0, 1.0, size=(m, n)).T.copy()   # natural order, column by column
     p_nat = rng.standard_normal(n) if with_target else None
     if ordering == "mirrored":
-        A = A_mir
+        A = A_mir if assemble else None
         img = (np.arange(S)[None, :] * n_b + np.arange(n_b)[:, None]).astype(np.int64)
         b = b_nat[nat_of_mir]
         p_t = p_nat[nat_of_mir] if p_nat is not None else None
         nat_of_global = nat_of_mir
     elif ordering == "natural":
-        perm = sp.csr_matrix((np.ones(n), (nat_of_mir, np.arange(n))), shape=(n, n))
-        A = (perm @ A_mir @ perm.T).tocsr()
-        A.sort_indices()
+        A = None
+        if assemble:
+            perm = sp.csr_matrix((np.ones(n), (nat_of_mir, np.arange(n))), shape=(n, n))
+            A = (perm @ A_mir @ perm.T).tocsr()
+            A.sort_indices()
         img = nat.T.copy().astype(np.int64)
         b = b_nat
         p_t = p_nat
@@ -383,7 +388,8 @@ def make_problem(N: Sequence[int], s: int, m: int = 1, seed: int = 0,
 CONFIG_SEED0 = 240705930
 
 
-def config_problem(name: str, scale: Optional[int] = None, ordering: str = "natural") -> Problem:
+def config_problem(name: str, scale: Optional[int] = None, ordering: str = "natural",
+                   assemble: bool = True) -> Problem:
     """Named workloads.  ``scale`` overrides the cell count per axis (for
     small parity instances of the same recipe)."""
     if name == "poisson2d_128_s1":
@@ -396,11 +402,11 @@ def config_problem(name: str, scale: Optional[int] = None, ordering: str = "natu
     if name == "jitter3d_192_s3":
         N = scale or 192
         return make_problem((N, N, N), s=3, m=1, seed=CONFIG_SEED0 + 2, jitter=0.2,
-                            kappa="lognormal", ordering=ordering)
+                            kappa="lognormal", ordering=ordering, assemble=assemble)
     if name == "adjoint3d_256_s3":
         N = scale or 256
         return make_problem((N, N, N), s=3, m=1, seed=CONFIG_SEED0 + 4, kappa="lognormal",
-                            ordering=ordering, with_target=True)
+                            ordering=ordering, with_target=True, assemble=assemble)
     raise KeyError(name)
 
 
