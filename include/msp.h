@@ -56,6 +56,10 @@ typedef enum {
     MSP_ERR_UNSUPPORTED = -8     /* input outside what this build handles */
 } msp_status;
 
+/* MSP_MIXED_FP32: FP32 V-cycle (smoother M = omega G^T G formed explicitly),
+   FP64 outer PCG, dots and coarsest solve.  MSP_MIXED_FP32_BF16G: as
+   MSP_MIXED_FP32 but the FSAI factors G, G^T are stored in bfloat16 and the
+   smoother is applied factored, G^T (G r), which keeps it SPD. */
 enum { MSP_FP64 = 0, MSP_MIXED_FP32 = 1, MSP_MIXED_FP32_BF16G = 2 };
 enum { MSP_PC_AMGR = 0, MSP_PC_FSAI = 1, MSP_PC_NONE = 2 };
 
@@ -156,8 +160,9 @@ int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz);
      2 x/r update, 3 p update, 4 Q_s butterflies, 5 precision casts,
      6 dense coarsest solve, 7 FSAI preconditioner products,
      8 low-rank corrections,
-     16 + 8*l + {0: A_l, 1: M_l = omega_l G_l^T G_l, 3: R_l = P_l^T, 4: P_l}
-     (V-cycle level l).
+     16 + 8*l + {0: A_l, 1: M_l = omega_l G_l^T G_l (or G_l in the BF16
+     variant, where the smoother stays factored), 2: G_l^T (BF16 variant),
+     3: R_l = P_l^T, 4: P_l} (V-cycle level l).
    While a kind is on, each of its launches is bracketed by HIP events on
    the solve's stream; totals are folded in when the solve returns.
    msp_set_timing(c, -1, on) switches every kind.  total_bytes sums the

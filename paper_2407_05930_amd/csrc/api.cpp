@@ -43,6 +43,7 @@ struct DevCsr {
 
 struct DevLevel {
     DevCsr A, P, R, M;
+    DevCsr G, GT;             // bfloat16 FSAI factors (BF16 variant only)
     double omega = 0.0;
     int64_t n = 0;
 };
@@ -52,7 +53,7 @@ struct Work {
     int C = 0;
     int m = 1;                // columns per subsystem of the current solve
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *zold = nullptr;
-    std::vector<void*> vy, vs, vr;        // per level, element type of the V-cycle
+    std::vector<void*> vy, vs, vr, vt;    // per level, element type of the V-cycle (vt: factored smoother)
     double* partial = nullptr;
     int nb_dot = 0;
     // partials of the fused PCG kernels: two column sets and the low-rank projections
@@ -322,9 +323,11 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
         struct Job { DevCsr* M; const T* X; T* Y; };
         T* vs = static_cast<T*>(w.vs[l]);
         T* vr = static_cast<T*>(w.vr[l]);
-        Job jobs[4] = {{&L.A, vs, vr}, {&L.M, vr, vs}, {&L.R, vr, static_cast<T*>(w.vy[l + 1])},
-                       {&L.P, static_cast<T*>(w.vs[l + 1]), vs}};
+        T* vt = w.vt[l] ? static_cast<T*>(w.vt[l]) : vr;
+        Job jobs[6] = {{&L.A, vs, vr}, {&L.M, vr, vs}, {&L.R, vr, static_cast<T*>(w.vy[l + 1])},
+                       {&L.P, static_cast<T*>(w.vs[l + 1]), vs}, {&L.G, vr, vt}, {&L.GT, vt, vs}};
         for (Job& jb : jobs) {
+            if (jb.M->nnz == 0) continue;
             const double avg = jb.M->nr ? static_cast<double>(jb.M->nnz) / static_cast<double>(jb.M->nr) : 0.0;
             int best = 1;
             float best_ms = 1e30f;
@@ -371,12 +374,15 @@ static Work& work(msp_ctx* c, int C) {
     w.vy.assign(L, nullptr);
     w.vs.assign(L, nullptr);
     w.vr.assign(L, nullptr);
+    w.vt.assign(L, nullptr);
     if (c->o.pc == MSP_PC_AMGR) {
         for (size_t l = 0; l < L; ++l) {
             const int64_t n = c->hier.lev[l].A.nr;
             w.vy[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
             w.vs[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
             w.vr[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
+            if (c->o.precision == MSP_MIXED_FP32_BF16G)
+                w.vt[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
         }
     }
     w.nb_dot = 512;
@@ -412,13 +418,23 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     T* yc = static_cast<T*>(w.vy[l + 1]);
     T* sc = static_cast<T*>(w.vs[l + 1]);
     const int kb = KD_LEVEL + 8 * static_cast<int>(l);
-    spmm<T>(c, kb + 1, st, C, L.M, y, s, nullptr, T(1), T(0));     // pre-smooth from zero: s = M y, M = w G^T G
+    // smoother s = beta s + M v with M = w G^T G (explicit, or factored with a temporary)
+    auto smooth = [&](const T* v, T beta) {
+        if (L.G.nnz) {
+            T* t = static_cast<T*>(w.vt[l]);
+            spmm<T>(c, kb + 1, st, C, L.G, v, t, nullptr, T(1), T(0));
+            spmm<T>(c, kb + 2, st, C, L.GT, t, s, beta != T(0) ? s : nullptr, static_cast<T>(L.omega), beta);
+        } else {
+            spmm<T>(c, kb + 1, st, C, L.M, v, s, beta != T(0) ? s : nullptr, T(1), beta);
+        }
+    };
+    smooth(y, T(0));                                               // pre-smooth from zero: s = M y
     spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // r = y - A s
     spmm<T>(c, kb + 3, st, C, L.R, r, yc, nullptr, T(1), T(0));    // r_c = P^T r
     vcycle<T>(c, w, st, l + 1, yc, sc);                            // coarse correction
     spmm<T>(c, kb + 4, st, C, L.P, sc, s, s, T(1), T(1));          // s += P h_c
     spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // post-smooth: s += M (y - A s)
-    spmm<T>(c, kb + 1, st, C, L.M, r, s, s, T(1), T(1));
+    smooth(r, T(1));
 }
 
 // out[c] = <X_c, Y_c> for the C columns of two n_b x C multivectors.
@@ -497,7 +513,13 @@ static void upload_all(msp_ctx* c) {
             D.A = upload_csr(c, H.A, f32);
             D.P = upload_csr(c, H.P, f32);
             D.R = upload_csr(c, H.R, f32);
-            D.M = upload_csr(c, H.M, f32, c->o.precision == MSP_MIXED_FP32_BF16G);
+            if (c->o.precision == MSP_MIXED_FP32_BF16G) {
+                // the smoother is kept factored, G^T (G r) with bfloat16 factors, so it stays SPD
+                D.G = upload_csr(c, H.G, true, true);
+                D.GT = upload_csr(c, H.GT, true, true);
+            } else {
+                D.M = upload_csr(c, H.M, f32);
+            }
             D.omega = H.omega;
         }
         c->nL = c->hier.lev.back().A.nr;

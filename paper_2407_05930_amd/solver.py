@@ -162,7 +162,7 @@ class Solver:
         if kind < 16:
             return Solver.KIND_NAMES.get(kind, f"kind{kind}")
         lev, op = divmod(kind - 16, 8)
-        return f"L{lev}.{['A', 'M', '?', 'R', 'P', '?', '?', '?'][op]}"
+        return f"L{lev}.{['A', 'M', 'GT', 'R', 'P', '?', '?', '?'][op]}"
 
     def set_timing(self, on: bool = True, kind: int = -1):
         check(lib.msp_set_timing(self._ctx, kind, 1 if on else 0))

@@ -167,7 +167,7 @@ def test_bf16_smoother_variant_reaches_tolerance():
     outer PCG still reaches 1e-10; error against the oracle is stated."""
     torch = _torch()
     from paper_2407_05930_amd import Solver
-    p = make_problem((24, 24, 24), s=3, m=1, seed=4, jitter=0.2, kappa="lognormal")
+    p = make_problem((48, 48, 48), s=3, m=1, seed=4, jitter=0.2, kappa="lognormal")
     ctx = krylov.setup(p.A, p.img, amg.AMGOptions(coarse_max=64))
     ref = krylov.solve(ctx, p.b, tol=1e-12)
     sv = Solver(p.A, p.img, tol=1e-10, precision="mixed_bf16g", k=16, coarse_max=64)
