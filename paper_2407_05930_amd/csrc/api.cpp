@@ -177,6 +177,15 @@ static Bf16 to_bf16(float f) {
     return Bf16{static_cast<uint16_t>(r >> 16)};
 }
 
+// value of a double after rounding to FP32 then to bfloat16
+static double bf16_value(double v) {
+    const Bf16 h = to_bf16(static_cast<float>(v));
+    const uint32_t u = static_cast<uint32_t>(h.bits) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
 static DevCsr upload_csr(msp_ctx* c, const Csr& M, bool fp32, bool bf16 = false) {
     DevCsr D;
     D.nr = M.nr;
@@ -510,17 +519,23 @@ static void upload_all(msp_ctx* c) {
             const HostLevel& H = c->hier.lev[l];
             DevLevel& D = c->dl[l];
             D.n = H.A.nr;
+            D.omega = H.omega;
             D.A = upload_csr(c, H.A, f32);
             D.P = upload_csr(c, H.P, f32);
             D.R = upload_csr(c, H.R, f32);
             if (c->o.precision == MSP_MIXED_FP32_BF16G) {
-                // the smoother is kept factored, G^T (G r) with bfloat16 factors, so it stays SPD
+                // the smoother is kept factored, G^T (G r) with bfloat16 factors, so it stays SPD;
+                // its damping is recomputed for the rounded factors (rounding can raise
+                // lambda_max(G A G^T) where large terms cancel)
                 D.G = upload_csr(c, H.G, true, true);
                 D.GT = upload_csr(c, H.GT, true, true);
+                Csr Gr = H.G, GTr = H.GT;
+                for (double& v : Gr.v) v = bf16_value(v);
+                for (double& v : GTr.v) v = bf16_value(v);
+                D.omega = damping(H.A, Gr, GTr, c->o.seed);
             } else {
                 D.M = upload_csr(c, H.M, f32);
             }
-            D.omega = H.omega;
         }
         c->nL = c->hier.lev.back().A.nr;
         c->d_cinv = c->upload(c->hier.coarse_inv.data(), static_cast<int64_t>(c->hier.coarse_inv.size()));

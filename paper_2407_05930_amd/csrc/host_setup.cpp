@@ -497,7 +497,7 @@ Csr fsai_full_lower(const Csr& A) {
 
 // omega = 4 / (3 lam), lam = v^T G A G^T v after 20 power iterations from
 // v_i = splitmix64(seed xor i)/2^64 - 1/2 (normalised).
-static double damping(const Csr& A, const Csr& G, const Csr& GT, uint64_t seed) {
+double damping(const Csr& A, const Csr& G, const Csr& GT, uint64_t seed) {
     const int64_t n = A.nr;
     std::vector<double> v(n), t1(n), t2(n), w(n);
     double nrm = 0.0;

@@ -56,6 +56,8 @@ struct SymParts {
 
 SymParts extract_blocks(const msp_csr* A, const msp_symmap* map);
 HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o);
+// omega = 4/(3 lam), lam from 20 power iterations on G A G^T (seeded start).
+double damping(const Csr& A, const Csr& G, const Csr& GT, uint64_t seed);
 // Static FSAI on the full lower pattern of A (the stand-alone FSAI of A_inn).
 Csr fsai_full_lower(const Csr& A);
 
