@@ -396,7 +396,7 @@ class AMGOptions:
     dist: int = 2
     jacobi0: int = 2          # interpolation steps at the reduction level
     jacobi: int = 1           # interpolation steps below it
-    coarse_max: int = 1024
+    coarse_max: int = 2560
     max_levels: int = 20
     max_ratio: float = 0.8
     seed: int = 240705930

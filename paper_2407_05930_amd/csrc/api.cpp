@@ -598,20 +598,26 @@ struct SolvePlan {
 
     double vb() const { return 8.0 * nb * C; }   // bytes of one FP64 multivector pass
 
+    // the mixed AMGR mode writes the FP32 V-cycle input in the update kernel
+    float* y32() const {
+        return (c->o.pc == MSP_PC_AMGR && mixed(c)) ? static_cast<float*>(w->vy[0]) : nullptr;
+    }
+
     // <r,r>, U^T r and the convergence check (initial: the active flags)
     void update_dots(bool upd) {
         Work& W = *w;
         const double wu = c->U32 ? 4.0 : 8.0;
-        const double bytes = (upd ? 6.0 : 1.0) * vb() + (flexible && upd ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0);
+        const double bytes = (upd ? 6.0 : 1.0) * vb() + (flexible && upd ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0) +
+                             (y32() ? 4.0 * nb * C : 0.0);
         timed(c, KD_UPDATE, bytes, st, [&] {
             if (c->U32 || !c->d_U)
                 HIPCHECK(launch_update_dots<float>(st, C, nbp, upd, flexible && upd, kl, nb, W.x, W.r, W.p, W.q, alpha,
                                                    W.z, static_cast<const float*>(c->d_U), S, m, W.pp1, W.pp2,
-                                                   W.plrc));
+                                                   W.plrc, y32()));
             else
                 HIPCHECK(launch_update_dots<double>(st, C, nbp, upd, flexible && upd, kl, nb, W.x, W.r, W.p, W.q,
                                                     alpha, W.z, static_cast<const double*>(c->d_U), S, m, W.pp1,
-                                                    W.pp2, W.plrc));
+                                                    W.pp2, W.plrc, y32()));
         });
         HIPCHECK(launch_fin_check(st, C, nbp, !upd, flexible && upd, O, m, W.pp1, W.pp2, W.plrc, thr, c->d_lrc_coef,
                                   active, iters, flags, rnorm, rzold, c->d_lrc_W));
@@ -622,10 +628,8 @@ struct SolvePlan {
         Work& W = *w;
         const float* s32 = nullptr;
         if (c->o.pc == MSP_PC_AMGR && mixed(c)) {
-            float* y0 = static_cast<float*>(W.vy[0]);
+            float* y0 = static_cast<float*>(W.vy[0]);   // written by the update kernel
             float* s0 = static_cast<float*>(W.vs[0]);
-            timed(c, KD_CAST, 12.0 * nb * C, st,
-                  [&] { HIPCHECK((launch_cast<float, double>(st, nb * C, W.r, y0))); });
             vcycle<float>(c, W, st, 0, y0, s0);
             s32 = s0;
         } else {
@@ -1017,7 +1021,7 @@ int msp_default_opts(msp_opts* o) {
     o->theta = 0.25;
     o->jacobi0 = 2;
     o->jacobi = 1;
-    o->coarse_max = 1024;
+    o->coarse_max = 2560;
     o->max_levels = 20;
     o->max_ratio = 0.8;
     o->tol = 1e-10;

@@ -78,6 +78,17 @@ __device__ __forceinline__ void row_accumulate(int32_t k0, int32_t k1, int step,
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Remap so that every XCD works on one contiguous range of logical
+// tiles: neighbouring rows, and the multivector rows they gather, then stay
+// in the same XCD's L2.  A bijection of [0, nb).
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
+    constexpr unsigned X = 8;
+    const unsigned q = nb / X, r = nb % X;
+    const unsigned x = b % X, i = b / X;
+    return x * q + (x < r ? x : r) + i;
+}
+
 static inline unsigned blocks_for(int64_t work, int per_block) {
     return (unsigned)((work + per_block - 1) / per_block);
 }

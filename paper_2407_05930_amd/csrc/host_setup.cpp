@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <utility>
 
 #include "internal.hpp"
@@ -649,29 +650,48 @@ HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface,
         A = std::move(Ac);
         ++lev;
     }
-    // dense inverse of the coarsest operator
+    // dense inverse of the coarsest operator: Cholesky A = L L^T, then
+    // Linv = L^{-1} column by column and A^{-1} = Linv^T Linv (threads over columns)
     const HostLevel& Lc = H.lev.back();
     const int64_t nc = Lc.A.nr;
-    if (nc > 16384) throw Error(MSP_ERR_UNSUPPORTED, "coarsest level too large for a dense solve");
+    if (nc > 8192) throw Error(MSP_ERR_UNSUPPORTED, "coarsest level too large for a dense solve");
     std::vector<double> M(nc * nc, 0.0);
     for (int64_t i = 0; i < nc; ++i)
         for (int64_t k = Lc.A.rp[i]; k < Lc.A.rp[i + 1]; ++k) M[i * nc + Lc.A.ci[k]] = Lc.A.v[k];
     if (!cholesky(static_cast<int>(nc), M.data())) throw Error(MSP_ERR_NOT_SPD, "coarsest level is not SPD");
-    // inverse: solve L Y = I, then L^T X = Y, column by column
-    H.coarse_inv.assign(nc * nc, 0.0);
-    std::vector<double> y(nc);
-    for (int64_t c = 0; c < nc; ++c) {
-        for (int64_t i = 0; i < nc; ++i) {
+    // column c of Linv holds entries c..nc-1, stored contiguously
+    std::vector<int64_t> coff(nc + 1, 0);
+    for (int64_t c = 0; c < nc; ++c) coff[c + 1] = coff[c] + (nc - c);
+    std::vector<double> Li(coff[nc]);
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto parallel = [&](auto&& body) {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nth; ++t)
+            th.emplace_back([&, t]() {
+                for (int64_t c = t; c < nc; c += nth) body(c);
+            });
+        for (auto& x : th) x.join();
+    };
+    parallel([&](int64_t c) {
+        double* y = Li.data() + coff[c];   // y[i - c] = Linv[i][c], i >= c
+        for (int64_t i = c; i < nc; ++i) {
             double s = (i == c) ? 1.0 : 0.0;
-            for (int64_t p = c; p < i; ++p) s -= M[i * nc + p] * y[p];
-            y[i] = (i < c) ? 0.0 : s / M[i * nc + i];
+            const double* Lr = M.data() + i * nc;
+            for (int64_t p = c; p < i; ++p) s -= Lr[p] * y[p - c];
+            y[i - c] = s / Lr[i];
         }
-        for (int64_t i = nc - 1; i >= 0; --i) {
-            double s = y[i];
-            for (int64_t p = i + 1; p < nc; ++p) s -= M[p * nc + i] * H.coarse_inv[p * nc + c];
-            H.coarse_inv[i * nc + c] = s / M[i * nc + i];
+    });
+    H.coarse_inv.assign(nc * nc, 0.0);
+    parallel([&](int64_t i) {
+        const double* ci = Li.data() + coff[i];
+        for (int64_t j = i; j < nc; ++j) {
+            const double* cj = Li.data() + coff[j];
+            double s = 0.0;
+            for (int64_t p = j; p < nc; ++p) s += ci[p - i] * cj[p - j];
+            H.coarse_inv[i * nc + j] = s;
+            H.coarse_inv[j * nc + i] = s;
         }
-    }
+    });
     return H;
 }
 

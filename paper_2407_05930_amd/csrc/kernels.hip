@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
                                                  const double* __restrict__ sigma, int S, int m) {
     using L = Lanes<T, C>;
     constexpr int VW = L::VW;
-    const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
+    const int64_t row = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * L::RPB + threadIdx.x / L::LPR;
     const int lane = threadIdx.x % L::LPR;
     if (row >= n) return;
     T acc[VW];
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
     const int slot = threadIdx.x / TPR;
     const int g = (threadIdx.x % TPR) / L::LPR;
     const int lane = threadIdx.x % L::LPR;
-    const int64_t row = (int64_t)blockIdx.x * RPB + slot;
+    const int64_t row = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * RPB + slot;
     T acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = T(0);
@@ -338,41 +338,46 @@ __global__ void k_thresholds(int C, int S, int m, double tol, const double* __re
 
 // ------------------------------------------------------------------ dense coarsest level
 // out[i, :] = sum_k Minv[i, k] * y[k, :] in FP64 (inputs/outputs of type T).
-// One block per row: the 256 / LPR lane groups split k and their partial
-// rows are summed in LDS in a fixed order.
+// A block computes RB = 256 / LPR consecutive rows; k runs in tiles of KT:
+// the RB x KT slab of Minv and the KT x C slab of y are staged in LDS with
+// coalesced loads, then every lane accumulates its row and VW columns.
 template <typename T, int C>
 __global__ __launch_bounds__(kBlock) void k_dense(int64_t nL, const double* __restrict__ Minv,
                                                   const T* __restrict__ y, T* __restrict__ out) {
     using L = Lanes<T, C>;
-    constexpr int VW = L::VW;
-    constexpr int G = kBlock / L::LPR;
-    __shared__ double sm[kBlock * VW];
-    const int64_t row = blockIdx.x;
-    const int g = threadIdx.x / L::LPR;
-    const int lane = threadIdx.x % L::LPR;
+    constexpr int VW = L::VW, LPR = L::LPR, RB = L::RPB;
+    constexpr int KT = 32;
+    __shared__ double sM[RB * KT];
+    __shared__ T sY[KT * C];
+    const int r = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+    const int64_t row0 = (int64_t)blockIdx.x * RB;
     double acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = 0.0;
-    const double* mr = Minv + row * nL;
-    for (int64_t k = g; k < nL; k += G) {
-        const double a = mr[k];
-        const Pack<T, VW> x = ld<T, VW>(y + k * C + lane * VW);
+    for (int64_t k0 = 0; k0 < nL; k0 += KT) {
+        for (int q = threadIdx.x; q < RB * KT; q += kBlock) {
+            const int rr = q / KT, kk = q % KT;
+            const int64_t gi = row0 + rr, gk = k0 + kk;
+            sM[q] = (gi < nL && gk < nL) ? Minv[gi * nL + gk] : 0.0;
+        }
+        for (int q = threadIdx.x; q < KT * C; q += kBlock) {
+            const int64_t gk = k0 + q / C;
+            sY[q] = gk < nL ? y[gk * C + q % C] : T(0);
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < KT; ++kk) {
+            const double a = sM[r * KT + kk];
 #pragma unroll
-        for (int e = 0; e < VW; ++e) acc[e] += a * (double)x.e[e];
+            for (int e = 0; e < VW; ++e) acc[e] += a * (double)sY[kk * C + lane * VW + e];
+        }
+        __syncthreads();
     }
-#pragma unroll
-    for (int e = 0; e < VW; ++e) sm[threadIdx.x * VW + e] = acc[e];
-    __syncthreads();
-    if (g == 0) {
-#pragma unroll
-        for (int e = 0; e < VW; ++e) acc[e] = 0.0;
-        for (int q = 0; q < G; ++q)
-#pragma unroll
-            for (int e = 0; e < VW; ++e) acc[e] += sm[(q * L::LPR + lane) * VW + e];
+    if (row0 + r < nL) {
         Pack<T, VW> o;
 #pragma unroll
         for (int e = 0; e < VW; ++e) o.e[e] = (T)acc[e];
-        st<T, VW>(out + row * C + lane * VW, o);
+        st<T, VW>(out + (row0 + r) * C + lane * VW, o);
     }
 }
 
@@ -707,7 +712,7 @@ template <typename T>
 hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out) {
     MSP_DISPATCH_C(C, {
         using L = Lanes<T, CC>;
-        hipLaunchKernelGGL((k_dense<T, CC>), dim3((unsigned)nL), dim3(kBlock), 0, st, nL, Minv, y, out);
+        hipLaunchKernelGGL((k_dense<T, CC>), dim3(blocks_for(nL, L::RPB)), dim3(kBlock), 0, st, nL, Minv, y, out);
     });
     return hipGetLastError();
 }

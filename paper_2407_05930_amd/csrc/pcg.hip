@@ -19,6 +19,14 @@ namespace msp {
 template <int C>
 using DL = Lanes<double, C>;
 
+// Tiles [t0, t1) of a block: a contiguous chunk per block, blocks remapped so
+// that each XCD owns a contiguous range of chunks.
+__device__ __forceinline__ void block_tiles(int64_t ntiles, int64_t& t0, int64_t& t1) {
+    const int64_t chunk = (ntiles + gridDim.x - 1) / gridDim.x;
+    t0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * chunk;
+    t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
+}
+
 // q = (A_inn + diag-outer) p; partial[b, c] = this block's sum of p[:, c] q[:, c]
 template <int C>
 __global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __restrict__ rp,
@@ -33,7 +41,9 @@ __global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __r
     double dacc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) dacc[e] = 0.0;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int64_t tb, te;
+    block_tiles(ntiles, tb, te);
+    for (int64_t tile = tb; tile < te; ++tile) {
         const int64_t row = tile * RPB + slot;
         if (row >= n) continue;
         double acc[VW];
@@ -85,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
                                                         const double* __restrict__ z, const TU* __restrict__ U,
                                                         int S, int k, int m, double* __restrict__ partial_rr,
                                                         double* __restrict__ partial_rz,
-                                                        double* __restrict__ partial_lrc) {
+                                                        double* __restrict__ partial_lrc, float* __restrict__ y32) {
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
     constexpr int KA = KMAX > 0 ? KMAX : 1;
     __shared__ double sm[kBlock * VW];
@@ -101,7 +111,9 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
 #pragma unroll
         for (int t = 0; t < KA; ++t) a_l[e][t] = 0.0;
     }
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int64_t tb, te;
+    block_tiles(ntiles, tb, te);
+    for (int64_t tile = tb; tile < te; ++tile) {
         const int64_t row = tile * RPB + slot;
         if (row >= n) continue;
         const int64_t o = row * C + lane * VW;
@@ -116,6 +128,12 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
             }
             st<double, VW>(x + o, xv);
             st<double, VW>(r + o, rv);
+        }
+        if (y32) {   // FP32 copy of r: the V-cycle input of the mixed mode
+            Pack<float, VW> yv;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) yv.e[e] = (float)rv.e[e];
+            st<float, VW>(y32 + o, yv);
         }
 #pragma unroll
         for (int e = 0; e < VW; ++e) a_rr[e] += rv.e[e] * rv.e[e];
@@ -230,7 +248,9 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
     double acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = 0.0;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int64_t tb, te;
+    block_tiles(ntiles, tb, te);
+    for (int64_t tile = tb; tile < te; ++tile) {
         const int64_t row = tile * RPB + slot;
         if (row >= n) continue;
         const int64_t o = row * C + lane * VW;
@@ -342,39 +362,39 @@ hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial
 template <int CC, bool UPD, bool FLEX, int KMAX, typename TU>
 static void upd_launch(hipStream_t st, int nb, int64_t n, double* x, double* r, const double* p, const double* q,
                        const double* alpha, const double* z, const TU* U, int S, int k, int m, double* prr,
-                       double* prz, double* plrc) {
+                       double* prz, double* plrc, float* y32) {
     hipLaunchKernelGGL((k_update_dots<CC, UPD, FLEX, KMAX, TU>), dim3(nb), dim3(kBlock), 0, st, n, x, r, p, q, alpha,
-                       z, U, S, k, m, prr, prz, plrc);
+                       z, U, S, k, m, prr, prz, plrc, y32);
 }
 
 template <typename TU>
 hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* x,
                               double* r, const double* p, const double* q, const double* alpha, const double* z,
-                              const TU* U, int S, int m, double* prr, double* prz, double* plrc) {
+                              const TU* U, int S, int m, double* prr, double* prz, double* plrc, float* y32) {
     if (k > 16) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         if (k > 8) {
-            if (upd && flex) upd_launch<CC, true, true, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
-            else if (upd) upd_launch<CC, true, false, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
-            else upd_launch<CC, false, false, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+            if (upd && flex) upd_launch<CC, true, true, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else if (upd) upd_launch<CC, true, false, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else upd_launch<CC, false, false, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
         } else if (k > 0) {
-            if (upd && flex) upd_launch<CC, true, true, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
-            else if (upd) upd_launch<CC, true, false, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
-            else upd_launch<CC, false, false, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+            if (upd && flex) upd_launch<CC, true, true, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else if (upd) upd_launch<CC, true, false, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else upd_launch<CC, false, false, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
         } else {
-            if (upd && flex) upd_launch<CC, true, true, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
-            else if (upd) upd_launch<CC, true, false, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
-            else upd_launch<CC, false, false, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc);
+            if (upd && flex) upd_launch<CC, true, true, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else if (upd) upd_launch<CC, true, false, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else upd_launch<CC, false, false, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
         }
     });
     return hipGetLastError();
 }
 template hipError_t launch_update_dots<float>(hipStream_t, int, int, bool, bool, int, int64_t, double*, double*,
                                               const double*, const double*, const double*, const double*,
-                                              const float*, int, int, double*, double*, double*);
+                                              const float*, int, int, double*, double*, double*, float*);
 template hipError_t launch_update_dots<double>(hipStream_t, int, int, bool, bool, int, int64_t, double*, double*,
                                                const double*, const double*, const double*, const double*,
-                                               const double*, int, int, double*, double*, double*);
+                                               const double*, int, int, double*, double*, double*, float*);
 
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
                             const double* prz, const double* plrc, const double* thr, const double* coef, int* active,

@@ -19,7 +19,7 @@ hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial
 template <typename TU>
 hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* x,
                               double* r, const double* p, const double* q, const double* alpha, const double* z,
-                              const TU* U, int S, int m, double* prr, double* prz, double* plrc);
+                              const TU* U, int S, int m, double* prr, double* prz, double* plrc, float* y32);
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
                             const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
                             int* iters, int* flags, double* rnorm, double* rzold, double* W);
