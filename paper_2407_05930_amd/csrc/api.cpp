@@ -56,6 +56,7 @@ struct Work {
     std::vector<void*> vy, vs, vr, vt;    // per level, element type of the V-cycle (vt: factored smoother)
     double* partial = nullptr;
     int nb_dot = 0;
+    double* dense_part = nullptr;   // k-chunk partials of the dense coarsest solve
     // partials of the fused PCG kernels: two column sets and the low-rank projections
     double *pp1 = nullptr, *pp2 = nullptr, *plrc = nullptr;
     double* scal = nullptr;   // 10 arrays of 64
@@ -394,6 +395,9 @@ static Work& work(msp_ctx* c, int C) {
                 w.vt[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
         }
     }
+    if (c->o.pc == MSP_PC_AMGR)
+        w.dense_part = c->dalloc<double>(static_cast<int64_t>(dense_splits(C, c->hier.lev.back().A.nr, mixed(c))) *
+                                         c->hier.lev.back().A.nr * C);
     w.nb_dot = 512;
     w.partial = c->dalloc<double>(static_cast<int64_t>(w.nb_dot) * 64);
     w.pp1 = c->dalloc<double>(static_cast<int64_t>(kPcgMaxBlocks) * 64);
@@ -419,7 +423,8 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     const int C = w.C;
     if (l + 1 == c->hier.lev.size()) {
         const double bytes = 8.0 * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
-        timed(c, KD_DENSE, bytes, st, [&] { HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s)); });
+        timed(c, KD_DENSE, bytes, st,
+              [&] { HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s, w.dense_part)); });
         return;
     }
     const DevLevel& L = c->dl[l];

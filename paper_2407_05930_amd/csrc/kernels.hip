@@ -337,13 +337,13 @@ __global__ void k_thresholds(int C, int S, int m, double tol, const double* __re
 }
 
 // ------------------------------------------------------------------ dense coarsest level
-// out[i, :] = sum_k Minv[i, k] * y[k, :] in FP64 (inputs/outputs of type T).
-// A block computes RB = 256 / LPR consecutive rows; k runs in tiles of KT:
-// the RB x KT slab of Minv and the KT x C slab of y are staged in LDS with
-// coalesced loads, then every lane accumulates its row and VW columns.
+// X = Minv Y in FP64 (Y, X of type T), split over k: block (bx, ks) computes
+// RB = 256 / LPR consecutive rows for k in chunk ks, staging the RB x KT slab
+// of Minv and the KT x C slab of Y in LDS per tile; the FP64 partial rows go
+// to part[ks] and a second kernel sums the chunks in a fixed order.
 template <typename T, int C>
-__global__ __launch_bounds__(kBlock) void k_dense(int64_t nL, const double* __restrict__ Minv,
-                                                  const T* __restrict__ y, T* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_dense_part(int64_t nL, int64_t kchunk, const double* __restrict__ Minv,
+                                                       const T* __restrict__ y, double* __restrict__ part) {
     using L = Lanes<T, C>;
     constexpr int VW = L::VW, LPR = L::LPR, RB = L::RPB;
     constexpr int KT = 32;
@@ -351,18 +351,20 @@ __global__ __launch_bounds__(kBlock) void k_dense(int64_t nL, const double* __re
     __shared__ T sY[KT * C];
     const int r = threadIdx.x / LPR, lane = threadIdx.x % LPR;
     const int64_t row0 = (int64_t)blockIdx.x * RB;
+    const int64_t kb = (int64_t)blockIdx.y * kchunk;
+    const int64_t ke = kb + kchunk < nL ? kb + kchunk : nL;
     double acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = 0.0;
-    for (int64_t k0 = 0; k0 < nL; k0 += KT) {
+    for (int64_t k0 = kb; k0 < ke; k0 += KT) {
         for (int q = threadIdx.x; q < RB * KT; q += kBlock) {
             const int rr = q / KT, kk = q % KT;
             const int64_t gi = row0 + rr, gk = k0 + kk;
-            sM[q] = (gi < nL && gk < nL) ? Minv[gi * nL + gk] : 0.0;
+            sM[q] = (gi < nL && gk < ke) ? Minv[gi * nL + gk] : 0.0;
         }
         for (int q = threadIdx.x; q < KT * C; q += kBlock) {
             const int64_t gk = k0 + q / C;
-            sY[q] = gk < nL ? y[gk * C + q % C] : T(0);
+            sY[q] = gk < ke ? y[gk * C + q % C] : T(0);
         }
         __syncthreads();
 #pragma unroll 8
@@ -374,11 +376,20 @@ __global__ __launch_bounds__(kBlock) void k_dense(int64_t nL, const double* __re
         __syncthreads();
     }
     if (row0 + r < nL) {
-        Pack<T, VW> o;
+        double* o = part + ((int64_t)blockIdx.y * nL + row0 + r) * C + lane * VW;
 #pragma unroll
-        for (int e = 0; e < VW; ++e) o.e[e] = (T)acc[e];
-        st<T, VW>(out + (row0 + r) * C + lane * VW, o);
+        for (int e = 0; e < VW; ++e) o[e] = acc[e];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dense_sum(int64_t len, int ks, const double* __restrict__ part,
+                                                      T* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= len) return;
+    double s = 0.0;
+    for (int q = 0; q < ks; ++q) s += part[(int64_t)q * len + i];
+    out[i] = (T)s;
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -708,16 +719,35 @@ hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, co
     return hipGetLastError();
 }
 
+// k-chunks of the dense product: about 1024 blocks in total, whole tiles per chunk
+int dense_splits(int C, int64_t nL, bool fp32) {
+    const int lpr = fp32 ? (C >= 4 ? C / 4 : 1) : (C >= 2 ? C / 2 : 1);
+    const int64_t rb = kBlock / lpr;
+    const int64_t rows = (nL + rb - 1) / rb;
+    int64_t ks = (1024 + rows - 1) / rows;
+    const int64_t tiles = (nL + 31) / 32;
+    if (ks > tiles) ks = tiles;
+    if (ks < 1) ks = 1;
+    if (ks > 64) ks = 64;
+    return (int)ks;
+}
+
 template <typename T>
-hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out) {
+hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part) {
+    const int ks = dense_splits(C, nL, sizeof(T) == 4);
+    const int64_t tiles = (nL + 31) / 32;
+    const int64_t kchunk = ((tiles + ks - 1) / ks) * 32;
     MSP_DISPATCH_C(C, {
         using L = Lanes<T, CC>;
-        hipLaunchKernelGGL((k_dense<T, CC>), dim3(blocks_for(nL, L::RPB)), dim3(kBlock), 0, st, nL, Minv, y, out);
+        hipLaunchKernelGGL((k_dense_part<T, CC>), dim3(blocks_for(nL, L::RPB), ks), dim3(kBlock), 0, st, nL, kchunk,
+                           Minv, y, part);
+        hipLaunchKernelGGL((k_dense_sum<T>), dim3(blocks_for(nL * CC, kBlock)), dim3(kBlock), 0, st, nL * CC, ks, part,
+                           out);
     });
     return hipGetLastError();
 }
-template hipError_t launch_dense<double>(hipStream_t, int, int64_t, const double*, const double*, double*);
-template hipError_t launch_dense<float>(hipStream_t, int, int64_t, const double*, const float*, float*);
+template hipError_t launch_dense<double>(hipStream_t, int, int64_t, const double*, const double*, double*, double*);
+template hipError_t launch_dense<float>(hipStream_t, int, int64_t, const double*, const float*, float*, double*);
 
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {

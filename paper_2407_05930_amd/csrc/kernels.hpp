@@ -48,8 +48,10 @@ hipError_t launch_colnorm2(hipStream_t st, int64_t n, int m, const double* b, do
                            double* out);
 hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, const double* bn2, double* thr);
 
+// out = Minv y (dense FP64 coarsest solve, split over k; part: dense_splits() * nL * C doubles)
+int dense_splits(int C, int64_t nL, bool fp32);
 template <typename T>
-hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out);
+hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part);
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v);
 template <typename TO, typename TI>

@@ -19,13 +19,6 @@ namespace msp {
 template <int C>
 using DL = Lanes<double, C>;
 
-// Tiles [t0, t1) of a block: a contiguous chunk per block, blocks remapped so
-// that each XCD owns a contiguous range of chunks.
-__device__ __forceinline__ void block_tiles(int64_t ntiles, int64_t& t0, int64_t& t1) {
-    const int64_t chunk = (ntiles + gridDim.x - 1) / gridDim.x;
-    t0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * chunk;
-    t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
-}
 
 // q = (A_inn + diag-outer) p; partial[b, c] = this block's sum of p[:, c] q[:, c]
 template <int C>
@@ -41,9 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __r
     double dacc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) dacc[e] = 0.0;
-    int64_t tb, te;
-    block_tiles(ntiles, tb, te);
-    for (int64_t tile = tb; tile < te; ++tile) {
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row = tile * RPB + slot;
         if (row >= n) continue;
         double acc[VW];
@@ -111,9 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
 #pragma unroll
         for (int t = 0; t < KA; ++t) a_l[e][t] = 0.0;
     }
-    int64_t tb, te;
-    block_tiles(ntiles, tb, te);
-    for (int64_t tile = tb; tile < te; ++tile) {
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row = tile * RPB + slot;
         if (row >= n) continue;
         const int64_t o = row * C + lane * VW;
@@ -248,9 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
     double acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = 0.0;
-    int64_t tb, te;
-    block_tiles(ntiles, tb, te);
-    for (int64_t tile = tb; tile < te; ++tile) {
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row = tile * RPB + slot;
         if (row >= n) continue;
         const int64_t o = row * C + lane * VW;
