@@ -456,3 +456,72 @@ def vcycle(H: Hierarchy, y: np.ndarray, lev: int = 0) -> np.ndarray:
     s = s + L.P @ hc
     s = s + L.omega * (GT @ (L.G @ (y - L.A @ s)))
     return s
+
+
+# ---------------------------------------------------------------------------
+# AMGR on the decoupled subsystems (Sec. 3.2 applied in the Q_s basis)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SubHierarchy:
+    """Level 0 (the reduction) is shared by every subsystem: its C/F split
+    forces the interface coarse, so P_0 = [W; I] is the same for all
+    A_a = A_inn + diag(sigma_a) (sigma_a lives on interface rows only).  The
+    reduced operators differ only on the interface diagonal:
+    A_1,a = P_0^T A_a P_0 = A_1,inn + diag(sigma_a[C]).  Levels below are
+    built for every subsystem from its own A_1,a, with the C/F splits and
+    smoother patterns of the shared hierarchy on A_inn (so all subsystems
+    share one sparsity pattern per level) and each subsystem's own values."""
+    level0: Level
+    subs: List[Hierarchy]          # per subsystem: levels 1.. (coarsest dense)
+
+
+def sub_level_values(A: sp.csr_matrix, shared: Level, steps: int, seed: int, level0: bool) -> Level:
+    """One level for a subsystem operator A with the shared level's C/F split
+    and FSAI pattern (from the strength of the shared operator)."""
+    n = A.shape[0]
+    C = shared.C
+    S = strength(shared.A, AMGOptions.theta)
+    block = C.astype(np.int64) if level0 else np.zeros(n, dtype=np.int64)
+    G = fsai(A, S, block)
+    om = damping(A, G, seed)
+    P = interpolation(A, C, steps)
+    R = P.T.tocsr()
+    R.sort_indices()
+    return Level(A=A, C=C, P=P, R=R, G=G, omega=om)
+
+
+def build_sub_hierarchy(hier: Hierarchy, sigma: np.ndarray, opt: AMGOptions) -> SubHierarchy:
+    """sigma: (n_b, 2^s) outer diagonal.  hier: the shared AMGR hierarchy on
+    A_inn (provides level 0 and the C/F splits and patterns below)."""
+    L0 = hier.levels[0]
+    cidx = np.flatnonzero(L0.C)
+    subs = []
+    for a in range(sigma.shape[1]):
+        A = (hier.levels[1].A + sp.diags(sigma[cidx, a])).tocsr()
+        A.sort_indices()
+        levels = []
+        for lev in range(1, hier.nlev):
+            if lev == hier.nlev - 1:
+                levels.append(Level(A=A))
+                break
+            Lv = sub_level_values(A, hier.levels[lev], opt.jacobi, opt.seed, False)
+            levels.append(Lv)
+            A = galerkin(A, Lv.P)
+        fac = sla.cho_factor(levels[-1].A.toarray(), lower=True)
+        subs.append(Hierarchy(levels=levels, coarse_factor=fac))
+    return SubHierarchy(level0=L0, subs=subs)
+
+
+def vcycle_sub(SH: SubHierarchy, Ahat_a: sp.csr_matrix, a: int, y: np.ndarray) -> np.ndarray:
+    """Alg. 3 for subsystem a: level-0 smoother and transfers shared, the
+    residual with the subsystem's own operator, the coarse correction by the
+    subsystem's hierarchy."""
+    L = SH.level0
+    GT = L.G.T
+    s = L.omega * (GT @ (L.G @ y))
+    r = y - Ahat_a @ s
+    hc = vcycle(SH.subs[a], L.R @ r, 0)
+    s = s + L.P @ hc
+    s = s + L.omega * (GT @ (L.G @ (y - Ahat_a @ s)))
+    return s

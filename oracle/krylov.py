@@ -16,7 +16,7 @@ import scipy.sparse as sp
 
 from . import symmetry
 from . import lrc as lrcmod
-from .amg import AMGOptions, Hierarchy, build_hierarchy, vcycle
+from .amg import AMGOptions, Hierarchy, build_hierarchy, build_sub_hierarchy, vcycle, vcycle_sub
 
 
 class Breakdown(RuntimeError):
@@ -90,22 +90,35 @@ class SolveResult:
 def setup(A: sp.csr_matrix, img: np.ndarray, opt: Optional[AMGOptions] = None,
           precond: str = "amgr", k: int = 0):
     """Setup of Alg. 1: base blocks, shared A_inn, per-subsystem outer parts,
-    interface set, and the shared preconditioner: "amgr" (AMGR hierarchy on
-    A_inn, LRCAMG(k) when k > 0), "fsai" (FSAI of A_inn, LRCFSAI(k) when
-    k > 0) or "none"."""
+    interface set, and the preconditioner: "amgr" (AMGR hierarchy on A_inn
+    shared by every subsystem, LRCAMG(k) when k > 0), "amgr_sub" (the shared
+    reduction level, then every subsystem's own reduced operator and levels
+    below it; LRCAMG(k) on top when k > 0), "fsai" (FSAI of A_inn,
+    LRCFSAI(k) when k > 0) or "none"."""
     opt = opt or AMGOptions()
     H = symmetry.base_blocks(A, img)
     Ainn, outs = symmetry.inner_outer(H)
     iface = symmetry.interface_rows(H)
-    hier = build_hierarchy(Ainn, iface, opt) if precond == "amgr" else None
+    hier = build_hierarchy(Ainn, iface, opt) if precond in ("amgr", "amgr_sub") else None
+    sub = None
+    if precond == "amgr_sub" and hier.nlev > 1:
+        sigma = np.stack([o.diagonal() for o in outs], axis=1)
+        sub = build_sub_hierarchy(hier, sigma, opt)
     G = lrcmod.fsai_inner(Ainn) if precond == "fsai" else None
     low = None
     if k > 0 and precond == "amgr":
         low = lrcmod.build_lrcamg(hier, Ainn, outs, k, opt.seed)
+    elif k > 0 and precond == "amgr_sub":
+        Ahat = [(Ainn + o).tocsr() for o in outs]
+        if sub is None:
+            low = lrcmod.build_lrcamg(hier, Ainn, outs, k, opt.seed)
+        else:
+            low = lrcmod.build_lrcamg(hier, Ainn, outs, k, opt.seed,
+                                      apply_Minv=lambda a, x: vcycle_sub(sub, Ahat[a], a, x))
     elif k > 0 and precond == "fsai":
         low = lrcmod.build_lrcfsai(G, Ainn, outs, k, opt.seed)
     return dict(H=H, Ainn=Ainn, outs=outs, interface=iface, hier=hier, G=G, lrc=low, img=img,
-                opt=opt, precond=precond)
+                opt=opt, precond=precond, sub=sub)
 
 
 def solve(ctx: dict, b: np.ndarray, tol: float = 1e-10, maxit: int = 1000,
@@ -134,6 +147,17 @@ def solve(ctx: dict, b: np.ndarray, tol: float = 1e-10, maxit: int = 1000,
     if precond == "amgr":
         def apply_M(R):
             Z = vcycle(hier, R)
+            if lrc is not None:
+                Z = Z + lrc.apply(R, m)
+            return Z
+    elif precond == "amgr_sub":
+        def apply_M(R):
+            if ctx["sub"] is None:
+                Z = vcycle(hier, R)
+            else:
+                Z = np.empty_like(R)
+                for a in range(S):
+                    Z[:, a * m:(a + 1) * m] = vcycle_sub(ctx["sub"], Ahat[a], a, R[:, a * m:(a + 1) * m])
             if lrc is not None:
                 Z = Z + lrc.apply(R, m)
             return Z

@@ -99,18 +99,24 @@ class LowRank:
 
 
 def build_lrcamg(hier, Ainn: sp.csr_matrix, outs, k: int, seed: int,
-                 keep_all: bool = False, steps: int = None) -> LowRank:
+                 keep_all: bool = False, steps: int = None, apply_Minv=None) -> LowRank:
     """LRCAMG(k) in symmetric form for every subsystem a: Lanczos on
     M^{-1} A_a in the A_a inner product; keep the k smallest Ritz pairs
     and, of those, the ones below 1; coefficient 1 - lam.  ``keep_all`` keeps
-    every pair (the full-rank statement of Thm. 2.2)."""
+    every pair (the full-rank statement of Thm. 2.2).  M^{-1} is the shared
+    V-cycle of ``hier``, or ``apply_Minv(a, x)`` when given (a preconditioner
+    of its own per subsystem)."""
     n = Ainn.shape[0]
     steps = steps or lanczos_steps(k, n)
     v0 = start_vector(n, seed)
     Us, cs, rs = [], [], []
     for a, Ao in enumerate(outs):
         Ah = (Ainn + Ao).tocsr()
-        V, al, be = lanczos(lambda v, Bv: vcycle(hier, Bv), lambda x: Ah @ x, v0, steps)
+        if apply_Minv is None:
+            op = lambda v, Bv: vcycle(hier, Bv)
+        else:
+            op = lambda v, Bv, a=a: apply_Minv(a, Bv)
+        V, al, be = lanczos(op, lambda x: Ah @ x, v0, steps)
         th, U = ritz(V, al, be, k)
         keep = np.ones(th.size, dtype=bool) if keep_all else th < 1.0
         Us.append(U[:, keep])

@@ -289,3 +289,90 @@ def test_two_grid_exact_coarse_solve():
     y = np.random.default_rng(2).standard_normal(A.shape[0])
     x = amg.vcycle(H, y)
     assert np.abs(A @ x - y).max() < 1e-12 * np.abs(y).max()
+
+
+# ----------------------------------------------------------------- AMGR per subsystem
+
+def _sub(N=(12, 12, 12), coarse_max=40, **kw):
+    p = make_problem(N, s=3, seed=4, **kw)
+    H = symmetry.base_blocks(p.A, p.img)
+    Ainn, outs = symmetry.inner_outer(H)
+    iface = symmetry.interface_rows(H)
+    opt = amg.AMGOptions(coarse_max=coarse_max)
+    hier = amg.build_hierarchy(Ainn.tocsr(), iface, opt)
+    sigma = np.stack([o.diagonal() for o in outs], axis=1)
+    Ahat = [(Ainn + o).tocsr() for o in outs]
+    return hier, sigma, Ahat, opt
+
+
+def test_sub_reduced_operator_is_galerkin_of_each_subsystem():
+    """The interface is coarse and P_0 = [W; I], so P_0^T (A_inn + diag sigma_a) P_0
+    differs from P_0^T A_inn P_0 only by sigma_a on the coarse interface points:
+    the shortcut A_1 + diag(sigma_a[C]) must equal the plain product."""
+    hier, sigma, Ahat, opt = _sub(y_stretch=1.5)
+    SH = amg.build_sub_hierarchy(hier, sigma, opt)
+    P0 = hier.levels[0].P.toarray()
+    for a, Aa in enumerate(Ahat):
+        ref = P0.T @ Aa.toarray() @ P0
+        got = SH.subs[a].levels[0].A.toarray()
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_sub_zero_shift_reproduces_shared_levels():
+    hier, sigma, _, opt = _sub()
+    SH = amg.build_sub_hierarchy(hier, np.zeros_like(sigma), opt)
+    for sub in SH.subs:
+        assert len(sub.levels) == hier.nlev - 1
+        for Ls, Lh in zip(sub.levels, hier.levels[1:]):
+            assert (Ls.A != Lh.A).nnz == 0
+            if Lh.P is not None:
+                assert (Ls.P != Lh.P).nnz == 0 and (Ls.G != Lh.G).nnz == 0
+                assert Ls.omega == Lh.omega
+
+
+def test_sub_patterns_equal_shared_patterns():
+    hier, sigma, _, opt = _sub(y_stretch=1.5)
+    SH = amg.build_sub_hierarchy(hier, sigma, opt)
+    for sub in SH.subs:
+        for Ls, Lh in zip(sub.levels, hier.levels[1:]):
+            for X, Y in ((Ls.A, Lh.A), (Ls.P, Lh.P), (Ls.G, Lh.G)):
+                if Y is None:
+                    continue
+                assert np.array_equal(X.indptr, Y.indptr) and np.array_equal(X.indices, Y.indices)
+
+
+def test_sub_two_grid_is_exact_two_grid_of_subsystem():
+    """With two levels the per-subsystem cycle is the two-grid method for
+    A_a with the Galerkin coarse operator solved exactly:
+    I - V A_a = (I - M A_a)(I - P (P^T A_a P)^{-1} P^T A_a)(I - M A_a)."""
+    hier, sigma, Ahat, opt = _sub(coarse_max=200)
+    assert hier.nlev == 2
+    SH = amg.build_sub_hierarchy(hier, sigma, opt)
+    L0 = hier.levels[0]
+    n = L0.A.shape[0]
+    P = L0.P.toarray()
+    G = L0.G.toarray()
+    M = L0.omega * G.T @ G
+    I = np.eye(n)
+    for a in (0, 3, 7):
+        Aa = Ahat[a].toarray()
+        V = np.column_stack([amg.vcycle_sub(SH, Ahat[a], a, e) for e in I])
+        Kc = P @ np.linalg.solve(P.T @ Aa @ P, P.T @ Aa)
+        E = (I - M @ Aa) @ (I - Kc) @ (I - M @ Aa)
+        assert np.abs((I - V @ Aa) - E).max() < 1e-10
+
+
+def test_sub_vcycle_symmetric_and_contracts():
+    hier, sigma, Ahat, opt = _sub((10, 10, 10), coarse_max=20, y_stretch=1.5)
+    assert hier.nlev >= 3
+    SH = amg.build_sub_hierarchy(hier, sigma, opt)
+    n = Ahat[0].shape[0]
+    I = np.eye(n)
+    for a in (1, 6):
+        Aa = Ahat[a].toarray()
+        V = np.column_stack([amg.vcycle_sub(SH, Ahat[a], a, e) for e in I])
+        assert np.abs(V - V.T).max() <= 1e-12 * np.abs(V).max()
+        assert np.linalg.eigvalsh(0.5 * (V + V.T)).min() > 0
+        L = np.linalg.cholesky(Aa)
+        E = I - V @ Aa
+        assert np.linalg.norm(L.T @ E @ np.linalg.inv(L.T), 2) < 0.9

@@ -72,3 +72,22 @@ def test_breakdown_detected_on_indefinite_matrix():
     ctx = krylov.setup(A, p.img, precond="none")
     with pytest.raises(krylov.Breakdown):
         krylov.solve(ctx, p.b, tol=1e-10)
+
+
+@pytest.mark.parametrize("k", [0, 4])
+def test_amgr_per_subsystem_matches_direct_solve_in_fewer_iterations(k):
+    """AMGR applied to every decoupled subsystem (shared reduction level, each
+    subsystem's own reduced operator below) is still an SPD preconditioner:
+    Alg. 1 reaches the direct solution, and the exact subsystem coarse
+    operators take no more iterations than the shared A_inn hierarchy."""
+    p = make_problem((16, 16, 16), s=3, m=2, seed=5, y_stretch=1.5)
+    opt = amg.AMGOptions(coarse_max=48)
+    ref = spla.splu(p.A.tocsc()).solve(p.b)
+    its = {}
+    for pc in ("amgr", "amgr_sub"):
+        ctx = krylov.setup(p.A, p.img, opt, precond=pc, k=k)
+        r = krylov.solve(ctx, p.b, tol=1e-11)
+        assert np.all(krylov.true_relres(p.A, r.x, p.b) <= 1e-11 * 1.0001)
+        assert np.linalg.norm(r.x - ref) <= 1e-8 * np.linalg.norm(ref)
+        its[pc] = int(np.max(r.iters))
+    assert its["amgr_sub"] < its["amgr"]
