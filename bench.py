@@ -79,7 +79,7 @@ def committed_traffic(kind_name):
     return None
 
 
-def cpu_baseline(problem, iters_gpu, k):
+def cpu_baseline(problem, iters_gpu, k, pc):
     """The FP64 oracle on the host: setup plus a bounded sample of PCG
     iterations on the same workload, extrapolated to the GPU's iteration
     count.  One thread (SciPy's sparse products are single-threaded; BLAS is
@@ -88,7 +88,7 @@ def cpu_baseline(problem, iters_gpu, k):
     from oracle import amg, krylov
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        ctx = krylov.setup(problem.A, problem.img, amg.AMGOptions(), k=0)
+        ctx = krylov.setup(problem.A, problem.img, amg.AMGOptions(), precond=pc, k=0)
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
         krylov.solve(ctx, problem.b, tol=1e-10, maxit=1)
@@ -97,7 +97,7 @@ def cpu_baseline(problem, iters_gpu, k):
         t2 = time.perf_counter()
     per_it = ((t2 - t1) - (t1 - t0)) / 2.0
     est = (t1 - t0) + per_it * max(iters_gpu - 1, 0)
-    sample = (f"oracle setup ({t_setup:.1f} s, k=0) then PCG runs of 1 and 3 iterations on the full workload; "
+    sample = (f"oracle setup ({pc}, {t_setup:.1f} s, k=0) then PCG runs of 1 and 3 iterations on the full workload; "
               f"{per_it:.2f} s/iteration extrapolated to the GPU FP64 iteration count ({iters_gpu}); "
               f"low-rank corrections (k={k}) not included in the oracle sample")
     return dict(value=round(est, 3), unit="s", cores=1, kind="oracle", sample=sample,
@@ -221,6 +221,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="channel3d_128_s3")
     ap.add_argument("--k", type=int, default=8, help="low-rank correction rank per subsystem")
+    ap.add_argument("--pc", default="amgr_sub", choices=["amgr", "amgr_sub"],
+                    help="AMGR per subsystem below the shared reduction level (default), or the AMGR "
+                         "hierarchy of A_inn shared by every subsystem")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing the other preconditioner beside the headline one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for the traffic counters)")
@@ -254,25 +259,31 @@ def main():
     p = config_problem(args.workload)
     b = torch.from_numpy(p.b).cuda()
     k = args.k
-    res = {}
-    for prec in ("fp64", "mixed"):
-        log(f"setup {prec} k={k}")
-        try:
-            sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=k)
-        except Exception as e:   # low-rank corrections may be unavailable in this build
-            log(f"  k={k} unavailable ({e}); using k=0")
-            k = 0
-            sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=0)
-        t_setup = sv.stats.t_setup_s
-        log(f"timing {prec}: warmup {args.warmup}, steps {args.steps}")
-        t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
-        iters = sv.last.iters
-        relres = [float(v) for v in sv.last.relres[: p.b.shape[1]]]
-        xs = x.cpu().numpy()
-        true_rr = np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)
-        res[prec] = dict(sv=sv, t=t, iters=iters, relres=relres, true_relres=true_rr.tolist(), t_setup=t_setup,
-                         x=xs)
-        log(f"  {prec}: {t * 1e3:.2f} ms/solve, {iters} iterations, true rel res {true_rr.max():.2e}")
+
+    def run_pc(pc, k):
+        res = {}
+        for prec in ("fp64", "mixed"):
+            log(f"setup {pc} {prec} k={k}")
+            sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=k, pc=pc)
+            t_setup = sv.stats.t_setup_s
+            log(f"timing {pc} {prec}: warmup {args.warmup}, steps {args.steps}")
+            t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
+            iters = sv.last.iters
+            relres = [float(v) for v in sv.last.relres[: p.b.shape[1]]]
+            xs = x.cpu().numpy()
+            true_rr = np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)
+            res[prec] = dict(sv=sv, t=t, iters=iters, relres=relres, true_relres=true_rr.tolist(), t_setup=t_setup,
+                             x=xs)
+            log(f"  {pc} {prec}: {t * 1e3:.2f} ms/solve, {iters} iterations, true rel res {true_rr.max():.2e}")
+        return res
+
+    res = run_pc(args.pc, k)
+    other_pc = "amgr" if args.pc == "amgr_sub" else "amgr_sub"
+    other = None
+    if not args.no_compare:
+        other = run_pc(other_pc, k)
+        for v in other.values():
+            v["sv"].close()
 
     # roofline of the dominant kernel of the headline (mixed) solve, measured
     # with HIP events on the solve's stream during the timed steps
@@ -309,6 +320,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(p.N), "s": p.s, "rhs": int(p.b.shape[1]),
                    "subsystem_columns": int((1 << p.s) * p.b.shape[1]), "lrc_k": k, "tol": 1e-10,
+                   "preconditioner": args.pc,
                    "precision": "mixed (FP32 V-cycle, FP64 PCG)", "unknowns": int(p.n)},
         "fp64_solve_s": round(t_fp64, 6),
         "mixed_speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
@@ -325,9 +337,18 @@ def main():
         "kernel_breakdown_mixed": breakdown,
         "timed_solve_with_kernel_events_s": round(t_head, 6),
     }
+    if other is not None:
+        out[{"amgr": "shared_cycle", "amgr_sub": "per_subsystem_cycle"}[other_pc]] = {
+            "preconditioner": other_pc,
+            "mixed_solve_s": round(other["mixed"]["t"], 6), "fp64_solve_s": round(other["fp64"]["t"], 6),
+            "iters": {kk: v["iters"] for kk, v in other.items()},
+            "true_relres_max": {kk: max(v["true_relres"]) for kk, v in other.items()},
+            "mixed_vs_headline_rel_diff": float(np.linalg.norm(other["mixed"]["x"] - res["mixed"]["x"])
+                                                / np.linalg.norm(res["mixed"]["x"])),
+        }
     if not args.no_cpu_baseline and rank == 0:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(p, res["fp64"]["iters"], k)
+        out["cpu_baseline"] = cpu_baseline(p, res["fp64"]["iters"], k, args.pc)
     if rank == 0:
         print(json.dumps(out), flush=True)
 

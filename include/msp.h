@@ -61,7 +61,22 @@ typedef enum {
    MSP_MIXED_FP32 but the FSAI factors G, G^T are stored in bfloat16 and the
    smoother is applied factored, G^T (G r), which keeps it SPD. */
 enum { MSP_FP64 = 0, MSP_MIXED_FP32 = 1, MSP_MIXED_FP32_BF16G = 2 };
-enum { MSP_PC_AMGR = 0, MSP_PC_FSAI = 1, MSP_PC_NONE = 2 };
+/* Preconditioners of the decoupled subsystems A_a = A_inn + diag(sigma_a)
+   (Sec. 2, eqs. (2.8)-(2.11)):
+   MSP_PC_AMGR: the AMGR hierarchy of A_inn (Sec. 3.2, Alg. 2 and 3) shared by
+     every subsystem, applied to all columns at once; low-rank corrections per
+     subsystem on top (LRCAMG(k), eq. (2.20)).
+   MSP_PC_FSAI: FSAI of A_inn with LRCFSAI(k) corrections (eq. (2.27)).
+   MSP_PC_NONE: plain CG.
+   MSP_PC_AMGR_SUB: AMGR of every subsystem A_a (Sec. 3.2 applied to each
+     decoupled system).  The reduction level is shared: its C/F split forces
+     the interface coarse, so P_0 = [W; I] serves every a and the level-0
+     residual uses A_a itself.  Below it each subsystem has its own reduced
+     operator A_1,a = P_0^T A_a P_0 and levels built from it with the shared
+     C/F splits and sparsity patterns (values per subsystem, so one SpMM pass
+     still serves all columns); each has its own dense coarsest inverse.
+     Optional LRCAMG(k) on top. */
+enum { MSP_PC_AMGR = 0, MSP_PC_FSAI = 1, MSP_PC_NONE = 2, MSP_PC_AMGR_SUB = 3 };
 
 typedef struct msp_ctx msp_ctx;
 
@@ -82,7 +97,7 @@ typedef struct {
 
 typedef struct {
     int32_t precision;   /* MSP_FP64 | MSP_MIXED_FP32 | MSP_MIXED_FP32_BF16G */
-    int32_t pc;          /* MSP_PC_AMGR | MSP_PC_FSAI | MSP_PC_NONE */
+    int32_t pc;          /* MSP_PC_AMGR | MSP_PC_FSAI | MSP_PC_NONE | MSP_PC_AMGR_SUB */
     int32_t lrc_k;       /* low-rank correction rank per subsystem, >= 0 */
     int32_t dist;        /* interpolation distance d of Alg. 2 (>= 1) */
     double theta;        /* strength threshold */
@@ -148,6 +163,13 @@ int msp_level_sizes(const msp_ctx* c, int32_t lev, int64_t* n, int64_t* nnz_A, i
 int msp_export_level(const msp_ctx* c, int32_t lev, int8_t* cf, int64_t* A_rp, int32_t* A_ci,
                      double* A_v, int64_t* P_rp, int32_t* P_ci, double* P_v, int64_t* G_rp,
                      int32_t* G_ci, double* G_v, double* omega);
+/* MSP_PC_AMGR_SUB only: values of subsystem a (0 <= a < 2^s) on level
+   lev >= 1, on the patterns msp_export_level gives for that level (A_v:
+   nnz_A values, P_v: nnz_P, G_v: nnz_G; P and G absent on the coarsest
+   level) and its damping.  Any pointer may be NULL.  MSP_ERR_ARG for
+   another preconditioner, lev = 0 or an index out of range. */
+int msp_export_sub_level(const msp_ctx* c, int32_t lev, int32_t a, double* A_v, double* P_v, double* G_v,
+                         double* omega);
 /* Outer part: sigma[i * 2^s + a] (diagonal of A_out,a) and the interface
    mask (1 for base cells coupled to another image). */
 int msp_export_outer(const msp_ctx* c, double* sigma, int8_t* interface_mask);

@@ -31,7 +31,7 @@ STATUS = {
     -8: "MSP_ERR_UNSUPPORTED",
 }
 PRECISION = {"fp64": 0, "mixed": 1, "mixed_bf16g": 2}
-PC = {"amgr": 0, "fsai": 1, "none": 2}
+PC = {"amgr": 0, "fsai": 1, "none": 2, "amgr_sub": 3}
 
 
 class msp_csr(ctypes.Structure):
@@ -79,6 +79,7 @@ SIGNATURES = {
     "msp_export_level": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                         _P(ctypes.c_double)]),
     "msp_export_outer": (ctypes.c_int, [_vp, _vp, _vp]),
+    "msp_export_sub_level": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp]),
     "msp_export_lrc": (ctypes.c_int, [_vp, _vp, _vp]),
     "msp_set_timing": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "msp_reset_timing": (ctypes.c_int, [_vp]),

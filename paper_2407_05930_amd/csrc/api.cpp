@@ -33,6 +33,7 @@ static thread_local std::string g_last_error;
 struct DevCsr {
     int64_t nr = 0, nc = 0, nnz = 0;
     int split = 1;           // lane groups per row (long rows are split)
+    int vs = 1;              // interleaved value sets (one per subsystem), entry k of set a at k * vs + a
     int tuned[2][7] = {};    // autotuned split by [FP32?][log2 C]; 0 = not tuned
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
@@ -57,6 +58,8 @@ struct Work {
     double* partial = nullptr;
     int nb_dot = 0;
     double* dense_part = nullptr;   // k-chunk partials of the dense coarsest solve
+    void* dense_pack = nullptr;     // per-subsystem packed right-hand sides of the coarsest solves
+    int dense_rows = 8;             // rows per wavefront of the per-subsystem coarsest solves (autotuned)
     // partials of the fused PCG kernels: two column sets and the low-rank projections
     double *pp1 = nullptr, *pp2 = nullptr, *plrc = nullptr;
     double* scal = nullptr;   // 10 arrays of 64
@@ -104,6 +107,8 @@ struct msp_ctx {
     msp_opts o{};
     msp::SymParts sym;
     msp::HostHierarchy hier;
+    msp::SubValues subv;      // per-subsystem values of levels >= 1 (pc = AMGR_SUB)
+    bool sub = false;         // levels >= 1 and the coarsest solve are per subsystem
     msp::Csr Gf;              // FSAI of A_inn (pc = FSAI)
     msp_stats stats{};
     bool on_device = false;
@@ -111,6 +116,7 @@ struct msp_ctx {
     std::vector<void*> allocs;
     int64_t* d_img = nullptr;
     double* d_sigma = nullptr;
+    double* d_sigma1 = nullptr;   // pc = AMGR_SUB: sigma_a at the coarse numbers of the interface (level 1)
     msp::DevCsr dAinn, dGf, dGfT;
     std::vector<msp::DevLevel> dl;
     double* d_cinv = nullptr;
@@ -214,6 +220,32 @@ static DevCsr upload_csr(msp_ctx* c, const Csr& M, bool fp32, bool bf16 = false)
     return D;
 }
 
+// Pattern of M with vs interleaved value sets (values: nnz * vs, entry k of set a at k * vs + a).
+static DevCsr upload_sets(msp_ctx* c, const Csr& M, const std::vector<double>& values, int vs, bool fp32) {
+    if (static_cast<int64_t>(values.size()) != M.nnz() * vs) throw Error(MSP_ERR_ARG, "value sets size mismatch");
+    Csr pat = M;
+    pat.v.assign(1, 0.0);
+    DevCsr D;
+    D.nr = M.nr;
+    D.nc = M.nc;
+    D.nnz = M.nnz();
+    D.vs = vs;
+    if (D.nnz >= (int64_t(1) << 31) / vs) throw Error(MSP_ERR_UNSUPPORTED, "matrix too large for 32-bit indices");
+    std::vector<int32_t> rp(M.nr + 1);
+    for (int64_t i = 0; i <= M.nr; ++i) rp[i] = static_cast<int32_t>(M.rp[i]);
+    D.rp = c->upload(rp.data(), M.nr + 1);
+    D.ci = c->upload(M.ci.data(), D.nnz);
+    D.v64 = c->upload(values.data(), static_cast<int64_t>(values.size()));
+    const double avg = M.nr > 0 ? static_cast<double>(D.nnz) / static_cast<double>(M.nr) : 0.0;
+    D.split = 1;
+    while (D.split < 64 && 4.0 * D.split * 2 <= avg) D.split *= 2;
+    if (fp32) {
+        std::vector<float> f(values.begin(), values.end());
+        D.v32 = c->upload(f.data(), static_cast<int64_t>(f.size()));
+    }
+    return D;
+}
+
 template <typename T>
 static const T* vals(const DevCsr& M);
 template <>
@@ -266,7 +298,7 @@ template <typename T>
 static double spmm_bytes(const DevCsr& M, int C, bool z, bool sig, int S) {
     const double w = sizeof(T);
     const double wv = (sizeof(T) == 4 && M.v16) ? 2.0 : w;
-    double b = static_cast<double>(M.nnz) * (wv + 4.0) + 4.0 * static_cast<double>(M.nr + 1);
+    double b = static_cast<double>(M.nnz) * (wv * M.vs + 4.0) + 4.0 * static_cast<double>(M.nr + 1);
     b += static_cast<double>(M.nc) * C * w + static_cast<double>(M.nr) * C * w;
     if (z) b += static_cast<double>(M.nr) * C * w;
     if (sig) b += static_cast<double>(M.nr) * S * 8.0;
@@ -286,19 +318,20 @@ static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const
                         T beta, const double* sigma, int S, int m) {
     if constexpr (sizeof(T) == 4) {
         if (M.v16) {
-            if (split > 1 && !sigma)
-                HIPCHECK((launch_spmm_split<float, Bf16>(st, C, split, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha,
-                                                         beta)));
+            if (split > 1)
+                HIPCHECK((launch_spmm_split<float, Bf16>(st, C, split, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta,
+                                                         1, m, sigma, S)));
             else
-                HIPCHECK((launch_spmm<float, Bf16>(st, C, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta, sigma, S,
-                                                   m)));
+                HIPCHECK((launch_spmm<float, Bf16>(st, C, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta, sigma, S, m,
+                                                   1)));
             return;
         }
     }
-    if (split > 1 && !sigma)
-        HIPCHECK((launch_spmm_split<T, T>(st, C, split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta)));
+    if (split > 1)
+        HIPCHECK((launch_spmm_split<T, T>(st, C, split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, M.vs, m,
+                                          sigma, S)));
     else
-        HIPCHECK((launch_spmm<T, T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m)));
+        HIPCHECK((launch_spmm<T, T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m, M.vs)));
 }
 
 template <typename T>
@@ -319,6 +352,8 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
     hipStream_t st = nullptr;
     const int C = w.C;
     const int lpr = C * static_cast<int>(sizeof(T)) >= 16 ? C / (16 / static_cast<int>(sizeof(T))) : 1;
+    const int S = 1 << c->sym.s;
+    const int mt = std::max(1, C / S);   // columns per subsystem assumed for matrices with value sets
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
@@ -343,10 +378,10 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
             float best_ms = 1e30f;
             for (int g = 1; g <= 64 && g * lpr <= 256; g *= 2) {   // 256 threads per block
                 if (g > 1 && g > std::max(1.0, avg / 2.0)) break;
-                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, T(1), T(0), nullptr, 1, 1);
+                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, T(1), T(0), nullptr, S, mt);
                 HIPCHECK(hipEventRecord(e0, st));
                 for (int rep = 0; rep < 3; ++rep)
-                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, T(1), T(0), nullptr, 1, 1);
+                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, T(1), T(0), nullptr, S, mt);
                 HIPCHECK(hipEventRecord(e1, st));
                 HIPCHECK(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -359,11 +394,35 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
             jb.M->tuned[sizeof(T) == 4 ? 1 : 0][log2i(C)] = best;
         }
     }
+    // rows per wavefront of the per-subsystem coarsest solves
+    if (c->sub) {
+        const size_t Lc = c->hier.lev.size() - 1;
+        T* y = static_cast<T*>(w.vy[Lc]);
+        T* s = static_cast<T*>(w.vs[Lc]);
+        float best_ms = 1e30f;
+        for (int R = 1; R <= dense_sets_rows_max(mt); R *= 2) {
+            auto run = [&] {
+                HIPCHECK(launch_dense_sets<T>(st, C, S, mt, c->nL, c->d_cinv, y, s, static_cast<T*>(w.dense_pack), R));
+            };
+            run();
+            HIPCHECK(hipEventRecord(e0, st));
+            for (int rep = 0; rep < 3; ++rep) run();
+            HIPCHECK(hipEventRecord(e1, st));
+            HIPCHECK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                w.dense_rows = R;
+            }
+        }
+    }
     HIPCHECK(hipEventDestroy(e0));
     HIPCHECK(hipEventDestroy(e1));
 }
 
 static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
+static bool amg(const msp_ctx* c) { return c->o.pc == MSP_PC_AMGR || c->o.pc == MSP_PC_AMGR_SUB; }
 
 // Workspace for C padded columns (allocated on first use, kept with the context).
 static Work& work(msp_ctx* c, int C) {
@@ -385,7 +444,7 @@ static Work& work(msp_ctx* c, int C) {
     w.vs.assign(L, nullptr);
     w.vr.assign(L, nullptr);
     w.vt.assign(L, nullptr);
-    if (c->o.pc == MSP_PC_AMGR) {
+    if (amg(c)) {
         for (size_t l = 0; l < L; ++l) {
             const int64_t n = c->hier.lev[l].A.nr;
             w.vy[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
@@ -395,9 +454,12 @@ static Work& work(msp_ctx* c, int C) {
                 w.vt[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
         }
     }
-    if (c->o.pc == MSP_PC_AMGR)
-        w.dense_part = c->dalloc<double>(static_cast<int64_t>(dense_splits(C, c->hier.lev.back().A.nr, mixed(c))) *
-                                         c->hier.lev.back().A.nr * C);
+    if (amg(c)) {
+        const int64_t nL = c->hier.lev.back().A.nr;
+        const int ks = dense_splits(C, nL, mixed(c));
+        w.dense_part = c->dalloc<double>(static_cast<int64_t>(ks) * nL * C);
+        if (c->sub) w.dense_pack = c->dalloc<double>(2 * nL * C);
+    }
     w.nb_dot = 512;
     w.partial = c->dalloc<double>(static_cast<int64_t>(w.nb_dot) * 64);
     w.pp1 = c->dalloc<double>(static_cast<int64_t>(kPcgMaxBlocks) * 64);
@@ -410,7 +472,7 @@ static Work& work(msp_ctx* c, int C) {
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_scal), SC_COUNT * 64 * sizeof(double),
                            hipHostMallocDefault));
     c->works[C] = std::move(wp);
-    if (c->o.pc == MSP_PC_AMGR && !c->dl.empty()) {
+    if (amg(c) && !c->dl.empty()) {
         if (mixed(c)) autotune_level_splits<float>(c, w);
         else autotune_level_splits<double>(c, w);
     }
@@ -421,10 +483,19 @@ static Work& work(msp_ctx* c, int C) {
 template <typename T>
 static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T* s) {
     const int C = w.C;
+    const int S = 1 << c->sym.s;
     if (l + 1 == c->hier.lev.size()) {
-        const double bytes = 8.0 * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
-        timed(c, KD_DENSE, bytes, st,
-              [&] { HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s, w.dense_part)); });
+        if (c->sub && l > 0) {   // every subsystem's own coarsest operator
+            const double bytes = 8.0 * S * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
+            timed(c, KD_DENSE, bytes, st, [&] {
+                HIPCHECK(launch_dense_sets<T>(st, C, S, w.m, c->nL, c->d_cinv, y, s, static_cast<T*>(w.dense_pack),
+                                              w.dense_rows));
+            });
+        } else {
+            const double bytes = 8.0 * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
+            timed(c, KD_DENSE, bytes, st,
+                  [&] { HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s, w.dense_part)); });
+        }
         return;
     }
     const DevLevel& L = c->dl[l];
@@ -439,15 +510,20 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
             spmm<T>(c, kb + 1, st, C, L.G, v, t, nullptr, T(1), T(0));
             spmm<T>(c, kb + 2, st, C, L.GT, t, s, beta != T(0) ? s : nullptr, static_cast<T>(L.omega), beta);
         } else {
-            spmm<T>(c, kb + 1, st, C, L.M, v, s, beta != T(0) ? s : nullptr, T(1), beta);
+            spmm<T>(c, kb + 1, st, C, L.M, v, s, beta != T(0) ? s : nullptr, T(1), beta, nullptr, 1 << c->sym.s,
+                    w.m);
         }
     };
-    smooth(y, T(0));                                               // pre-smooth from zero: s = M y
-    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // r = y - A s
-    spmm<T>(c, kb + 3, st, C, L.R, r, yc, nullptr, T(1), T(0));    // r_c = P^T r
-    vcycle<T>(c, w, st, l + 1, yc, sc);                            // coarse correction
-    spmm<T>(c, kb + 4, st, C, L.P, sc, s, s, T(1), T(1));          // s += P h_c
-    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1));          // post-smooth: s += M (y - A s)
+    // per-subsystem hierarchy: the reduction level applies each subsystem's
+    // operator A_inn + diag(sigma_a); the levels below carry one value set per subsystem
+    const double* sg = !c->sub ? nullptr : (l == 0 ? c->d_sigma : (l == 1 ? c->d_sigma1 : nullptr));
+    const int m = w.m;
+    smooth(y, T(0));                                                     // pre-smooth from zero: s = M y
+    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1), sg, S, m);      // r = y - A s
+    spmm<T>(c, kb + 3, st, C, L.R, r, yc, nullptr, T(1), T(0), nullptr, S, m);   // r_c = P^T r
+    vcycle<T>(c, w, st, l + 1, yc, sc);                                  // coarse correction
+    spmm<T>(c, kb + 4, st, C, L.P, sc, s, s, T(1), T(1), nullptr, S, m);  // s += P h_c
+    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1), sg, S, m);      // post-smooth: s += M (y - A s)
     smooth(r, T(1));
 }
 
@@ -481,7 +557,7 @@ static void precondition_base(msp_ctx* c, Work& w, hipStream_t st, const double*
                               bool with_lrc_fsai) {
     const int C = w.C;
     const int64_t nb = c->sym.n_b;
-    if (c->o.pc == MSP_PC_AMGR) {
+    if (amg(c)) {
         if (mixed(c)) {
             float* y0 = static_cast<float*>(w.vy[0]);
             float* s0 = static_cast<float*>(w.vs[0]);
@@ -509,7 +585,7 @@ static void precondition_base(msp_ctx* c, Work& w, hipStream_t st, const double*
 // per-subsystem low-rank corrections.
 static void precondition(msp_ctx* c, Work& w, hipStream_t st, const double* r, double* z) {
     precondition_base(c, w, st, r, z, true);
-    if (c->d_U && c->o.pc == MSP_PC_AMGR) lrc_apply(c, w, st, r, z);
+    if (c->d_U && amg(c)) lrc_apply(c, w, st, r, z);
 }
 
 static void upload_all(msp_ctx* c) {
@@ -518,13 +594,40 @@ static void upload_all(msp_ctx* c) {
     c->d_img = c->upload(c->sym.img.data(), static_cast<int64_t>(c->sym.img.size()));
     c->d_sigma = c->upload(c->sym.sigma.data(), static_cast<int64_t>(c->sym.sigma.size()));
     c->dAinn = upload_csr(c, c->sym.Ainn, false);
-    if (c->o.pc == MSP_PC_AMGR) {
+    if (amg(c)) {
+        const int S = 1 << c->sym.s;
         c->dl.resize(c->hier.lev.size() - 1);
         for (size_t l = 0; l + 1 < c->hier.lev.size(); ++l) {
             const HostLevel& H = c->hier.lev[l];
             DevLevel& D = c->dl[l];
             D.n = H.A.nr;
             D.omega = H.omega;
+            if (c->sub && l > 0) {
+                // one value set per subsystem on the shared patterns; the smoother is
+                // explicit (omega_a G_a^T G_a) in every precision.  A_1,a = A_1 + diag(sigma_a)
+                // on the coarse interface points, so level 1 keeps the shared values and
+                // applies the outer diagonal like the reduction level does.
+                if (l == 1) {
+                    D.A = upload_csr(c, H.A, f32);
+                    std::vector<double> s1(static_cast<size_t>(H.A.nr) * S, 0.0);
+                    int64_t j = 0;
+                    const HostLevel& L0 = c->hier.lev[0];
+                    for (int64_t i = 0; i < L0.A.nr; ++i) {
+                        if (!L0.cf[i]) continue;
+                        if (c->sym.iface[i])
+                            for (int a = 0; a < S; ++a) s1[j * S + a] = c->sym.sigma[i * S + a];
+                        ++j;
+                    }
+                    if (j != H.A.nr) throw Error(MSP_ERR_ARG, "coarse numbering of the reduction level");
+                    c->d_sigma1 = c->upload(s1.data(), static_cast<int64_t>(s1.size()));
+                } else {
+                    D.A = upload_sets(c, H.A, c->subv.A[l], S, f32);
+                }
+                D.P = upload_sets(c, H.P, c->subv.P[l], S, f32);
+                D.R = upload_sets(c, H.R, c->subv.R[l], S, f32);
+                D.M = upload_sets(c, H.M, c->subv.M[l], S, f32);
+                continue;
+            }
             D.A = upload_csr(c, H.A, f32);
             D.P = upload_csr(c, H.P, f32);
             D.R = upload_csr(c, H.R, f32);
@@ -543,7 +646,8 @@ static void upload_all(msp_ctx* c) {
             }
         }
         c->nL = c->hier.lev.back().A.nr;
-        c->d_cinv = c->upload(c->hier.coarse_inv.data(), static_cast<int64_t>(c->hier.coarse_inv.size()));
+        const std::vector<double>& inv = c->sub ? c->subv.coarse_inv : c->hier.coarse_inv;
+        c->d_cinv = c->upload(inv.data(), static_cast<int64_t>(inv.size()));
     } else if (c->o.pc == MSP_PC_FSAI) {
         c->dGf = upload_csr(c, c->Gf, false);
         c->dGfT = upload_csr(c, transpose(c->Gf), false);
@@ -594,9 +698,9 @@ struct SolvePlan {
         active = w->iscal;
         iters = w->iscal + 64;
         flags = w->iscal + 128;
-        flexible = mixed(c) && c->o.pc == MSP_PC_AMGR;
+        flexible = mixed(c) && amg(c);
         nbp = pcg_grid(C, nb);
-        lrc_amg = c->d_U && c->o.pc == MSP_PC_AMGR;
+        lrc_amg = c->d_U && amg(c);
         kl = lrc_amg ? c->lrc_k : 0;
         O = S * kl * m;
     }
@@ -605,7 +709,7 @@ struct SolvePlan {
 
     // the mixed AMGR mode writes the FP32 V-cycle input in the update kernel
     float* y32() const {
-        return (c->o.pc == MSP_PC_AMGR && mixed(c)) ? static_cast<float*>(w->vy[0]) : nullptr;
+        return (amg(c) && mixed(c)) ? static_cast<float*>(w->vy[0]) : nullptr;
     }
 
     // <r,r>, U^T r and the convergence check (initial: the active flags)
@@ -632,7 +736,7 @@ struct SolvePlan {
     void precond_dot(bool init) {
         Work& W = *w;
         const float* s32 = nullptr;
-        if (c->o.pc == MSP_PC_AMGR && mixed(c)) {
+        if (amg(c) && mixed(c)) {
             float* y0 = static_cast<float*>(W.vy[0]);   // written by the update kernel
             float* s0 = static_cast<float*>(W.vs[0]);
             vcycle<float>(c, W, st, 0, y0, s0);
@@ -815,7 +919,7 @@ static int guarded(F&& f) {
 static void check_opts(const msp_opts* o) {
     if (!o) throw Error(MSP_ERR_ARG, "null options");
     if (o->precision < MSP_FP64 || o->precision > MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_ARG, "precision");
-    if (o->pc < MSP_PC_AMGR || o->pc > MSP_PC_NONE) throw Error(MSP_ERR_ARG, "pc");
+    if (o->pc < MSP_PC_AMGR || o->pc > MSP_PC_AMGR_SUB) throw Error(MSP_ERR_ARG, "pc");
     if (o->lrc_k < 0 || o->dist < 1 || o->jacobi0 < 1 || o->jacobi < 1 || o->coarse_max < 1 || o->max_levels < 1 ||
         !(o->theta >= 0.0) || !(o->tol > 0.0) || o->maxit < 0)
         throw Error(MSP_ERR_ARG, "invalid option value");
@@ -830,8 +934,12 @@ static std::unique_ptr<msp_ctx> setup_host(const msp_csr* A, const msp_symmap* m
     c->device = o->device;
     c->lrc_k = o->lrc_k;
     c->sym = msp::extract_blocks(A, map);
-    if (o->pc == MSP_PC_AMGR) {
+    if (o->pc == MSP_PC_AMGR || o->pc == MSP_PC_AMGR_SUB) {
         c->hier = msp::build_hierarchy(c->sym.Ainn, c->sym.iface, *o);
+        if (o->pc == MSP_PC_AMGR_SUB && c->hier.lev.size() > 1) {
+            c->subv = msp::build_sub_values(c->hier, c->sym.sigma, c->sym.iface, 1 << c->sym.s, *o);
+            c->sub = true;
+        }
     } else {
         c->hier.lev.emplace_back();
         c->hier.lev.back().A = c->sym.Ainn;
@@ -1127,6 +1235,23 @@ int msp_export_level(const msp_ctx* c, int32_t lev, int8_t* cf, int64_t* A_rp, i
     return MSP_OK;
 }
 
+int msp_export_sub_level(const msp_ctx* c, int32_t lev, int32_t a, double* A_v, double* P_v, double* G_v,
+                         double* omega) {
+    if (!c || !c->sub || lev < 1 || lev >= static_cast<int32_t>(c->hier.lev.size()) || a < 0 || a >= c->subv.S)
+        return MSP_ERR_ARG;
+    const int S = c->subv.S;
+    auto take = [&](const std::vector<double>& v, double* out) {
+        if (!out) return;
+        const size_t n = v.size() / S;
+        for (size_t k = 0; k < n; ++k) out[k] = v[k * S + a];
+    };
+    take(c->subv.A[lev], A_v);
+    take(c->subv.P[lev], P_v);
+    take(c->subv.G[lev], G_v);
+    if (omega) *omega = c->subv.omega[lev][a];
+    return MSP_OK;
+}
+
 int msp_export_outer(const msp_ctx* c, double* sigma, int8_t* iface) {
     if (!c) return MSP_ERR_ARG;
     if (sigma) std::copy(c->sym.sigma.begin(), c->sym.sigma.end(), sigma);
@@ -1255,7 +1380,7 @@ void build_lrc(msp_ctx* c) {
     const int64_t n = c->sym.n_b;
     const int K = static_cast<int>(std::min<int64_t>(std::max(4 * k, 40), n));
     const int C = next_pow2(S);
-    const bool amg = c->o.pc == MSP_PC_AMGR;
+    const bool amg = msp::amg(c);
     Work& w = work(c, C);
     w.m = 1;
     hipStream_t st = nullptr;

@@ -49,15 +49,17 @@ struct Lanes {
 
 // acc[e] += sum over k = k0, k0+step, ... < k1 of va[k] * X[ci[k], lane*VW + e],
 // accumulated in that order with four entries' loads in flight at a time.
-template <typename T, int C, int VW, typename TV = T>
+// With SETS the matrix carries vs interleaved value sets (value of entry k at
+// va[k * vs], va offset to the set used).
+template <typename T, int C, int VW, typename TV = T, bool SETS = false>
 __device__ __forceinline__ void row_accumulate(int32_t k0, int32_t k1, int step, const int32_t* __restrict__ ci,
                                                const TV* __restrict__ va, const T* __restrict__ X, int lane,
-                                               T* acc) {
+                                               T* acc, int vs = 1) {
+    auto val = [&](int32_t k) -> T { return cvt<T>(va[SETS ? (int64_t)k * vs : (int64_t)k]); };
     int32_t k = k0;
     for (; k + 3 * step < k1; k += 4 * step) {
         const int32_t c0 = ci[k], c1 = ci[k + step], c2 = ci[k + 2 * step], c3 = ci[k + 3 * step];
-        const T a0 = cvt<T>(va[k]), a1 = cvt<T>(va[k + step]), a2 = cvt<T>(va[k + 2 * step]),
-                a3 = cvt<T>(va[k + 3 * step]);
+        const T a0 = val(k), a1 = val(k + step), a2 = val(k + 2 * step), a3 = val(k + 3 * step);
         const Pack<T, VW> x0 = ld<T, VW>(X + (int64_t)c0 * C + lane * VW);
         const Pack<T, VW> x1 = ld<T, VW>(X + (int64_t)c1 * C + lane * VW);
         const Pack<T, VW> x2 = ld<T, VW>(X + (int64_t)c2 * C + lane * VW);
@@ -72,10 +74,37 @@ __device__ __forceinline__ void row_accumulate(int32_t k0, int32_t k1, int step,
     }
     for (; k < k1; k += step) {
         const Pack<T, VW> x = ld<T, VW>(X + (int64_t)ci[k] * C + lane * VW);
-        const T a = cvt<T>(va[k]);
+        const T a = val(k);
 #pragma unroll
         for (int e = 0; e < VW; ++e) acc[e] += a * x.e[e];
     }
+}
+
+// As row_accumulate with interleaved value sets where the VW columns of the
+// lane belong to different sets: column e uses va[k * vs + set[e]].
+template <typename T, int C, int VW, typename TV = T>
+__device__ __forceinline__ void row_accumulate_sets(int32_t k0, int32_t k1, int step,
+                                                    const int32_t* __restrict__ ci, const TV* __restrict__ va,
+                                                    const T* __restrict__ X, int lane, T* acc, int vs,
+                                                    const int* set) {
+    for (int32_t k = k0; k < k1; k += step) {
+        const Pack<T, VW> x = ld<T, VW>(X + (int64_t)ci[k] * C + lane * VW);
+        const TV* vk = va + (int64_t)k * vs;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] += cvt<T>(vk[set[e]]) * x.e[e];
+    }
+}
+
+// Multivector column -> value set: column c belongs to set c / vm (sets own vm
+// consecutive columns); padded columns use the last set.
+template <int VW>
+__device__ __forceinline__ bool column_sets(int lane, int vs, int vm, int* set) {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+        const int q = (lane * VW + e) / vm;
+        set[e] = q < vs ? q : vs - 1;
+    }
+    return set[0] == set[VW - 1];   // sets are nondecreasing in e
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD

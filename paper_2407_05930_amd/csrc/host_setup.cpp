@@ -577,6 +577,50 @@ void sym_eig(int n, std::vector<double> A, std::vector<double>& w, std::vector<d
 
 // ------------------------------------------------------------------ hierarchy
 
+// Dense inverse of a small SPD matrix: Cholesky A = L L^T, then Linv = L^{-1}
+// column by column and A^{-1} = Linv^T Linv (threads over columns).
+static std::vector<double> dense_inverse(const Csr& Ac) {
+    const int64_t nc = Ac.nr;
+    if (nc > 8192) throw Error(MSP_ERR_UNSUPPORTED, "coarsest level too large for a dense solve");
+    std::vector<double> M(nc * nc, 0.0);
+    for (int64_t i = 0; i < nc; ++i)
+        for (int64_t k = Ac.rp[i]; k < Ac.rp[i + 1]; ++k) M[i * nc + Ac.ci[k]] = Ac.v[k];
+    if (!cholesky(static_cast<int>(nc), M.data())) throw Error(MSP_ERR_NOT_SPD, "coarsest level is not SPD");
+    std::vector<int64_t> coff(nc + 1, 0);
+    for (int64_t c = 0; c < nc; ++c) coff[c + 1] = coff[c] + (nc - c);
+    std::vector<double> Li(coff[nc]);
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto parallel = [&](auto&& body) {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nth; ++t)
+            th.emplace_back([&, t]() {
+                for (int64_t c = t; c < nc; c += nth) body(c);
+            });
+        for (auto& x : th) x.join();
+    };
+    parallel([&](int64_t c) {
+        double* y = Li.data() + coff[c];   // y[i - c] = Linv[i][c], i >= c
+        for (int64_t i = c; i < nc; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            const double* Lr = M.data() + i * nc;
+            for (int64_t p = c; p < i; ++p) s -= Lr[p] * y[p - c];
+            y[i - c] = s / Lr[i];
+        }
+    });
+    std::vector<double> inv(nc * nc, 0.0);
+    parallel([&](int64_t i) {
+        const double* ci = Li.data() + coff[i];
+        for (int64_t j = i; j < nc; ++j) {
+            const double* cj = Li.data() + coff[j];
+            double s = 0.0;
+            for (int64_t p = j; p < nc; ++p) s += ci[p - i] * cj[p - j];
+            inv[i * nc + j] = s;
+            inv[j * nc + i] = s;
+        }
+    });
+    return inv;
+}
+
 HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o) {
     HostHierarchy H;
     Csr A = Ainn;
@@ -650,49 +694,100 @@ HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface,
         A = std::move(Ac);
         ++lev;
     }
-    // dense inverse of the coarsest operator: Cholesky A = L L^T, then
-    // Linv = L^{-1} column by column and A^{-1} = Linv^T Linv (threads over columns)
-    const HostLevel& Lc = H.lev.back();
-    const int64_t nc = Lc.A.nr;
-    if (nc > 8192) throw Error(MSP_ERR_UNSUPPORTED, "coarsest level too large for a dense solve");
-    std::vector<double> M(nc * nc, 0.0);
-    for (int64_t i = 0; i < nc; ++i)
-        for (int64_t k = Lc.A.rp[i]; k < Lc.A.rp[i + 1]; ++k) M[i * nc + Lc.A.ci[k]] = Lc.A.v[k];
-    if (!cholesky(static_cast<int>(nc), M.data())) throw Error(MSP_ERR_NOT_SPD, "coarsest level is not SPD");
-    // column c of Linv holds entries c..nc-1, stored contiguously
-    std::vector<int64_t> coff(nc + 1, 0);
-    for (int64_t c = 0; c < nc; ++c) coff[c + 1] = coff[c] + (nc - c);
-    std::vector<double> Li(coff[nc]);
-    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    auto parallel = [&](auto&& body) {
-        std::vector<std::thread> th;
-        for (unsigned t = 0; t < nth; ++t)
-            th.emplace_back([&, t]() {
-                for (int64_t c = t; c < nc; c += nth) body(c);
-            });
-        for (auto& x : th) x.join();
-    };
-    parallel([&](int64_t c) {
-        double* y = Li.data() + coff[c];   // y[i - c] = Linv[i][c], i >= c
-        for (int64_t i = c; i < nc; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            const double* Lr = M.data() + i * nc;
-            for (int64_t p = c; p < i; ++p) s -= Lr[p] * y[p - c];
-            y[i - c] = s / Lr[i];
-        }
-    });
-    H.coarse_inv.assign(nc * nc, 0.0);
-    parallel([&](int64_t i) {
-        const double* ci = Li.data() + coff[i];
-        for (int64_t j = i; j < nc; ++j) {
-            const double* cj = Li.data() + coff[j];
-            double s = 0.0;
-            for (int64_t p = j; p < nc; ++p) s += ci[p - i] * cj[p - j];
-            H.coarse_inv[i * nc + j] = s;
-            H.coarse_inv[j * nc + i] = s;
-        }
-    });
+    H.coarse_inv = dense_inverse(H.lev.back().A);
     return H;
+}
+
+static bool same_pattern(const Csr& X, const Csr& Y) { return X.rp == Y.rp && X.ci == Y.ci; }
+
+SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& sigma, const std::vector<int8_t>& iface,
+                           int S, const msp_opts& o) {
+    SubValues V;
+    V.S = S;
+    const int L = static_cast<int>(H.lev.size());
+    if (L < 2) return V;
+    V.A.assign(L, {});
+    V.P.assign(L, {});
+    V.R.assign(L, {});
+    V.M.assign(L, {});
+    V.G.assign(L, {});
+    V.omega.assign(L, std::vector<double>(S, 0.0));
+    for (int l = 1; l < L; ++l) {
+        V.A[l].assign(H.lev[l].A.nnz() * S, 0.0);
+        if (l + 1 < L) {
+            V.P[l].assign(H.lev[l].P.nnz() * S, 0.0);
+            V.R[l].assign(H.lev[l].R.nnz() * S, 0.0);
+            V.M[l].assign(H.lev[l].M.nnz() * S, 0.0);
+            V.G[l].assign(H.lev[l].G.nnz() * S, 0.0);
+        }
+    }
+    const int64_t nL = H.lev[L - 1].A.nr;
+    V.coarse_inv.assign(static_cast<size_t>(S) * nL * nL, 0.0);
+    // coarse numbers of the reduction level
+    const HostLevel& L0 = H.lev[0];
+    std::vector<int32_t> cnum(L0.A.nr, -1);
+    int32_t nc = 0;
+    for (int64_t i = 0; i < L0.A.nr; ++i)
+        if (L0.cf[i]) cnum[i] = nc++;
+    std::vector<std::string> errs(S);
+    auto one = [&](int a) {
+        Csr A = H.lev[1].A;
+        for (int64_t i = 0; i < L0.A.nr; ++i) {
+            if (!iface[i]) continue;
+            const int32_t j = cnum[i];
+            if (j < 0) throw Error(MSP_ERR_ARG, "interface point is not coarse");
+            const int32_t* b = A.ci.data() + A.rp[j];
+            const int32_t* e = A.ci.data() + A.rp[j + 1];
+            const int32_t* f = std::lower_bound(b, e, j);
+            if (f == e || *f != j) throw Error(MSP_ERR_ARG, "missing diagonal in the reduced operator");
+            double& d = A.v[f - A.ci.data()];
+            d = d + sigma[static_cast<size_t>(i) * S + a];
+        }
+        for (int l = 1; l < L; ++l) {
+            const HostLevel& Ls = H.lev[l];
+            for (int64_t k = 0; k < A.nnz(); ++k) V.A[l][k * S + a] = A.v[k];
+            if (l + 1 == L) break;
+            std::vector<std::vector<int32_t>> lower(A.nr);
+            for (int64_t i = 0; i < A.nr; ++i)
+                for (int64_t k = Ls.G.rp[i]; k < Ls.G.rp[i + 1]; ++k)
+                    if (Ls.G.ci[k] != i) lower[i].push_back(Ls.G.ci[k]);
+            Csr G = fsai_rows(A, lower);
+            Csr GT = transpose(G);
+            const double om = damping(A, G, GT, o.seed);
+            Csr P = interpolation(A, Ls.cf, o.jacobi);
+            Csr R = transpose(P);
+            Csr M = spgemm(GT, G);
+            for (double& v : M.v) v *= om;
+            if (!same_pattern(P, Ls.P) || !same_pattern(M, Ls.M) || !same_pattern(G, Ls.G))
+                throw Error(MSP_ERR_ARG, "subsystem level pattern differs from the shared level");
+            V.omega[l][a] = om;
+            for (int64_t k = 0; k < P.nnz(); ++k) V.P[l][k * S + a] = P.v[k];
+            for (int64_t k = 0; k < R.nnz(); ++k) V.R[l][k * S + a] = R.v[k];
+            for (int64_t k = 0; k < M.nnz(); ++k) V.M[l][k * S + a] = M.v[k];
+            for (int64_t k = 0; k < G.nnz(); ++k) V.G[l][k * S + a] = G.v[k];
+            Csr Anext = spgemm(R, spgemm(A, P));
+            if (!same_pattern(Anext, H.lev[l + 1].A))
+                throw Error(MSP_ERR_ARG, "subsystem reduced operator pattern differs from the shared one");
+            A = std::move(Anext);
+        }
+        const std::vector<double> inv = dense_inverse(A);
+        std::copy(inv.begin(), inv.end(), V.coarse_inv.begin() + static_cast<size_t>(a) * nL * nL);
+    };
+    std::vector<std::thread> th;
+    std::vector<int> codes(S, MSP_OK);
+    for (int a = 0; a < S; ++a)
+        th.emplace_back([&, a]() {
+            try {
+                one(a);
+            } catch (const Error& e) {
+                codes[a] = e.status;
+                errs[a] = e.what();
+            }
+        });
+    for (auto& t : th) t.join();
+    for (int a = 0; a < S; ++a)
+        if (codes[a] != MSP_OK) throw Error(codes[a], "subsystem " + std::to_string(a) + ": " + errs[a]);
+    return V;
 }
 
 }  // namespace msp

@@ -44,6 +44,22 @@ struct HostHierarchy {
     std::vector<double> coarse_inv;   // dense inverse of the coarsest A, row-major
 };
 
+// Per-subsystem values of the levels below the reduction (AMGR on every
+// decoupled subsystem): level l >= 1 of subsystem a has the patterns of the
+// shared level l (same C/F split and smoother pattern) and its own values.
+// Values are interleaved, entry k of subsystem a at [k * S + a].
+struct SubValues {
+    int S = 0;
+    std::vector<std::vector<double>> A, P, R, M, G;   // by level (index 0 unused)
+    std::vector<std::vector<double>> omega;           // by level, S values
+    std::vector<double> coarse_inv;                   // S blocks of nL x nL
+};
+
+// A_1,a = A_1,inn + diag(sigma_a on the interface coarse points), then the
+// standard levels with the shared splits and patterns.
+SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& sigma,
+                           const std::vector<int8_t>& iface, int S, const msp_opts& o);
+
 // Result of block extraction (Sec. 2).
 struct SymParts {
     int s = 0;

@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -20,12 +21,16 @@ namespace msp {
 // sigma[row * S + col / m] * X[row, col] (the per-subsystem outer diagonal of
 // eq. (2.11), one value per subsystem, broadcast over its m columns).
 // Y may alias Z (each lane reads its own Z elements before writing them).
-template <typename T, typename TV, int C>
+// With SETS the matrix holds vs interleaved value sets (entry k of set a at
+// va[k * vs + a]) and column c is multiplied by set min(c / m, vs - 1): one
+// pass applies a different operator of one sparsity pattern to every
+// subsystem's columns.
+template <typename T, typename TV, int C, bool SETS>
 __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ ci,
                                                  const TV* __restrict__ va, const T* __restrict__ X,
                                                  T* Y, const T* Z, T alpha, T beta,
-                                                 const double* __restrict__ sigma, int S, int m) {
+                                                 const double* __restrict__ sigma, int S, int m, int vs) {
     using L = Lanes<T, C>;
     constexpr int VW = L::VW;
     const int64_t row = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * L::RPB + threadIdx.x / L::LPR;
@@ -34,7 +39,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
     T acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = T(0);
-    row_accumulate<T, C, VW, TV>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc);
+    if constexpr (SETS) {
+        int set[VW];
+        if (column_sets<VW>(lane, vs, m, set))
+            row_accumulate<T, C, VW, TV, true>(rp[row], rp[row + 1], 1, ci, va + set[0], X, lane, acc, vs);
+        else
+            row_accumulate_sets<T, C, VW, TV>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc, vs, set);
+    } else {
+        row_accumulate<T, C, VW, TV>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc);
+    }
     if (sigma) {
         const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
 #pragma unroll
@@ -58,11 +71,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
 // Split-row SpMM for long rows (coarse levels): each row is shared by G lane
 // groups (G * LPR threads); group g accumulates entries k0 + g, k0 + g + G, ...
 // and the G partial rows are summed in LDS in a fixed order.
-template <typename T, typename TV, int C, int G>
+template <typename T, typename TV, int C, int G, bool SETS>
 __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        const TV* __restrict__ va, const T* __restrict__ X,
-                                                       T* Y, const T* Z, T alpha, T beta) {
+                                                       T* Y, const T* Z, T alpha, T beta, int vs, int m,
+                                                       const double* __restrict__ sigma, int S) {
     using L = Lanes<T, C>;
     constexpr int VW = L::VW;
     constexpr int TPR = G * L::LPR;             // threads per row
@@ -75,7 +89,17 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
     T acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = T(0);
-    if (row < n) row_accumulate<T, C, VW, TV>(rp[row] + g, rp[row + 1], G, ci, va, X, lane, acc);
+    if (row < n) {
+        if constexpr (SETS) {
+            int set[VW];
+            if (column_sets<VW>(lane, vs, m, set))
+                row_accumulate<T, C, VW, TV, true>(rp[row] + g, rp[row + 1], G, ci, va + set[0], X, lane, acc, vs);
+            else
+                row_accumulate_sets<T, C, VW, TV>(rp[row] + g, rp[row + 1], G, ci, va, X, lane, acc, vs, set);
+        } else {
+            row_accumulate<T, C, VW, TV>(rp[row] + g, rp[row + 1], G, ci, va, X, lane, acc);
+        }
+    }
 #pragma unroll
     for (int e = 0; e < VW; ++e) sm[threadIdx.x * VW + e] = acc[e];
     __syncthreads();
@@ -86,6 +110,14 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
         for (int q = 0; q < G; ++q) {
 #pragma unroll
             for (int e = 0; e < VW; ++e) acc[e] += sm[((slot * G + q) * L::LPR + lane) * VW + e];
+        }
+        if (sigma) {   // outer diagonal, as in k_spmm
+            const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                const int a = (lane * VW + e) / m;
+                if (a < S) acc[e] += (T)sigma[row * S + a] * x.e[e];
+            }
         }
         Pack<T, VW> out;
         if (Z) {
@@ -382,13 +414,95 @@ __global__ __launch_bounds__(kBlock) void k_dense_part(int64_t nL, int64_t kchun
     }
 }
 
+// yp[(a * nL + k) * MP + j] = y[k, a*m + j] (zero for j >= m): every
+// subsystem's m columns packed contiguously for the dense solves below.
+template <typename T, int MP>
+__global__ __launch_bounds__(kBlock) void k_pack_sets(int64_t nL, int C, int S, int m, const T* __restrict__ y,
+                                                      T* __restrict__ yp) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (int64_t)S * nL * MP) return;
+    const int j = (int)(idx % MP);
+    const int64_t ak = idx / MP;
+    const int a = (int)(ak / nL);
+    const int64_t k = ak % nL;
+    yp[idx] = j < m ? y[k * C + a * m + j] : T(0);
+}
+
+// Per-subsystem coarsest solves: out[:, a*m + j] = Minv_a y[:, a*m + j] for
+// subsystem a = blockIdx.y with its own inverse Minv + a * nL * nL.  With
+// only m columns per inverse this is a bandwidth-bound batched GEMV: each
+// wavefront owns R rows, its lanes walk k with stride 64 (every row read as
+// 512-byte coalesced segments, every entry of the inverses read once; the
+// right-hand sides come packed, MP values per k contiguous), and the per-lane
+// partial sums are reduced across the wave by a fixed butterfly.  Blocks of
+// the last subsystem also clear the padded columns >= S * m.
+template <typename T, int MP, int R>
+__global__ __launch_bounds__(kBlock) void k_dense_sets(int64_t nL, int C, int S, int m,
+                                                       const double* __restrict__ Minv, const T* __restrict__ yp,
+                                                       T* __restrict__ out) {
+    constexpr int W = 64;
+    constexpr int PW = (MP * (int)sizeof(T)) >= 16 ? 16 / (int)sizeof(T) : MP;   // values per packed load
+    const int wave = threadIdx.x / W, lane = threadIdx.x % W;
+    const int a = blockIdx.y;
+    const int64_t row0 = ((int64_t)blockIdx.x * (kBlock / W) + wave) * R;
+    if (row0 >= nL) return;   // the whole wavefront leaves together
+    const double* Ma = Minv + (int64_t)a * nL * nL;
+    const T* ya = yp + (int64_t)a * nL * MP;
+    double acc[R][MP];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < MP; ++j) acc[r][j] = 0.0;
+#pragma unroll 4
+    for (int64_t k = lane; k < nL; k += W) {
+        double xv[MP];
+#pragma unroll
+        for (int q = 0; q < MP; q += PW) {
+            const Pack<T, PW> v = ld<T, PW>(ya + k * MP + q);
+#pragma unroll
+            for (int e = 0; e < PW; ++e) xv[q + e] = (double)v.e[e];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double v = row0 + r < nL ? Ma[(row0 + r) * nL + k] : 0.0;
+#pragma unroll
+            for (int j = 0; j < MP; ++j) acc[r][j] += v * xv[j];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < MP; ++j) {
+            double v = acc[r][j];
+#pragma unroll
+            for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+            acc[r][j] = v;
+        }
+    // lane r * MP + j writes row r, column j (R * MP <= 64)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < MP; ++j)
+            if (lane == r * MP + j && j < m && row0 + r < nL) out[(row0 + r) * C + a * m + j] = (T)acc[r][j];
+    if (a == S - 1) {
+        const int pad = C - S * m;
+        for (int q = lane; q < R * pad; q += W) {
+            const int64_t i = row0 + q / pad;
+            if (i < nL) out[i * C + S * m + q % pad] = T(0);
+        }
+    }
+}
+
+// out[i] = sum over the ks chunks; columns >= ncol (never written by the
+// per-subsystem solve) are set to zero.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dense_sum(int64_t len, int ks, const double* __restrict__ part,
-                                                      T* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_dense_sum(int64_t len, int ks, int C, int ncol,
+                                                      const double* __restrict__ part, T* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= len) return;
     double s = 0.0;
-    for (int q = 0; q < ks; ++q) s += part[(int64_t)q * len + i];
+    if ((int)(i % C) < ncol)
+        for (int q = 0; q < ks; ++q) s += part[(int64_t)q * len + i];
     out[i] = (T)s;
 }
 
@@ -572,45 +686,69 @@ __global__ void k_gather_flags(int nsys, int* const* __restrict__ ptrs, int* __r
         default: return hipErrorInvalidValue;                    \
     }
 
+// value sets are supported for FP64 and FP32 values (not bfloat16)
+template <typename TV>
+constexpr bool sets_ok() {
+    return !std::is_same<TV, Bf16>::value;
+}
+
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
-                       const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m) {
+                       const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m, int vs) {
     if (n <= 0) return hipSuccess;
+    if (vs > 1 && (!sets_ok<TV>() || m < 1)) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         using L = Lanes<T, CC>;
-        hipLaunchKernelGGL((k_spmm<T, TV, CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp, ci, va, X,
-                           Y, Z, alpha, beta, sigma, S, m);
+        if constexpr (sets_ok<TV>()) {
+            if (vs > 1) {
+                hipLaunchKernelGGL((k_spmm<T, TV, CC, true>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp,
+                                   ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs);
+                break;
+            }
+        }
+        hipLaunchKernelGGL((k_spmm<T, TV, CC, false>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp, ci, va,
+                           X, Y, Z, alpha, beta, sigma, S, m, 1);
     });
     return hipGetLastError();
 }
 
 template <typename T, typename TV, int CC, int G>
 static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va, const T* X,
-                         T* Y, const T* Z, T alpha, T beta) {
+                         T* Y, const T* Z, T alpha, T beta, int vs, int m, const double* sigma, int S) {
     constexpr int TPR = G * Lanes<T, CC>::LPR;
     if constexpr (TPR <= kBlock) {
         constexpr int RPB = kBlock / TPR;
-        hipLaunchKernelGGL((k_spmm_split<T, TV, CC, G>), dim3(blocks_for(n, RPB)), dim3(kBlock), 0, st, n, rp, ci,
-                           va, X, Y, Z, alpha, beta);
+        if constexpr (sets_ok<TV>()) {
+            if (vs > 1) {
+                hipLaunchKernelGGL((k_spmm_split<T, TV, CC, G, true>), dim3(blocks_for(n, RPB)), dim3(kBlock), 0, st,
+                                   n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_spmm_split<T, TV, CC, G, false>), dim3(blocks_for(n, RPB)), dim3(kBlock), 0, st, n, rp,
+                           ci, va, X, Y, Z, alpha, beta, 1, m, sigma, S);
     }
 }
 
 template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
-                             const TV* va, const T* X, T* Y, const T* Z, T alpha, T beta) {
+                             const TV* va, const T* X, T* Y, const T* Z, T alpha, T beta, int vs, int m,
+                             const double* sigma, int S) {
     if (n <= 0) return hipSuccess;
+    if ((vs > 1 || sigma) && m < 1) return hipErrorInvalidValue;
+    if (vs > 1 && !sets_ok<TV>()) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         constexpr int LPR = Lanes<T, CC>::LPR;
         const int gmax = kBlock / LPR;
         const int g = G < gmax ? G : gmax;
         switch (g) {
-            case 2: launch_split<T, TV, CC, 2>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 4: launch_split<T, TV, CC, 4>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 8: launch_split<T, TV, CC, 8>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 16: launch_split<T, TV, CC, 16>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 32: launch_split<T, TV, CC, 32>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            case 64: launch_split<T, TV, CC, 64>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
-            default: launch_split<T, TV, CC, 1>(st, n, rp, ci, va, X, Y, Z, alpha, beta); break;
+            case 2: launch_split<T, TV, CC, 2>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
+            case 4: launch_split<T, TV, CC, 4>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
+            case 8: launch_split<T, TV, CC, 8>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
+            case 16: launch_split<T, TV, CC, 16>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
+            case 32: launch_split<T, TV, CC, 32>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
+            case 64: launch_split<T, TV, CC, 64>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
+            default: launch_split<T, TV, CC, 1>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
         }
     });
     return hipGetLastError();
@@ -618,9 +756,10 @@ hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int3
 
 #define MSP_SPMM_INST(T, TV)                                                                                         \
     template hipError_t launch_spmm<T, TV>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const TV*,     \
-                                           const T*, T*, const T*, T, T, const double*, int, int);                   \
+                                           const T*, T*, const T*, T, T, const double*, int, int, int);              \
     template hipError_t launch_spmm_split<T, TV>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,     \
-                                                 const TV*, const T*, T*, const T*, T, T);
+                                                 const TV*, const T*, T*, const T*, T, T, int, int, const double*, \
+                                                 int);
 MSP_SPMM_INST(double, double)
 MSP_SPMM_INST(float, float)
 MSP_SPMM_INST(float, Bf16)
@@ -741,13 +880,70 @@ hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, c
         using L = Lanes<T, CC>;
         hipLaunchKernelGGL((k_dense_part<T, CC>), dim3(blocks_for(nL, L::RPB), ks), dim3(kBlock), 0, st, nL, kchunk,
                            Minv, y, part);
-        hipLaunchKernelGGL((k_dense_sum<T>), dim3(blocks_for(nL * CC, kBlock)), dim3(kBlock), 0, st, nL * CC, ks, part,
-                           out);
+        hipLaunchKernelGGL((k_dense_sum<T>), dim3(blocks_for(nL * CC, kBlock)), dim3(kBlock), 0, st, nL * CC, ks, CC,
+                           CC, part, out);
     });
     return hipGetLastError();
 }
 template hipError_t launch_dense<double>(hipStream_t, int, int64_t, const double*, const double*, double*, double*);
 template hipError_t launch_dense<float>(hipStream_t, int, int64_t, const double*, const float*, float*, double*);
+
+static int pow2_at_least(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+template <typename T, int MP, int R>
+static void launch_dense_sets_r(hipStream_t st, int C, int S, int m, int64_t nL, const double* Minv, const T* yp,
+                                T* out) {
+    if constexpr (R * MP <= 64) {
+        const int64_t rows_per_block = (int64_t)(kBlock / 64) * R;
+        hipLaunchKernelGGL((k_dense_sets<T, MP, R>), dim3(blocks_for(nL, (int)rows_per_block), S), dim3(kBlock), 0,
+                           st, nL, C, S, m, Minv, yp, out);
+    }
+}
+
+template <typename T, int MP>
+static void launch_dense_sets_mp(hipStream_t st, int C, int S, int m, int64_t nL, const double* Minv, const T* y,
+                                 T* out, T* yp, int R) {
+    hipLaunchKernelGGL((k_pack_sets<T, MP>), dim3(blocks_for((int64_t)S * nL * MP, kBlock)), dim3(kBlock), 0, st, nL,
+                       C, S, m, y, yp);
+    switch (R) {
+        case 8: launch_dense_sets_r<T, MP, 8>(st, C, S, m, nL, Minv, yp, out); break;
+        case 4: launch_dense_sets_r<T, MP, 4>(st, C, S, m, nL, Minv, yp, out); break;
+        case 2: launch_dense_sets_r<T, MP, 2>(st, C, S, m, nL, Minv, yp, out); break;
+        default: launch_dense_sets_r<T, MP, 1>(st, C, S, m, nL, Minv, yp, out); break;
+    }
+}
+
+int dense_sets_rows_max(int m) {
+    const int mp = pow2_at_least(m);
+    return mp <= 8 ? 8 : 64 / mp;
+}
+
+template <typename T>
+hipError_t launch_dense_sets(hipStream_t st, int C, int S, int m, int64_t nL, const double* Minv, const T* y,
+                             T* out, T* yp, int R) {
+    if (S * m > C || m < 1 || m > 64 || S < 1) return hipErrorInvalidValue;
+    if (R != 1 && R != 2 && R != 4 && R != 8) return hipErrorInvalidValue;
+    if (R > dense_sets_rows_max(m)) R = dense_sets_rows_max(m);
+    if (nL <= 0) return hipSuccess;
+    switch (pow2_at_least(m)) {
+        case 1: launch_dense_sets_mp<T, 1>(st, C, S, m, nL, Minv, y, out, yp, R); break;
+        case 2: launch_dense_sets_mp<T, 2>(st, C, S, m, nL, Minv, y, out, yp, R); break;
+        case 4: launch_dense_sets_mp<T, 4>(st, C, S, m, nL, Minv, y, out, yp, R); break;
+        case 8: launch_dense_sets_mp<T, 8>(st, C, S, m, nL, Minv, y, out, yp, R); break;
+        case 16: launch_dense_sets_mp<T, 16>(st, C, S, m, nL, Minv, y, out, yp, R); break;
+        case 32: launch_dense_sets_mp<T, 32>(st, C, S, m, nL, Minv, y, out, yp, R); break;
+        default: launch_dense_sets_mp<T, 64>(st, C, S, m, nL, Minv, y, out, yp, R); break;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_dense_sets<double>(hipStream_t, int, int, int, int64_t, const double*, const double*,
+                                              double*, double*, int);
+template hipError_t launch_dense_sets<float>(hipStream_t, int, int, int, int64_t, const double*, const float*,
+                                             float*, float*, int);
 
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {

@@ -14,14 +14,17 @@ struct Bf16 {
 };
 
 // Y = alpha (A X [+ outer diagonal]) + beta Z with matrix values of type TV
-// (TV = T, or Bf16 with T = float) and multivectors of type T.
+// (TV = T, or Bf16 with T = float) and multivectors of type T.  vs > 1: the
+// matrix holds vs interleaved value sets (entry k of set a at va[k*vs + a],
+// FP64/FP32 values only) and column c uses set min(c / m, vs - 1).
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
-                       const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m);
+                       const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m, int vs);
 // Same product for long rows: G lane groups share each row (G a power of two).
 template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
-                             const TV* va, const T* X, T* Y, const T* Z, T alpha, T beta);
+                             const TV* va, const T* X, T* Y, const T* Z, T alpha, T beta, int vs, int m,
+                             const double* sigma, int S);
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
                       double* out);
@@ -52,6 +55,14 @@ hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, co
 int dense_splits(int C, int64_t nL, bool fp32);
 template <typename T>
 hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part);
+// Per-subsystem coarsest solves: columns a*m .. a*m + m - 1 times Minv + a*nL*nL
+// (S inverses); columns >= S*m of out are zero.  yp: scratch of S * nL * MP
+// values, MP = m rounded up to a power of two (at most 2 * nL * C).  R: rows
+// per wavefront (1, 2, 4 or 8; capped at dense_sets_rows_max(m)).
+int dense_sets_rows_max(int m);
+template <typename T>
+hipError_t launch_dense_sets(hipStream_t st, int C, int S, int m, int64_t nL, const double* Minv, const T* y,
+                             T* out, T* yp, int R);
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v);
 template <typename TO, typename TI>

@@ -42,7 +42,7 @@ class Solver:
     indptr/indices/data) and the symmetry map ``img`` (n_b x 2^s, row of
     image a of base cell i); options as in ``msp_opts`` (``k`` = LRC rank,
     ``precision`` in {"fp64", "mixed", "mixed_bf16g"}, ``pc`` in
-    {"amgr", "fsai", "none"}, ``device`` = -1 for a host-only setup)."""
+    {"amgr", "fsai", "none", "amgr_sub"}, ``device`` = -1 for a host-only setup)."""
 
     def __init__(self, A, img, **opts):
         img = np.ascontiguousarray(img, dtype=np.int64)
@@ -134,6 +134,30 @@ class Solver:
             out["cf"] = cf.astype(bool)
             out["P"] = sp.csr_matrix((Pv, Pci, Prp), shape=(n, nc))
             out["G"] = sp.csr_matrix((Gv, Gci, Grp), shape=(n, n))
+        return out
+
+    def export_sub_level(self, lev: int, a: int) -> dict:
+        """pc = "amgr_sub": level ``lev`` >= 1 of subsystem ``a`` -- A, P, G on
+        the shared level's patterns (scipy CSR) with this subsystem's values,
+        and its damping."""
+        shared = self.export_level(lev)
+        vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        Av = np.zeros(shared["A"].nnz)
+        Pv = np.zeros(shared["P"].nnz) if "P" in shared else None
+        Gv = np.zeros(shared["G"].nnz) if "G" in shared else None
+        om = ctypes.c_double()
+        check(lib.msp_export_sub_level(self._ctx, lev, a, vp(Av), vp(Pv) if Pv is not None else None,
+                                       vp(Gv) if Gv is not None else None, ctypes.byref(om)))
+        import scipy.sparse as sp
+
+        def like(M, v):
+            return sp.csr_matrix((v, M.indices.copy(), M.indptr.copy()), shape=M.shape)
+
+        out = dict(A=like(shared["A"], Av), omega=om.value)
+        if Pv is not None:
+            out["cf"] = shared["cf"]
+            out["P"] = like(shared["P"], Pv)
+            out["G"] = like(shared["G"], Gv)
         return out
 
     def export_outer(self):

@@ -130,3 +130,53 @@ def test_library_assembly_matches_generator(kw):
     assert A.shape == p.A.shape
     assert np.array_equal(A.indptr, p.A.indptr) and np.array_equal(A.indices, p.A.indices)
     assert np.abs(A.data - p.A.data).max() <= 1e-15 * np.abs(p.A.data).max()
+
+
+@pytest.mark.parametrize("case", [
+    dict(N=(32, 32, 32), s=3, kw=dict(jitter=0.2, kappa="lognormal"), opt=dict(coarse_max=64)),
+    dict(N=(48, 40, 32), s=2, kw=dict(y_stretch=1.5), opt=dict(coarse_max=100)),
+])
+def test_subsystem_hierarchy_matches_oracle(case):
+    """AMGR per subsystem: the library's per-subsystem values on the shared
+    patterns equal the oracle's subsystem hierarchies level by level."""
+    p = make_problem(case["N"], s=case["s"], seed=2, **case["kw"])
+    sv = _setup(p, pc="amgr_sub", **case["opt"])
+    ctx = krylov.setup(p.A, p.img, amg.AMGOptions(**case["opt"]), precond="amgr_sub")
+    SH = ctx["sub"]
+    H = ctx["hier"]
+    assert sv.num_levels() == H.nlev >= 3
+    for a in range(1 << p.s):
+        # Rescaling an interpolation row to the direct row sum divides by the
+        # sum of its weights; where they nearly cancel, rounding differences in
+        # the summation order grow by sum|w| / |sum w|, and so do all values
+        # computed from that level on.  The bound follows that factor.
+        amp = 1.0
+        for lev in range(1, H.nlev):
+            e = sv.export_sub_level(lev, a)
+            L = SH.subs[a].levels[lev - 1]
+            tol = 1e-13 * amp
+            assert np.array_equal(e["A"].indices, L.A.indices) and np.array_equal(e["A"].indptr, L.A.indptr)
+            assert np.abs(e["A"].data - L.A.data).max() <= tol * np.abs(L.A.data).max()
+            if L.P is not None:
+                W = abs(L.P)
+                cancel = np.asarray(W.sum(axis=1)).ravel() / np.maximum(
+                    np.abs(np.asarray(L.P.sum(axis=1)).ravel()), 1e-300)
+                amp = max(amp, float(cancel.max()))
+                for key in ("P", "G"):
+                    M1, M2 = e[key], getattr(L, key)
+                    assert np.array_equal(M1.indices, M2.indices) and np.array_equal(M1.indptr, M2.indptr)
+                    assert np.abs(M1.data - M2.data).max() <= 1e-13 * amp * np.abs(M2.data).max()
+                assert abs(e["omega"] - L.omega) <= 1e-10 * L.omega
+
+
+def test_subsystem_export_rejects_other_modes():
+    from paper_2407_05930_amd._lib import MspError
+    p = make_problem((16, 16, 16), s=3, seed=2)
+    sv = _setup(p, coarse_max=40)
+    with pytest.raises(MspError):
+        sv.export_sub_level(1, 0)
+    sv2 = _setup(p, pc="amgr_sub", coarse_max=40)
+    with pytest.raises(MspError):
+        sv2.export_sub_level(0, 0)
+    with pytest.raises(MspError):
+        sv2.export_sub_level(1, 8)
