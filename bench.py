@@ -114,7 +114,7 @@ def bench_jitter(args, torch, np):
     b = torch.from_numpy(p.b).cuda()
     out = {}
     for prec in ("fp64", "mixed", "mixed_bf16g"):
-        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=args.k)
+        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=args.k, pc=args.pc)
         t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
         xs = x.cpu().numpy()
         rr = float(np.max(np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)))
@@ -128,7 +128,7 @@ def bench_jitter(args, torch, np):
     return {"metric": "solve time to 1e-10 rel-res, 192^3 jittered s=3, k=16", "value": out["mixed_bf16g"]["solve_s"],
             "unit": "s", "higher_is_better": False, "dtype": "f64+f32+bf16",
             "config": {"workload": "jitter3d_192_s3", "grid": list(p.N), "s": 3, "rhs": 1, "lrc_k": args.k,
-                       "unknowns": int(p.n)}, "variants": out}
+                       "unknowns": int(p.n), "preconditioner": args.pc}, "variants": out}
 
 
 def bench_batch(args, torch, np):
@@ -140,7 +140,7 @@ def bench_batch(args, torch, np):
     probs = batch_problems(64)
     bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
     t0 = time.perf_counter()
-    bsol = BatchSolver([(pr.A, pr.img) for pr in probs], tol=1e-10, precision="mixed")
+    bsol = BatchSolver([(pr.A, pr.img) for pr in probs], tol=1e-10, precision="mixed", pc=args.pc)
     t_setup = time.perf_counter() - t0
     for _ in range(args.warmup):
         bsol.solve(bs)
@@ -159,7 +159,7 @@ def bench_batch(args, torch, np):
     bsol.close()
     # the same systems one after another, one context each (no batching)
     from paper_2407_05930_amd import Solver
-    sols = [Solver(pr.A, pr.img, tol=1e-10, precision="mixed") for pr in probs]
+    sols = [Solver(pr.A, pr.img, tol=1e-10, precision="mixed", pc=args.pc) for pr in probs]
     for sv, b in zip(sols, bs):
         sv.solve(b)
     torch.cuda.synchronize()
@@ -174,7 +174,7 @@ def bench_batch(args, torch, np):
     return {"metric": "batched solve time to 1e-10 rel-res, 64 uneven systems", "value": round(t, 6), "unit": "s",
             "higher_is_better": False, "dtype": "f64+f32",
             "config": {"workload": "batch64", "systems": len(probs), "unknowns": int(sum(pr.n for pr in probs)),
-                       "rhs_total": int(sum(pr.b.shape[1] for pr in probs))},
+                       "rhs_total": int(sum(pr.b.shape[1] for pr in probs)), "preconditioner": args.pc},
             "iters_min_max": [min(its), max(its)], "true_relres_max": worst, "setup_s": round(t_setup, 2),
             "unknown_rhs_per_s": round(unk / t, 1), "sequential_single_solves_s": round(t_seq, 6),
             "batch_speedup_vs_sequential": round(t_seq / t, 3)}
@@ -188,7 +188,7 @@ def bench_adjoint(args, torch, np):
     log("building workload adjoint3d_256_s3 (geometry only)")
     pr = config_problem("adjoint3d_256_s3", assemble=False)
     t0 = time.perf_counter()
-    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-10)
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-10, pc=args.pc)
     f = torch.from_numpy(pr.b).cuda()
     pst = torch.from_numpy(pr.p_target[:, None]).cuda()
     kap = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
@@ -209,7 +209,8 @@ def bench_adjoint(args, torch, np):
     t = sum(times) / len(times)
     return {"metric": "forward + adjoint solve time, 256^3 s=3 lognormal kappa", "value": round(t, 6), "unit": "s",
             "higher_is_better": False, "dtype": "f64",
-            "config": {"workload": "adjoint3d_256_s3", "grid": list(pr.N), "s": 3, "unknowns": int(pr.n)},
+            "config": {"workload": "adjoint3d_256_s3", "grid": list(pr.N), "s": 3, "unknowns": int(pr.n),
+                       "preconditioner": args.pc},
             "iters": dp.solver.last.iters, "setup_s": round(t_setup, 2), "loss": float(loss.item()),
             "grad_kappa_norm": float(kap.grad.norm().item()), "grad_f_norm": float(fr.grad.norm().item())}
 

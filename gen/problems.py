@@ -25,7 +25,7 @@ Ordering conventions
 * image ``a`` (0 <= a < 2^s) reflects axis t (``i -> N_t-1-i``) when bit t of
   ``a`` is set; image 0 is the base mesh;
 * "mirrored" global ordering: row ``a*n_b + beta`` (the ordering of the
-  paper's block structure, eq. (2.2)/(2.4));
+  paper's block structure, eqs. (2.2)-(2.5));
 * "natural" global ordering: lexicographic ``i + Nx*(j + Ny*k)`` over the
   full grid.  ``img[beta, a]`` gives the global row of image a of base cell
   beta in whichever ordering the matrix is returned in.
@@ -85,7 +85,7 @@ class Problem:
 
 
 def tanh_nodes(N: int, gamma: float) -> np.ndarray:
-    """Node coordinates of the hyperbolic stretching law of Sec. 2 (eq. (2.23)),
+    """Node coordinates of the hyperbolic stretching law of Sec. 2 (eq. (2.26)),
     written 0-based: y_j = (1 + tanh(gamma (2j/N - 1)) / tanh(gamma)) / 2."""
     j = np.arange(N + 1, dtype=np.float64)
     return 0.5 * (1.0 + np.tanh(gamma * (2.0 * j / N - 1.0)) / np.tanh(gamma))
@@ -256,7 +256,7 @@ def transmissibility(faces: BaseFaces, kappa_base: np.ndarray) -> np.ndarray:
 
 
 def base_blocks(faces: BaseFaces, T: np.ndarray, n_b: int, s: int):
-    """The base-mesh blocks H_j (Sec. 2, eq. (2.4) and the text after it):
+    """The base-mesh blocks H_j (Sec. 2, eqs. (2.4)-(2.5) and the text after them):
     H_0 couples the base mesh with itself, H_{2^t} with its reflection about
     plane t (diagonal, one entry per cell touching that plane); all other H_j
     are zero for a two-point stencil.  Returns {j: csr}."""
@@ -299,7 +299,7 @@ def _natural_index(N, s, B, n_b):
 
 def assemble_full(H: dict, n_b: int, s: int) -> sp.csr_matrix:
     """Full matrix in mirrored ordering from the base blocks: block (a, b) is
-    H_{a xor b} (eq. (2.4) generalised to 2^s subdomains)."""
+    H_{a xor b} (eqs. (2.4)-(2.5) generalised to 2^s subdomains)."""
     S = 1 << s
     out = None
     for j, Hj in H.items():

@@ -10,11 +10,11 @@
  *     passes the full matrix and the symmetry map; the library extracts the
  *     base-mesh blocks H_j, checks the block structure "block (a,b) of A =
  *     H_{a xor b}" bit for bit, keeps only the shared inner block
- *     A_inn = H_0 plus the per-subsystem outer part (eq. (2.11)), and builds
+ *     A_inn = H_0 plus the per-subsystem outer part (eq. (2.14)), and builds
  *     one preconditioner shared by all 2^s subsystems: the multigrid
- *     reduction hierarchy of Sec. 3.2 (Alg. 2, eqs. (3.11)-(3.13)) on A_inn,
- *     or the FSAI of A_inn (eq. (2.15)), optionally with per-subsystem
- *     low-rank corrections (LRCAMG(k), eq. (2.27); LRCFSAI(k), eq. (2.20)).
+ *     reduction hierarchy of Sec. 3.2 (Alg. 2, eqs. (3.13)-(3.15)) on A_inn,
+ *     or the FSAI of A_inn (eq. (2.17)), optionally with per-subsystem
+ *     low-rank corrections (LRCAMG(k), eq. (2.32); LRCFSAI(k), eq. (2.24)).
  *   solve (Alg. 1): bhat = Q_s b, decoupled PCG on every subsystem and
  *     right-hand side with the shared preconditioner applied to all
  *     2^s * m columns at once (SpMM, eqs. (2.7)-(2.8)), x = Q_s xhat.
@@ -62,11 +62,11 @@ typedef enum {
    smoother is applied factored, G^T (G r), which keeps it SPD. */
 enum { MSP_FP64 = 0, MSP_MIXED_FP32 = 1, MSP_MIXED_FP32_BF16G = 2 };
 /* Preconditioners of the decoupled subsystems A_a = A_inn + diag(sigma_a)
-   (Sec. 2, eqs. (2.8)-(2.11)):
+   (Sec. 2, eqs. (2.13)-(2.14)):
    MSP_PC_AMGR: the AMGR hierarchy of A_inn (Sec. 3.2, Alg. 2 and 3) shared by
      every subsystem, applied to all columns at once; low-rank corrections per
-     subsystem on top (LRCAMG(k), eq. (2.20)).
-   MSP_PC_FSAI: FSAI of A_inn with LRCFSAI(k) corrections (eq. (2.27)).
+     subsystem on top (LRCAMG(k), eq. (2.32)).
+   MSP_PC_FSAI: FSAI of A_inn with LRCFSAI(k) corrections (eq. (2.24)).
    MSP_PC_NONE: plain CG.
    MSP_PC_AMGR_SUB: AMGR of every subsystem A_a (Sec. 3.2 applied to each
      decoupled system).  The reduction level is shared: its C/F split forces

@@ -10,10 +10,10 @@ symmetries") written with NumPy/SciPy primitives.
 Modules
   splitmix   the counter-based hash used for all pseudo-random choices
   symmetry   Sec. 2: base blocks H_j, the change of basis Q_s, the decoupled
-             subsystems (eqs. (2.4)-(2.11)) and Alg. 1
+             subsystems (eqs. (2.4)-(2.14)) and Alg. 1
   amg        Sec. 3.2: strength, Alg. 2 populated coarsening, the reduction
-             prolongation (eq. (3.11)), the block-FSAI top smoother
-             (eq. (3.12)), the reduced operator (eq. (3.13)), standard AMG
+             prolongation (eq. (3.15)), the block-FSAI top smoother
+             (eq. (3.14)), the reduced operator (eq. (3.15)), standard AMG
              levels below it and the V-cycle of Alg. 3
   krylov     per-column PCG for the decoupled systems of Alg. 1
   lrc        Sec. 2.1/2.2: low-rank corrections (LRCFSAI(k), LRCAMG(k)),

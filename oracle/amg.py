@@ -13,10 +13,10 @@ listed with its reason in the design notes):
     (number of strong dependants, then hash);
   * interpolation: the ideal interpolation -A_FF^{-1} A_FC truncated after a
     few Jacobi steps, with symbolic patterns, rows rescaled to the direct
-    interpolation row sum; P = [W; I] (eq. (3.11));
+    interpolation row sum; P = [W; I] (eq. (3.13));
   * smoother: static-pattern FSAI, block-diagonal over F/C at level 0
-    (eq. (3.12)), damped by 4/(3 lambda_max(G A G^T));
-  * reduced operator A_c = P^T A P (eq. (3.13)), symbolic pattern;
+    (eq. (3.14)), damped by 4/(3 lambda_max(G A G^T));
+  * reduced operator A_c = P^T A P (eq. (3.15)), symbolic pattern;
   * coarsest level: dense Cholesky.
 """
 from __future__ import annotations
@@ -224,7 +224,7 @@ def coarsen_standard(A: sp.csr_matrix, level: int, theta: float, seed: int,
 
 
 # ---------------------------------------------------------------------------
-# interpolation, P = [W; I] (eq. (3.11))
+# interpolation, P = [W; I] (eq. (3.13))
 # ---------------------------------------------------------------------------
 
 def interpolation(A: sp.csr_matrix, C: np.ndarray, steps: int) -> sp.csr_matrix:
@@ -288,7 +288,7 @@ def interpolation(A: sp.csr_matrix, C: np.ndarray, steps: int) -> sp.csr_matrix:
 
 
 def galerkin(A: sp.csr_matrix, P: sp.csr_matrix) -> sp.csr_matrix:
-    """Reduced operator A_c = P^T A P (eq. (3.13)), symbolic pattern,
+    """Reduced operator A_c = P^T A P (eq. (3.15)), symbolic pattern,
     computed as R (A P) with R = P^T."""
     R = P.T.tocsr()
     R.sort_indices()
@@ -297,7 +297,7 @@ def galerkin(A: sp.csr_matrix, P: sp.csr_matrix) -> sp.csr_matrix:
 
 
 # ---------------------------------------------------------------------------
-# FSAI smoother (eq. (2.15) factor; block form eq. (3.12))
+# FSAI smoother (eq. (2.17) factor; block form eq. (3.14))
 # ---------------------------------------------------------------------------
 
 def fsai_pattern(S: sp.csr_matrix, block: np.ndarray):

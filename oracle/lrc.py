@@ -1,5 +1,5 @@
-"""Low-rank corrections of Sec. 2.1 (LRCFSAI(k), eq. (2.20)) and Sec. 2.2
-(LRCAMG(k), eq. (2.27)), per decoupled subsystem.
+"""Low-rank corrections of Sec. 2.1 (LRCFSAI(k), eq. (2.24)) and Sec. 2.2
+(LRCAMG(k), eq. (2.32)), per decoupled subsystem.
 
 LRCAMG in symmetric form.  With M^{-1} the shared V-cycle and
 X_a = M^{-1} A_a (self-adjoint in the A_a inner product), let (lam_j, u_j)
@@ -136,7 +136,7 @@ def fsai_inner(Ainn: sp.csr_matrix) -> sp.csr_matrix:
 
 def build_lrcfsai(G: sp.csr_matrix, Ainn: sp.csr_matrix, outs, k: int, seed: int,
                   keep_all: bool = False, steps: int = None) -> LowRank:
-    """LRCFSAI(k) per subsystem (eq. (2.18)-(2.20)): Lanczos on X_a = G A_a G^T
+    """LRCFSAI(k) per subsystem (eqs. (2.18)-(2.24)): Lanczos on X_a = G A_a G^T
     (Euclidean), k smallest Ritz pairs (lam, v); Z = G^T v, coefficient
     Theta = 1/lam - 1 (pairs with lam >= 1 carry a non-positive coefficient
     and are dropped, keeping the correction positive semidefinite)."""
@@ -157,5 +157,5 @@ def build_lrcfsai(G: sp.csr_matrix, Ainn: sp.csr_matrix, outs, k: int, seed: int
 
 
 def fsai_apply(G: sp.csr_matrix, R: np.ndarray) -> np.ndarray:
-    """z = G^T G r (the FSAI preconditioner of eq. (2.15))."""
+    """z = G^T G r (the FSAI preconditioner of eq. (2.17))."""
     return G.T @ (G @ R)

@@ -4,7 +4,7 @@ Q_s and the decoupled subsystems; Alg. 1.
 Conventions: ``img[i, a]`` is the row (in the caller's ordering) of image a of
 base cell i; bit t of ``a`` means "reflected about mirror plane t", so images
 compose by XOR.  The mirrored ordering puts image a's cells in block a
-(rows a*n_b .. a*n_b + n_b - 1), as in eq. (2.1)/(2.4).
+(rows a*n_b .. a*n_b + n_b - 1), as in eqs. (2.1) and (2.4)-(2.5).
 """
 from __future__ import annotations
 
@@ -49,7 +49,7 @@ def check_map(img: np.ndarray, n: int) -> None:
 
 
 def base_blocks(A: sp.csr_matrix, img: np.ndarray):
-    """Blocks H_j (eq. (2.4) generalised): H_j couples the base mesh (image 0)
+    """Blocks H_j (eqs. (2.4)-(2.5) generalised): H_j couples the base mesh (image 0)
     with image j.  Checks, exactly, that block (a, b) of the mirrored matrix
     equals H_{a xor b} and that A is symmetric.  Exact zeros are dropped.
     Returns {j: csr (n_b x n_b)}."""
@@ -72,7 +72,7 @@ def base_blocks(A: sp.csr_matrix, img: np.ndarray):
 
 
 def q_matrix(s: int, n_b: int) -> sp.csr_matrix:
-    """Q_s of eq. (2.9): the product over i = 1..s of
+    """Q_s of eq. (2.12): the product over i = 1..s of
     I_{2^{i-1}} (x) (1/sqrt2)[[1,1],[1,-1]] (x) I_{n/2^i}.  Written out as
     that product of sparse factors."""
     n = n_b << s
@@ -99,7 +99,7 @@ def subsystem(H: dict, a: int) -> sp.csr_matrix:
 
 
 def inner_outer(H: dict):
-    """Splitting of eq. (2.11): A_inn = H_0 shared by all subsystems and the
+    """Splitting of eq. (2.14): A_inn = H_0 shared by all subsystems and the
     per-subsystem outer parts A_out,a = sum_{j != 0} (-1)^popcount(a&j) H_j.
     Returns (A_inn, [A_out,a for a in 0..2^s-1])."""
     S = len(H)

@@ -1364,7 +1364,7 @@ const char* msp_last_error(void) { return msp::g_last_error.c_str(); }
 
 namespace msp {
 
-// Low-rank corrections (Sec. 2.1 eq. (2.20), Sec. 2.2 eq. (2.27)), eigenpairs by
+// Low-rank corrections (Sec. 2.1 eq. (2.24), Sec. 2.2 eq. (2.32)), eigenpairs by
 // Lanczos with full reorthogonalisation, run for all 2^s subsystems at once as
 // the columns of one multivector:
 //   AMGR: operator M^{-1} A_a in the A_a inner product (M^{-1} = the shared

@@ -80,6 +80,81 @@ __device__ __forceinline__ void row_accumulate(int32_t k0, int32_t k1, int step,
     }
 }
 
+// The same sum for rows handled by LPR >= 4 lanes that sit in one wavefront:
+// the row's entries are fetched CH = min(LPR, 8) at a time, lane q of the row
+// loading entry q (one coalesced load of column indices and values instead of
+// every lane reading each entry), and are broadcast with cross-lane shuffles,
+// so the CH gathers of X rows are issued back to back.  Entries are added in
+// increasing k, the order of row_accumulate.  base = first lane of the row
+// within its wavefront.  Every lane of the row must make the call (the
+// shuffles read the other lanes' registers).
+template <typename T, int C, int VW, int LPR, typename TV = T>
+__device__ __forceinline__ void row_accumulate_bcast(int32_t k0, int32_t k1, const int32_t* __restrict__ ci,
+                                                     const TV* __restrict__ va, const T* __restrict__ X, int lane,
+                                                     int base, T* acc) {
+    constexpr int CH = LPR < 8 ? LPR : 8;
+    for (int32_t kb = k0; kb < k1; kb += CH) {
+        const int32_t kk = kb + lane;
+        const bool have = lane < CH && kk < k1;
+        const int32_t c = have ? ci[kk] : 0;
+        const T a = have ? cvt<T>(va[kk]) : T(0);
+        const int cnt = k1 - kb < CH ? k1 - kb : CH;
+        Pack<T, VW> xs[CH];
+        T as[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int32_t cq = __shfl(c, base + q, 64);
+            as[q] = __shfl(a, base + q, 64);
+            if (q < cnt) xs[q] = ld<T, VW>(X + (int64_t)cq * C + lane * VW);
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            if (q < cnt) {
+#pragma unroll
+                for (int e = 0; e < VW; ++e) acc[e] += as[q] * xs[q].e[e];
+            }
+        }
+    }
+}
+
+// The broadcast form for matrices with vs interleaved value sets: only the
+// column indices are broadcast; each lane reads the values of its own
+// columns' sets (set[e] for column e, from column_sets; one load per entry
+// when all VW columns share a set).  Every lane of the row must make the call.
+template <typename T, int C, int VW, int LPR, typename TV = T>
+__device__ __forceinline__ void row_accumulate_bcast_sets(int32_t k0, int32_t k1, const int32_t* __restrict__ ci,
+                                                          const TV* __restrict__ va, const T* __restrict__ X,
+                                                          int lane, int base, T* acc, int vs, const int* set,
+                                                          bool uniform) {
+    constexpr int CH = LPR < 8 ? LPR : 8;
+    for (int32_t kb = k0; kb < k1; kb += CH) {
+        const int32_t kk = kb + lane;
+        const bool have = lane < CH && kk < k1;
+        const int32_t c = have ? ci[kk] : 0;
+        const int cnt = k1 - kb < CH ? k1 - kb : CH;
+        Pack<T, VW> xs[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int32_t cq = __shfl(c, base + q, 64);
+            if (q < cnt) xs[q] = ld<T, VW>(X + (int64_t)cq * C + lane * VW);
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            if (q < cnt) {
+                const TV* vk = va + (int64_t)(kb + q) * vs;
+                if (uniform) {
+                    const T a = cvt<T>(vk[set[0]]);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) acc[e] += a * xs[q].e[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) acc[e] += cvt<T>(vk[set[e]]) * xs[q].e[e];
+                }
+            }
+        }
+    }
+}
+
 // As row_accumulate with interleaved value sets where the VW columns of the
 // lane belong to different sets: column e uses va[k * vs + set[e]].
 template <typename T, int C, int VW, typename TV = T>

@@ -1,5 +1,5 @@
 // Host-side setup: block extraction and validation (Sec. 2) and the shared
-// multigrid-reduction hierarchy on A_inn (Sec. 3.2, Alg. 2, eqs. (3.11)-(3.13)).
+// multigrid-reduction hierarchy on A_inn (Sec. 3.2, Alg. 2, eqs. (3.13)-(3.15)).
 //
 // Pattern-deciding arithmetic (strength thresholds, symbolic products) is
 // compiled without floating-point contraction so that each decision is one

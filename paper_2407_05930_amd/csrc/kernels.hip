@@ -19,7 +19,7 @@ namespace msp {
 // ------------------------------------------------------------------ SpMM
 // Y = alpha * (A X + diag-outer(X)) + beta * Z, where the outer term adds
 // sigma[row * S + col / m] * X[row, col] (the per-subsystem outer diagonal of
-// eq. (2.11), one value per subsystem, broadcast over its m columns).
+// eq. (2.14), one value per subsystem, broadcast over its m columns).
 // Y may alias Z (each lane reads its own Z elements before writing them).
 // With SETS the matrix holds vs interleaved value sets (entry k of set a at
 // va[k * vs + a]) and column c is multiplied by set min(c / m, vs - 1): one
@@ -39,14 +39,25 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
     T acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = T(0);
+    constexpr bool BC = L::LPR >= 4;   // broadcast row entries across the row's lanes
+    const int base = (int)(threadIdx.x % 64) - lane;
     if constexpr (SETS) {
         int set[VW];
-        if (column_sets<VW>(lane, vs, m, set))
-            row_accumulate<T, C, VW, TV, true>(rp[row], rp[row + 1], 1, ci, va + set[0], X, lane, acc, vs);
-        else
-            row_accumulate_sets<T, C, VW, TV>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc, vs, set);
+        const bool uniform = column_sets<VW>(lane, vs, m, set);
+        if constexpr (BC) {   // all lanes of the row together (shuffles)
+            row_accumulate_bcast_sets<T, C, VW, L::LPR, TV>(rp[row], rp[row + 1], ci, va, X, lane, base, acc, vs, set,
+                                                            uniform);
+        } else {
+            if (uniform)
+                row_accumulate<T, C, VW, TV, true>(rp[row], rp[row + 1], 1, ci, va + set[0], X, lane, acc, vs);
+            else
+                row_accumulate_sets<T, C, VW, TV>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc, vs, set);
+        }
     } else {
-        row_accumulate<T, C, VW, TV>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc);
+        if constexpr (BC)
+            row_accumulate_bcast<T, C, VW, L::LPR, TV>(rp[row], rp[row + 1], ci, va, X, lane, base, acc);
+        else
+            row_accumulate<T, C, VW, TV>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc);
     }
     if (sigma) {
         const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
@@ -290,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_pupdate(int64_t n, double* __res
     st<double, VW>(p + o, pv);
 }
 
-// ------------------------------------------------------------------ Q_s (Alg. 1, eq. (2.9))
+// ------------------------------------------------------------------ Q_s (Alg. 1, eq. (2.12))
 // Q_s = 2^{-s/2} Had (x) I: a Walsh-Hadamard butterfly over the 2^s images of
 // each base cell, fused with the layout change between the caller's n x m
 // column-major vectors and the n_b x C multivector (column a*m + j).

@@ -40,7 +40,11 @@ __global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __r
         double acc[VW];
 #pragma unroll
         for (int e = 0; e < VW; ++e) acc[e] = 0.0;
-        row_accumulate<double, C, VW>(rp[row], rp[row + 1], 1, ci, va, p, lane, acc);
+        if constexpr (LPR >= 4)
+            row_accumulate_bcast<double, C, VW, LPR>(rp[row], rp[row + 1], ci, va, p, lane,
+                                                     (int)(threadIdx.x % 64) - lane, acc);
+        else
+            row_accumulate<double, C, VW>(rp[row], rp[row + 1], 1, ci, va, p, lane, acc);
         const Pack<double, VW> pr = ld<double, VW>(p + row * C + lane * VW);
         Pack<double, VW> out;
 #pragma unroll

@@ -1,5 +1,5 @@
 """Pins of the multigrid-reduction part of the oracle (Sec. 3.2: Alg. 2,
-eqs. (3.11)-(3.13), Alg. 3) against invariants, special cases that reduce
+eqs. (3.13)-(3.15), Alg. 3) against invariants, special cases that reduce
 to textbook formulas, and brute force."""
 import itertools
 
@@ -187,7 +187,7 @@ def test_interpolation_many_steps_tends_to_ideal():
 # ----------------------------------------------------------------- Galerkin
 
 def test_galerkin_four_term_expansion():
-    """A_c = W^T A_FF W + W^T A_FC + A_CF W + A_CC (eq. (3.13)), symmetric and
+    """A_c = W^T A_FF W + W^T A_FC + A_CF W + A_CC (eq. (3.15)), symmetric and
     positive definite."""
     A, iface = _inner((12, 12, 12), y_stretch=1.5)
     C = amg.coarsen_level0(A, iface, 0.25, 2, 3)

@@ -1,5 +1,5 @@
-"""Pins of the low-rank corrections (Thm. 2.1 / eq. (2.20) and Thm. 2.2 /
-eq. (2.27)) on inputs small enough for dense eigendecompositions."""
+"""Pins of the low-rank corrections (Thm. 2.1 / eq. (2.24) and Thm. 2.2 /
+eq. (2.32)) on inputs small enough for dense eigendecompositions."""
 import numpy as np
 import pytest
 

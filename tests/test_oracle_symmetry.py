@@ -53,7 +53,7 @@ def test_uniform_spectrum_closed_form(N, s):
 @pytest.mark.parametrize("kw", [dict(), dict(y_stretch=1.5), dict(jitter=0.2, kappa="lognormal")])
 def test_block_structure_exact(ordering, kw):
     """Block (a, b) of the mirrored matrix equals H_{a xor b} bit for bit
-    (eq. (2.4)); A is symmetric."""
+    (eqs. (2.4)-(2.5)); A is symmetric."""
     p = make_problem((8, 8, 8), s=3, seed=5, ordering=ordering, **kw)
     H = symmetry.base_blocks(p.A, p.img)
     assert (p.A != p.A.T).nnz == 0
@@ -98,7 +98,7 @@ def test_q_orthogonal_involution(s):
 @pytest.mark.parametrize("kw", [dict(), dict(y_stretch=1.5), dict(jitter=0.2, kappa="lognormal")])
 def test_qaq_block_diagonal_and_spectrum(kw):
     """Q_s A Q_s^{-1} is block diagonal with blocks sum_j (-1)^{|a&j|} H_j
-    (eqs. (2.10)-(2.11)); its blocks' eigenvalues are A's."""
+    (eqs. (2.12)-(2.13)); its blocks' eigenvalues are A's."""
     p = make_problem((8, 6, 4), s=2, seed=7, **kw)
     H = symmetry.base_blocks(p.A, p.img)
     n_b, S = p.img.shape
