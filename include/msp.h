@@ -127,7 +127,7 @@ typedef struct {
 } msp_stats;
 
 /* Fill *o with the defaults: FP64, AMGR, k = 0, d = 2, theta = 0.25,
-   jacobi0 = 2, jacobi = 1, coarse_max = 2560, max_levels = 20,
+   jacobi0 = 3, jacobi = 1, coarse_max = 2560, max_levels = 20,
    max_ratio = 0.8, tol = 1e-10, maxit = 1000, device = 0, seed = 240705930. */
 int msp_default_opts(msp_opts* o);
 

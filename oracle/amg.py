@@ -394,7 +394,7 @@ class Hierarchy:
 class AMGOptions:
     theta: float = 0.25
     dist: int = 2
-    jacobi0: int = 2          # interpolation steps at the reduction level
+    jacobi0: int = 3          # interpolation steps at the reduction level
     jacobi: int = 1           # interpolation steps below it
     coarse_max: int = 2560
     max_levels: int = 20

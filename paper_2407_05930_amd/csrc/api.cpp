@@ -1132,7 +1132,7 @@ int msp_default_opts(msp_opts* o) {
     o->lrc_k = 0;
     o->dist = 2;
     o->theta = 0.25;
-    o->jacobi0 = 2;
+    o->jacobi0 = 3;
     o->jacobi = 1;
     o->coarse_max = 2560;
     o->max_levels = 20;

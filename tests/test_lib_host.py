@@ -38,7 +38,7 @@ def _setup(p, **kw):
     dict(N=(64, 64), s=1, kw=dict(), opt=dict(coarse_max=64)),
     dict(N=(32, 32, 32), s=3, kw=dict(jitter=0.2, kappa="lognormal"), opt=dict(coarse_max=64)),
     dict(N=(48, 48, 48), s=2, kw=dict(y_stretch=1.5), opt=dict()),
-    dict(N=(24, 16, 20), s=3, kw=dict(y_stretch=1.5), opt=dict(coarse_max=32, dist=3, jacobi0=3)),
+    dict(N=(24, 16, 20), s=3, kw=dict(y_stretch=1.5), opt=dict(coarse_max=32, dist=3, jacobi0=2)),
 ])
 def test_hierarchy_bit_exact_with_oracle(case):
     p = make_problem(case["N"], s=case["s"], seed=1, **case["kw"])
