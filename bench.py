@@ -79,7 +79,7 @@ def committed_traffic(kind_name):
     return None
 
 
-def cpu_baseline(problem, iters_gpu, k, pc):
+def cpu_baseline(problem, iters_gpu, k, pc, extra):
     """The FP64 oracle on the host: setup plus a bounded sample of PCG
     iterations on the same workload, extrapolated to the GPU's iteration
     count.  One thread (SciPy's sparse products are single-threaded; BLAS is
@@ -88,7 +88,7 @@ def cpu_baseline(problem, iters_gpu, k, pc):
     from oracle import amg, krylov
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        ctx = krylov.setup(problem.A, problem.img, amg.AMGOptions(), precond=pc, k=0)
+        ctx = krylov.setup(problem.A, problem.img, amg.AMGOptions(**extra), precond=pc, k=0)
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
         krylov.solve(ctx, problem.b, tol=1e-10, maxit=1)
@@ -114,7 +114,7 @@ def bench_jitter(args, torch, np):
     b = torch.from_numpy(p.b).cuda()
     out = {}
     for prec in ("fp64", "mixed", "mixed_bf16g"):
-        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=args.k, pc=args.pc)
+        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=args.k, pc=args.pc, **args.extra)
         t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
         xs = x.cpu().numpy()
         rr = float(np.max(np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)))
@@ -140,7 +140,7 @@ def bench_batch(args, torch, np):
     probs = batch_problems(64)
     bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
     t0 = time.perf_counter()
-    bsol = BatchSolver([(pr.A, pr.img) for pr in probs], tol=1e-10, precision="mixed", pc=args.pc)
+    bsol = BatchSolver([(pr.A, pr.img) for pr in probs], tol=1e-10, precision="mixed", pc=args.pc, **args.extra)
     t_setup = time.perf_counter() - t0
     for _ in range(args.warmup):
         bsol.solve(bs)
@@ -159,7 +159,7 @@ def bench_batch(args, torch, np):
     bsol.close()
     # the same systems one after another, one context each (no batching)
     from paper_2407_05930_amd import Solver
-    sols = [Solver(pr.A, pr.img, tol=1e-10, precision="mixed", pc=args.pc) for pr in probs]
+    sols = [Solver(pr.A, pr.img, tol=1e-10, precision="mixed", pc=args.pc, **args.extra) for pr in probs]
     for sv, b in zip(sols, bs):
         sv.solve(b)
     torch.cuda.synchronize()
@@ -188,7 +188,7 @@ def bench_adjoint(args, torch, np):
     log("building workload adjoint3d_256_s3 (geometry only)")
     pr = config_problem("adjoint3d_256_s3", assemble=False)
     t0 = time.perf_counter()
-    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-10, pc=args.pc)
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-10, pc=args.pc, **args.extra)
     f = torch.from_numpy(pr.b).cuda()
     pst = torch.from_numpy(pr.p_target[:, None]).cuda()
     kap = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
@@ -225,6 +225,8 @@ def main():
     ap.add_argument("--pc", default="amgr_sub", choices=["amgr", "amgr_sub"],
                     help="AMGR per subsystem below the shared reduction level (default), or the AMGR "
                          "hierarchy of A_inn shared by every subsystem")
+    ap.add_argument("--trunc0", type=float, default=None,
+                    help="reduction-level interpolation truncation (library default when omitted)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip timing the other preconditioner beside the headline one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -243,6 +245,8 @@ def main():
     from paper_2407_05930_amd import Solver
 
     rank = int(os.environ.get("RANK", "0"))
+    extra = {} if args.trunc0 is None else {"trunc0": args.trunc0}
+    args.extra = extra
     other = {"jitter3d_192_s3": bench_jitter, "batch64": bench_batch, "adjoint3d_256_s3": bench_adjoint}
     if args.workload in other:
         res = other[args.workload](args, torch, np)
@@ -265,7 +269,7 @@ def main():
         res = {}
         for prec in ("fp64", "mixed"):
             log(f"setup {pc} {prec} k={k}")
-            sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=k, pc=pc)
+            sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=k, pc=pc, **args.extra)
             t_setup = sv.stats.t_setup_s
             log(f"timing {pc} {prec}: warmup {args.warmup}, steps {args.steps}")
             t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
@@ -349,7 +353,7 @@ def main():
         }
     if not args.no_cpu_baseline and rank == 0:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(p, res["fp64"]["iters"], k, args.pc)
+        out["cpu_baseline"] = cpu_baseline(p, res["fp64"]["iters"], k, args.pc, args.extra)
     if rank == 0:
         print(json.dumps(out), flush=True)
 

@@ -110,6 +110,9 @@ typedef struct {
     int32_t maxit;
     int32_t device;      /* HIP device ordinal; -1 = host-only setup (no solve) */
     uint64_t seed;       /* seed of the hash priorities and start vectors */
+    double trunc0;       /* reduction-level interpolation: each F row drops the weights below
+                            trunc0 * (its largest weight magnitude) before the row-sum rescaling;
+                            0 keeps every weight of the symbolic pattern; 0 <= trunc0 < 1 */
 } msp_opts;
 
 typedef struct {
@@ -128,7 +131,8 @@ typedef struct {
 
 /* Fill *o with the defaults: FP64, AMGR, k = 0, d = 2, theta = 0.25,
    jacobi0 = 3, jacobi = 1, coarse_max = 2560, max_levels = 20,
-   max_ratio = 0.8, tol = 1e-10, maxit = 1000, device = 0, seed = 240705930. */
+   max_ratio = 0.8, tol = 1e-10, maxit = 1000, device = 0, seed = 240705930,
+   trunc0 = 0.05. */
 int msp_default_opts(msp_opts* o);
 
 /* Build a context from A and its symmetry map.  Validates the map
@@ -199,11 +203,13 @@ int msp_get_timing(const msp_ctx* c, int32_t kind, int64_t* count, double* total
  * right-hand-side counts) solved together.  Setup builds one context per
  * system (host parts in parallel threads).  Solve starts every system on its
  * own stream, then replays one captured HIP graph holding K PCG iterations of
- * every system in parallel branches (default K = 4) until all columns of all
- * systems have converged; columns that converge earlier are frozen on the
- * device (their updates are zero), so the extra iterations of a chunk leave
- * their solutions unchanged.  The graph is re-captured when the vector of m
- * changes.  SpMM lane-group splits are autotuned per matrix and column count.
+ * every system in parallel branches (default K = 4) until the first system
+ * has converged, then a second graph holding one iteration of every system
+ * until all columns of all systems have converged; columns that converge
+ * earlier are frozen on the device (their updates are zero), so the extra
+ * iterations leave their solutions unchanged.  The graphs are re-captured when
+ * the vector of m changes.  SpMM lane-group splits are autotuned per matrix
+ * and column count.
  * --------------------------------------------------------------------------- */
 typedef struct msp_batch msp_batch;   /* opaque; owned by the library until msp_batch_free */
 
@@ -215,7 +221,7 @@ int msp_batch_setup(int32_t nsys, const msp_csr* A, const msp_symmap* maps, cons
 int msp_batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b, double* const* d_x, void* hip_stream,
                     msp_stats* st);
 int msp_batch_size(const msp_batch* bt, int32_t* nsys);
-/* Iterations per graph replay (1..64). */
+/* Iterations per replay of the first graph (1..64). */
 int msp_batch_set_chunk(msp_batch* bt, int32_t iterations);
 void msp_batch_free(msp_batch* bt);
 

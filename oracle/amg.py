@@ -227,12 +227,14 @@ def coarsen_standard(A: sp.csr_matrix, level: int, theta: float, seed: int,
 # interpolation, P = [W; I] (eq. (3.13))
 # ---------------------------------------------------------------------------
 
-def interpolation(A: sp.csr_matrix, C: np.ndarray, steps: int) -> sp.csr_matrix:
+def interpolation(A: sp.csr_matrix, C: np.ndarray, steps: int, trunc: float = 0.0) -> sp.csr_matrix:
     """Jacobi-truncated ideal interpolation (parity reading of the cited long
     distance schemes): W1 = -D^{-1} A_FC, W_{t+1} = -D^{-1}(A_FC + O W_t) with
-    D = diag(A_FF), O = A_FF - D, symbolic patterns.  Each F row with nonzero
-    sum is rescaled to rho_i = -sum_{l != i} a_il / a_ii.  Returns P (n x n_c),
-    coarse unknowns numbered by increasing fine index."""
+    D = diag(A_FF), O = A_FF - D, symbolic patterns.  With trunc > 0 every F
+    row keeps only the weights with |w| >= trunc * max |w| of the row (the
+    others leave the pattern).  Each F row with nonzero sum is then rescaled
+    to rho_i = -sum_{l != i} a_il / a_ii.  Returns P (n x n_c), coarse
+    unknowns numbered by increasing fine index."""
     A = A.tocsr()
     n = A.shape[0]
     F = ~C
@@ -255,6 +257,14 @@ def interpolation(A: sp.csr_matrix, C: np.ndarray, steps: int) -> sp.csr_matrix:
     for _ in range(steps - 1):
         inner = sym_add(AFC, sym_matmul(O, W))
         W = embed(-(Dinv @ inner), inner)
+    if trunc > 0.0:
+        nrow = np.diff(W.indptr)
+        rmax = np.zeros(W.shape[0])
+        np.maximum.at(rmax, np.repeat(np.arange(W.shape[0]), nrow), np.abs(W.data))
+        keep = np.abs(W.data) >= trunc * np.repeat(rmax, nrow)
+        rows_w = np.repeat(np.arange(W.shape[0]), nrow)
+        kept = np.bincount(rows_w[keep], minlength=W.shape[0])
+        W = sp.csr_matrix((W.data[keep], W.indices[keep], np.concatenate([[0], np.cumsum(kept)])), shape=W.shape)
     # row rescaling to the direct-interpolation row sum
     diagA = A.diagonal()
     rowsA = np.repeat(np.arange(n), np.diff(A.indptr))
@@ -395,6 +405,7 @@ class AMGOptions:
     theta: float = 0.25
     dist: int = 2
     jacobi0: int = 3          # interpolation steps at the reduction level
+    trunc0: float = 0.05      # relative weight truncation at the reduction level (0 = none)
     jacobi: int = 1           # interpolation steps below it
     coarse_max: int = 2560
     max_levels: int = 20
@@ -420,10 +431,10 @@ def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions)
             break
         if lev == 0:
             C = coarsen_level0(A, interface, opt.theta, opt.dist, opt.seed, opt.mis_method)
-            steps = opt.jacobi0
+            steps, trunc = opt.jacobi0, opt.trunc0
         else:
             C = coarsen_standard(A, lev, opt.theta, opt.seed, opt.mis_method)
-            steps = opt.jacobi
+            steps, trunc = opt.jacobi, 0.0
         nc = int(C.sum())
         if nc == 0 or nc > opt.max_ratio * n:
             break
@@ -432,7 +443,7 @@ def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions)
         L.C = C
         L.G = fsai(A, S, block)
         L.omega = damping(A, L.G, opt.seed)
-        L.P = interpolation(A, C, steps)
+        L.P = interpolation(A, C, steps, trunc)
         L.R = L.P.T.tocsr()
         L.R.sort_indices()
         A = galerkin(A, L.P)

@@ -48,7 +48,7 @@ class msp_opts(ctypes.Structure):
                 ("dist", ctypes.c_int32), ("theta", ctypes.c_double), ("jacobi0", ctypes.c_int32),
                 ("jacobi", ctypes.c_int32), ("coarse_max", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("max_ratio", ctypes.c_double), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("trunc0", ctypes.c_double)]
 
 
 class msp_stats(ctypes.Structure):

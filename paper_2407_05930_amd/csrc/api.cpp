@@ -921,7 +921,7 @@ static void check_opts(const msp_opts* o) {
     if (o->precision < MSP_FP64 || o->precision > MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_ARG, "precision");
     if (o->pc < MSP_PC_AMGR || o->pc > MSP_PC_AMGR_SUB) throw Error(MSP_ERR_ARG, "pc");
     if (o->lrc_k < 0 || o->dist < 1 || o->jacobi0 < 1 || o->jacobi < 1 || o->coarse_max < 1 || o->max_levels < 1 ||
-        !(o->theta >= 0.0) || !(o->tol > 0.0) || o->maxit < 0)
+        !(o->theta >= 0.0) || !(o->tol > 0.0) || o->maxit < 0 || !(o->trunc0 >= 0.0 && o->trunc0 < 1.0))
         throw Error(MSP_ERR_ARG, "invalid option value");
     if (o->lrc_k > 0 && o->pc == MSP_PC_NONE) throw Error(MSP_ERR_ARG, "low-rank corrections need a preconditioner");
     if (o->lrc_k > 16) throw Error(MSP_ERR_UNSUPPORTED, "low-rank correction rank above 16");
@@ -971,6 +971,8 @@ struct msp_batch {
     std::vector<int> graph_m;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph1 = nullptr;      // one iteration of every system (the tail after the first convergence)
+    hipGraphExec_t exec1 = nullptr;
     int K = 4;
     int** d_flag_ptrs = nullptr;
     int* d_flags = nullptr;
@@ -978,6 +980,8 @@ struct msp_batch {
     ~msp_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (exec1) (void)hipGraphExecDestroy(exec1);
+        if (graph1) (void)hipGraphDestroy(graph1);
         for (auto e : joins) (void)hipEventDestroy(e);
         if (fork) (void)hipEventDestroy(fork);
         for (auto s : streams) (void)hipStreamDestroy(s);
@@ -1066,16 +1070,17 @@ static int batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b
     HIPCHECK(hipMemcpy(bt->d_flag_ptrs, ptrs.data(), sizeof(int*) * nsys, hipMemcpyHostToDevice));
     for (int i = 0; i < nsys; ++i) HIPCHECK(hipStreamSynchronize(bt->streams[i]));
     std::vector<int> mv(m, m + nsys);
-    if (!bt->exec || mv != bt->graph_m) {
-        if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
-        if (bt->graph) (void)hipGraphDestroy(bt->graph);
-        bt->exec = nullptr;
-        bt->graph = nullptr;
+    // graph of `iters` iterations of every system on parallel branches, then the flags gathered
+    auto capture = [&](int iters, hipGraph_t* g, hipGraphExec_t* ex) {
+        if (*ex) (void)hipGraphExecDestroy(*ex);
+        if (*g) (void)hipGraphDestroy(*g);
+        *ex = nullptr;
+        *g = nullptr;
         HIPCHECK(hipStreamBeginCapture(bt->main, hipStreamCaptureModeRelaxed));
         HIPCHECK(hipEventRecord(bt->fork, bt->main));
         for (int i = 0; i < nsys; ++i) {
             HIPCHECK(hipStreamWaitEvent(bt->streams[i], bt->fork, 0));
-            for (int k = 0; k < bt->K; ++k) {
+            for (int k = 0; k < iters; ++k) {
                 plans[i]->half_a();
                 plans[i]->half_b();
             }
@@ -1083,8 +1088,19 @@ static int batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b
             HIPCHECK(hipStreamWaitEvent(bt->main, bt->joins[i], 0));
         }
         HIPCHECK(launch_gather_flags(bt->main, nsys, bt->d_flag_ptrs, bt->d_flags));
-        HIPCHECK(hipStreamEndCapture(bt->main, &bt->graph));
-        HIPCHECK(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+        HIPCHECK(hipStreamEndCapture(bt->main, g));
+        HIPCHECK(hipGraphInstantiate(ex, *g, nullptr, nullptr, 0));
+    };
+    if (!bt->exec || mv != bt->graph_m) {
+        capture(bt->K, &bt->graph, &bt->exec);
+        if (bt->K > 1) {
+            capture(1, &bt->graph1, &bt->exec1);
+        } else {
+            if (bt->exec1) (void)hipGraphExecDestroy(bt->exec1);
+            if (bt->graph1) (void)hipGraphDestroy(bt->graph1);
+            bt->exec1 = nullptr;
+            bt->graph1 = nullptr;
+        }
         bt->graph_m = mv;
     }
     int maxit = 0;
@@ -1093,14 +1109,22 @@ static int batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b
     HIPCHECK(launch_gather_flags(bt->main, nsys, bt->d_flag_ptrs, bt->d_flags));
     HIPCHECK(hipMemcpyAsync(bt->h_flags, bt->d_flags, sizeof(int) * 2 * nsys, hipMemcpyDeviceToHost, bt->main));
     HIPCHECK(hipStreamSynchronize(bt->main));
-    for (int it = 0; it < maxit; it += bt->K) {
+    // chunks of K iterations until the first system has converged, then single iterations:
+    // the systems run in lockstep, so the tail costs only the iterations it needs
+    std::vector<char> started(nsys, 0);
+    for (int i = 0; i < nsys; ++i) started[i] = bt->h_flags[2 * i + 1] > 0;
+    bool tail = false;
+    for (int it = 0; it < maxit;) {
         bool any = false, broke = false;
         for (int i = 0; i < nsys; ++i) {
             any |= bt->h_flags[2 * i + 1] > 0;
             broke |= bt->h_flags[2 * i] != 0;
+            tail |= started[i] && bt->h_flags[2 * i + 1] == 0;
         }
         if (!any || broke) break;
-        HIPCHECK(hipGraphLaunch(bt->exec, bt->main));
+        const bool one = tail && bt->exec1;
+        HIPCHECK(hipGraphLaunch(one ? bt->exec1 : bt->exec, bt->main));
+        it += one ? 1 : bt->K;
         HIPCHECK(hipMemcpyAsync(bt->h_flags, bt->d_flags, sizeof(int) * 2 * nsys, hipMemcpyDeviceToHost, bt->main));
         HIPCHECK(hipStreamSynchronize(bt->main));
     }
@@ -1133,6 +1157,7 @@ int msp_default_opts(msp_opts* o) {
     o->dist = 2;
     o->theta = 0.25;
     o->jacobi0 = 3;
+    o->trunc0 = 0.05;
     o->jacobi = 1;
     o->coarse_max = 2560;
     o->max_levels = 20;

@@ -307,8 +307,9 @@ static std::vector<int8_t> mis_scan(const Graph& T, const std::vector<int8_t>& c
 
 // Jacobi-truncated ideal interpolation with symbolic patterns and row sums
 // rescaled to -sum_{l != i} a_il / a_ii; P = [W; I] in fine-row order with
-// coarse unknowns numbered by increasing fine index.
-static Csr interpolation(const Csr& A, const std::vector<int8_t>& cf, int steps) {
+// coarse unknowns numbered by increasing fine index.  With trunc > 0 each F row
+// first drops the weights below trunc * (largest magnitude in the row).
+static Csr interpolation(const Csr& A, const std::vector<int8_t>& cf, int steps, double trunc = 0.0) {
     const int64_t n = A.nr;
     std::vector<int32_t> cnum(n, -1), fnum(n, -1);
     int32_t nc = 0, nf = 0;
@@ -391,6 +392,26 @@ static Csr interpolation(const Csr& A, const std::vector<int8_t>& cf, int steps)
         W.rp.swap(Wn.rp);
         W.ci.swap(Wn.ci);
         W.v.swap(Wn.v);
+    }
+    if (trunc > 0.0) {
+        Csr T;
+        T.nr = nf;
+        T.nc = nc;
+        T.rp.assign(nf + 1, 0);
+        for (int32_t r = 0; r < nf; ++r) {
+            double mx = 0.0;
+            for (int64_t p = W.rp[r]; p < W.rp[r + 1]; ++p) mx = std::max(mx, std::fabs(W.v[p]));
+            const double lim = trunc * mx;
+            for (int64_t p = W.rp[r]; p < W.rp[r + 1]; ++p)
+                if (std::fabs(W.v[p]) >= lim) {
+                    T.ci.push_back(W.ci[p]);
+                    T.v.push_back(W.v[p]);
+                }
+            T.rp[r + 1] = static_cast<int64_t>(T.ci.size());
+        }
+        W.rp.swap(T.rp);
+        W.ci.swap(T.ci);
+        W.v.swap(T.v);
     }
     // rescale rows to rho_i = -sum_{l != i} a_il / a_ii
     for (int32_t r = 0; r < nf; ++r) {
@@ -685,7 +706,7 @@ HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface,
         L.omega = damping(A, L.G, L.GT, seed);
         L.M = spgemm(L.GT, L.G);
         for (double& v : L.M.v) v *= L.omega;
-        L.P = interpolation(A, cf, lev == 0 ? o.jacobi0 : o.jacobi);
+        L.P = interpolation(A, cf, lev == 0 ? o.jacobi0 : o.jacobi, lev == 0 ? o.trunc0 : 0.0);
         L.R = transpose(L.P);
         L.cf = std::move(cf);
         Csr AP = spgemm(A, L.P);

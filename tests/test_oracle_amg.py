@@ -9,7 +9,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from gen import make_problem
-from oracle import amg, symmetry
+from oracle import amg, krylov, symmetry
 
 
 def _inner(N=(12, 12, 12), s=3, **kw):
@@ -376,3 +376,44 @@ def test_sub_vcycle_symmetric_and_contracts():
         L = np.linalg.cholesky(Aa)
         E = I - V @ Aa
         assert np.linalg.norm(L.T @ E @ np.linalg.inv(L.T), 2) < 0.9
+
+
+def test_interpolation_truncation_keeps_large_weights_and_row_sums():
+    """With trunc > 0 an F row keeps exactly the weights of the untruncated
+    row with |w| >= trunc * max|w| (the row-sum rescaling multiplies a row by
+    one factor, so the relative test reads the same before and after it) and
+    is rescaled to the same row sum rho_i."""
+    A, iface = _inner(y_stretch=1.5)
+    C = amg.coarsen_level0(A, iface, 0.25, 2, 7, "rounds")
+    full = amg.interpolation(A, C, 3)
+    for tr in (0.0, 0.05, 0.1, 0.3):
+        P = amg.interpolation(A, C, 3, tr)
+        assert P.shape == full.shape
+        for i in np.flatnonzero(~C)[::7]:
+            fr = full[i].toarray().ravel()
+            pr = P[i].toarray().ravel()
+            mx = np.abs(fr).max()
+            expect = set(full.indices[full.indptr[i]:full.indptr[i + 1]][
+                np.abs(full.data[full.indptr[i]:full.indptr[i + 1]]) >= tr * mx])
+            got = set(P.indices[P.indptr[i]:P.indptr[i + 1]])
+            assert got == expect, (tr, i)
+            if abs(fr.sum()) > 1e-12:
+                assert abs(pr.sum() - fr.sum()) <= 1e-12 * np.abs(fr).sum()
+            if tr == 0.0:
+                assert np.array_equal(pr, fr)
+        for i in np.flatnonzero(C)[::11]:
+            assert P[i].nnz == 1 and P[i].data[0] == 1.0
+
+
+def test_truncated_reduction_keeps_convergence():
+    """Dropping small reduction-level weights (trunc0 = 0.05) thins the reduced
+    operator but leaves the per-subsystem cycle's PCG iteration count within
+    one of the untruncated cycle's."""
+    p = make_problem((24, 24, 24), s=3, m=1, seed=5, y_stretch=1.5)
+    res = {}
+    for tr in (0.0, 0.05):
+        ctx = krylov.setup(p.A, p.img, amg.AMGOptions(coarse_max=64, trunc0=tr), precond="amgr_sub")
+        r = krylov.solve(ctx, p.b, tol=1e-10)
+        res[tr] = (int(r.iters.max()), ctx["hier"].levels[1].A.nnz)
+    assert res[0.05][1] < res[0.0][1]
+    assert res[0.05][0] <= res[0.0][0] + 1
