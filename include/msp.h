@@ -183,7 +183,7 @@ int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz);
 
 /* Optional per-kernel timers.  Launch classes ("kinds"):
      0 operator (A_inn + outer diagonal) SpMM, 1 per-column dots,
-     2 x/r update, 3 p update, 4 Q_s butterflies, 5 precision casts,
+     2 r update with its dots, 3 x and p update, 4 Q_s butterflies, 5 precision casts,
      6 dense coarsest solve, 7 FSAI preconditioner products,
      8 low-rank corrections,
      16 + 8*l + {0: A_l, 1: M_l = omega_l G_l^T G_l (or G_l in the BF16

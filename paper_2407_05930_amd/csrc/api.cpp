@@ -75,8 +75,8 @@ enum { SC_RR = 0, SC_RZ, SC_PQ, SC_RHO, SC_ALPHA, SC_BETA, SC_THR, SC_RNORM, SC_
 enum {
     KD_OP = 0,        // q = (A_inn + outer diagonal) p
     KD_DOT = 1,       // per-column dot products (partials + reduction)
-    KD_UPDATE = 2,    // x += alpha p, r -= alpha q
-    KD_PUPDATE = 3,   // p = z + beta p
+    KD_UPDATE = 2,    // r -= alpha q with <r,r>, <r,z_old>, U^T r
+    KD_PUPDATE = 3,   // x += alpha p, p = z + beta p
     KD_QS = 4,        // Q_s butterflies
     KD_CAST = 5,      // precision casts at the preconditioner boundary
     KD_DENSE = 6,     // coarsest-level dense solve
@@ -676,6 +676,7 @@ struct SolvePlan {
     int m, S, C, nbp, kl, O;
     int64_t nb, n;
     bool flexible, lrc_amg;
+    bool x_pending = false;   // an x += alpha p step not yet applied
     double *rr, *rz, *pq, *rho, *alpha, *beta, *thr, *rnorm, *bn2, *rzold;
     int *active, *iters, *flags;
 
@@ -716,17 +717,17 @@ struct SolvePlan {
     void update_dots(bool upd) {
         Work& W = *w;
         const double wu = c->U32 ? 4.0 : 8.0;
-        const double bytes = (upd ? 6.0 : 1.0) * vb() + (flexible && upd ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0) +
+        const double bytes = (upd ? 3.0 : 1.0) * vb() + (flexible && upd ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0) +
                              (y32() ? 4.0 * nb * C : 0.0);
         timed(c, KD_UPDATE, bytes, st, [&] {
             if (c->U32 || !c->d_U)
-                HIPCHECK(launch_update_dots<float>(st, C, nbp, upd, flexible && upd, kl, nb, W.x, W.r, W.p, W.q, alpha,
-                                                   W.z, static_cast<const float*>(c->d_U), S, m, W.pp1, W.pp2,
-                                                   W.plrc, y32()));
+                HIPCHECK(launch_update_dots<float>(st, C, nbp, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
+                                                   static_cast<const float*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
+                                                   y32()));
             else
-                HIPCHECK(launch_update_dots<double>(st, C, nbp, upd, flexible && upd, kl, nb, W.x, W.r, W.p, W.q,
-                                                    alpha, W.z, static_cast<const double*>(c->d_U), S, m, W.pp1,
-                                                    W.pp2, W.plrc, y32()));
+                HIPCHECK(launch_update_dots<double>(st, C, nbp, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
+                                                    static_cast<const double*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
+                                                    y32()));
         });
         HIPCHECK(launch_fin_check(st, C, nbp, !upd, flexible && upd, O, m, W.pp1, W.pp2, W.plrc, thr, c->d_lrc_coef,
                                   active, iters, flags, rnorm, rzold, c->d_lrc_W));
@@ -793,13 +794,15 @@ struct SolvePlan {
         });
         HIPCHECK(launch_fin_alpha(st, C, nbp, W.pp1, active, rho, alpha, pq, flags));
         update_dots(true);
+        x_pending = true;   // x += alpha p follows with the p update (or in finish)
     }
 
     void half_b() {
         Work& W = *w;
         precond_dot(false);
-        timed(c, KD_PUPDATE, 24.0 * nb * C, st,
-              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, W.p, W.z, beta, active)); });
+        timed(c, KD_PUPDATE, 5.0 * vb(), st,
+              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, W.x, W.p, W.z, alpha, beta, active)); });
+        x_pending = false;
     }
 
     void read_flags() {
@@ -810,6 +813,10 @@ struct SolvePlan {
     // Q_s backward and statistics (status: MSP_OK / MSP_NOT_CONVERGED / breakdown)
     int finish(double* d_x, int status, double seconds, msp_stats* out) {
         Work& W = *w;
+        if (x_pending) {   // the last iteration stopped before its p update
+            timed(c, KD_PUPDATE, 3.0 * vb(), st, [&] { HIPCHECK(launch_pcg_xupdate(st, C, nb, W.x, W.p, alpha)); });
+            x_pending = false;
+        }
         timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // x = Q_s xhat
               [&] { HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, W.x, d_x)); });
         HIPCHECK(hipMemcpyAsync(W.h_iters, iters, 64 * sizeof(int), hipMemcpyDeviceToHost, st));

@@ -281,8 +281,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n, double* __rest
 
 // p = z + beta p on active columns
 template <int C>
-__global__ __launch_bounds__(kBlock) void k_pcg_pupdate(int64_t n, double* __restrict__ p,
+__global__ __launch_bounds__(kBlock) void k_pcg_pupdate(int64_t n, double* __restrict__ x, double* __restrict__ p,
                                                         const double* __restrict__ z,
+                                                        const double* __restrict__ alpha,
                                                         const double* __restrict__ beta,
                                                         const int* __restrict__ active) {
     using L = Lanes<double, C>;
@@ -292,13 +293,34 @@ __global__ __launch_bounds__(kBlock) void k_pcg_pupdate(int64_t n, double* __res
     if (row >= n) return;
     const int64_t o = row * C + lane * VW;
     Pack<double, VW> pv = ld<double, VW>(p + o);
+    Pack<double, VW> xv = ld<double, VW>(x + o);
     const Pack<double, VW> zv = ld<double, VW>(z + o);
 #pragma unroll
     for (int e = 0; e < VW; ++e) {
         const int c = lane * VW + e;
+        xv.e[e] += alpha[c] * pv.e[e];   // this iteration's x step (alpha = 0 on frozen columns)
         if (active[c]) pv.e[e] = zv.e[e] + beta[c] * pv.e[e];
     }
+    st<double, VW>(x + o, xv);
     st<double, VW>(p + o, pv);
+}
+
+// x += alpha p: the x step of an iteration that ends the solve before its p update
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_pcg_xupdate(int64_t n, double* __restrict__ x,
+                                                        const double* __restrict__ p,
+                                                        const double* __restrict__ alpha) {
+    using L = Lanes<double, C>;
+    constexpr int VW = L::VW;
+    const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
+    const int lane = threadIdx.x % L::LPR;
+    if (row >= n) return;
+    const int64_t o = row * C + lane * VW;
+    Pack<double, VW> xv = ld<double, VW>(x + o);
+    const Pack<double, VW> pv = ld<double, VW>(p + o);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) xv.e[e] += alpha[lane * VW + e] * pv.e[e];
+    st<double, VW>(x + o, xv);
 }
 
 // ------------------------------------------------------------------ Q_s (Alg. 1, eq. (2.12))
@@ -818,12 +840,19 @@ hipError_t launch_pcg_update(hipStream_t st, int C, int64_t n, double* x, double
     });
     return hipGetLastError();
 }
-hipError_t launch_pcg_pupdate(hipStream_t st, int C, int64_t n, double* p, const double* z, const double* beta,
-                              const int* active) {
+hipError_t launch_pcg_pupdate(hipStream_t st, int C, int64_t n, double* x, double* p, const double* z,
+                              const double* alpha, const double* beta, const int* active) {
     MSP_DISPATCH_C(C, {
         using L = Lanes<double, CC>;
-        hipLaunchKernelGGL((k_pcg_pupdate<CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, p, z, beta,
-                           active);
+        hipLaunchKernelGGL((k_pcg_pupdate<CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, x, p, z, alpha,
+                           beta, active);
+    });
+    return hipGetLastError();
+}
+hipError_t launch_pcg_xupdate(hipStream_t st, int C, int64_t n, double* x, const double* p, const double* alpha) {
+    MSP_DISPATCH_C(C, {
+        using L = Lanes<double, CC>;
+        hipLaunchKernelGGL((k_pcg_xupdate<CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, x, p, alpha);
     });
     return hipGetLastError();
 }

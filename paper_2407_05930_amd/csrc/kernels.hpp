@@ -39,8 +39,11 @@ hipError_t launch_pcg_beta(hipStream_t st, int C, const double* rz, const double
                            double* rho, double* beta, int flexible);
 hipError_t launch_pcg_update(hipStream_t st, int C, int64_t n, double* x, double* r, const double* p,
                              const double* q, const double* alpha);
-hipError_t launch_pcg_pupdate(hipStream_t st, int C, int64_t n, double* p, const double* z, const double* beta,
-                              const int* active);
+// x += alpha p (every column; alpha = 0 on frozen ones), then p = z + beta p on active columns
+hipError_t launch_pcg_pupdate(hipStream_t st, int C, int64_t n, double* x, double* p, const double* z,
+                              const double* alpha, const double* beta, const int* active);
+// x += alpha p
+hipError_t launch_pcg_xupdate(hipStream_t st, int C, int64_t n, double* x, const double* p, const double* alpha);
 
 hipError_t launch_qs_forward(hipStream_t st, int S, int64_t n_b, int m, int C, int64_t n, const int64_t* img,
                              const double* b, double* out);

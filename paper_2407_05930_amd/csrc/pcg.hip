@@ -79,13 +79,14 @@ __global__ __launch_bounds__(kBlock) void k_fin_alpha(int nb, int C, const doubl
     }
 }
 
-// UPD: x += alpha p, r -= alpha q.  Then per-block partials of <r,r>
-// (partial_rr), of <r,z> with the current z when FLEX (partial_rz), and of
-// the low-rank projections U_a^T r_a when KMAX > 0:
+// UPD: r -= alpha q (the matching x += alpha p is applied by the p update,
+// which reads p anyway).  Then per-block partials of <r,r> (partial_rr), of
+// <r,z> with the current z when FLEX (partial_rz), and of the low-rank
+// projections U_a^T r_a when KMAX > 0:
 // partial_lrc[b, (a*k + t)*m + j] = sum_rows U[i, a*k+t] r[i, a*m+j].
 template <int C, bool UPD, bool FLEX, int KMAX, typename TU>
-__global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __restrict__ x, double* __restrict__ r,
-                                                        const double* __restrict__ p, const double* __restrict__ q,
+__global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __restrict__ r,
+                                                        const double* __restrict__ q,
                                                         const double* __restrict__ alpha,
                                                         const double* __restrict__ z, const TU* __restrict__ U,
                                                         int S, int k, int m, double* __restrict__ partial_rr,
@@ -94,7 +95,6 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
     constexpr int KA = KMAX > 0 ? KMAX : 1;
     __shared__ double sm[kBlock * VW];
-    __shared__ double tot[C];
     const int slot = threadIdx.x / LPR, lane = threadIdx.x % LPR;
     const int64_t ntiles = (n + RPB - 1) / RPB;
     double a_rr[VW], a_rz[VW], a_l[VW][KA];
@@ -112,14 +112,9 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
         const int64_t o = row * C + lane * VW;
         Pack<double, VW> rv = ld<double, VW>(r + o);
         if (UPD) {
-            Pack<double, VW> xv = ld<double, VW>(x + o);
-            const Pack<double, VW> pv = ld<double, VW>(p + o), qv = ld<double, VW>(q + o);
+            const Pack<double, VW> qv = ld<double, VW>(q + o);
 #pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                xv.e[e] += al[e] * pv.e[e];
-                rv.e[e] -= al[e] * qv.e[e];
-            }
-            st<double, VW>(x + o, xv);
+            for (int e = 0; e < VW; ++e) rv.e[e] -= al[e] * qv.e[e];
             st<double, VW>(r + o, rv);
         }
         if (y32) {   // FP32 copy of r: the V-cycle input of the mixed mode
@@ -162,16 +157,28 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
     block_column_sums<C, VW>(a_rr, sm, partial_rr + (int64_t)blockIdx.x * C);
     if (FLEX) block_column_sums<C, VW>(a_rz, sm, partial_rz + (int64_t)blockIdx.x * C);
     if (KMAX > 0) {
+        // up to 8 projections per pass: slm[(tt * kBlock + thread) * VW + e] for t = t0 + tt,
+        // then one thread per output (column, t) sums the RPB row slots in a fixed order
+        extern __shared__ double slm[];
         const int O = S * k * m;
-        for (int t = 0; t < k && t < KA; ++t) {
-            double v[VW];
 #pragma unroll
-            for (int e = 0; e < VW; ++e) v[e] = a_l[e][t];
-            block_column_sums<C, VW>(v, sm, tot);
-            if (threadIdx.x < S * m) {
-                const int col = threadIdx.x, a = col / m, j = col % m;
-                partial_lrc[(int64_t)blockIdx.x * O + (a * k + t) * m + j] = tot[col];
+        for (int t0 = 0; t0 < KA; t0 += 8) {
+            if (t0 >= k) break;
+#pragma unroll
+            for (int tt = 0; tt < 8 && t0 + tt < KA; ++tt) {
+#pragma unroll
+                for (int e = 0; e < VW; ++e) slm[(tt * kBlock + threadIdx.x) * VW + e] = a_l[e][t0 + tt];
             }
+            __syncthreads();
+            const int nt = k - t0 < 8 ? k - t0 : 8;
+            for (int q = threadIdx.x; q < S * m * nt; q += kBlock) {
+                const int col = q % (S * m), tt = q / (S * m);
+                double v = 0.0;
+                for (int r = 0; r < RPB; ++r) v += slm[tt * kBlock * VW + r * C + col];
+                const int a = col / m, j = col % m;
+                partial_lrc[(int64_t)blockIdx.x * O + (a * k + t0 + tt) * m + j] = v;
+            }
+            __syncthreads();
         }
     }
 }
@@ -351,41 +358,43 @@ hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial
 }
 
 template <int CC, bool UPD, bool FLEX, int KMAX, typename TU>
-static void upd_launch(hipStream_t st, int nb, int64_t n, double* x, double* r, const double* p, const double* q,
-                       const double* alpha, const double* z, const TU* U, int S, int k, int m, double* prr,
-                       double* prz, double* plrc, float* y32) {
-    hipLaunchKernelGGL((k_update_dots<CC, UPD, FLEX, KMAX, TU>), dim3(nb), dim3(kBlock), 0, st, n, x, r, p, q, alpha,
-                       z, U, S, k, m, prr, prz, plrc, y32);
+static void upd_launch(hipStream_t st, int nb, int64_t n, double* r, const double* q, const double* alpha,
+                       const double* z, const TU* U, int S, int k, int m, double* prr, double* prz, double* plrc,
+                       float* y32) {
+    constexpr int VW = DL<CC>::VW;
+    const size_t lds = KMAX > 0 ? sizeof(double) * 8 * kBlock * VW : 0;   // projection partials, 8 at a time
+    hipLaunchKernelGGL((k_update_dots<CC, UPD, FLEX, KMAX, TU>), dim3(nb), dim3(kBlock), lds, st, n, r, q, alpha, z,
+                       U, S, k, m, prr, prz, plrc, y32);
 }
 
 template <typename TU>
-hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* x,
-                              double* r, const double* p, const double* q, const double* alpha, const double* z,
-                              const TU* U, int S, int m, double* prr, double* prz, double* plrc, float* y32) {
+hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* r,
+                              const double* q, const double* alpha, const double* z, const TU* U, int S, int m,
+                              double* prr, double* prz, double* plrc, float* y32) {
     if (k > 16) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         if (k > 8) {
-            if (upd && flex) upd_launch<CC, true, true, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else if (upd) upd_launch<CC, true, false, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else upd_launch<CC, false, false, 16, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            if (upd && flex) upd_launch<CC, true, true, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else if (upd) upd_launch<CC, true, false, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else upd_launch<CC, false, false, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
         } else if (k > 0) {
-            if (upd && flex) upd_launch<CC, true, true, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else if (upd) upd_launch<CC, true, false, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else upd_launch<CC, false, false, 8, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            if (upd && flex) upd_launch<CC, true, true, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else if (upd) upd_launch<CC, true, false, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else upd_launch<CC, false, false, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
         } else {
-            if (upd && flex) upd_launch<CC, true, true, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else if (upd) upd_launch<CC, true, false, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else upd_launch<CC, false, false, 0, TU>(st, nb, n, x, r, p, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            if (upd && flex) upd_launch<CC, true, true, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else if (upd) upd_launch<CC, true, false, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            else upd_launch<CC, false, false, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
         }
     });
     return hipGetLastError();
 }
-template hipError_t launch_update_dots<float>(hipStream_t, int, int, bool, bool, int, int64_t, double*, double*,
-                                              const double*, const double*, const double*, const double*,
-                                              const float*, int, int, double*, double*, double*, float*);
-template hipError_t launch_update_dots<double>(hipStream_t, int, int, bool, bool, int, int64_t, double*, double*,
-                                               const double*, const double*, const double*, const double*,
-                                               const double*, int, int, double*, double*, double*, float*);
+template hipError_t launch_update_dots<float>(hipStream_t, int, int, bool, bool, int, int64_t, double*,
+                                              const double*, const double*, const double*, const float*, int, int,
+                                              double*, double*, double*, float*);
+template hipError_t launch_update_dots<double>(hipStream_t, int, int, bool, bool, int, int64_t, double*,
+                                               const double*, const double*, const double*, const double*, int, int,
+                                               double*, double*, double*, float*);
 
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
                             const double* prz, const double* plrc, const double* thr, const double* coef, int* active,

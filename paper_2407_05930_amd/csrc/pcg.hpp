@@ -16,10 +16,11 @@ hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t
                          double* partial);
 hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial, const int* active,
                             const double* rho, double* alpha, double* pq, int* flags);
+// upd: r -= alpha q (x is updated by launch_pcg_pupdate / launch_pcg_xupdate)
 template <typename TU>
-hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* x,
-                              double* r, const double* p, const double* q, const double* alpha, const double* z,
-                              const TU* U, int S, int m, double* prr, double* prz, double* plrc, float* y32);
+hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* r,
+                              const double* q, const double* alpha, const double* z, const TU* U, int S, int m,
+                              double* prr, double* prz, double* plrc, float* y32);
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
                             const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
                             int* iters, int* flags, double* rnorm, double* rzold, double* W);
