@@ -32,6 +32,8 @@ def stats(path, out, command):
     rows = list(csv.DictReader(open(path)))
     lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
              f"Library source hash: `{source_hash()}`", "",
+             "Totals cover the whole command: the setup (upload, autotuning, the Lanczos runs of the low-rank "
+             "corrections: `k_axpy_cols`, `k_dot<double, 8>`, copies) and every timed solve.", "",
              "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for r in rows[:30]:
         name = r["Name"].replace("|", "/")
