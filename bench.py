@@ -29,6 +29,11 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "solve time to 1e-10 rel-res, 128^3 s=3; mixed vs FP64 plain; V-cycle HBM GB/s"
 
 
+PRECISION_NOTE = {"mixed": "mixed (FP32 V-cycle, FP64 PCG)",
+                  "mixed_bf16": "mixed (V-cycle multivectors bfloat16 with FP32 arithmetic, FP32 matrices, "
+                                "FP64 coarsest inverse and PCG)"}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -113,7 +118,7 @@ def bench_jitter(args, torch, np):
     p = config_problem("jitter3d_192_s3")
     b = torch.from_numpy(p.b).cuda()
     out = {}
-    for prec in ("fp64", "mixed", "mixed_bf16g"):
+    for prec in ("fp64", "mixed", "mixed_bf16g", "mixed_bf16"):
         sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=args.k, pc=args.pc, **args.extra)
         t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
         xs = x.cpu().numpy()
@@ -140,7 +145,8 @@ def bench_batch(args, torch, np):
     probs = batch_problems(64)
     bs = [torch.from_numpy(pr.b).cuda() for pr in probs]
     t0 = time.perf_counter()
-    bsol = BatchSolver([(pr.A, pr.img) for pr in probs], tol=1e-10, precision="mixed", pc=args.pc, **args.extra)
+    bsol = BatchSolver([(pr.A, pr.img) for pr in probs], tol=1e-10, precision=args.mixed, pc=args.pc,
+                       **args.extra)
     t_setup = time.perf_counter() - t0
     for _ in range(args.warmup):
         bsol.solve(bs)
@@ -159,7 +165,7 @@ def bench_batch(args, torch, np):
     bsol.close()
     # the same systems one after another, one context each (no batching)
     from paper_2407_05930_amd import Solver
-    sols = [Solver(pr.A, pr.img, tol=1e-10, precision="mixed", pc=args.pc, **args.extra) for pr in probs]
+    sols = [Solver(pr.A, pr.img, tol=1e-10, precision=args.mixed, pc=args.pc, **args.extra) for pr in probs]
     for sv, b in zip(sols, bs):
         sv.solve(b)
     torch.cuda.synchronize()
@@ -172,9 +178,10 @@ def bench_batch(args, torch, np):
     for sv in sols:
         sv.close()
     return {"metric": "batched solve time to 1e-10 rel-res, 64 uneven systems", "value": round(t, 6), "unit": "s",
-            "higher_is_better": False, "dtype": "f64+f32",
+            "higher_is_better": False, "dtype": "f64+f32+bf16" if args.mixed == "mixed_bf16" else "f64+f32",
             "config": {"workload": "batch64", "systems": len(probs), "unknowns": int(sum(pr.n for pr in probs)),
-                       "rhs_total": int(sum(pr.b.shape[1] for pr in probs)), "preconditioner": args.pc},
+                       "rhs_total": int(sum(pr.b.shape[1] for pr in probs)), "preconditioner": args.pc,
+                       "precision": PRECISION_NOTE[args.mixed]},
             "iters_min_max": [min(its), max(its)], "true_relres_max": worst, "setup_s": round(t_setup, 2),
             "unknown_rhs_per_s": round(unk / t, 1), "sequential_single_solves_s": round(t_seq, 6),
             "batch_speedup_vs_sequential": round(t_seq / t, 3)}
@@ -225,6 +232,9 @@ def main():
     ap.add_argument("--pc", default="amgr_sub", choices=["amgr", "amgr_sub"],
                     help="AMGR per subsystem below the shared reduction level (default), or the AMGR "
                          "hierarchy of A_inn shared by every subsystem")
+    ap.add_argument("--mixed", default="mixed_bf16", choices=["mixed", "mixed_bf16"],
+                    help="mixed-precision variant of the headline: V-cycle multivectors in bfloat16 (default) or "
+                         "FP32; the other one is timed beside it")
     ap.add_argument("--trunc0", type=float, default=None,
                     help="reduction-level interpolation truncation (library default when omitted)")
     ap.add_argument("--no-compare", action="store_true",
@@ -265,9 +275,9 @@ def main():
     b = torch.from_numpy(p.b).cuda()
     k = args.k
 
-    def run_pc(pc, k):
+    def run_pc(pc, k, precs):
         res = {}
-        for prec in ("fp64", "mixed"):
+        for prec in precs:
             log(f"setup {pc} {prec} k={k}")
             sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=k, pc=pc, **args.extra)
             t_setup = sv.stats.t_setup_s
@@ -282,11 +292,16 @@ def main():
             log(f"  {pc} {prec}: {t * 1e3:.2f} ms/solve, {iters} iterations, true rel res {true_rr.max():.2e}")
         return res
 
-    res = run_pc(args.pc, k)
+    head = args.mixed   # the mixed-precision variant reported as the headline
+    alt = "mixed" if head == "mixed_bf16" else "mixed_bf16"
+    res = run_pc(args.pc, k, ("fp64", head, alt))
+    res["alt"] = res.pop(alt)
+    res["mixed"] = res.pop(head)
+    res["alt"]["sv"].close()
     other_pc = "amgr" if args.pc == "amgr_sub" else "amgr_sub"
     other = None
     if not args.no_compare:
-        other = run_pc(other_pc, k)
+        other = run_pc(other_pc, k, ("fp64", "mixed"))
         for v in other.values():
             v["sv"].close()
 
@@ -321,19 +336,21 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32",
+        "dtype": "f64+f32+bf16" if head == "mixed_bf16" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(p.N), "s": p.s, "rhs": int(p.b.shape[1]),
                    "subsystem_columns": int((1 << p.s) * p.b.shape[1]), "lrc_k": k, "tol": 1e-10,
                    "preconditioner": args.pc,
-                   "precision": "mixed (FP32 V-cycle, FP64 PCG)", "unknowns": int(p.n)},
+                   "precision": PRECISION_NOTE[head], "unknowns": int(p.n)},
+        "other_mixed_variant": {"precision": PRECISION_NOTE[alt], "solve_s": round(res["alt"]["t"], 6),
+                                "iters": res["alt"]["iters"], "true_relres_max": max(res["alt"]["true_relres"])},
         "fp64_solve_s": round(t_fp64, 6),
         "mixed_speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
         "iters": {"fp64": res["fp64"]["iters"], "mixed": res["mixed"]["iters"]},
-        "true_relres_max": {kk: max(v["true_relres"]) for kk, v in res.items()},
+        "true_relres_max": {kk: max(res[kk]["true_relres"]) for kk in ("fp64", "mixed")},
         "mixed_vs_fp64_rel_diff": float(np.linalg.norm(res["mixed"]["x"] - res["fp64"]["x"])
                                         / np.linalg.norm(res["fp64"]["x"])),
-        "setup_s": {kk: round(v["t_setup"], 3) for kk, v in res.items()},
+        "setup_s": {kk: round(res[kk]["t_setup"], 3) for kk in ("fp64", "mixed")},
         "vcycle_GBs": round(vc_by / (vc_ms * 1e-3) / 1e9, 1) if vc_ms > 0 else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(Solver.kind_name(kind)),

@@ -59,8 +59,11 @@ typedef enum {
 /* MSP_MIXED_FP32: FP32 V-cycle (smoother M = omega G^T G formed explicitly),
    FP64 outer PCG, dots and coarsest solve.  MSP_MIXED_FP32_BF16G: as
    MSP_MIXED_FP32 but the FSAI factors G, G^T are stored in bfloat16 and the
-   smoother is applied factored, G^T (G r), which keeps it SPD. */
-enum { MSP_FP64 = 0, MSP_MIXED_FP32 = 1, MSP_MIXED_FP32_BF16G = 2 };
+   smoother is applied factored, G^T (G r), which keeps it SPD.
+   MSP_MIXED_BF16: as MSP_MIXED_FP32 but the V-cycle multivectors are stored
+   in bfloat16 (FP32 matrices, FP32 arithmetic and accumulation, FP64
+   coarsest inverse); the outer PCG stays FP64. */
+enum { MSP_FP64 = 0, MSP_MIXED_FP32 = 1, MSP_MIXED_FP32_BF16G = 2, MSP_MIXED_BF16 = 3 };
 /* Preconditioners of the decoupled subsystems A_a = A_inn + diag(sigma_a)
    (Sec. 2, eqs. (2.13)-(2.14)):
    MSP_PC_AMGR: the AMGR hierarchy of A_inn (Sec. 3.2, Alg. 2 and 3) shared by
@@ -96,7 +99,7 @@ typedef struct {
 } msp_symmap;
 
 typedef struct {
-    int32_t precision;   /* MSP_FP64 | MSP_MIXED_FP32 | MSP_MIXED_FP32_BF16G */
+    int32_t precision;   /* MSP_FP64 | MSP_MIXED_FP32 | MSP_MIXED_FP32_BF16G | MSP_MIXED_BF16 */
     int32_t pc;          /* MSP_PC_AMGR | MSP_PC_FSAI | MSP_PC_NONE | MSP_PC_AMGR_SUB */
     int32_t lrc_k;       /* low-rank correction rank per subsystem, >= 0 */
     int32_t dist;        /* interpolation distance d of Alg. 2 (>= 1) */

@@ -30,7 +30,7 @@ STATUS = {
     -4: "MSP_ERR_BREAKDOWN", -5: "MSP_ERR_HIP", -6: "MSP_ERR_OOM", -7: "MSP_ERR_NOT_SPD",
     -8: "MSP_ERR_UNSUPPORTED",
 }
-PRECISION = {"fp64": 0, "mixed": 1, "mixed_bf16g": 2}
+PRECISION = {"fp64": 0, "mixed": 1, "mixed_bf16g": 2, "mixed_bf16": 3}
 PC = {"amgr": 0, "fsai": 1, "none": 2, "amgr_sub": 3}
 
 

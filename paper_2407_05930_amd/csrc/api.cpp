@@ -11,6 +11,7 @@
 #include <memory>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -34,7 +35,7 @@ struct DevCsr {
     int64_t nr = 0, nc = 0, nnz = 0;
     int split = 1;           // lane groups per row (long rows are split)
     int vs = 1;              // interleaved value sets (one per subsystem), entry k of set a at k * vs + a
-    int tuned[2][7] = {};    // autotuned split by [FP32?][log2 C]; 0 = not tuned
+    int tuned[3][7] = {};    // autotuned split by [multivector type: FP64, FP32, BF16][log2 C]; 0 = not tuned
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
     double* v64 = nullptr;
@@ -65,6 +66,9 @@ struct Work {
     double* scal = nullptr;   // 10 arrays of 64
     int* iscal = nullptr;     // active[64], iters[64], flags[2]
     int* h_flags = nullptr;   // pinned host copy of flags
+    int* h_pub = nullptr;     // fine-grained host memory the device publishes flags into: flags, sequence number
+    int* d_pub = nullptr;     // its device-visible address
+    int pub_seq = 0;
     int* h_iters = nullptr;
     double* h_scal = nullptr;
 };
@@ -145,6 +149,7 @@ struct msp_ctx {
             for (void* p : allocs) (void)hipFree(p);
             for (auto& kv : works) {
                 if (kv.second->h_flags) (void)hipHostFree(kv.second->h_flags);
+                if (kv.second->h_pub) (void)hipHostFree(kv.second->h_pub);
                 if (kv.second->h_iters) (void)hipHostFree(kv.second->h_iters);
                 if (kv.second->h_scal) (void)hipHostFree(kv.second->h_scal);
             }
@@ -246,12 +251,28 @@ static DevCsr upload_sets(msp_ctx* c, const Csr& M, const std::vector<double>& v
     return D;
 }
 
+// matrix values used with multivectors of type T (bfloat16 multivectors take FP32 values)
 template <typename T>
-static const T* vals(const DevCsr& M);
+struct ValOf {
+    using type = T;
+};
+template <>
+struct ValOf<Bf16> {
+    using type = float;
+};
+template <typename T>
+static const typename ValOf<T>::type* vals(const DevCsr& M);
 template <>
 const double* vals<double>(const DevCsr& M) { return M.v64; }
 template <>
 const float* vals<float>(const DevCsr& M) { return M.v32; }
+template <>
+const float* vals<Bf16>(const DevCsr& M) { return M.v32; }
+
+template <typename T>
+static int tslot() {
+    return sizeof(T) == 8 ? 0 : (sizeof(T) == 4 ? 1 : 2);
+}
 
 static hipEvent_t take_event(msp_ctx* c) {
     if (!c->tm.pool.empty()) {
@@ -297,7 +318,7 @@ static void resolve_timers(msp_ctx* c) {
 template <typename T>
 static double spmm_bytes(const DevCsr& M, int C, bool z, bool sig, int S) {
     const double w = sizeof(T);
-    const double wv = (sizeof(T) == 4 && M.v16) ? 2.0 : w;
+    const double wv = (sizeof(T) == 4 && M.v16) ? 2.0 : static_cast<double>(sizeof(typename ValOf<T>::type));
     double b = static_cast<double>(M.nnz) * (wv * M.vs + 4.0) + 4.0 * static_cast<double>(M.nr + 1);
     b += static_cast<double>(M.nc) * C * w + static_cast<double>(M.nr) * C * w;
     if (z) b += static_cast<double>(M.nr) * C * w;
@@ -314,9 +335,10 @@ static int log2i(int C) {
 // One SpMM launch with an explicit lane-group split (1 = one group per row);
 // FP32 products use the bfloat16 values when the matrix carries them.
 template <typename T>
-static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const T* X, T* Y, const T* Z, T alpha,
-                        T beta, const double* sigma, int S, int m) {
-    if constexpr (sizeof(T) == 4) {
+static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const T* X, T* Y, const T* Z,
+                        acc_t<T> alpha, acc_t<T> beta, const double* sigma, int S, int m) {
+    using TV = typename ValOf<T>::type;
+    if constexpr (std::is_same<T, float>::value) {
         if (M.v16) {
             if (split > 1)
                 HIPCHECK((launch_spmm_split<float, Bf16>(st, C, split, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta,
@@ -328,17 +350,17 @@ static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const
         }
     }
     if (split > 1)
-        HIPCHECK((launch_spmm_split<T, T>(st, C, split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, M.vs, m,
-                                          sigma, S)));
+        HIPCHECK((launch_spmm_split<T, TV>(st, C, split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, M.vs, m,
+                                           sigma, S)));
     else
-        HIPCHECK((launch_spmm<T, T>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m, M.vs)));
+        HIPCHECK((launch_spmm<T, TV>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m, M.vs)));
 }
 
 template <typename T>
 static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, const T* X, T* Y, const T* Z,
-                 T alpha, T beta, const double* sigma = nullptr, int S = 1, int m = 1) {
+                 acc_t<T> alpha, acc_t<T> beta, const double* sigma = nullptr, int S = 1, int m = 1) {
     const double bytes = c->tm.on[kind] ? spmm_bytes<T>(M, C, Z != nullptr, sigma != nullptr, S) : 0.0;
-    const int tuned = M.tuned[sizeof(T) == 4 ? 1 : 0][log2i(C)];
+    const int tuned = M.tuned[tslot<T>()][log2i(C)];
     const int split = tuned ? tuned : M.split;
     timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, X, Y, Z, alpha, beta, sigma, S, m); });
 }
@@ -351,7 +373,8 @@ template <typename T>
 static void autotune_level_splits(msp_ctx* c, Work& w) {
     hipStream_t st = nullptr;
     const int C = w.C;
-    const int lpr = C * static_cast<int>(sizeof(T)) >= 16 ? C / (16 / static_cast<int>(sizeof(T))) : 1;
+    const int vw = lane_width(static_cast<int>(sizeof(T)));
+    const int lpr = C >= vw ? C / vw : 1;   // lanes per row of Lanes<T, C>
     const int S = 1 << c->sym.s;
     const int mt = std::max(1, C / S);   // columns per subsystem assumed for matrices with value sets
     hipEvent_t e0, e1;
@@ -359,9 +382,9 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
     HIPCHECK(hipEventCreate(&e1));
     for (size_t l = 0; l < c->hier.lev.size(); ++l) {
         const int64_t n = c->hier.lev[l].A.nr;
-        HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vy[l]), T(0)));
-        HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vs[l]), T(0)));
-        HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vr[l]), T(0)));
+        HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vy[l]), T{}));
+        HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vs[l]), T{}));
+        HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vr[l]), T{}));
     }
     for (size_t l = 0; l < c->dl.size(); ++l) {
         DevLevel& L = c->dl[l];
@@ -378,10 +401,10 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
             float best_ms = 1e30f;
             for (int g = 1; g <= 64 && g * lpr <= 256; g *= 2) {   // 256 threads per block
                 if (g > 1 && g > std::max(1.0, avg / 2.0)) break;
-                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, T(1), T(0), nullptr, S, mt);
+                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0), nullptr, S, mt);
                 HIPCHECK(hipEventRecord(e0, st));
                 for (int rep = 0; rep < 3; ++rep)
-                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, T(1), T(0), nullptr, S, mt);
+                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0), nullptr, S, mt);
                 HIPCHECK(hipEventRecord(e1, st));
                 HIPCHECK(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -391,7 +414,7 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
                     best = g;
                 }
             }
-            jb.M->tuned[sizeof(T) == 4 ? 1 : 0][log2i(C)] = best;
+            jb.M->tuned[tslot<T>()][log2i(C)] = best;
         }
     }
     // rows per wavefront of the per-subsystem coarsest solves
@@ -422,6 +445,10 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
 }
 
 static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
+// bytes per element of the V-cycle multivectors
+static int vbytes(const msp_ctx* c) {
+    return c->o.precision == MSP_FP64 ? 8 : (c->o.precision == MSP_MIXED_BF16 ? 2 : 4);
+}
 static bool amg(const msp_ctx* c) { return c->o.pc == MSP_PC_AMGR || c->o.pc == MSP_PC_AMGR_SUB; }
 
 // Workspace for C padded columns (allocated on first use, kept with the context).
@@ -438,7 +465,7 @@ static Work& work(msp_ctx* c, int C) {
     w.p = c->dalloc<double>(nb * C);
     w.q = c->dalloc<double>(nb * C);
     w.zold = c->dalloc<double>(nb * C);
-    const size_t es = mixed(c) ? sizeof(float) : sizeof(double);
+    const size_t es = static_cast<size_t>(vbytes(c));
     const size_t L = c->hier.lev.size();
     w.vy.assign(L, nullptr);
     w.vs.assign(L, nullptr);
@@ -456,7 +483,7 @@ static Work& work(msp_ctx* c, int C) {
     }
     if (amg(c)) {
         const int64_t nL = c->hier.lev.back().A.nr;
-        const int ks = dense_splits(C, nL, mixed(c));
+        const int ks = dense_splits(C, nL, vbytes(c));
         w.dense_part = c->dalloc<double>(static_cast<int64_t>(ks) * nL * C);
         if (c->sub) w.dense_pack = c->dalloc<double>(2 * nL * C);
     }
@@ -468,12 +495,17 @@ static Work& work(msp_ctx* c, int C) {
     w.scal = c->dalloc<double>(SC_COUNT * 64);
     w.iscal = c->dalloc<int>(64 * 2 + 2);
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_flags), 2 * sizeof(int), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_pub), 4 * sizeof(int),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    w.h_pub[0] = w.h_pub[1] = w.h_pub[2] = w.h_pub[3] = 0;
+    HIPCHECK(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.d_pub), w.h_pub, 0));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_iters), 64 * sizeof(int), hipHostMallocDefault));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_scal), SC_COUNT * 64 * sizeof(double),
                            hipHostMallocDefault));
     c->works[C] = std::move(wp);
     if (amg(c) && !c->dl.empty()) {
-        if (mixed(c)) autotune_level_splits<float>(c, w);
+        if (c->o.precision == MSP_MIXED_BF16) autotune_level_splits<Bf16>(c, w);
+        else if (mixed(c)) autotune_level_splits<float>(c, w);
         else autotune_level_splits<double>(c, w);
     }
     return w;
@@ -504,13 +536,14 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     T* sc = static_cast<T*>(w.vs[l + 1]);
     const int kb = KD_LEVEL + 8 * static_cast<int>(l);
     // smoother s = beta s + M v with M = w G^T G (explicit, or factored with a temporary)
-    auto smooth = [&](const T* v, T beta) {
+    using TC = acc_t<T>;
+    auto smooth = [&](const T* v, TC beta) {
         if (L.G.nnz) {
             T* t = static_cast<T*>(w.vt[l]);
-            spmm<T>(c, kb + 1, st, C, L.G, v, t, nullptr, T(1), T(0));
-            spmm<T>(c, kb + 2, st, C, L.GT, t, s, beta != T(0) ? s : nullptr, static_cast<T>(L.omega), beta);
+            spmm<T>(c, kb + 1, st, C, L.G, v, t, nullptr, TC(1), TC(0));
+            spmm<T>(c, kb + 2, st, C, L.GT, t, s, beta != TC(0) ? s : nullptr, static_cast<TC>(L.omega), beta);
         } else {
-            spmm<T>(c, kb + 1, st, C, L.M, v, s, beta != T(0) ? s : nullptr, T(1), beta, nullptr, 1 << c->sym.s,
+            spmm<T>(c, kb + 1, st, C, L.M, v, s, beta != TC(0) ? s : nullptr, TC(1), beta, nullptr, 1 << c->sym.s,
                     w.m);
         }
     };
@@ -518,13 +551,13 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     // operator A_inn + diag(sigma_a); the levels below carry one value set per subsystem
     const double* sg = !c->sub ? nullptr : (l == 0 ? c->d_sigma : (l == 1 ? c->d_sigma1 : nullptr));
     const int m = w.m;
-    smooth(y, T(0));                                                     // pre-smooth from zero: s = M y
-    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1), sg, S, m);      // r = y - A s
-    spmm<T>(c, kb + 3, st, C, L.R, r, yc, nullptr, T(1), T(0), nullptr, S, m);   // r_c = P^T r
-    vcycle<T>(c, w, st, l + 1, yc, sc);                                  // coarse correction
-    spmm<T>(c, kb + 4, st, C, L.P, sc, s, s, T(1), T(1), nullptr, S, m);  // s += P h_c
-    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, T(-1), T(1), sg, S, m);      // post-smooth: s += M (y - A s)
-    smooth(r, T(1));
+    smooth(y, TC(0));                                                      // pre-smooth from zero: s = M y
+    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, TC(-1), TC(1), sg, S, m);      // r = y - A s
+    spmm<T>(c, kb + 3, st, C, L.R, r, yc, nullptr, TC(1), TC(0), nullptr, S, m);   // r_c = P^T r
+    vcycle<T>(c, w, st, l + 1, yc, sc);                                    // coarse correction
+    spmm<T>(c, kb + 4, st, C, L.P, sc, s, s, TC(1), TC(1), nullptr, S, m);  // s += P h_c
+    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, TC(-1), TC(1), sg, S, m);      // post-smooth: s += M (y - A s)
+    smooth(r, TC(1));
 }
 
 // out[c] = <X_c, Y_c> for the C columns of two n_b x C multivectors.
@@ -559,11 +592,17 @@ static void precondition_base(msp_ctx* c, Work& w, hipStream_t st, const double*
     const int64_t nb = c->sym.n_b;
     if (amg(c)) {
         if (mixed(c)) {
-            float* y0 = static_cast<float*>(w.vy[0]);
-            float* s0 = static_cast<float*>(w.vs[0]);
-            timed(c, KD_CAST, 12.0 * nb * C, st, [&] { HIPCHECK((launch_cast<float, double>(st, nb * C, r, y0))); });
-            vcycle<float>(c, w, st, 0, y0, s0);
-            timed(c, KD_CAST, 12.0 * nb * C, st, [&] { HIPCHECK((launch_cast<double, float>(st, nb * C, s0, z))); });
+            auto run = [&](auto tag) {
+                using T = decltype(tag);
+                T* y0 = static_cast<T*>(w.vy[0]);
+                T* s0 = static_cast<T*>(w.vs[0]);
+                const double cb = (8.0 + sizeof(T)) * nb * C;
+                timed(c, KD_CAST, cb, st, [&] { HIPCHECK((launch_cast<T, double>(st, nb * C, r, y0))); });
+                vcycle<T>(c, w, st, 0, y0, s0);
+                timed(c, KD_CAST, cb, st, [&] { HIPCHECK((launch_cast<double, T>(st, nb * C, s0, z))); });
+            };
+            if (c->o.precision == MSP_MIXED_BF16) run(Bf16{});
+            else run(0.0f);
         } else {
             vcycle<double>(c, w, st, 0, r, z);
         }
@@ -710,7 +749,10 @@ struct SolvePlan {
 
     // the mixed AMGR mode writes the FP32 V-cycle input in the update kernel
     float* y32() const {
-        return (amg(c) && mixed(c)) ? static_cast<float*>(w->vy[0]) : nullptr;
+        return (amg(c) && mixed(c) && c->o.precision != MSP_MIXED_BF16) ? static_cast<float*>(w->vy[0]) : nullptr;
+    }
+    Bf16* y16() const {
+        return (amg(c) && c->o.precision == MSP_MIXED_BF16) ? static_cast<Bf16*>(w->vy[0]) : nullptr;
     }
 
     // <r,r>, U^T r and the convergence check (initial: the active flags)
@@ -718,16 +760,16 @@ struct SolvePlan {
         Work& W = *w;
         const double wu = c->U32 ? 4.0 : 8.0;
         const double bytes = (upd ? 3.0 : 1.0) * vb() + (flexible && upd ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0) +
-                             (y32() ? 4.0 * nb * C : 0.0);
+                             (y32() ? 4.0 * nb * C : 0.0) + (y16() ? 2.0 * nb * C : 0.0);
         timed(c, KD_UPDATE, bytes, st, [&] {
             if (c->U32 || !c->d_U)
                 HIPCHECK(launch_update_dots<float>(st, C, nbp, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
                                                    static_cast<const float*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
-                                                   y32()));
+                                                   y32(), y16()));
             else
                 HIPCHECK(launch_update_dots<double>(st, C, nbp, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
                                                     static_cast<const double*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
-                                                    y32()));
+                                                    y32(), y16()));
         });
         HIPCHECK(launch_fin_check(st, C, nbp, !upd, flexible && upd, O, m, W.pp1, W.pp2, W.plrc, thr, c->d_lrc_coef,
                                   active, iters, flags, rnorm, rzold, c->d_lrc_W));
@@ -737,7 +779,13 @@ struct SolvePlan {
     void precond_dot(bool init) {
         Work& W = *w;
         const float* s32 = nullptr;
-        if (amg(c) && mixed(c)) {
+        const Bf16* s16 = nullptr;
+        if (amg(c) && c->o.precision == MSP_MIXED_BF16) {
+            Bf16* y0 = static_cast<Bf16*>(W.vy[0]);   // written by the update kernel
+            Bf16* s0 = static_cast<Bf16*>(W.vs[0]);
+            vcycle<Bf16>(c, W, st, 0, y0, s0);
+            s16 = s0;
+        } else if (amg(c) && mixed(c)) {
             float* y0 = static_cast<float*>(W.vy[0]);   // written by the update kernel
             float* s0 = static_cast<float*>(W.vs[0]);
             vcycle<float>(c, W, st, 0, y0, s0);
@@ -746,10 +794,19 @@ struct SolvePlan {
             precondition_base(c, W, st, W.r, W.z, true);
         }
         const double wu = c->U32 ? 4.0 : 8.0;
-        const double bytes = (s32 ? 4.0 : 8.0) * nb * C + 2.0 * vb() + (kl ? nb * S * kl * wu : 0.0);
+        const double bytes =
+            (s16 ? 2.0 : (s32 ? 4.0 : 8.0)) * nb * C + 2.0 * vb() + (kl ? nb * S * kl * wu : 0.0);
         const void* U = lrc_amg ? c->d_U : nullptr;
         timed(c, KD_CAST, bytes, st, [&] {
-            if (s32) {
+            if (s16) {
+                if (c->U32 || !c->d_U)
+                    HIPCHECK((launch_zfinish<Bf16, float>(st, C, nbp, nb, s16, W.z, W.r, static_cast<const float*>(U),
+                                                          c->d_lrc_W, S, kl, m, W.pp1)));
+                else
+                    HIPCHECK((launch_zfinish<Bf16, double>(st, C, nbp, nb, s16, W.z, W.r,
+                                                           static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
+                                                           W.pp1)));
+            } else if (s32) {
                 if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<float, float>(st, C, nbp, nb, s32, W.z, W.r, static_cast<const float*>(U),
                                                            c->d_lrc_W, S, kl, m, W.pp1)));
@@ -805,9 +862,39 @@ struct SolvePlan {
         x_pending = false;
     }
 
+    // The host decides whether to iterate on: the device publishes the two flags and a
+    // sequence number into fine-grained host memory and the host waits for that number
+    // (polling memory wakes up sooner than a stream synchronisation).  Every 1024 polls
+    // the stream is queried; once it has drained without the number showing, the
+    // flags are copied the ordinary way.
     void read_flags() {
-        HIPCHECK(hipMemcpyAsync(w->h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipStreamSynchronize(st));
+        Work& W = *w;
+        const int seq = ++W.pub_seq;
+        HIPCHECK(launch_publish_flags(st, flags, W.d_pub, seq));
+        volatile int* hp = W.h_pub;
+        bool seen = false;
+        for (int64_t spin = 1; !seen; ++spin) {
+            if (hp[2] == seq) {
+                seen = true;
+                break;
+            }
+            if ((spin & 1023) == 0) {
+                const hipError_t q = hipStreamQuery(st);
+                if (q == hipSuccess) {
+                    seen = hp[2] == seq;
+                    break;
+                }
+                if (q != hipErrorNotReady) HIPCHECK(q);
+            }
+        }
+        if (seen) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            W.h_flags[0] = hp[0];
+            W.h_flags[1] = hp[1];
+        } else {
+            HIPCHECK(hipMemcpyAsync(W.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+        }
     }
 
     // Q_s backward and statistics (status: MSP_OK / MSP_NOT_CONVERGED / breakdown)
@@ -925,7 +1012,7 @@ static int guarded(F&& f) {
 
 static void check_opts(const msp_opts* o) {
     if (!o) throw Error(MSP_ERR_ARG, "null options");
-    if (o->precision < MSP_FP64 || o->precision > MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_ARG, "precision");
+    if (o->precision < MSP_FP64 || o->precision > MSP_MIXED_BF16) throw Error(MSP_ERR_ARG, "precision");
     if (o->pc < MSP_PC_AMGR || o->pc > MSP_PC_AMGR_SUB) throw Error(MSP_ERR_ARG, "pc");
     if (o->lrc_k < 0 || o->dist < 1 || o->jacobi0 < 1 || o->jacobi < 1 || o->coarse_max < 1 || o->max_levels < 1 ||
         !(o->theta >= 0.0) || !(o->tol > 0.0) || o->maxit < 0 || !(o->trunc0 >= 0.0 && o->trunc0 < 1.0))

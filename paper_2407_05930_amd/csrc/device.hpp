@@ -21,6 +21,25 @@ __device__ __forceinline__ float cvt<float>(Bf16 v) {
     return __uint_as_float(static_cast<uint32_t>(v.bits) << 16);
 }
 
+// storage <-> arithmetic conversions (identity except for bfloat16)
+__device__ __forceinline__ float to_acc(Bf16 v) { return cvt<float>(v); }
+__device__ __forceinline__ float to_acc(float v) { return v; }
+__device__ __forceinline__ double to_acc(double v) { return v; }
+template <typename T>
+__device__ __forceinline__ T from_acc(acc_t<T> v) {
+    return v;
+}
+template <>
+__device__ __forceinline__ Bf16 from_acc<Bf16>(float f) {   // round to nearest even (finite inputs)
+    const uint32_t u = __float_as_uint(f);
+    return Bf16{static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16)};
+}
+// a storage value from a double (casts at the boundary of the V-cycle)
+template <typename T>
+__device__ __forceinline__ T from_double(double v) {
+    return from_acc<T>(static_cast<acc_t<T>>(v));
+}
+
 constexpr int kBlock = 256;
 
 template <typename T, int VW>
@@ -38,11 +57,12 @@ __device__ __forceinline__ void st(T* p, const Pack<T, VW>& v) {
 }
 
 // Lane layout of an n x C row-major multivector: each row is handled by
-// LPR = C / VW lanes with VW consecutive columns per lane (16-byte accesses
-// where the row is wide enough); a 256-thread block covers RPB rows.
+// LPR = C / VW lanes with VW consecutive columns per lane (lane_width
+// columns: 16-byte accesses, 8-byte for bfloat16, where the row is wide
+// enough); a 256-thread block covers RPB rows.
 template <typename T, int C>
 struct Lanes {
-    static constexpr int VW = (16 / (int)sizeof(T)) < C ? (16 / (int)sizeof(T)) : C;
+    static constexpr int VW = lane_width((int)sizeof(T)) < C ? lane_width((int)sizeof(T)) : C;
     static constexpr int LPR = C / VW;
     static constexpr int RPB = kBlock / LPR;
 };
@@ -54,29 +74,30 @@ struct Lanes {
 template <typename T, int C, int VW, typename TV = T, bool SETS = false>
 __device__ __forceinline__ void row_accumulate(int32_t k0, int32_t k1, int step, const int32_t* __restrict__ ci,
                                                const TV* __restrict__ va, const T* __restrict__ X, int lane,
-                                               T* acc, int vs = 1) {
-    auto val = [&](int32_t k) -> T { return cvt<T>(va[SETS ? (int64_t)k * vs : (int64_t)k]); };
+                                               acc_t<T>* acc, int vs = 1) {
+    using TC = acc_t<T>;
+    auto val = [&](int32_t k) -> TC { return cvt<TC>(va[SETS ? (int64_t)k * vs : (int64_t)k]); };
     int32_t k = k0;
     for (; k + 3 * step < k1; k += 4 * step) {
         const int32_t c0 = ci[k], c1 = ci[k + step], c2 = ci[k + 2 * step], c3 = ci[k + 3 * step];
-        const T a0 = val(k), a1 = val(k + step), a2 = val(k + 2 * step), a3 = val(k + 3 * step);
+        const TC a0 = val(k), a1 = val(k + step), a2 = val(k + 2 * step), a3 = val(k + 3 * step);
         const Pack<T, VW> x0 = ld<T, VW>(X + (int64_t)c0 * C + lane * VW);
         const Pack<T, VW> x1 = ld<T, VW>(X + (int64_t)c1 * C + lane * VW);
         const Pack<T, VW> x2 = ld<T, VW>(X + (int64_t)c2 * C + lane * VW);
         const Pack<T, VW> x3 = ld<T, VW>(X + (int64_t)c3 * C + lane * VW);
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
-            acc[e] += a0 * x0.e[e];
-            acc[e] += a1 * x1.e[e];
-            acc[e] += a2 * x2.e[e];
-            acc[e] += a3 * x3.e[e];
+            acc[e] += a0 * to_acc(x0.e[e]);
+            acc[e] += a1 * to_acc(x1.e[e]);
+            acc[e] += a2 * to_acc(x2.e[e]);
+            acc[e] += a3 * to_acc(x3.e[e]);
         }
     }
     for (; k < k1; k += step) {
         const Pack<T, VW> x = ld<T, VW>(X + (int64_t)ci[k] * C + lane * VW);
-        const T a = val(k);
+        const TC a = val(k);
 #pragma unroll
-        for (int e = 0; e < VW; ++e) acc[e] += a * x.e[e];
+        for (int e = 0; e < VW; ++e) acc[e] += a * to_acc(x.e[e]);
     }
 }
 
@@ -91,16 +112,17 @@ __device__ __forceinline__ void row_accumulate(int32_t k0, int32_t k1, int step,
 template <typename T, int C, int VW, int LPR, typename TV = T>
 __device__ __forceinline__ void row_accumulate_bcast(int32_t k0, int32_t k1, const int32_t* __restrict__ ci,
                                                      const TV* __restrict__ va, const T* __restrict__ X, int lane,
-                                                     int base, T* acc) {
+                                                     int base, acc_t<T>* acc) {
+    using TC = acc_t<T>;
     constexpr int CH = LPR < 8 ? LPR : 8;
     for (int32_t kb = k0; kb < k1; kb += CH) {
         const int32_t kk = kb + lane;
         const bool have = lane < CH && kk < k1;
         const int32_t c = have ? ci[kk] : 0;
-        const T a = have ? cvt<T>(va[kk]) : T(0);
+        const TC a = have ? cvt<TC>(va[kk]) : TC(0);
         const int cnt = k1 - kb < CH ? k1 - kb : CH;
         Pack<T, VW> xs[CH];
-        T as[CH];
+        TC as[CH];
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
             const int32_t cq = __shfl(c, base + q, 64);
@@ -111,7 +133,7 @@ __device__ __forceinline__ void row_accumulate_bcast(int32_t k0, int32_t k1, con
         for (int q = 0; q < CH; ++q) {
             if (q < cnt) {
 #pragma unroll
-                for (int e = 0; e < VW; ++e) acc[e] += as[q] * xs[q].e[e];
+                for (int e = 0; e < VW; ++e) acc[e] += as[q] * to_acc(xs[q].e[e]);
             }
         }
     }
@@ -124,8 +146,9 @@ __device__ __forceinline__ void row_accumulate_bcast(int32_t k0, int32_t k1, con
 template <typename T, int C, int VW, int LPR, typename TV = T>
 __device__ __forceinline__ void row_accumulate_bcast_sets(int32_t k0, int32_t k1, const int32_t* __restrict__ ci,
                                                           const TV* __restrict__ va, const T* __restrict__ X,
-                                                          int lane, int base, T* acc, int vs, const int* set,
+                                                          int lane, int base, acc_t<T>* acc, int vs, const int* set,
                                                           bool uniform) {
+    using TC = acc_t<T>;
     constexpr int CH = LPR < 8 ? LPR : 8;
     for (int32_t kb = k0; kb < k1; kb += CH) {
         const int32_t kk = kb + lane;
@@ -143,12 +166,12 @@ __device__ __forceinline__ void row_accumulate_bcast_sets(int32_t k0, int32_t k1
             if (q < cnt) {
                 const TV* vk = va + (int64_t)(kb + q) * vs;
                 if (uniform) {
-                    const T a = cvt<T>(vk[set[0]]);
+                    const TC a = cvt<TC>(vk[set[0]]);
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) acc[e] += a * xs[q].e[e];
+                    for (int e = 0; e < VW; ++e) acc[e] += a * to_acc(xs[q].e[e]);
                 } else {
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) acc[e] += cvt<T>(vk[set[e]]) * xs[q].e[e];
+                    for (int e = 0; e < VW; ++e) acc[e] += cvt<TC>(vk[set[e]]) * to_acc(xs[q].e[e]);
                 }
             }
         }
@@ -160,13 +183,14 @@ __device__ __forceinline__ void row_accumulate_bcast_sets(int32_t k0, int32_t k1
 template <typename T, int C, int VW, typename TV = T>
 __device__ __forceinline__ void row_accumulate_sets(int32_t k0, int32_t k1, int step,
                                                     const int32_t* __restrict__ ci, const TV* __restrict__ va,
-                                                    const T* __restrict__ X, int lane, T* acc, int vs,
+                                                    const T* __restrict__ X, int lane, acc_t<T>* acc, int vs,
                                                     const int* set) {
+    using TC = acc_t<T>;
     for (int32_t k = k0; k < k1; k += step) {
         const Pack<T, VW> x = ld<T, VW>(X + (int64_t)ci[k] * C + lane * VW);
         const TV* vk = va + (int64_t)k * vs;
 #pragma unroll
-        for (int e = 0; e < VW; ++e) acc[e] += cvt<T>(vk[set[e]]) * x.e[e];
+        for (int e = 0; e < VW; ++e) acc[e] += cvt<TC>(vk[set[e]]) * to_acc(x.e[e]);
     }
 }
 

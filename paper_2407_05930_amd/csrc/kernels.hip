@@ -25,20 +25,22 @@ namespace msp {
 // va[k * vs + a]) and column c is multiplied by set min(c / m, vs - 1): one
 // pass applies a different operator of one sparsity pattern to every
 // subsystem's columns.
+// T is the storage type of the multivectors; arithmetic is in acc_t<T>.
 template <typename T, typename TV, int C, bool SETS>
 __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ ci,
                                                  const TV* __restrict__ va, const T* __restrict__ X,
-                                                 T* Y, const T* Z, T alpha, T beta,
+                                                 T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta,
                                                  const double* __restrict__ sigma, int S, int m, int vs) {
     using L = Lanes<T, C>;
+    using TC = acc_t<T>;
     constexpr int VW = L::VW;
     const int64_t row = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * L::RPB + threadIdx.x / L::LPR;
     const int lane = threadIdx.x % L::LPR;
     if (row >= n) return;
-    T acc[VW];
+    TC acc[VW];
 #pragma unroll
-    for (int e = 0; e < VW; ++e) acc[e] = T(0);
+    for (int e = 0; e < VW; ++e) acc[e] = TC(0);
     constexpr bool BC = L::LPR >= 4;   // broadcast row entries across the row's lanes
     const int base = (int)(threadIdx.x % 64) - lane;
     if constexpr (SETS) {
@@ -64,17 +66,17 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
             const int a = (lane * VW + e) / m;
-            if (a < S) acc[e] += (T)sigma[row * S + a] * x.e[e];
+            if (a < S) acc[e] += (TC)sigma[row * S + a] * to_acc(x.e[e]);
         }
     }
     Pack<T, VW> out;
     if (Z) {
         const Pack<T, VW> z = ld<T, VW>(Z + row * C + lane * VW);
 #pragma unroll
-        for (int e = 0; e < VW; ++e) out.e[e] = alpha * acc[e] + beta * z.e[e];
+        for (int e = 0; e < VW; ++e) out.e[e] = from_acc<T>(alpha * acc[e] + beta * to_acc(z.e[e]));
     } else {
 #pragma unroll
-        for (int e = 0; e < VW; ++e) out.e[e] = alpha * acc[e];
+        for (int e = 0; e < VW; ++e) out.e[e] = from_acc<T>(alpha * acc[e]);
     }
     st<T, VW>(Y + row * C + lane * VW, out);
 }
@@ -86,20 +88,21 @@ template <typename T, typename TV, int C, int G, bool SETS>
 __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        const TV* __restrict__ va, const T* __restrict__ X,
-                                                       T* Y, const T* Z, T alpha, T beta, int vs, int m,
-                                                       const double* __restrict__ sigma, int S) {
+                                                       T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs,
+                                                       int m, const double* __restrict__ sigma, int S) {
     using L = Lanes<T, C>;
+    using TC = acc_t<T>;
     constexpr int VW = L::VW;
     constexpr int TPR = G * L::LPR;             // threads per row
     constexpr int RPB = kBlock / TPR;           // rows per block
-    __shared__ T sm[kBlock * VW];
+    __shared__ TC sm[kBlock * VW];
     const int slot = threadIdx.x / TPR;
     const int g = (threadIdx.x % TPR) / L::LPR;
     const int lane = threadIdx.x % L::LPR;
     const int64_t row = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * RPB + slot;
-    T acc[VW];
+    TC acc[VW];
 #pragma unroll
-    for (int e = 0; e < VW; ++e) acc[e] = T(0);
+    for (int e = 0; e < VW; ++e) acc[e] = TC(0);
     if (row < n) {
         if constexpr (SETS) {
             int set[VW];
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
     if (g == 0 && row < n) {
         // sm index of (slot, group q, lane, e) = ((slot * G + q) * LPR + lane) * VW + e
 #pragma unroll
-        for (int e = 0; e < VW; ++e) acc[e] = T(0);
+        for (int e = 0; e < VW; ++e) acc[e] = TC(0);
         for (int q = 0; q < G; ++q) {
 #pragma unroll
             for (int e = 0; e < VW; ++e) acc[e] += sm[((slot * G + q) * L::LPR + lane) * VW + e];
@@ -127,17 +130,17 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
 #pragma unroll
             for (int e = 0; e < VW; ++e) {
                 const int a = (lane * VW + e) / m;
-                if (a < S) acc[e] += (T)sigma[row * S + a] * x.e[e];
+                if (a < S) acc[e] += (TC)sigma[row * S + a] * to_acc(x.e[e]);
             }
         }
         Pack<T, VW> out;
         if (Z) {
             const Pack<T, VW> z = ld<T, VW>(Z + row * C + lane * VW);
 #pragma unroll
-            for (int e = 0; e < VW; ++e) out.e[e] = alpha * acc[e] + beta * z.e[e];
+            for (int e = 0; e < VW; ++e) out.e[e] = from_acc<T>(alpha * acc[e] + beta * to_acc(z.e[e]));
         } else {
 #pragma unroll
-            for (int e = 0; e < VW; ++e) out.e[e] = alpha * acc[e];
+            for (int e = 0; e < VW; ++e) out.e[e] = from_acc<T>(alpha * acc[e]);
         }
         st<T, VW>(Y + row * C + lane * VW, out);
     }
@@ -429,14 +432,14 @@ __global__ __launch_bounds__(kBlock) void k_dense_part(int64_t nL, int64_t kchun
         }
         for (int q = threadIdx.x; q < KT * C; q += kBlock) {
             const int64_t gk = k0 + q / C;
-            sY[q] = gk < ke ? y[gk * C + q % C] : T(0);
+            sY[q] = gk < ke ? y[gk * C + q % C] : T{};
         }
         __syncthreads();
 #pragma unroll 8
         for (int kk = 0; kk < KT; ++kk) {
             const double a = sM[r * KT + kk];
 #pragma unroll
-            for (int e = 0; e < VW; ++e) acc[e] += a * (double)sY[kk * C + lane * VW + e];
+            for (int e = 0; e < VW; ++e) acc[e] += a * (double)to_acc(sY[kk * C + lane * VW + e]);
         }
         __syncthreads();
     }
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_sets(int64_t nL, int C, int S, 
     const int64_t ak = idx / MP;
     const int a = (int)(ak / nL);
     const int64_t k = ak % nL;
-    yp[idx] = j < m ? y[k * C + a * m + j] : T(0);
+    yp[idx] = j < m ? y[k * C + a * m + j] : T{};
 }
 
 // Per-subsystem coarsest solves: out[:, a*m + j] = Minv_a y[:, a*m + j] for
@@ -493,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_sets(int64_t nL, int C, int S,
         for (int q = 0; q < MP; q += PW) {
             const Pack<T, PW> v = ld<T, PW>(ya + k * MP + q);
 #pragma unroll
-            for (int e = 0; e < PW; ++e) xv[q + e] = (double)v.e[e];
+            for (int e = 0; e < PW; ++e) xv[q + e] = (double)to_acc(v.e[e]);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -516,12 +519,12 @@ __global__ __launch_bounds__(kBlock) void k_dense_sets(int64_t nL, int C, int S,
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int j = 0; j < MP; ++j)
-            if (lane == r * MP + j && j < m && row0 + r < nL) out[(row0 + r) * C + a * m + j] = (T)acc[r][j];
+            if (lane == r * MP + j && j < m && row0 + r < nL) out[(row0 + r) * C + a * m + j] = from_double<T>(acc[r][j]);
     if (a == S - 1) {
         const int pad = C - S * m;
         for (int q = lane; q < R * pad; q += W) {
             const int64_t i = row0 + q / pad;
-            if (i < nL) out[i * C + S * m + q % pad] = T(0);
+            if (i < nL) out[i * C + S * m + q % pad] = T{};
         }
     }
 }
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_sum(int64_t len, int ks, int C
     double s = 0.0;
     if ((int)(i % C) < ncol)
         for (int q = 0; q < ks; ++q) s += part[(int64_t)q * len + i];
-    out[i] = (T)s;
+    out[i] = from_double<T>(s);
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -549,7 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(int64_t len, T* __restrict__ p,
 template <typename TO, typename TI>
 __global__ __launch_bounds__(kBlock) void k_cast(int64_t len, const TI* __restrict__ a, TO* __restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < len) b[i] = (TO)a[i];
+    if (i < len) b[i] = from_double<TO>(static_cast<double>(to_acc(a[i])));
 }
 
 // ------------------------------------------------------------------ column-wise vector ops
@@ -695,6 +698,20 @@ __global__ __launch_bounds__(kBlock) void k_kappa_grad(int64_t n_b, int S, int64
     grad[i] = acc;
 }
 
+// pub[0..1] = flags[0..1], then pub[2] = seq: a solve's flags published to
+// fine-grained host memory; the sequence number is stored last, after a
+// system-scope fence, so a host that sees seq also sees the flags.
+__global__ void k_publish_flags(const int* __restrict__ flags, int* pub, int seq) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        volatile int* v = pub;
+        v[0] = flags[0];
+        v[1] = flags[1];
+        __threadfence_system();
+        v[2] = seq;
+        __threadfence_system();
+    }
+}
+
 // out[2i], out[2i+1] = breakdown flag and active-column count of system i
 __global__ void k_gather_flags(int nsys, int* const* __restrict__ ptrs, int* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -727,7 +744,8 @@ constexpr bool sets_ok() {
 
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
-                       const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m, int vs) {
+                       const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, const double* sigma, int S, int m,
+                       int vs) {
     if (n <= 0) return hipSuccess;
     if (vs > 1 && (!sets_ok<TV>() || m < 1)) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
@@ -747,7 +765,7 @@ hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, cons
 
 template <typename T, typename TV, int CC, int G>
 static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va, const T* X,
-                         T* Y, const T* Z, T alpha, T beta, int vs, int m, const double* sigma, int S) {
+                         T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m, const double* sigma, int S) {
     constexpr int TPR = G * Lanes<T, CC>::LPR;
     if constexpr (TPR <= kBlock) {
         constexpr int RPB = kBlock / TPR;
@@ -765,7 +783,7 @@ static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int
 
 template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
-                             const TV* va, const T* X, T* Y, const T* Z, T alpha, T beta, int vs, int m,
+                             const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m,
                              const double* sigma, int S) {
     if (n <= 0) return hipSuccess;
     if ((vs > 1 || sigma) && m < 1) return hipErrorInvalidValue;
@@ -789,13 +807,14 @@ hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int3
 
 #define MSP_SPMM_INST(T, TV)                                                                                         \
     template hipError_t launch_spmm<T, TV>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const TV*,     \
-                                           const T*, T*, const T*, T, T, const double*, int, int, int);              \
+                                           const T*, T*, const T*, acc_t<T>, acc_t<T>, const double*, int, int, int); \
     template hipError_t launch_spmm_split<T, TV>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,     \
-                                                 const TV*, const T*, T*, const T*, T, T, int, int, const double*, \
-                                                 int);
+                                                 const TV*, const T*, T*, const T*, acc_t<T>, acc_t<T>, int, int,   \
+                                                 const double*, int);
 MSP_SPMM_INST(double, double)
 MSP_SPMM_INST(float, float)
 MSP_SPMM_INST(float, Bf16)
+MSP_SPMM_INST(Bf16, float)
 
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
@@ -899,8 +918,9 @@ hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, co
 }
 
 // k-chunks of the dense product: about 1024 blocks in total, whole tiles per chunk
-int dense_splits(int C, int64_t nL, bool fp32) {
-    const int lpr = fp32 ? (C >= 4 ? C / 4 : 1) : (C >= 2 ? C / 2 : 1);
+int dense_splits(int C, int64_t nL, int elem_bytes) {
+    const int vw = lane_width(elem_bytes);
+    const int lpr = C >= vw ? C / vw : 1;   // lanes per row of Lanes<T, C> for a T of elem_bytes
     const int64_t rb = kBlock / lpr;
     const int64_t rows = (nL + rb - 1) / rb;
     int64_t ks = (1024 + rows - 1) / rows;
@@ -913,7 +933,7 @@ int dense_splits(int C, int64_t nL, bool fp32) {
 
 template <typename T>
 hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part) {
-    const int ks = dense_splits(C, nL, sizeof(T) == 4);
+    const int ks = dense_splits(C, nL, (int)sizeof(T));
     const int64_t tiles = (nL + 31) / 32;
     const int64_t kchunk = ((tiles + ks - 1) / ks) * 32;
     MSP_DISPATCH_C(C, {
@@ -927,6 +947,7 @@ hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, c
 }
 template hipError_t launch_dense<double>(hipStream_t, int, int64_t, const double*, const double*, double*, double*);
 template hipError_t launch_dense<float>(hipStream_t, int, int64_t, const double*, const float*, float*, double*);
+template hipError_t launch_dense<Bf16>(hipStream_t, int, int64_t, const double*, const Bf16*, Bf16*, double*);
 
 static int pow2_at_least(int x) {
     int p = 1;
@@ -984,6 +1005,8 @@ template hipError_t launch_dense_sets<double>(hipStream_t, int, int, int, int64_
                                               double*, double*, int);
 template hipError_t launch_dense_sets<float>(hipStream_t, int, int, int, int64_t, const double*, const float*,
                                              float*, float*, int);
+template hipError_t launch_dense_sets<Bf16>(hipStream_t, int, int, int, int64_t, const double*, const Bf16*, Bf16*,
+                                            Bf16*, int);
 
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {
@@ -994,6 +1017,12 @@ hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {
 template hipError_t launch_fill<double>(hipStream_t, int64_t, double*, double);
 template hipError_t launch_fill<float>(hipStream_t, int64_t, float*, float);
 template hipError_t launch_fill<int>(hipStream_t, int64_t, int*, int);
+template hipError_t launch_fill<Bf16>(hipStream_t, int64_t, Bf16*, Bf16);
+
+hipError_t launch_publish_flags(hipStream_t st, const int* flags, int* pub, int seq) {
+    hipLaunchKernelGGL(k_publish_flags, dim3(1), dim3(64), 0, st, flags, pub, seq);
+    return hipGetLastError();
+}
 
 hipError_t launch_gather_flags(hipStream_t st, int nsys, int* const* ptrs, int* out) {
     hipLaunchKernelGGL(k_gather_flags, dim3(blocks_for(nsys, 64)), dim3(64), 0, st, nsys, ptrs, out);
@@ -1059,5 +1088,7 @@ hipError_t launch_cast(hipStream_t st, int64_t len, const TI* a, TO* b) {
 }
 template hipError_t launch_cast<float, double>(hipStream_t, int64_t, const double*, float*);
 template hipError_t launch_cast<double, float>(hipStream_t, int64_t, const float*, double*);
+template hipError_t launch_cast<Bf16, double>(hipStream_t, int64_t, const double*, Bf16*);
+template hipError_t launch_cast<double, Bf16>(hipStream_t, int64_t, const Bf16*, double*);
 
 }  // namespace msp

@@ -9,9 +9,28 @@
 namespace msp {
 
 // bfloat16 storage (upper 16 bits of an IEEE binary32), used for matrix values
+// and, in the MSP_MIXED_BF16 mode, for the V-cycle multivectors
 struct Bf16 {
     uint16_t bits;
 };
+
+// Arithmetic type of a storage type: multivectors stored in bfloat16 are
+// loaded into FP32 registers and accumulated in FP32.
+template <typename T>
+struct Acc {
+    using type = T;
+};
+template <>
+struct Acc<Bf16> {
+    using type = float;
+};
+template <typename T>
+using acc_t = typename Acc<T>::type;
+
+// Columns per lane of an n x C multivector of elem_bytes elements: 16-byte
+// vectors for FP32/FP64; 8-byte vectors (4 columns) for bfloat16, so that a
+// lane's columns stay within one subsystem for m = 4 as they do in FP32.
+constexpr int lane_width(int elem_bytes) { return (elem_bytes == 2 ? 8 : 16) / elem_bytes; }
 
 // Y = alpha (A X [+ outer diagonal]) + beta Z with matrix values of type TV
 // (TV = T, or Bf16 with T = float) and multivectors of type T.  vs > 1: the
@@ -19,11 +38,12 @@ struct Bf16 {
 // FP64/FP32 values only) and column c uses set min(c / m, vs - 1).
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
-                       const T* X, T* Y, const T* Z, T alpha, T beta, const double* sigma, int S, int m, int vs);
+                       const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, const double* sigma, int S, int m,
+                       int vs);
 // Same product for long rows: G lane groups share each row (G a power of two).
 template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
-                             const TV* va, const T* X, T* Y, const T* Z, T alpha, T beta, int vs, int m,
+                             const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m,
                              const double* sigma, int S);
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
@@ -54,8 +74,8 @@ hipError_t launch_colnorm2(hipStream_t st, int64_t n, int m, const double* b, do
                            double* out);
 hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, const double* bn2, double* thr);
 
-// out = Minv y (dense FP64 coarsest solve, split over k; part: dense_splits() * nL * C doubles)
-int dense_splits(int C, int64_t nL, bool fp32);
+// out = Minv y (dense FP64 coarsest solve, split over k; part: dense_splits(C, nL, sizeof(T)) * nL * C doubles)
+int dense_splits(int C, int64_t nL, int elem_bytes);
 template <typename T>
 hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part);
 // Per-subsystem coarsest solves: columns a*m .. a*m + m - 1 times Minv + a*nL*nL
@@ -71,6 +91,8 @@ hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v);
 template <typename TO, typename TI>
 hipError_t launch_cast(hipStream_t st, int64_t len, const TI* a, TO* b);
 
+// flags[0..1] to fine-grained host memory pub (device-visible pointer), then pub[2] = seq
+hipError_t launch_publish_flags(hipStream_t st, const int* flags, int* pub, int seq);
 // flags of every system of a batch into one array (2 ints per system)
 hipError_t launch_gather_flags(hipStream_t st, int nsys, int* const* ptrs, int* out);
 

@@ -91,7 +91,8 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
                                                         const double* __restrict__ z, const TU* __restrict__ U,
                                                         int S, int k, int m, double* __restrict__ partial_rr,
                                                         double* __restrict__ partial_rz,
-                                                        double* __restrict__ partial_lrc, float* __restrict__ y32) {
+                                                        double* __restrict__ partial_lrc, float* __restrict__ y32,
+                                                        Bf16* __restrict__ y16) {
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
     constexpr int KA = KMAX > 0 ? KMAX : 1;
     __shared__ double sm[kBlock * VW];
@@ -122,6 +123,12 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
 #pragma unroll
             for (int e = 0; e < VW; ++e) yv.e[e] = (float)rv.e[e];
             st<float, VW>(y32 + o, yv);
+        }
+        if (y16) {   // bfloat16 copy of r (V-cycle multivectors in bfloat16)
+            Pack<Bf16, VW> yv;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) yv.e[e] = from_double<Bf16>(rv.e[e]);
+            st<Bf16, VW>(y16 + o, yv);
         }
 #pragma unroll
         for (int e = 0; e < VW; ++e) a_rr[e] += rv.e[e] * rv.e[e];
@@ -255,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
         Pack<double, VW> zv;
         const Pack<TS, VW> sv = ld<TS, VW>(s + o);
 #pragma unroll
-        for (int e = 0; e < VW; ++e) zv.e[e] = (double)sv.e[e];
+        for (int e = 0; e < VW; ++e) zv.e[e] = (double)to_acc(sv.e[e]);
         if (LRC) {
 #pragma unroll
             for (int e = 0; e < VW; ++e) {
@@ -360,41 +367,41 @@ hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial
 template <int CC, bool UPD, bool FLEX, int KMAX, typename TU>
 static void upd_launch(hipStream_t st, int nb, int64_t n, double* r, const double* q, const double* alpha,
                        const double* z, const TU* U, int S, int k, int m, double* prr, double* prz, double* plrc,
-                       float* y32) {
+                       float* y32, Bf16* y16) {
     constexpr int VW = DL<CC>::VW;
     const size_t lds = KMAX > 0 ? sizeof(double) * 8 * kBlock * VW : 0;   // projection partials, 8 at a time
     hipLaunchKernelGGL((k_update_dots<CC, UPD, FLEX, KMAX, TU>), dim3(nb), dim3(kBlock), lds, st, n, r, q, alpha, z,
-                       U, S, k, m, prr, prz, plrc, y32);
+                       U, S, k, m, prr, prz, plrc, y32, y16);
 }
 
 template <typename TU>
 hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* r,
                               const double* q, const double* alpha, const double* z, const TU* U, int S, int m,
-                              double* prr, double* prz, double* plrc, float* y32) {
+                              double* prr, double* prz, double* plrc, float* y32, Bf16* y16) {
     if (k > 16) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         if (k > 8) {
-            if (upd && flex) upd_launch<CC, true, true, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else if (upd) upd_launch<CC, true, false, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else upd_launch<CC, false, false, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            if (upd && flex) upd_launch<CC, true, true, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
+            else if (upd) upd_launch<CC, true, false, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
+            else upd_launch<CC, false, false, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
         } else if (k > 0) {
-            if (upd && flex) upd_launch<CC, true, true, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else if (upd) upd_launch<CC, true, false, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else upd_launch<CC, false, false, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            if (upd && flex) upd_launch<CC, true, true, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
+            else if (upd) upd_launch<CC, true, false, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
+            else upd_launch<CC, false, false, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
         } else {
-            if (upd && flex) upd_launch<CC, true, true, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else if (upd) upd_launch<CC, true, false, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
-            else upd_launch<CC, false, false, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32);
+            if (upd && flex) upd_launch<CC, true, true, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
+            else if (upd) upd_launch<CC, true, false, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
+            else upd_launch<CC, false, false, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
         }
     });
     return hipGetLastError();
 }
 template hipError_t launch_update_dots<float>(hipStream_t, int, int, bool, bool, int, int64_t, double*,
                                               const double*, const double*, const double*, const float*, int, int,
-                                              double*, double*, double*, float*);
+                                              double*, double*, double*, float*, Bf16*);
 template hipError_t launch_update_dots<double>(hipStream_t, int, int, bool, bool, int, int64_t, double*,
                                                const double*, const double*, const double*, const double*, int, int,
-                                               double*, double*, double*, float*);
+                                               double*, double*, double*, float*, Bf16*);
 
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
                             const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
@@ -427,6 +434,10 @@ template hipError_t launch_zfinish<double, float>(hipStream_t, int, int, int64_t
                                                   const double*, const float*, const double*, int, int, int, double*);
 template hipError_t launch_zfinish<float, double>(hipStream_t, int, int, int64_t, const float*, double*,
                                                   const double*, const double*, const double*, int, int, int, double*);
+template hipError_t launch_zfinish<Bf16, float>(hipStream_t, int, int, int64_t, const Bf16*, double*, const double*,
+                                                const float*, const double*, int, int, int, double*);
+template hipError_t launch_zfinish<Bf16, double>(hipStream_t, int, int, int64_t, const Bf16*, double*, const double*,
+                                                 const double*, const double*, int, int, int, double*);
 
 hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
                            const int* active, const double* rzold, double* rho, double* beta, double* rz) {

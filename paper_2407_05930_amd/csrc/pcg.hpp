@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "kernels.hpp"
+
 namespace msp {
 
 constexpr int kPcgMaxBlocks = 2048;   // grid of the dot-producing kernels (grid-stride over row tiles)
@@ -20,7 +22,7 @@ hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial
 template <typename TU>
 hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* r,
                               const double* q, const double* alpha, const double* z, const TU* U, int S, int m,
-                              double* prr, double* prz, double* plrc, float* y32);
+                              double* prr, double* prz, double* plrc, float* y32, Bf16* y16);
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
                             const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
                             int* iters, int* flags, double* rnorm, double* rzold, double* W);

@@ -41,7 +41,7 @@ class Solver:
     """Setup from the full symmetric matrix ``A`` (scipy CSR or anything with
     indptr/indices/data) and the symmetry map ``img`` (n_b x 2^s, row of
     image a of base cell i); options as in ``msp_opts`` (``k`` = LRC rank,
-    ``precision`` in {"fp64", "mixed", "mixed_bf16g"}, ``pc`` in
+    ``precision`` in {"fp64", "mixed", "mixed_bf16g", "mixed_bf16"}, ``pc`` in
     {"amgr", "fsai", "none", "amgr_sub"}, ``device`` = -1 for a host-only setup)."""
 
     def __init__(self, A, img, **opts):

@@ -289,3 +289,39 @@ def test_full_size_channel_per_subsystem_amgr():
         assert np.all(rr <= 2e-10)
         sv.close()
     assert its["amgr_sub"] < its["amgr"]
+
+
+@pytest.mark.parametrize("pc", ["amgr", "amgr_sub"])
+def test_bf16_multivector_vcycle_reaches_tolerance(pc):
+    """V-cycle multivectors stored in bfloat16 (FP32 arithmetic, FP64 outer
+    PCG): the flexible PCG still reaches 1e-10 in at most 10% (plus one) more
+    iterations than the FP32-vector mode; the error against the FP64 oracle
+    is stated."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    p = make_problem((32, 32, 32), s=3, m=2, seed=6, jitter=0.2, kappa="lognormal")
+    ctx = krylov.setup(p.A, p.img, amg.AMGOptions(coarse_max=64))
+    ref = krylov.solve(ctx, p.b, tol=1e-12)
+    b = torch.from_numpy(p.b).cuda()
+    its = {}
+    for prec in ("mixed", "mixed_bf16"):
+        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, pc=pc, coarse_max=64)
+        x = sv.solve(b).cpu().numpy()
+        rr = krylov.true_relres(p.A, x, p.b)
+        err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+        its[prec] = sv.last.iters
+        _say(pc, prec, "its", sv.last.iters, "relres", rr.max(), "err", err)
+        assert np.all(rr <= 1.5e-10)
+        assert err <= 1e-7
+    assert its["mixed_bf16"] <= int(1.1 * its["mixed"]) + 1
+
+
+def test_full_size_channel_bf16_multivectors():
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    p = config_problem("channel3d_128_s3")
+    sv = Solver(p.A, p.img, tol=1e-10, precision="mixed_bf16", pc="amgr_sub", k=8)
+    x = sv.solve(torch.from_numpy(p.b).cuda()).cpu().numpy()
+    rr = krylov.true_relres(p.A, x, p.b)
+    _say("128^3 bf16 vectors iters", sv.last.iters, "relres", rr, "t", sv.last.t_solve_s)
+    assert np.all(rr <= 2e-10)
