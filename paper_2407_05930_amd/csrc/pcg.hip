@@ -19,6 +19,10 @@ namespace msp {
 template <int C>
 using DL = Lanes<double, C>;
 
+// low-rank projections reduced per LDS pass in k_update_dots (LDS: 4 * 256 * VW doubles,
+// small enough that registers, not LDS, bound the kernel's occupancy)
+constexpr int kUpdTch = 4;
+
 
 // q = (A_inn + diag-outer) p; partial[b, c] = this block's sum of p[:, c] q[:, c]
 template <int C>
@@ -164,20 +168,20 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
     block_column_sums<C, VW>(a_rr, sm, partial_rr + (int64_t)blockIdx.x * C);
     if (FLEX) block_column_sums<C, VW>(a_rz, sm, partial_rz + (int64_t)blockIdx.x * C);
     if (KMAX > 0) {
-        // up to 8 projections per pass: slm[(tt * kBlock + thread) * VW + e] for t = t0 + tt,
+        // kUpdTch projections per pass: slm[(tt * kBlock + thread) * VW + e] for t = t0 + tt,
         // then one thread per output (column, t) sums the RPB row slots in a fixed order
         extern __shared__ double slm[];
         const int O = S * k * m;
 #pragma unroll
-        for (int t0 = 0; t0 < KA; t0 += 8) {
+        for (int t0 = 0; t0 < KA; t0 += kUpdTch) {
             if (t0 >= k) break;
 #pragma unroll
-            for (int tt = 0; tt < 8 && t0 + tt < KA; ++tt) {
+            for (int tt = 0; tt < kUpdTch && t0 + tt < KA; ++tt) {
 #pragma unroll
                 for (int e = 0; e < VW; ++e) slm[(tt * kBlock + threadIdx.x) * VW + e] = a_l[e][t0 + tt];
             }
             __syncthreads();
-            const int nt = k - t0 < 8 ? k - t0 : 8;
+            const int nt = k - t0 < kUpdTch ? k - t0 : kUpdTch;
             for (int q = threadIdx.x; q < S * m * nt; q += kBlock) {
                 const int col = q % (S * m), tt = q / (S * m);
                 double v = 0.0;
@@ -369,7 +373,7 @@ static void upd_launch(hipStream_t st, int nb, int64_t n, double* r, const doubl
                        const double* z, const TU* U, int S, int k, int m, double* prr, double* prz, double* plrc,
                        float* y32, Bf16* y16) {
     constexpr int VW = DL<CC>::VW;
-    const size_t lds = KMAX > 0 ? sizeof(double) * 8 * kBlock * VW : 0;   // projection partials, 8 at a time
+    const size_t lds = KMAX > 0 ? sizeof(double) * kUpdTch * kBlock * VW : 0;   // projection partials per pass
     hipLaunchKernelGGL((k_update_dots<CC, UPD, FLEX, KMAX, TU>), dim3(nb), dim3(kBlock), lds, st, n, r, q, alpha, z,
                        U, S, k, m, prr, prz, plrc, y32, y16);
 }
