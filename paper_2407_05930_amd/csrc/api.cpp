@@ -129,7 +129,8 @@ struct msp_ctx {
     // low-rank corrections: U (n_b x S*k, FP64 or FP32), coefficients (S*k)
     int lrc_k = 0;
     void* d_U = nullptr;
-    bool U32 = false;
+    bool U32 = false;             // U in FP32 (mixed modes)
+    bool U16 = false;             // U in bfloat16 (bfloat16-multivector mode with AMGR)
     double* d_lrc_coef = nullptr;
     double* d_lrc_part = nullptr;
     double* d_lrc_W = nullptr;
@@ -620,13 +621,6 @@ static void precondition_base(msp_ctx* c, Work& w, hipStream_t st, const double*
     }
 }
 
-// z = M^{-1} r on all columns: the shared preconditioner plus the
-// per-subsystem low-rank corrections.
-static void precondition(msp_ctx* c, Work& w, hipStream_t st, const double* r, double* z) {
-    precondition_base(c, w, st, r, z, true);
-    if (c->d_U && amg(c)) lrc_apply(c, w, st, r, z);
-}
-
 static void upload_all(msp_ctx* c) {
     HIPCHECK(hipSetDevice(c->device));
     const bool f32 = mixed(c);
@@ -746,6 +740,7 @@ struct SolvePlan {
     }
 
     double vb() const { return 8.0 * nb * C; }   // bytes of one FP64 multivector pass
+    double ubytes() const { return c->U16 ? 2.0 : (c->U32 ? 4.0 : 8.0); }   // bytes per element of U
 
     // the mixed AMGR mode writes the FP32 V-cycle input in the update kernel
     float* y32() const {
@@ -758,11 +753,15 @@ struct SolvePlan {
     // <r,r>, U^T r and the convergence check (initial: the active flags)
     void update_dots(bool upd) {
         Work& W = *w;
-        const double wu = c->U32 ? 4.0 : 8.0;
+        const double wu = ubytes();
         const double bytes = (upd ? 3.0 : 1.0) * vb() + (flexible && upd ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0) +
                              (y32() ? 4.0 * nb * C : 0.0) + (y16() ? 2.0 * nb * C : 0.0);
         timed(c, KD_UPDATE, bytes, st, [&] {
-            if (c->U32 || !c->d_U)
+            if (c->U16)
+                HIPCHECK(launch_update_dots<Bf16>(st, C, nbp, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
+                                                  static_cast<const Bf16*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
+                                                  y32(), y16()));
+            else if (c->U32 || !c->d_U)
                 HIPCHECK(launch_update_dots<float>(st, C, nbp, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
                                                    static_cast<const float*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
                                                    y32(), y16()));
@@ -793,13 +792,16 @@ struct SolvePlan {
         } else {
             precondition_base(c, W, st, W.r, W.z, true);
         }
-        const double wu = c->U32 ? 4.0 : 8.0;
+        const double wu = ubytes();
         const double bytes =
             (s16 ? 2.0 : (s32 ? 4.0 : 8.0)) * nb * C + 2.0 * vb() + (kl ? nb * S * kl * wu : 0.0);
         const void* U = lrc_amg ? c->d_U : nullptr;
         timed(c, KD_CAST, bytes, st, [&] {
             if (s16) {
-                if (c->U32 || !c->d_U)
+                if (c->U16)
+                    HIPCHECK((launch_zfinish<Bf16, Bf16>(st, C, nbp, nb, s16, W.z, W.r, static_cast<const Bf16*>(U),
+                                                         c->d_lrc_W, S, kl, m, W.pp1)));
+                else if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<Bf16, float>(st, C, nbp, nb, s16, W.z, W.r, static_cast<const float*>(U),
                                                           c->d_lrc_W, S, kl, m, W.pp1)));
                 else
@@ -1609,8 +1611,13 @@ void build_lrc(msp_ctx* c) {
         }
     }
     double* dcm = c->upload(cm.data(), static_cast<int64_t>(cm.size()));
-    c->U32 = mixed(c);
-    if (c->U32) {
+    c->U16 = amg && c->o.precision == MSP_MIXED_BF16;
+    c->U32 = mixed(c) && !c->U16;
+    if (c->U16) {
+        Bf16* U = c->dalloc<Bf16>(n * S * k);
+        HIPCHECK(launch_lrc_combine<Bf16>(st, n, S, k, K, C, V, dcm, U));
+        c->d_U = U;
+    } else if (c->U32) {
         float* U = c->dalloc<float>(n * S * k);
         HIPCHECK(launch_lrc_combine<float>(st, n, S, k, K, C, V, dcm, U));
         c->d_U = U;

@@ -588,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_lrc_combine(int64_t n, int S, int k,
     const int a = at / k, t = at % k;
     double s = 0.0;
     for (int j = 0; j < K; ++j) s += V[((int64_t)j * n + i) * C + a] * cm[((int64_t)a * K + j) * k + t];
-    U[idx] = (TU)s;
+    U[idx] = from_double<TU>(s);
 }
 
 // partial[b, o] = sum over block b's rows of U[i, a*k+t] * R[i, a*m+j],
@@ -607,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void k_lrc_project(int64_t n, int S, int k,
         const int a = at / k;
         double s = 0.0;
         for (int64_t i = r0; i < r1; ++i)
-            s += (double)U[i * (S * k) + at] * R[i * C + a * m + j];
+            s += (double)to_acc(U[i * (S * k) + at]) * R[i * C + a * m + j];
         partial[(int64_t)blockIdx.x * O + o] = s;
     }
 }
@@ -636,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_lrc_expand(int64_t n, int S, int k, 
     const int a = col / m, j = col % m;
     double s = 0.0;
     const TU* u = U + i * (S * k) + a * k;
-    for (int t = 0; t < k; ++t) s += (double)u[t] * W[(a * k + t) * m + j];
+    for (int t = 0; t < k; ++t) s += (double)to_acc(u[t]) * W[(a * k + t) * m + j];
     Z[idx] += s;
 }
 
@@ -1063,6 +1063,8 @@ template hipError_t launch_lrc_combine<double>(hipStream_t, int64_t, int, int, i
                                                const double*, double*);
 template hipError_t launch_lrc_combine<float>(hipStream_t, int64_t, int, int, int, int, const double*,
                                               const double*, float*);
+template hipError_t launch_lrc_combine<Bf16>(hipStream_t, int64_t, int, int, int, int, const double*,
+                                             const double*, Bf16*);
 
 template <typename TU>
 hipError_t launch_lrc_apply(hipStream_t st, int64_t n, int S, int k, int m, int C, const TU* U, const double* R,

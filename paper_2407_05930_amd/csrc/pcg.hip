@@ -154,12 +154,12 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
                             if (t < k) {
                                 const Pack<TU, 4> u4 = ld<TU, 4>(u + t);
 #pragma unroll
-                                for (int q = 0; q < 4 && t + q < KA; ++q) a_l[e][t + q] += (double)u4.e[q] * rv.e[e];
+                                for (int q = 0; q < 4 && t + q < KA; ++q) a_l[e][t + q] += (double)to_acc(u4.e[q]) * rv.e[e];
                             }
                     } else {
 #pragma unroll
                         for (int t = 0; t < KA; ++t)
-                            if (t < k) a_l[e][t] += (double)u[t] * rv.e[e];
+                            if (t < k) a_l[e][t] += (double)to_acc(u[t]) * rv.e[e];
                     }
                 }
             }
@@ -277,14 +277,14 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
                     const double* w = wl + (a * k) * m + j;
                     double t2 = 0.0;
                     int t = 0;
-                    for (; t + 4 <= k; t += 4) {
+                    for (; (k & 3) == 0 && t + 4 <= k; t += 4) {   // aligned 4-wide loads when k % 4 == 0
                         const Pack<TU, 4> u4 = ld<TU, 4>(u + t);
-                        t2 += (double)u4.e[0] * w[t * m];
-                        t2 += (double)u4.e[1] * w[(t + 1) * m];
-                        t2 += (double)u4.e[2] * w[(t + 2) * m];
-                        t2 += (double)u4.e[3] * w[(t + 3) * m];
+                        t2 += (double)to_acc(u4.e[0]) * w[t * m];
+                        t2 += (double)to_acc(u4.e[1]) * w[(t + 1) * m];
+                        t2 += (double)to_acc(u4.e[2]) * w[(t + 2) * m];
+                        t2 += (double)to_acc(u4.e[3]) * w[(t + 3) * m];
                     }
-                    for (; t < k; ++t) t2 += (double)u[t] * w[t * m];
+                    for (; t < k; ++t) t2 += (double)to_acc(u[t]) * w[t * m];
                     zv.e[e] += t2;
                 }
             }
@@ -406,6 +406,9 @@ template hipError_t launch_update_dots<float>(hipStream_t, int, int, bool, bool,
 template hipError_t launch_update_dots<double>(hipStream_t, int, int, bool, bool, int, int64_t, double*,
                                                const double*, const double*, const double*, const double*, int, int,
                                                double*, double*, double*, float*, Bf16*);
+template hipError_t launch_update_dots<Bf16>(hipStream_t, int, int, bool, bool, int, int64_t, double*,
+                                             const double*, const double*, const double*, const Bf16*, int, int,
+                                             double*, double*, double*, float*, Bf16*);
 
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
                             const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
@@ -442,6 +445,8 @@ template hipError_t launch_zfinish<Bf16, float>(hipStream_t, int, int, int64_t, 
                                                 const float*, const double*, int, int, int, double*);
 template hipError_t launch_zfinish<Bf16, double>(hipStream_t, int, int, int64_t, const Bf16*, double*, const double*,
                                                  const double*, const double*, int, int, int, double*);
+template hipError_t launch_zfinish<Bf16, Bf16>(hipStream_t, int, int, int64_t, const Bf16*, double*, const double*,
+                                               const Bf16*, const double*, int, int, int, double*);
 
 hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
                            const int* active, const double* rzold, double* rho, double* beta, double* rz) {
