@@ -43,6 +43,13 @@ struct DevCsr {
     Bf16* v16 = nullptr;      // bfloat16 values (smoother in the BF16 variant)
 };
 
+// Outer diagonal on the device (OuterDiag) with its size for the byte counts.
+struct DevOuter {
+    OuterDiag d{nullptr, nullptr};
+    int64_t rows = 0;     // rows of the operator
+    int64_t carried = 0;  // rows with an outer term
+};
+
 struct DevLevel {
     DevCsr A, P, R, M;
     DevCsr G, GT;             // bfloat16 FSAI factors (BF16 variant only)
@@ -119,8 +126,8 @@ struct msp_ctx {
     int device = -1;
     std::vector<void*> allocs;
     int64_t* d_img = nullptr;
-    double* d_sigma = nullptr;
-    double* d_sigma1 = nullptr;   // pc = AMGR_SUB: sigma_a at the coarse numbers of the interface (level 1)
+    msp::DevOuter dsig;       // outer diagonal of the base rows (compact: interface rows only)
+    msp::DevOuter dsig1;      // pc = AMGR_SUB: the same at level 1 (the interface's coarse numbers)
     msp::DevCsr dAinn, dGf, dGfT;
     std::vector<msp::DevLevel> dl;
     double* d_cinv = nullptr;
@@ -317,13 +324,13 @@ static void resolve_timers(msp_ctx* c) {
 // Algorithmic bytes of Y = alpha (M X) + beta Z: the matrix once, X once,
 // Y written once, Z read once if present, the outer diagonal once.
 template <typename T>
-static double spmm_bytes(const DevCsr& M, int C, bool z, bool sig, int S) {
+static double spmm_bytes(const DevCsr& M, int C, bool z, const DevOuter* sig, int S) {
     const double w = sizeof(T);
     const double wv = (sizeof(T) == 4 && M.v16) ? 2.0 : static_cast<double>(sizeof(typename ValOf<T>::type));
     double b = static_cast<double>(M.nnz) * (wv * M.vs + 4.0) + 4.0 * static_cast<double>(M.nr + 1);
     b += static_cast<double>(M.nc) * C * w + static_cast<double>(M.nr) * C * w;
     if (z) b += static_cast<double>(M.nr) * C * w;
-    if (sig) b += static_cast<double>(M.nr) * S * 8.0;
+    if (sig) b += 4.0 * static_cast<double>(sig->rows) + 8.0 * static_cast<double>(sig->carried) * S;
     return b;
 }
 
@@ -337,7 +344,7 @@ static int log2i(int C) {
 // FP32 products use the bfloat16 values when the matrix carries them.
 template <typename T>
 static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const T* X, T* Y, const T* Z,
-                        acc_t<T> alpha, acc_t<T> beta, const double* sigma, int S, int m) {
+                        acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m) {
     using TV = typename ValOf<T>::type;
     if constexpr (std::is_same<T, float>::value) {
         if (M.v16) {
@@ -359,11 +366,12 @@ static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const
 
 template <typename T>
 static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, const T* X, T* Y, const T* Z,
-                 acc_t<T> alpha, acc_t<T> beta, const double* sigma = nullptr, int S = 1, int m = 1) {
-    const double bytes = c->tm.on[kind] ? spmm_bytes<T>(M, C, Z != nullptr, sigma != nullptr, S) : 0.0;
+                 acc_t<T> alpha, acc_t<T> beta, const DevOuter* sigma = nullptr, int S = 1, int m = 1) {
+    const double bytes = c->tm.on[kind] ? spmm_bytes<T>(M, C, Z != nullptr, sigma, S) : 0.0;
+    const OuterDiag od = sigma ? sigma->d : OuterDiag{nullptr, nullptr};
     const int tuned = M.tuned[tslot<T>()][log2i(C)];
     const int split = tuned ? tuned : M.split;
-    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, X, Y, Z, alpha, beta, sigma, S, m); });
+    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, X, Y, Z, alpha, beta, od, S, m); });
 }
 
 // Autotuner: for every V-cycle matrix, time the candidate lane-group splits
@@ -402,10 +410,12 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
             float best_ms = 1e30f;
             for (int g = 1; g <= 64 && g * lpr <= 256; g *= 2) {   // 256 threads per block
                 if (g > 1 && g > std::max(1.0, avg / 2.0)) break;
-                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0), nullptr, S, mt);
+                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0), OuterDiag{nullptr, nullptr},
+                               S, mt);
                 HIPCHECK(hipEventRecord(e0, st));
                 for (int rep = 0; rep < 3; ++rep)
-                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0), nullptr, S, mt);
+                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0), OuterDiag{nullptr, nullptr},
+                               S, mt);
                 HIPCHECK(hipEventRecord(e1, st));
                 HIPCHECK(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -550,7 +560,7 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     };
     // per-subsystem hierarchy: the reduction level applies each subsystem's
     // operator A_inn + diag(sigma_a); the levels below carry one value set per subsystem
-    const double* sg = !c->sub ? nullptr : (l == 0 ? c->d_sigma : (l == 1 ? c->d_sigma1 : nullptr));
+    const DevOuter* sg = !c->sub ? nullptr : (l == 0 ? &c->dsig : (l == 1 ? &c->dsig1 : nullptr));
     const int m = w.m;
     smooth(y, TC(0));                                                      // pre-smooth from zero: s = M y
     spmm<T>(c, kb + 0, st, C, L.A, s, r, y, TC(-1), TC(1), sg, S, m);      // r = y - A s
@@ -621,11 +631,31 @@ static void precondition_base(msp_ctx* c, Work& w, hipStream_t st, const double*
     }
 }
 
+// Compact outer diagonal: rows whose S values are not all zero, in row order.
+static DevOuter upload_outer(msp_ctx* c, const std::vector<double>& dense, int64_t rows, int S) {
+    std::vector<int32_t> idx(rows, -1);
+    std::vector<double> val;
+    int32_t q = 0;
+    for (int64_t i = 0; i < rows; ++i) {
+        bool any = false;
+        for (int a = 0; a < S; ++a) any |= dense[i * S + a] != 0.0;
+        if (!any) continue;
+        idx[i] = q++;
+        val.insert(val.end(), dense.begin() + i * S, dense.begin() + (i + 1) * S);
+    }
+    DevOuter o;
+    o.rows = rows;
+    o.carried = q;
+    o.d.idx = c->upload(idx.data(), rows);
+    o.d.val = c->upload(val.data(), static_cast<int64_t>(val.size()));
+    return o;
+}
+
 static void upload_all(msp_ctx* c) {
     HIPCHECK(hipSetDevice(c->device));
     const bool f32 = mixed(c);
     c->d_img = c->upload(c->sym.img.data(), static_cast<int64_t>(c->sym.img.size()));
-    c->d_sigma = c->upload(c->sym.sigma.data(), static_cast<int64_t>(c->sym.sigma.size()));
+    c->dsig = upload_outer(c, c->sym.sigma, c->sym.n_b, 1 << c->sym.s);
     c->dAinn = upload_csr(c, c->sym.Ainn, false);
     if (amg(c)) {
         const int S = 1 << c->sym.s;
@@ -652,7 +682,7 @@ static void upload_all(msp_ctx* c) {
                         ++j;
                     }
                     if (j != H.A.nr) throw Error(MSP_ERR_ARG, "coarse numbering of the reduction level");
-                    c->d_sigma1 = c->upload(s1.data(), static_cast<int64_t>(s1.size()));
+                    c->dsig1 = upload_outer(c, s1, H.A.nr, S);
                 } else {
                     D.A = upload_sets(c, H.A, c->subv.A[l], S, f32);
                 }
@@ -846,9 +876,9 @@ struct SolvePlan {
 
     void half_a() {
         Work& W = *w;
-        const double opb = spmm_bytes<double>(c->dAinn, C, false, true, S) + vb();
+        const double opb = spmm_bytes<double>(c->dAinn, C, false, &c->dsig, S);   // p read once, q written once
         timed(c, KD_OP, opb, st, [&] {   // q = Ahat p and <p, q>
-            HIPCHECK(launch_op_dot(st, C, nbp, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, c->d_sigma, S, m, W.p, W.q,
+            HIPCHECK(launch_op_dot(st, C, nbp, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, c->dsig.d, S, m, W.p, W.q,
                                    W.pp1));
         });
         HIPCHECK(launch_fin_alpha(st, C, nbp, W.pp1, active, rho, alpha, pq, flags));
@@ -1516,7 +1546,7 @@ void build_lrc(msp_ctx* c) {
     std::vector<double> h(64), hv(len);
 
     auto applyB = [&](const double* x, double* y) {   // y = A_a x per column
-        spmm<double>(c, KD_OP, st, C, c->dAinn, x, y, nullptr, 1.0, 0.0, c->d_sigma, S, 1);
+        spmm<double>(c, KD_OP, st, C, c->dAinn, x, y, nullptr, 1.0, 0.0, &c->dsig, S, 1);
     };
     auto op = [&](const double* v, const double* bv, double* out) {
         if (amg) {

@@ -18,8 +18,9 @@ namespace msp {
 
 // ------------------------------------------------------------------ SpMM
 // Y = alpha * (A X + diag-outer(X)) + beta * Z, where the outer term adds
-// sigma[row * S + col / m] * X[row, col] (the per-subsystem outer diagonal of
-// eq. (2.14), one value per subsystem, broadcast over its m columns).
+// sigma_a[row] * X[row, col], a = col / m (the per-subsystem outer diagonal of
+// eq. (2.14), one value per subsystem, broadcast over its m columns; only
+// rows listed in the compact OuterDiag carry it).
 // Y may alias Z (each lane reads its own Z elements before writing them).
 // With SETS the matrix holds vs interleaved value sets (entry k of set a at
 // va[k * vs + a]) and column c is multiplied by set min(c / m, vs - 1): one
@@ -31,7 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
                                                  const int32_t* __restrict__ ci,
                                                  const TV* __restrict__ va, const T* __restrict__ X,
                                                  T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta,
-                                                 const double* __restrict__ sigma, int S, int m, int vs) {
+                                                 OuterDiag sigma, int S, int m, int vs) {
     using L = Lanes<T, C>;
     using TC = acc_t<T>;
     constexpr int VW = L::VW;
@@ -61,12 +62,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
         else
             row_accumulate<T, C, VW, TV>(rp[row], rp[row + 1], 1, ci, va, X, lane, acc);
     }
-    if (sigma) {
-        const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
+    if (sigma.idx) {
+        const int32_t q = sigma.idx[row];
+        if (q >= 0) {
+            const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
 #pragma unroll
-        for (int e = 0; e < VW; ++e) {
-            const int a = (lane * VW + e) / m;
-            if (a < S) acc[e] += (TC)sigma[row * S + a] * to_acc(x.e[e]);
+            for (int e = 0; e < VW; ++e) {
+                const int a = (lane * VW + e) / m;
+                if (a < S) acc[e] += (TC)sigma.val[(int64_t)q * S + a] * to_acc(x.e[e]);
+            }
         }
     }
     Pack<T, VW> out;
@@ -89,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
                                                        const int32_t* __restrict__ ci,
                                                        const TV* __restrict__ va, const T* __restrict__ X,
                                                        T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs,
-                                                       int m, const double* __restrict__ sigma, int S) {
+                                                       int m, OuterDiag sigma, int S) {
     using L = Lanes<T, C>;
     using TC = acc_t<T>;
     constexpr int VW = L::VW;
@@ -125,12 +129,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
 #pragma unroll
             for (int e = 0; e < VW; ++e) acc[e] += sm[((slot * G + q) * L::LPR + lane) * VW + e];
         }
-        if (sigma) {   // outer diagonal, as in k_spmm
-            const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
+        if (sigma.idx) {   // outer diagonal, as in k_spmm
+            const int32_t q = sigma.idx[row];
+            if (q >= 0) {
+                const Pack<T, VW> x = ld<T, VW>(X + row * C + lane * VW);
 #pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                const int a = (lane * VW + e) / m;
-                if (a < S) acc[e] += (TC)sigma[row * S + a] * to_acc(x.e[e]);
+                for (int e = 0; e < VW; ++e) {
+                    const int a = (lane * VW + e) / m;
+                    if (a < S) acc[e] += (TC)sigma.val[(int64_t)q * S + a] * to_acc(x.e[e]);
+                }
             }
         }
         Pack<T, VW> out;
@@ -744,7 +751,7 @@ constexpr bool sets_ok() {
 
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
-                       const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, const double* sigma, int S, int m,
+                       const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m,
                        int vs) {
     if (n <= 0) return hipSuccess;
     if (vs > 1 && (!sets_ok<TV>() || m < 1)) return hipErrorInvalidValue;
@@ -765,7 +772,7 @@ hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, cons
 
 template <typename T, typename TV, int CC, int G>
 static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va, const T* X,
-                         T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m, const double* sigma, int S) {
+                         T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m, OuterDiag sigma, int S) {
     constexpr int TPR = G * Lanes<T, CC>::LPR;
     if constexpr (TPR <= kBlock) {
         constexpr int RPB = kBlock / TPR;
@@ -784,9 +791,9 @@ static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int
 template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
                              const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m,
-                             const double* sigma, int S) {
+                             OuterDiag sigma, int S) {
     if (n <= 0) return hipSuccess;
-    if ((vs > 1 || sigma) && m < 1) return hipErrorInvalidValue;
+    if ((vs > 1 || sigma.idx) && m < 1) return hipErrorInvalidValue;
     if (vs > 1 && !sets_ok<TV>()) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         constexpr int LPR = Lanes<T, CC>::LPR;
@@ -807,10 +814,10 @@ hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int3
 
 #define MSP_SPMM_INST(T, TV)                                                                                         \
     template hipError_t launch_spmm<T, TV>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const TV*,     \
-                                           const T*, T*, const T*, acc_t<T>, acc_t<T>, const double*, int, int, int); \
+                                           const T*, T*, const T*, acc_t<T>, acc_t<T>, OuterDiag, int, int, int);     \
     template hipError_t launch_spmm_split<T, TV>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,     \
                                                  const TV*, const T*, T*, const T*, acc_t<T>, acc_t<T>, int, int,   \
-                                                 const double*, int);
+                                                 OuterDiag, int);
 MSP_SPMM_INST(double, double)
 MSP_SPMM_INST(float, float)
 MSP_SPMM_INST(float, Bf16)

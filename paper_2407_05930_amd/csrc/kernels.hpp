@@ -27,6 +27,15 @@ struct Acc<Bf16> {
 template <typename T>
 using acc_t = typename Acc<T>::type;
 
+// Per-subsystem outer diagonal of the decoupled operators (eq. (2.14)), kept
+// only for the rows that carry one (the interface): idx[row] = -1 for a row
+// without it, else its row q in val, val[q * S + a] = sigma_a.  idx == nullptr:
+// no outer term.
+struct OuterDiag {
+    const int32_t* idx;
+    const double* val;
+};
+
 // Columns per lane of an n x C multivector of elem_bytes elements: 16-byte
 // vectors for FP32/FP64; 8-byte vectors (4 columns) for bfloat16, so that a
 // lane's columns stay within one subsystem for m = 4 as they do in FP32.
@@ -38,13 +47,13 @@ constexpr int lane_width(int elem_bytes) { return (elem_bytes == 2 ? 8 : 16) / e
 // FP64/FP32 values only) and column c uses set min(c / m, vs - 1).
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
-                       const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, const double* sigma, int S, int m,
+                       const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m,
                        int vs);
 // Same product for long rows: G lane groups share each row (G a power of two).
 template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
                              const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m,
-                             const double* sigma, int S);
+                             OuterDiag sigma, int S);
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
                       double* out);

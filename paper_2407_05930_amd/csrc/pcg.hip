@@ -25,10 +25,11 @@ constexpr int kUpdTch = 4;
 
 
 // q = (A_inn + diag-outer) p; partial[b, c] = this block's sum of p[:, c] q[:, c]
+// (sigma.idx must be set: the operator always has the outer diagonal)
 template <int C>
 __global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ ci, const double* __restrict__ va,
-                                                   const double* __restrict__ sigma, int S, int m,
+                                                   OuterDiag sigma, int S, int m,
                                                    const double* __restrict__ p, double* __restrict__ q,
                                                    double* __restrict__ partial) {
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
@@ -50,11 +51,12 @@ __global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __r
         else
             row_accumulate<double, C, VW>(rp[row], rp[row + 1], 1, ci, va, p, lane, acc);
         const Pack<double, VW> pr = ld<double, VW>(p + row * C + lane * VW);
+        const int32_t sq = sigma.idx[row];   // interface row: its outer diagonal
         Pack<double, VW> out;
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
             const int a = (lane * VW + e) / m;
-            if (a < S) acc[e] += sigma[row * S + a] * pr.e[e];
+            if (sq >= 0 && a < S) acc[e] += sigma.val[(int64_t)sq * S + a] * pr.e[e];
             out.e[e] = acc[e];
             dacc[e] += pr.e[e] * acc[e];
         }
@@ -354,7 +356,7 @@ int pcg_grid(int C, int64_t n) {
 }
 
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
-                         const double* va, const double* sigma, int S, int m, const double* p, double* q,
+                         const double* va, OuterDiag sigma, int S, int m, const double* p, double* q,
                          double* partial) {
     MSP_DISPATCH_C(C, {
         hipLaunchKernelGGL((k_op_dot<CC>), dim3(nb), dim3(kBlock), 0, st, n, rp, ci, va, sigma, S, m, p, q, partial);

@@ -14,7 +14,7 @@ constexpr int kPcgMaxBlocks = 2048;   // grid of the dot-producing kernels (grid
 int pcg_grid(int C, int64_t n);
 
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
-                         const double* va, const double* sigma, int S, int m, const double* p, double* q,
+                         const double* va, OuterDiag sigma, int S, int m, const double* p, double* q,
                          double* partial);
 hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial, const int* active,
                             const double* rho, double* alpha, double* pq, int* flags);
