@@ -736,7 +736,8 @@ struct SolvePlan {
     msp_ctx* c;
     Work* w;
     hipStream_t st;
-    int m, S, C, nbp, kl, O;
+    int m, S, C, kl, O;
+    int nbo = 0, nbu = 0, nbz = 0;   // grids of the operator, update and z-finish kernels (partial rows)
     int64_t nb, n;
     bool flexible, lrc_amg;
     bool x_pending = false;   // an x += alpha p step not yet applied
@@ -763,10 +764,26 @@ struct SolvePlan {
         iters = w->iscal + 64;
         flags = w->iscal + 128;
         flexible = mixed(c) && amg(c);
-        nbp = pcg_grid(C, nb);
         lrc_amg = c->d_U && amg(c);
         kl = lrc_amg ? c->lrc_k : 0;
         O = S * kl * m;
+        HIPCHECK(op_dot_grid(C, nb, &nbo));
+        if (c->U16) HIPCHECK(update_dots_grid<Bf16>(C, flexible, kl, nb, &nbu));
+        else if (c->U32 || !c->d_U) HIPCHECK(update_dots_grid<float>(C, flexible, kl, nb, &nbu));
+        else HIPCHECK(update_dots_grid<double>(C, flexible, kl, nb, &nbu));
+        const bool lz = lrc_amg && kl > 0;
+        const bool s16 = amg(c) && c->o.precision == MSP_MIXED_BF16, s32 = !s16 && amg(c) && mixed(c);
+        if (s16) {
+            if (c->U16) HIPCHECK((zfinish_grid<Bf16, Bf16>(C, lz, nb, &nbz)));
+            else if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<Bf16, float>(C, lz, nb, &nbz)));
+            else HIPCHECK((zfinish_grid<Bf16, double>(C, lz, nb, &nbz)));
+        } else if (s32) {
+            if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<float, float>(C, lz, nb, &nbz)));
+            else HIPCHECK((zfinish_grid<float, double>(C, lz, nb, &nbz)));
+        } else {
+            if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<double, float>(C, lz, nb, &nbz)));
+            else HIPCHECK((zfinish_grid<double, double>(C, lz, nb, &nbz)));
+        }
     }
 
     double vb() const { return 8.0 * nb * C; }   // bytes of one FP64 multivector pass
@@ -788,19 +805,19 @@ struct SolvePlan {
                              (y32() ? 4.0 * nb * C : 0.0) + (y16() ? 2.0 * nb * C : 0.0);
         timed(c, KD_UPDATE, bytes, st, [&] {
             if (c->U16)
-                HIPCHECK(launch_update_dots<Bf16>(st, C, nbp, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
+                HIPCHECK(launch_update_dots<Bf16>(st, C, nbu, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
                                                   static_cast<const Bf16*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
                                                   y32(), y16()));
             else if (c->U32 || !c->d_U)
-                HIPCHECK(launch_update_dots<float>(st, C, nbp, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
+                HIPCHECK(launch_update_dots<float>(st, C, nbu, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
                                                    static_cast<const float*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
                                                    y32(), y16()));
             else
-                HIPCHECK(launch_update_dots<double>(st, C, nbp, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
+                HIPCHECK(launch_update_dots<double>(st, C, nbu, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
                                                     static_cast<const double*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
                                                     y32(), y16()));
         });
-        HIPCHECK(launch_fin_check(st, C, nbp, !upd, flexible && upd, O, m, W.pp1, W.pp2, W.plrc, thr, c->d_lrc_coef,
+        HIPCHECK(launch_fin_check(st, C, nbu, !upd, flexible && upd, O, m, W.pp1, W.pp2, W.plrc, thr, c->d_lrc_coef,
                                   active, iters, flags, rnorm, rzold, c->d_lrc_W));
     }
 
@@ -829,35 +846,35 @@ struct SolvePlan {
         timed(c, KD_CAST, bytes, st, [&] {
             if (s16) {
                 if (c->U16)
-                    HIPCHECK((launch_zfinish<Bf16, Bf16>(st, C, nbp, nb, s16, W.z, W.r, static_cast<const Bf16*>(U),
+                    HIPCHECK((launch_zfinish<Bf16, Bf16>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const Bf16*>(U),
                                                          c->d_lrc_W, S, kl, m, W.pp1)));
                 else if (c->U32 || !c->d_U)
-                    HIPCHECK((launch_zfinish<Bf16, float>(st, C, nbp, nb, s16, W.z, W.r, static_cast<const float*>(U),
+                    HIPCHECK((launch_zfinish<Bf16, float>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const float*>(U),
                                                           c->d_lrc_W, S, kl, m, W.pp1)));
                 else
-                    HIPCHECK((launch_zfinish<Bf16, double>(st, C, nbp, nb, s16, W.z, W.r,
+                    HIPCHECK((launch_zfinish<Bf16, double>(st, C, nbz, nb, s16, W.z, W.r,
                                                            static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
                                                            W.pp1)));
             } else if (s32) {
                 if (c->U32 || !c->d_U)
-                    HIPCHECK((launch_zfinish<float, float>(st, C, nbp, nb, s32, W.z, W.r, static_cast<const float*>(U),
+                    HIPCHECK((launch_zfinish<float, float>(st, C, nbz, nb, s32, W.z, W.r, static_cast<const float*>(U),
                                                            c->d_lrc_W, S, kl, m, W.pp1)));
                 else
-                    HIPCHECK((launch_zfinish<float, double>(st, C, nbp, nb, s32, W.z, W.r,
+                    HIPCHECK((launch_zfinish<float, double>(st, C, nbz, nb, s32, W.z, W.r,
                                                             static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
                                                             W.pp1)));
             } else {
                 if (c->U32 || !c->d_U)
-                    HIPCHECK((launch_zfinish<double, float>(st, C, nbp, nb, W.z, W.z, W.r,
+                    HIPCHECK((launch_zfinish<double, float>(st, C, nbz, nb, W.z, W.z, W.r,
                                                             static_cast<const float*>(U), c->d_lrc_W, S, kl, m,
                                                             W.pp1)));
                 else
-                    HIPCHECK((launch_zfinish<double, double>(st, C, nbp, nb, W.z, W.z, W.r,
+                    HIPCHECK((launch_zfinish<double, double>(st, C, nbz, nb, W.z, W.z, W.r,
                                                              static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
                                                              W.pp1)));
             }
         });
-        HIPCHECK(launch_fin_beta(st, C, nbp, init, flexible, W.pp1, active, rzold, rho, beta, rz));
+        HIPCHECK(launch_fin_beta(st, C, nbz, init, flexible, W.pp1, active, rzold, rho, beta, rz));
     }
 
     void begin(const double* d_b) {
@@ -878,10 +895,10 @@ struct SolvePlan {
         Work& W = *w;
         const double opb = spmm_bytes<double>(c->dAinn, C, false, &c->dsig, S);   // p read once, q written once
         timed(c, KD_OP, opb, st, [&] {   // q = Ahat p and <p, q>
-            HIPCHECK(launch_op_dot(st, C, nbp, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, c->dsig.d, S, m, W.p, W.q,
+            HIPCHECK(launch_op_dot(st, C, nbo, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, c->dsig.d, S, m, W.p, W.q,
                                    W.pp1));
         });
-        HIPCHECK(launch_fin_alpha(st, C, nbp, W.pp1, active, rho, alpha, pq, flags));
+        HIPCHECK(launch_fin_alpha(st, C, nbo, W.pp1, active, rho, alpha, pq, flags));
         update_dots(true);
         x_pending = true;   // x += alpha p follows with the p update (or in finish)
     }

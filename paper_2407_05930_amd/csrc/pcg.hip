@@ -337,23 +337,65 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(int nb, int C, int init, in
         default: return hipErrorInvalidValue;                    \
     }
 
-template <int C>
-static unsigned grid_for(int64_t n, int nbmax) {
+// Blocks for a grid-stride kernel over n rows: its row tiles, at most
+// kPcgMaxBlocks, and at most the blocks of this kernel that the device holds
+// at once (its occupancy on one compute unit times the compute units), so
+// that no block waits for a slot while the others run.
+template <int C, typename K>
+static hipError_t resident_grid(K kernel, size_t lds, int64_t n, int* nb) {
     const int64_t tiles = (n + DL<C>::RPB - 1) / DL<C>::RPB;
-    return (unsigned)(tiles < nbmax ? tiles : nbmax);
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kernel), kBlock, lds);
+    if (e != hipSuccess) return e;
+    int64_t cap = kPcgMaxBlocks;
+    if (per > 0 && cus > 0 && (int64_t)per * cus < cap) cap = (int64_t)per * cus;
+    *nb = (int)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap);
+    return hipSuccess;
 }
 
-int pcg_grid(int C, int64_t n) {
-    switch (C) {
-        case 1: return grid_for<1>(n, kPcgMaxBlocks);
-        case 2: return grid_for<2>(n, kPcgMaxBlocks);
-        case 4: return grid_for<4>(n, kPcgMaxBlocks);
-        case 8: return grid_for<8>(n, kPcgMaxBlocks);
-        case 16: return grid_for<16>(n, kPcgMaxBlocks);
-        case 32: return grid_for<32>(n, kPcgMaxBlocks);
-        default: return grid_for<64>(n, kPcgMaxBlocks);
-    }
+hipError_t op_dot_grid(int C, int64_t n, int* nb) {
+    MSP_DISPATCH_C(C, { return resident_grid<CC>(k_op_dot<CC>, 0, n, nb); });
+    return hipErrorInvalidValue;
 }
+
+template <typename TU>
+hipError_t update_dots_grid(int C, bool flex, int k, int64_t n, int* nb) {
+    if (k > 16) return hipErrorInvalidValue;
+    MSP_DISPATCH_C(C, {
+        constexpr size_t lds = sizeof(double) * kUpdTch * kBlock * DL<CC>::VW;
+        if (k > 8)
+            return flex ? resident_grid<CC>(k_update_dots<CC, true, true, 16, TU>, lds, n, nb)
+                        : resident_grid<CC>(k_update_dots<CC, true, false, 16, TU>, lds, n, nb);
+        if (k > 0)
+            return flex ? resident_grid<CC>(k_update_dots<CC, true, true, 8, TU>, lds, n, nb)
+                        : resident_grid<CC>(k_update_dots<CC, true, false, 8, TU>, lds, n, nb);
+        return flex ? resident_grid<CC>(k_update_dots<CC, true, true, 0, TU>, 0, n, nb)
+                    : resident_grid<CC>(k_update_dots<CC, true, false, 0, TU>, 0, n, nb);
+    });
+    return hipErrorInvalidValue;
+}
+template hipError_t update_dots_grid<float>(int, bool, int, int64_t, int*);
+template hipError_t update_dots_grid<double>(int, bool, int, int64_t, int*);
+template hipError_t update_dots_grid<Bf16>(int, bool, int, int64_t, int*);
+
+template <typename TS, typename TU>
+hipError_t zfinish_grid(int C, bool lrc, int64_t n, int* nb) {
+    MSP_DISPATCH_C(C, {
+        return lrc ? resident_grid<CC>(k_zfinish<CC, TS, true, TU>, 0, n, nb)
+                   : resident_grid<CC>(k_zfinish<CC, TS, false, TU>, 0, n, nb);
+    });
+    return hipErrorInvalidValue;
+}
+template hipError_t zfinish_grid<float, float>(int, bool, int64_t, int*);
+template hipError_t zfinish_grid<double, double>(int, bool, int64_t, int*);
+template hipError_t zfinish_grid<double, float>(int, bool, int64_t, int*);
+template hipError_t zfinish_grid<float, double>(int, bool, int64_t, int*);
+template hipError_t zfinish_grid<Bf16, float>(int, bool, int64_t, int*);
+template hipError_t zfinish_grid<Bf16, double>(int, bool, int64_t, int*);
+template hipError_t zfinish_grid<Bf16, Bf16>(int, bool, int64_t, int*);
 
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
                          const double* va, OuterDiag sigma, int S, int m, const double* p, double* q,

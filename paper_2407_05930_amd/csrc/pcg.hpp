@@ -9,9 +9,18 @@
 
 namespace msp {
 
-constexpr int kPcgMaxBlocks = 2048;   // grid of the dot-producing kernels (grid-stride over row tiles)
+constexpr int kPcgMaxBlocks = 2048;   // largest grid of the dot-producing kernels (grid-stride over row tiles)
 
-int pcg_grid(int C, int64_t n);
+// Grids of the dot-producing kernels over n rows: the row tiles, capped at
+// kPcgMaxBlocks and at the blocks of that kernel the current device holds at
+// once.  The partial arrays they fill have nb rows; the finisher that reads
+// them takes the same nb.  update_dots_grid sizes the updating variant (the
+// initial, non-updating one uses fewer registers and fits the same grid).
+hipError_t op_dot_grid(int C, int64_t n, int* nb);
+template <typename TU>
+hipError_t update_dots_grid(int C, bool flex, int k, int64_t n, int* nb);
+template <typename TS, typename TU>
+hipError_t zfinish_grid(int C, bool lrc, int64_t n, int* nb);
 
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
                          const double* va, OuterDiag sigma, int S, int m, const double* p, double* q,
