@@ -131,6 +131,7 @@ struct msp_ctx {
     msp::DevCsr dAinn, dGf, dGfT;
     std::vector<msp::DevLevel> dl;
     double* d_cinv = nullptr;
+    float* d_cinv32 = nullptr;    // per-subsystem coarsest inverses in FP32 (mixed modes), rows padded to 4
     int64_t nL = 0;
     std::map<int, std::unique_ptr<msp::Work>> works;   // by padded column count
     // low-rank corrections: U (n_b x S*k, FP64 or FP32), coefficients (S*k)
@@ -378,6 +379,32 @@ static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, c
 // (1, 2, 4, ... up to the block's capacity and about half the mean row
 // length) on this column count and keep the fastest.  Runs once per context
 // and column count, on scratch multivectors cleared first.
+static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
+
+// Per-subsystem coarsest solves with R rows per wavefront: FP64 inverses for
+// the FP64 V-cycle, FP32 ones for the mixed modes.
+template <typename T>
+static void dense_sets(const msp_ctx* c, const Work& w, hipStream_t st, int m, const T* y, T* s, int R) {
+    const int S = 1 << c->sym.s;
+    if constexpr (std::is_same<T, double>::value) {
+        if (!c->d_cinv) throw Error(MSP_ERR_UNSUPPORTED, "FP64 coarsest inverses not on the device");
+        HIPCHECK((launch_dense_sets<double, double>(st, w.C, S, m, c->nL, c->d_cinv, y, s,
+                                                    static_cast<double*>(w.dense_pack), R)));
+    } else {
+        if (!c->d_cinv32) throw Error(MSP_ERR_UNSUPPORTED, "FP32 coarsest inverses not on the device");
+        HIPCHECK((launch_dense_sets<T, float>(st, w.C, S, m, c->nL, c->d_cinv32, y, s, static_cast<T*>(w.dense_pack),
+                                              R)));
+    }
+}
+
+// bytes of the per-subsystem coarsest solves (inverses and the y, s multivectors)
+template <typename T>
+static double dense_sets_bytes(const msp_ctx* c, int C) {
+    const int S = 1 << c->sym.s;
+    const double eb = std::is_same<T, double>::value ? 8.0 : 4.0;
+    return eb * S * c->nL * dense_sets_ld(c->nL, (int)eb) + 2.0 * sizeof(T) * c->nL * C;
+}
+
 template <typename T>
 static void autotune_level_splits(msp_ctx* c, Work& w) {
     hipStream_t st = nullptr;
@@ -436,7 +463,7 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
         float best_ms = 1e30f;
         for (int R = 1; R <= dense_sets_rows_max(mt); R *= 2) {
             auto run = [&] {
-                HIPCHECK(launch_dense_sets<T>(st, C, S, mt, c->nL, c->d_cinv, y, s, static_cast<T*>(w.dense_pack), R));
+                dense_sets<T>(c, w, st, mt, y, s, R);
             };
             run();
             HIPCHECK(hipEventRecord(e0, st));
@@ -455,7 +482,6 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
     HIPCHECK(hipEventDestroy(e1));
 }
 
-static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
 // bytes per element of the V-cycle multivectors
 static int vbytes(const msp_ctx* c) {
     return c->o.precision == MSP_FP64 ? 8 : (c->o.precision == MSP_MIXED_BF16 ? 2 : 4);
@@ -496,7 +522,7 @@ static Work& work(msp_ctx* c, int C) {
         const int64_t nL = c->hier.lev.back().A.nr;
         const int ks = dense_splits(C, nL, vbytes(c));
         w.dense_part = c->dalloc<double>(static_cast<int64_t>(ks) * nL * C);
-        if (c->sub) w.dense_pack = c->dalloc<double>(2 * nL * C);
+        if (c->sub) w.dense_pack = c->dalloc<double>(2 * (nL + 4) * C);
     }
     w.nb_dot = 512;
     w.partial = c->dalloc<double>(static_cast<int64_t>(w.nb_dot) * 64);
@@ -529,11 +555,7 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     const int S = 1 << c->sym.s;
     if (l + 1 == c->hier.lev.size()) {
         if (c->sub && l > 0) {   // every subsystem's own coarsest operator
-            const double bytes = 8.0 * S * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
-            timed(c, KD_DENSE, bytes, st, [&] {
-                HIPCHECK(launch_dense_sets<T>(st, C, S, w.m, c->nL, c->d_cinv, y, s, static_cast<T*>(w.dense_pack),
-                                              w.dense_rows));
-            });
+            timed(c, KD_DENSE, dense_sets_bytes<T>(c, C), st, [&] { dense_sets<T>(c, w, st, w.m, y, s, w.dense_rows); });
         } else {
             const double bytes = 8.0 * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
             timed(c, KD_DENSE, bytes, st,
@@ -710,7 +732,20 @@ static void upload_all(msp_ctx* c) {
         }
         c->nL = c->hier.lev.back().A.nr;
         const std::vector<double>& inv = c->sub ? c->subv.coarse_inv : c->hier.coarse_inv;
-        c->d_cinv = c->upload(inv.data(), static_cast<int64_t>(inv.size()));
+        if (c->sub && mixed(c)) {
+            // the V-cycle computes in FP32: its coarsest inverses are read in FP32 too
+            const int64_t nL = c->nL, ld = dense_sets_ld(nL, 4);
+            const int64_t S = int64_t(1) << c->sym.s;
+            std::vector<float> f(static_cast<size_t>(S * nL * ld), 0.0f);
+            for (int64_t a = 0; a < S; ++a)
+                for (int64_t i = 0; i < nL; ++i)
+                    for (int64_t k = 0; k < nL; ++k)
+                        f[static_cast<size_t>((a * nL + i) * ld + k)] =
+                            static_cast<float>(inv[static_cast<size_t>((a * nL + i) * nL + k)]);
+            c->d_cinv32 = c->upload(f.data(), static_cast<int64_t>(f.size()));
+        } else {
+            c->d_cinv = c->upload(inv.data(), static_cast<int64_t>(inv.size()));
+        }
     } else if (c->o.pc == MSP_PC_FSAI) {
         c->dGf = upload_csr(c, c->Gf, false);
         c->dGfT = upload_csr(c, transpose(c->Gf), false);

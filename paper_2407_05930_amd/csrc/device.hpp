@@ -122,18 +122,17 @@ __device__ __forceinline__ void row_accumulate_bcast(int32_t k0, int32_t k1, con
         const TC a = have ? cvt<TC>(va[kk]) : TC(0);
         const int cnt = k1 - kb < CH ? k1 - kb : CH;
         Pack<T, VW> xs[CH];
-        TC as[CH];
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
             const int32_t cq = __shfl(c, base + q, 64);
-            as[q] = __shfl(a, base + q, 64);
             if (q < cnt) xs[q] = ld<T, VW>(X + (int64_t)cq * C + lane * VW);
         }
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
+            const TC aq = __shfl(a, base + q, 64);
             if (q < cnt) {
 #pragma unroll
-                for (int e = 0; e < VW; ++e) acc[e] += as[q] * to_acc(xs[q].e[e]);
+                for (int e = 0; e < VW; ++e) acc[e] += aq * to_acc(xs[q].e[e]);
             }
         }
     }

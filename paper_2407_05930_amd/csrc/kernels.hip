@@ -457,59 +457,76 @@ __global__ __launch_bounds__(kBlock) void k_dense_part(int64_t nL, int64_t kchun
     }
 }
 
-// yp[(a * nL + k) * MP + j] = y[k, a*m + j] (zero for j >= m): every
-// subsystem's m columns packed contiguously for the dense solves below.
+// yp[(a * ldm + k) * MP + j] = y[k, a*m + j] (zero for j >= m or k >= nL):
+// every subsystem's m columns packed contiguously, ldm rows per subsystem,
+// for the dense solves below.
 template <typename T, int MP>
-__global__ __launch_bounds__(kBlock) void k_pack_sets(int64_t nL, int C, int S, int m, const T* __restrict__ y,
-                                                      T* __restrict__ yp) {
+__global__ __launch_bounds__(kBlock) void k_pack_sets(int64_t nL, int64_t ldm, int C, int S, int m,
+                                                      const T* __restrict__ y, T* __restrict__ yp) {
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= (int64_t)S * nL * MP) return;
+    if (idx >= (int64_t)S * ldm * MP) return;
     const int j = (int)(idx % MP);
     const int64_t ak = idx / MP;
-    const int a = (int)(ak / nL);
-    const int64_t k = ak % nL;
-    yp[idx] = j < m ? y[k * C + a * m + j] : T{};
+    const int a = (int)(ak / ldm);
+    const int64_t k = ak % ldm;
+    yp[idx] = j < m && k < nL ? y[k * C + a * m + j] : T{};
 }
 
 // Per-subsystem coarsest solves: out[:, a*m + j] = Minv_a y[:, a*m + j] for
-// subsystem a = blockIdx.y with its own inverse Minv + a * nL * nL.  With
-// only m columns per inverse this is a bandwidth-bound batched GEMV: each
-// wavefront owns R rows, its lanes walk k with stride 64 (every row read as
-// 512-byte coalesced segments, every entry of the inverses read once; the
-// right-hand sides come packed, MP values per k contiguous), and the per-lane
-// partial sums are reduced across the wave by a fixed butterfly.  Blocks of
-// the last subsystem also clear the padded columns >= S * m.
-template <typename T, int MP, int R>
-__global__ __launch_bounds__(kBlock) void k_dense_sets(int64_t nL, int C, int S, int m,
-                                                       const double* __restrict__ Minv, const T* __restrict__ yp,
+// subsystem a = blockIdx.y with its own inverse Minv + a * nL * ldm (rows of
+// ldm entries, the ones past nL zero).  With only m columns per inverse this
+// is a bandwidth-bound batched GEMV: each wavefront owns R rows, its lanes
+// walk k in steps of 64 * KV (KV consecutive entries per lane, so every row
+// is read as coalesced 512- or 1024-byte segments and every entry of the
+// inverses once; the right-hand sides come packed, MP values per k
+// contiguous), the sums are kept in FP64, and the per-lane partial sums are
+// reduced across the wave by a fixed butterfly.  Blocks of the last subsystem
+// also clear the padded columns >= S * m.
+template <typename T, typename TM, int MP, int R>
+__global__ __launch_bounds__(kBlock) void k_dense_sets(int64_t nL, int64_t ldm, int C, int S, int m,
+                                                       const TM* __restrict__ Minv, const T* __restrict__ yp,
                                                        T* __restrict__ out) {
     constexpr int W = 64;
+    constexpr int KV = sizeof(TM) == 4 ? 4 : 1;                                   // inverse entries per lane load
     constexpr int PW = (MP * (int)sizeof(T)) >= 16 ? 16 / (int)sizeof(T) : MP;   // values per packed load
     const int wave = threadIdx.x / W, lane = threadIdx.x % W;
     const int a = blockIdx.y;
     const int64_t row0 = ((int64_t)blockIdx.x * (kBlock / W) + wave) * R;
     if (row0 >= nL) return;   // the whole wavefront leaves together
-    const double* Ma = Minv + (int64_t)a * nL * nL;
-    const T* ya = yp + (int64_t)a * nL * MP;
+    const TM* Ma = Minv + (int64_t)a * nL * ldm;
+    const T* ya = yp + (int64_t)a * ldm * MP;
     double acc[R][MP];
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int j = 0; j < MP; ++j) acc[r][j] = 0.0;
 #pragma unroll 4
-    for (int64_t k = lane; k < nL; k += W) {
-        double xv[MP];
-#pragma unroll
-        for (int q = 0; q < MP; q += PW) {
-            const Pack<T, PW> v = ld<T, PW>(ya + k * MP + q);
-#pragma unroll
-            for (int e = 0; e < PW; ++e) xv[q + e] = (double)to_acc(v.e[e]);
-        }
+    for (int64_t k0 = (int64_t)lane * KV; k0 < ldm; k0 += W * KV) {
+        Pack<TM, KV> mv[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double v = row0 + r < nL ? Ma[(row0 + r) * nL + k] : 0.0;
+            if (row0 + r < nL) {
+                mv[r] = ld<TM, KV>(Ma + (row0 + r) * ldm + k0);
+            } else {
 #pragma unroll
-            for (int j = 0; j < MP; ++j) acc[r][j] += v * xv[j];
+                for (int e = 0; e < KV; ++e) mv[r].e[e] = TM(0);
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KV; ++kk) {
+            double xv[MP];
+#pragma unroll
+            for (int q = 0; q < MP; q += PW) {
+                const Pack<T, PW> v = ld<T, PW>(ya + (k0 + kk) * MP + q);
+#pragma unroll
+                for (int e = 0; e < PW; ++e) xv[q + e] = (double)to_acc(v.e[e]);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double mvd = (double)mv[r].e[kk];
+#pragma unroll
+                for (int j = 0; j < MP; ++j) acc[r][j] += mvd * xv[j];
+            }
         }
     }
 #pragma unroll
@@ -962,26 +979,26 @@ static int pow2_at_least(int x) {
     return p;
 }
 
-template <typename T, int MP, int R>
-static void launch_dense_sets_r(hipStream_t st, int C, int S, int m, int64_t nL, const double* Minv, const T* yp,
-                                T* out) {
+template <typename T, typename TM, int MP, int R>
+static void launch_dense_sets_r(hipStream_t st, int C, int S, int m, int64_t nL, int64_t ldm, const TM* Minv,
+                                const T* yp, T* out) {
     if constexpr (R * MP <= 64) {
         const int64_t rows_per_block = (int64_t)(kBlock / 64) * R;
-        hipLaunchKernelGGL((k_dense_sets<T, MP, R>), dim3(blocks_for(nL, (int)rows_per_block), S), dim3(kBlock), 0,
-                           st, nL, C, S, m, Minv, yp, out);
+        hipLaunchKernelGGL((k_dense_sets<T, TM, MP, R>), dim3(blocks_for(nL, (int)rows_per_block), S), dim3(kBlock),
+                           0, st, nL, ldm, C, S, m, Minv, yp, out);
     }
 }
 
-template <typename T, int MP>
-static void launch_dense_sets_mp(hipStream_t st, int C, int S, int m, int64_t nL, const double* Minv, const T* y,
-                                 T* out, T* yp, int R) {
-    hipLaunchKernelGGL((k_pack_sets<T, MP>), dim3(blocks_for((int64_t)S * nL * MP, kBlock)), dim3(kBlock), 0, st, nL,
-                       C, S, m, y, yp);
+template <typename T, typename TM, int MP>
+static void launch_dense_sets_mp(hipStream_t st, int C, int S, int m, int64_t nL, int64_t ldm, const TM* Minv,
+                                 const T* y, T* out, T* yp, int R) {
+    hipLaunchKernelGGL((k_pack_sets<T, MP>), dim3(blocks_for((int64_t)S * ldm * MP, kBlock)), dim3(kBlock), 0, st, nL,
+                       ldm, C, S, m, y, yp);
     switch (R) {
-        case 8: launch_dense_sets_r<T, MP, 8>(st, C, S, m, nL, Minv, yp, out); break;
-        case 4: launch_dense_sets_r<T, MP, 4>(st, C, S, m, nL, Minv, yp, out); break;
-        case 2: launch_dense_sets_r<T, MP, 2>(st, C, S, m, nL, Minv, yp, out); break;
-        default: launch_dense_sets_r<T, MP, 1>(st, C, S, m, nL, Minv, yp, out); break;
+        case 8: launch_dense_sets_r<T, TM, MP, 8>(st, C, S, m, nL, ldm, Minv, yp, out); break;
+        case 4: launch_dense_sets_r<T, TM, MP, 4>(st, C, S, m, nL, ldm, Minv, yp, out); break;
+        case 2: launch_dense_sets_r<T, TM, MP, 2>(st, C, S, m, nL, ldm, Minv, yp, out); break;
+        default: launch_dense_sets_r<T, TM, MP, 1>(st, C, S, m, nL, ldm, Minv, yp, out); break;
     }
 }
 
@@ -990,30 +1007,33 @@ int dense_sets_rows_max(int m) {
     return mp <= 8 ? 8 : 64 / mp;
 }
 
-template <typename T>
-hipError_t launch_dense_sets(hipStream_t st, int C, int S, int m, int64_t nL, const double* Minv, const T* y,
+int64_t dense_sets_ld(int64_t nL, int minv_bytes) { return minv_bytes == 4 ? (nL + 3) / 4 * 4 : nL; }
+
+template <typename T, typename TM>
+hipError_t launch_dense_sets(hipStream_t st, int C, int S, int m, int64_t nL, const TM* Minv, const T* y,
                              T* out, T* yp, int R) {
     if (S * m > C || m < 1 || m > 64 || S < 1) return hipErrorInvalidValue;
     if (R != 1 && R != 2 && R != 4 && R != 8) return hipErrorInvalidValue;
     if (R > dense_sets_rows_max(m)) R = dense_sets_rows_max(m);
     if (nL <= 0) return hipSuccess;
+    const int64_t ldm = dense_sets_ld(nL, (int)sizeof(TM));
     switch (pow2_at_least(m)) {
-        case 1: launch_dense_sets_mp<T, 1>(st, C, S, m, nL, Minv, y, out, yp, R); break;
-        case 2: launch_dense_sets_mp<T, 2>(st, C, S, m, nL, Minv, y, out, yp, R); break;
-        case 4: launch_dense_sets_mp<T, 4>(st, C, S, m, nL, Minv, y, out, yp, R); break;
-        case 8: launch_dense_sets_mp<T, 8>(st, C, S, m, nL, Minv, y, out, yp, R); break;
-        case 16: launch_dense_sets_mp<T, 16>(st, C, S, m, nL, Minv, y, out, yp, R); break;
-        case 32: launch_dense_sets_mp<T, 32>(st, C, S, m, nL, Minv, y, out, yp, R); break;
-        default: launch_dense_sets_mp<T, 64>(st, C, S, m, nL, Minv, y, out, yp, R); break;
+        case 1: launch_dense_sets_mp<T, TM, 1>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
+        case 2: launch_dense_sets_mp<T, TM, 2>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
+        case 4: launch_dense_sets_mp<T, TM, 4>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
+        case 8: launch_dense_sets_mp<T, TM, 8>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
+        case 16: launch_dense_sets_mp<T, TM, 16>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
+        case 32: launch_dense_sets_mp<T, TM, 32>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
+        default: launch_dense_sets_mp<T, TM, 64>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
     }
     return hipGetLastError();
 }
-template hipError_t launch_dense_sets<double>(hipStream_t, int, int, int, int64_t, const double*, const double*,
-                                              double*, double*, int);
-template hipError_t launch_dense_sets<float>(hipStream_t, int, int, int, int64_t, const double*, const float*,
-                                             float*, float*, int);
-template hipError_t launch_dense_sets<Bf16>(hipStream_t, int, int, int, int64_t, const double*, const Bf16*, Bf16*,
-                                            Bf16*, int);
+template hipError_t launch_dense_sets<double, double>(hipStream_t, int, int, int, int64_t, const double*,
+                                                      const double*, double*, double*, int);
+template hipError_t launch_dense_sets<float, float>(hipStream_t, int, int, int, int64_t, const float*, const float*,
+                                                    float*, float*, int);
+template hipError_t launch_dense_sets<Bf16, float>(hipStream_t, int, int, int, int64_t, const float*, const Bf16*,
+                                                   Bf16*, Bf16*, int);
 
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {

@@ -87,14 +87,17 @@ hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, co
 int dense_splits(int C, int64_t nL, int elem_bytes);
 template <typename T>
 hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part);
-// Per-subsystem coarsest solves: columns a*m .. a*m + m - 1 times Minv + a*nL*nL
-// (S inverses); columns >= S*m of out are zero.  yp: scratch of S * nL * MP
-// values, MP = m rounded up to a power of two (at most 2 * nL * C).  R: rows
-// per wavefront (1, 2, 4 or 8; capped at dense_sets_rows_max(m)).
+// Per-subsystem coarsest solves: columns a*m .. a*m + m - 1 times the
+// inverse Minv + a*nL*ld (S inverses, rows of ld = dense_sets_ld(nL,
+// sizeof(TM)) entries, the ones past nL zero; TM = double or float); columns
+// >= S*m of out are zero.  yp: scratch of S * ld * MP values, MP = m rounded
+// up to a power of two (at most 2 * (nL + 4) * C).  R: rows per wavefront
+// (1, 2, 4 or 8; capped at dense_sets_rows_max(m)).
 int dense_sets_rows_max(int m);
-template <typename T>
-hipError_t launch_dense_sets(hipStream_t st, int C, int S, int m, int64_t nL, const double* Minv, const T* y,
-                             T* out, T* yp, int R);
+int64_t dense_sets_ld(int64_t nL, int minv_bytes);
+template <typename T, typename TM>
+hipError_t launch_dense_sets(hipStream_t st, int C, int S, int m, int64_t nL, const TM* Minv, const T* y, T* out,
+                             T* yp, int R);
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v);
 template <typename TO, typename TI>
