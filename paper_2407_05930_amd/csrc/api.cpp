@@ -375,10 +375,6 @@ static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, c
     timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, X, Y, Z, alpha, beta, od, S, m); });
 }
 
-// Autotuner: for every V-cycle matrix, time the candidate lane-group splits
-// (1, 2, 4, ... up to the block's capacity and about half the mean row
-// length) on this column count and keep the fastest.  Runs once per context
-// and column count, on scratch multivectors cleared first.
 static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
 
 // Per-subsystem coarsest solves with R rows per wavefront: FP64 inverses for
@@ -405,6 +401,10 @@ static double dense_sets_bytes(const msp_ctx* c, int C) {
     return eb * S * c->nL * dense_sets_ld(c->nL, (int)eb) + 2.0 * sizeof(T) * c->nL * C;
 }
 
+// Autotuner: for every V-cycle matrix, time the candidate lane-group splits
+// (1, 2, 4, ... up to the block's capacity and about half the mean row
+// length) on this column count and keep the fastest.  Runs once per context
+// and column count, on scratch multivectors cleared first.
 template <typename T>
 static void autotune_level_splits(msp_ctx* c, Work& w) {
     hipStream_t st = nullptr;
