@@ -6,6 +6,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -413,6 +415,8 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
     const int lpr = C >= vw ? C / vw : 1;   // lanes per row of Lanes<T, C>
     const int S = 1 << c->sym.s;
     const int mt = std::max(1, C / S);   // columns per subsystem assumed for matrices with value sets
+    const char* logv = std::getenv("MSP_AUTOTUNE_LOG");   // set (non-empty, not "0"): timings to stderr
+    const bool log = logv && *logv && std::strcmp(logv, "0") != 0;
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
@@ -430,23 +434,29 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
         T* vt = w.vt[l] ? static_cast<T*>(w.vt[l]) : vr;
         Job jobs[6] = {{&L.A, vs, vr}, {&L.M, vr, vs}, {&L.R, vr, static_cast<T*>(w.vy[l + 1])},
                        {&L.P, static_cast<T*>(w.vs[l + 1]), vs}, {&L.G, vr, vt}, {&L.GT, vt, vs}};
-        for (Job& jb : jobs) {
+        static const char* const names[6] = {"A", "M", "R", "P", "G", "GT"};
+        for (int j = 0; j < 6; ++j) {
+            Job& jb = jobs[j];
             if (jb.M->nnz == 0) continue;
             const double avg = jb.M->nr ? static_cast<double>(jb.M->nnz) / static_cast<double>(jb.M->nr) : 0.0;
             int best = 1;
             float best_ms = 1e30f;
             for (int g = 1; g <= 64 && g * lpr <= 256; g *= 2) {   // 256 threads per block
                 if (g > 1 && g > std::max(1.0, avg / 2.0)) break;
-                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0), OuterDiag{nullptr, nullptr},
-                               S, mt);
+                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0),
+                               OuterDiag{nullptr, nullptr}, S, mt);
                 HIPCHECK(hipEventRecord(e0, st));
                 for (int rep = 0; rep < 3; ++rep)
-                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0), OuterDiag{nullptr, nullptr},
-                               S, mt);
+                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0),
+                                   OuterDiag{nullptr, nullptr}, S, mt);
                 HIPCHECK(hipEventRecord(e1, st));
                 HIPCHECK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+                if (log)
+                    std::fprintf(stderr, "msp autotune: C=%d elem=%d level %zu %s (%lld rows, %.1f nnz/row, %d sets) "
+                                 "split %d: %.2f us\n", C, static_cast<int>(sizeof(T)), l, names[j],
+                                 static_cast<long long>(jb.M->nr), avg, jb.M->vs, g, 1000.0 * ms / 3);
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = g;
@@ -472,6 +482,9 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
             HIPCHECK(hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+            if (log)
+                std::fprintf(stderr, "msp autotune: C=%d elem=%d coarsest solves, %d rows per wavefront: %.2f us\n", C,
+                             static_cast<int>(sizeof(T)), R, 1000.0 * ms / 3);
             if (ms < best_ms) {
                 best_ms = ms;
                 w.dense_rows = R;
