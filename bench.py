@@ -30,8 +30,8 @@ METRIC = "solve time to 1e-10 rel-res, 128^3 s=3; mixed vs FP64 plain; V-cycle H
 
 
 PRECISION_NOTE = {"mixed": "mixed (FP32 V-cycle, FP64 PCG)",
-                  "mixed_bf16": "mixed (V-cycle multivectors bfloat16 with FP32 arithmetic, FP32 matrices, "
-                                "FP64 coarsest inverse and PCG)"}
+                  "mixed_bf16": "mixed (V-cycle multivectors bfloat16 with FP32 arithmetic, FP32 matrices and "
+                                "coarsest inverses, FP64 PCG)"}
 
 
 def log(*a):

@@ -57,12 +57,14 @@ typedef enum {
 } msp_status;
 
 /* MSP_MIXED_FP32: FP32 V-cycle (smoother M = omega G^T G formed explicitly),
-   FP64 outer PCG, dots and coarsest solve.  MSP_MIXED_FP32_BF16G: as
+   FP64 outer PCG and dots.  The dense coarsest inverse is computed in FP64;
+   the shared cycle applies it in FP64, the per-subsystem cycle reads its
+   inverses rounded to FP32 (sums in FP64).  MSP_MIXED_FP32_BF16G: as
    MSP_MIXED_FP32 but the FSAI factors G, G^T are stored in bfloat16 and the
    smoother is applied factored, G^T (G r), which keeps it SPD.
    MSP_MIXED_BF16: as MSP_MIXED_FP32 but the V-cycle multivectors are stored
-   in bfloat16 (FP32 matrices, FP32 arithmetic and accumulation, FP64
-   coarsest inverse); the outer PCG stays FP64. */
+   in bfloat16 (FP32 matrices, FP32 arithmetic and accumulation); the outer
+   PCG stays FP64. */
 enum { MSP_FP64 = 0, MSP_MIXED_FP32 = 1, MSP_MIXED_FP32_BF16G = 2, MSP_MIXED_BF16 = 3 };
 /* Preconditioners of the decoupled subsystems A_a = A_inn + diag(sigma_a)
    (Sec. 2, eqs. (2.13)-(2.14)):
