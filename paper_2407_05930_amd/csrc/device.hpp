@@ -56,6 +56,32 @@ __device__ __forceinline__ void st(T* p, const Pack<T, VW>& v) {
     *reinterpret_cast<Pack<T, VW>*>(p) = v;
 }
 
+// Streaming accesses (nontemporal hint) for data whose next use is further
+// away than the memory-side cache reaches (the per-subsystem coarsest
+// inverses, read once per V-cycle): they then do not displace the V-cycle's
+// matrices and vectors, which are reused within a cycle.
+template <int B>
+struct NtWord;   // an integer vector of B bytes
+template <>
+struct NtWord<32> { typedef uint32_t type __attribute__((ext_vector_type(8))); };
+template <>
+struct NtWord<16> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
+template <>
+struct NtWord<8> { typedef uint32_t type __attribute__((ext_vector_type(2))); };
+template <>
+struct NtWord<4> { typedef uint32_t type; };
+template <>
+struct NtWord<2> { typedef uint16_t type; };
+
+template <typename T, int VW>
+__device__ __forceinline__ Pack<T, VW> ld_stream(const T* p) {
+    using W = typename NtWord<sizeof(Pack<T, VW>)>::type;
+    const W w = __builtin_nontemporal_load(reinterpret_cast<const W*>(p));
+    Pack<T, VW> v;
+    __builtin_memcpy(&v, &w, sizeof(v));
+    return v;
+}
+
 // Lane layout of an n x C row-major multivector: each row is handled by
 // LPR = C / VW lanes with VW consecutive columns per lane (lane_width
 // columns: 16-byte accesses, 8-byte for bfloat16, where the row is wide

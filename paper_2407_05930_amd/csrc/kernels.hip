@@ -506,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_sets(int64_t nL, int64_t ldm, 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (row0 + r < nL) {
-                mv[r] = ld<TM, KV>(Ma + (row0 + r) * ldm + k0);
+                mv[r] = ld_stream<TM, KV>(Ma + (row0 + r) * ldm + k0);
             } else {
 #pragma unroll
                 for (int e = 0; e < KV; ++e) mv[r].e[e] = TM(0);
