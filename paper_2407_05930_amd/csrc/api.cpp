@@ -237,9 +237,7 @@ static DevCsr upload_csr(msp_ctx* c, const Csr& M, bool fp32, bool bf16 = false)
 }
 
 // Pattern of M with vs interleaved value sets (values: nnz * vs, entry k of set a at k * vs + a).
-// bf16: also a bfloat16 copy of the values (read with bfloat16 multivectors).
-static DevCsr upload_sets(msp_ctx* c, const Csr& M, const std::vector<double>& values, int vs, bool fp32,
-                          bool bf16 = false) {
+static DevCsr upload_sets(msp_ctx* c, const Csr& M, const std::vector<double>& values, int vs, bool fp32) {
     if (static_cast<int64_t>(values.size()) != M.nnz() * vs) throw Error(MSP_ERR_ARG, "value sets size mismatch");
     Csr pat = M;
     pat.v.assign(1, 0.0);
@@ -260,11 +258,6 @@ static DevCsr upload_sets(msp_ctx* c, const Csr& M, const std::vector<double>& v
     if (fp32) {
         std::vector<float> f(values.begin(), values.end());
         D.v32 = c->upload(f.data(), static_cast<int64_t>(f.size()));
-        if (bf16) {
-            std::vector<Bf16> h(f.size());
-            for (size_t q = 0; q < f.size(); ++q) h[q] = to_bf16(f[q]);
-            D.v16 = c->upload(h.data(), static_cast<int64_t>(h.size()));
-        }
     }
     return D;
 }
@@ -336,7 +329,7 @@ static void resolve_timers(msp_ctx* c) {
 template <typename T>
 static double spmm_bytes(const DevCsr& M, int C, bool z, const DevOuter* sig, int S) {
     const double w = sizeof(T);
-    const double wv = (sizeof(T) <= 4 && M.v16) ? 2.0 : static_cast<double>(sizeof(typename ValOf<T>::type));
+    const double wv = (sizeof(T) == 4 && M.v16) ? 2.0 : static_cast<double>(sizeof(typename ValOf<T>::type));
     double b = static_cast<double>(M.nnz) * (wv * M.vs + 4.0) + 4.0 * static_cast<double>(M.nr + 1);
     b += static_cast<double>(M.nc) * C * w + static_cast<double>(M.nr) * C * w;
     if (z) b += static_cast<double>(M.nr) * C * w;
@@ -351,21 +344,19 @@ static int log2i(int C) {
 }
 
 // One SpMM launch with an explicit lane-group split (1 = one group per row);
-// FP32 and bfloat16 products use the bfloat16 values when the matrix carries
-// them (the factored smoother of the BF16 variant; the per-subsystem value
-// sets of the bfloat16-multivector mode).
+// FP32 products use the bfloat16 values when the matrix carries them.
 template <typename T>
 static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const T* X, T* Y, const T* Z,
                         acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m) {
     using TV = typename ValOf<T>::type;
-    if constexpr (std::is_same<T, float>::value || std::is_same<T, Bf16>::value) {
+    if constexpr (std::is_same<T, float>::value) {
         if (M.v16) {
             if (split > 1)
-                HIPCHECK((launch_spmm_split<T, Bf16>(st, C, split, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta,
-                                                     M.vs, m, sigma, S)));
+                HIPCHECK((launch_spmm_split<float, Bf16>(st, C, split, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta,
+                                                         1, m, sigma, S)));
             else
-                HIPCHECK((launch_spmm<T, Bf16>(st, C, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta, sigma, S, m,
-                                               M.vs)));
+                HIPCHECK((launch_spmm<float, Bf16>(st, C, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta, sigma, S, m,
+                                                   1)));
             return;
         }
     }
@@ -698,9 +689,6 @@ static DevOuter upload_outer(msp_ctx* c, const std::vector<double>& dense, int64
 static void upload_all(msp_ctx* c) {
     HIPCHECK(hipSetDevice(c->device));
     const bool f32 = mixed(c);
-    // the bfloat16-multivector mode also reads the per-subsystem value sets (interpolation,
-    // restriction, and the operators below level 1) in bfloat16
-    const bool b16 = c->o.precision == MSP_MIXED_BF16;
     c->d_img = c->upload(c->sym.img.data(), static_cast<int64_t>(c->sym.img.size()));
     c->dsig = upload_outer(c, c->sym.sigma, c->sym.n_b, 1 << c->sym.s);
     c->dAinn = upload_csr(c, c->sym.Ainn, false);
@@ -732,10 +720,10 @@ static void upload_all(msp_ctx* c) {
                     if (j != H.A.nr) throw Error(MSP_ERR_ARG, "coarse numbering of the reduction level");
                     c->dsig1 = upload_outer(c, s1, H.A.nr, S);
                 } else {
-                    D.A = upload_sets(c, H.A, c->subv.A[l], S, f32, b16);
+                    D.A = upload_sets(c, H.A, c->subv.A[l], S, f32);
                 }
-                D.P = upload_sets(c, H.P, c->subv.P[l], S, f32, b16);
-                D.R = upload_sets(c, H.R, c->subv.R[l], S, f32, b16);
+                D.P = upload_sets(c, H.P, c->subv.P[l], S, f32);
+                D.R = upload_sets(c, H.R, c->subv.R[l], S, f32);
                 D.M = upload_sets(c, H.M, c->subv.M[l], 1, f32);   // shared smoother, one value set
                 continue;
             }

@@ -760,11 +760,10 @@ __global__ void k_gather_flags(int nsys, int* const* __restrict__ ptrs, int* __r
         default: return hipErrorInvalidValue;                    \
     }
 
-// value sets are supported for FP64 and FP32 values, and for bfloat16 values
-// with bfloat16 multivectors
-template <typename T, typename TV>
+// value sets are supported for FP64 and FP32 values (not bfloat16)
+template <typename TV>
 constexpr bool sets_ok() {
-    return !std::is_same<TV, Bf16>::value || std::is_same<T, Bf16>::value;
+    return !std::is_same<TV, Bf16>::value;
 }
 
 template <typename T, typename TV>
@@ -772,10 +771,10 @@ hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, cons
                        const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m,
                        int vs) {
     if (n <= 0) return hipSuccess;
-    if (vs > 1 && (!sets_ok<T, TV>() || m < 1)) return hipErrorInvalidValue;
+    if (vs > 1 && (!sets_ok<TV>() || m < 1)) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         using L = Lanes<T, CC>;
-        if constexpr (sets_ok<T, TV>()) {
+        if constexpr (sets_ok<TV>()) {
             if (vs > 1) {
                 hipLaunchKernelGGL((k_spmm<T, TV, CC, true>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp,
                                    ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs);
@@ -794,7 +793,7 @@ static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int
     constexpr int TPR = G * Lanes<T, CC>::LPR;
     if constexpr (TPR <= kBlock) {
         constexpr int RPB = kBlock / TPR;
-        if constexpr (sets_ok<T, TV>()) {
+        if constexpr (sets_ok<TV>()) {
             if (vs > 1) {
                 hipLaunchKernelGGL((k_spmm_split<T, TV, CC, G, true>), dim3(blocks_for(n, RPB)), dim3(kBlock), 0, st,
                                    n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S);
@@ -812,7 +811,7 @@ hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int3
                              OuterDiag sigma, int S) {
     if (n <= 0) return hipSuccess;
     if ((vs > 1 || sigma.idx) && m < 1) return hipErrorInvalidValue;
-    if (vs > 1 && !sets_ok<T, TV>()) return hipErrorInvalidValue;
+    if (vs > 1 && !sets_ok<TV>()) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         constexpr int LPR = Lanes<T, CC>::LPR;
         const int gmax = kBlock / LPR;
@@ -840,7 +839,6 @@ MSP_SPMM_INST(double, double)
 MSP_SPMM_INST(float, float)
 MSP_SPMM_INST(float, Bf16)
 MSP_SPMM_INST(Bf16, float)
-MSP_SPMM_INST(Bf16, Bf16)
 
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
