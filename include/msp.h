@@ -78,11 +78,9 @@ enum { MSP_FP64 = 0, MSP_MIXED_FP32 = 1, MSP_MIXED_FP32_BF16G = 2, MSP_MIXED_BF1
      the interface coarse, so P_0 = [W; I] serves every a and the level-0
      residual uses A_a itself.  Below it each subsystem has its own reduced
      operator A_1,a = P_0^T A_a P_0 and levels built from it with the shared
-     C/F splits and sparsity patterns (interpolation and Galerkin values per
-     subsystem, so one SpMM pass still serves all columns); the smoother of
-     such a level is shared, the shared level's FSAI factor with the smallest
-     of the subsystems' dampings; each subsystem has its own dense coarsest
-     inverse.  Optional LRCAMG(k) on top. */
+     C/F splits and sparsity patterns (values per subsystem, so one SpMM pass
+     still serves all columns); each has its own dense coarsest inverse.
+     Optional LRCAMG(k) on top. */
 enum { MSP_PC_AMGR = 0, MSP_PC_FSAI = 1, MSP_PC_NONE = 2, MSP_PC_AMGR_SUB = 3 };
 
 typedef struct msp_ctx msp_ctx;
@@ -177,9 +175,8 @@ int msp_export_level(const msp_ctx* c, int32_t lev, int8_t* cf, int64_t* A_rp, i
 /* MSP_PC_AMGR_SUB only: values of subsystem a (0 <= a < 2^s) on level
    lev >= 1, on the patterns msp_export_level gives for that level (A_v:
    nnz_A values, P_v: nnz_P, G_v: nnz_G; P and G absent on the coarsest
-   level) and its smoother damping (G and the damping are the same for every
-   subsystem).  Any pointer may be NULL.  MSP_ERR_ARG for another
-   preconditioner, lev = 0 or an index out of range. */
+   level) and its damping.  Any pointer may be NULL.  MSP_ERR_ARG for
+   another preconditioner, lev = 0 or an index out of range. */
 int msp_export_sub_level(const msp_ctx* c, int32_t lev, int32_t a, double* A_v, double* P_v, double* G_v,
                          double* omega);
 /* Outer part: sigma[i * 2^s + a] (diagonal of A_out,a) and the interface

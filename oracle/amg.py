@@ -480,24 +480,21 @@ class SubHierarchy:
     A_a = A_inn + diag(sigma_a) (sigma_a lives on interface rows only).  The
     reduced operators differ only on the interface diagonal:
     A_1,a = P_0^T A_a P_0 = A_1,inn + diag(sigma_a[C]).  Levels below are
-    built for every subsystem from its own A_1,a: its own interpolation and
-    Galerkin operators on the C/F splits of the shared hierarchy on A_inn (so
-    all subsystems share one sparsity pattern per level).  The smoother of
-    such a level is shared: the FSAI factor G of the shared level, damped
-    with the smallest of the subsystems' dampings (omega_a from the power
-    iteration on G A_l,a G^T), so omega lambda_max(G A_l,a G^T) stays within
-    the bound of each subsystem's own damping and one M = omega G^T G serves
-    every subsystem."""
+    built for every subsystem from its own A_1,a, with the C/F splits and
+    smoother patterns of the shared hierarchy on A_inn (so all subsystems
+    share one sparsity pattern per level) and each subsystem's own values."""
     level0: Level
     subs: List[Hierarchy]          # per subsystem: levels 1.. (coarsest dense)
 
 
-def sub_level_values(A: sp.csr_matrix, shared: Level, steps: int, seed: int) -> Level:
-    """One level for a subsystem operator A: the shared level's C/F split and
-    smoother factor G, the damping of G for this A (before the minimum over
-    the subsystems is taken), and A's own interpolation."""
+def sub_level_values(A: sp.csr_matrix, shared: Level, steps: int, seed: int, level0: bool) -> Level:
+    """One level for a subsystem operator A with the shared level's C/F split
+    and FSAI pattern (from the strength of the shared operator)."""
+    n = A.shape[0]
     C = shared.C
-    G = shared.G
+    S = strength(shared.A, AMGOptions.theta)
+    block = C.astype(np.int64) if level0 else np.zeros(n, dtype=np.int64)
+    G = fsai(A, S, block)
     om = damping(A, G, seed)
     P = interpolation(A, C, steps)
     R = P.T.tocsr()
@@ -519,15 +516,11 @@ def build_sub_hierarchy(hier: Hierarchy, sigma: np.ndarray, opt: AMGOptions) -> 
             if lev == hier.nlev - 1:
                 levels.append(Level(A=A))
                 break
-            Lv = sub_level_values(A, hier.levels[lev], opt.jacobi, opt.seed)
+            Lv = sub_level_values(A, hier.levels[lev], opt.jacobi, opt.seed, False)
             levels.append(Lv)
             A = galerkin(A, Lv.P)
         fac = sla.cho_factor(levels[-1].A.toarray(), lower=True)
         subs.append(Hierarchy(levels=levels, coarse_factor=fac))
-    for lev in range(hier.nlev - 2):   # one damping per level: the smallest
-        om = min(sub.levels[lev].omega for sub in subs)
-        for sub in subs:
-            sub.levels[lev].omega = om
     return SubHierarchy(level0=L0, subs=subs)
 
 

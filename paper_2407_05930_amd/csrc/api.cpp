@@ -701,9 +701,8 @@ static void upload_all(msp_ctx* c) {
             D.n = H.A.nr;
             D.omega = H.omega;
             if (c->sub && l > 0) {
-                // one value set per subsystem on the shared patterns for A, P and R; the
-                // smoother is the shared level's, explicit omega G^T G with the smallest of
-                // the subsystems' dampings, in every precision.  A_1,a = A_1 + diag(sigma_a)
+                // one value set per subsystem on the shared patterns; the smoother is
+                // explicit (omega_a G_a^T G_a) in every precision.  A_1,a = A_1 + diag(sigma_a)
                 // on the coarse interface points, so level 1 keeps the shared values and
                 // applies the outer diagonal like the reduction level does.
                 if (l == 1) {
@@ -724,7 +723,7 @@ static void upload_all(msp_ctx* c) {
                 }
                 D.P = upload_sets(c, H.P, c->subv.P[l], S, f32);
                 D.R = upload_sets(c, H.R, c->subv.R[l], S, f32);
-                D.M = upload_sets(c, H.M, c->subv.M[l], 1, f32);   // shared smoother, one value set
+                D.M = upload_sets(c, H.M, c->subv.M[l], S, f32);
                 continue;
             }
             D.A = upload_csr(c, H.A, f32);
@@ -1464,9 +1463,8 @@ int msp_export_sub_level(const msp_ctx* c, int32_t lev, int32_t a, double* A_v, 
     };
     take(c->subv.A[lev], A_v);
     take(c->subv.P[lev], P_v);
-    const msp::Csr& G = c->hier.lev[lev].G;   // the smoother factor is the shared level's
-    if (G_v && lev + 1 < static_cast<int32_t>(c->hier.lev.size())) std::copy(G.v.begin(), G.v.end(), G_v);
-    if (omega) *omega = lev + 1 < static_cast<int32_t>(c->hier.lev.size()) ? c->subv.omega[lev] : 0.0;
+    take(c->subv.G[lev], G_v);
+    if (omega) *omega = c->subv.omega[lev][a];
     return MSP_OK;
 }
 

@@ -731,13 +731,15 @@ SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& si
     V.P.assign(L, {});
     V.R.assign(L, {});
     V.M.assign(L, {});
-    V.omega.assign(L, 0.0);
-    std::vector<std::vector<double>> om_sub(L, std::vector<double>(S, 0.0));   // each subsystem's own damping
+    V.G.assign(L, {});
+    V.omega.assign(L, std::vector<double>(S, 0.0));
     for (int l = 1; l < L; ++l) {
         V.A[l].assign(H.lev[l].A.nnz() * S, 0.0);
         if (l + 1 < L) {
             V.P[l].assign(H.lev[l].P.nnz() * S, 0.0);
             V.R[l].assign(H.lev[l].R.nnz() * S, 0.0);
+            V.M[l].assign(H.lev[l].M.nnz() * S, 0.0);
+            V.G[l].assign(H.lev[l].G.nnz() * S, 0.0);
         }
     }
     const int64_t nL = H.lev[L - 1].A.nr;
@@ -766,13 +768,24 @@ SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& si
             const HostLevel& Ls = H.lev[l];
             for (int64_t k = 0; k < A.nnz(); ++k) V.A[l][k * S + a] = A.v[k];
             if (l + 1 == L) break;
-            om_sub[l][a] = damping(A, Ls.G, Ls.GT, o.seed);   // the shared factor on this subsystem
+            std::vector<std::vector<int32_t>> lower(A.nr);
+            for (int64_t i = 0; i < A.nr; ++i)
+                for (int64_t k = Ls.G.rp[i]; k < Ls.G.rp[i + 1]; ++k)
+                    if (Ls.G.ci[k] != i) lower[i].push_back(Ls.G.ci[k]);
+            Csr G = fsai_rows(A, lower);
+            Csr GT = transpose(G);
+            const double om = damping(A, G, GT, o.seed);
             Csr P = interpolation(A, Ls.cf, o.jacobi);
             Csr R = transpose(P);
-            if (!same_pattern(P, Ls.P))
+            Csr M = spgemm(GT, G);
+            for (double& v : M.v) v *= om;
+            if (!same_pattern(P, Ls.P) || !same_pattern(M, Ls.M) || !same_pattern(G, Ls.G))
                 throw Error(MSP_ERR_ARG, "subsystem level pattern differs from the shared level");
+            V.omega[l][a] = om;
             for (int64_t k = 0; k < P.nnz(); ++k) V.P[l][k * S + a] = P.v[k];
             for (int64_t k = 0; k < R.nnz(); ++k) V.R[l][k * S + a] = R.v[k];
+            for (int64_t k = 0; k < M.nnz(); ++k) V.M[l][k * S + a] = M.v[k];
+            for (int64_t k = 0; k < G.nnz(); ++k) V.G[l][k * S + a] = G.v[k];
             Csr Anext = spgemm(R, spgemm(A, P));
             if (!same_pattern(Anext, H.lev[l + 1].A))
                 throw Error(MSP_ERR_ARG, "subsystem reduced operator pattern differs from the shared one");
@@ -795,15 +808,6 @@ SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& si
     for (auto& t : th) t.join();
     for (int a = 0; a < S; ++a)
         if (codes[a] != MSP_OK) throw Error(codes[a], "subsystem " + std::to_string(a) + ": " + errs[a]);
-    // one smoother per level for every subsystem: omega G^T G with the smallest damping
-    for (int l = 1; l + 1 < L; ++l) {
-        const HostLevel& Ls = H.lev[l];
-        V.omega[l] = *std::min_element(om_sub[l].begin(), om_sub[l].end());
-        Csr M = spgemm(Ls.GT, Ls.G);
-        if (!same_pattern(M, Ls.M)) throw Error(MSP_ERR_ARG, "smoother pattern differs from the shared level");
-        for (double& v : M.v) v *= V.omega[l];
-        V.M[l] = std::move(M.v);
-    }
     return V;
 }
 

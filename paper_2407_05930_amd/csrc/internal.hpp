@@ -50,16 +50,13 @@ struct HostHierarchy {
 // Values are interleaved, entry k of subsystem a at [k * S + a].
 struct SubValues {
     int S = 0;
-    std::vector<std::vector<double>> A, P, R;   // by level (index 0 unused), S interleaved value sets
-    std::vector<std::vector<double>> M;         // by level: one value set (the shared smoother)
-    std::vector<double> omega;                  // by level: the damping of the shared smoother
-    std::vector<double> coarse_inv;             // S blocks of nL x nL
+    std::vector<std::vector<double>> A, P, R, M, G;   // by level (index 0 unused)
+    std::vector<std::vector<double>> omega;           // by level, S values
+    std::vector<double> coarse_inv;                   // S blocks of nL x nL
 };
 
 // A_1,a = A_1,inn + diag(sigma_a on the interface coarse points), then the
-// standard levels with the shared splits and patterns: each subsystem's own
-// interpolation and Galerkin operators, and one smoother per level, the
-// shared level's factor G with the smallest of the subsystems' dampings.
+// standard levels with the shared splits and patterns.
 SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& sigma,
                            const std::vector<int8_t>& iface, int S, const msp_opts& o);
 

@@ -341,31 +341,6 @@ def test_sub_patterns_equal_shared_patterns():
                 assert np.array_equal(X.indptr, Y.indptr) and np.array_equal(X.indices, Y.indices)
 
 
-def test_sub_smoother_is_shared_factor_with_smallest_damping():
-    """Below the reduction level every subsystem uses the shared level's FSAI
-    factor G with one damping: the smallest of the subsystems' own dampings.
-    Checked against dense spectra: omega * lambda_max(G A_l,a G^T) < 2 for
-    every subsystem (a convergent damped smoother for each), and the
-    subsystem with the largest spectrum sets omega (omega lambda_max close to
-    the 4/3 of the damping rule, up to the power iteration's underestimate)."""
-    hier, sigma, _, opt = _sub((10, 10, 10), coarse_max=20, y_stretch=1.5)
-    assert hier.nlev >= 3
-    SH = amg.build_sub_hierarchy(hier, sigma, opt)
-    for lev in range(1, hier.nlev - 1):
-        Gs = hier.levels[lev].G
-        Gd = Gs.toarray()
-        om = SH.subs[0].levels[lev - 1].omega
-        lams, own = [], []
-        for sub in SH.subs:
-            L = sub.levels[lev - 1]
-            assert (L.G != Gs).nnz == 0 and L.omega == om
-            lams.append(np.linalg.eigvalsh(Gd @ L.A.toarray() @ Gd.T).max())
-            own.append(amg.damping(L.A, Gs, opt.seed))
-        assert om == min(own)
-        assert max(om * lam for lam in lams) < 2.0
-        assert 4.0 / 3.0 <= om * max(lams) <= 4.0 / 3.0 * 1.2
-
-
 def test_sub_two_grid_is_exact_two_grid_of_subsystem():
     """With two levels the per-subsystem cycle is the two-grid method for
     A_a with the Galerkin coarse operator solved exactly:
