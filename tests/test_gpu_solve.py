@@ -325,3 +325,30 @@ def test_full_size_channel_bf16_multivectors():
     rr = krylov.true_relres(p.A, x, p.b)
     _say("128^3 bf16 vectors iters", sv.last.iters, "relres", rr, "t", sv.last.t_solve_s)
     assert np.all(rr <= 2e-10)
+
+
+def test_full_size_jitter_config_properties():
+    """192^3 jittered octant with lognormal kappa, s = 3, k = 16 (the jittered
+    workload at its full size, in the configuration the bench times): the
+    FP64 and the bfloat16-multivector solves reach a true relative residual of
+    1e-10; the bfloat16 one in at most 10% (plus one) more iterations, and
+    both solutions agree to 1e-9 (the tolerance times the condition growth of
+    a high-contrast kappa)."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    p = config_problem("jitter3d_192_s3")
+    b = torch.from_numpy(p.b).cuda()
+    out = {}
+    for prec in ("fp64", "mixed_bf16"):
+        _say("192^3 jittered", prec)
+        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, pc="amgr_sub", k=16)
+        x = sv.solve(b).cpu().numpy()
+        rr = krylov.true_relres(p.A, x, p.b)
+        out[prec] = (x, sv.last.iters)
+        _say("  iters", sv.last.iters, "relres", rr.max(), "t", sv.last.t_solve_s)
+        assert np.all(rr <= 1.5e-10)
+        assert sv.last.iters < 30
+        sv.close()
+    assert out["mixed_bf16"][1] <= int(1.1 * out["fp64"][1]) + 1
+    x64, xb = out["fp64"][0], out["mixed_bf16"][0]
+    assert np.linalg.norm(xb - x64) / np.linalg.norm(x64) <= 1e-9
