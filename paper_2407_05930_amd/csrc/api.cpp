@@ -888,38 +888,39 @@ struct SolvePlan {
             precondition_base(c, W, st, W.r, W.z, true);
         }
         const double wu = ubytes();
-        const double bytes =
-            (s16 ? 2.0 : (s32 ? 4.0 : 8.0)) * nb * C + 2.0 * vb() + (kl ? nb * S * kl * wu : 0.0);
+        double* z2 = init ? W.p : nullptr;   // the first search direction p = z
+        const double bytes = (s16 ? 2.0 : (s32 ? 4.0 : 8.0)) * nb * C + (init ? 3.0 : 2.0) * vb() +
+                             (kl ? nb * S * kl * wu : 0.0);
         const void* U = lrc_amg ? c->d_U : nullptr;
         timed(c, KD_CAST, bytes, st, [&] {
             if (s16) {
                 if (c->U16)
                     HIPCHECK((launch_zfinish<Bf16, Bf16>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const Bf16*>(U),
-                                                         c->d_lrc_W, S, kl, m, W.pp1)));
+                                                         c->d_lrc_W, S, kl, m, W.pp1, z2)));
                 else if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<Bf16, float>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const float*>(U),
-                                                          c->d_lrc_W, S, kl, m, W.pp1)));
+                                                          c->d_lrc_W, S, kl, m, W.pp1, z2)));
                 else
                     HIPCHECK((launch_zfinish<Bf16, double>(st, C, nbz, nb, s16, W.z, W.r,
                                                            static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
-                                                           W.pp1)));
+                                                           W.pp1, z2)));
             } else if (s32) {
                 if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<float, float>(st, C, nbz, nb, s32, W.z, W.r, static_cast<const float*>(U),
-                                                           c->d_lrc_W, S, kl, m, W.pp1)));
+                                                           c->d_lrc_W, S, kl, m, W.pp1, z2)));
                 else
                     HIPCHECK((launch_zfinish<float, double>(st, C, nbz, nb, s32, W.z, W.r,
                                                             static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
-                                                            W.pp1)));
+                                                            W.pp1, z2)));
             } else {
                 if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<double, float>(st, C, nbz, nb, W.z, W.z, W.r,
                                                             static_cast<const float*>(U), c->d_lrc_W, S, kl, m,
-                                                            W.pp1)));
+                                                            W.pp1, z2)));
                 else
                     HIPCHECK((launch_zfinish<double, double>(st, C, nbz, nb, W.z, W.z, W.r,
                                                              static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
-                                                             W.pp1)));
+                                                             W.pp1, z2)));
             }
         });
         HIPCHECK(launch_fin_beta(st, C, nbz, init, flexible, W.pp1, active, rzold, rho, beta, rz));
@@ -929,14 +930,13 @@ struct SolvePlan {
         Work& W = *w;
         HIPCHECK(launch_colnorm2(st, n, m, d_b, W.pp1, std::min<int64_t>(512, (n + 255) / 256), bn2));
         HIPCHECK(launch_thresholds(st, C, S, m, c->o.tol, bn2, thr));
-        HIPCHECK(launch_fill<double>(st, nb * C, W.r, 0.0));
+        if (S * m < C) HIPCHECK(launch_fill<double>(st, nb * C, W.r, 0.0));   // padded columns (Q_s writes the rest)
         HIPCHECK(launch_fill<double>(st, nb * C, W.x, 0.0));
         HIPCHECK(launch_fill<int>(st, 2, flags, 0));
         timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // bhat = Q_s b
               [&] { HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, W.r)); });
         update_dots(false);
-        precond_dot(true);
-        HIPCHECK(hipMemcpyAsync(W.p, W.z, sizeof(double) * nb * C, hipMemcpyDeviceToDevice, st));
+        precond_dot(true);   // also writes p = z
     }
 
     void half_a() {
@@ -997,12 +997,14 @@ struct SolvePlan {
     // Q_s backward and statistics (status: MSP_OK / MSP_NOT_CONVERGED / breakdown)
     int finish(double* d_x, int status, double seconds, msp_stats* out) {
         Work& W = *w;
-        if (x_pending) {   // the last iteration stopped before its p update
-            timed(c, KD_PUPDATE, 3.0 * vb(), st, [&] { HIPCHECK(launch_pcg_xupdate(st, C, nb, W.x, W.p, alpha)); });
-            x_pending = false;
-        }
-        timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // x = Q_s xhat
-              [&] { HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, W.x, d_x)); });
+        // x = Q_s xhat; when the last iteration stopped before its p update, its
+        // x step is applied inside the transform (xhat + alpha p)
+        const bool xp = x_pending;
+        x_pending = false;
+        timed(c, KD_QS, (xp ? 24.0 : 16.0) * n * m + 8.0 * n, st, [&] {
+            HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, W.x, d_x, xp ? W.p : nullptr,
+                                        xp ? alpha : nullptr));
+        });
         HIPCHECK(hipMemcpyAsync(W.h_iters, iters, 64 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipMemcpyAsync(W.h_scal, W.scal, SC_COUNT * 64 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipMemcpyAsync(W.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));

@@ -315,24 +315,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_pupdate(int64_t n, double* __res
     st<double, VW>(p + o, pv);
 }
 
-// x += alpha p: the x step of an iteration that ends the solve before its p update
-template <int C>
-__global__ __launch_bounds__(kBlock) void k_pcg_xupdate(int64_t n, double* __restrict__ x,
-                                                        const double* __restrict__ p,
-                                                        const double* __restrict__ alpha) {
-    using L = Lanes<double, C>;
-    constexpr int VW = L::VW;
-    const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
-    const int lane = threadIdx.x % L::LPR;
-    if (row >= n) return;
-    const int64_t o = row * C + lane * VW;
-    Pack<double, VW> xv = ld<double, VW>(x + o);
-    const Pack<double, VW> pv = ld<double, VW>(p + o);
-#pragma unroll
-    for (int e = 0; e < VW; ++e) xv.e[e] += alpha[lane * VW + e] * pv.e[e];
-    st<double, VW>(x + o, xv);
-}
-
 // ------------------------------------------------------------------ Q_s (Alg. 1, eq. (2.12))
 // Q_s = 2^{-s/2} Had (x) I: a Walsh-Hadamard butterfly over the 2^s images of
 // each base cell, fused with the layout change between the caller's n x m
@@ -367,18 +349,23 @@ __global__ __launch_bounds__(kBlock) void k_qs_forward(int64_t n_b, int m, int C
     for (int a = 0; a < S; ++a) out[i * C + a * m + j] = scale * v[a];
 }
 
+// p != nullptr: the transform reads xh + alpha p (an x step not yet applied).
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_qs_backward(int64_t n_b, int m, int C, int64_t n,
                                                         const int64_t* __restrict__ img,
                                                         const double* __restrict__ xh, double* __restrict__ x,
-                                                        double scale) {
+                                                        double scale, const double* __restrict__ p,
+                                                        const double* __restrict__ alpha) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= n_b * m) return;
     const int64_t i = t / m;
     const int j = (int)(t % m);
     double v[S];
 #pragma unroll
-    for (int a = 0; a < S; ++a) v[a] = xh[i * C + a * m + j];
+    for (int a = 0; a < S; ++a) {
+        v[a] = xh[i * C + a * m + j];
+        if (p) v[a] += alpha[a * m + j] * p[i * C + a * m + j];
+    }
     fwht<S>(v);
 #pragma unroll
     for (int a = 0; a < S; ++a) x[img[i * S + a] + (int64_t)j * n] = scale * v[a];
@@ -892,14 +879,6 @@ hipError_t launch_pcg_pupdate(hipStream_t st, int C, int64_t n, double* x, doubl
     });
     return hipGetLastError();
 }
-hipError_t launch_pcg_xupdate(hipStream_t st, int C, int64_t n, double* x, const double* p, const double* alpha) {
-    MSP_DISPATCH_C(C, {
-        using L = Lanes<double, CC>;
-        hipLaunchKernelGGL((k_pcg_xupdate<CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, x, p, alpha);
-    });
-    return hipGetLastError();
-}
-
 #define MSP_DISPATCH_S(S, ...)                                   \
     switch (S) {                                                 \
         case 1: { constexpr int SS = 1; __VA_ARGS__; } break;    \
@@ -922,11 +901,12 @@ hipError_t launch_qs_forward(hipStream_t st, int S, int64_t n_b, int m, int C, i
     return hipGetLastError();
 }
 hipError_t launch_qs_backward(hipStream_t st, int S, int64_t n_b, int m, int C, int64_t n, const int64_t* img,
-                              const double* xh, double* x) {
+                              const double* xh, double* x, const double* p, const double* alpha) {
+    if (p && !alpha) return hipErrorInvalidValue;
     const double scale = 1.0 / std::sqrt((double)S);
     MSP_DISPATCH_S(S, {
         hipLaunchKernelGGL((k_qs_backward<SS>), dim3(blocks_for(n_b * m, kBlock)), dim3(kBlock), 0, st, n_b, m, C,
-                           n, img, xh, x, scale);
+                           n, img, xh, x, scale, p, alpha);
     });
     return hipGetLastError();
 }

@@ -71,13 +71,13 @@ hipError_t launch_pcg_update(hipStream_t st, int C, int64_t n, double* x, double
 // x += alpha p (every column; alpha = 0 on frozen ones), then p = z + beta p on active columns
 hipError_t launch_pcg_pupdate(hipStream_t st, int C, int64_t n, double* x, double* p, const double* z,
                               const double* alpha, const double* beta, const int* active);
-// x += alpha p
-hipError_t launch_pcg_xupdate(hipStream_t st, int C, int64_t n, double* x, const double* p, const double* alpha);
 
 hipError_t launch_qs_forward(hipStream_t st, int S, int64_t n_b, int m, int C, int64_t n, const int64_t* img,
                              const double* b, double* out);
+// p != nullptr: transforms xh + alpha p (alpha per column), the x step of an
+// iteration that ended the solve before its p update
 hipError_t launch_qs_backward(hipStream_t st, int S, int64_t n_b, int m, int C, int64_t n, const int64_t* img,
-                              const double* xh, double* x);
+                              const double* xh, double* x, const double* p = nullptr, const double* alpha = nullptr);
 // out[j] = ||b_j||^2 for the m columns of an n x m column-major array (partial: nb * m scratch)
 hipError_t launch_colnorm2(hipStream_t st, int64_t n, int m, const double* b, double* partial, int nb,
                            double* out);

@@ -245,10 +245,12 @@ __global__ __launch_bounds__(kBlock) void k_fin_check(int nb, int C, int init, i
 
 // z = s (cast to FP64; s may alias z) + sum_t U[i, a*k+t] W[(a*k+t)*m + j]
 // (the expansion of the low-rank correction); partial[b, c] = sum r z.
+// z2 != nullptr: z is also written there (the first search direction).
 template <int C, typename TS, bool LRC, typename TU>
 __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, double* z, const double* __restrict__ r,
                                                     const TU* __restrict__ U, const double* __restrict__ W, int S,
-                                                    int k, int m, double* __restrict__ partial) {
+                                                    int k, int m, double* __restrict__ partial,
+                                                    double* __restrict__ z2) {
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
     __shared__ double sm[kBlock * VW];
     __shared__ double wl[LRC ? 64 * 16 : 1];
@@ -292,6 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
             }
         }
         st<double, VW>(z + o, zv);
+        if (z2) st<double, VW>(z2 + o, zv);
         const Pack<double, VW> rv = ld<double, VW>(r + o);
 #pragma unroll
         for (int e = 0; e < VW; ++e) acc[e] += rv.e[e] * zv.e[e];
@@ -465,32 +468,27 @@ hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex,
 
 template <typename TS, typename TU>
 hipError_t launch_zfinish(hipStream_t st, int C, int nb, int64_t n, const TS* s, double* z, const double* r,
-                          const TU* U, const double* W, int S, int k, int m, double* partial) {
+                          const TU* U, const double* W, int S, int k, int m, double* partial, double* z2) {
     MSP_DISPATCH_C(C, {
         if (U && k > 0)
             hipLaunchKernelGGL((k_zfinish<CC, TS, true, TU>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k, m,
-                               partial);
+                               partial, z2);
         else
             hipLaunchKernelGGL((k_zfinish<CC, TS, false, TU>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k,
-                               m, partial);
+                               m, partial, z2);
     });
     return hipGetLastError();
 }
-template hipError_t launch_zfinish<float, float>(hipStream_t, int, int, int64_t, const float*, double*,
-                                                 const double*, const float*, const double*, int, int, int, double*);
-template hipError_t launch_zfinish<double, double>(hipStream_t, int, int, int64_t, const double*, double*,
-                                                   const double*, const double*, const double*, int, int, int,
-                                                   double*);
-template hipError_t launch_zfinish<double, float>(hipStream_t, int, int, int64_t, const double*, double*,
-                                                  const double*, const float*, const double*, int, int, int, double*);
-template hipError_t launch_zfinish<float, double>(hipStream_t, int, int, int64_t, const float*, double*,
-                                                  const double*, const double*, const double*, int, int, int, double*);
-template hipError_t launch_zfinish<Bf16, float>(hipStream_t, int, int, int64_t, const Bf16*, double*, const double*,
-                                                const float*, const double*, int, int, int, double*);
-template hipError_t launch_zfinish<Bf16, double>(hipStream_t, int, int, int64_t, const Bf16*, double*, const double*,
-                                                 const double*, const double*, int, int, int, double*);
-template hipError_t launch_zfinish<Bf16, Bf16>(hipStream_t, int, int, int64_t, const Bf16*, double*, const double*,
-                                               const Bf16*, const double*, int, int, int, double*);
+#define MSP_ZFINISH_INST(TS, TU)                                                                                  \
+    template hipError_t launch_zfinish<TS, TU>(hipStream_t, int, int, int64_t, const TS*, double*, const double*,    \
+                                               const TU*, const double*, int, int, int, double*, double*);
+MSP_ZFINISH_INST(float, float)
+MSP_ZFINISH_INST(double, double)
+MSP_ZFINISH_INST(double, float)
+MSP_ZFINISH_INST(float, double)
+MSP_ZFINISH_INST(Bf16, float)
+MSP_ZFINISH_INST(Bf16, double)
+MSP_ZFINISH_INST(Bf16, Bf16)
 
 hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
                            const int* active, const double* rzold, double* rho, double* beta, double* rz) {

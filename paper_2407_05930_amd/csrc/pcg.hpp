@@ -27,7 +27,7 @@ hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t
                          double* partial);
 hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial, const int* active,
                             const double* rho, double* alpha, double* pq, int* flags);
-// upd: r -= alpha q (x is updated by launch_pcg_pupdate / launch_pcg_xupdate)
+// upd: r -= alpha q (x is updated by launch_pcg_pupdate, or by the back transform after the last iteration)
 template <typename TU>
 hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* r,
                               const double* q, const double* alpha, const double* z, const TU* U, int S, int m,
@@ -35,9 +35,10 @@ hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
                             const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
                             int* iters, int* flags, double* rnorm, double* rzold, double* W);
+// z2 != nullptr: z also written there (the first search direction p = z)
 template <typename TS, typename TU>
 hipError_t launch_zfinish(hipStream_t st, int C, int nb, int64_t n, const TS* s, double* z, const double* r,
-                          const TU* U, const double* W, int S, int k, int m, double* partial);
+                          const TU* U, const double* W, int S, int k, int m, double* partial, double* z2 = nullptr);
 hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
                            const int* active, const double* rzold, double* rho, double* beta, double* rz);
 
