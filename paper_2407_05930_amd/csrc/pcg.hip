@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "device.hpp"
 #include "pcg.hpp"
@@ -104,14 +105,18 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
     __shared__ double sm[kBlock * VW];
     const int slot = threadIdx.x / LPR, lane = threadIdx.x % LPR;
     const int64_t ntiles = (n + RPB - 1) / RPB;
-    double a_rr[VW], a_rz[VW], a_l[VW][KA];
+    // each thread's share of the projections (about a dozen rows) is summed in
+    // FP32 when U itself is FP32 or bfloat16; block and grid sums are FP64
+    using TA = typename std::conditional<std::is_same<TU, double>::value, double, float>::type;
+    double a_rr[VW], a_rz[VW];
+    TA a_l[VW][KA];
     double al[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) {
         a_rr[e] = a_rz[e] = 0.0;
         al[e] = UPD ? alpha[lane * VW + e] : 0.0;
 #pragma unroll
-        for (int t = 0; t < KA; ++t) a_l[e][t] = 0.0;
+        for (int t = 0; t < KA; ++t) a_l[e][t] = TA(0);
     }
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row = tile * RPB + slot;
@@ -156,12 +161,13 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
                             if (t < k) {
                                 const Pack<TU, 4> u4 = ld<TU, 4>(u + t);
 #pragma unroll
-                                for (int q = 0; q < 4 && t + q < KA; ++q) a_l[e][t + q] += (double)to_acc(u4.e[q]) * rv.e[e];
+                                for (int q = 0; q < 4 && t + q < KA; ++q)
+                                    a_l[e][t + q] += (TA)to_acc(u4.e[q]) * (TA)rv.e[e];
                             }
                     } else {
 #pragma unroll
                         for (int t = 0; t < KA; ++t)
-                            if (t < k) a_l[e][t] += (double)to_acc(u[t]) * rv.e[e];
+                            if (t < k) a_l[e][t] += (TA)to_acc(u[t]) * (TA)rv.e[e];
                     }
                 }
             }
@@ -180,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
 #pragma unroll
             for (int tt = 0; tt < kUpdTch && t0 + tt < KA; ++tt) {
 #pragma unroll
-                for (int e = 0; e < VW; ++e) slm[(tt * kBlock + threadIdx.x) * VW + e] = a_l[e][t0 + tt];
+                for (int e = 0; e < VW; ++e) slm[(tt * kBlock + threadIdx.x) * VW + e] = (double)a_l[e][t0 + tt];
             }
             __syncthreads();
             const int nt = k - t0 < kUpdTch ? k - t0 : kUpdTch;
