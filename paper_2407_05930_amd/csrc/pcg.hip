@@ -106,8 +106,9 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
     const int slot = threadIdx.x / LPR, lane = threadIdx.x % LPR;
     const int64_t ntiles = (n + RPB - 1) / RPB;
     // each thread's share of the projections (about a dozen rows) is summed in
-    // FP32 when U itself is FP32 or bfloat16; block and grid sums are FP64
-    using TA = typename std::conditional<std::is_same<TU, double>::value, double, float>::type;
+    // FP32 when U is bfloat16 (it frees the registers that bound the occupancy);
+    // block and grid sums are FP64
+    using TA = typename std::conditional<std::is_same<TU, Bf16>::value, float, double>::type;
     double a_rr[VW], a_rz[VW];
     TA a_l[VW][KA];
     double al[VW];
