@@ -151,7 +151,11 @@ int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ct
 /* Solve for m right-hand sides held in device memory (d_b, d_x: n x m
    column-major FP64, on the context's device), enqueued on hip_stream (NULL
    = the default stream).  Returns when the solve has finished.
-   st may be NULL. */
+   st may be NULL.  The first solve with a given column count times the
+   candidate kernel shapes of every V-cycle matrix (lane-group splits; rows
+   per wavefront of the per-subsystem coarsest solves) and keeps the fastest;
+   with the environment variable MSP_AUTOTUNE_LOG set (not "0") the timings
+   are printed to stderr. */
 int msp_solve_device(msp_ctx* c, int32_t m, const double* d_b, double* d_x, void* hip_stream,
                      msp_stats* st);
 
