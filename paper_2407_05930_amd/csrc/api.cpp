@@ -67,6 +67,7 @@ struct Work {
     std::vector<void*> vy, vs, vr, vt;    // per level, element type of the V-cycle (vt: factored smoother)
     double* partial = nullptr;
     int nb_dot = 0;
+    int grid_op = 0, grid_upd = 0, grid_z = 0;   // PCG kernel grids (set by the first solve plan)
     double* dense_part = nullptr;   // k-chunk partials of the dense coarsest solve
     void* dense_pack = nullptr;     // per-subsystem packed right-hand sides of the coarsest solves
     int dense_rows = 8;             // rows per wavefront of the per-subsystem coarsest solves (autotuned)
@@ -815,6 +816,12 @@ struct SolvePlan {
         lrc_amg = c->d_U && amg(c);
         kl = lrc_amg ? c->lrc_k : 0;
         O = S * kl * m;
+        if (w->grid_op > 0) {   // the kernel variants are fixed per context and column count
+            nbo = w->grid_op;
+            nbu = w->grid_upd;
+            nbz = w->grid_z;
+            return;
+        }
         HIPCHECK(op_dot_grid(C, nb, &nbo));
         if (c->U16) HIPCHECK(update_dots_grid<Bf16>(C, flexible, kl, nb, &nbu));
         else if (c->U32 || !c->d_U) HIPCHECK(update_dots_grid<float>(C, flexible, kl, nb, &nbu));
@@ -832,6 +839,9 @@ struct SolvePlan {
             if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<double, float>(C, lz, nb, &nbz)));
             else HIPCHECK((zfinish_grid<double, double>(C, lz, nb, &nbz)));
         }
+        w->grid_op = nbo;
+        w->grid_upd = nbu;
+        w->grid_z = nbz;
     }
 
     double vb() const { return 8.0 * nb * C; }   // bytes of one FP64 multivector pass
