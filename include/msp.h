@@ -53,7 +53,7 @@ typedef enum {
     MSP_ERR_HIP = -5,            /* HIP runtime error */
     MSP_ERR_OOM = -6,            /* host or device allocation failed */
     MSP_ERR_NOT_SPD = -7,        /* a dense Cholesky factorisation failed */
-    MSP_ERR_UNSUPPORTED = -8     /* input outside what this build handles */
+    MSP_ERR_UNSUPPORTED = -8     /* input outside what the library handles */
 } msp_status;
 
 /* MSP_MIXED_FP32: FP32 V-cycle (smoother M = omega G^T G formed explicitly),
