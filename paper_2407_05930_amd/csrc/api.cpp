@@ -38,6 +38,7 @@ struct DevCsr {
     int split = 1;           // lane groups per row (long rows are split)
     int vs = 1;              // interleaved value sets (one per subsystem), entry k of set a at k * vs + a
     int tuned[3][7] = {};    // autotuned split by [multivector type: FP64, FP32, BF16][log2 C]; 0 = not tuned
+    bool wide[3][7] = {};    // autotuned 16-byte lanes of the one-group kernel, same indexing
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
     double* v64 = nullptr;
@@ -347,7 +348,7 @@ static int log2i(int C) {
 // One SpMM launch with an explicit lane-group split (1 = one group per row);
 // FP32 products use the bfloat16 values when the matrix carries them.
 template <typename T>
-static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const T* X, T* Y, const T* Z,
+static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, bool wide, const T* X, T* Y, const T* Z,
                         acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m) {
     using TV = typename ValOf<T>::type;
     if constexpr (std::is_same<T, float>::value) {
@@ -357,7 +358,7 @@ static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const
                                                          1, m, sigma, S)));
             else
                 HIPCHECK((launch_spmm<float, Bf16>(st, C, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta, sigma, S, m,
-                                                   1)));
+                                                   1, wide)));
             return;
         }
     }
@@ -365,7 +366,8 @@ static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, const
         HIPCHECK((launch_spmm_split<T, TV>(st, C, split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, M.vs, m,
                                            sigma, S)));
     else
-        HIPCHECK((launch_spmm<T, TV>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m, M.vs)));
+        HIPCHECK((launch_spmm<T, TV>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m, M.vs,
+                                     wide)));
 }
 
 template <typename T>
@@ -375,7 +377,8 @@ static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, c
     const OuterDiag od = sigma ? sigma->d : OuterDiag{nullptr, nullptr};
     const int tuned = M.tuned[tslot<T>()][log2i(C)];
     const int split = tuned ? tuned : M.split;
-    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, X, Y, Z, alpha, beta, od, S, m); });
+    const bool wide = tuned && M.wide[tslot<T>()][log2i(C)];
+    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, wide, X, Y, Z, alpha, beta, od, S, m); });
 }
 
 static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
@@ -441,14 +444,25 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
             if (jb.M->nnz == 0) continue;
             const double avg = jb.M->nr ? static_cast<double>(jb.M->nnz) / static_cast<double>(jb.M->nr) : 0.0;
             int best = 1;
+            bool best_w = false;
             float best_ms = 1e30f;
+            // candidates (split g, wide lanes w): 16-byte lanes only for one group per row
+            // and one value set, where they differ from the default lanes
+            std::vector<std::pair<int, bool>> cand;
             for (int g = 1; g <= 64 && g * lpr <= 256; g *= 2) {   // 256 threads per block
                 if (g > 1 && g > std::max(1.0, avg / 2.0)) break;
-                spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0),
+                cand.emplace_back(g, false);
+                if (g == 1 && jb.M->vs == 1 && spmm_has_wide(C, static_cast<int>(sizeof(T))))
+                    cand.emplace_back(1, true);
+            }
+            for (const auto& gw : cand) {
+                const int g = gw.first;
+                const bool wv = gw.second;
+                spmm_launch<T>(st, C, *jb.M, g, wv, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0),
                                OuterDiag{nullptr, nullptr}, S, mt);
                 HIPCHECK(hipEventRecord(e0, st));
                 for (int rep = 0; rep < 3; ++rep)
-                    spmm_launch<T>(st, C, *jb.M, g, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0),
+                    spmm_launch<T>(st, C, *jb.M, g, wv, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0),
                                    OuterDiag{nullptr, nullptr}, S, mt);
                 HIPCHECK(hipEventRecord(e1, st));
                 HIPCHECK(hipEventSynchronize(e1));
@@ -456,14 +470,17 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
                 HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
                 if (log)
                     std::fprintf(stderr, "msp autotune: C=%d elem=%d level %zu %s (%lld rows, %.1f nnz/row, %d sets) "
-                                 "split %d: %.2f us\n", C, static_cast<int>(sizeof(T)), l, names[j],
-                                 static_cast<long long>(jb.M->nr), avg, jb.M->vs, g, 1000.0 * ms / 3);
+                                 "split %d%s: %.2f us\n", C, static_cast<int>(sizeof(T)), l, names[j],
+                                 static_cast<long long>(jb.M->nr), avg, jb.M->vs, g, wv ? " wide" : "",
+                                 1000.0 * ms / 3);
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = g;
+                    best_w = wv;
                 }
             }
             jb.M->tuned[tslot<T>()][log2i(C)] = best;
+            jb.M->wide[tslot<T>()][log2i(C)] = best_w;
         }
     }
     // rows per wavefront of the per-subsystem coarsest solves

@@ -86,9 +86,12 @@ __device__ __forceinline__ Pack<T, VW> ld_stream(const T* p) {
 // LPR = C / VW lanes with VW consecutive columns per lane (lane_width
 // columns: 16-byte accesses, 8-byte for bfloat16, where the row is wide
 // enough); a 256-thread block covers RPB rows.
-template <typename T, int C>
+// WIDE: 16-byte lanes for every type (8 bfloat16 columns per lane), for
+// products with one value set, where a lane may span two subsystems.
+template <typename T, int C, bool WIDE = false>
 struct Lanes {
-    static constexpr int VW = lane_width((int)sizeof(T)) < C ? lane_width((int)sizeof(T)) : C;
+    static constexpr int LW = WIDE ? 16 / (int)sizeof(T) : lane_width((int)sizeof(T));
+    static constexpr int VW = LW < C ? LW : C;
     static constexpr int LPR = C / VW;
     static constexpr int RPB = kBlock / LPR;
 };

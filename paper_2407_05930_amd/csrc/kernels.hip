@@ -27,13 +27,14 @@ namespace msp {
 // pass applies a different operator of one sparsity pattern to every
 // subsystem's columns.
 // T is the storage type of the multivectors; arithmetic is in acc_t<T>.
-template <typename T, typename TV, int C, bool SETS>
+// WIDE: 16-byte lanes (Lanes<T, C, true>; matrices with one value set).
+template <typename T, typename TV, int C, bool SETS, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ ci,
                                                  const TV* __restrict__ va, const T* __restrict__ X,
                                                  T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta,
                                                  OuterDiag sigma, int S, int m, int vs) {
-    using L = Lanes<T, C>;
+    using L = Lanes<T, C, WIDE>;
     using TC = acc_t<T>;
     constexpr int VW = L::VW;
     const int64_t row = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * L::RPB + threadIdx.x / L::LPR;
@@ -756,22 +757,33 @@ constexpr bool sets_ok() {
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
                        const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m,
-                       int vs) {
+                       int vs, bool wide) {
     if (n <= 0) return hipSuccess;
     if (vs > 1 && (!sets_ok<TV>() || m < 1)) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         using L = Lanes<T, CC>;
         if constexpr (sets_ok<TV>()) {
             if (vs > 1) {
-                hipLaunchKernelGGL((k_spmm<T, TV, CC, true>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp,
-                                   ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs);
+                hipLaunchKernelGGL((k_spmm<T, TV, CC, true, false>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st,
+                                   n, rp, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs);
                 break;
             }
         }
-        hipLaunchKernelGGL((k_spmm<T, TV, CC, false>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp, ci, va,
-                           X, Y, Z, alpha, beta, sigma, S, m, 1);
+        using LW = Lanes<T, CC, true>;
+        if (wide && LW::VW != L::VW) {
+            hipLaunchKernelGGL((k_spmm<T, TV, CC, false, true>), dim3(blocks_for(n, LW::RPB)), dim3(kBlock), 0, st, n,
+                               rp, ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1);
+            break;
+        }
+        hipLaunchKernelGGL((k_spmm<T, TV, CC, false, false>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp,
+                           ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1);
     });
     return hipGetLastError();
+}
+
+bool spmm_has_wide(int C, int elem_bytes) {
+    const int vw = lane_width(elem_bytes), ww = 16 / elem_bytes;
+    return (ww < C ? ww : C) != (vw < C ? vw : C);
 }
 
 template <typename T, typename TV, int CC, int G>
@@ -818,7 +830,8 @@ hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int3
 
 #define MSP_SPMM_INST(T, TV)                                                                                         \
     template hipError_t launch_spmm<T, TV>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const TV*,     \
-                                           const T*, T*, const T*, acc_t<T>, acc_t<T>, OuterDiag, int, int, int);     \
+                                           const T*, T*, const T*, acc_t<T>, acc_t<T>, OuterDiag, int, int, int,      \
+                                           bool);                                                                      \
     template hipError_t launch_spmm_split<T, TV>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,     \
                                                  const TV*, const T*, T*, const T*, acc_t<T>, acc_t<T>, int, int,   \
                                                  OuterDiag, int);

@@ -45,10 +45,13 @@ constexpr int lane_width(int elem_bytes) { return (elem_bytes == 2 ? 8 : 16) / e
 // (TV = T, or Bf16 with T = float) and multivectors of type T.  vs > 1: the
 // matrix holds vs interleaved value sets (entry k of set a at va[k*vs + a],
 // FP64/FP32 values only) and column c uses set min(c / m, vs - 1).
+// wide (one value set only): 16-byte lanes where they differ from the default
+// (bfloat16: 8 columns per lane), see spmm_has_wide.
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
                        const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m,
-                       int vs);
+                       int vs, bool wide = false);
+bool spmm_has_wide(int C, int elem_bytes);
 // Same product for long rows: G lane groups share each row (G a power of two).
 template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
