@@ -276,7 +276,8 @@ def test_amgr_per_subsystem_mixed_reaches_tolerance(prec):
     dict(N=(24, 20, 16), s=2, m=3, k=4),   # 12 columns padded to 16
     dict(N=(20, 20, 20), s=3, m=4, k=8),   # 32 columns, no padding
     dict(N=(24, 24), s=1, m=5, k=0),       # 2D, 10 columns padded to 16
-], ids=["s2_m3_padded", "s3_m4", "2d_s1_m5_padded"])
+    dict(N=(16, 16, 16), s=3, m=8, k=4),   # 64 columns, the widest multivector
+], ids=["s2_m3_padded", "s3_m4", "2d_s1_m5_padded", "s3_m8_max_width"])
 def test_amgr_per_subsystem_bf16_multivectors_match_oracle(shape):
     """Per-subsystem cycle with bfloat16 V-cycle multivectors (the bench's
     mode), with and without padded columns: true relative residual 1e-10
@@ -376,3 +377,17 @@ def test_full_size_jitter_config_properties():
     assert out["mixed_bf16"][1] <= int(1.1 * out["fp64"][1]) + 1
     x64, xb = out["fp64"][0], out["mixed_bf16"][0]
     assert np.linalg.norm(xb - x64) / np.linalg.norm(x64) <= 1e-9
+
+
+def test_more_than_64_columns_is_rejected():
+    """2^s * m > 64 columns: the solve returns MSP_ERR_UNSUPPORTED before any
+    launch, and the context stays usable for a width it supports."""
+    torch = _torch()
+    from paper_2407_05930_amd import MspError, Solver
+    p = make_problem((12, 12, 12), s=3, m=9, seed=3)
+    sv = Solver(p.A, p.img, tol=1e-10, pc="amgr_sub", coarse_max=48)
+    b = torch.from_numpy(p.b).cuda()
+    with pytest.raises(MspError, match="UNSUPPORTED"):
+        sv.solve(b)
+    x = sv.solve(b[:, :8].contiguous()).cpu().numpy()
+    assert np.all(krylov.true_relres(p.A, x, p.b[:, :8]) <= 1.5e-10)
