@@ -284,7 +284,7 @@ def main():
             log(f"timing {pc} {prec}: warmup {args.warmup}, steps {args.steps}")
             t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
             iters = sv.last.iters
-            relres = [float(v) for v in sv.last.relres[: p.b.shape[1]]]
+            relres = [float(v) for v in sv.last.relres_rec[: p.b.shape[1]]]
             xs = x.cpu().numpy()
             true_rr = np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)
             res[prec] = dict(sv=sv, t=t, iters=iters, relres=relres, true_relres=true_rr.tolist(), t_setup=t_setup,

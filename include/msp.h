@@ -123,7 +123,10 @@ typedef struct {
 typedef struct {
     int32_t iters;               /* PCG iterations of the slowest column */
     int32_t status;
-    double relres[64];           /* recursive-residual bound per RHS (m <= 64) */
+    double relres_rec[64];       /* per RHS (m <= 64): the relative residual the stopping test
+                                    saw, sqrt(sum_a ||rhat_a||^2) / ||b_j|| from the recursively
+                                    updated residuals; the true residual ||b - A x|| / ||b|| agrees
+                                    with it to rounding (the library does not form A x) */
     int32_t nlev;
     int64_t rows[32];
     int64_t nnz[32];

@@ -12,7 +12,7 @@ Modules
   symmetry   Sec. 2: base blocks H_j, the change of basis Q_s, the decoupled
              subsystems (eqs. (2.4)-(2.14)) and Alg. 1
   amg        Sec. 3.2: strength, Alg. 2 populated coarsening, the reduction
-             prolongation (eq. (3.15)), the block-FSAI top smoother
+             prolongation (eq. (3.13)), the block-FSAI top smoother
              (eq. (3.14)), the reduced operator (eq. (3.15)), standard AMG
              levels below it and the V-cycle of Alg. 3
   krylov     per-column PCG for the decoupled systems of Alg. 1

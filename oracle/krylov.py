@@ -37,17 +37,22 @@ def pcg_columns(apply_A: Callable, apply_M: Callable, B: np.ndarray, thresh: np.
 
     apply_A(X), apply_M(R) act column-wise on (n, k) blocks.  Column c stops
     once ||r_c|| <= thresh[c]; columns already below their threshold at
-    the start (including zero columns) do no iteration.  ``flexible`` selects
-    beta = <r_new, z_new - z_old>/<r_old, z_old> instead of <r_new,z_new>/<r_old,z_old>.
-    Breakdown (p^T A p <= 0 or not finite in an active column) raises."""
+    the start (including zero columns) do no iteration.  Standard beta is
+    <r_new, z_new> / <r_old, z_old>.  ``flexible`` selects the flexible CG of
+    Notay (SIAM J. Sci. Comput. 22, 2000) with one kept direction:
+    beta = -<z_new, A p> / <p, A p>, which makes every new direction
+    A-orthogonal to the previous one whatever the preconditioner does (a
+    preconditioner that changes between iterations, such as a V-cycle run in
+    reduced precision); for a fixed SPD preconditioner it equals the standard
+    beta in exact arithmetic.  Breakdown (p^T A p <= 0 or not finite in an
+    active column) raises."""
     n, k = B.shape
     X = np.zeros((n, k))
     R = B.copy()
     active = np.linalg.norm(R, axis=0) > thresh
     iters = np.zeros(k, dtype=np.int64)
-    Z = apply_M(R)
-    P = Z.copy()
-    rho = np.einsum("ij,ij->j", R, Z)
+    P = apply_M(R)
+    rho = np.einsum("ij,ij->j", R, P)
     hist = [np.linalg.norm(R, axis=0)]
     it = 0
     while active.any() and it < maxit:
@@ -69,12 +74,10 @@ def pcg_columns(apply_A: Callable, apply_M: Callable, B: np.ndarray, thresh: np.
         Znew = apply_M(R)
         rho_new = np.einsum("ij,ij->j", R, Znew)
         if flexible:
-            num = np.einsum("ij,ij->j", R, Znew - Z)
+            beta = np.where(active, -np.einsum("ij,ij->j", Znew, Q) / np.where(active, pq, 1.0), 0.0)
         else:
-            num = rho_new
-        beta = np.where(active, num / np.where(active, rho, 1.0), 0.0)
+            beta = np.where(active, rho_new / np.where(active, rho, 1.0), 0.0)
         P = np.where(active[None, :], Znew + beta * P, P)
-        Z = Znew
         rho = np.where(active, rho_new, rho)
     return PCGResult(x=X, iters=iters, converged=~active, history=hist)
 

@@ -52,7 +52,7 @@ class msp_opts(ctypes.Structure):
 
 
 class msp_stats(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres", ctypes.c_double * 64),
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres_rec", ctypes.c_double * 64),
                 ("nlev", ctypes.c_int32), ("rows", ctypes.c_int64 * 32), ("nnz", ctypes.c_int64 * 32),
                 ("op_complexity", ctypes.c_double), ("c_rat", ctypes.c_double), ("avg_nnzr", ctypes.c_double),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double)]

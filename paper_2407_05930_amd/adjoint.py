@@ -15,7 +15,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import _lib
-from ._lib import check, lib
+from ._lib import MSP_NOT_CONVERGED, MspError, check, lib
 from .solver import Solver
 
 
@@ -92,17 +92,30 @@ class DifferentiablePoisson:
         self.solver = None
 
     def solver_for(self, kappa):
+        """The solver for this kappa (rebuilt when kappa changes).  The
+        previous solver is not closed here: an autograd graph recorded with
+        it may still need it for its backward solve, and it is freed when the
+        last reference goes."""
         kap = kappa.detach().cpu().numpy()
         if self._kappa is None or not np.array_equal(kap, self._kappa):
             A = self.op.assemble(kap)
-            if self.solver is not None:
-                self.solver.close()
             self.solver = Solver(A, self.op.img, **self.opts)
             self._kappa = kap.copy()
         return self.solver
 
     def __call__(self, f, kappa):
         return PoissonSolve.apply(f, kappa, self)
+
+
+def _converged_solve(sv, rhs, what):
+    """A solve whose result feeds a gradient: an unconverged one is an error."""
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", RuntimeWarning)
+        x = sv.solve(rhs)
+    if sv.status != MSP_NOT_CONVERGED:
+        return x
+    raise MspError(MSP_NOT_CONVERGED, f"{what} solve did not reach the tolerance in {sv.last.iters} iterations")
 
 
 def _torch_function():
@@ -115,7 +128,7 @@ def _torch_function():
         @staticmethod
         def forward(ctx, f, kappa, dp):
             sv = dp.solver_for(kappa)
-            p = sv.solve(f.contiguous())
+            p = _converged_solve(sv, f.contiguous(), "forward")
             ctx.dp = dp
             ctx.sv = sv
             ctx.save_for_backward(p, kappa)
@@ -124,7 +137,7 @@ def _torch_function():
         @staticmethod
         def backward(ctx, g):
             p, kappa = ctx.saved_tensors
-            lam = ctx.sv.solve(g.contiguous())
+            lam = _converged_solve(ctx.sv, g.contiguous(), "adjoint")
             gk = ctx.dp.op.kappa_grad(kappa, lam, p) if ctx.needs_input_grad[1] else None
             return lam, gk, None
 

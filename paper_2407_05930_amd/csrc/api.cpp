@@ -84,7 +84,7 @@ struct Work {
     double* h_scal = nullptr;
 };
 
-enum { SC_RR = 0, SC_RZ, SC_PQ, SC_RHO, SC_ALPHA, SC_BETA, SC_THR, SC_RNORM, SC_BN2, SC_RZOLD, SC_COUNT };
+enum { SC_RR = 0, SC_RZ, SC_PQ, SC_RHO, SC_ALPHA, SC_BETA, SC_THR, SC_RNORM, SC_BN2, SC_COUNT };
 
 // Launch classes for the optional per-kernel timers (msp_set_timing).
 enum {
@@ -407,10 +407,23 @@ static double dense_sets_bytes(const msp_ctx* c, int C) {
     return eb * S * c->nL * dense_sets_ld(c->nL, (int)eb) + 2.0 * sizeof(T) * c->nL * C;
 }
 
+// Integer value of an environment variable, or -1 when unset or not a number.
+static int env_int(const char* name) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return -1;
+    char* end = nullptr;
+    const long x = std::strtol(v, &end, 10);
+    return (end && *end == 0 && x >= 0 && x < (1 << 20)) ? static_cast<int>(x) : -1;
+}
+
 // Autotuner: for every V-cycle matrix, time the candidate lane-group splits
 // (1, 2, 4, ... up to the block's capacity and about half the mean row
 // length) on this column count and keep the fastest.  Runs once per context
 // and column count, on scratch multivectors cleared first.
+// Fixed variants instead of timings (every variant computes the same
+// product; tests use these to cover each one): MSP_SPMM_SPLIT=g (a power of
+// two; clamped to what a block holds), MSP_SPMM_WIDE=1 (16-byte lanes where a
+// matrix has them), MSP_DENSE_ROWS=R (1, 2, 4 or 8 rows per wavefront).
 template <typename T>
 static void autotune_level_splits(msp_ctx* c, Work& w) {
     hipStream_t st = nullptr;
@@ -421,6 +434,23 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
     const int mt = std::max(1, C / S);   // columns per subsystem assumed for matrices with value sets
     const char* logv = std::getenv("MSP_AUTOTUNE_LOG");   // set (non-empty, not "0"): timings to stderr
     const bool log = logv && *logv && std::strcmp(logv, "0") != 0;
+    const int force_split = env_int("MSP_SPMM_SPLIT");
+    const int force_wide = env_int("MSP_SPMM_WIDE");
+    const int force_rows = env_int("MSP_DENSE_ROWS");
+    if (force_split > 0 || force_wide >= 0 || force_rows > 0) {
+        int g = 1;
+        while (force_split > 0 && g * 2 <= force_split && g * 2 * lpr <= 256) g *= 2;
+        for (auto& L : c->dl)
+            for (DevCsr* M : {&L.A, &L.M, &L.R, &L.P, &L.G, &L.GT}) {
+                M->tuned[tslot<T>()][log2i(C)] = g;
+                M->wide[tslot<T>()][log2i(C)] =
+                    g == 1 && force_wide == 1 && M->vs == 1 && spmm_has_wide(C, static_cast<int>(sizeof(T)));
+            }
+        int R = 1;
+        while (force_rows > 0 && R * 2 <= force_rows && R * 2 <= 8) R *= 2;
+        w.dense_rows = force_rows > 0 ? R : 8;
+        return;
+    }
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
@@ -807,7 +837,7 @@ struct SolvePlan {
     int64_t nb, n;
     bool flexible, lrc_amg;
     bool x_pending = false;   // an x += alpha p step not yet applied
-    double *rr, *rz, *pq, *rho, *alpha, *beta, *thr, *rnorm, *bn2, *rzold;
+    double *rr, *rz, *pq, *rho, *alpha, *beta, *thr, *rnorm, *bn2;
     int *active, *iters, *flags;
 
     SolvePlan(msp_ctx* c_, int m_, hipStream_t st_) : c(c_), st(st_), m(m_) {
@@ -825,7 +855,7 @@ struct SolvePlan {
         double* sc = w->scal;
         rr = sc + SC_RR * 64; rz = sc + SC_RZ * 64; pq = sc + SC_PQ * 64; rho = sc + SC_RHO * 64;
         alpha = sc + SC_ALPHA * 64; beta = sc + SC_BETA * 64; thr = sc + SC_THR * 64;
-        rnorm = sc + SC_RNORM * 64; bn2 = sc + SC_BN2 * 64; rzold = sc + SC_RZOLD * 64;
+        rnorm = sc + SC_RNORM * 64; bn2 = sc + SC_BN2 * 64;
         active = w->iscal;
         iters = w->iscal + 64;
         flags = w->iscal + 128;
@@ -840,21 +870,21 @@ struct SolvePlan {
             return;
         }
         HIPCHECK(op_dot_grid(C, nb, &nbo));
-        if (c->U16) HIPCHECK(update_dots_grid<Bf16>(C, flexible, kl, nb, &nbu));
-        else if (c->U32 || !c->d_U) HIPCHECK(update_dots_grid<float>(C, flexible, kl, nb, &nbu));
-        else HIPCHECK(update_dots_grid<double>(C, flexible, kl, nb, &nbu));
+        if (c->U16) HIPCHECK(update_dots_grid<Bf16>(C, kl, nb, &nbu));
+        else if (c->U32 || !c->d_U) HIPCHECK(update_dots_grid<float>(C, kl, nb, &nbu));
+        else HIPCHECK(update_dots_grid<double>(C, kl, nb, &nbu));
         const bool lz = lrc_amg && kl > 0;
         const bool s16 = amg(c) && c->o.precision == MSP_MIXED_BF16, s32 = !s16 && amg(c) && mixed(c);
         if (s16) {
-            if (c->U16) HIPCHECK((zfinish_grid<Bf16, Bf16>(C, lz, nb, &nbz)));
-            else if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<Bf16, float>(C, lz, nb, &nbz)));
-            else HIPCHECK((zfinish_grid<Bf16, double>(C, lz, nb, &nbz)));
+            if (c->U16) HIPCHECK((zfinish_grid<Bf16, Bf16>(C, lz, flexible, nb, &nbz)));
+            else if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<Bf16, float>(C, lz, flexible, nb, &nbz)));
+            else HIPCHECK((zfinish_grid<Bf16, double>(C, lz, flexible, nb, &nbz)));
         } else if (s32) {
-            if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<float, float>(C, lz, nb, &nbz)));
-            else HIPCHECK((zfinish_grid<float, double>(C, lz, nb, &nbz)));
+            if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<float, float>(C, lz, flexible, nb, &nbz)));
+            else HIPCHECK((zfinish_grid<float, double>(C, lz, flexible, nb, &nbz)));
         } else {
-            if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<double, float>(C, lz, nb, &nbz)));
-            else HIPCHECK((zfinish_grid<double, double>(C, lz, nb, &nbz)));
+            if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<double, float>(C, lz, flexible, nb, &nbz)));
+            else HIPCHECK((zfinish_grid<double, double>(C, lz, flexible, nb, &nbz)));
         }
         w->grid_op = nbo;
         w->grid_upd = nbu;
@@ -876,24 +906,24 @@ struct SolvePlan {
     void update_dots(bool upd) {
         Work& W = *w;
         const double wu = ubytes();
-        const double bytes = (upd ? 3.0 : 1.0) * vb() + (flexible && upd ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0) +
-                             (y32() ? 4.0 * nb * C : 0.0) + (y16() ? 2.0 * nb * C : 0.0);
+        const double bytes = (upd ? 3.0 : 1.0) * vb() + (kl ? nb * S * kl * wu : 0.0) + (y32() ? 4.0 * nb * C : 0.0) +
+                             (y16() ? 2.0 * nb * C : 0.0);
         timed(c, KD_UPDATE, bytes, st, [&] {
             if (c->U16)
-                HIPCHECK(launch_update_dots<Bf16>(st, C, nbu, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
-                                                  static_cast<const Bf16*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
-                                                  y32(), y16()));
+                HIPCHECK(launch_update_dots<Bf16>(st, C, nbu, upd, kl, nb, W.r, W.q, alpha,
+                                                  static_cast<const Bf16*>(c->d_U), S, m, W.pp1, W.plrc, y32(),
+                                                  y16()));
             else if (c->U32 || !c->d_U)
-                HIPCHECK(launch_update_dots<float>(st, C, nbu, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
-                                                   static_cast<const float*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
-                                                   y32(), y16()));
+                HIPCHECK(launch_update_dots<float>(st, C, nbu, upd, kl, nb, W.r, W.q, alpha,
+                                                   static_cast<const float*>(c->d_U), S, m, W.pp1, W.plrc, y32(),
+                                                   y16()));
             else
-                HIPCHECK(launch_update_dots<double>(st, C, nbu, upd, flexible && upd, kl, nb, W.r, W.q, alpha, W.z,
-                                                    static_cast<const double*>(c->d_U), S, m, W.pp1, W.pp2, W.plrc,
-                                                    y32(), y16()));
+                HIPCHECK(launch_update_dots<double>(st, C, nbu, upd, kl, nb, W.r, W.q, alpha,
+                                                    static_cast<const double*>(c->d_U), S, m, W.pp1, W.plrc, y32(),
+                                                    y16()));
         });
-        HIPCHECK(launch_fin_check(st, C, nbu, !upd, flexible && upd, O, m, W.pp1, W.pp2, W.plrc, thr, c->d_lrc_coef,
-                                  active, iters, flags, rnorm, rzold, c->d_lrc_W));
+        HIPCHECK(launch_fin_check(st, C, nbu, !upd, O, m, W.pp1, W.plrc, thr, c->d_lrc_coef, active, iters, flags,
+                                  rnorm, c->d_lrc_W));
     }
 
     // z = M^{-1} r (+ low-rank corrections), <r,z>, beta and rho
@@ -916,41 +946,44 @@ struct SolvePlan {
         }
         const double wu = ubytes();
         double* z2 = init ? W.p : nullptr;   // the first search direction p = z
+        const bool fq = flexible && !init;   // <q, z> for the flexible beta
+        const double* qf = fq ? W.q : nullptr;
+        double* pqz = fq ? W.pp2 : nullptr;
         const double bytes = (s16 ? 2.0 : (s32 ? 4.0 : 8.0)) * nb * C + (init ? 3.0 : 2.0) * vb() +
-                             (kl ? nb * S * kl * wu : 0.0);
+                             (fq ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0);
         const void* U = lrc_amg ? c->d_U : nullptr;
         timed(c, KD_CAST, bytes, st, [&] {
             if (s16) {
                 if (c->U16)
                     HIPCHECK((launch_zfinish<Bf16, Bf16>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const Bf16*>(U),
-                                                         c->d_lrc_W, S, kl, m, W.pp1, z2)));
+                                                         c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz)));
                 else if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<Bf16, float>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const float*>(U),
-                                                          c->d_lrc_W, S, kl, m, W.pp1, z2)));
+                                                          c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz)));
                 else
                     HIPCHECK((launch_zfinish<Bf16, double>(st, C, nbz, nb, s16, W.z, W.r,
                                                            static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
-                                                           W.pp1, z2)));
+                                                           W.pp1, z2, qf, pqz)));
             } else if (s32) {
                 if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<float, float>(st, C, nbz, nb, s32, W.z, W.r, static_cast<const float*>(U),
-                                                           c->d_lrc_W, S, kl, m, W.pp1, z2)));
+                                                           c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz)));
                 else
                     HIPCHECK((launch_zfinish<float, double>(st, C, nbz, nb, s32, W.z, W.r,
                                                             static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
-                                                            W.pp1, z2)));
+                                                            W.pp1, z2, qf, pqz)));
             } else {
                 if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<double, float>(st, C, nbz, nb, W.z, W.z, W.r,
                                                             static_cast<const float*>(U), c->d_lrc_W, S, kl, m,
-                                                            W.pp1, z2)));
+                                                            W.pp1, z2, qf, pqz)));
                 else
                     HIPCHECK((launch_zfinish<double, double>(st, C, nbz, nb, W.z, W.z, W.r,
                                                              static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
-                                                             W.pp1, z2)));
+                                                             W.pp1, z2, qf, pqz)));
             }
         });
-        HIPCHECK(launch_fin_beta(st, C, nbz, init, flexible, W.pp1, active, rzold, rho, beta, rz));
+        HIPCHECK(launch_fin_beta(st, C, nbz, init, flexible, W.pp1, W.pp2, active, pq, rho, beta, rz));
     }
 
     void begin(const double* d_b) {
@@ -1042,7 +1075,7 @@ struct SolvePlan {
         msp_stats& R = c->stats;
         R.iters = 0;
         for (int q = 0; q < S * m; ++q) R.iters = std::max(R.iters, W.h_iters[q]);
-        for (int j = 0; j < 64; ++j) R.relres[j] = 0.0;
+        for (int j = 0; j < 64; ++j) R.relres_rec[j] = 0.0;
         for (int j = 0; j < m && j < 64; ++j) {
             double s2 = 0.0;
             for (int a = 0; a < S; ++a) {
@@ -1050,7 +1083,7 @@ struct SolvePlan {
                 s2 += v * v;
             }
             const double bn = std::sqrt(W.h_scal[SC_BN2 * 64 + j]);
-            R.relres[j] = bn > 0 ? std::sqrt(s2) / bn : 0.0;
+            R.relres_rec[j] = bn > 0 ? std::sqrt(s2) / bn : 0.0;
         }
         R.status = status;
         R.t_solve_s = seconds;
@@ -1065,7 +1098,11 @@ static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipSt
     const auto t0 = std::chrono::steady_clock::now();
     P.begin(d_b);
     P.read_flags();
-    int status = P.w->h_flags[0] ? MSP_ERR_BREAKDOWN : MSP_OK;
+    if (P.w->h_flags[0]) {   // before any iteration: the right-hand side itself
+        P.finish(d_x, MSP_ERR_BREAKDOWN, 0.0, out);
+        throw Error(MSP_ERR_BREAKDOWN, "non-finite value in the right-hand side");
+    }
+    int status = MSP_OK;
     int nactive = P.w->h_flags[1];
     int it = 0;
     while (status == MSP_OK && nactive > 0 && it < c->o.maxit) {

@@ -274,7 +274,7 @@ __device__ __forceinline__ double block_sum_partials(int nb, int O, int o, const
     for (int b = threadIdx.x; b < nb; b += kBlock) s += partial[(int64_t)b * O + o];
     sm[threadIdx.x] = s;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
+    for (unsigned w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
         __syncthreads();
     }

@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_colnorm2(int64_t n, int m, const dou
     }
     sm[threadIdx.x] = s;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
+    for (unsigned w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
         __syncthreads();
     }
@@ -624,8 +624,8 @@ __global__ __launch_bounds__(kBlock) void k_lrc_project(int64_t n, int S, int k,
     }
 }
 
-// W[o] = coef[a*k + t] * sum_b partial[b, o]  (fixed order over b)
-__global__ __launch_bounds__(kBlock) void k_lrc_finish(int nb, int O, int k, int m,
+// W[o] = coef[o / m] * sum_b partial[b, o]  (fixed order over b; o = (a*k + t)*m + j)
+__global__ __launch_bounds__(kBlock) void k_lrc_finish(int nb, int O, int m,
                                                        const double* __restrict__ partial,
                                                        const double* __restrict__ coef, double* __restrict__ W) {
     const int o = blockIdx.x * kBlock + threadIdx.x;
@@ -1091,8 +1091,7 @@ hipError_t launch_lrc_apply(hipStream_t st, int64_t n, int S, int k, int m, int 
                             double* Z, const double* coef, double* partial, int nb, double* W) {
     const int O = S * k * m;
     hipLaunchKernelGGL((k_lrc_project<TU>), dim3(nb), dim3(kBlock), 0, st, n, S, k, m, C, U, R, partial);
-    hipLaunchKernelGGL(k_lrc_finish, dim3(blocks_for(O, kBlock)), dim3(kBlock), 0, st, nb, O, k, m, partial, coef,
-                       W);
+    hipLaunchKernelGGL(k_lrc_finish, dim3(blocks_for(O, kBlock)), dim3(kBlock), 0, st, nb, O, m, partial, coef, W);
     hipLaunchKernelGGL((k_lrc_expand<TU>), dim3(blocks_for(n * C, kBlock)), dim3(kBlock), 0, st, n, S, k, m, C, U,
                        W, Z);
     return hipGetLastError();

@@ -87,17 +87,14 @@ __global__ __launch_bounds__(kBlock) void k_fin_alpha(int nb, int C, const doubl
 }
 
 // UPD: r -= alpha q (the matching x += alpha p is applied by the p update,
-// which reads p anyway).  Then per-block partials of <r,r> (partial_rr), of
-// <r,z> with the current z when FLEX (partial_rz), and of the low-rank
-// projections U_a^T r_a when KMAX > 0:
+// which reads p anyway).  Then per-block partials of <r,r> (partial_rr) and
+// of the low-rank projections U_a^T r_a when KMAX > 0:
 // partial_lrc[b, (a*k + t)*m + j] = sum_rows U[i, a*k+t] r[i, a*m+j].
-template <int C, bool UPD, bool FLEX, int KMAX, typename TU>
+template <int C, bool UPD, int KMAX, typename TU>
 __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __restrict__ r,
                                                         const double* __restrict__ q,
-                                                        const double* __restrict__ alpha,
-                                                        const double* __restrict__ z, const TU* __restrict__ U,
+                                                        const double* __restrict__ alpha, const TU* __restrict__ U,
                                                         int S, int k, int m, double* __restrict__ partial_rr,
-                                                        double* __restrict__ partial_rz,
                                                         double* __restrict__ partial_lrc, float* __restrict__ y32,
                                                         Bf16* __restrict__ y16) {
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
@@ -109,12 +106,12 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
     // FP32 when U is bfloat16 (it frees the registers that bound the occupancy);
     // block and grid sums are FP64
     using TA = typename std::conditional<std::is_same<TU, Bf16>::value, float, double>::type;
-    double a_rr[VW], a_rz[VW];
+    double a_rr[VW];
     TA a_l[VW][KA];
     double al[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) {
-        a_rr[e] = a_rz[e] = 0.0;
+        a_rr[e] = 0.0;
         al[e] = UPD ? alpha[lane * VW + e] : 0.0;
 #pragma unroll
         for (int t = 0; t < KA; ++t) a_l[e][t] = TA(0);
@@ -144,11 +141,6 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
         }
 #pragma unroll
         for (int e = 0; e < VW; ++e) a_rr[e] += rv.e[e] * rv.e[e];
-        if (FLEX) {
-            const Pack<double, VW> zv = ld<double, VW>(z + o);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) a_rz[e] += rv.e[e] * zv.e[e];
-        }
         if (KMAX > 0) {
 #pragma unroll
             for (int e = 0; e < VW; ++e) {
@@ -175,7 +167,6 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
         }
     }
     block_column_sums<C, VW>(a_rr, sm, partial_rr + (int64_t)blockIdx.x * C);
-    if (FLEX) block_column_sums<C, VW>(a_rz, sm, partial_rz + (int64_t)blockIdx.x * C);
     if (KMAX > 0) {
         // kUpdTch projections per pass: slm[(tt * kBlock + thread) * VW + e] for t = t0 + tt,
         // then one thread per output (column, t) sums the RPB row slots in a fixed order
@@ -204,15 +195,12 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
 }
 
 // Blocks [0, C): <r,r> -> convergence check (INIT: set the active flags);
-// blocks [C, 2C) when FLEX: <r, z_old>; the next S*k*m blocks when LRC:
-// W[o] = coef[o / m] * U^T r.
-__global__ __launch_bounds__(kBlock) void k_fin_check(int nb, int C, int init, int flex, int O, int m,
+// the next S*k*m blocks when LRC: W[o] = coef[o / m] * U^T r.
+__global__ __launch_bounds__(kBlock) void k_fin_check(int nb, int C, int init, int O, int m,
                                                       const double* __restrict__ partial_rr,
-                                                      const double* __restrict__ partial_rz,
                                                       const double* __restrict__ partial_lrc,
                                                       const double* __restrict__ thr, const double* __restrict__ coef,
-                                                      int* active, int* iters, int* flags, double* rnorm,
-                                                      double* rzold, double* W) {
+                                                      int* active, int* iters, int* flags, double* rnorm, double* W) {
     __shared__ double sm[kBlock];
     int b = blockIdx.x;
     if (b < C) {
@@ -222,6 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_check(int nb, int C, int init, i
             if (init) {
                 rnorm[b] = nr;
                 iters[b] = 0;
+                if (!isfinite(nr) || !(thr[b] >= 0.0)) atomicOr(&flags[0], 1);   // non-finite right-hand side
                 const int a = nr > thr[b] ? 1 : 0;
                 active[b] = a;
                 if (a) atomicAdd(&flags[1], 1);
@@ -236,14 +225,6 @@ __global__ __launch_bounds__(kBlock) void k_fin_check(int nb, int C, int init, i
         return;
     }
     b -= C;
-    if (flex) {
-        if (b < C) {
-            const double s = block_sum_partials(nb, C, b, partial_rz, sm);
-            if (threadIdx.x == 0) rzold[b] = s;
-            return;
-        }
-        b -= C;
-    }
     if (b < O) {
         const double s = block_sum_partials(nb, O, b, partial_lrc, sm);
         if (threadIdx.x == 0) W[b] = coef[b / m] * s;
@@ -251,13 +232,16 @@ __global__ __launch_bounds__(kBlock) void k_fin_check(int nb, int C, int init, i
 }
 
 // z = s (cast to FP64; s may alias z) + sum_t U[i, a*k+t] W[(a*k+t)*m + j]
-// (the expansion of the low-rank correction); partial[b, c] = sum r z.
+// (the expansion of the low-rank correction); partial[b, c] = sum r z and,
+// when FLEX, partial_qz[b, c] = sum q z (q = A p of this iteration: the
+// numerator of the flexible beta).
 // z2 != nullptr: z is also written there (the first search direction).
-template <int C, typename TS, bool LRC, typename TU>
+template <int C, typename TS, bool LRC, typename TU, bool FLEX>
 __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, double* z, const double* __restrict__ r,
                                                     const TU* __restrict__ U, const double* __restrict__ W, int S,
                                                     int k, int m, double* __restrict__ partial,
-                                                    double* __restrict__ z2) {
+                                                    double* __restrict__ z2, const double* __restrict__ q,
+                                                    double* __restrict__ partial_qz) {
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
     __shared__ double sm[kBlock * VW];
     __shared__ double wl[LRC ? 64 * 16 : 1];
@@ -267,9 +251,9 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
         for (int o = threadIdx.x; o < S * k * m; o += kBlock) wl[o] = W[o];
         __syncthreads();
     }
-    double acc[VW];
+    double acc[VW], aqz[VW];
 #pragma unroll
-    for (int e = 0; e < VW; ++e) acc[e] = 0.0;
+    for (int e = 0; e < VW; ++e) acc[e] = aqz[e] = 0.0;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t row = tile * RPB + slot;
         if (row >= n) continue;
@@ -305,31 +289,46 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
         const Pack<double, VW> rv = ld<double, VW>(r + o);
 #pragma unroll
         for (int e = 0; e < VW; ++e) acc[e] += rv.e[e] * zv.e[e];
+        if (FLEX) {
+            const Pack<double, VW> qv = ld<double, VW>(q + o);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) aqz[e] += qv.e[e] * zv.e[e];
+        }
     }
     block_column_sums<C, VW>(acc, sm, partial + (int64_t)blockIdx.x * C);
+    if (FLEX) block_column_sums<C, VW>(aqz, sm, partial_qz + (int64_t)blockIdx.x * C);
 }
 
-// beta (standard: <r,z>/rho; flexible: (<r,z> - <r,z_old>)/rho), rho = <r,z>
-// on active columns.  INIT: rho = <r,z> for every column.
+// beta and rho = <r,z> on active columns; INIT: rho = <r,z> for every
+// column.  Standard beta: <r,z>/rho.  Flexible (Notay's flexible CG with one
+// kept direction): beta = -<z, A p>/<p, A p>, which keeps the new direction
+// A-orthogonal to the last one when the preconditioner varies between
+// iterations (the reduced-precision V-cycle).  Block c < C sums <r,z> and
+// sets rho; when FLEX, block C + c sums <q,z> (q = A p) and sets beta from it
+// and pq alone, so the two blocks of a column share no data.
 __global__ __launch_bounds__(kBlock) void k_fin_beta(int nb, int C, int init, int flex,
-                                                     const double* __restrict__ partial, const int* __restrict__ active,
-                                                     const double* __restrict__ rzold, double* rho, double* beta,
-                                                     double* rz) {
+                                                     const double* __restrict__ partial,
+                                                     const double* __restrict__ partial_qz,
+                                                     const int* __restrict__ active, const double* __restrict__ pq,
+                                                     double* rho, double* beta, double* rz) {
     __shared__ double sm[kBlock];
-    const int c = blockIdx.x;
-    const double s = block_sum_partials(nb, C, c, partial, sm);
-    if (threadIdx.x == 0) {
-        rz[c] = s;
-        if (init) {
-            rho[c] = s;
-            beta[c] = 0.0;
-        } else if (active[c]) {
-            const double num = flex ? s - rzold[c] : s;
-            beta[c] = num / rho[c];
-            rho[c] = s;
-        } else {
-            beta[c] = 0.0;
-        }
+    const bool qz_block = (int)blockIdx.x >= C;
+    const int c = qz_block ? blockIdx.x - C : blockIdx.x;
+    const double s = block_sum_partials(nb, C, c, qz_block ? partial_qz : partial, sm);
+    if (threadIdx.x != 0) return;
+    if (qz_block) {   // flexible beta (non-initial calls only)
+        beta[c] = active[c] ? -s / pq[c] : 0.0;
+        return;
+    }
+    rz[c] = s;
+    if (init) {
+        rho[c] = s;
+        beta[c] = 0.0;
+    } else if (active[c]) {
+        if (!flex) beta[c] = s / rho[c];
+        rho[c] = s;
+    } else if (!flex) {
+        beta[c] = 0.0;
     }
 }
 
@@ -372,40 +371,38 @@ hipError_t op_dot_grid(int C, int64_t n, int* nb) {
 }
 
 template <typename TU>
-hipError_t update_dots_grid(int C, bool flex, int k, int64_t n, int* nb) {
+hipError_t update_dots_grid(int C, int k, int64_t n, int* nb) {
     if (k > 16) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         constexpr size_t lds = sizeof(double) * kUpdTch * kBlock * DL<CC>::VW;
-        if (k > 8)
-            return flex ? resident_grid<CC>(k_update_dots<CC, true, true, 16, TU>, lds, n, nb)
-                        : resident_grid<CC>(k_update_dots<CC, true, false, 16, TU>, lds, n, nb);
-        if (k > 0)
-            return flex ? resident_grid<CC>(k_update_dots<CC, true, true, 8, TU>, lds, n, nb)
-                        : resident_grid<CC>(k_update_dots<CC, true, false, 8, TU>, lds, n, nb);
-        return flex ? resident_grid<CC>(k_update_dots<CC, true, true, 0, TU>, 0, n, nb)
-                    : resident_grid<CC>(k_update_dots<CC, true, false, 0, TU>, 0, n, nb);
+        if (k > 8) return resident_grid<CC>(k_update_dots<CC, true, 16, TU>, lds, n, nb);
+        if (k > 0) return resident_grid<CC>(k_update_dots<CC, true, 8, TU>, lds, n, nb);
+        return resident_grid<CC>(k_update_dots<CC, true, 0, TU>, 0, n, nb);
     });
     return hipErrorInvalidValue;
 }
-template hipError_t update_dots_grid<float>(int, bool, int, int64_t, int*);
-template hipError_t update_dots_grid<double>(int, bool, int, int64_t, int*);
-template hipError_t update_dots_grid<Bf16>(int, bool, int, int64_t, int*);
+template hipError_t update_dots_grid<float>(int, int, int64_t, int*);
+template hipError_t update_dots_grid<double>(int, int, int64_t, int*);
+template hipError_t update_dots_grid<Bf16>(int, int, int64_t, int*);
 
 template <typename TS, typename TU>
-hipError_t zfinish_grid(int C, bool lrc, int64_t n, int* nb) {
+hipError_t zfinish_grid(int C, bool lrc, bool flex, int64_t n, int* nb) {
     MSP_DISPATCH_C(C, {
-        return lrc ? resident_grid<CC>(k_zfinish<CC, TS, true, TU>, 0, n, nb)
-                   : resident_grid<CC>(k_zfinish<CC, TS, false, TU>, 0, n, nb);
+        if (flex)
+            return lrc ? resident_grid<CC>(k_zfinish<CC, TS, true, TU, true>, 0, n, nb)
+                       : resident_grid<CC>(k_zfinish<CC, TS, false, TU, true>, 0, n, nb);
+        return lrc ? resident_grid<CC>(k_zfinish<CC, TS, true, TU, false>, 0, n, nb)
+                   : resident_grid<CC>(k_zfinish<CC, TS, false, TU, false>, 0, n, nb);
     });
     return hipErrorInvalidValue;
 }
-template hipError_t zfinish_grid<float, float>(int, bool, int64_t, int*);
-template hipError_t zfinish_grid<double, double>(int, bool, int64_t, int*);
-template hipError_t zfinish_grid<double, float>(int, bool, int64_t, int*);
-template hipError_t zfinish_grid<float, double>(int, bool, int64_t, int*);
-template hipError_t zfinish_grid<Bf16, float>(int, bool, int64_t, int*);
-template hipError_t zfinish_grid<Bf16, double>(int, bool, int64_t, int*);
-template hipError_t zfinish_grid<Bf16, Bf16>(int, bool, int64_t, int*);
+template hipError_t zfinish_grid<float, float>(int, bool, bool, int64_t, int*);
+template hipError_t zfinish_grid<double, double>(int, bool, bool, int64_t, int*);
+template hipError_t zfinish_grid<double, float>(int, bool, bool, int64_t, int*);
+template hipError_t zfinish_grid<float, double>(int, bool, bool, int64_t, int*);
+template hipError_t zfinish_grid<Bf16, float>(int, bool, bool, int64_t, int*);
+template hipError_t zfinish_grid<Bf16, double>(int, bool, bool, int64_t, int*);
+template hipError_t zfinish_grid<Bf16, Bf16>(int, bool, bool, int64_t, int*);
 
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
                          const double* va, OuterDiag sigma, int S, int m, const double* p, double* q,
@@ -422,73 +419,79 @@ hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial
     return hipGetLastError();
 }
 
-template <int CC, bool UPD, bool FLEX, int KMAX, typename TU>
+template <int CC, bool UPD, int KMAX, typename TU>
 static void upd_launch(hipStream_t st, int nb, int64_t n, double* r, const double* q, const double* alpha,
-                       const double* z, const TU* U, int S, int k, int m, double* prr, double* prz, double* plrc,
-                       float* y32, Bf16* y16) {
+                       const TU* U, int S, int k, int m, double* prr, double* plrc, float* y32, Bf16* y16) {
     constexpr int VW = DL<CC>::VW;
     const size_t lds = KMAX > 0 ? sizeof(double) * kUpdTch * kBlock * VW : 0;   // projection partials per pass
-    hipLaunchKernelGGL((k_update_dots<CC, UPD, FLEX, KMAX, TU>), dim3(nb), dim3(kBlock), lds, st, n, r, q, alpha, z,
-                       U, S, k, m, prr, prz, plrc, y32, y16);
+    hipLaunchKernelGGL((k_update_dots<CC, UPD, KMAX, TU>), dim3(nb), dim3(kBlock), lds, st, n, r, q, alpha, U, S, k,
+                       m, prr, plrc, y32, y16);
 }
 
 template <typename TU>
-hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* r,
-                              const double* q, const double* alpha, const double* z, const TU* U, int S, int m,
-                              double* prr, double* prz, double* plrc, float* y32, Bf16* y16) {
+hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, int k, int64_t n, double* r, const double* q,
+                              const double* alpha, const TU* U, int S, int m, double* prr, double* plrc, float* y32,
+                              Bf16* y16) {
     if (k > 16) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         if (k > 8) {
-            if (upd && flex) upd_launch<CC, true, true, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
-            else if (upd) upd_launch<CC, true, false, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
-            else upd_launch<CC, false, false, 16, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
+            if (upd) upd_launch<CC, true, 16, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
+            else upd_launch<CC, false, 16, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
         } else if (k > 0) {
-            if (upd && flex) upd_launch<CC, true, true, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
-            else if (upd) upd_launch<CC, true, false, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
-            else upd_launch<CC, false, false, 8, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
+            if (upd) upd_launch<CC, true, 8, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
+            else upd_launch<CC, false, 8, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
         } else {
-            if (upd && flex) upd_launch<CC, true, true, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
-            else if (upd) upd_launch<CC, true, false, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
-            else upd_launch<CC, false, false, 0, TU>(st, nb, n, r, q, alpha, z, U, S, k, m, prr, prz, plrc, y32, y16);
+            if (upd) upd_launch<CC, true, 0, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
+            else upd_launch<CC, false, 0, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
         }
     });
     return hipGetLastError();
 }
-template hipError_t launch_update_dots<float>(hipStream_t, int, int, bool, bool, int, int64_t, double*,
-                                              const double*, const double*, const double*, const float*, int, int,
-                                              double*, double*, double*, float*, Bf16*);
-template hipError_t launch_update_dots<double>(hipStream_t, int, int, bool, bool, int, int64_t, double*,
-                                               const double*, const double*, const double*, const double*, int, int,
-                                               double*, double*, double*, float*, Bf16*);
-template hipError_t launch_update_dots<Bf16>(hipStream_t, int, int, bool, bool, int, int64_t, double*,
-                                             const double*, const double*, const double*, const Bf16*, int, int,
-                                             double*, double*, double*, float*, Bf16*);
+template hipError_t launch_update_dots<float>(hipStream_t, int, int, bool, int, int64_t, double*, const double*,
+                                              const double*, const float*, int, int, double*, double*, float*,
+                                              Bf16*);
+template hipError_t launch_update_dots<double>(hipStream_t, int, int, bool, int, int64_t, double*, const double*,
+                                               const double*, const double*, int, int, double*, double*, float*,
+                                               Bf16*);
+template hipError_t launch_update_dots<Bf16>(hipStream_t, int, int, bool, int, int64_t, double*, const double*,
+                                             const double*, const Bf16*, int, int, double*, double*, float*, Bf16*);
 
-hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
-                            const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
-                            int* iters, int* flags, double* rnorm, double* rzold, double* W) {
-    const unsigned blocks = (unsigned)(C + (flex ? C : 0) + O);
-    hipLaunchKernelGGL(k_fin_check, dim3(blocks), dim3(kBlock), 0, st, nb, C, init ? 1 : 0, flex ? 1 : 0, O, m, prr,
-                       prz, plrc, thr, coef, active, iters, flags, rnorm, rzold, W);
+hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, int O, int m, const double* prr,
+                            const double* plrc, const double* thr, const double* coef, int* active, int* iters,
+                            int* flags, double* rnorm, double* W) {
+    const unsigned blocks = (unsigned)(C + O);
+    hipLaunchKernelGGL(k_fin_check, dim3(blocks), dim3(kBlock), 0, st, nb, C, init ? 1 : 0, O, m, prr, plrc, thr,
+                       coef, active, iters, flags, rnorm, W);
     return hipGetLastError();
+}
+
+template <int CC, typename TS, bool LRC, typename TU>
+static void zfinish_launch(hipStream_t st, int nb, int64_t n, const TS* s, double* z, const double* r, const TU* U,
+                           const double* W, int S, int k, int m, double* partial, double* z2, const double* q,
+                           double* partial_qz) {
+    if (q)
+        hipLaunchKernelGGL((k_zfinish<CC, TS, LRC, TU, true>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k,
+                           m, partial, z2, q, partial_qz);
+    else
+        hipLaunchKernelGGL((k_zfinish<CC, TS, LRC, TU, false>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k,
+                           m, partial, z2, q, partial_qz);
 }
 
 template <typename TS, typename TU>
 hipError_t launch_zfinish(hipStream_t st, int C, int nb, int64_t n, const TS* s, double* z, const double* r,
-                          const TU* U, const double* W, int S, int k, int m, double* partial, double* z2) {
+                          const TU* U, const double* W, int S, int k, int m, double* partial, double* z2,
+                          const double* q, double* partial_qz) {
+    if (q && !partial_qz) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
-        if (U && k > 0)
-            hipLaunchKernelGGL((k_zfinish<CC, TS, true, TU>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k, m,
-                               partial, z2);
-        else
-            hipLaunchKernelGGL((k_zfinish<CC, TS, false, TU>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k,
-                               m, partial, z2);
+        if (U && k > 0) zfinish_launch<CC, TS, true, TU>(st, nb, n, s, z, r, U, W, S, k, m, partial, z2, q, partial_qz);
+        else zfinish_launch<CC, TS, false, TU>(st, nb, n, s, z, r, U, W, S, k, m, partial, z2, q, partial_qz);
     });
     return hipGetLastError();
 }
 #define MSP_ZFINISH_INST(TS, TU)                                                                                  \
     template hipError_t launch_zfinish<TS, TU>(hipStream_t, int, int, int64_t, const TS*, double*, const double*,    \
-                                               const TU*, const double*, int, int, int, double*, double*);
+                                               const TU*, const double*, int, int, int, double*, double*,           \
+                                               const double*, double*);
 MSP_ZFINISH_INST(float, float)
 MSP_ZFINISH_INST(double, double)
 MSP_ZFINISH_INST(double, float)
@@ -498,9 +501,12 @@ MSP_ZFINISH_INST(Bf16, double)
 MSP_ZFINISH_INST(Bf16, Bf16)
 
 hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
-                           const int* active, const double* rzold, double* rho, double* beta, double* rz) {
-    hipLaunchKernelGGL(k_fin_beta, dim3(C), dim3(kBlock), 0, st, nb, C, init ? 1 : 0, flex ? 1 : 0, partial, active,
-                       rzold, rho, beta, rz);
+                           const double* partial_qz, const int* active, const double* pq, double* rho, double* beta,
+                           double* rz) {
+    const bool fq = flex && !init;
+    if (fq && (!partial_qz || !pq)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fin_beta, dim3(fq ? 2 * C : C), dim3(kBlock), 0, st, nb, C, init ? 1 : 0, fq ? 1 : 0, partial,
+                       partial_qz, active, pq, rho, beta, rz);
     return hipGetLastError();
 }
 

@@ -18,9 +18,9 @@ constexpr int kPcgMaxBlocks = 2048;   // largest grid of the dot-producing kerne
 // initial, non-updating one uses fewer registers and fits the same grid).
 hipError_t op_dot_grid(int C, int64_t n, int* nb);
 template <typename TU>
-hipError_t update_dots_grid(int C, bool flex, int k, int64_t n, int* nb);
+hipError_t update_dots_grid(int C, int k, int64_t n, int* nb);
 template <typename TS, typename TU>
-hipError_t zfinish_grid(int C, bool lrc, int64_t n, int* nb);
+hipError_t zfinish_grid(int C, bool lrc, bool flex, int64_t n, int* nb);
 
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
                          const double* va, OuterDiag sigma, int S, int m, const double* p, double* q,
@@ -29,17 +29,21 @@ hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial
                             const double* rho, double* alpha, double* pq, int* flags);
 // upd: r -= alpha q (x is updated by launch_pcg_pupdate, or by the back transform after the last iteration)
 template <typename TU>
-hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, bool flex, int k, int64_t n, double* r,
-                              const double* q, const double* alpha, const double* z, const TU* U, int S, int m,
-                              double* prr, double* prz, double* plrc, float* y32, Bf16* y16);
-hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, bool flex, int O, int m, const double* prr,
-                            const double* prz, const double* plrc, const double* thr, const double* coef, int* active,
-                            int* iters, int* flags, double* rnorm, double* rzold, double* W);
-// z2 != nullptr: z also written there (the first search direction p = z)
+hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, int k, int64_t n, double* r, const double* q,
+                              const double* alpha, const TU* U, int S, int m, double* prr, double* plrc, float* y32,
+                              Bf16* y16);
+hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, int O, int m, const double* prr,
+                            const double* plrc, const double* thr, const double* coef, int* active, int* iters,
+                            int* flags, double* rnorm, double* W);
+// z2 != nullptr: z also written there (the first search direction p = z).
+// q != nullptr (flexible beta): partial_qz also receives the partials of <q, z>.
 template <typename TS, typename TU>
 hipError_t launch_zfinish(hipStream_t st, int C, int nb, int64_t n, const TS* s, double* z, const double* r,
-                          const TU* U, const double* W, int S, int k, int m, double* partial, double* z2 = nullptr);
+                          const TU* U, const double* W, int S, int k, int m, double* partial, double* z2 = nullptr,
+                          const double* q = nullptr, double* partial_qz = nullptr);
+// flex (non-initial calls): beta = -<q,z>/<p,q> from partial_qz and pq
 hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
-                           const int* active, const double* rzold, double* rho, double* beta, double* rz);
+                           const double* partial_qz, const int* active, const double* pq, double* rho, double* beta,
+                           double* rz);
 
 }  // namespace msp

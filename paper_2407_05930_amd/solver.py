@@ -4,6 +4,7 @@ library's HIP kernels.  Device arrays are torch tensors."""
 from __future__ import annotations
 
 import ctypes
+import warnings
 from typing import Optional
 
 import numpy as np
@@ -35,6 +36,12 @@ def make_opts(**kw) -> _lib.msp_opts:
             raise TypeError(f"unknown option {key}")
         setattr(o, key, val)
     return o
+
+
+def _warn_not_converged(rc, what):
+    if rc == _lib.MSP_NOT_CONVERGED:
+        warnings.warn(f"{what}: maximum iteration count reached before the tolerance (MSP_NOT_CONVERGED); "
+                      "the result is the last iterate", RuntimeWarning, stacklevel=3)
 
 
 class Solver:
@@ -84,6 +91,7 @@ class Solver:
                                         ctypes.c_void_p(xt.data_ptr()), ctypes.c_void_p(st.cuda_stream),
                                         ctypes.byref(self.last)))
         self.status = rc
+        _warn_not_converged(rc, "Solver.solve")
         x = xt.t()
         return x.reshape(-1) if vec else x.contiguous()
 
@@ -96,6 +104,7 @@ class Solver:
         rc = check(lib.msp_solve(self._ctx, m, bt.ctypes.data_as(ctypes.c_void_p),
                                  xt.ctypes.data_as(ctypes.c_void_p), ctypes.byref(self.last)))
         self.status = rc
+        _warn_not_converged(rc, "Solver.solve_host")
         return xt.T.reshape(-1) if vec else np.ascontiguousarray(xt.T)
 
     # ------------------------------------------------------------------ introspection
@@ -269,6 +278,7 @@ class BatchSolver:
             px[i] = xt.data_ptr()
         st = stream if stream is not None else torch.cuda.current_stream(bs[0].device)
         self.status = check(lib.msp_batch_solve(self._h, ms, pb, px, ctypes.c_void_p(st.cuda_stream), self.stats))
+        _warn_not_converged(self.status, "BatchSolver.solve")
         return [x.t().reshape(-1) if vec else x.t().contiguous() for x, vec in zip(xts, shapes)]
 
     def close(self):

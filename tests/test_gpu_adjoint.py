@@ -64,3 +64,40 @@ def test_adjoint_gradient_central_difference_on_gpu():
         km[i] -= eps
         fd = (loss_of(kp) - loss_of(km)) / (2 * eps)
         assert abs(fd - g[i]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(g).max())
+
+
+def test_two_forwards_with_different_kappa_then_one_backward():
+    """A loss summed over two kappa samples: the first graph's backward still
+    uses the solver of its own kappa after the second forward built another
+    one; each gradient equals the oracle's for its kappa."""
+    torch = _torch()
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    pr = make_problem((16, 16, 16), s=3, m=1, seed=14, kappa="lognormal", with_target=True)
+    k2 = pr.kappa_base * np.exp(0.3 * np.random.default_rng(1).standard_normal(pr.n_b))
+    pstar = pr.p_target[:, None]
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-13, coarse_max=48)
+    f = torch.from_numpy(pr.b).cuda().requires_grad_(True)
+    ka = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
+    kb = torch.from_numpy(k2).cuda().requires_grad_(True)
+    pst = torch.from_numpy(pstar).cuda()
+    loss = 0.5 * ((dp(f, ka) - pst) ** 2).sum() + 0.5 * ((dp(f, kb) - pst) ** 2).sum()
+    loss.backward()
+    La, lam_a, ga, _ = adjoint.loss_and_gradients(pr.faces, pr.img, pr.kappa_base, pr.b, pstar)
+    Lb, lam_b, gb, _ = adjoint.loss_and_gradients(pr.faces, pr.img, k2, pr.b, pstar)
+    assert abs(loss.item() - (La + Lb)) <= 1e-9 * abs(La + Lb)
+    assert np.linalg.norm(ka.grad.cpu().numpy() - ga) <= 1e-9 * np.linalg.norm(ga)
+    assert np.linalg.norm(kb.grad.cpu().numpy() - gb) <= 1e-9 * np.linalg.norm(gb)
+    gf = lam_a + lam_b
+    assert np.linalg.norm(f.grad.cpu().numpy() - gf) <= 1e-9 * np.linalg.norm(gf)
+
+
+def test_unconverged_solve_is_an_error_in_the_autograd_function():
+    torch = _torch()
+    from paper_2407_05930_amd import MspError
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    pr = make_problem((12, 12, 12), s=3, m=1, seed=15, kappa="lognormal", with_target=True)
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-13, coarse_max=48, maxit=2)
+    f = torch.from_numpy(pr.b).cuda()
+    kap = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
+    with pytest.raises(MspError, match="NOT_CONVERGED"):
+        dp(f, kap)

@@ -108,6 +108,27 @@ def test_mis_distance_d_independent_and_maximal(d):
     assert np.all(dist[np.ix_(notsel, sel)].min(axis=1) <= d)
 
 
+def test_coarse_priorities_count_dependants_not_dependencies():
+    """Levels below the reduction rank a node by how many nodes depend on it
+    strongly, #{j : i in S_j} (a column count of S), ties broken by the hash.
+    On a hand-built asymmetric strength graph the row count (how many nodes i
+    depends on) orders the nodes differently, so this fixes the direction."""
+    from oracle.splitmix import splitmix64
+    # S_0 = {1}, S_1 = {0}, S_2 = {1}, S_3 = {1}, S_4 = {3}: node 1 is a strong
+    # dependency of 0, 2 and 3; every row has exactly one entry
+    rows = np.array([0, 1, 2, 3, 4])
+    cols = np.array([1, 0, 1, 1, 3])
+    S = sp.csr_matrix((np.ones(5), (rows, cols)), shape=(5, 5))
+    seed, level = 77, 2
+    rank = amg.priorities_coarse(S, level, seed)
+    dependants = np.array([1, 3, 0, 1, 0])            # column counts, worked out by hand
+    h = splitmix64(np.uint64(seed) ^ (np.uint64(level) << np.uint64(40)) ^ np.arange(5, dtype=np.uint64))
+    expect = sorted(range(5), key=lambda i: (dependants[i], int(h[i])))
+    assert [int(i) for i in np.argsort(rank)] == expect
+    assert int(np.argmax(rank)) == 1
+    assert sorted(rank.tolist()) == list(range(5))
+
+
 def test_distance_graph_matches_bfs():
     A, iface = _inner((8, 8, 8))
     T = amg.symmetrise(amg.strength(A, 0.25))

@@ -91,3 +91,60 @@ def test_amgr_per_subsystem_matches_direct_solve_in_fewer_iterations(k):
         assert np.linalg.norm(r.x - ref) <= 1e-8 * np.linalg.norm(ref)
         its[pc] = int(np.max(r.iters))
     assert its["amgr_sub"] < its["amgr"]
+
+
+def _recording_A(A, log):
+    def apply_A(X):
+        log.append(X.copy())
+        return A @ X
+    return apply_A
+
+
+def test_flexible_beta_equals_standard_for_a_fixed_spd_preconditioner():
+    """With a fixed SPD preconditioner (the shared AMGR V-cycle) the flexible
+    beta -<z_new, A p>/<p, A p> equals <r_new, z_new>/<r_old, z_old> in exact
+    arithmetic: both runs take the same iterations and residual histories
+    agree to rounding."""
+    p = make_problem((12, 12, 12), s=0, m=2, seed=11, y_stretch=1.5)
+    A = p.A.tocsr()
+    hier = amg.build_hierarchy(A, np.zeros(A.shape[0], dtype=bool), amg.AMGOptions(coarse_max=64))
+    thr = 1e-12 * np.linalg.norm(p.b, axis=0)
+    runs = [krylov.pcg_columns(lambda X: A @ X, lambda R: amg.vcycle(hier, R), p.b, thr, 200, flexible=f)
+            for f in (False, True)]
+    assert np.array_equal(runs[0].iters, runs[1].iters)
+    for h0, h1 in zip(runs[0].history, runs[1].history):
+        assert np.all(np.abs(h0 - h1) <= 1e-8 * np.abs(h0) + 1e-14 * np.linalg.norm(p.b, axis=0))
+    assert np.linalg.norm(runs[0].x - runs[1].x) <= 1e-10 * np.linalg.norm(runs[0].x)
+
+
+def test_flexible_beta_keeps_consecutive_directions_a_orthogonal():
+    """Under a preconditioner that changes every iteration (a random positive
+    diagonal drawn per call) the flexible beta still makes p_{k+1} A-orthogonal
+    to p_k in every column (Notay's local orthogonality), and the method still
+    converges; the standard beta loses that orthogonality."""
+    p = make_problem((10, 10, 10), s=0, m=2, seed=12, jitter=0.2, kappa="lognormal")
+    A = p.A.tocsr()
+    thr = 1e-10 * np.linalg.norm(p.b, axis=0)
+    worst = {}
+    for flexible in (False, True):
+        rng = np.random.default_rng(5)
+        dirs = []
+
+        def apply_M(R):
+            return rng.uniform(0.2, 5.0, size=R.shape[0])[:, None] * R
+
+        res = krylov.pcg_columns(_recording_A(A, dirs), apply_M, p.b, thr, 400, flexible=flexible)
+        ratio = 0.0
+        for P0, P1 in zip(dirs[:-1], dirs[1:]):
+            AP0 = A @ P0
+            num = np.abs(np.einsum("ij,ij->j", P1, AP0))
+            den = np.sqrt(np.einsum("ij,ij->j", P1, A @ P1) * np.einsum("ij,ij->j", P0, AP0))
+            live = ~np.all(P1 == P0, axis=0)      # frozen columns keep their direction
+            if live.any():
+                ratio = max(ratio, float((num[live] / den[live]).max()))
+        worst[flexible] = ratio
+        if flexible:
+            assert np.all(res.converged)
+            assert np.all(krylov.true_relres(A, res.x, p.b) <= 1e-10 * 1.0001)
+    assert worst[True] <= 1e-10, worst
+    assert worst[False] >= 1e-3, worst
