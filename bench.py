@@ -50,63 +50,104 @@ def timed_solves(sv, b, steps, warmup, torch):
     return (t1 - t0) / steps, x
 
 
-def dominant_kernel(sv, b):
-    """Kind with the largest total time over one fully instrumented solve."""
+def kernel_breakdown(sv, b):
+    """One fully instrumented solve: per timer class (kind) its launches, time,
+    algorithmic bytes and kernel function; and the same grouped by kernel
+    function (several classes can run one function, e.g. the level-0
+    operator and smoother products)."""
     sv.reset_timing()
     sv.set_timing(True)
     sv.solve(b)
     sv.set_timing(False)
     tm = sv.timing()
+    names = sv.timing_kernels()
     sv.reset_timing()
-    kind = max(tm, key=lambda k: tm[k][1])
-    total = sum(v[1] for v in tm.values())
-    return kind, tm, total
+    funcs = {}
+    for kind, (cnt, ms, by) in tm.items():
+        f = funcs.setdefault(names[kind], dict(kinds=[], launches=0, ms=0.0, bytes=0.0))
+        f["kinds"].append(kind)
+        f["launches"] += cnt
+        f["ms"] += ms
+        f["bytes"] += by
+    return tm, names, funcs
 
 
-KIND_KERNEL = {"update": "k_update_dots", "operator": "k_op_dot", "cast": "k_zfinish"}
-
-
-def committed_traffic(kind_name):
-    """Calibrated HBM bytes per launch of the dominant kernel from the committed
+def committed_traffic(kernel):
+    """Calibrated HBM bytes per launch of a kernel function from the committed
     rocprofv3 counter summary, if it was taken on the current library source."""
     import glob
     from paper_2407_05930_amd.profiling import source_hash
-    want = KIND_KERNEL.get(kind_name)
-    if not want:
-        return None
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
         try:
             info = json.load(open(path))
         except Exception:
             continue
-        if want in info.get("kernel", "") and info.get("source_hash") == source_hash():
+        if info.get("kernel") == kernel and info.get("source_hash") == source_hash():
             return int(info["traffic_bytes_per_launch"])
     return None
 
 
-def cpu_baseline(problem, iters_gpu, k, pc, extra):
-    """The FP64 oracle on the host: setup plus a bounded sample of PCG
-    iterations on the same workload, extrapolated to the GPU's iteration
-    count.  One thread (SciPy's sparse products are single-threaded; BLAS is
-    pinned to one thread)."""
-    from threadpoolctl import threadpool_limits
+def copy_ceiling(torch, nbytes=1 << 30, reps=10):
+    """Achievable bandwidth of a plain device copy of nbytes (read + write
+    counted), timed with events on the current stream."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return dict(bytes_moved=2 * nbytes, ms=round(ms, 4), GBs=round(2 * nbytes / (ms * 1e-3) / 1e9, 1))
+
+
+def window_marker(torch):
+    """A tiny int16 fill launched just before and just after the timed steps of
+    the headline solve, so that a kernel trace of this command can be cut to
+    exactly those steps (profiling.py window)."""
+    torch.empty(1, dtype=torch.int16, device="cuda").fill_(7)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(problem, k, pc, extra):
+    """The FP64 oracle on the host, on the same workload with the same
+    preconditioner and correction rank: setup (hierarchy and Lanczos) timed
+    on its own, then one complete solve to 1e-10, measured.  BLAS (dense
+    products of the oracle) may use every core; SciPy's sparse products, the
+    bulk of the work, run on one core."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import amg, krylov
-    with threadpool_limits(limits=1):
+    ncpu = os.cpu_count() or 1
+    with threadpool_limits(limits=ncpu):
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
         t0 = time.perf_counter()
-        ctx = krylov.setup(problem.A, problem.img, amg.AMGOptions(**extra), precond=pc, k=0)
+        ctx = krylov.setup(problem.A, problem.img, amg.AMGOptions(**extra), precond=pc, k=k)
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
-        krylov.solve(ctx, problem.b, tol=1e-10, maxit=1)
-        t1 = time.perf_counter()
-        krylov.solve(ctx, problem.b, tol=1e-10, maxit=3)
-        t2 = time.perf_counter()
-    per_it = ((t2 - t1) - (t1 - t0)) / 2.0
-    est = (t1 - t0) + per_it * max(iters_gpu - 1, 0)
-    sample = (f"oracle setup ({pc}, {t_setup:.1f} s, k=0) then PCG runs of 1 and 3 iterations on the full workload; "
-              f"{per_it:.2f} s/iteration extrapolated to the GPU FP64 iteration count ({iters_gpu}); "
-              f"low-rank corrections (k={k}) not included in the oracle sample")
-    return dict(value=round(est, 3), unit="s", cores=1, kind="oracle", sample=sample,
-                setup_s=round(t_setup, 2), s_per_iteration=round(per_it, 3))
+        ref = krylov.solve(ctx, problem.b, tol=1e-10)
+        t_solve = time.perf_counter() - t0
+    its = int(ref.iters.max())
+    sample = (f"the whole headline workload: oracle setup ({pc}, k={k}: hierarchy and Lanczos) {t_setup:.1f} s, timed "
+              f"apart; then one complete FP64 solve to 1e-10 ({its} iterations), measured, not extrapolated; "
+              f"{ncpu} host cores, BLAS pool {blas} threads, SciPy sparse products on 1 core")
+    return dict(value=round(t_solve, 3), unit="s", cores=int(blas), kind="oracle", sample=sample,
+                setup_s=round(t_setup, 2), iters=its, s_per_iteration=round(t_solve / max(its, 1), 3),
+                host_cpu_count=ncpu, host_cpu_model=cpu_model(), x=ref.x)
 
 
 def bench_jitter(args, torch, np):
@@ -239,6 +280,9 @@ def main():
                     help="reduction-level interpolation truncation (library default when omitted)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip timing the other preconditioner beside the headline one")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline mixed solve (for profiler runs): no other precision, no "
+                         "comparison, no copy ceiling, no CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for the traffic counters)")
@@ -274,57 +318,96 @@ def main():
     p = config_problem(args.workload)
     b = torch.from_numpy(p.b).cuda()
     k = args.k
-
-    def run_pc(pc, k, precs):
-        res = {}
-        for prec in precs:
-            log(f"setup {pc} {prec} k={k}")
-            sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=k, pc=pc, **args.extra)
-            t_setup = sv.stats.t_setup_s
-            log(f"timing {pc} {prec}: warmup {args.warmup}, steps {args.steps}")
-            t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
-            iters = sv.last.iters
-            relres = [float(v) for v in sv.last.relres_rec[: p.b.shape[1]]]
-            xs = x.cpu().numpy()
-            true_rr = np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)
-            res[prec] = dict(sv=sv, t=t, iters=iters, relres=relres, true_relres=true_rr.tolist(), t_setup=t_setup,
-                             x=xs)
-            log(f"  {pc} {prec}: {t * 1e3:.2f} ms/solve, {iters} iterations, true rel res {true_rr.max():.2e}")
-        return res
-
     head = args.mixed   # the mixed-precision variant reported as the headline
     alt = "mixed" if head == "mixed_bf16" else "mixed_bf16"
-    res = run_pc(args.pc, k, ("fp64", head, alt))
-    res["alt"] = res.pop(alt)
-    res["mixed"] = res.pop(head)
+
+    def run(pc, prec, label=None, markers=False, **opts):
+        label = label or prec
+        log(f"setup {pc} {label} k={k}")
+        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=k, pc=pc, **args.extra, **opts)
+        log(f"timing {pc} {label}: warmup {args.warmup}, steps {args.steps}")
+        for _ in range(args.warmup):
+            sv.solve(b)
+        torch.cuda.synchronize()
+        if markers:
+            window_marker(torch)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x = sv.solve(b)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        if markers:
+            window_marker(torch)
+            torch.cuda.synchronize()
+        xs = x.cpu().numpy()
+        true_rr = np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)
+        log(f"  {pc} {label}: {t * 1e3:.3f} ms/solve, {sv.last.iters} iterations, true rel res {true_rr.max():.2e}")
+        return dict(sv=sv, t=t, iters=sv.last.iters, true_relres=true_rr.tolist(), t_setup=sv.stats.t_setup_s, x=xs)
+
+    res = {}
+    res["mixed"] = run(args.pc, head, markers=True)
+    if args.headline_only:
+        print(json.dumps({"metric": METRIC, "value": round(res["mixed"]["t"], 6), "unit": "s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "iters": res["mixed"]["iters"],
+                          "note": "headline solve only (profiler run)"}), flush=True)
+        return
+    res["fp64"] = run(args.pc, "fp64")
+    res["alt"] = run(args.pc, alt)
     res["alt"]["sv"].close()
+    ns = run(args.pc, "mixed", label="mixed_fp64_coarsest", coarse64=1) if args.pc == "amgr_sub" else None
+    if ns is not None:
+        ns["sv"].close()
     other_pc = "amgr" if args.pc == "amgr_sub" else "amgr_sub"
     other = None
     if not args.no_compare:
-        other = run_pc(other_pc, k, ("fp64", "mixed"))
+        other = {prec: run(other_pc, prec) for prec in ("fp64", "mixed")}
         for v in other.values():
             v["sv"].close()
 
-    # roofline of the dominant kernel of the headline (mixed) solve, measured
-    # with HIP events on the solve's stream during the timed steps
+    # Roofline of the dominant kernel function of the headline solve: the
+    # function with the largest share of one fully instrumented solve; then
+    # its launches alone are bracketed by HIP events on the solve's stream
+    # during a second run of the timed steps.
     svm = res["mixed"]["sv"]
-    kind, tm_all, total_ms = dominant_kernel(svm, b)
-    svm.set_timing(True, kind)
-    t_head, _ = timed_solves(svm, b, args.steps, 0, torch)
-    svm.set_timing(False, kind)
-    cnt, ms, by = svm.timing()[kind]
+    tm_all, names, funcs = kernel_breakdown(svm, b)
+    top = max(funcs, key=lambda f: funcs[f]["ms"])
+    for kind in funcs[top]["kinds"]:
+        svm.set_timing(True, kind)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        svm.solve(b)
+    torch.cuda.synchronize()
+    t_head = (time.perf_counter() - t0) / args.steps
+    svm.set_timing(False)
+    live = svm.timing()
+    svm.reset_timing()
+    cnt = sum(live[kd][0] for kd in funcs[top]["kinds"] if kd in live)
+    ms = sum(live[kd][1] for kd in funcs[top]["kinds"] if kd in live)
+    by = sum(live[kd][2] for kd in funcs[top]["kinds"] if kd in live)
     avg_ms = ms / cnt
     bytes_per_launch = by / cnt
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    breakdown = {Solver.kind_name(kk): dict(launches=v[0], ms=round(v[1], 3),
+    ceiling = copy_ceiling(torch)
+    log(f"copy ceiling: {ceiling['GBs']} GB/s")
+    breakdown = {Solver.kind_name(kk): dict(launches=v[0], ms=round(v[1], 3), kernel=names[kk],
                                             GBs=round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None)
                  for kk, v in sorted(tm_all.items(), key=lambda kv: -kv[1][1])}
+    by_function = {f: dict(launches=v["launches"], ms=round(v["ms"], 3),
+                           classes=[Solver.kind_name(kk) for kk in v["kinds"]],
+                           GBs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None)
+                   for f, v in sorted(funcs.items(), key=lambda kv: -kv[1]["ms"])}
     # V-cycle aggregate GB/s: all level kernels and the dense coarsest solve
     vc_ms = sum(v[1] for kk, v in tm_all.items() if kk >= 16 or kk == 6)
     vc_by = sum(v[2] for kk, v in tm_all.items() if kk >= 16 or kk == 6)
+    vc_gbs = vc_by / (vc_ms * 1e-3) / 1e9 if vc_ms > 0 else None
 
     t_mixed = res["mixed"]["t"]
     t_fp64 = res["fp64"]["t"]
+    x64 = res["fp64"]["x"]
+
+    def rel(x, y):
+        return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
     out = {
         "metric": METRIC,
         "value": round(t_mixed, 6),
@@ -343,34 +426,47 @@ def main():
                    "preconditioner": args.pc,
                    "precision": PRECISION_NOTE[head], "unknowns": int(p.n)},
         "other_mixed_variant": {"precision": PRECISION_NOTE[alt], "solve_s": round(res["alt"]["t"], 6),
-                                "iters": res["alt"]["iters"], "true_relres_max": max(res["alt"]["true_relres"])},
+                                "iters": res["alt"]["iters"], "true_relres_max": max(res["alt"]["true_relres"]),
+                                "rel_diff_vs_fp64": rel(res["alt"]["x"], x64)},
         "fp64_solve_s": round(t_fp64, 6),
         "mixed_speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
         "iters": {"fp64": res["fp64"]["iters"], "mixed": res["mixed"]["iters"]},
         "true_relres_max": {kk: max(res[kk]["true_relres"]) for kk in ("fp64", "mixed")},
-        "mixed_vs_fp64_rel_diff": float(np.linalg.norm(res["mixed"]["x"] - res["fp64"]["x"])
-                                        / np.linalg.norm(res["fp64"]["x"])),
+        "mixed_vs_fp64_rel_diff": rel(res["mixed"]["x"], x64),
         "setup_s": {kk: round(res[kk]["t_setup"], 3) for kk in ("fp64", "mixed")},
-        "vcycle_GBs": round(vc_by / (vc_ms * 1e-3) / 1e9, 1) if vc_ms > 0 else None,
+        "vcycle_GBs": round(vc_gbs, 1) if vc_gbs else None,
+        "vcycle_frac": round(vc_gbs / HBM_PEAK_GBS, 4) if vc_gbs else None,
+        "vcycle_frac_of_copy_ceiling": round(vc_gbs / ceiling["GBs"], 4) if vc_gbs else None,
+        "copy_ceiling": ceiling,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(Solver.kind_name(kind)),
-                     "kernel": Solver.kind_name(kind), "avg_ms": round(avg_ms, 5),
-                     "algorithmic_bytes_per_launch": int(bytes_per_launch), "launches": cnt},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(top),
+                     "kernel": top, "classes": [Solver.kind_name(kk) for kk in funcs[top]["kinds"]],
+                     "avg_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                     "launches": cnt, "frac_of_copy_ceiling": round(achieved / ceiling["GBs"], 4)},
+        "kernel_functions_mixed": by_function,
         "kernel_breakdown_mixed": breakdown,
         "timed_solve_with_kernel_events_s": round(t_head, 6),
     }
+    if ns is not None:
+        out["mixed_fp32_vcycle_fp64_coarsest"] = {
+            "precision": "mixed (FP32 V-cycle: FP32 matrices, vectors and accumulation; FP64 coarsest solve; FP64 PCG)",
+            "solve_s": round(ns["t"], 6), "iters": ns["iters"], "true_relres_max": max(ns["true_relres"]),
+            "rel_diff_vs_fp64": rel(ns["x"], x64), "speedup_vs_fp64": round(t_fp64 / ns["t"], 3)}
     if other is not None:
         out[{"amgr": "shared_cycle", "amgr_sub": "per_subsystem_cycle"}[other_pc]] = {
             "preconditioner": other_pc,
             "mixed_solve_s": round(other["mixed"]["t"], 6), "fp64_solve_s": round(other["fp64"]["t"], 6),
             "iters": {kk: v["iters"] for kk, v in other.items()},
             "true_relres_max": {kk: max(v["true_relres"]) for kk, v in other.items()},
-            "mixed_vs_headline_rel_diff": float(np.linalg.norm(other["mixed"]["x"] - res["mixed"]["x"])
-                                                / np.linalg.norm(res["mixed"]["x"])),
+            "mixed_vs_headline_rel_diff": rel(other["mixed"]["x"], res["mixed"]["x"]),
         }
     if not args.no_cpu_baseline and rank == 0:
-        log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(p, res["fp64"]["iters"], k, args.pc, args.extra)
+        log("cpu baseline (oracle, same workload, preconditioner and k)")
+        cb = cpu_baseline(p, k, args.pc, args.extra)
+        xo = cb.pop("x")
+        cb["gpu_fp64_vs_oracle_rel_diff"] = rel(x64, xo)
+        cb["gpu_mixed_vs_oracle_rel_diff"] = rel(res["mixed"]["x"], xo)
+        out["cpu_baseline"] = cb
     if rank == 0:
         print(json.dumps(out), flush=True)
 

@@ -118,6 +118,9 @@ typedef struct {
     double trunc0;       /* reduction-level interpolation: each F row drops the weights below
                             trunc0 * (its largest weight magnitude) before the row-sum rescaling;
                             0 keeps every weight of the symbolic pattern; 0 <= trunc0 < 1 */
+    int32_t coarse64;    /* mixed modes with MSP_PC_AMGR_SUB: 1 = the per-subsystem coarsest
+                            inverses are read in FP64 (the V-cycle's vectors are converted at that
+                            level), 0 = rounded to FP32 (default) */
 } msp_opts;
 
 typedef struct {
@@ -140,7 +143,7 @@ typedef struct {
 /* Fill *o with the defaults: FP64, AMGR, k = 0, d = 2, theta = 0.25,
    jacobi0 = 3, jacobi = 1, coarse_max = 2560, max_levels = 20,
    max_ratio = 0.8, tol = 1e-10, maxit = 1000, device = 0, seed = 240705930,
-   trunc0 = 0.05. */
+   trunc0 = 0.05, coarse64 = 0. */
 int msp_default_opts(msp_opts* o);
 
 /* Build a context from A and its symmetry map.  Validates the map
@@ -209,6 +212,10 @@ int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz);
 int msp_set_timing(msp_ctx* c, int32_t kind, int32_t on);
 int msp_reset_timing(msp_ctx* c);
 int msp_get_timing(const msp_ctx* c, int32_t kind, int64_t* count, double* total_ms, double* total_bytes);
+/* Name of the kernel function (template instance, as a profiler lists it;
+   "a+b" for a class that launches two kernels) of the last timed launch of
+   a kind, NUL-terminated and truncated to len - 1 characters ("" if none). */
+int msp_get_timing_kernel(const msp_ctx* c, int32_t kind, char* name, int32_t len);
 
 /* ---------------------------------------------------------------------------
  * Batched solves: many independent systems (different sizes, symmetries and

@@ -48,7 +48,8 @@ class msp_opts(ctypes.Structure):
                 ("dist", ctypes.c_int32), ("theta", ctypes.c_double), ("jacobi0", ctypes.c_int32),
                 ("jacobi", ctypes.c_int32), ("coarse_max", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("max_ratio", ctypes.c_double), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("trunc0", ctypes.c_double)]
+                ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("trunc0", ctypes.c_double),
+                ("coarse64", ctypes.c_int32)]
 
 
 class msp_stats(ctypes.Structure):
@@ -85,6 +86,7 @@ SIGNATURES = {
     "msp_reset_timing": (ctypes.c_int, [_vp]),
     "msp_get_timing": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_double),
                                       _P(ctypes.c_double)]),
+    "msp_get_timing_kernel": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32]),
     "msp_batch_setup": (ctypes.c_int, [ctypes.c_int32, _P(msp_csr), _P(msp_symmap), _P(msp_opts), _P(_vp)]),
     "msp_batch_solve": (ctypes.c_int, [_vp, _P(ctypes.c_int32), _P(_vp), _P(_vp), _vp, _P(msp_stats)]),
     "msp_batch_size": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),

@@ -27,6 +27,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 
 SOURCES = [
     ("host_setup.cpp", ["-ffp-contract=off"]),
+    ("opts.cpp", []),
     ("api.cpp", []),
     ("fv.cpp", []),
     ("kernels.hip", DEVICE),

@@ -112,6 +112,7 @@ struct Timers {
     std::vector<int64_t> count = std::vector<int64_t>(KD_COUNT, 0);
     std::vector<double> ms = std::vector<double>(KD_COUNT, 0.0);
     std::vector<double> bytes = std::vector<double>(KD_COUNT, 0.0);
+    std::vector<std::string> variant = std::vector<std::string>(KD_COUNT);   // kernel(s) of the last timed launch
     std::vector<PendingTime> pending;
     std::vector<hipEvent_t> pool;
 };
@@ -287,6 +288,12 @@ static int tslot() {
     return sizeof(T) == 8 ? 0 : (sizeof(T) == 4 ? 1 : 2);
 }
 
+// short type names for the kernel names the timers report
+template <typename T>
+static const char* tname() {
+    return std::is_same<T, double>::value ? "double" : (std::is_same<T, float>::value ? "float" : "Bf16");
+}
+
 static hipEvent_t take_event(msp_ctx* c) {
     if (!c->tm.pool.empty()) {
         hipEvent_t e = c->tm.pool.back();
@@ -298,13 +305,15 @@ static hipEvent_t take_event(msp_ctx* c) {
     return e;
 }
 
-// Run `launch` bracketed by events on `st` when timers for `kind` are on.
-template <typename F>
-static void timed(msp_ctx* c, int kind, double bytes, hipStream_t st, F&& launch) {
+// Run `launch` bracketed by events on `st` when timers for `kind` are on;
+// name() gives the kernel function(s) the launch runs (evaluated only then).
+template <typename F, typename N>
+static void timed(msp_ctx* c, int kind, double bytes, hipStream_t st, F&& launch, N&& name) {
     if (kind < 0 || kind >= KD_COUNT || !c->tm.on[kind]) {
         launch();
         return;
     }
+    c->tm.variant[kind] = name();
     PendingTime p{kind, bytes, take_event(c), take_event(c)};
     HIPCHECK(hipEventRecord(p.e0, st));
     launch();
@@ -378,7 +387,17 @@ static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, c
     const int tuned = M.tuned[tslot<T>()][log2i(C)];
     const int split = tuned ? tuned : M.split;
     const bool wide = tuned && M.wide[tslot<T>()][log2i(C)];
-    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, wide, X, Y, Z, alpha, beta, od, S, m); });
+    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, wide, X, Y, Z, alpha, beta, od, S, m); },
+          [&] {
+              // the instance spmm_launch picks (bfloat16 values only for FP32 products of the BF16-G variant)
+              const char* tv = (std::is_same<T, float>::value && M.v16) ? "Bf16" : tname<typename ValOf<T>::type>();
+              const std::string ty = std::string(tname<T>()) + ", " + tv + ", " + std::to_string(C);
+              const bool sets = M.vs > 1;
+              if (split > 1)
+                  return "k_spmm_split<" + ty + ", " + std::to_string(split) + ", " + (sets ? "true" : "false") + ">";
+              return "k_spmm<" + ty + ", " + (sets ? "true" : "false") + ", " + (wide && !sets ? "true" : "false") +
+                     ">";
+          });
 }
 
 static bool mixed(const msp_ctx* c) { return c->o.precision != MSP_FP64; }
@@ -392,10 +411,13 @@ static void dense_sets(const msp_ctx* c, const Work& w, hipStream_t st, int m, c
         if (!c->d_cinv) throw Error(MSP_ERR_UNSUPPORTED, "FP64 coarsest inverses not on the device");
         HIPCHECK((launch_dense_sets<double, double>(st, w.C, S, m, c->nL, c->d_cinv, y, s,
                                                     static_cast<double*>(w.dense_pack), R)));
-    } else {
-        if (!c->d_cinv32) throw Error(MSP_ERR_UNSUPPORTED, "FP32 coarsest inverses not on the device");
+    } else if (c->d_cinv32) {
         HIPCHECK((launch_dense_sets<T, float>(st, w.C, S, m, c->nL, c->d_cinv32, y, s, static_cast<T*>(w.dense_pack),
                                               R)));
+    } else {   // FP64 inverses applied to the reduced-precision vectors (sums in FP64)
+        if (!c->d_cinv) throw Error(MSP_ERR_UNSUPPORTED, "coarsest inverses not on the device");
+        HIPCHECK((launch_dense_sets<T, double>(st, w.C, S, m, c->nL, c->d_cinv, y, s, static_cast<T*>(w.dense_pack),
+                                               R)));
     }
 }
 
@@ -403,7 +425,7 @@ static void dense_sets(const msp_ctx* c, const Work& w, hipStream_t st, int m, c
 template <typename T>
 static double dense_sets_bytes(const msp_ctx* c, int C) {
     const int S = 1 << c->sym.s;
-    const double eb = std::is_same<T, double>::value ? 8.0 : 4.0;
+    const double eb = (std::is_same<T, double>::value || !c->d_cinv32) ? 8.0 : 4.0;
     return eb * S * c->nL * dense_sets_ld(c->nL, (int)eb) + 2.0 * sizeof(T) * c->nL * C;
 }
 
@@ -616,11 +638,19 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     const int S = 1 << c->sym.s;
     if (l + 1 == c->hier.lev.size()) {
         if (c->sub && l > 0) {   // every subsystem's own coarsest operator
-            timed(c, KD_DENSE, dense_sets_bytes<T>(c, C), st, [&] { dense_sets<T>(c, w, st, w.m, y, s, w.dense_rows); });
+            timed(c, KD_DENSE, dense_sets_bytes<T>(c, C), st, [&] { dense_sets<T>(c, w, st, w.m, y, s, w.dense_rows); },
+                  [&] {
+                      int mp = 1;
+                      while (mp < w.m) mp *= 2;
+                      return std::string("k_pack_sets+k_dense_sets<") + tname<T>() + ", " +
+                             (std::is_same<T, double>::value || !c->d_cinv32 ? "double" : "float") + ", " +
+                             std::to_string(mp) + ", " + std::to_string(w.dense_rows) + ">";
+                  });
         } else {
             const double bytes = 8.0 * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
             timed(c, KD_DENSE, bytes, st,
-                  [&] { HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s, w.dense_part)); });
+                  [&] { HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s, w.dense_part)); },
+                  [&] { return std::string("k_dense_part+k_dense_sum<") + tname<T>() + ", " + std::to_string(C) + ">"; });
         }
         return;
     }
@@ -659,7 +689,8 @@ static void dot(msp_ctx* c, Work& w, hipStream_t st, const double* X, const doub
     const int64_t nb = c->sym.n_b;
     const int C = w.C;
     timed(c, KD_DOT, 16.0 * nb * C, st,
-          [&] { HIPCHECK(launch_dot<double>(st, C, nb, X, Y, w.partial, w.nb_dot, out)); });
+          [&] { HIPCHECK(launch_dot<double>(st, C, nb, X, Y, w.partial, w.nb_dot, out)); },
+          [&] { return "k_dot+k_reduce_partials<double, " + std::to_string(C) + ">"; });
 }
 
 // z += U_a diag(coef_a) U_a^T r_a for every subsystem a (low-rank corrections).
@@ -674,7 +705,7 @@ static void lrc_apply(msp_ctx* c, Work& w, hipStream_t st, const double* r, doub
         else
             HIPCHECK(launch_lrc_apply<double>(st, nb, S, k, w.m, w.C, static_cast<const double*>(c->d_U), r, z,
                                               c->d_lrc_coef, c->d_lrc_part, c->lrc_nb, c->d_lrc_W));
-    });
+    }, [] { return std::string("k_lrc_project+k_lrc_finish+k_lrc_expand"); });
 }
 
 // The shared preconditioner without corrections: the V-cycle (AMGR), G^T G
@@ -691,9 +722,11 @@ static void precondition_base(msp_ctx* c, Work& w, hipStream_t st, const double*
                 T* y0 = static_cast<T*>(w.vy[0]);
                 T* s0 = static_cast<T*>(w.vs[0]);
                 const double cb = (8.0 + sizeof(T)) * nb * C;
-                timed(c, KD_CAST, cb, st, [&] { HIPCHECK((launch_cast<T, double>(st, nb * C, r, y0))); });
+                timed(c, KD_CAST, cb, st, [&] { HIPCHECK((launch_cast<T, double>(st, nb * C, r, y0))); },
+                      [] { return std::string("k_cast<") + tname<T>() + ", double>"; });
                 vcycle<T>(c, w, st, 0, y0, s0);
-                timed(c, KD_CAST, cb, st, [&] { HIPCHECK((launch_cast<double, T>(st, nb * C, s0, z))); });
+                timed(c, KD_CAST, cb, st, [&] { HIPCHECK((launch_cast<double, T>(st, nb * C, s0, z))); },
+                      [] { return std::string("k_cast<double, ") + tname<T>() + ">"; });
             };
             if (c->o.precision == MSP_MIXED_BF16) run(Bf16{});
             else run(0.0f);
@@ -793,7 +826,7 @@ static void upload_all(msp_ctx* c) {
         }
         c->nL = c->hier.lev.back().A.nr;
         const std::vector<double>& inv = c->sub ? c->subv.coarse_inv : c->hier.coarse_inv;
-        if (c->sub && mixed(c)) {
+        if (c->sub && mixed(c) && !c->o.coarse64) {
             // the V-cycle computes in FP32: its coarsest inverses are read in FP32 too
             const int64_t nL = c->nL, ld = dense_sets_ld(nL, 4);
             const int64_t S = int64_t(1) << c->sym.s;
@@ -921,6 +954,10 @@ struct SolvePlan {
                 HIPCHECK(launch_update_dots<double>(st, C, nbu, upd, kl, nb, W.r, W.q, alpha,
                                                     static_cast<const double*>(c->d_U), S, m, W.pp1, W.plrc, y32(),
                                                     y16()));
+        }, [&] {
+            const char* tu = c->U16 ? "Bf16" : ((c->U32 || !c->d_U) ? "float" : "double");
+            return "k_update_dots<" + std::to_string(C) + ", " + (upd ? "true" : "false") + ", " +
+                   std::to_string(kl > 8 ? 16 : (kl > 0 ? 8 : 0)) + ", " + tu + ">";
         });
         HIPCHECK(launch_fin_check(st, C, nbu, !upd, O, m, W.pp1, W.plrc, thr, c->d_lrc_coef, active, iters, flags,
                                   rnorm, c->d_lrc_W));
@@ -982,6 +1019,11 @@ struct SolvePlan {
                                                              static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
                                                              W.pp1, z2, qf, pqz)));
             }
+        }, [&] {
+            const char* ts = s16 ? "Bf16" : (s32 ? "float" : "double");
+            const char* tu = c->U16 ? "Bf16" : ((c->U32 || !c->d_U) ? "float" : "double");
+            return "k_zfinish<" + std::to_string(C) + ", " + ts + ", " + (U && kl > 0 ? "true" : "false") + ", " + tu +
+                   ", " + (fq ? "true" : "false") + ">";
         });
         HIPCHECK(launch_fin_beta(st, C, nbz, init, flexible, W.pp1, W.pp2, active, pq, rho, beta, rz));
     }
@@ -994,7 +1036,8 @@ struct SolvePlan {
         HIPCHECK(launch_fill<double>(st, nb * C, W.x, 0.0));
         HIPCHECK(launch_fill<int>(st, 2, flags, 0));
         timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // bhat = Q_s b
-              [&] { HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, W.r)); });
+              [&] { HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, W.r)); },
+              [&] { return "k_qs_forward<" + std::to_string(S) + ">"; });
         update_dots(false);
         precond_dot(true);   // also writes p = z
     }
@@ -1005,7 +1048,7 @@ struct SolvePlan {
         timed(c, KD_OP, opb, st, [&] {   // q = Ahat p and <p, q>
             HIPCHECK(launch_op_dot(st, C, nbo, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, c->dsig.d, S, m, W.p, W.q,
                                    W.pp1));
-        });
+        }, [&] { return "k_op_dot<" + std::to_string(C) + ">"; });
         HIPCHECK(launch_fin_alpha(st, C, nbo, W.pp1, active, rho, alpha, pq, flags));
         update_dots(true);
         x_pending = true;   // x += alpha p follows with the p update (or in finish)
@@ -1015,7 +1058,8 @@ struct SolvePlan {
         Work& W = *w;
         precond_dot(false);
         timed(c, KD_PUPDATE, 5.0 * vb(), st,
-              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, W.x, W.p, W.z, alpha, beta, active)); });
+              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, W.x, W.p, W.z, alpha, beta, active)); },
+              [&] { return "k_pcg_pupdate<" + std::to_string(C) + ">"; });
         x_pending = false;
     }
 
@@ -1064,7 +1108,7 @@ struct SolvePlan {
         timed(c, KD_QS, (xp ? 24.0 : 16.0) * n * m + 8.0 * n, st, [&] {
             HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, W.x, d_x, xp ? W.p : nullptr,
                                         xp ? alpha : nullptr));
-        });
+        }, [&] { return "k_qs_backward<" + std::to_string(S) + ">"; });
         HIPCHECK(hipMemcpyAsync(W.h_iters, iters, 64 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipMemcpyAsync(W.h_scal, W.scal, SC_COUNT * 64 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipMemcpyAsync(W.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1182,6 +1226,7 @@ static void check_opts(const msp_opts* o) {
         throw Error(MSP_ERR_ARG, "invalid option value");
     if (o->lrc_k > 0 && o->pc == MSP_PC_NONE) throw Error(MSP_ERR_ARG, "low-rank corrections need a preconditioner");
     if (o->lrc_k > 16) throw Error(MSP_ERR_UNSUPPORTED, "low-rank correction rank above 16");
+    if (o->coarse64 != 0 && o->coarse64 != 1) throw Error(MSP_ERR_ARG, "coarse64 must be 0 or 1");
 }
 
 // Host part of the setup: blocks, validation, hierarchy (no HIP calls).
@@ -1405,27 +1450,6 @@ static int batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b
 
 extern "C" {
 
-int msp_default_opts(msp_opts* o) {
-    if (!o) return MSP_ERR_ARG;
-    std::memset(o, 0, sizeof(*o));
-    o->precision = MSP_FP64;
-    o->pc = MSP_PC_AMGR;
-    o->lrc_k = 0;
-    o->dist = 2;
-    o->theta = 0.25;
-    o->jacobi0 = 3;
-    o->trunc0 = 0.05;
-    o->jacobi = 1;
-    o->coarse_max = 2560;
-    o->max_levels = 20;
-    o->max_ratio = 0.8;
-    o->tol = 1e-10;
-    o->maxit = 1000;
-    o->device = 0;
-    o->seed = 240705930ull;
-    return MSP_OK;
-}
-
 int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ctx** out) {
     return guarded([&]() -> int {
         if (!out) throw Error(MSP_ERR_ARG, "null output");
@@ -1593,6 +1617,15 @@ int msp_reset_timing(msp_ctx* c) {
     std::fill(c->tm.count.begin(), c->tm.count.end(), 0);
     std::fill(c->tm.ms.begin(), c->tm.ms.end(), 0.0);
     std::fill(c->tm.bytes.begin(), c->tm.bytes.end(), 0.0);
+    return MSP_OK;
+}
+
+int msp_get_timing_kernel(const msp_ctx* c, int32_t kind, char* name, int32_t len) {
+    if (!c || kind < 0 || kind >= msp::KD_COUNT || !name || len <= 0) return MSP_ERR_ARG;
+    const std::string& v = c->tm.variant[kind];
+    const size_t k = std::min(v.size(), static_cast<size_t>(len - 1));
+    std::memcpy(name, v.data(), k);
+    name[k] = 0;
     return MSP_OK;
 }
 

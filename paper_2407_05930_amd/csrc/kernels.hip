@@ -1027,6 +1027,10 @@ template hipError_t launch_dense_sets<float, float>(hipStream_t, int, int, int, 
                                                     float*, float*, int);
 template hipError_t launch_dense_sets<Bf16, float>(hipStream_t, int, int, int, int64_t, const float*, const Bf16*,
                                                    Bf16*, Bf16*, int);
+template hipError_t launch_dense_sets<float, double>(hipStream_t, int, int, int, int64_t, const double*,
+                                                     const float*, float*, float*, int);
+template hipError_t launch_dense_sets<Bf16, double>(hipStream_t, int, int, int, int64_t, const double*, const Bf16*,
+                                                    Bf16*, Bf16*, int);
 
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {

@@ -1,12 +1,18 @@
 """Summaries of rocprofv3 output for the committed profile notes.
 
-    python -m paper_2407_05930_amd.profiling stats <kernel_stats.csv> <out.md> <command>
+    python -m paper_2407_05930_amd.profiling window <kernel_trace.csv> <out.md> <command...>
     python -m paper_2407_05930_amd.profiling traffic <fetch_counter_collection.csv>
-        <write_counter_collection.csv> <kernel substring> <copy bytes> <out.md> <command...>
+        <write_counter_collection.csv> <kernel name> <copy bytes> <out.md> <command...>
+    python -m paper_2407_05930_amd.profiling counters <counter_collection.csv> <out.md> <command...>
 
-The traffic summary scales each counter of the named kernel by the ratio
-between the known size of a plain device copy and what the same counter
-reads for that copy (rocprofv3 reports FETCH_SIZE / WRITE_SIZE in KiB).
+``window`` keeps the dispatches between the two int16 fill kernels that
+bench.py launches just before and just after the timed steps of the headline
+solve (setup, autotuning and the other legs fall outside), and tabulates
+them per kernel function.  ``traffic`` scales each counter of the named
+kernel (dispatches inside the window) by the ratio between the known size of
+a plain device copy and what the same counter reads for that copy (rocprofv3
+reports FETCH_SIZE / WRITE_SIZE in KiB).  ``counters`` averages every counter
+per kernel function inside the window.
 """
 from __future__ import annotations
 
@@ -28,68 +34,140 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stats(path, out, command):
+MARKER = "FillFunctor<short>"   # the int16 fill bench.py launches around the timed steps
+
+
+def short_name(name):
+    """Kernel function as the library's timers name it: no return type,
+    namespace or argument list ("void msp::k_op_dot<32>(long, ...)" ->
+    "k_op_dot<32>")."""
+    n = name.strip()
+    if n.startswith("void "):
+        n = n[5:]
+    n = n.replace("msp::", "")
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return n[:i]
+    return n
+
+
+def _in_window(rows, order_key):
+    """Rows strictly between the first and the last marker dispatch (all rows
+    when the markers are missing), in dispatch order; flag says which."""
+    rows = sorted(rows, key=order_key)
+    marks = [i for i, r in enumerate(rows) if MARKER in r["Kernel_Name"]]
+    if len(marks) < 2:
+        return rows, False
+    return [r for r in rows[marks[0] + 1:marks[-1]] if MARKER not in r["Kernel_Name"]], True
+
+
+def window(path, out, command):
     rows = list(csv.DictReader(open(path)))
-    lines = [f"# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+    rows, found = _in_window(rows, lambda r: int(r["Start_Timestamp"]))
+    per = {}
+    for r in rows:
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        e = per.setdefault(short_name(r["Kernel_Name"]), [0, 0])
+        e[0] += 1
+        e[1] += d
+    total = sum(v[1] for v in per.values()) or 1
+    span = (int(rows[-1]["End_Timestamp"]) - int(rows[0]["Start_Timestamp"])) if rows else 0
+    lines = ["# rocprofv3 kernel statistics of the timed headline solves", "", f"Command: `{command}`", "",
              f"Library source hash: `{source_hash()}`", "",
-             "Totals cover the whole command: the setup (upload, autotuning, the Lanczos runs of the low-rank "
-             "corrections: `k_axpy_cols`, `k_dot<double, 8>`, copies) and every timed solve.", "",
+             ("Only the dispatches between the two int16 fill markers that bench.py launches around its timed steps "
+              "are counted (no setup, autotuning or Lanczos kernels)." if found else
+              "The window markers were not found: every dispatch of the command is counted."), "",
+             f"Dispatches: {len(rows)}; kernel busy time {total / 1e6:.3f} ms; window span {span / 1e6:.3f} ms.", "",
              "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
-    for r in rows[:30]:
-        name = r["Name"].replace("|", "/")
-        if len(name) > 110:
-            name = name[:110] + "..."
-        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
-                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    for name, (cnt, ns) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        nm = name.replace("|", "/")
+        if len(nm) > 140:
+            nm = nm[:140] + "..."
+        lines.append(f"| `{nm}` | {cnt} | {ns / 1e6:.3f} | {ns / cnt / 1e3:.2f} | {100.0 * ns / total:.2f} |")
     open(out, "w").write("\n".join(lines) + "\n")
+    json.dump({name: dict(calls=c, total_ns=t, avg_ns=t / c) for name, (c, t) in per.items()},
+              open(os.path.splitext(out)[0] + ".json", "w"), indent=1)
 
 
-def _counter_rows(path, counter):
+def _dispatches(path):
+    """{(kernel, dispatch id): {counter: value summed over its instances}} for the
+    dispatches inside the marker window, and the copy dispatches outside it."""
     rows = list(csv.DictReader(open(path)))
-    out = []
+    per = {}
     for r in rows:
         name = r.get("Counter_Name") or r.get("Counter")
-        if name != counter:
-            continue
-        out.append((r["Kernel_Name"], float(r.get("Counter_Value") or r.get("Value")),
-                    int(r.get("Dispatch_Id", 0))))
-    return out
+        key = (r["Kernel_Name"], int(r.get("Dispatch_Id", 0)))
+        d = per.setdefault(key, {})
+        d[name] = d.get(name, 0.0) + float(r.get("Counter_Value") or r.get("Value"))
+    items = [dict(Kernel_Name=k[0], Dispatch_Id=k[1], values=v) for k, v in per.items()]
+    inside, found = _in_window(items, lambda r: r["Dispatch_Id"])
+    return items, inside, found
 
 
 def traffic(fetch_csv, write_csv, kernel, copy_bytes, out, command):
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        rows = _counter_rows(path, counter)
-        # per-dispatch values summed over the counter's instances
-        per = {}
-        for name, val, did in rows:
-            per.setdefault((name, did), 0.0)
-            per[(name, did)] += val
-        copy = [v for (nm, _), v in per.items() if "copy" in nm.lower() or "elementwise" in nm.lower()]
-        kern = [v for (nm, _), v in per.items() if kernel in nm]
+        items, inside, found = _dispatches(path)
+        copy = [r["values"][counter] for r in items if "copy" in r["Kernel_Name"].lower() and counter in r["values"]]
+        kern = [r["values"][counter] for r in inside if short_name(r["Kernel_Name"]) == kernel and counter in r["values"]]
         if not copy or not kern:
             raise SystemExit(f"{counter}: copy or kernel dispatches not found")
         copy_kib = max(copy)
         factor = copy_bytes / (copy_kib * 1024.0)
         avg_kib = sum(kern) / len(kern)
         res[counter] = dict(copy_kib=copy_kib, factor=factor, kernel_avg_kib=avg_kib,
-                            kernel_bytes=avg_kib * 1024.0 * factor, dispatches=len(kern))
+                            kernel_bytes=avg_kib * 1024.0 * factor, dispatches=len(kern), window=found)
     total = res["FETCH_SIZE"]["kernel_bytes"] + res["WRITE_SIZE"]["kernel_bytes"]
     info = dict(kernel=kernel, source_hash=source_hash(), traffic_bytes_per_launch=total, counters=res,
                 command=command)
     json.dump(info, open(os.path.splitext(out)[0] + ".json", "w"), indent=1)
     lines = [f"# HBM traffic of `{kernel}` (rocprofv3 counters)", "", f"Command: `{command}`", "",
-             f"Library source hash: `{source_hash()}`", ""]
+             f"Library source hash: `{source_hash()}`", "",
+             "Dispatches of the timed headline solves only (between the bench's window markers)." if
+             res["FETCH_SIZE"]["window"] else "All dispatches of the command (window markers not found).", ""]
     for cn, v in res.items():
         lines.append(f"- {cn}: kernel average {v['kernel_avg_kib']:.0f} KiB over {v['dispatches']} dispatches; "
-                     f"copy of {copy_bytes} bytes reads {v['copy_kib']:.0f} KiB -> factor {v['factor']:.4f}; "
+                     f"copy of {copy_bytes:.0f} bytes reads {v['copy_kib']:.0f} KiB -> factor {v['factor']:.4f}; "
                      f"calibrated {v['kernel_bytes'] / 1e6:.1f} MB per launch")
     lines.append(f"- total: {total / 1e6:.1f} MB per launch")
     open(out, "w").write("\n".join(lines) + "\n")
 
 
+def counters(path, out, command):
+    """Average of every collected counter per kernel function inside the window."""
+    items, inside, found = _dispatches(path)
+    per = {}
+    for r in inside:
+        e = per.setdefault(short_name(r["Kernel_Name"]), dict(n=0, sums={}))
+        e["n"] += 1
+        for cn, v in r["values"].items():
+            e["sums"][cn] = e["sums"].get(cn, 0.0) + v
+    names = sorted({cn for e in per.values() for cn in e["sums"]})
+    lines = ["# rocprofv3 counters per kernel function (timed headline solves)", "", f"Command: `{command}`", "",
+             f"Library source hash: `{source_hash()}`", "",
+             "Per-dispatch averages over the dispatches between the bench's window markers." if found else
+             "Per-dispatch averages over every dispatch of the command (window markers not found).", "",
+             "| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for name, e in sorted(per.items(), key=lambda kv: kv[0]):
+        nm = name.replace("|", "/")
+        if len(nm) > 110:
+            nm = nm[:110] + "..."
+        vals = " | ".join(f"{e['sums'].get(cn, 0.0) / e['n']:.0f}" for cn in names)
+        lines.append(f"| `{nm}` | {e['n']} | {vals} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
-        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    if sys.argv[1] == "window":
+        window(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), sys.argv[6], " ".join(sys.argv[7:]))
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    else:
+        raise SystemExit(__doc__)

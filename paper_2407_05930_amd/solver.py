@@ -213,6 +213,15 @@ class Solver:
                 out[kind] = (cnt.value, ms.value, by.value)
         return out
 
+    def timing_kernels(self) -> dict:
+        """{kind: kernel function name} for kinds with timed launches."""
+        out = {}
+        buf = ctypes.create_string_buffer(256)
+        for kind in self.timing():
+            check(lib.msp_get_timing_kernel(self._ctx, kind, buf, 256))
+            out[kind] = buf.value.decode()
+        return out
+
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx.value:
             lib.msp_free(self._ctx)
