@@ -168,6 +168,22 @@ int msp_solve_device(msp_ctx* c, int32_t m, const double* d_b, double* d_x, void
 /* Same with host arrays (copies in and out). */
 int msp_solve(msp_ctx* c, int32_t m, const double* b, double* x, msp_stats* st);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): msp_solve_device without
+   any allocation.  Same arguments, results and errors.  The whole workspace
+   (PCG and V-cycle multivectors, partial sums, scalars) is carved from a
+   128 MiB device array that every GPU running the library holds until the
+   process ends; a system whose workspace for this column count exceeds it
+   returns MSP_ERR_UNSUPPORTED (the message gives both sizes).  No kernel
+   shapes are timed: the call uses the lane-group splits that an earlier
+   msp_solve_device of this context and column count tuned, else the
+   defaults.  Per-kernel timers must be off (MSP_ERR_ARG otherwise).  Every
+   call on one GPU uses the same array, so calls that overlap on one GPU
+   (on different streams, contexts or threads) race; the array keeps the
+   last call's contents and each call clears what it needs cleared. */
+int msp_solve_device_noalloc(msp_ctx* c, int32_t m, const double* d_b, double* d_x, void* hip_stream,
+                             msp_stats* st);
+
 /* Hierarchy introspection (works for host-only contexts). */
 int msp_get_stats(const msp_ctx* c, msp_stats* st);
 int msp_num_levels(const msp_ctx* c, int32_t* nlev);

@@ -73,6 +73,7 @@ SIGNATURES = {
     "msp_setup": (ctypes.c_int, [_P(msp_csr), _P(msp_symmap), _P(msp_opts), _P(_vp)]),
     "msp_solve_device": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _P(msp_stats)]),
     "msp_solve": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _P(msp_stats)]),
+    "msp_solve_device_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _P(msp_stats)]),
     "msp_get_stats": (ctypes.c_int, [_vp, _P(msp_stats)]),
     "msp_num_levels": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
     "msp_level_sizes": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_int64),

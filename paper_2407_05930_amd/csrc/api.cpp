@@ -60,12 +60,28 @@ struct DevLevel {
     int64_t n = 0;
 };
 
-// Column-count-dependent workspace.
+constexpr int kMaxLevels = 32;   // hierarchy depth the workspace and the statistics hold
+
+// Pinned host memory the solve reads flags and statistics into.
+struct HostBufs {
+    int* h_flags = nullptr;   // pinned host copy of flags
+    int* h_pub = nullptr;     // fine-grained host memory the device publishes flags into: flags, sequence number
+    int* d_pub = nullptr;     // its device-visible address
+    int* h_iters = nullptr;
+    double* h_scal = nullptr;
+};
+
+// Column-count-dependent workspace.  Every device array is carved from one
+// block (carve_work): the library's own allocation for msp_solve_device, the
+// static scratch array for the allocation-free entry point.
 struct Work {
     int C = 0;
     int m = 1;                // columns per subsystem of the current solve
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *zold = nullptr;
-    std::vector<void*> vy, vs, vr, vt;    // per level, element type of the V-cycle (vt: factored smoother)
+    void* vy[kMaxLevels] = {};   // per level, element type of the V-cycle
+    void* vs[kMaxLevels] = {};
+    void* vr[kMaxLevels] = {};
+    void* vt[kMaxLevels] = {};   // factored smoother (BF16-G variant)
     double* partial = nullptr;
     int nb_dot = 0;
     int grid_op = 0, grid_upd = 0, grid_z = 0;   // PCG kernel grids (set by the first solve plan)
@@ -74,14 +90,15 @@ struct Work {
     int dense_rows = 8;             // rows per wavefront of the per-subsystem coarsest solves (autotuned)
     // partials of the fused PCG kernels: two column sets and the low-rank projections
     double *pp1 = nullptr, *pp2 = nullptr, *plrc = nullptr;
-    double* scal = nullptr;   // 10 arrays of 64
+    double* scal = nullptr;   // SC_COUNT arrays of 64
     int* iscal = nullptr;     // active[64], iters[64], flags[2]
-    int* h_flags = nullptr;   // pinned host copy of flags
-    int* h_pub = nullptr;     // fine-grained host memory the device publishes flags into: flags, sequence number
-    int* d_pub = nullptr;     // its device-visible address
+    int* h_flags = nullptr;   // host buffers (HostBufs of the workspace or of the context)
+    int* h_pub = nullptr;
+    int* d_pub = nullptr;
     int pub_seq = 0;
     int* h_iters = nullptr;
     double* h_scal = nullptr;
+    HostBufs own;             // pinned buffers this workspace allocated (freed with the context)
 };
 
 enum { SC_RR = 0, SC_RZ, SC_PQ, SC_RHO, SC_ALPHA, SC_BETA, SC_THR, SC_RNORM, SC_BN2, SC_COUNT };
@@ -139,6 +156,8 @@ struct msp_ctx {
     float* d_cinv32 = nullptr;    // per-subsystem coarsest inverses in FP32 (mixed modes), rows padded to 4
     int64_t nL = 0;
     std::map<int, std::unique_ptr<msp::Work>> works;   // by padded column count
+    msp::HostBufs nohb;       // pinned host buffers of the allocation-free solves (allocated at setup)
+    int nopub_seq = 0;
     // low-rank corrections: U (n_b x S*k, FP64 or FP32), coefficients (S*k)
     int lrc_k = 0;
     void* d_U = nullptr;
@@ -161,12 +180,14 @@ struct msp_ctx {
             }
             for (auto e : tm.pool) (void)hipEventDestroy(e);
             for (void* p : allocs) (void)hipFree(p);
-            for (auto& kv : works) {
-                if (kv.second->h_flags) (void)hipHostFree(kv.second->h_flags);
-                if (kv.second->h_pub) (void)hipHostFree(kv.second->h_pub);
-                if (kv.second->h_iters) (void)hipHostFree(kv.second->h_iters);
-                if (kv.second->h_scal) (void)hipHostFree(kv.second->h_scal);
-            }
+            auto free_host = [](msp::HostBufs& h) {
+                if (h.h_flags) (void)hipHostFree(h.h_flags);
+                if (h.h_pub) (void)hipHostFree(h.h_pub);
+                if (h.h_iters) (void)hipHostFree(h.h_iters);
+                if (h.h_scal) (void)hipHostFree(h.h_scal);
+            };
+            for (auto& kv : works) free_host(kv.second->own);
+            free_host(nohb);
         }
     }
 
@@ -571,57 +592,82 @@ static int vbytes(const msp_ctx* c) {
 }
 static bool amg(const msp_ctx* c) { return c->o.pc == MSP_PC_AMGR || c->o.pc == MSP_PC_AMGR_SUB; }
 
+// Carves the device arrays of a C-column workspace out of base (base ==
+// nullptr: offsets only); each array starts on a 256-byte boundary.  Returns
+// the bytes the block needs.
+static size_t carve_work(const msp_ctx* c, int C, Work& w, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        off = (off + 255) & ~static_cast<size_t>(255);
+        void* p = base ? static_cast<void*>(base + off) : nullptr;
+        off += bytes > 0 ? bytes : 1;
+        return p;
+    };
+    const size_t nb = static_cast<size_t>(c->sym.n_b);
+    const size_t vec = sizeof(double) * nb * static_cast<size_t>(C);
+    w.C = C;
+    w.x = static_cast<double*>(take(vec));
+    w.r = static_cast<double*>(take(vec));
+    w.z = static_cast<double*>(take(vec));
+    w.p = static_cast<double*>(take(vec));
+    w.q = static_cast<double*>(take(vec));
+    w.zold = static_cast<double*>(take(vec));
+    const size_t es = static_cast<size_t>(vbytes(c));
+    const size_t L = c->hier.lev.size();
+    if (amg(c)) {
+        for (size_t l = 0; l < L; ++l) {
+            const size_t n = static_cast<size_t>(c->hier.lev[l].A.nr);
+            w.vy[l] = take(es * n * C);
+            w.vs[l] = take(es * n * C);
+            w.vr[l] = take(es * n * C);
+            if (c->o.precision == MSP_MIXED_FP32_BF16G) w.vt[l] = take(es * n * C);
+        }
+        const int64_t nL = c->hier.lev.back().A.nr;
+        const int ks = dense_splits(C, nL, vbytes(c));
+        w.dense_part = static_cast<double*>(take(sizeof(double) * static_cast<size_t>(ks * nL * C)));
+        if (c->sub) w.dense_pack = take(sizeof(double) * static_cast<size_t>(2 * (nL + 4) * C));
+    }
+    w.nb_dot = 512;
+    w.partial = static_cast<double*>(take(sizeof(double) * static_cast<size_t>(w.nb_dot) * 64));
+    w.pp1 = static_cast<double*>(take(sizeof(double) * static_cast<size_t>(kPcgMaxBlocks) * 64));
+    w.pp2 = static_cast<double*>(take(sizeof(double) * static_cast<size_t>(kPcgMaxBlocks) * 64));
+    if (c->lrc_k > 0)
+        w.plrc = static_cast<double*>(take(sizeof(double) * static_cast<size_t>(kPcgMaxBlocks) * 64 * c->lrc_k));
+    w.scal = static_cast<double*>(take(sizeof(double) * SC_COUNT * 64));
+    w.iscal = static_cast<int*>(take(sizeof(int) * (64 * 2 + 2)));
+    return off;
+}
+
+// Pinned host buffers for the flags and statistics of a solve.
+static void alloc_host_bufs(HostBufs& h) {
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&h.h_flags), 2 * sizeof(int), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&h.h_pub), 4 * sizeof(int),
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    h.h_pub[0] = h.h_pub[1] = h.h_pub[2] = h.h_pub[3] = 0;
+    HIPCHECK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h.d_pub), h.h_pub, 0));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&h.h_iters), 64 * sizeof(int), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&h.h_scal), SC_COUNT * 64 * sizeof(double),
+                           hipHostMallocDefault));
+}
+
+static void use_host_bufs(Work& w, const HostBufs& h) {
+    w.h_flags = h.h_flags;
+    w.h_pub = h.h_pub;
+    w.d_pub = h.d_pub;
+    w.h_iters = h.h_iters;
+    w.h_scal = h.h_scal;
+}
+
 // Workspace for C padded columns (allocated on first use, kept with the context).
 static Work& work(msp_ctx* c, int C) {
     auto it = c->works.find(C);
     if (it != c->works.end()) return *it->second;
     std::unique_ptr<Work> wp(new Work());
     Work& w = *wp;
-    const int64_t nb = c->sym.n_b;
-    w.C = C;
-    w.x = c->dalloc<double>(nb * C);
-    w.r = c->dalloc<double>(nb * C);
-    w.z = c->dalloc<double>(nb * C);
-    w.p = c->dalloc<double>(nb * C);
-    w.q = c->dalloc<double>(nb * C);
-    w.zold = c->dalloc<double>(nb * C);
-    const size_t es = static_cast<size_t>(vbytes(c));
-    const size_t L = c->hier.lev.size();
-    w.vy.assign(L, nullptr);
-    w.vs.assign(L, nullptr);
-    w.vr.assign(L, nullptr);
-    w.vt.assign(L, nullptr);
-    if (amg(c)) {
-        for (size_t l = 0; l < L; ++l) {
-            const int64_t n = c->hier.lev[l].A.nr;
-            w.vy[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
-            w.vs[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
-            w.vr[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
-            if (c->o.precision == MSP_MIXED_FP32_BF16G)
-                w.vt[l] = c->dalloc<char>(static_cast<int64_t>(es) * n * C);
-        }
-    }
-    if (amg(c)) {
-        const int64_t nL = c->hier.lev.back().A.nr;
-        const int ks = dense_splits(C, nL, vbytes(c));
-        w.dense_part = c->dalloc<double>(static_cast<int64_t>(ks) * nL * C);
-        if (c->sub) w.dense_pack = c->dalloc<double>(2 * (nL + 4) * C);
-    }
-    w.nb_dot = 512;
-    w.partial = c->dalloc<double>(static_cast<int64_t>(w.nb_dot) * 64);
-    w.pp1 = c->dalloc<double>(static_cast<int64_t>(kPcgMaxBlocks) * 64);
-    w.pp2 = c->dalloc<double>(static_cast<int64_t>(kPcgMaxBlocks) * 64);
-    if (c->lrc_k > 0) w.plrc = c->dalloc<double>(static_cast<int64_t>(kPcgMaxBlocks) * 64 * c->lrc_k);
-    w.scal = c->dalloc<double>(SC_COUNT * 64);
-    w.iscal = c->dalloc<int>(64 * 2 + 2);
-    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_flags), 2 * sizeof(int), hipHostMallocDefault));
-    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_pub), 4 * sizeof(int),
-                           hipHostMallocMapped | hipHostMallocCoherent));
-    w.h_pub[0] = w.h_pub[1] = w.h_pub[2] = w.h_pub[3] = 0;
-    HIPCHECK(hipHostGetDevicePointer(reinterpret_cast<void**>(&w.d_pub), w.h_pub, 0));
-    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_iters), 64 * sizeof(int), hipHostMallocDefault));
-    HIPCHECK(hipHostMalloc(reinterpret_cast<void**>(&w.h_scal), SC_COUNT * 64 * sizeof(double),
-                           hipHostMallocDefault));
+    const size_t bytes = carve_work(c, C, w, nullptr);
+    carve_work(c, C, w, c->dalloc<char>(static_cast<int64_t>(bytes)));
+    alloc_host_bufs(w.own);
+    use_host_bufs(w, w.own);
     c->works[C] = std::move(wp);
     if (amg(c) && !c->dl.empty()) {
         if (c->o.precision == MSP_MIXED_BF16) autotune_level_splits<Bf16>(c, w);
@@ -873,7 +919,10 @@ struct SolvePlan {
     double *rr, *rz, *pq, *rho, *alpha, *beta, *thr, *rnorm, *bn2;
     int *active, *iters, *flags;
 
-    SolvePlan(msp_ctx* c_, int m_, hipStream_t st_) : c(c_), st(st_), m(m_) {
+    // noalloc: the workspace is carved from the device's static scratch array
+    // (no allocation, no autotuning: the lane-group splits tuned by earlier
+    // solves of this context and column count, else the defaults)
+    SolvePlan(msp_ctx* c_, int m_, hipStream_t st_, Work* noalloc = nullptr) : c(c_), st(st_), m(m_) {
         if (!c->on_device) throw Error(MSP_ERR_ARG, "context was set up without a device");
         if (m <= 0) throw Error(MSP_ERR_ARG, "need m > 0");
         HIPCHECK(hipSetDevice(c->device));
@@ -881,7 +930,23 @@ struct SolvePlan {
         const int ncol = S * m;
         if (ncol > 64) throw Error(MSP_ERR_UNSUPPORTED, "2^s * m must not exceed 64");
         C = next_pow2(ncol);
-        w = &work(c, C);
+        if (noalloc) {
+            char* base = static_cast<char*>(scratch_address(c->device));
+            if (!base) throw Error(MSP_ERR_HIP, "scratch array not set up on this device");
+            const size_t need = carve_work(c, C, *noalloc, nullptr);
+            if (need > kScratchBytes)
+                throw Error(MSP_ERR_UNSUPPORTED, "the allocation-free solve needs " + std::to_string(need) +
+                                                     " bytes of workspace for this system and column count; the "
+                                                     "scratch array holds " + std::to_string(kScratchBytes));
+            carve_work(c, C, *noalloc, base);
+            use_host_bufs(*noalloc, c->nohb);
+            noalloc->pub_seq = c->nopub_seq;
+            auto it = c->works.find(C);
+            if (it != c->works.end()) noalloc->dense_rows = it->second->dense_rows;
+            w = noalloc;
+        } else {
+            w = &work(c, C);
+        }
         w->m = m;
         nb = c->sym.n_b;
         n = c->sym.n;
@@ -1136,9 +1201,17 @@ struct SolvePlan {
     }
 };
 
-static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipStream_t st, msp_stats* out) {
+static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipStream_t st, msp_stats* out,
+                        Work* noalloc = nullptr) {
     if (!d_b || !d_x) throw Error(MSP_ERR_ARG, "need device arrays");
-    SolvePlan P(c, m, st);
+    SolvePlan P(c, m, st, noalloc);
+    struct SeqKeep {   // the published-flag sequence of the context's shared host buffers
+        msp_ctx* c;
+        Work* w;
+        ~SeqKeep() {
+            if (w) c->nopub_seq = w->pub_seq;
+        }
+    } keep{c, noalloc};
     const auto t0 = std::chrono::steady_clock::now();
     P.begin(d_b);
     P.read_flags();
@@ -1227,6 +1300,7 @@ static void check_opts(const msp_opts* o) {
     if (o->lrc_k > 0 && o->pc == MSP_PC_NONE) throw Error(MSP_ERR_ARG, "low-rank corrections need a preconditioner");
     if (o->lrc_k > 16) throw Error(MSP_ERR_UNSUPPORTED, "low-rank correction rank above 16");
     if (o->coarse64 != 0 && o->coarse64 != 1) throw Error(MSP_ERR_ARG, "coarse64 must be 0 or 1");
+    if (o->max_levels > msp::kMaxLevels) throw Error(MSP_ERR_UNSUPPORTED, "more than 32 levels");
 }
 
 // Host part of the setup: blocks, validation, hierarchy (no HIP calls).
@@ -1257,6 +1331,8 @@ static void setup_device(msp_ctx* c) {
     HIPCHECK(hipGetDeviceCount(&ndev));
     if (c->o.device >= ndev) throw Error(MSP_ERR_ARG, "device ordinal out of range");
     msp::upload_all(c);
+    HIPCHECK(msp::scratch_init());   // the allocation-free solve's workspace on this device
+    msp::alloc_host_bufs(c->nohb);
     if (c->lrc_k > 0) msp::build_lrc(c);
     HIPCHECK(hipDeviceSynchronize());
 }
@@ -1469,6 +1545,17 @@ int msp_solve_device(msp_ctx* c, int32_t m, const double* d_b, double* d_x, void
     return guarded([&]() -> int {
         if (!c) throw Error(MSP_ERR_ARG, "null context");
         return msp::solve_device(c, m, d_b, d_x, static_cast<hipStream_t>(hip_stream), st);
+    });
+}
+
+int msp_solve_device_noalloc(msp_ctx* c, int32_t m, const double* d_b, double* d_x, void* hip_stream,
+                             msp_stats* st) {
+    return guarded([&]() -> int {
+        if (!c) throw Error(MSP_ERR_ARG, "null context");
+        for (char on : c->tm.on)
+            if (on) throw Error(MSP_ERR_ARG, "per-kernel timers must be off for the allocation-free solve");
+        msp::Work w;
+        return msp::solve_device(c, m, d_b, d_x, static_cast<hipStream_t>(hip_stream), st, &w);
     });
 }
 

@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 
 #include "device.hpp"
@@ -731,6 +732,41 @@ __global__ void k_gather_flags(int nsys, int* const* __restrict__ ptrs, int* __r
         out[2 * i] = ptrs[i][0];
         out[2 * i + 1] = ptrs[i][1];
     }
+}
+
+// ------------------------------------------------------------------ allocation-free workspace
+// The workspace of msp_solve_device_noalloc lives in this file-scope device
+// array: every GPU the library runs on holds its own copy until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol); it takes the device address from
+// hipGetSymbolAddress, looked up once per device with that device current.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+hipError_t scratch_init() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+    return hipSuccess;
+}
+
+void* scratch_address(int device) {
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 // ------------------------------------------------------------------ host launchers

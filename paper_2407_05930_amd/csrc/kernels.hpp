@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <cstddef>
 #include <cstdint>
 
 namespace msp {
@@ -105,6 +106,13 @@ template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v);
 template <typename TO, typename TI>
 hipError_t launch_cast(hipStream_t st, int64_t len, const TI* a, TO* b);
+
+// Device scratch of the allocation-free solve: a file-scope device array of
+// kScratchBytes per GPU.  scratch_init looks up its address on the current
+// device (once per device); scratch_address returns it (nullptr before).
+constexpr size_t kScratchBytes = size_t(128) << 20;
+hipError_t scratch_init();
+void* scratch_address(int device);
 
 // flags[0..1] to fine-grained host memory pub (device-visible pointer), then pub[2] = seq
 hipError_t launch_publish_flags(hipStream_t st, const int* flags, int* pub, int seq);
