@@ -31,6 +31,7 @@ SOURCES = [
     ("api.cpp", []),
     ("fv.cpp", []),
     ("kernels.hip", DEVICE),
+    ("sell.hip", DEVICE),
     ("pcg.hip", DEVICE),
 ]
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -32,6 +33,18 @@ static thread_local std::string g_last_error;
                         std::string(#expr) + ": " + hipGetErrorString(e_));                            \
     } while (0)
 
+// Sliced-ELL form of a matrix for one row split G (sell.hip).
+struct DevSell {
+    int G = 0;               // 0 = not built
+    int64_t slots = 0;
+    int64_t* off = nullptr;  // first slot of each slice of 64 virtual rows
+    int32_t* wid = nullptr;  // width of each slice
+    int32_t* ci = nullptr;   // column per slot, -1 for padding
+    double* v64 = nullptr;   // values per slot (vs interleaved sets)
+    float* v32 = nullptr;
+};
+constexpr int kSellForms = 5;   // G = 1, 2, 4, 8, 16
+
 // Device CSR: 32-bit row pointers and columns, FP64 and (mixed modes) FP32 values.
 struct DevCsr {
     int64_t nr = 0, nc = 0, nnz = 0;
@@ -39,6 +52,11 @@ struct DevCsr {
     int vs = 1;              // interleaved value sets (one per subsystem), entry k of set a at k * vs + a
     int tuned[3][7] = {};    // autotuned split by [multivector type: FP64, FP32, BF16][log2 C]; 0 = not tuned
     bool wide[3][7] = {};    // autotuned 16-byte lanes of the one-group kernel, same indexing
+    int sg[3][7] = {};       // autotuned: 0 = CSR kernels, else the row split G of the sliced-ELL kernel
+    const Csr* hpat = nullptr;                  // host pattern and values (V-cycle matrices: the sliced
+    const std::vector<double>* hval = nullptr;  // forms are built from them when the autotuner needs them)
+    bool f32 = false;                           // FP32 values on the device (mixed modes)
+    DevSell sell[kSellForms];
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
     double* v64 = nullptr;
@@ -151,6 +169,7 @@ struct msp_ctx {
     msp::DevOuter dsig;       // outer diagonal of the base rows (compact: interface rows only)
     msp::DevOuter dsig1;      // pc = AMGR_SUB: the same at level 1 (the interface's coarse numbers)
     msp::DevCsr dAinn, dGf, dGfT;
+    int op_sell[7] = {-1, -1, -1, -1, -1, -1, -1};   // operator kernel by log2 C: -1 not tuned, 0 CSR, 1 sliced
     std::vector<msp::DevLevel> dl;
     double* d_cinv = nullptr;
     float* d_cinv32 = nullptr;    // per-subsystem coarsest inverses in FP32 (mixed modes), rows padded to 4
@@ -375,12 +394,25 @@ static int log2i(int C) {
     return l;
 }
 
-// One SpMM launch with an explicit lane-group split (1 = one group per row);
-// FP32 products use the bfloat16 values when the matrix carries them.
+static int log2i(int C);
+
+// One SpMM launch with an explicit lane-group split (1 = one group per row),
+// or on the sliced-ELL form with row split sg > 0; FP32 products use the
+// bfloat16 values when the matrix carries them.
 template <typename T>
 static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, bool wide, const T* X, T* Y, const T* Z,
-                        acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m) {
+                        acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m, int sg = 0) {
     using TV = typename ValOf<T>::type;
+    if (sg > 0) {
+        const DevSell& F = M.sell[log2i(sg)];
+        if (F.G != sg) throw Error(MSP_ERR_ARG, "sliced form not built");
+        const TV* va;
+        if constexpr (std::is_same<TV, double>::value) va = F.v64;
+        else va = F.v32;
+        HIPCHECK((launch_sell<T, TV>(st, C, sg, M.nr, F.off, F.wid, F.ci, va, X, Y, Z, alpha, beta, sigma, S, m, M.vs,
+                                     wide)));
+        return;
+    }
     if constexpr (std::is_same<T, float>::value) {
         if (M.v16) {
             if (split > 1)
@@ -408,12 +440,17 @@ static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, c
     const int tuned = M.tuned[tslot<T>()][log2i(C)];
     const int split = tuned ? tuned : M.split;
     const bool wide = tuned && M.wide[tslot<T>()][log2i(C)];
-    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, wide, X, Y, Z, alpha, beta, od, S, m); },
+    const int sg = tuned ? M.sg[tslot<T>()][log2i(C)] : 0;
+    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, wide, X, Y, Z, alpha, beta, od, S, m, sg); },
           [&] {
               // the instance spmm_launch picks (bfloat16 values only for FP32 products of the BF16-G variant)
               const char* tv = (std::is_same<T, float>::value && M.v16) ? "Bf16" : tname<typename ValOf<T>::type>();
               const std::string ty = std::string(tname<T>()) + ", " + tv + ", " + std::to_string(C);
               const bool sets = M.vs > 1;
+              const bool w = wide && !sets && spmm_has_wide(C, static_cast<int>(sizeof(T)));
+              if (sg > 0)
+                  return "k_sell<" + ty + ", " + std::to_string(sg) + ", " + (sets ? "true" : "false") + ", " +
+                         (w ? "true" : "false") + ">";
               if (split > 1)
                   return "k_spmm_split<" + ty + ", " + std::to_string(split) + ", " + (sets ? "true" : "false") + ">";
               return "k_spmm<" + ty + ", " + (sets ? "true" : "false") + ", " + (wide && !sets ? "true" : "false") +
@@ -459,50 +496,190 @@ static int env_int(const char* name) {
     return (end && *end == 0 && x >= 0 && x < (1 << 20)) ? static_cast<int>(x) : -1;
 }
 
-// Autotuner: for every V-cycle matrix, time the candidate lane-group splits
-// (1, 2, 4, ... up to the block's capacity and about half the mean row
-// length) on this column count and keep the fastest.  Runs once per context
-// and column count, on scratch multivectors cleared first.
+// Sliced-ELL form of M with rows split into G virtual rows (layout in
+// sell.hip), built from the host pattern and values and uploaded with the
+// value type the context's V-cycle uses.
+static void build_sell(msp_ctx* c, DevCsr& M, int G) {
+    DevSell& F = M.sell[log2i(G)];
+    if (F.G == G) return;
+    if (!M.hpat || !M.hval) throw Error(MSP_ERR_ARG, "no host copy of the matrix for the sliced form");
+    const Csr& P = *M.hpat;
+    const std::vector<double>& V = *M.hval;
+    const int vs = M.vs;
+    const int64_t nv = P.nr * G, ns = (nv + 63) / 64;
+    std::vector<int64_t> off(static_cast<size_t>(ns) + 1, 0);
+    std::vector<int32_t> wid(static_cast<size_t>(ns), 0);
+    for (int64_t v = 0; v < nv; ++v) {
+        const int64_t r = v / G, g = v % G;
+        const int64_t len = P.rp[r + 1] - P.rp[r];
+        const int64_t cnt = len > g ? (len - g + G - 1) / G : 0;
+        wid[v / 64] = std::max(wid[v / 64], static_cast<int32_t>(cnt));
+    }
+    for (int64_t q = 0; q < ns; ++q) off[q + 1] = off[q] + 64 * static_cast<int64_t>(wid[q]);
+    const int64_t slots = off[ns];
+    std::vector<int32_t> ci(static_cast<size_t>(slots), -1);
+    std::vector<double> val(static_cast<size_t>(slots) * vs, 0.0);
+    for (int64_t r = 0; r < P.nr; ++r)
+        for (int64_t j = 0; j < P.rp[r + 1] - P.rp[r]; ++j) {
+            const int64_t v = r * G + j % G, k = j / G;
+            const int64_t q = off[v / 64] + 64 * k + v % 64;
+            ci[q] = P.ci[P.rp[r] + j];
+            for (int a = 0; a < vs; ++a) val[q * vs + a] = V[(P.rp[r] + j) * vs + a];
+        }
+    F.off = c->upload(off.data(), ns + 1);
+    F.wid = c->upload(wid.data(), ns);
+    F.ci = c->upload(ci.data(), slots);
+    if (M.f32) {
+        std::vector<float> f(val.begin(), val.end());
+        F.v32 = c->upload(f.data(), static_cast<int64_t>(f.size()));
+    } else {
+        F.v64 = c->upload(val.data(), static_cast<int64_t>(val.size()));
+    }
+    F.slots = slots;
+    F.G = G;
+}
+
+static void free_sell(msp_ctx* c, DevSell& F) {
+    for (void* q : {static_cast<void*>(F.off), static_cast<void*>(F.wid), static_cast<void*>(F.ci),
+                    static_cast<void*>(F.v64), static_cast<void*>(F.v32)})
+        if (q) c->dfree(q);
+    F = DevSell();
+}
+
+
+// Key of one tuned choice in a tuning file: precision, preconditioner, base
+// rows, level, matrix, multivector type and column count.
+static std::string tune_key(const msp_ctx* c, size_t l, const char* what, int ts, int C) {
+    return "p" + std::to_string(c->o.precision) + " pc" + std::to_string(c->o.pc) + " nb" +
+           std::to_string(c->sym.n_b) + " L" + std::to_string(l) + " " + what + " t" + std::to_string(ts) + " c" +
+           std::to_string(C);
+}
+
+// Autotuner: for every V-cycle matrix and this column count, time the
+// candidate kernels -- the CSR kernels with 1, 2, 4, ... lane groups per row
+// (up to the block's capacity and about half the mean row length), their
+// 16-byte-lane form, and the sliced-ELL kernel with rows split G = 1, 2, 4,
+// ... ways -- and keep the fastest.  Each candidate is timed as the solve
+// sees it: the memory-side cache is first cleared by writing a 512 MB block,
+// the input multivector is rewritten (in the solve it was just produced),
+// then the product alone runs between two events; the median of three such
+// runs counts.  Runs once per context and column count.
 // Fixed variants instead of timings (every variant computes the same
 // product; tests use these to cover each one): MSP_SPMM_SPLIT=g (a power of
 // two; clamped to what a block holds), MSP_SPMM_WIDE=1 (16-byte lanes where a
-// matrix has them), MSP_DENSE_ROWS=R (1, 2, 4 or 8 rows per wavefront).
+// matrix has them), MSP_SPMM_SELL=G (the sliced-ELL kernel with the largest
+// row split <= G that fits; 0 = the CSR kernels), MSP_DENSE_ROWS=R (1, 2, 4
+// or 8 rows per wavefront).  MSP_TUNE_SAVE=path appends the choices to a
+// file, MSP_TUNE_LOAD=path takes them from one (a profiler run then launches
+// the kernels a timed run chose).
 template <typename T>
 static void autotune_level_splits(msp_ctx* c, Work& w) {
     hipStream_t st = nullptr;
     const int C = w.C;
-    const int vw = lane_width(static_cast<int>(sizeof(T)));
+    const int ts = tslot<T>(), lc = log2i(C);
+    const int eb = static_cast<int>(sizeof(T));
+    const int vw = lane_width(eb);
     const int lpr = C >= vw ? C / vw : 1;   // lanes per row of Lanes<T, C>
     const int S = 1 << c->sym.s;
     const int mt = std::max(1, C / S);   // columns per subsystem assumed for matrices with value sets
     const char* logv = std::getenv("MSP_AUTOTUNE_LOG");   // set (non-empty, not "0"): timings to stderr
     const bool log = logv && *logv && std::strcmp(logv, "0") != 0;
+    static const char* const names[6] = {"A", "M", "R", "P", "G", "GT"};
+    auto mats = [](DevLevel& L) { return std::array<DevCsr*, 6>{&L.A, &L.M, &L.R, &L.P, &L.G, &L.GT}; };
+    auto sell_ok = [&](const DevCsr* M, int G, bool wide) {
+        return M->hpat && !M->v16 && sell_fits(C, eb, G, wide && M->vs == 1);
+    };
     const int force_split = env_int("MSP_SPMM_SPLIT");
     const int force_wide = env_int("MSP_SPMM_WIDE");
+    const int force_sell = env_int("MSP_SPMM_SELL");
     const int force_rows = env_int("MSP_DENSE_ROWS");
-    if (force_split > 0 || force_wide >= 0 || force_rows > 0) {
+    if (force_split > 0 || force_wide >= 0 || force_sell >= 0 || force_rows > 0) {
         int g = 1;
         while (force_split > 0 && g * 2 <= force_split && g * 2 * lpr <= 256) g *= 2;
         for (auto& L : c->dl)
-            for (DevCsr* M : {&L.A, &L.M, &L.R, &L.P, &L.G, &L.GT}) {
-                M->tuned[tslot<T>()][log2i(C)] = g;
-                M->wide[tslot<T>()][log2i(C)] =
-                    g == 1 && force_wide == 1 && M->vs == 1 && spmm_has_wide(C, static_cast<int>(sizeof(T)));
+            for (DevCsr* M : mats(L)) {
+                M->tuned[ts][lc] = g;
+                const bool wd = force_wide == 1 && M->vs == 1 && spmm_has_wide(C, eb);
+                M->wide[ts][lc] = (g == 1 || force_sell > 0) && wd;
+                int G = 0;
+                if (force_sell > 0 && M->nnz > 0) {
+                    G = 1;
+                    while (G * 2 <= force_sell && sell_ok(M, G * 2, wd)) G *= 2;
+                    if (!sell_ok(M, G, wd)) G = 0;
+                    if (G) build_sell(c, *M, G);
+                }
+                M->sg[ts][lc] = G;
             }
         int R = 1;
         while (force_rows > 0 && R * 2 <= force_rows && R * 2 <= 8) R *= 2;
         w.dense_rows = force_rows > 0 ? R : 8;
         return;
     }
+    // choices from a tuning file, when it has every one of them
+    if (const char* path = std::getenv("MSP_TUNE_LOAD")) {
+        std::map<std::string, std::array<int, 3>> tab;
+        if (std::FILE* f = std::fopen(path, "r")) {
+            char line[512];
+            while (std::fgets(line, sizeof(line), f)) {
+                std::string ln(line);
+                const size_t eq = ln.find('=');
+                if (eq == std::string::npos) continue;
+                std::array<int, 3> v{0, 0, 0};
+                if (std::sscanf(ln.c_str() + eq + 1, "%d %d %d", &v[0], &v[1], &v[2]) >= 1) tab[ln.substr(0, eq)] = v;
+            }
+            std::fclose(f);
+        }
+        bool all = true;
+        for (size_t l = 0; l < c->dl.size() && all; ++l) {
+            auto ms = mats(c->dl[l]);
+            for (int j = 0; j < 6 && all; ++j)
+                if (ms[j]->nnz) all = tab.count(tune_key(c, l, names[j], ts, C)) > 0;
+        }
+        const std::string dk = tune_key(c, c->dl.size(), "dense", ts, C);
+        if (c->sub) all = all && tab.count(dk);
+        if (all) {
+            for (size_t l = 0; l < c->dl.size(); ++l) {
+                auto ms = mats(c->dl[l]);
+                for (int j = 0; j < 6; ++j) {
+                    if (!ms[j]->nnz) continue;
+                    const auto& v = tab[tune_key(c, l, names[j], ts, C)];
+                    ms[j]->tuned[ts][lc] = std::max(1, v[0]);
+                    ms[j]->wide[ts][lc] = v[1] != 0;
+                    ms[j]->sg[ts][lc] = v[2];
+                    if (v[2] > 0) build_sell(c, *ms[j], v[2]);
+                }
+            }
+            if (c->sub) w.dense_rows = tab[dk][0];
+            return;
+        }
+    }
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
+    const int64_t flush_n = int64_t(1) << 27;   // 512 MB of int: more than the memory-side cache
+    int* flush = c->dalloc<int>(flush_n);
     for (size_t l = 0; l < c->hier.lev.size(); ++l) {
         const int64_t n = c->hier.lev[l].A.nr;
         HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vy[l]), T{}));
         HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vs[l]), T{}));
         HIPCHECK(launch_fill<T>(st, n * C, static_cast<T*>(w.vr[l]), T{}));
     }
+    // median of three runs of launch(), each after the cache is cleared and X rewritten
+    auto time_cold = [&](const T* X, int64_t nx, auto&& launch) {
+        float t[3];
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHECK(launch_fill<int>(st, flush_n, flush, rep));
+            HIPCHECK(launch_fill<T>(st, nx * C, const_cast<T*>(X), T{}));
+            HIPCHECK(hipEventRecord(e0, st));
+            launch();
+            HIPCHECK(hipEventRecord(e1, st));
+            HIPCHECK(hipEventSynchronize(e1));
+            HIPCHECK(hipEventElapsedTime(&t[rep], e0, e1));
+        }
+        std::sort(t, t + 3);
+        return t[1];
+    };
+    std::string saved;
     for (size_t l = 0; l < c->dl.size(); ++l) {
         DevLevel& L = c->dl[l];
         struct Job { DevCsr* M; const T* X; T* Y; };
@@ -511,49 +688,57 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
         T* vt = w.vt[l] ? static_cast<T*>(w.vt[l]) : vr;
         Job jobs[6] = {{&L.A, vs, vr}, {&L.M, vr, vs}, {&L.R, vr, static_cast<T*>(w.vy[l + 1])},
                        {&L.P, static_cast<T*>(w.vs[l + 1]), vs}, {&L.G, vr, vt}, {&L.GT, vt, vs}};
-        static const char* const names[6] = {"A", "M", "R", "P", "G", "GT"};
         for (int j = 0; j < 6; ++j) {
             Job& jb = jobs[j];
             if (jb.M->nnz == 0) continue;
             const double avg = jb.M->nr ? static_cast<double>(jb.M->nnz) / static_cast<double>(jb.M->nr) : 0.0;
-            int best = 1;
-            bool best_w = false;
-            float best_ms = 1e30f;
-            // candidates (split g, wide lanes w): 16-byte lanes only for one group per row
-            // and one value set, where they differ from the default lanes
-            std::vector<std::pair<int, bool>> cand;
+            struct Cand { int g; bool wide; int sg; };
+            std::vector<Cand> cand;
             for (int g = 1; g <= 64 && g * lpr <= 256; g *= 2) {   // 256 threads per block
                 if (g > 1 && g > std::max(1.0, avg / 2.0)) break;
-                cand.emplace_back(g, false);
-                if (g == 1 && jb.M->vs == 1 && spmm_has_wide(C, static_cast<int>(sizeof(T))))
-                    cand.emplace_back(1, true);
+                cand.push_back({g, false, 0});
+                if (g == 1 && jb.M->vs == 1 && spmm_has_wide(C, eb)) cand.push_back({1, true, 0});
             }
-            for (const auto& gw : cand) {
-                const int g = gw.first;
-                const bool wv = gw.second;
-                spmm_launch<T>(st, C, *jb.M, g, wv, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0),
-                               OuterDiag{nullptr, nullptr}, S, mt);
-                HIPCHECK(hipEventRecord(e0, st));
-                for (int rep = 0; rep < 3; ++rep)
-                    spmm_launch<T>(st, C, *jb.M, g, wv, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0),
-                                   OuterDiag{nullptr, nullptr}, S, mt);
-                HIPCHECK(hipEventRecord(e1, st));
-                HIPCHECK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+            for (int G = 1; G <= 16; G *= 2) {
+                if (G > 1 && G > std::max(1.0, avg / 2.0)) break;
+                if (sell_ok(jb.M, G, false)) cand.push_back({1, false, G});
+                if (jb.M->vs == 1 && spmm_has_wide(C, eb) && sell_ok(jb.M, G, true)) cand.push_back({1, true, G});
+            }
+            Cand best = cand[0];
+            float best_ms = 1e30f;
+            for (const Cand& cd : cand) {
+                if (cd.sg > 0) build_sell(c, *jb.M, cd.sg);
+                const int64_t nx = jb.M->nc;
+                auto run = [&] {
+                    spmm_launch<T>(st, C, *jb.M, cd.g, cd.wide, jb.X, jb.Y, nullptr, acc_t<T>(1), acc_t<T>(0),
+                                   OuterDiag{nullptr, nullptr}, S, mt, cd.sg);
+                };
+                run();   // first launch of this kernel shape (code load) outside the timing
+                const float ms = time_cold(jb.X, nx, run);
                 if (log)
                     std::fprintf(stderr, "msp autotune: C=%d elem=%d level %zu %s (%lld rows, %.1f nnz/row, %d sets) "
-                                 "split %d%s: %.2f us\n", C, static_cast<int>(sizeof(T)), l, names[j],
-                                 static_cast<long long>(jb.M->nr), avg, jb.M->vs, g, wv ? " wide" : "",
-                                 1000.0 * ms / 3);
+                                 "%s %d%s: %.2f us\n", C, eb, l, names[j], static_cast<long long>(jb.M->nr), avg,
+                                 jb.M->vs, cd.sg ? "sliced G" : "split", cd.sg ? cd.sg : cd.g,
+                                 cd.wide ? " wide" : "", 1000.0 * ms);
                 if (ms < best_ms) {
                     best_ms = ms;
-                    best = g;
-                    best_w = wv;
+                    best = cd;
                 }
             }
-            jb.M->tuned[tslot<T>()][log2i(C)] = best;
-            jb.M->wide[tslot<T>()][log2i(C)] = best_w;
+            jb.M->tuned[ts][lc] = best.g;
+            jb.M->wide[ts][lc] = best.wide;
+            jb.M->sg[ts][lc] = best.sg;
+            saved += tune_key(c, l, names[j], ts, C) + "=" + std::to_string(best.g) + " " +
+                     std::to_string(best.wide ? 1 : 0) + " " + std::to_string(best.sg) + "\n";
+            // drop the sliced forms no column count uses
+            for (int q = 0; q < kSellForms; ++q) {
+                DevSell& F = jb.M->sell[q];
+                if (!F.G) continue;
+                bool used = false;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 7; ++b) used |= jb.M->tuned[a][b] && jb.M->sg[a][b] == F.G;
+                if (!used) free_sell(c, F);
+            }
         }
     }
     // rows per wavefront of the per-subsystem coarsest solves
@@ -563,27 +748,109 @@ static void autotune_level_splits(msp_ctx* c, Work& w) {
         T* s = static_cast<T*>(w.vs[Lc]);
         float best_ms = 1e30f;
         for (int R = 1; R <= dense_sets_rows_max(mt); R *= 2) {
-            auto run = [&] {
-                dense_sets<T>(c, w, st, mt, y, s, R);
-            };
+            auto run = [&] { dense_sets<T>(c, w, st, mt, y, s, R); };
             run();
-            HIPCHECK(hipEventRecord(e0, st));
-            for (int rep = 0; rep < 3; ++rep) run();
-            HIPCHECK(hipEventRecord(e1, st));
-            HIPCHECK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+            const float ms = time_cold(y, c->nL, run);
             if (log)
                 std::fprintf(stderr, "msp autotune: C=%d elem=%d coarsest solves, %d rows per wavefront: %.2f us\n", C,
-                             static_cast<int>(sizeof(T)), R, 1000.0 * ms / 3);
+                             eb, R, 1000.0 * ms);
             if (ms < best_ms) {
                 best_ms = ms;
                 w.dense_rows = R;
             }
         }
+        saved += tune_key(c, Lc, "dense", ts, C) + "=" + std::to_string(w.dense_rows) + "\n";
     }
+    HIPCHECK(hipStreamSynchronize(st));
+    c->dfree(flush);
     HIPCHECK(hipEventDestroy(e0));
     HIPCHECK(hipEventDestroy(e1));
+    if (const char* path = std::getenv("MSP_TUNE_SAVE")) {
+        if (std::FILE* f = std::fopen(path, "a")) {
+            std::fputs(saved.c_str(), f);
+            std::fclose(f);
+        }
+    }
+}
+
+// The operator kernel (A_inn + outer diagonal, FP64) on its CSR or its
+// sliced-ELL form: both timed once per column count in the same cold-cache
+// conditions as the V-cycle products, the faster kept.  MSP_OP_SELL=0/1
+// fixes the choice; MSP_TUNE_LOAD / MSP_TUNE_SAVE as for the V-cycle.
+static void autotune_operator(msp_ctx* c, Work& w) {
+    const int C = w.C, lc = log2i(C);
+    const int S = 1 << c->sym.s;
+    const int64_t nb = c->sym.n_b;
+    const std::string key = tune_key(c, 0, "op", 0, C);
+    int choice = env_int("MSP_OP_SELL");
+    if (choice < 0) {
+        if (const char* path = std::getenv("MSP_TUNE_LOAD")) {
+            if (std::FILE* f = std::fopen(path, "r")) {
+                char line[512];
+                while (std::fgets(line, sizeof(line), f)) {
+                    const std::string ln(line);
+                    const size_t eq = ln.find('=');
+                    if (eq != std::string::npos && ln.substr(0, eq) == key) choice = std::atoi(ln.c_str() + eq + 1);
+                }
+                std::fclose(f);
+            }
+        }
+    }
+    if (choice >= 0) {
+        if (choice > 0) build_sell(c, c->dAinn, 1);
+        c->op_sell[lc] = choice > 0 ? 1 : 0;
+        return;
+    }
+    build_sell(c, c->dAinn, 1);
+    hipStream_t st = nullptr;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    const int64_t flush_n = int64_t(1) << 27;   // 512 MB of int: more than the memory-side cache
+    int* flush = c->dalloc<int>(flush_n);
+    const DevSell& F = c->dAinn.sell[0];
+    float best = 1e30f;
+    int pick = 0;
+    for (int v = 0; v < 2; ++v) {
+        const SellRef sl = v ? SellRef{F.off, F.wid, F.ci, F.v64} : SellRef{nullptr, nullptr, nullptr, nullptr};
+        int grid = 0;
+        HIPCHECK(op_dot_grid(C, v == 1, nb, &grid));
+        auto run = [&] {
+            HIPCHECK(launch_op_dot(st, C, grid, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, sl, c->dsig.d, S, 1, w.p,
+                                   w.q, w.pp1));
+        };
+        HIPCHECK(launch_fill<double>(st, nb * C, w.p, 0.0));
+        run();
+        float t[3];
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHECK(launch_fill<int>(st, flush_n, flush, rep));
+            HIPCHECK(launch_fill<double>(st, nb * C, w.p, 0.0));
+            HIPCHECK(hipEventRecord(e0, st));
+            run();
+            HIPCHECK(hipEventRecord(e1, st));
+            HIPCHECK(hipEventSynchronize(e1));
+            HIPCHECK(hipEventElapsedTime(&t[rep], e0, e1));
+        }
+        std::sort(t, t + 3);
+        const char* logv = std::getenv("MSP_AUTOTUNE_LOG");
+        if (logv && *logv && std::strcmp(logv, "0") != 0)
+            std::fprintf(stderr, "msp autotune: C=%d operator %s: %.2f us\n", C, v ? "sliced" : "CSR", 1000.0 * t[1]);
+        if (t[1] < best) {
+            best = t[1];
+            pick = v;
+        }
+    }
+    c->op_sell[lc] = pick;
+    HIPCHECK(hipStreamSynchronize(st));
+    c->dfree(flush);
+    HIPCHECK(hipEventDestroy(e0));
+    HIPCHECK(hipEventDestroy(e1));
+    if (const char* path = std::getenv("MSP_TUNE_SAVE")) {
+        if (std::FILE* f = std::fopen(path, "a")) {
+            std::fprintf(f, "%s=%d\n", key.c_str(), pick);
+            std::fclose(f);
+        }
+    }
 }
 
 // bytes per element of the V-cycle multivectors
@@ -669,6 +936,7 @@ static Work& work(msp_ctx* c, int C) {
     alloc_host_bufs(w.own);
     use_host_bufs(w, w.own);
     c->works[C] = std::move(wp);
+    autotune_operator(c, w);
     if (amg(c) && !c->dl.empty()) {
         if (c->o.precision == MSP_MIXED_BF16) autotune_level_splits<Bf16>(c, w);
         else if (mixed(c)) autotune_level_splits<float>(c, w);
@@ -819,6 +1087,8 @@ static void upload_all(msp_ctx* c) {
     c->d_img = c->upload(c->sym.img.data(), static_cast<int64_t>(c->sym.img.size()));
     c->dsig = upload_outer(c, c->sym.sigma, c->sym.n_b, 1 << c->sym.s);
     c->dAinn = upload_csr(c, c->sym.Ainn, false);
+    c->dAinn.hpat = &c->sym.Ainn;   // the operator's sliced form is built from these (FP64 values)
+    c->dAinn.hval = &c->sym.Ainn.v;
     if (amg(c)) {
         const int S = 1 << c->sym.s;
         c->dl.resize(c->hier.lev.size() - 1);
@@ -827,6 +1097,11 @@ static void upload_all(msp_ctx* c) {
             DevLevel& D = c->dl[l];
             D.n = H.A.nr;
             D.omega = H.omega;
+            auto keep_host = [&](DevCsr& Dm, const Csr& pat, const std::vector<double>& val) {
+                Dm.hpat = &pat;
+                Dm.hval = &val;
+                Dm.f32 = f32;
+            };
             if (c->sub && l > 0) {
                 // one value set per subsystem on the shared patterns; the smoother is
                 // explicit (omega_a G_a^T G_a) in every precision.  A_1,a = A_1 + diag(sigma_a)
@@ -834,6 +1109,7 @@ static void upload_all(msp_ctx* c) {
                 // applies the outer diagonal like the reduction level does.
                 if (l == 1) {
                     D.A = upload_csr(c, H.A, f32);
+                    keep_host(D.A, H.A, H.A.v);
                     std::vector<double> s1(static_cast<size_t>(H.A.nr) * S, 0.0);
                     int64_t j = 0;
                     const HostLevel& L0 = c->hier.lev[0];
@@ -847,15 +1123,22 @@ static void upload_all(msp_ctx* c) {
                     c->dsig1 = upload_outer(c, s1, H.A.nr, S);
                 } else {
                     D.A = upload_sets(c, H.A, c->subv.A[l], S, f32);
+                    keep_host(D.A, H.A, c->subv.A[l]);
                 }
                 D.P = upload_sets(c, H.P, c->subv.P[l], S, f32);
                 D.R = upload_sets(c, H.R, c->subv.R[l], S, f32);
                 D.M = upload_sets(c, H.M, c->subv.M[l], S, f32);
+                keep_host(D.P, H.P, c->subv.P[l]);
+                keep_host(D.R, H.R, c->subv.R[l]);
+                keep_host(D.M, H.M, c->subv.M[l]);
                 continue;
             }
             D.A = upload_csr(c, H.A, f32);
             D.P = upload_csr(c, H.P, f32);
             D.R = upload_csr(c, H.R, f32);
+            keep_host(D.A, H.A, H.A.v);
+            keep_host(D.P, H.P, H.P.v);
+            keep_host(D.R, H.R, H.R.v);
             if (c->o.precision == MSP_MIXED_FP32_BF16G) {
                 // the smoother is kept factored, G^T (G r) with bfloat16 factors, so it stays SPD;
                 // its damping is recomputed for the rounded factors (rounding can raise
@@ -868,6 +1151,7 @@ static void upload_all(msp_ctx* c) {
                 D.omega = damping(H.A, Gr, GTr, c->o.seed);
             } else {
                 D.M = upload_csr(c, H.M, f32);
+                keep_host(D.M, H.M, H.M.v);
             }
         }
         c->nL = c->hier.lev.back().A.nr;
@@ -967,7 +1251,7 @@ struct SolvePlan {
             nbz = w->grid_z;
             return;
         }
-        HIPCHECK(op_dot_grid(C, nb, &nbo));
+        HIPCHECK(op_dot_grid(C, op_sliced(), nb, &nbo));
         if (c->U16) HIPCHECK(update_dots_grid<Bf16>(C, kl, nb, &nbu));
         else if (c->U32 || !c->d_U) HIPCHECK(update_dots_grid<float>(C, kl, nb, &nbu));
         else HIPCHECK(update_dots_grid<double>(C, kl, nb, &nbu));
@@ -990,6 +1274,13 @@ struct SolvePlan {
     }
 
     double vb() const { return 8.0 * nb * C; }   // bytes of one FP64 multivector pass
+
+    // the operator kernel on the sliced form (chosen by the first solve with this column count)
+    bool op_sliced() const { return c->op_sell[log2i(C)] == 1 && c->dAinn.sell[0].G == 1; }
+    SellRef op_sell_ref() const {
+        const DevSell& F = c->dAinn.sell[0];
+        return op_sliced() ? SellRef{F.off, F.wid, F.ci, F.v64} : SellRef{nullptr, nullptr, nullptr, nullptr};
+    }
     double ubytes() const { return c->U16 ? 2.0 : (c->U32 ? 4.0 : 8.0); }   // bytes per element of U
 
     // the mixed AMGR mode writes the FP32 V-cycle input in the update kernel
@@ -1111,9 +1402,9 @@ struct SolvePlan {
         Work& W = *w;
         const double opb = spmm_bytes<double>(c->dAinn, C, false, &c->dsig, S);   // p read once, q written once
         timed(c, KD_OP, opb, st, [&] {   // q = Ahat p and <p, q>
-            HIPCHECK(launch_op_dot(st, C, nbo, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, c->dsig.d, S, m, W.p, W.q,
-                                   W.pp1));
-        }, [&] { return "k_op_dot<" + std::to_string(C) + ">"; });
+            HIPCHECK(launch_op_dot(st, C, nbo, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, op_sell_ref(), c->dsig.d, S,
+                                   m, W.p, W.q, W.pp1));
+        }, [&] { return "k_op_dot<" + std::to_string(C) + ", " + (op_sliced() ? "true" : "false") + ">"; });
         HIPCHECK(launch_fin_alpha(st, C, nbo, W.pp1, active, rho, alpha, pq, flags));
         update_dots(true);
         x_pending = true;   // x += alpha p follows with the p update (or in finish)

@@ -37,6 +37,15 @@ struct OuterDiag {
     const double* val;
 };
 
+// Sliced-ELL form of an FP64 matrix with one group per row (the operator):
+// ci == nullptr means the CSR form is used.
+struct SellRef {
+    const int64_t* off;
+    const int32_t* wid;
+    const int32_t* ci;
+    const double* va;
+};
+
 // Columns per lane of an n x C multivector of elem_bytes elements: 16-byte
 // vectors for FP32/FP64; 8-byte vectors (4 columns) for bfloat16, so that a
 // lane's columns stay within one subsystem for m = 4 as they do in FP32.
@@ -58,6 +67,16 @@ template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
                              const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m,
                              OuterDiag sigma, int S);
+// The same product on the sliced-ELL form (sell.hip): rows split into G
+// virtual rows (G = 1, 2, 4, 8, 16), slices of 64 virtual rows with width
+// wid[s] stored column-major from slot off[s] (column -1 = padding), values
+// with vs interleaved sets.  sell_fits: whether G row groups of this lane
+// layout fit in one wavefront.
+bool sell_fits(int C, int elem_bytes, int G, bool wide);
+template <typename T, typename TV>
+hipError_t launch_sell(hipStream_t st, int C, int G, int64_t n, const int64_t* off, const int32_t* wid,
+                       const int32_t* ci, const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta,
+                       OuterDiag sigma, int S, int m, int vs, bool wide = false);
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
                       double* out);

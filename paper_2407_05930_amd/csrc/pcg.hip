@@ -26,11 +26,14 @@ constexpr int kUpdTch = 4;
 
 
 // q = (A_inn + diag-outer) p; partial[b, c] = this block's sum of p[:, c] q[:, c]
-// (sigma.idx must be set: the operator always has the outer diagonal)
-template <int C>
+// (sigma.idx must be set: the operator always has the outer diagonal).
+// SELL: A_inn in the sliced-ELL form of sell.hip with one group per row
+// (sl.off, sl.wid, sl.ci, sl.va): the column indices and values of 8 entries
+// are loaded together, then their 8 gathers, with no row-pointer load.
+template <int C, bool SELL>
 __global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ ci, const double* __restrict__ va,
-                                                   OuterDiag sigma, int S, int m,
+                                                   SellRef sl, OuterDiag sigma, int S, int m,
                                                    const double* __restrict__ p, double* __restrict__ q,
                                                    double* __restrict__ partial) {
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
@@ -46,11 +49,40 @@ __global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __r
         double acc[VW];
 #pragma unroll
         for (int e = 0; e < VW; ++e) acc[e] = 0.0;
-        if constexpr (LPR >= 4)
+        if constexpr (SELL) {
+            const int64_t sidx = row / 64;
+            const int w = sl.wid[sidx];
+            const int64_t q0 = sl.off[sidx] + row % 64;
+            for (int k0 = 0; k0 < w; k0 += 8) {
+                int32_t cc[8];
+                double aa[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool in = k0 + u < w;
+                    cc[u] = in ? sl.ci[q0 + (int64_t)(k0 + u) * 64] : -1;
+                    aa[u] = in ? sl.va[q0 + (int64_t)(k0 + u) * 64] : 0.0;
+                }
+                Pack<double, VW> xs[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (cc[u] >= 0) {
+                        xs[u] = ld<double, VW>(p + (int64_t)cc[u] * C + lane * VW);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) xs[u].e[e] = 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) acc[e] += aa[u] * xs[u].e[e];
+            }
+        } else if constexpr (LPR >= 4) {
             row_accumulate_bcast<double, C, VW, LPR>(rp[row], rp[row + 1], ci, va, p, lane,
                                                      (int)(threadIdx.x % 64) - lane, acc);
-        else
+        } else {
             row_accumulate<double, C, VW>(rp[row], rp[row + 1], 1, ci, va, p, lane, acc);
+        }
         const Pack<double, VW> pr = ld<double, VW>(p + row * C + lane * VW);
         const int32_t sq = sigma.idx[row];   // interface row: its outer diagonal
         Pack<double, VW> out;
@@ -365,8 +397,10 @@ static hipError_t resident_grid(K kernel, size_t lds, int64_t n, int* nb) {
     return hipSuccess;
 }
 
-hipError_t op_dot_grid(int C, int64_t n, int* nb) {
-    MSP_DISPATCH_C(C, { return resident_grid<CC>(k_op_dot<CC>, 0, n, nb); });
+hipError_t op_dot_grid(int C, bool sell, int64_t n, int* nb) {
+    MSP_DISPATCH_C(C, {
+        return sell ? resident_grid<CC>(k_op_dot<CC, true>, 0, n, nb) : resident_grid<CC>(k_op_dot<CC, false>, 0, n, nb);
+    });
     return hipErrorInvalidValue;
 }
 
@@ -405,10 +439,15 @@ template hipError_t zfinish_grid<Bf16, double>(int, bool, bool, int64_t, int*);
 template hipError_t zfinish_grid<Bf16, Bf16>(int, bool, bool, int64_t, int*);
 
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
-                         const double* va, OuterDiag sigma, int S, int m, const double* p, double* q,
+                         const double* va, SellRef sl, OuterDiag sigma, int S, int m, const double* p, double* q,
                          double* partial) {
     MSP_DISPATCH_C(C, {
-        hipLaunchKernelGGL((k_op_dot<CC>), dim3(nb), dim3(kBlock), 0, st, n, rp, ci, va, sigma, S, m, p, q, partial);
+        if (sl.ci)
+            hipLaunchKernelGGL((k_op_dot<CC, true>), dim3(nb), dim3(kBlock), 0, st, n, rp, ci, va, sl, sigma, S, m, p,
+                               q, partial);
+        else
+            hipLaunchKernelGGL((k_op_dot<CC, false>), dim3(nb), dim3(kBlock), 0, st, n, rp, ci, va, sl, sigma, S, m, p,
+                               q, partial);
     });
     return hipGetLastError();
 }

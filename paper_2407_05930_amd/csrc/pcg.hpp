@@ -16,14 +16,15 @@ constexpr int kPcgMaxBlocks = 2048;   // largest grid of the dot-producing kerne
 // once.  The partial arrays they fill have nb rows; the finisher that reads
 // them takes the same nb.  update_dots_grid sizes the updating variant (the
 // initial, non-updating one uses fewer registers and fits the same grid).
-hipError_t op_dot_grid(int C, int64_t n, int* nb);
+hipError_t op_dot_grid(int C, bool sell, int64_t n, int* nb);
 template <typename TU>
 hipError_t update_dots_grid(int C, int k, int64_t n, int* nb);
 template <typename TS, typename TU>
 hipError_t zfinish_grid(int C, bool lrc, bool flex, int64_t n, int* nb);
 
+// sl.ci != nullptr: the operator in its sliced-ELL form (one group per row)
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
-                         const double* va, OuterDiag sigma, int S, int m, const double* p, double* q,
+                         const double* va, SellRef sl, OuterDiag sigma, int S, int m, const double* p, double* q,
                          double* partial);
 hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial, const int* active,
                             const double* rho, double* alpha, double* pq, int* flags);

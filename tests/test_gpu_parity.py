@@ -114,36 +114,84 @@ def test_fp64_per_subsystem_lrc_matches_oracle(shape):
     sv.close()
 
 
-VARIANTS = [dict(MSP_SPMM_SPLIT="1", MSP_SPMM_WIDE="0", MSP_DENSE_ROWS="1"),
-            dict(MSP_SPMM_SPLIT="1", MSP_SPMM_WIDE="1", MSP_DENSE_ROWS="2"),
-            dict(MSP_SPMM_SPLIT="2", MSP_SPMM_WIDE="0", MSP_DENSE_ROWS="4"),
-            dict(MSP_SPMM_SPLIT="4", MSP_SPMM_WIDE="0", MSP_DENSE_ROWS="8"),
-            dict(MSP_SPMM_SPLIT="16", MSP_SPMM_WIDE="0", MSP_DENSE_ROWS="8"),
-            dict(MSP_SPMM_SPLIT="64", MSP_SPMM_WIDE="0", MSP_DENSE_ROWS="8")]
+VARIANTS = [dict(MSP_SPMM_SPLIT="1", MSP_SPMM_WIDE="0", MSP_SPMM_SELL="0", MSP_OP_SELL="0", MSP_DENSE_ROWS="1"),
+            dict(MSP_SPMM_SPLIT="1", MSP_SPMM_WIDE="1", MSP_SPMM_SELL="0", MSP_OP_SELL="1", MSP_DENSE_ROWS="2"),
+            dict(MSP_SPMM_SPLIT="2", MSP_SPMM_WIDE="0", MSP_SPMM_SELL="0", MSP_OP_SELL="0", MSP_DENSE_ROWS="4"),
+            dict(MSP_SPMM_SPLIT="4", MSP_SPMM_WIDE="0", MSP_SPMM_SELL="0", MSP_OP_SELL="1", MSP_DENSE_ROWS="8"),
+            dict(MSP_SPMM_SPLIT="16", MSP_SPMM_WIDE="0", MSP_SPMM_SELL="0", MSP_OP_SELL="0", MSP_DENSE_ROWS="8"),
+            dict(MSP_SPMM_SPLIT="64", MSP_SPMM_WIDE="0", MSP_SPMM_SELL="0", MSP_OP_SELL="1", MSP_DENSE_ROWS="8"),
+            dict(MSP_SPMM_SELL="1", MSP_SPMM_WIDE="0", MSP_OP_SELL="1", MSP_DENSE_ROWS="8"),
+            dict(MSP_SPMM_SELL="1", MSP_SPMM_WIDE="1", MSP_OP_SELL="1", MSP_DENSE_ROWS="8"),
+            dict(MSP_SPMM_SELL="2", MSP_SPMM_WIDE="0", MSP_OP_SELL="0", MSP_DENSE_ROWS="8"),
+            dict(MSP_SPMM_SELL="4", MSP_SPMM_WIDE="1", MSP_OP_SELL="1", MSP_DENSE_ROWS="8"),
+            dict(MSP_SPMM_SELL="8", MSP_SPMM_WIDE="0", MSP_OP_SELL="1", MSP_DENSE_ROWS="8"),
+            dict(MSP_SPMM_SELL="16", MSP_SPMM_WIDE="1", MSP_OP_SELL="1", MSP_DENSE_ROWS="8")]
+SHAPES = [dict(N=(20, 20, 20), s=3, m=4, kw=dict(y_stretch=1.5), opt=dict(coarse_max=48)),    # 32 columns
+          dict(N=(48, 40), s=1, m=3, kw=dict(), opt=dict(coarse_max=40)),                      # 6 of 8 columns
+          dict(N=(16, 12, 20), s=2, m=1, kw=dict(jitter=0.2, kappa="lognormal"), opt=dict(coarse_max=40))]
 
 
+_REFS = {}
+
+
+def _vid(v):
+    if v.get("MSP_SPMM_SELL", "0") != "0":
+        return f"sliced{v['MSP_SPMM_SELL']}_wide{v['MSP_SPMM_WIDE']}_op{v['MSP_OP_SELL']}"
+    return f"split{v['MSP_SPMM_SPLIT']}_wide{v['MSP_SPMM_WIDE']}_op{v['MSP_OP_SELL']}_rows{v['MSP_DENSE_ROWS']}"
+
+
+@pytest.mark.parametrize("shape", range(len(SHAPES)), ids=["3d_32cols", "2d_8cols", "3d_jitter_4cols"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_bf16"])
-@pytest.mark.parametrize("var", VARIANTS, ids=[f"split{v['MSP_SPMM_SPLIT']}_wide{v['MSP_SPMM_WIDE']}_rows"
-                                               f"{v['MSP_DENSE_ROWS']}" for v in VARIANTS])
-def test_every_spmm_variant_matches_oracle(var, prec, monkeypatch):
-    """Each SpMM kernel variant the autotuner can pick (lane groups per row,
-    16-byte lanes, rows per wavefront of the coarsest solves), forced for
-    every V-cycle matrix: FP64 solves match the oracle to 1e-9, the mixed
-    modes reach the tolerance and stay within 1e-7 of it."""
+@pytest.mark.parametrize("var", VARIANTS, ids=[_vid(v) for v in VARIANTS])
+def test_every_spmm_variant_matches_oracle(var, prec, shape, monkeypatch):
+    """Each kernel variant the autotuner can pick for the V-cycle products
+    (CSR with lane groups per row, 16-byte lanes, the sliced-ELL form with
+    rows split G ways; rows per wavefront of the coarsest solves) and for the
+    operator (CSR or sliced), forced for every matrix: FP64 solves match the
+    oracle to 1e-9 with equal iteration counts, the mixed modes reach the
+    tolerance and stay within 1e-7 of it."""
     for key, val in var.items():
         monkeypatch.setenv(key, val)
-    p = make_problem((20, 20, 20), s=3, m=4, seed=43, y_stretch=1.5)
-    ctx = krylov.setup(p.A, p.img, amg.AMGOptions(coarse_max=48), precond="amgr_sub")
-    ref = krylov.solve(ctx, p.b, tol=TOL)
+    sh = SHAPES[shape]
+    if shape not in _REFS:   # one oracle solve per shape for every variant
+        p = make_problem(sh["N"], s=sh["s"], m=sh["m"], seed=43, **sh["kw"])
+        ctx = krylov.setup(p.A, p.img, amg.AMGOptions(**sh["opt"]), precond="amgr_sub")
+        _REFS[shape] = (p, krylov.solve(ctx, p.b, tol=TOL))
+    p, ref = _REFS[shape]
     if prec == "fp64":
-        sv, x = _solve_gpu(p, tol=TOL, pc="amgr_sub", coarse_max=48)
+        sv, x = _solve_gpu(p, tol=TOL, pc="amgr_sub", **sh["opt"])
         assert sv.last.iters == int(ref.iters.max())
         _agree(x, ref.x)
     else:
-        sv, x = _solve_gpu(p, tol=1e-10, pc="amgr_sub", coarse_max=48, precision=prec)
+        sv, x = _solve_gpu(p, tol=1e-10, pc="amgr_sub", precision=prec, **sh["opt"])
         assert np.all(krylov.true_relres(p.A, x, p.b) <= 1.5e-10)
         _agree(x, ref.x, 1e-7)
     sv.close()
+
+
+def test_tuning_file_reproduces_the_chosen_kernels(tmp_path, monkeypatch):
+    """MSP_TUNE_SAVE records the autotuner's choices; a second context with
+    MSP_TUNE_LOAD launches the same kernel functions without timing and gives
+    the same bits."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    path = str(tmp_path / "tune.txt")
+    p = make_problem((24, 24, 24), s=3, m=4, seed=44, y_stretch=1.5)
+    b = torch.from_numpy(p.b).cuda()
+    names = []
+    xs = []
+    for env in ("MSP_TUNE_SAVE", "MSP_TUNE_LOAD"):
+        monkeypatch.delenv("MSP_TUNE_SAVE", raising=False)
+        monkeypatch.delenv("MSP_TUNE_LOAD", raising=False)
+        monkeypatch.setenv(env, path)
+        sv = Solver(p.A, p.img, tol=1e-10, pc="amgr_sub", coarse_max=48, precision="mixed_bf16", k=8)
+        sv.set_timing(True)
+        xs.append(sv.solve(b))
+        names.append(sv.timing_kernels())
+        sv.close()
+    assert open(path).read().count("=") >= 10
+    assert names[0] == names[1]
+    assert torch.equal(xs[0], xs[1])
 
 
 def test_batched_systems_match_oracle_one_by_one():
