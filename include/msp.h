@@ -236,15 +236,19 @@ int msp_get_timing_kernel(const msp_ctx* c, int32_t kind, char* name, int32_t le
 /* ---------------------------------------------------------------------------
  * Batched solves: many independent systems (different sizes, symmetries and
  * right-hand-side counts) solved together.  Setup builds one context per
- * system (host parts in parallel threads).  Solve starts every system on its
- * own stream, then replays one captured HIP graph holding K PCG iterations of
- * every system in parallel branches (default K = 4) until the first system
- * has converged, then a second graph holding one iteration of every system
- * until all columns of all systems have converged; columns that converge
- * earlier are frozen on the device (their updates are zero), so the extra
- * iterations leave their solutions unchanged.  The graphs are re-captured when
- * the vector of m changes.  SpMM lane-group splits are autotuned per matrix
- * and column count.
+ * system (host parts in parallel threads).  A solve starts every system on
+ * its own stream, then launches one captured HIP graph that holds a fixed
+ * number of PCG iterations of every system on parallel branches.  The
+ * iterations are gated on the device: each kernel of a system whose columns
+ * have all converged (or that broke down) returns at once, so every system
+ * does only the iterations it needs and the host reads the convergence flags
+ * once, after the graph.  The graph holds the iterations the previous solve
+ * needed (16 before the first solve, or msp_batch_set_chunk's value; at most
+ * maxit); a system still active after it continues with one-iteration graph
+ * launches up to maxit.  A gated kernel still dispatches its grid, so the
+ * graph is captured again when a solve needs more iterations than it holds
+ * or leaves two or more unused, and when the vector of m changes.  SpMM
+ * kernel shapes are autotuned per matrix and column count.
  * --------------------------------------------------------------------------- */
 typedef struct msp_batch msp_batch;   /* opaque; owned by the library until msp_batch_free */
 
@@ -256,8 +260,11 @@ int msp_batch_setup(int32_t nsys, const msp_csr* A, const msp_symmap* maps, cons
 int msp_batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b, double* const* d_x, void* hip_stream,
                     msp_stats* st);
 int msp_batch_size(const msp_batch* bt, int32_t* nsys);
-/* Iterations per replay of the first graph (1..64). */
+/* Iterations the next solve's graph holds (1..1000; clamped to maxit). */
 int msp_batch_set_chunk(msp_batch* bt, int32_t iterations);
+/* Graph launches of the last msp_batch_solve (1 when its graph held every
+   iteration the systems needed). */
+int msp_batch_last_launches(const msp_batch* bt, int32_t* launches);
 void msp_batch_free(msp_batch* bt);
 
 /* ---------------------------------------------------------------------------

@@ -92,6 +92,7 @@ SIGNATURES = {
     "msp_batch_solve": (ctypes.c_int, [_vp, _P(ctypes.c_int32), _P(_vp), _P(_vp), _vp, _P(msp_stats)]),
     "msp_batch_size": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
     "msp_batch_set_chunk": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "msp_batch_last_launches": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
     "msp_batch_free": (None, [_vp]),
     "msp_fv_create": (ctypes.c_int, [_P(msp_faces), _P(msp_symmap), ctypes.c_int32, _P(_vp)]),
     "msp_fv_nnz": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),

@@ -170,6 +170,7 @@ struct msp_ctx {
     msp::DevOuter dsig1;      // pc = AMGR_SUB: the same at level 1 (the interface's coarse numbers)
     msp::DevCsr dAinn, dGf, dGfT;
     int op_sell[7] = {-1, -1, -1, -1, -1, -1, -1};   // operator kernel by log2 C: -1 not tuned, 0 CSR, 1 sliced
+    const int* gate = nullptr;   // while a batch captures this system's iterations: its active flags (kernel gate)
     std::vector<msp::DevLevel> dl;
     double* d_cinv = nullptr;
     float* d_cinv32 = nullptr;    // per-subsystem coarsest inverses in FP32 (mixed modes), rows padded to 4
@@ -401,7 +402,8 @@ static int log2i(int C);
 // bfloat16 values when the matrix carries them.
 template <typename T>
 static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, bool wide, const T* X, T* Y, const T* Z,
-                        acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m, int sg = 0) {
+                        acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m, int sg = 0,
+                        const int* gate = nullptr) {
     using TV = typename ValOf<T>::type;
     if (sg > 0) {
         const DevSell& F = M.sell[log2i(sg)];
@@ -410,26 +412,26 @@ static void spmm_launch(hipStream_t st, int C, const DevCsr& M, int split, bool 
         if constexpr (std::is_same<TV, double>::value) va = F.v64;
         else va = F.v32;
         HIPCHECK((launch_sell<T, TV>(st, C, sg, M.nr, F.off, F.wid, F.ci, va, X, Y, Z, alpha, beta, sigma, S, m, M.vs,
-                                     wide)));
+                                     wide, gate)));
         return;
     }
     if constexpr (std::is_same<T, float>::value) {
         if (M.v16) {
             if (split > 1)
                 HIPCHECK((launch_spmm_split<float, Bf16>(st, C, split, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta,
-                                                         1, m, sigma, S)));
+                                                         1, m, sigma, S, gate)));
             else
                 HIPCHECK((launch_spmm<float, Bf16>(st, C, M.nr, M.rp, M.ci, M.v16, X, Y, Z, alpha, beta, sigma, S, m,
-                                                   1, wide)));
+                                                   1, wide, gate)));
             return;
         }
     }
     if (split > 1)
         HIPCHECK((launch_spmm_split<T, TV>(st, C, split, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, M.vs, m,
-                                           sigma, S)));
+                                           sigma, S, gate)));
     else
         HIPCHECK((launch_spmm<T, TV>(st, C, M.nr, M.rp, M.ci, vals<T>(M), X, Y, Z, alpha, beta, sigma, S, m, M.vs,
-                                     wide)));
+                                     wide, gate)));
 }
 
 template <typename T>
@@ -441,7 +443,8 @@ static void spmm(msp_ctx* c, int kind, hipStream_t st, int C, const DevCsr& M, c
     const int split = tuned ? tuned : M.split;
     const bool wide = tuned && M.wide[tslot<T>()][log2i(C)];
     const int sg = tuned ? M.sg[tslot<T>()][log2i(C)] : 0;
-    timed(c, kind, bytes, st, [&] { spmm_launch<T>(st, C, M, split, wide, X, Y, Z, alpha, beta, od, S, m, sg); },
+    timed(c, kind, bytes, st,
+          [&] { spmm_launch<T>(st, C, M, split, wide, X, Y, Z, alpha, beta, od, S, m, sg, c->gate); },
           [&] {
               // the instance spmm_launch picks (bfloat16 values only for FP32 products of the BF16-G variant)
               const char* tv = (std::is_same<T, float>::value && M.v16) ? "Bf16" : tname<typename ValOf<T>::type>();
@@ -468,14 +471,14 @@ static void dense_sets(const msp_ctx* c, const Work& w, hipStream_t st, int m, c
     if constexpr (std::is_same<T, double>::value) {
         if (!c->d_cinv) throw Error(MSP_ERR_UNSUPPORTED, "FP64 coarsest inverses not on the device");
         HIPCHECK((launch_dense_sets<double, double>(st, w.C, S, m, c->nL, c->d_cinv, y, s,
-                                                    static_cast<double*>(w.dense_pack), R)));
+                                                    static_cast<double*>(w.dense_pack), R, c->gate)));
     } else if (c->d_cinv32) {
         HIPCHECK((launch_dense_sets<T, float>(st, w.C, S, m, c->nL, c->d_cinv32, y, s, static_cast<T*>(w.dense_pack),
-                                              R)));
+                                              R, c->gate)));
     } else {   // FP64 inverses applied to the reduced-precision vectors (sums in FP64)
         if (!c->d_cinv) throw Error(MSP_ERR_UNSUPPORTED, "coarsest inverses not on the device");
         HIPCHECK((launch_dense_sets<T, double>(st, w.C, S, m, c->nL, c->d_cinv, y, s, static_cast<T*>(w.dense_pack),
-                                               R)));
+                                               R, c->gate)));
     }
 }
 
@@ -963,7 +966,7 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
         } else {
             const double bytes = 8.0 * c->nL * c->nL + 2.0 * sizeof(T) * c->nL * C;
             timed(c, KD_DENSE, bytes, st,
-                  [&] { HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s, w.dense_part)); },
+                  [&] { HIPCHECK(launch_dense<T>(st, C, c->nL, c->d_cinv, y, s, w.dense_part, c->gate)); },
                   [&] { return std::string("k_dense_part+k_dense_sum<") + tname<T>() + ", " + std::to_string(C) + ">"; });
         }
         return;
@@ -1301,15 +1304,15 @@ struct SolvePlan {
             if (c->U16)
                 HIPCHECK(launch_update_dots<Bf16>(st, C, nbu, upd, kl, nb, W.r, W.q, alpha,
                                                   static_cast<const Bf16*>(c->d_U), S, m, W.pp1, W.plrc, y32(),
-                                                  y16()));
+                                                  y16(), c->gate));
             else if (c->U32 || !c->d_U)
                 HIPCHECK(launch_update_dots<float>(st, C, nbu, upd, kl, nb, W.r, W.q, alpha,
                                                    static_cast<const float*>(c->d_U), S, m, W.pp1, W.plrc, y32(),
-                                                   y16()));
+                                                   y16(), c->gate));
             else
                 HIPCHECK(launch_update_dots<double>(st, C, nbu, upd, kl, nb, W.r, W.q, alpha,
                                                     static_cast<const double*>(c->d_U), S, m, W.pp1, W.plrc, y32(),
-                                                    y16()));
+                                                    y16(), c->gate));
         }, [&] {
             const char* tu = c->U16 ? "Bf16" : ((c->U32 || !c->d_U) ? "float" : "double");
             return "k_update_dots<" + std::to_string(C) + ", " + (upd ? "true" : "false") + ", " +
@@ -1349,31 +1352,31 @@ struct SolvePlan {
             if (s16) {
                 if (c->U16)
                     HIPCHECK((launch_zfinish<Bf16, Bf16>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const Bf16*>(U),
-                                                         c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz)));
+                                                         c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz, c->gate)));
                 else if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<Bf16, float>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const float*>(U),
-                                                          c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz)));
+                                                          c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz, c->gate)));
                 else
                     HIPCHECK((launch_zfinish<Bf16, double>(st, C, nbz, nb, s16, W.z, W.r,
                                                            static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
-                                                           W.pp1, z2, qf, pqz)));
+                                                           W.pp1, z2, qf, pqz, c->gate)));
             } else if (s32) {
                 if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<float, float>(st, C, nbz, nb, s32, W.z, W.r, static_cast<const float*>(U),
-                                                           c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz)));
+                                                           c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz, c->gate)));
                 else
                     HIPCHECK((launch_zfinish<float, double>(st, C, nbz, nb, s32, W.z, W.r,
                                                             static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
-                                                            W.pp1, z2, qf, pqz)));
+                                                            W.pp1, z2, qf, pqz, c->gate)));
             } else {
                 if (c->U32 || !c->d_U)
                     HIPCHECK((launch_zfinish<double, float>(st, C, nbz, nb, W.z, W.z, W.r,
                                                             static_cast<const float*>(U), c->d_lrc_W, S, kl, m,
-                                                            W.pp1, z2, qf, pqz)));
+                                                            W.pp1, z2, qf, pqz, c->gate)));
                 else
                     HIPCHECK((launch_zfinish<double, double>(st, C, nbz, nb, W.z, W.z, W.r,
                                                              static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
-                                                             W.pp1, z2, qf, pqz)));
+                                                             W.pp1, z2, qf, pqz, c->gate)));
             }
         }, [&] {
             const char* ts = s16 ? "Bf16" : (s32 ? "float" : "double");
@@ -1381,7 +1384,7 @@ struct SolvePlan {
             return "k_zfinish<" + std::to_string(C) + ", " + ts + ", " + (U && kl > 0 ? "true" : "false") + ", " + tu +
                    ", " + (fq ? "true" : "false") + ">";
         });
-        HIPCHECK(launch_fin_beta(st, C, nbz, init, flexible, W.pp1, W.pp2, active, pq, rho, beta, rz));
+        HIPCHECK(launch_fin_beta(st, C, nbz, init, flexible, W.pp1, W.pp2, active, pq, rho, beta, rz, c->gate));
     }
 
     void begin(const double* d_b) {
@@ -1390,7 +1393,8 @@ struct SolvePlan {
         HIPCHECK(launch_thresholds(st, C, S, m, c->o.tol, bn2, thr));
         if (S * m < C) HIPCHECK(launch_fill<double>(st, nb * C, W.r, 0.0));   // padded columns (Q_s writes the rest)
         HIPCHECK(launch_fill<double>(st, nb * C, W.x, 0.0));
-        HIPCHECK(launch_fill<int>(st, 2, flags, 0));
+        HIPCHECK(launch_fill<int>(st, 64 * 2 + 2, active, 0));   // active, iterations, flags (all 64 slots)
+        HIPCHECK(launch_fill<double>(st, 64, alpha, 0.0));
         timed(c, KD_QS, 16.0 * n * m + 8.0 * n, st,   // bhat = Q_s b
               [&] { HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b, W.r)); },
               [&] { return "k_qs_forward<" + std::to_string(S) + ">"; });
@@ -1403,7 +1407,7 @@ struct SolvePlan {
         const double opb = spmm_bytes<double>(c->dAinn, C, false, &c->dsig, S);   // p read once, q written once
         timed(c, KD_OP, opb, st, [&] {   // q = Ahat p and <p, q>
             HIPCHECK(launch_op_dot(st, C, nbo, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, op_sell_ref(), c->dsig.d, S,
-                                   m, W.p, W.q, W.pp1));
+                                   m, W.p, W.q, W.pp1, c->gate));
         }, [&] { return "k_op_dot<" + std::to_string(C) + ", " + (op_sliced() ? "true" : "false") + ">"; });
         HIPCHECK(launch_fin_alpha(st, C, nbo, W.pp1, active, rho, alpha, pq, flags));
         update_dots(true);
@@ -1414,7 +1418,7 @@ struct SolvePlan {
         Work& W = *w;
         precond_dot(false);
         timed(c, KD_PUPDATE, 5.0 * vb(), st,
-              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, W.x, W.p, W.z, alpha, beta, active)); },
+              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, W.x, W.p, W.z, alpha, beta, active, c->gate != nullptr)); },
               [&] { return "k_pcg_pupdate<" + std::to_string(C) + ">"; });
         x_pending = false;
     }
@@ -1636,13 +1640,16 @@ struct msp_batch {
     hipStream_t main = nullptr;
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> joins;
-    // graph of K iterations of every system, cached for one vector of m
+    // graph of `cap` gated iterations of every system (the whole solve in one launch), cached for one
+    // vector of m and one cap; a one-iteration graph continues a solve that needs more
     std::vector<int> graph_m;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraph_t graph1 = nullptr;      // one iteration of every system (the tail after the first convergence)
+    hipGraph_t graph1 = nullptr;
     hipGraphExec_t exec1 = nullptr;
-    int K = 4;
+    int cap = 16;          // iterations the next solve's graph holds
+    int cap_built = 0;     // iterations the cached graph holds
+    int launches = 0;      // graph launches of the last solve
     int** d_flag_ptrs = nullptr;
     int* d_flags = nullptr;
     int* h_flags = nullptr;
@@ -1713,9 +1720,18 @@ static void batch_setup(int nsys, const msp_csr* A, const msp_symmap* maps, cons
     *out = bt.release();
 }
 
-// Solve every system: eager start per system on its own stream, then graph
-// replays of K iterations of all systems (one branch per system) until every
-// column of every system has converged, then the back transforms.
+// Solve every system: an eager start per system on its own stream, then one
+// launch of a captured graph holding `cap` iterations of every system on
+// parallel branches.  The iterations are gated on the device: every kernel
+// of a system whose columns have all converged returns at once (its p update
+// stops once every step is zero), so each system does the iterations it
+// needs and the host reads the flags once.  A system still active after the
+// graph continues by one-iteration graph launches up to maxit.  The next
+// solve's graph holds the iterations this one needed (at most maxit): a
+// gated kernel returns at once but still dispatches its grid, so extra
+// iterations are not free.  The graph is captured again when a solve needs
+// more iterations than it holds or leaves two or more of them unused, or
+// when the vector of m changes.
 static int batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b, double* const* d_x,
                        hipStream_t user, msp_stats* st) {
     const int nsys = static_cast<int>(bt->sys.size());
@@ -1727,6 +1743,9 @@ static int batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b
         std::fill(bt->sys[i]->tm.on.begin(), bt->sys[i]->tm.on.end(), 0);
         plans[i].reset(new SolvePlan(bt->sys[i], m[i], bt->streams[i]));
     }
+    int maxit = 0;
+    for (auto c : bt->sys) maxit = std::max(maxit, c->o.maxit);
+    const int cap = std::max(1, std::min(bt->cap, maxit));
     const auto t0 = std::chrono::steady_clock::now();
     HIPCHECK(hipEventRecord(bt->fork, user));
     for (int i = 0; i < nsys; ++i) {
@@ -1739,76 +1758,83 @@ static int batch_solve(msp_batch* bt, const int32_t* m, const double* const* d_b
     HIPCHECK(hipMemcpy(bt->d_flag_ptrs, ptrs.data(), sizeof(int*) * nsys, hipMemcpyHostToDevice));
     for (int i = 0; i < nsys; ++i) HIPCHECK(hipStreamSynchronize(bt->streams[i]));
     std::vector<int> mv(m, m + nsys);
-    // graph of `iters` iterations of every system on parallel branches, then the flags gathered
+    // graph of `iters` gated iterations of every system on parallel branches, then the flags gathered
     auto capture = [&](int iters, hipGraph_t* g, hipGraphExec_t* ex) {
         if (*ex) (void)hipGraphExecDestroy(*ex);
         if (*g) (void)hipGraphDestroy(*g);
         *ex = nullptr;
         *g = nullptr;
-        HIPCHECK(hipStreamBeginCapture(bt->main, hipStreamCaptureModeRelaxed));
-        HIPCHECK(hipEventRecord(bt->fork, bt->main));
-        for (int i = 0; i < nsys; ++i) {
-            HIPCHECK(hipStreamWaitEvent(bt->streams[i], bt->fork, 0));
-            for (int k = 0; k < iters; ++k) {
-                plans[i]->half_a();
-                plans[i]->half_b();
+        for (int i = 0; i < nsys; ++i) bt->sys[i]->gate = plans[i]->active;
+        try {
+            HIPCHECK(hipStreamBeginCapture(bt->main, hipStreamCaptureModeRelaxed));
+            HIPCHECK(hipEventRecord(bt->fork, bt->main));
+            for (int i = 0; i < nsys; ++i) {
+                HIPCHECK(hipStreamWaitEvent(bt->streams[i], bt->fork, 0));
+                for (int k = 0; k < iters; ++k) {
+                    plans[i]->half_a();
+                    plans[i]->half_b();
+                }
+                HIPCHECK(hipEventRecord(bt->joins[i], bt->streams[i]));
+                HIPCHECK(hipStreamWaitEvent(bt->main, bt->joins[i], 0));
             }
-            HIPCHECK(hipEventRecord(bt->joins[i], bt->streams[i]));
-            HIPCHECK(hipStreamWaitEvent(bt->main, bt->joins[i], 0));
+            HIPCHECK(launch_gather_flags(bt->main, nsys, bt->d_flag_ptrs, bt->d_flags));
+            HIPCHECK(hipStreamEndCapture(bt->main, g));
+        } catch (...) {
+            for (auto c : bt->sys) c->gate = nullptr;
+            throw;
         }
-        HIPCHECK(launch_gather_flags(bt->main, nsys, bt->d_flag_ptrs, bt->d_flags));
-        HIPCHECK(hipStreamEndCapture(bt->main, g));
+        for (auto c : bt->sys) c->gate = nullptr;
         HIPCHECK(hipGraphInstantiate(ex, *g, nullptr, nullptr, 0));
     };
-    if (!bt->exec || mv != bt->graph_m) {
-        capture(bt->K, &bt->graph, &bt->exec);
-        if (bt->K > 1) {
-            capture(1, &bt->graph1, &bt->exec1);
-        } else {
-            if (bt->exec1) (void)hipGraphExecDestroy(bt->exec1);
-            if (bt->graph1) (void)hipGraphDestroy(bt->graph1);
-            bt->exec1 = nullptr;
-            bt->graph1 = nullptr;
-        }
+    if (!bt->exec || mv != bt->graph_m || bt->cap_built != cap) {
+        capture(cap, &bt->graph, &bt->exec);
+        capture(1, &bt->graph1, &bt->exec1);
         bt->graph_m = mv;
+        bt->cap_built = cap;
     }
-    int maxit = 0;
-    for (auto c : bt->sys) maxit = std::max(maxit, c->o.maxit);
-    std::vector<int> status(nsys, MSP_OK);
-    HIPCHECK(launch_gather_flags(bt->main, nsys, bt->d_flag_ptrs, bt->d_flags));
-    HIPCHECK(hipMemcpyAsync(bt->h_flags, bt->d_flags, sizeof(int) * 2 * nsys, hipMemcpyDeviceToHost, bt->main));
-    HIPCHECK(hipStreamSynchronize(bt->main));
-    // chunks of K iterations until the first system has converged, then single iterations:
-    // the systems run in lockstep, so the tail costs only the iterations it needs
-    std::vector<char> started(nsys, 0);
-    for (int i = 0; i < nsys; ++i) started[i] = bt->h_flags[2 * i + 1] > 0;
-    bool tail = false;
-    for (int it = 0; it < maxit;) {
+    auto read_flags = [&] {
+        HIPCHECK(hipMemcpyAsync(bt->h_flags, bt->d_flags, sizeof(int) * 2 * nsys, hipMemcpyDeviceToHost, bt->main));
+        HIPCHECK(hipStreamSynchronize(bt->main));
         bool any = false, broke = false;
         for (int i = 0; i < nsys; ++i) {
             any |= bt->h_flags[2 * i + 1] > 0;
             broke |= bt->h_flags[2 * i] != 0;
-            tail |= started[i] && bt->h_flags[2 * i + 1] == 0;
         }
-        if (!any || broke) break;
-        const bool one = tail && bt->exec1;
-        HIPCHECK(hipGraphLaunch(one ? bt->exec1 : bt->exec, bt->main));
-        it += one ? 1 : bt->K;
-        HIPCHECK(hipMemcpyAsync(bt->h_flags, bt->d_flags, sizeof(int) * 2 * nsys, hipMemcpyDeviceToHost, bt->main));
-        HIPCHECK(hipStreamSynchronize(bt->main));
+        return any && !broke;
+    };
+    HIPCHECK(launch_gather_flags(bt->main, nsys, bt->d_flag_ptrs, bt->d_flags));
+    int it = 0;
+    bt->launches = 0;
+    if (read_flags()) {
+        HIPCHECK(hipGraphLaunch(bt->exec, bt->main));
+        bt->launches = 1;
+        it = cap;
+        while (read_flags() && it < maxit) {
+            HIPCHECK(hipGraphLaunch(bt->exec1, bt->main));
+            ++bt->launches;
+            ++it;
+        }
     }
     HIPCHECK(hipEventRecord(bt->fork, bt->main));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int worst = MSP_OK;
+    int most = 0;
     for (int i = 0; i < nsys; ++i) {
         HIPCHECK(hipStreamWaitEvent(bt->streams[i], bt->fork, 0));
-        const int rc = plans[i]->finish(d_x[i], MSP_OK, secs, st ? &st[i] : nullptr);
+        msp_stats si{};
+        const int rc = plans[i]->finish(d_x[i], MSP_OK, secs, &si);
+        if (st) st[i] = si;
+        most = std::max(most, si.iters);
         if (rc < worst || (worst == MSP_OK && rc != MSP_OK)) worst = rc;
     }
     for (int i = 0; i < nsys; ++i) {
         HIPCHECK(hipEventRecord(bt->joins[i], bt->streams[i]));
         HIPCHECK(hipStreamWaitEvent(user, bt->joins[i], 0));
     }
+    // the next graph: this solve's count when it needed more, or when the cached graph wastes two or more
+    // iterations (a gated kernel still dispatches its grid); otherwise keep the cached graph
+    const int need = std::max(1, std::min(maxit, most));
+    bt->cap = (need > bt->cap_built || need + 1 < bt->cap_built) ? need : bt->cap_built;
     if (worst == MSP_ERR_BREAKDOWN) throw Error(MSP_ERR_BREAKDOWN, "PCG breakdown in a batched system");
     return worst;
 }
@@ -1973,11 +1999,14 @@ int msp_batch_size(const msp_batch* bt, int32_t* nsys) {
 }
 
 int msp_batch_set_chunk(msp_batch* bt, int32_t iterations) {
-    if (!bt || iterations < 1 || iterations > 64) return MSP_ERR_ARG;
-    if (bt->K != iterations) {
-        bt->K = iterations;
-        bt->graph_m.clear();
-    }
+    if (!bt || iterations < 1 || iterations > 1000) return MSP_ERR_ARG;
+    bt->cap = iterations;
+    return MSP_OK;
+}
+
+int msp_batch_last_launches(const msp_batch* bt, int32_t* launches) {
+    if (!bt || !launches) return MSP_ERR_ARG;
+    *launches = bt->launches;
     return MSP_OK;
 }
 

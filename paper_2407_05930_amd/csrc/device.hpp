@@ -234,6 +234,26 @@ __device__ __forceinline__ bool column_sets(int lane, int vs, int vm, int* set) 
     return set[0] == set[VW - 1];   // sets are nondecreasing in e
 }
 
+// Gates of the batched solve.  A batch runs every system's kernels inside one
+// captured graph for as many iterations as the slowest system needs; a kernel
+// of a system that has no active column left (or has broken down) returns at
+// once.  gate: that system's per-column active flags (64 ints, zero past its
+// columns), its breakdown flag at gate[128]; nullptr = always run.  The
+// decision is a wavefront vote, so every lane of the wavefront must make the
+// call, before any lane leaves.
+__device__ __forceinline__ bool gate_closed(const int* __restrict__ gate) {
+    if (!gate) return false;
+    const bool on = gate[threadIdx.x & 63] != 0;
+    return gate[128] != 0 || __ballot(on) == 0;
+}
+
+// The p update's gate: every column's step alpha is zero (the alpha kernel
+// zeroes it on inactive columns), so there is nothing to apply.
+__device__ __forceinline__ bool alpha_gate_closed(const double* __restrict__ alpha, bool gated) {
+    if (!gated) return false;
+    return __ballot(alpha[threadIdx.x & 63] != 0.0) == 0;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b % 8).  Remap so that every XCD works on one contiguous range of logical
 // tiles: neighbouring rows, and the multivector rows they gather, then stay

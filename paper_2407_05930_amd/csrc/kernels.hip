@@ -34,7 +34,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(int64_t n, const int32_t* __res
                                                  const int32_t* __restrict__ ci,
                                                  const TV* __restrict__ va, const T* __restrict__ X,
                                                  T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta,
-                                                 OuterDiag sigma, int S, int m, int vs) {
+                                                 OuterDiag sigma, int S, int m, int vs, const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     using L = Lanes<T, C, WIDE>;
     using TC = acc_t<T>;
     constexpr int VW = L::VW;
@@ -95,7 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_split(int64_t n, const int32_t*
                                                        const int32_t* __restrict__ ci,
                                                        const TV* __restrict__ va, const T* __restrict__ X,
                                                        T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs,
-                                                       int m, OuterDiag sigma, int S) {
+                                                       int m, OuterDiag sigma, int S, const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     using L = Lanes<T, C>;
     using TC = acc_t<T>;
     constexpr int VW = L::VW;
@@ -194,110 +196,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(int nb, int O, const
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-// ------------------------------------------------------------------ PCG scalar steps (one block)
-// Column state: active[c] (0/1), rho[c], alpha[c], beta[c], iters[c],
-// thr[c] (stop once ||r_c|| <= thr[c]); flags[0] = breakdown, flags[1] = #active.
-
-__global__ void k_pcg_init(int C, const double* __restrict__ rr, const double* __restrict__ rz,
-                           const double* __restrict__ thr, int* active, double* rho, int* iters,
-                           int* flags, double* rnorm) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    const int c = threadIdx.x;
-    if (c < C) {
-        const double nr = sqrt(rr[c]);
-        rnorm[c] = nr;
-        const int a = nr > thr[c] ? 1 : 0;
-        active[c] = a;
-        rho[c] = rz[c];
-        iters[c] = 0;
-        if (a) atomicAdd(&cnt, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        flags[0] = 0;
-        flags[1] = cnt;
-    }
-}
-
-__global__ void k_pcg_alpha(int C, const double* __restrict__ pq, const int* __restrict__ active,
-                            const double* __restrict__ rho, double* alpha, int* flags) {
-    const int c = threadIdx.x;
-    if (c < C) {
-        double a = 0.0;
-        if (active[c]) {
-            const double d = pq[c];
-            if (!(d > 0.0) || !isfinite(d) || !isfinite(rho[c])) flags[0] = 1;
-            else a = rho[c] / d;
-        }
-        alpha[c] = a;
-    }
-}
-
-__global__ void k_pcg_check(int C, const double* __restrict__ rr, const double* __restrict__ thr,
-                            int* active, int* iters, int* flags, double* rnorm) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    const int c = threadIdx.x;
-    if (c < C && active[c]) {
-        iters[c] += 1;
-        const double nr = sqrt(rr[c]);
-        rnorm[c] = nr;
-        if (!isfinite(nr)) flags[0] = 1;
-        if (nr > thr[c]) atomicAdd(&cnt, 1);
-        else active[c] = 0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) flags[1] = cnt;
-}
-
-// standard beta = <r,z>_new / <r,z>_old; flexible: (<r,z>_new - <r,z_old>) / <r,z>_old
-__global__ void k_pcg_beta(int C, const double* __restrict__ rz, const double* __restrict__ rzold,
-                           const int* __restrict__ active, double* rho, double* beta, int flexible) {
-    const int c = threadIdx.x;
-    if (c < C) {
-        double b = 0.0;
-        if (active[c]) {
-            const double num = flexible ? rz[c] - rzold[c] : rz[c];
-            b = num / rho[c];
-            rho[c] = rz[c];
-        }
-        beta[c] = b;
-    }
-}
-
-// x += alpha p, r -= alpha q (per column alpha; zero for frozen columns)
-template <int C>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(int64_t n, double* __restrict__ x, double* __restrict__ r,
-                                                       const double* __restrict__ p, const double* __restrict__ q,
-                                                       const double* __restrict__ alpha) {
-    using L = Lanes<double, C>;
-    constexpr int VW = L::VW;
-    const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
-    const int lane = threadIdx.x % L::LPR;
-    if (row >= n) return;
-    const int64_t o = row * C + lane * VW;
-    Pack<double, VW> xv = ld<double, VW>(x + o), rv = ld<double, VW>(r + o);
-    const Pack<double, VW> pv = ld<double, VW>(p + o), qv = ld<double, VW>(q + o);
-#pragma unroll
-    for (int e = 0; e < VW; ++e) {
-        const double a = alpha[lane * VW + e];
-        xv.e[e] += a * pv.e[e];
-        rv.e[e] -= a * qv.e[e];
-    }
-    st<double, VW>(x + o, xv);
-    st<double, VW>(r + o, rv);
-}
-
 // p = z + beta p on active columns
 template <int C>
 __global__ __launch_bounds__(kBlock) void k_pcg_pupdate(int64_t n, double* __restrict__ x, double* __restrict__ p,
                                                         const double* __restrict__ z,
                                                         const double* __restrict__ alpha,
                                                         const double* __restrict__ beta,
-                                                        const int* __restrict__ active) {
+                                                        const int* __restrict__ active, int gated) {
+    if (alpha_gate_closed(alpha, gated != 0)) return;
     using L = Lanes<double, C>;
     constexpr int VW = L::VW;
     const int64_t row = (int64_t)blockIdx.x * L::RPB + threadIdx.x / L::LPR;
@@ -407,7 +313,9 @@ __global__ void k_thresholds(int C, int S, int m, double tol, const double* __re
 // to part[ks] and a second kernel sums the chunks in a fixed order.
 template <typename T, int C>
 __global__ __launch_bounds__(kBlock) void k_dense_part(int64_t nL, int64_t kchunk, const double* __restrict__ Minv,
-                                                       const T* __restrict__ y, double* __restrict__ part) {
+                                                       const T* __restrict__ y, double* __restrict__ part,
+                                                       const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     using L = Lanes<T, C>;
     constexpr int VW = L::VW, LPR = L::LPR, RB = L::RPB;
     constexpr int KT = 32;
@@ -451,7 +359,9 @@ __global__ __launch_bounds__(kBlock) void k_dense_part(int64_t nL, int64_t kchun
 // for the dense solves below.
 template <typename T, int MP>
 __global__ __launch_bounds__(kBlock) void k_pack_sets(int64_t nL, int64_t ldm, int C, int S, int m,
-                                                      const T* __restrict__ y, T* __restrict__ yp) {
+                                                      const T* __restrict__ y, T* __restrict__ yp,
+                                                      const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (idx >= (int64_t)S * ldm * MP) return;
     const int j = (int)(idx % MP);
@@ -474,7 +384,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_sets(int64_t nL, int64_t ldm, i
 template <typename T, typename TM, int MP, int R>
 __global__ __launch_bounds__(kBlock) void k_dense_sets(int64_t nL, int64_t ldm, int C, int S, int m,
                                                        const TM* __restrict__ Minv, const T* __restrict__ yp,
-                                                       T* __restrict__ out) {
+                                                       T* __restrict__ out, const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     constexpr int W = 64;
     constexpr int KV = sizeof(TM) == 4 ? 4 : 1;                                   // inverse entries per lane load
     constexpr int PW = (MP * (int)sizeof(T)) >= 16 ? 16 / (int)sizeof(T) : MP;   // values per packed load
@@ -546,7 +457,9 @@ __global__ __launch_bounds__(kBlock) void k_dense_sets(int64_t nL, int64_t ldm, 
 // per-subsystem solve) are set to zero.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dense_sum(int64_t len, int ks, int C, int ncol,
-                                                      const double* __restrict__ part, T* __restrict__ out) {
+                                                      const double* __restrict__ part, T* __restrict__ out,
+                                                      const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= len) return;
     double s = 0.0;
@@ -793,7 +706,7 @@ constexpr bool sets_ok() {
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
                        const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m,
-                       int vs, bool wide) {
+                       int vs, bool wide, const int* gate) {
     if (n <= 0) return hipSuccess;
     if (vs > 1 && (!sets_ok<TV>() || m < 1)) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
@@ -801,18 +714,18 @@ hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, cons
         if constexpr (sets_ok<TV>()) {
             if (vs > 1) {
                 hipLaunchKernelGGL((k_spmm<T, TV, CC, true, false>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st,
-                                   n, rp, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs);
+                                   n, rp, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs, gate);
                 break;
             }
         }
         using LW = Lanes<T, CC, true>;
         if (wide && LW::VW != L::VW) {
             hipLaunchKernelGGL((k_spmm<T, TV, CC, false, true>), dim3(blocks_for(n, LW::RPB)), dim3(kBlock), 0, st, n,
-                               rp, ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1);
+                               rp, ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1, gate);
             break;
         }
         hipLaunchKernelGGL((k_spmm<T, TV, CC, false, false>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, rp,
-                           ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1);
+                           ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1, gate);
     });
     return hipGetLastError();
 }
@@ -824,26 +737,27 @@ bool spmm_has_wide(int C, int elem_bytes) {
 
 template <typename T, typename TV, int CC, int G>
 static void launch_split(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va, const T* X,
-                         T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m, OuterDiag sigma, int S) {
+                         T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m, OuterDiag sigma, int S,
+                         const int* gate) {
     constexpr int TPR = G * Lanes<T, CC>::LPR;
     if constexpr (TPR <= kBlock) {
         constexpr int RPB = kBlock / TPR;
         if constexpr (sets_ok<TV>()) {
             if (vs > 1) {
                 hipLaunchKernelGGL((k_spmm_split<T, TV, CC, G, true>), dim3(blocks_for(n, RPB)), dim3(kBlock), 0, st,
-                                   n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S);
+                                   n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S, gate);
                 return;
             }
         }
         hipLaunchKernelGGL((k_spmm_split<T, TV, CC, G, false>), dim3(blocks_for(n, RPB)), dim3(kBlock), 0, st, n, rp,
-                           ci, va, X, Y, Z, alpha, beta, 1, m, sigma, S);
+                           ci, va, X, Y, Z, alpha, beta, 1, m, sigma, S, gate);
     }
 }
 
 template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
                              const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m,
-                             OuterDiag sigma, int S) {
+                             OuterDiag sigma, int S, const int* gate) {
     if (n <= 0) return hipSuccess;
     if ((vs > 1 || sigma.idx) && m < 1) return hipErrorInvalidValue;
     if (vs > 1 && !sets_ok<TV>()) return hipErrorInvalidValue;
@@ -852,13 +766,13 @@ hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int3
         const int gmax = kBlock / LPR;
         const int g = G < gmax ? G : gmax;
         switch (g) {
-            case 2: launch_split<T, TV, CC, 2>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
-            case 4: launch_split<T, TV, CC, 4>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
-            case 8: launch_split<T, TV, CC, 8>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
-            case 16: launch_split<T, TV, CC, 16>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
-            case 32: launch_split<T, TV, CC, 32>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
-            case 64: launch_split<T, TV, CC, 64>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
-            default: launch_split<T, TV, CC, 1>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S); break;
+            case 2: launch_split<T, TV, CC, 2>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S, gate); break;
+            case 4: launch_split<T, TV, CC, 4>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S, gate); break;
+            case 8: launch_split<T, TV, CC, 8>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S, gate); break;
+            case 16: launch_split<T, TV, CC, 16>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S, gate); break;
+            case 32: launch_split<T, TV, CC, 32>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S, gate); break;
+            case 64: launch_split<T, TV, CC, 64>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S, gate); break;
+            default: launch_split<T, TV, CC, 1>(st, n, rp, ci, va, X, Y, Z, alpha, beta, vs, m, sigma, S, gate); break;
         }
     });
     return hipGetLastError();
@@ -867,10 +781,10 @@ hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int3
 #define MSP_SPMM_INST(T, TV)                                                                                         \
     template hipError_t launch_spmm<T, TV>(hipStream_t, int, int64_t, const int32_t*, const int32_t*, const TV*,     \
                                            const T*, T*, const T*, acc_t<T>, acc_t<T>, OuterDiag, int, int, int,      \
-                                           bool);                                                                      \
+                                           bool, const int*);                                                          \
     template hipError_t launch_spmm_split<T, TV>(hipStream_t, int, int, int64_t, const int32_t*, const int32_t*,     \
                                                  const TV*, const T*, T*, const T*, acc_t<T>, acc_t<T>, int, int,   \
-                                                 OuterDiag, int);
+                                                 OuterDiag, int, const int*);
 MSP_SPMM_INST(double, double)
 MSP_SPMM_INST(float, float)
 MSP_SPMM_INST(float, Bf16)
@@ -890,41 +804,12 @@ template hipError_t launch_dot<double>(hipStream_t, int, int64_t, const double*,
 template hipError_t launch_dot<float>(hipStream_t, int, int64_t, const float*, const float*, double*, int,
                                       double*);
 
-hipError_t launch_pcg_init(hipStream_t st, int C, const double* rr, const double* rz, const double* thr,
-                           int* active, double* rho, int* iters, int* flags, double* rnorm) {
-    hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(64), 0, st, C, rr, rz, thr, active, rho, iters, flags, rnorm);
-    return hipGetLastError();
-}
-hipError_t launch_pcg_alpha(hipStream_t st, int C, const double* pq, const int* active, const double* rho,
-                            double* alpha, int* flags) {
-    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(64), 0, st, C, pq, active, rho, alpha, flags);
-    return hipGetLastError();
-}
-hipError_t launch_pcg_check(hipStream_t st, int C, const double* rr, const double* thr, int* active, int* iters,
-                            int* flags, double* rnorm) {
-    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(64), 0, st, C, rr, thr, active, iters, flags, rnorm);
-    return hipGetLastError();
-}
-hipError_t launch_pcg_beta(hipStream_t st, int C, const double* rz, const double* rzold, const int* active,
-                           double* rho, double* beta, int flexible) {
-    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, st, C, rz, rzold, active, rho, beta, flexible);
-    return hipGetLastError();
-}
-hipError_t launch_pcg_update(hipStream_t st, int C, int64_t n, double* x, double* r, const double* p,
-                             const double* q, const double* alpha) {
-    MSP_DISPATCH_C(C, {
-        using L = Lanes<double, CC>;
-        hipLaunchKernelGGL((k_pcg_update<CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, x, r, p, q,
-                           alpha);
-    });
-    return hipGetLastError();
-}
 hipError_t launch_pcg_pupdate(hipStream_t st, int C, int64_t n, double* x, double* p, const double* z,
-                              const double* alpha, const double* beta, const int* active) {
+                              const double* alpha, const double* beta, const int* active, bool gated) {
     MSP_DISPATCH_C(C, {
         using L = Lanes<double, CC>;
         hipLaunchKernelGGL((k_pcg_pupdate<CC>), dim3(blocks_for(n, L::RPB)), dim3(kBlock), 0, st, n, x, p, z, alpha,
-                           beta, active);
+                           beta, active, gated ? 1 : 0);
     });
     return hipGetLastError();
 }
@@ -985,22 +870,26 @@ int dense_splits(int C, int64_t nL, int elem_bytes) {
 }
 
 template <typename T>
-hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part) {
+hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part,
+                        const int* gate) {
     const int ks = dense_splits(C, nL, (int)sizeof(T));
     const int64_t tiles = (nL + 31) / 32;
     const int64_t kchunk = ((tiles + ks - 1) / ks) * 32;
     MSP_DISPATCH_C(C, {
         using L = Lanes<T, CC>;
         hipLaunchKernelGGL((k_dense_part<T, CC>), dim3(blocks_for(nL, L::RPB), ks), dim3(kBlock), 0, st, nL, kchunk,
-                           Minv, y, part);
+                           Minv, y, part, gate);
         hipLaunchKernelGGL((k_dense_sum<T>), dim3(blocks_for(nL * CC, kBlock)), dim3(kBlock), 0, st, nL * CC, ks, CC,
-                           CC, part, out);
+                           CC, part, out, gate);
     });
     return hipGetLastError();
 }
-template hipError_t launch_dense<double>(hipStream_t, int, int64_t, const double*, const double*, double*, double*);
-template hipError_t launch_dense<float>(hipStream_t, int, int64_t, const double*, const float*, float*, double*);
-template hipError_t launch_dense<Bf16>(hipStream_t, int, int64_t, const double*, const Bf16*, Bf16*, double*);
+template hipError_t launch_dense<double>(hipStream_t, int, int64_t, const double*, const double*, double*, double*,
+                                             const int*);
+template hipError_t launch_dense<float>(hipStream_t, int, int64_t, const double*, const float*, float*, double*,
+                                             const int*);
+template hipError_t launch_dense<Bf16>(hipStream_t, int, int64_t, const double*, const Bf16*, Bf16*, double*,
+                                             const int*);
 
 static int pow2_at_least(int x) {
     int p = 1;
@@ -1010,24 +899,24 @@ static int pow2_at_least(int x) {
 
 template <typename T, typename TM, int MP, int R>
 static void launch_dense_sets_r(hipStream_t st, int C, int S, int m, int64_t nL, int64_t ldm, const TM* Minv,
-                                const T* yp, T* out) {
+                                const T* yp, T* out, const int* gate) {
     if constexpr (R * MP <= 64) {
         const int64_t rows_per_block = (int64_t)(kBlock / 64) * R;
         hipLaunchKernelGGL((k_dense_sets<T, TM, MP, R>), dim3(blocks_for(nL, (int)rows_per_block), S), dim3(kBlock),
-                           0, st, nL, ldm, C, S, m, Minv, yp, out);
+                           0, st, nL, ldm, C, S, m, Minv, yp, out, gate);
     }
 }
 
 template <typename T, typename TM, int MP>
 static void launch_dense_sets_mp(hipStream_t st, int C, int S, int m, int64_t nL, int64_t ldm, const TM* Minv,
-                                 const T* y, T* out, T* yp, int R) {
+                                 const T* y, T* out, T* yp, int R, const int* gate) {
     hipLaunchKernelGGL((k_pack_sets<T, MP>), dim3(blocks_for((int64_t)S * ldm * MP, kBlock)), dim3(kBlock), 0, st, nL,
-                       ldm, C, S, m, y, yp);
+                       ldm, C, S, m, y, yp, gate);
     switch (R) {
-        case 8: launch_dense_sets_r<T, TM, MP, 8>(st, C, S, m, nL, ldm, Minv, yp, out); break;
-        case 4: launch_dense_sets_r<T, TM, MP, 4>(st, C, S, m, nL, ldm, Minv, yp, out); break;
-        case 2: launch_dense_sets_r<T, TM, MP, 2>(st, C, S, m, nL, ldm, Minv, yp, out); break;
-        default: launch_dense_sets_r<T, TM, MP, 1>(st, C, S, m, nL, ldm, Minv, yp, out); break;
+        case 8: launch_dense_sets_r<T, TM, MP, 8>(st, C, S, m, nL, ldm, Minv, yp, out, gate); break;
+        case 4: launch_dense_sets_r<T, TM, MP, 4>(st, C, S, m, nL, ldm, Minv, yp, out, gate); break;
+        case 2: launch_dense_sets_r<T, TM, MP, 2>(st, C, S, m, nL, ldm, Minv, yp, out, gate); break;
+        default: launch_dense_sets_r<T, TM, MP, 1>(st, C, S, m, nL, ldm, Minv, yp, out, gate); break;
     }
 }
 
@@ -1040,33 +929,33 @@ int64_t dense_sets_ld(int64_t nL, int minv_bytes) { return minv_bytes == 4 ? (nL
 
 template <typename T, typename TM>
 hipError_t launch_dense_sets(hipStream_t st, int C, int S, int m, int64_t nL, const TM* Minv, const T* y,
-                             T* out, T* yp, int R) {
+                             T* out, T* yp, int R, const int* gate) {
     if (S * m > C || m < 1 || m > 64 || S < 1) return hipErrorInvalidValue;
     if (R != 1 && R != 2 && R != 4 && R != 8) return hipErrorInvalidValue;
     if (R > dense_sets_rows_max(m)) R = dense_sets_rows_max(m);
     if (nL <= 0) return hipSuccess;
     const int64_t ldm = dense_sets_ld(nL, (int)sizeof(TM));
     switch (pow2_at_least(m)) {
-        case 1: launch_dense_sets_mp<T, TM, 1>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
-        case 2: launch_dense_sets_mp<T, TM, 2>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
-        case 4: launch_dense_sets_mp<T, TM, 4>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
-        case 8: launch_dense_sets_mp<T, TM, 8>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
-        case 16: launch_dense_sets_mp<T, TM, 16>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
-        case 32: launch_dense_sets_mp<T, TM, 32>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
-        default: launch_dense_sets_mp<T, TM, 64>(st, C, S, m, nL, ldm, Minv, y, out, yp, R); break;
+        case 1: launch_dense_sets_mp<T, TM, 1>(st, C, S, m, nL, ldm, Minv, y, out, yp, R, gate); break;
+        case 2: launch_dense_sets_mp<T, TM, 2>(st, C, S, m, nL, ldm, Minv, y, out, yp, R, gate); break;
+        case 4: launch_dense_sets_mp<T, TM, 4>(st, C, S, m, nL, ldm, Minv, y, out, yp, R, gate); break;
+        case 8: launch_dense_sets_mp<T, TM, 8>(st, C, S, m, nL, ldm, Minv, y, out, yp, R, gate); break;
+        case 16: launch_dense_sets_mp<T, TM, 16>(st, C, S, m, nL, ldm, Minv, y, out, yp, R, gate); break;
+        case 32: launch_dense_sets_mp<T, TM, 32>(st, C, S, m, nL, ldm, Minv, y, out, yp, R, gate); break;
+        default: launch_dense_sets_mp<T, TM, 64>(st, C, S, m, nL, ldm, Minv, y, out, yp, R, gate); break;
     }
     return hipGetLastError();
 }
 template hipError_t launch_dense_sets<double, double>(hipStream_t, int, int, int, int64_t, const double*,
-                                                      const double*, double*, double*, int);
+                                                      const double*, double*, double*, int, const int*);
 template hipError_t launch_dense_sets<float, float>(hipStream_t, int, int, int, int64_t, const float*, const float*,
-                                                    float*, float*, int);
+                                                    float*, float*, int, const int*);
 template hipError_t launch_dense_sets<Bf16, float>(hipStream_t, int, int, int, int64_t, const float*, const Bf16*,
-                                                   Bf16*, Bf16*, int);
+                                                   Bf16*, Bf16*, int, const int*);
 template hipError_t launch_dense_sets<float, double>(hipStream_t, int, int, int, int64_t, const double*,
-                                                     const float*, float*, float*, int);
+                                                     const float*, float*, float*, int, const int*);
 template hipError_t launch_dense_sets<Bf16, double>(hipStream_t, int, int, int, int64_t, const double*, const Bf16*,
-                                                    Bf16*, Bf16*, int);
+                                                    Bf16*, Bf16*, int, const int*);
 
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v) {

@@ -51,6 +51,10 @@ struct SellRef {
 // lane's columns stay within one subsystem for m = 4 as they do in FP32.
 constexpr int lane_width(int elem_bytes) { return (elem_bytes == 2 ? 8 : 16) / elem_bytes; }
 
+// Every launcher of the solve's kernels takes an optional gate (device.hpp,
+// gate_closed): the batched solve passes its system's active flags, so the
+// kernels of a converged system return at once.
+//
 // Y = alpha (A X [+ outer diagonal]) + beta Z with matrix values of type TV
 // (TV = T, or Bf16 with T = float) and multivectors of type T.  vs > 1: the
 // matrix holds vs interleaved value sets (entry k of set a at va[k*vs + a],
@@ -60,13 +64,13 @@ constexpr int lane_width(int elem_bytes) { return (elem_bytes == 2 ? 8 : 16) / e
 template <typename T, typename TV>
 hipError_t launch_spmm(hipStream_t st, int C, int64_t n, const int32_t* rp, const int32_t* ci, const TV* va,
                        const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m,
-                       int vs, bool wide = false);
+                       int vs, bool wide = false, const int* gate = nullptr);
 bool spmm_has_wide(int C, int elem_bytes);
 // Same product for long rows: G lane groups share each row (G a power of two).
 template <typename T, typename TV>
 hipError_t launch_spmm_split(hipStream_t st, int C, int G, int64_t n, const int32_t* rp, const int32_t* ci,
                              const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta, int vs, int m,
-                             OuterDiag sigma, int S);
+                             OuterDiag sigma, int S, const int* gate = nullptr);
 // The same product on the sliced-ELL form (sell.hip): rows split into G
 // virtual rows (G = 1, 2, 4, 8, 16), slices of 64 virtual rows with width
 // wid[s] stored column-major from slot off[s] (column -1 = padding), values
@@ -76,24 +80,15 @@ bool sell_fits(int C, int elem_bytes, int G, bool wide);
 template <typename T, typename TV>
 hipError_t launch_sell(hipStream_t st, int C, int G, int64_t n, const int64_t* off, const int32_t* wid,
                        const int32_t* ci, const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta,
-                       OuterDiag sigma, int S, int m, int vs, bool wide = false);
+                       OuterDiag sigma, int S, int m, int vs, bool wide = false, const int* gate = nullptr);
 template <typename T>
 hipError_t launch_dot(hipStream_t st, int C, int64_t n, const T* X, const T* Y, double* partial, int nb,
                       double* out);
 
-hipError_t launch_pcg_init(hipStream_t st, int C, const double* rr, const double* rz, const double* thr,
-                           int* active, double* rho, int* iters, int* flags, double* rnorm);
-hipError_t launch_pcg_alpha(hipStream_t st, int C, const double* pq, const int* active, const double* rho,
-                            double* alpha, int* flags);
-hipError_t launch_pcg_check(hipStream_t st, int C, const double* rr, const double* thr, int* active, int* iters,
-                            int* flags, double* rnorm);
-hipError_t launch_pcg_beta(hipStream_t st, int C, const double* rz, const double* rzold, const int* active,
-                           double* rho, double* beta, int flexible);
-hipError_t launch_pcg_update(hipStream_t st, int C, int64_t n, double* x, double* r, const double* p,
-                             const double* q, const double* alpha);
-// x += alpha p (every column; alpha = 0 on frozen ones), then p = z + beta p on active columns
+// x += alpha p (every column; alpha = 0 on frozen ones), then p = z + beta p on active columns;
+// gated: nothing runs when every alpha is zero
 hipError_t launch_pcg_pupdate(hipStream_t st, int C, int64_t n, double* x, double* p, const double* z,
-                              const double* alpha, const double* beta, const int* active);
+                              const double* alpha, const double* beta, const int* active, bool gated = false);
 
 hipError_t launch_qs_forward(hipStream_t st, int S, int64_t n_b, int m, int C, int64_t n, const int64_t* img,
                              const double* b, double* out);
@@ -109,7 +104,8 @@ hipError_t launch_thresholds(hipStream_t st, int C, int S, int m, double tol, co
 // out = Minv y (dense FP64 coarsest solve, split over k; part: dense_splits(C, nL, sizeof(T)) * nL * C doubles)
 int dense_splits(int C, int64_t nL, int elem_bytes);
 template <typename T>
-hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part);
+hipError_t launch_dense(hipStream_t st, int C, int64_t nL, const double* Minv, const T* y, T* out, double* part,
+                        const int* gate = nullptr);
 // Per-subsystem coarsest solves: columns a*m .. a*m + m - 1 times the
 // inverse Minv + a*nL*ld (S inverses, rows of ld = dense_sets_ld(nL,
 // sizeof(TM)) entries, the ones past nL zero; TM = double or float); columns
@@ -120,7 +116,7 @@ int dense_sets_rows_max(int m);
 int64_t dense_sets_ld(int64_t nL, int minv_bytes);
 template <typename T, typename TM>
 hipError_t launch_dense_sets(hipStream_t st, int C, int S, int m, int64_t nL, const TM* Minv, const T* y, T* out,
-                             T* yp, int R);
+                             T* yp, int R, const int* gate = nullptr);
 template <typename T>
 hipError_t launch_fill(hipStream_t st, int64_t len, T* p, T v);
 template <typename TO, typename TI>

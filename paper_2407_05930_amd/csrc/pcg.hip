@@ -35,7 +35,8 @@ __global__ __launch_bounds__(kBlock) void k_op_dot(int64_t n, const int32_t* __r
                                                    const int32_t* __restrict__ ci, const double* __restrict__ va,
                                                    SellRef sl, OuterDiag sigma, int S, int m,
                                                    const double* __restrict__ p, double* __restrict__ q,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
     __shared__ double sm[kBlock * VW];
     const int slot = threadIdx.x / LPR, lane = threadIdx.x % LPR;
@@ -128,7 +129,8 @@ __global__ __launch_bounds__(kBlock) void k_update_dots(int64_t n, double* __res
                                                         const double* __restrict__ alpha, const TU* __restrict__ U,
                                                         int S, int k, int m, double* __restrict__ partial_rr,
                                                         double* __restrict__ partial_lrc, float* __restrict__ y32,
-                                                        Bf16* __restrict__ y16) {
+                                                        Bf16* __restrict__ y16, const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
     constexpr int KA = KMAX > 0 ? KMAX : 1;
     __shared__ double sm[kBlock * VW];
@@ -273,7 +275,8 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
                                                     const TU* __restrict__ U, const double* __restrict__ W, int S,
                                                     int k, int m, double* __restrict__ partial,
                                                     double* __restrict__ z2, const double* __restrict__ q,
-                                                    double* __restrict__ partial_qz) {
+                                                    double* __restrict__ partial_qz, const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
     __shared__ double sm[kBlock * VW];
     __shared__ double wl[LRC ? 64 * 16 : 1];
@@ -342,7 +345,9 @@ __global__ __launch_bounds__(kBlock) void k_fin_beta(int nb, int C, int init, in
                                                      const double* __restrict__ partial,
                                                      const double* __restrict__ partial_qz,
                                                      const int* __restrict__ active, const double* __restrict__ pq,
-                                                     double* rho, double* beta, double* rz) {
+                                                     double* rho, double* beta, double* rz,
+                                                     const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     __shared__ double sm[kBlock];
     const bool qz_block = (int)blockIdx.x >= C;
     const int c = qz_block ? blockIdx.x - C : blockIdx.x;
@@ -440,14 +445,14 @@ template hipError_t zfinish_grid<Bf16, Bf16>(int, bool, bool, int64_t, int*);
 
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
                          const double* va, SellRef sl, OuterDiag sigma, int S, int m, const double* p, double* q,
-                         double* partial) {
+                         double* partial, const int* gate) {
     MSP_DISPATCH_C(C, {
         if (sl.ci)
             hipLaunchKernelGGL((k_op_dot<CC, true>), dim3(nb), dim3(kBlock), 0, st, n, rp, ci, va, sl, sigma, S, m, p,
-                               q, partial);
+                               q, partial, gate);
         else
             hipLaunchKernelGGL((k_op_dot<CC, false>), dim3(nb), dim3(kBlock), 0, st, n, rp, ci, va, sl, sigma, S, m, p,
-                               q, partial);
+                               q, partial, gate);
     });
     return hipGetLastError();
 }
@@ -460,40 +465,41 @@ hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial
 
 template <int CC, bool UPD, int KMAX, typename TU>
 static void upd_launch(hipStream_t st, int nb, int64_t n, double* r, const double* q, const double* alpha,
-                       const TU* U, int S, int k, int m, double* prr, double* plrc, float* y32, Bf16* y16) {
+                       const TU* U, int S, int k, int m, double* prr, double* plrc, float* y32, Bf16* y16,
+                       const int* gate) {
     constexpr int VW = DL<CC>::VW;
     const size_t lds = KMAX > 0 ? sizeof(double) * kUpdTch * kBlock * VW : 0;   // projection partials per pass
     hipLaunchKernelGGL((k_update_dots<CC, UPD, KMAX, TU>), dim3(nb), dim3(kBlock), lds, st, n, r, q, alpha, U, S, k,
-                       m, prr, plrc, y32, y16);
+                       m, prr, plrc, y32, y16, gate);
 }
 
 template <typename TU>
 hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, int k, int64_t n, double* r, const double* q,
                               const double* alpha, const TU* U, int S, int m, double* prr, double* plrc, float* y32,
-                              Bf16* y16) {
+                              Bf16* y16, const int* gate) {
     if (k > 16) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
         if (k > 8) {
-            if (upd) upd_launch<CC, true, 16, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
-            else upd_launch<CC, false, 16, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
+            if (upd) upd_launch<CC, true, 16, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16, gate);
+            else upd_launch<CC, false, 16, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16, gate);
         } else if (k > 0) {
-            if (upd) upd_launch<CC, true, 8, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
-            else upd_launch<CC, false, 8, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
+            if (upd) upd_launch<CC, true, 8, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16, gate);
+            else upd_launch<CC, false, 8, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16, gate);
         } else {
-            if (upd) upd_launch<CC, true, 0, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
-            else upd_launch<CC, false, 0, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16);
+            if (upd) upd_launch<CC, true, 0, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16, gate);
+            else upd_launch<CC, false, 0, TU>(st, nb, n, r, q, alpha, U, S, k, m, prr, plrc, y32, y16, gate);
         }
     });
     return hipGetLastError();
 }
 template hipError_t launch_update_dots<float>(hipStream_t, int, int, bool, int, int64_t, double*, const double*,
                                               const double*, const float*, int, int, double*, double*, float*,
-                                              Bf16*);
+                                              Bf16*, const int*);
 template hipError_t launch_update_dots<double>(hipStream_t, int, int, bool, int, int64_t, double*, const double*,
                                                const double*, const double*, int, int, double*, double*, float*,
-                                               Bf16*);
+                                               Bf16*, const int*);
 template hipError_t launch_update_dots<Bf16>(hipStream_t, int, int, bool, int, int64_t, double*, const double*,
-                                             const double*, const Bf16*, int, int, double*, double*, float*, Bf16*);
+                                             const double*, const Bf16*, int, int, double*, double*, float*, Bf16*, const int*);
 
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, int O, int m, const double* prr,
                             const double* plrc, const double* thr, const double* coef, int* active, int* iters,
@@ -507,30 +513,30 @@ hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, int O, int
 template <int CC, typename TS, bool LRC, typename TU>
 static void zfinish_launch(hipStream_t st, int nb, int64_t n, const TS* s, double* z, const double* r, const TU* U,
                            const double* W, int S, int k, int m, double* partial, double* z2, const double* q,
-                           double* partial_qz) {
+                           double* partial_qz, const int* gate) {
     if (q)
         hipLaunchKernelGGL((k_zfinish<CC, TS, LRC, TU, true>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k,
-                           m, partial, z2, q, partial_qz);
+                           m, partial, z2, q, partial_qz, gate);
     else
         hipLaunchKernelGGL((k_zfinish<CC, TS, LRC, TU, false>), dim3(nb), dim3(kBlock), 0, st, n, s, z, r, U, W, S, k,
-                           m, partial, z2, q, partial_qz);
+                           m, partial, z2, q, partial_qz, gate);
 }
 
 template <typename TS, typename TU>
 hipError_t launch_zfinish(hipStream_t st, int C, int nb, int64_t n, const TS* s, double* z, const double* r,
                           const TU* U, const double* W, int S, int k, int m, double* partial, double* z2,
-                          const double* q, double* partial_qz) {
+                          const double* q, double* partial_qz, const int* gate) {
     if (q && !partial_qz) return hipErrorInvalidValue;
     MSP_DISPATCH_C(C, {
-        if (U && k > 0) zfinish_launch<CC, TS, true, TU>(st, nb, n, s, z, r, U, W, S, k, m, partial, z2, q, partial_qz);
-        else zfinish_launch<CC, TS, false, TU>(st, nb, n, s, z, r, U, W, S, k, m, partial, z2, q, partial_qz);
+        if (U && k > 0) zfinish_launch<CC, TS, true, TU>(st, nb, n, s, z, r, U, W, S, k, m, partial, z2, q, partial_qz, gate);
+        else zfinish_launch<CC, TS, false, TU>(st, nb, n, s, z, r, U, W, S, k, m, partial, z2, q, partial_qz, gate);
     });
     return hipGetLastError();
 }
 #define MSP_ZFINISH_INST(TS, TU)                                                                                  \
     template hipError_t launch_zfinish<TS, TU>(hipStream_t, int, int, int64_t, const TS*, double*, const double*,    \
                                                const TU*, const double*, int, int, int, double*, double*,           \
-                                               const double*, double*);
+                                               const double*, double*, const int*);
 MSP_ZFINISH_INST(float, float)
 MSP_ZFINISH_INST(double, double)
 MSP_ZFINISH_INST(double, float)
@@ -541,11 +547,11 @@ MSP_ZFINISH_INST(Bf16, Bf16)
 
 hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
                            const double* partial_qz, const int* active, const double* pq, double* rho, double* beta,
-                           double* rz) {
+                           double* rz, const int* gate) {
     const bool fq = flex && !init;
     if (fq && (!partial_qz || !pq)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fin_beta, dim3(fq ? 2 * C : C), dim3(kBlock), 0, st, nb, C, init ? 1 : 0, fq ? 1 : 0, partial,
-                       partial_qz, active, pq, rho, beta, rz);
+                       partial_qz, active, pq, rho, beta, rz, gate);
     return hipGetLastError();
 }
 

@@ -25,14 +25,14 @@ hipError_t zfinish_grid(int C, bool lrc, bool flex, int64_t n, int* nb);
 // sl.ci != nullptr: the operator in its sliced-ELL form (one group per row)
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
                          const double* va, SellRef sl, OuterDiag sigma, int S, int m, const double* p, double* q,
-                         double* partial);
+                         double* partial, const int* gate = nullptr);
 hipError_t launch_fin_alpha(hipStream_t st, int C, int nb, const double* partial, const int* active,
                             const double* rho, double* alpha, double* pq, int* flags);
 // upd: r -= alpha q (x is updated by launch_pcg_pupdate, or by the back transform after the last iteration)
 template <typename TU>
 hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, int k, int64_t n, double* r, const double* q,
                               const double* alpha, const TU* U, int S, int m, double* prr, double* plrc, float* y32,
-                              Bf16* y16);
+                              Bf16* y16, const int* gate = nullptr);
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, int O, int m, const double* prr,
                             const double* plrc, const double* thr, const double* coef, int* active, int* iters,
                             int* flags, double* rnorm, double* W);
@@ -41,10 +41,10 @@ hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, int O, int
 template <typename TS, typename TU>
 hipError_t launch_zfinish(hipStream_t st, int C, int nb, int64_t n, const TS* s, double* z, const double* r,
                           const TU* U, const double* W, int S, int k, int m, double* partial, double* z2 = nullptr,
-                          const double* q = nullptr, double* partial_qz = nullptr);
+                          const double* q = nullptr, double* partial_qz = nullptr, const int* gate = nullptr);
 // flex (non-initial calls): beta = -<q,z>/<p,q> from partial_qz and pq
 hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
                            const double* partial_qz, const int* active, const double* pq, double* rho, double* beta,
-                           double* rz);
+                           double* rz, const int* gate = nullptr);
 
 }  // namespace msp

@@ -36,7 +36,8 @@ __global__ __launch_bounds__(kBlock) void k_sell(int64_t n, const int64_t* __res
                                                  const int32_t* __restrict__ wid, const int32_t* __restrict__ ci,
                                                  const TV* __restrict__ va, const T* __restrict__ X, T* Y, const T* Z,
                                                  acc_t<T> alpha, acc_t<T> beta, OuterDiag sigma, int S, int m,
-                                                 int vs) {
+                                                 int vs, const int* __restrict__ gate) {
+    if (gate_closed(gate)) return;
     using L = Lanes<T, C, WIDE>;
     using TC = acc_t<T>;
     constexpr int VW = L::VW, LPR = L::LPR;
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(int64_t n, const int64_t* __res
 template <typename T, typename TV, int CC, int G>
 static void sell_launch_g(hipStream_t st, int64_t n, const int64_t* off, const int32_t* wid, const int32_t* ci,
                           const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta,
-                          OuterDiag sigma, int S, int m, int vs, bool wide) {
+                          OuterDiag sigma, int S, int m, int vs, bool wide, const int* gate) {
     using LN = Lanes<T, CC, false>;
     using LW = Lanes<T, CC, true>;
     const bool w = wide && vs == 1 && LW::VW != LN::VW;
@@ -145,7 +146,7 @@ static void sell_launch_g(hipStream_t st, int64_t n, const int64_t* off, const i
         if (w) {
             constexpr int VPB = kBlock / LW::LPR;
             hipLaunchKernelGGL((k_sell<T, TV, CC, G, false, true>), dim3(blocks_for(n * G, VPB)), dim3(kBlock), 0, st,
-                               n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1);
+                               n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1, gate);
             return;
         }
     }
@@ -153,10 +154,10 @@ static void sell_launch_g(hipStream_t st, int64_t n, const int64_t* off, const i
         constexpr int VPB = kBlock / LN::LPR;
         if (vs > 1)
             hipLaunchKernelGGL((k_sell<T, TV, CC, G, true, false>), dim3(blocks_for(n * G, VPB)), dim3(kBlock), 0, st,
-                               n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs);
+                               n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs, gate);
         else
             hipLaunchKernelGGL((k_sell<T, TV, CC, G, false, false>), dim3(blocks_for(n * G, VPB)), dim3(kBlock), 0,
-                               st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1);
+                               st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, 1, gate);
     }
 }
 
@@ -169,24 +170,28 @@ bool sell_fits(int C, int elem_bytes, int G, bool wide) {
 template <typename T, typename TV>
 hipError_t launch_sell(hipStream_t st, int C, int G, int64_t n, const int64_t* off, const int32_t* wid,
                        const int32_t* ci, const TV* va, const T* X, T* Y, const T* Z, acc_t<T> alpha, acc_t<T> beta,
-                       OuterDiag sigma, int S, int m, int vs, bool wide) {
+                       OuterDiag sigma, int S, int m, int vs, bool wide, const int* gate) {
     if (n <= 0) return hipSuccess;
     if ((vs > 1 || sigma.idx) && m < 1) return hipErrorInvalidValue;
     if (!sell_fits(C, (int)sizeof(T), G, wide && vs == 1)) return hipErrorInvalidValue;
-#define MSP_SELL_G(CC)                                                                                             \
-    switch (G) {                                                                                                   \
-        case 1: sell_launch_g<T, TV, CC, 1>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs, wide); \
-            break;                                                                                                 \
-        case 2: sell_launch_g<T, TV, CC, 2>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs, wide); \
-            break;                                                                                                 \
-        case 4: sell_launch_g<T, TV, CC, 4>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs, wide); \
-            break;                                                                                                 \
-        case 8: sell_launch_g<T, TV, CC, 8>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs, wide); \
-            break;                                                                                                 \
-        case 16: sell_launch_g<T, TV, CC, 16>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs,      \
-                                              wide);                                                               \
-            break;                                                                                                 \
-        default: return hipErrorInvalidValue;                                                                      \
+#define MSP_SELL_G(CC)                                                                                         \
+    switch (G) {                                                                                               \
+        case 1: sell_launch_g<T, TV, CC, 1>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs,   \
+                                            wide, gate);                                                       \
+            break;                                                                                             \
+        case 2: sell_launch_g<T, TV, CC, 2>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs,   \
+                                            wide, gate);                                                       \
+            break;                                                                                             \
+        case 4: sell_launch_g<T, TV, CC, 4>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs,   \
+                                            wide, gate);                                                       \
+            break;                                                                                             \
+        case 8: sell_launch_g<T, TV, CC, 8>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs,   \
+                                            wide, gate);                                                       \
+            break;                                                                                             \
+        case 16: sell_launch_g<T, TV, CC, 16>(st, n, off, wid, ci, va, X, Y, Z, alpha, beta, sigma, S, m, vs, \
+                                              wide, gate);                                                     \
+            break;                                                                                             \
+        default: return hipErrorInvalidValue;                                                                  \
     }
     switch (C) {
         case 1: MSP_SELL_G(1) break;
@@ -205,7 +210,7 @@ hipError_t launch_sell(hipStream_t st, int C, int G, int64_t n, const int64_t* o
 #define MSP_SELL_INST(T, TV)                                                                                      \
     template hipError_t launch_sell<T, TV>(hipStream_t, int, int, int64_t, const int64_t*, const int32_t*,       \
                                            const int32_t*, const TV*, const T*, T*, const T*, acc_t<T>, acc_t<T>, \
-                                           OuterDiag, int, int, int, bool);
+                                           OuterDiag, int, int, int, bool, const int*);
 MSP_SELL_INST(double, double)
 MSP_SELL_INST(float, float)
 MSP_SELL_INST(Bf16, float)

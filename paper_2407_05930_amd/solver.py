@@ -235,9 +235,10 @@ class Solver:
 
 
 class BatchSolver:
-    """Many independent systems solved together (one captured HIP graph per
-    chunk of iterations).  ``systems`` is a list of (A, img) pairs; options as
-    for Solver (shared by all systems)."""
+    """Many independent systems solved together: one launch of a captured
+    HIP graph whose iterations are gated per system on the device.
+    ``systems`` is a list of (A, img) pairs; options as for Solver (shared by
+    all systems)."""
 
     def __init__(self, systems, **opts):
         self.n = []
@@ -264,7 +265,16 @@ class BatchSolver:
         self.stats = (_lib.msp_stats * len(systems))()
 
     def set_chunk(self, iterations: int):
+        """Iterations the next solve's graph holds (later solves size it from
+        the iterations the previous one needed)."""
         check(lib.msp_batch_set_chunk(self._h, iterations))
+
+    @property
+    def last_launches(self) -> int:
+        """Graph launches of the last solve (1 when one graph held them all)."""
+        v = ctypes.c_int32()
+        check(lib.msp_batch_last_launches(self._h, ctypes.byref(v)))
+        return v.value
 
     def solve(self, bs, stream=None):
         """bs: list of float64 CUDA tensors (n_i,) or (n_i, m_i).  Returns the

@@ -209,11 +209,22 @@ def test_batched_systems_match_oracle_one_by_one():
         refs.append(krylov.solve(ctx, p.b, tol=TOL))
     bs_in = [torch.from_numpy(p.b).cuda() for p in probs]
     bs = BatchSolver([(p.A, p.img) for p in probs], tol=TOL, pc="amgr_sub", coarse_max=48)
+    bs.set_chunk(4)   # the first solve's graph holds too few iterations: one-iteration launches finish it
     xs = bs.solve(bs_in)
+    _say("first batched solve: graph launches", bs.last_launches)
+    assert bs.last_launches > 1
     for i, (p, x, ref) in enumerate(zip(probs, xs, refs)):
         _say("batch fp64 system", i, "iterations", bs.stats[i].iters, "oracle", int(ref.iters.max()))
         assert bs.stats[i].iters == int(ref.iters.max())
         _agree(x.cpu().numpy(), ref.x)
+    # the next solve's graph holds every iteration: one launch, the systems converging at their own
+    # iteration counts inside it, and the same bits
+    xs2 = bs.solve(bs_in)
+    assert bs.last_launches == 1
+    its = [bs.stats[i].iters for i in range(len(probs))]
+    assert len(set(its)) > 1, its
+    for x, x2 in zip(xs, xs2):
+        assert torch.equal(x, x2)
     bs.close()
     bm = BatchSolver([(p.A, p.img) for p in probs], tol=1e-10, pc="amgr_sub", coarse_max=48, precision="mixed")
     xs = bm.solve(bs_in)
@@ -233,7 +244,11 @@ def test_batch_workload_fp32_vcycle_full_size():
     from paper_2407_05930_amd import BatchSolver
     probs = batch_problems(64)
     bs = BatchSolver([(p.A, p.img) for p in probs], tol=1e-10, pc="amgr_sub", precision="mixed")
-    xs = bs.solve([torch.from_numpy(p.b).cuda() for p in probs])
+    b_in = [torch.from_numpy(p.b).cuda() for p in probs]
+    bs.solve(b_in)
+    xs = bs.solve(b_in)
+    _say("batch64 graph launches", bs.last_launches)
+    assert bs.last_launches == 1
     xh = [x.cpu().numpy() for x in xs]
     worst = max(float(krylov.true_relres(p.A, x, p.b).max()) for p, x in zip(probs, xh))
     _say("batch64 worst true relres", worst)
