@@ -427,3 +427,97 @@ def batch_problems(count: int = 64, seed: int = CONFIG_SEED0 + 3, n_min: int = 3
         out.append(make_problem((N, N, N), s=int(ss[i]), m=int(ms[i]), seed=int(subseeds[i]),
                                 ordering=ordering))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Repeated geometries: a domain made of copies of one subdomain
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class CopiesProblem:
+    N: tuple                 # cells per axis of one copy
+    copies: int              # number of copies placed side by side along axis 0
+    n: int                   # total unknowns
+    n_b: int                 # unknowns of one copy
+    A: sp.csr_matrix         # full matrix, natural (lexicographic) order of the whole grid
+    sub: np.ndarray          # (n_b, copies) int64: global row of cell i of the base copy in copy a
+    b: np.ndarray            # (n, m) right-hand sides
+
+
+def make_repeated_problem(N: Sequence[int], copies: int, m: int = 1, seed: int = 0, mirror: bool = False,
+                          walls: str = "dirichlet", kappa: str = "lognormal") -> CopiesProblem:
+    """``copies`` copies of an N grid of unit cells placed side by side along
+    axis 0 (a repeated geometry; with ``mirror`` every odd copy is the mirror
+    image of the base copy, a reflected geometry).  The coefficient of a cell
+    (lognormal(0, 1) per cell of the base copy, or 1) is the same in every
+    copy.  Cell-centred two-point fluxes with the harmonic mean of the two
+    cells; homogeneous Dirichlet walls (flux 2 kappa h^(D-2)).  walls =
+    "mixed" makes the boundary conditions differ between copies: the low wall
+    of axis 1 is insulating (no flux) in every odd copy, and so is the wall
+    closing the domain at the far end of axis 0.  Right-hand sides i.i.d.
+    uniform[-1, 1] in natural order.  The diagonal sums opposite faces first,
+    so a cell and its image carry the same bits."""
+    N = tuple(int(v) for v in N)
+    D = len(N)
+    if D not in (2, 3) or copies < 1:
+        raise ValueError("2D or 3D copies, at least one")
+    rng = np.random.default_rng(seed)
+    n_b = int(np.prod(N))
+    full = (N[0] * copies,) + N[1:]
+    n = n_b * copies
+    kb = rng.lognormal(0.0, 1.0, size=n_b) if kappa == "lognormal" else np.ones(n_b)
+
+    def base_of(idx):            # full grid multi-index -> (copy, base multi-index)
+        a = idx[0] // N[0]
+        x0 = idx[0] % N[0]
+        if mirror and a % 2 == 1:
+            x0 = N[0] - 1 - x0
+        return a, (x0,) + tuple(idx[1:])
+
+    strides_full = np.cumprod((1,) + full[:-1])     # axis 0 fastest
+    strides_base = np.cumprod((1,) + N[:-1])
+    grid = np.stack(np.meshgrid(*[np.arange(v) for v in full], indexing="ij"), axis=-1).reshape(-1, D)
+    gidx = grid @ strides_full
+    order = np.argsort(gidx)
+    grid = grid[order]
+    copy_of = np.empty(n, dtype=np.int64)
+    base_idx = np.empty(n, dtype=np.int64)
+    for g in range(n):
+        a, bi = base_of(tuple(grid[g]))
+        copy_of[g] = a
+        base_idx[g] = int(np.dot(bi, strides_base))
+    kap = kb[base_idx]
+    rows, cols, vals = [], [], []
+    for g in range(n):
+        idx = grid[g]
+        face = np.zeros(2 * D)
+        for ax in range(D):
+            for side, step in ((0, -1), (1, 1)):
+                nb = idx.copy()
+                nb[ax] += step
+                f = 2 * ax + side
+                if nb[ax] < 0 or nb[ax] >= full[ax]:
+                    insulated = walls == "mixed" and (
+                        (ax == 1 and side == 0 and copy_of[g] % 2 == 1) or
+                        (ax == 0 and side == 1 and nb[ax] >= full[ax]))
+                    face[f] = 0.0 if insulated else 2.0 * kap[g]
+                    continue
+                h = int(np.dot(nb, strides_full))
+                t = 1.0 / (0.5 / kap[g] + 0.5 / kap[h])
+                face[f] = t
+                rows.append(g)
+                cols.append(h)
+                vals.append(-t)
+        pairs = [face[2 * ax] + face[2 * ax + 1] for ax in range(D)]
+        diag = pairs[0] + pairs[1]
+        if D == 3:
+            diag = diag + pairs[2]
+        rows.append(g)
+        cols.append(g)
+        vals.append(diag)
+    A = sp.csr_matrix((np.array(vals), (np.array(rows), np.array(cols))), shape=(n, n))
+    A.sort_indices()
+    sub = np.empty((n_b, copies), dtype=np.int64)
+    sub[base_idx, copy_of] = np.arange(n)
+    b = rng.uniform(-1.0, 1.0, size=(m, n)).T.copy()
+    return CopiesProblem(N=N, copies=copies, n=n, n_b=n_b, A=A, sub=sub, b=np.ascontiguousarray(b))

@@ -414,11 +414,14 @@ class AMGOptions:
     mis_method: str = "rounds"
 
 
-def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions) -> Hierarchy:
+def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions,
+                    coarse0: Optional[np.ndarray] = None) -> Hierarchy:
     """AMGR on the shared inner block: level 0 is the multigrid reduction of
     Sec. 3.2 (Alg. 2 coarsening with the interface forced coarse, P = [W; I],
     block-FSAI smoother), levels below are standard AMG on the reduced
-    operator, the last level is solved densely."""
+    operator, the last level is solved densely.  ``coarse0``: a level-0
+    coarse set computed elsewhere (the populated interface of a domain of
+    copies), used instead of Alg. 2 on this matrix."""
     levels = []
     A = Ainn.tocsr()
     A.sort_indices()
@@ -429,7 +432,10 @@ def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions)
         n = A.shape[0]
         if n <= opt.coarse_max or lev == opt.max_levels - 1:
             break
-        if lev == 0:
+        if lev == 0 and coarse0 is not None:
+            C = np.asarray(coarse0, dtype=bool).copy()
+            steps, trunc = opt.jacobi0, opt.trunc0
+        elif lev == 0:
             C = coarsen_level0(A, interface, opt.theta, opt.dist, opt.seed, opt.mis_method)
             steps, trunc = opt.jacobi0, opt.trunc0
         else:
