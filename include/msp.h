@@ -100,6 +100,16 @@ typedef struct {
     const int64_t* img;      /* n_b * 2^s */
 } msp_symmap;
 
+/* A domain made of copies of one subdomain (host memory): translated or
+   reflected copies, any number of them, whose boundary conditions may differ
+   from copy to copy.  sub[i * copies + a] is the row of unknown i of the base
+   copy in copy a (a permutation of 0..n-1, n = n_b * copies). */
+typedef struct {
+    int32_t copies;          /* number of copies, >= 1 */
+    int64_t n_b;             /* unknowns of one copy */
+    const int64_t* sub;      /* n_b * copies */
+} msp_copies;
+
 typedef struct {
     int32_t precision;   /* MSP_FP64 | MSP_MIXED_FP32 | MSP_MIXED_FP32_BF16G | MSP_MIXED_BF16 */
     int32_t pc;          /* MSP_PC_AMGR | MSP_PC_FSAI | MSP_PC_NONE | MSP_PC_AMGR_SUB */
@@ -153,6 +163,25 @@ int msp_default_opts(msp_opts* o);
    hierarchy is uploaded to that GPU and low-rank corrections are computed
    there.  On success *out owns all library memory until msp_free. */
 int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ctx** out);
+
+/* AMGR in the original basis for a domain made of copies (Sec. 3 with the
+   inner-interface ordering of eq. (3.1); Sec. 3.2: Alg. 2, eqs. (3.13)-(3.15),
+   Alg. 3), for the domains the change of basis Q_s cannot take.  The
+   interface is every base unknown that, in some copy, is coupled to another
+   copy or has a row inside its copy (read in base numbering) that differs
+   from the base copy's in pattern or value; every copy then has the same inner
+   block.  Alg. 2 runs once, on the base copy's block with that interface, and
+   its split is replicated to every copy (the populated interface); level 0 of
+   the hierarchy on the whole matrix uses it (P = [W; I], block FSAI over the
+   F/C blocks, A_c = P^T A P), the levels below are standard AMG.  The
+   context solves the whole system in the caller's ordering through the same
+   entry points as msp_setup's (one subsystem: msp_export_outer reports the
+   interface over all n unknowns and a zero outer diagonal).  pc must be
+   MSP_PC_AMGR, MSP_PC_FSAI or MSP_PC_NONE (MSP_PC_AMGR_SUB needs the Q_s
+   subsystems: MSP_ERR_ARG).  Errors as msp_setup's; a copy map that is not a
+   permutation is MSP_ERR_BAD_MAP.  On success *out owns all library memory
+   until msp_free. */
+int msp_setup_copies(const msp_csr* A, const msp_copies* map, const msp_opts* o, msp_ctx** out);
 
 /* Solve for m right-hand sides held in device memory (d_b, d_x: n x m
    column-major FP64, on the context's device), enqueued on hip_stream (NULL

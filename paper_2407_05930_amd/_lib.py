@@ -43,6 +43,10 @@ class msp_symmap(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int32), ("n_b", ctypes.c_int64), ("img", ctypes.POINTER(ctypes.c_int64))]
 
 
+class msp_copies(ctypes.Structure):
+    _fields_ = [("copies", ctypes.c_int32), ("n_b", ctypes.c_int64), ("sub", ctypes.POINTER(ctypes.c_int64))]
+
+
 class msp_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("pc", ctypes.c_int32), ("lrc_k", ctypes.c_int32),
                 ("dist", ctypes.c_int32), ("theta", ctypes.c_double), ("jacobi0", ctypes.c_int32),
@@ -71,6 +75,7 @@ _vp = ctypes.c_void_p
 SIGNATURES = {
     "msp_default_opts": (ctypes.c_int, [_P(msp_opts)]),
     "msp_setup": (ctypes.c_int, [_P(msp_csr), _P(msp_symmap), _P(msp_opts), _P(_vp)]),
+    "msp_setup_copies": (ctypes.c_int, [_P(msp_csr), _P(msp_copies), _P(msp_opts), _P(_vp)]),
     "msp_solve_device": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _P(msp_stats)]),
     "msp_solve": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _P(msp_stats)]),
     "msp_solve_device_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _P(msp_stats)]),

@@ -1620,6 +1620,28 @@ static std::unique_ptr<msp_ctx> setup_host(const msp_csr* A, const msp_symmap* m
     return c;
 }
 
+// Host part of the setup for a domain made of copies: one subsystem holding the
+// whole matrix, level 0 split by the replicated populated interface.
+static std::unique_ptr<msp_ctx> setup_host_copies(const msp_csr* A, const msp_copies* map, const msp_opts* o) {
+    if (o->pc == MSP_PC_AMGR_SUB)
+        throw Error(MSP_ERR_ARG, "a domain of copies is solved in its own basis: use MSP_PC_AMGR");
+    std::unique_ptr<msp_ctx> c(new msp_ctx());
+    c->o = *o;
+    c->device = o->device;
+    c->lrc_k = o->lrc_k;
+    msp::CopyParts parts = msp::extract_copies(A, map, *o);
+    c->sym = std::move(parts.sym);
+    if (o->pc == MSP_PC_AMGR) {
+        c->hier = msp::build_hierarchy(c->sym.Ainn, c->sym.iface, *o, &parts.cf0);
+    } else {
+        c->hier.lev.emplace_back();
+        c->hier.lev.back().A = c->sym.Ainn;
+        if (o->pc == MSP_PC_FSAI) c->Gf = msp::fsai_full_lower(c->sym.Ainn);
+    }
+    msp::fill_stats(c.get());
+    return c;
+}
+
 // Device part: upload and low-rank corrections.
 static void setup_device(msp_ctx* c) {
     int ndev = 0;
@@ -1850,6 +1872,21 @@ int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ct
         check_opts(o);
         const auto t0 = std::chrono::steady_clock::now();
         std::unique_ptr<msp_ctx> c = setup_host(A, map, o);
+        if (o->device >= 0) setup_device(c.get());
+        const auto t1 = std::chrono::steady_clock::now();
+        c->stats.t_setup_s = std::chrono::duration<double>(t1 - t0).count();
+        *out = c.release();
+        return MSP_OK;
+    });
+}
+
+int msp_setup_copies(const msp_csr* A, const msp_copies* map, const msp_opts* o, msp_ctx** out) {
+    return guarded([&]() -> int {
+        if (!out) throw Error(MSP_ERR_ARG, "null output");
+        *out = nullptr;
+        check_opts(o);
+        const auto t0 = std::chrono::steady_clock::now();
+        std::unique_ptr<msp_ctx> c = setup_host_copies(A, map, o);
         if (o->device >= 0) setup_device(c.get());
         const auto t1 = std::chrono::steady_clock::now();
         c->stats.t_setup_s = std::chrono::duration<double>(t1 - t0).count();

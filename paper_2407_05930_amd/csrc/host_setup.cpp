@@ -95,17 +95,11 @@ static void spmv(const Csr& A, const double* x, double* y) {
 
 // ------------------------------------------------------------------ block extraction
 
-SymParts extract_blocks(const msp_csr* A, const msp_symmap* map) {
-    if (!A || !map || !A->rowptr || !A->col || !A->val || !map->img)
-        throw Error(MSP_ERR_ARG, "null matrix or map");
-    if (map->s < 0 || map->s > 6) throw Error(MSP_ERR_ARG, "s must be in 0..6");
-    const int s = map->s;
-    const int S = 1 << s;
+// Sorted, zero-free copy of the caller's matrix, checked for valid indices,
+// duplicates and exact symmetry.
+static Csr checked_copy(const msp_csr* A) {
     const int64_t n = A->n;
-    if (n <= 0 || map->n_b <= 0 || (map->n_b << s) != n)
-        throw Error(MSP_ERR_ARG, "n must equal n_b * 2^s and be positive");
     if (n >= (int64_t(1) << 31)) throw Error(MSP_ERR_UNSUPPORTED, "n must fit in int32");
-    const int64_t n_b = map->n_b;
     const int64_t* rp = A->rowptr;
     if (rp[0] != 0) throw Error(MSP_ERR_ARG, "rowptr[0] must be 0");
     for (int64_t g = 0; g < n; ++g)
@@ -113,19 +107,6 @@ SymParts extract_blocks(const msp_csr* A, const msp_symmap* map) {
     const int64_t nnz = rp[n];
     for (int64_t k = 0; k < nnz; ++k)
         if (A->col[k] < 0 || A->col[k] >= n) throw Error(MSP_ERR_ARG, "column index out of range");
-
-    // map: permutation, inverse
-    std::vector<int32_t> inv_i(n, -1);
-    std::vector<int8_t> inv_a(n, 0);
-    for (int64_t i = 0; i < n_b; ++i)
-        for (int a = 0; a < S; ++a) {
-            const int64_t g = map->img[i * S + a];
-            if (g < 0 || g >= n || inv_i[g] >= 0) throw Error(MSP_ERR_BAD_MAP, "symmetry map is not a permutation");
-            inv_i[g] = static_cast<int32_t>(i);
-            inv_a[g] = static_cast<int8_t>(a);
-        }
-
-    // sorted, zero-free copy of every row
     Csr As;
     As.nr = As.nc = n;
     As.rp.assign(n + 1, 0);
@@ -155,6 +136,31 @@ SymParts extract_blocks(const msp_csr* A, const msp_symmap* map) {
             const int32_t* f = std::lower_bound(b, e, static_cast<int32_t>(g));
             if (f == e || *f != g || !(As.v[f - As.ci.data()] == As.v[k]))
                 throw Error(MSP_ERR_NOT_SYMMETRIC, "matrix is not exactly symmetric");
+        }
+    return As;
+}
+
+SymParts extract_blocks(const msp_csr* A, const msp_symmap* map) {
+    if (!A || !map || !A->rowptr || !A->col || !A->val || !map->img)
+        throw Error(MSP_ERR_ARG, "null matrix or map");
+    if (map->s < 0 || map->s > 6) throw Error(MSP_ERR_ARG, "s must be in 0..6");
+    const int s = map->s;
+    const int S = 1 << s;
+    const int64_t n = A->n;
+    if (n <= 0 || map->n_b <= 0 || (map->n_b << s) != n)
+        throw Error(MSP_ERR_ARG, "n must equal n_b * 2^s and be positive");
+    const int64_t n_b = map->n_b;
+    const Csr As = checked_copy(A);
+
+    // map: permutation, inverse
+    std::vector<int32_t> inv_i(n, -1);
+    std::vector<int8_t> inv_a(n, 0);
+    for (int64_t i = 0; i < n_b; ++i)
+        for (int a = 0; a < S; ++a) {
+            const int64_t g = map->img[i * S + a];
+            if (g < 0 || g >= n || inv_i[g] >= 0) throw Error(MSP_ERR_BAD_MAP, "symmetry map is not a permutation");
+            inv_i[g] = static_cast<int32_t>(i);
+            inv_a[g] = static_cast<int8_t>(a);
         }
 
     // block structure: row of image a of base cell i, read as (j = a xor b, l)
@@ -642,7 +648,105 @@ static std::vector<double> dense_inverse(const Csr& Ac) {
     return inv;
 }
 
-HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o) {
+// ------------------------------------------------------------------ domains made of copies
+
+CopyParts extract_copies(const msp_csr* A, const msp_copies* map, const msp_opts& o) {
+    if (!A || !map || !A->rowptr || !A->col || !A->val || !map->sub)
+        throw Error(MSP_ERR_ARG, "null matrix or copy map");
+    const int64_t n = A->n, n_b = map->n_b;
+    const int64_t nc = map->copies;
+    if (n <= 0 || n_b <= 0 || nc <= 0 || n_b * nc != n)
+        throw Error(MSP_ERR_ARG, "n must equal n_b * copies and be positive");
+    CopyParts P;
+    P.sym.s = 0;
+    P.sym.n = P.sym.n_b = n;
+    P.sym.Ainn = checked_copy(A);
+    const Csr& As = P.sym.Ainn;
+    std::vector<int32_t> copy_of(n, -1), base_of(n, -1);
+    for (int64_t i = 0; i < n_b; ++i)
+        for (int64_t a = 0; a < nc; ++a) {
+            const int64_t g = map->sub[i * nc + a];
+            if (g < 0 || g >= n || copy_of[g] >= 0) throw Error(MSP_ERR_BAD_MAP, "copy map is not a permutation");
+            copy_of[g] = static_cast<int32_t>(a);
+            base_of[g] = static_cast<int32_t>(i);
+        }
+    // Interface (Sec. 3, eq. (3.1)): a base unknown coupled to another copy in
+    // some copy, or whose row inside its copy (read in base numbering) differs
+    // from the base copy's row in pattern or value.
+    P.iface_base.assign(n_b, 0);
+    P.A00.nr = P.A00.nc = n_b;
+    P.A00.rp.assign(n_b + 1, 0);
+    std::vector<std::pair<int32_t, double>> row0, row;
+    auto copy_row = [&](int64_t i, int64_t a, std::vector<std::pair<int32_t, double>>& out) {
+        out.clear();
+        bool cross = false;
+        const int64_t g = map->sub[i * nc + a];
+        for (int64_t k = As.rp[g]; k < As.rp[g + 1]; ++k) {
+            const int32_t h = As.ci[k];
+            if (copy_of[h] != a)
+                cross = true;
+            else
+                out.emplace_back(base_of[h], As.v[k]);
+        }
+        std::sort(out.begin(), out.end(), [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+            return x.first < y.first;
+        });
+        return cross;
+    };
+    for (int64_t i = 0; i < n_b; ++i) {
+        bool on = copy_row(i, 0, row0);
+        for (const auto& e : row0) {
+            P.A00.ci.push_back(e.first);
+            P.A00.v.push_back(e.second);
+        }
+        P.A00.rp[i + 1] = static_cast<int64_t>(P.A00.ci.size());
+        for (int64_t a = 1; a < nc && !on; ++a) {
+            on = copy_row(i, a, row);
+            if (!on && row != row0) on = true;
+        }
+        P.iface_base[i] = on ? 1 : 0;
+    }
+    // Alg. 2 on the base copy, the split replicated to every copy
+    const std::vector<int8_t> cf_base = reduction_split(P.A00, P.iface_base, o);
+    P.cf0.assign(n, 0);
+    P.sym.iface.assign(n, 0);
+    for (int64_t i = 0; i < n_b; ++i)
+        for (int64_t a = 0; a < nc; ++a) {
+            const int64_t g = map->sub[i * nc + a];
+            P.cf0[g] = cf_base[i];
+            P.sym.iface[g] = P.iface_base[i];
+        }
+    P.sym.sigma.assign(n, 0.0);
+    P.sym.img.resize(n);
+    std::iota(P.sym.img.begin(), P.sym.img.end(), int64_t(0));
+    return P;
+}
+
+// Alg. 2: the maximal independent set of T^d over the inner nodes, scanned in
+// decreasing hash priority of the node index, joined with the interface.
+static std::vector<int8_t> reduction_split(const Graph& S, int64_t n, const std::vector<int8_t>& iface,
+                                           const msp_opts& o) {
+    const Graph T = symmetrise(S, n);
+    std::vector<int8_t> cand(n, 1);
+    std::vector<int32_t> order;
+    for (int64_t i = 0; i < n; ++i) {
+        cand[i] = iface[i] ? 0 : 1;
+        if (cand[i]) order.push_back(static_cast<int32_t>(i));
+    }
+    std::vector<uint64_t> pri(n);
+    for (int64_t i = 0; i < n; ++i) pri[i] = splitmix64(o.seed ^ static_cast<uint64_t>(i));
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return pri[x] > pri[y]; });
+    std::vector<int8_t> cf = mis_scan(T, cand, order, o.dist);
+    for (int64_t i = 0; i < n; ++i) cf[i] = (cf[i] || iface[i]) ? 1 : 0;
+    return cf;
+}
+
+std::vector<int8_t> reduction_split(const Csr& A, const std::vector<int8_t>& iface, const msp_opts& o) {
+    return reduction_split(strength(A, o.theta), A.nr, iface, o);
+}
+
+HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o,
+                              const std::vector<int8_t>* cf0) {
     HostHierarchy H;
     Csr A = Ainn;
     int lev = 0;
@@ -656,40 +760,30 @@ HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface,
             break;
         }
         Graph S = strength(A, o.theta);
-        Graph T = symmetrise(S, n);
-        std::vector<int8_t> cf(n, 0), cand(n, 1);
-        std::vector<int32_t> order;
-        int d;
-        if (lev == 0) {
-            // Alg. 2: MIS of T^d over inner nodes, then interface forced coarse
-            for (int64_t i = 0; i < n; ++i) {
-                cand[i] = iface[i] ? 0 : 1;
-                if (cand[i]) order.push_back(static_cast<int32_t>(i));
-            }
-            std::vector<uint64_t> pri(n);
-            for (int64_t i = 0; i < n; ++i) pri[i] = splitmix64(seed ^ static_cast<uint64_t>(i));
-            std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return pri[x] > pri[y]; });
-            d = o.dist;
+        std::vector<int8_t> cf;
+        if (lev == 0 && cf0) {
+            // a split computed elsewhere (the populated interface of a domain of copies)
+            if (static_cast<int64_t>(cf0->size()) != n) throw Error(MSP_ERR_ARG, "level-0 split size");
+            cf = *cf0;
+        } else if (lev == 0) {
+            cf = reduction_split(S, n, iface, o);
         } else {
-            // standard level: priority (number of strong dependants, hash)
+            // standard level: MIS of T, priority (number of strong dependants, hash)
+            Graph T = symmetrise(S, n);
             std::vector<int64_t> lam(n, 0);
             for (int64_t k = 0; k < S.rp[n]; ++k) lam[S.ci[k]]++;
             std::vector<uint64_t> h(n);
             for (int64_t i = 0; i < n; ++i)
                 h[i] = splitmix64(seed ^ (static_cast<uint64_t>(lev) << 40) ^ static_cast<uint64_t>(i));
-            order.resize(n);
+            std::vector<int32_t> order(n);
             std::iota(order.begin(), order.end(), 0);
             std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
                 return lam[x] != lam[y] ? lam[x] > lam[y] : h[x] > h[y];
             });
-            d = 1;
+            cf = mis_scan(T, std::vector<int8_t>(n, 1), order, 1);
         }
-        std::vector<int8_t> mis = mis_scan(T, cand, order, d);
         int64_t nc = 0;
-        for (int64_t i = 0; i < n; ++i) {
-            cf[i] = (mis[i] || (lev == 0 && iface[i])) ? 1 : 0;
-            nc += cf[i];
-        }
+        for (int64_t i = 0; i < n; ++i) nc += cf[i];
         if (nc == 0 || static_cast<double>(nc) > o.max_ratio * static_cast<double>(n)) {
             L.A = std::move(A);
             break;

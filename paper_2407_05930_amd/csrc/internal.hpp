@@ -71,7 +71,24 @@ struct SymParts {
 };
 
 SymParts extract_blocks(const msp_csr* A, const msp_symmap* map);
-HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o);
+
+// A domain made of copies of one subdomain, solved in its own ordering: the
+// parts of a one-subsystem context (s = 0, identity map, no outer diagonal)
+// plus the interface of the copies and the replicated level-0 split.
+struct CopyParts {
+    SymParts sym;                  // Ainn = the whole matrix; iface over all n unknowns
+    Csr A00;                       // the base copy's block, base numbering
+    std::vector<int8_t> iface_base;
+    std::vector<int8_t> cf0;       // populated interface over all n unknowns
+};
+CopyParts extract_copies(const msp_csr* A, const msp_copies* map, const msp_opts& o);
+
+// Alg. 2 on A with the given interface (MIS of T^d over the inner nodes, joined
+// with the interface); 1 = coarse.
+std::vector<int8_t> reduction_split(const Csr& A, const std::vector<int8_t>& iface, const msp_opts& o);
+// cf0: a level-0 split computed elsewhere, used instead of Alg. 2 on Ainn.
+HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o,
+                              const std::vector<int8_t>* cf0 = nullptr);
 // omega = 4/(3 lam), lam from 20 power iterations on G A G^T (seeded start).
 double damping(const Csr& A, const Csr& G, const Csr& GT, uint64_t seed);
 // Static FSAI on the full lower pattern of A (the stand-alone FSAI of A_inn).

@@ -17,6 +17,16 @@ def _ptr(a: np.ndarray, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
+def _csr(A):
+    """The matrix as contiguous arrays (kept alive by the caller) and its msp_csr."""
+    indptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(A.indices, dtype=np.int32)
+    data = np.ascontiguousarray(A.data, dtype=np.float64)
+    csr = _lib.msp_csr(indptr.size - 1, _ptr(indptr, ctypes.c_int64), _ptr(indices, ctypes.c_int32),
+                       _ptr(data, ctypes.c_double))
+    return (indptr, indices, data), csr
+
+
 def default_opts() -> _lib.msp_opts:
     o = _lib.msp_opts()
     check(lib.msp_default_opts(ctypes.byref(o)))
@@ -59,19 +69,35 @@ class Solver:
         s = S.bit_length() - 1
         if 1 << s != S:
             raise ValueError("img must have 2^s columns")
-        indptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
-        indices = np.ascontiguousarray(A.indices, dtype=np.int32)
-        data = np.ascontiguousarray(A.data, dtype=np.float64)
-        n = indptr.size - 1
-        self.n, self.n_b, self.s = n, n_b, s
-        csr = _lib.msp_csr(n, _ptr(indptr, ctypes.c_int64), _ptr(indices, ctypes.c_int32),
-                           _ptr(data, ctypes.c_double))
+        arrays, csr = _csr(A)
+        self.n, self.n_b, self.s = csr.n, n_b, s
         smap = _lib.msp_symmap(s, n_b, _ptr(img, ctypes.c_int64))
         self.opts = make_opts(**opts)
         self._ctx = ctypes.c_void_p()
         check(lib.msp_setup(ctypes.byref(csr), ctypes.byref(smap), ctypes.byref(self.opts),
                             ctypes.byref(self._ctx)))
         self.last = _lib.msp_stats()
+
+    @classmethod
+    def from_copies(cls, A, sub, **opts):
+        """Setup of AMGR in the original basis for a domain made of copies of
+        one subdomain (msp_setup_copies): ``sub`` is (n_b, copies), the row of
+        base unknown i in copy a.  The context solves the whole system in its
+        own ordering; ``export_outer`` reports the interface over all n
+        unknowns."""
+        sub = np.ascontiguousarray(sub, dtype=np.int64)
+        if sub.ndim != 2:
+            raise ValueError("sub must be (n_b, copies)")
+        arrays, csr = _csr(A)
+        self = cls.__new__(cls)
+        self.n, self.n_b, self.s = csr.n, csr.n, 0
+        cmap = _lib.msp_copies(sub.shape[1], sub.shape[0], _ptr(sub, ctypes.c_int64))
+        self.opts = make_opts(**opts)
+        self._ctx = ctypes.c_void_p()
+        check(lib.msp_setup_copies(ctypes.byref(csr), ctypes.byref(cmap), ctypes.byref(self.opts),
+                                   ctypes.byref(self._ctx)))
+        self.last = _lib.msp_stats()
+        return self
 
     # ------------------------------------------------------------------ solves
     def solve(self, b, stream=None):
