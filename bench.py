@@ -106,6 +106,37 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=10):
     return dict(bytes_moved=2 * nbytes, ms=round(ms, 4), GBs=round(2 * nbytes / (ms * 1e-3) / 1e9, 1))
 
 
+def same_size_copy(torch, nbytes, reps=11, flush_bytes=512 << 20):
+    """A plain device copy moving nbytes (nbytes / 2 read, nbytes / 2 written),
+    the dominant kernel's algorithmic bytes per launch: median time per copy
+    with the caches holding its operands (hot), and after a 512 MB write that
+    evicts them from L2 and the memory-side cache (cold), as the solve's
+    kernels find their operands after the PCG vectors have streamed through."""
+    half = max(int(nbytes) // 2 // 8, 1)
+    src = torch.ones(half, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    junk = torch.empty(flush_bytes // 4, dtype=torch.float32, device="cuda")
+    out = {}
+    for mode in ("hot", "cold"):
+        ts = []
+        dst.copy_(src)
+        for _ in range(reps):
+            if mode == "cold":
+                junk.fill_(1.0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            dst.copy_(src)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[reps // 2]
+        out[mode] = dict(ms=round(ms, 5), GBs=round(2 * half * 8 / (ms * 1e-3) / 1e9, 1))
+    del src, dst, junk
+    torch.cuda.empty_cache()
+    out["bytes_moved"] = 2 * half * 8
+    return out
+
+
 def window_marker(torch):
     """A tiny int16 fill launched just before and just after the timed steps of
     the headline solve, so that a kernel trace of this command can be cut to
@@ -401,6 +432,9 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     ceiling = copy_ceiling(torch)
     log(f"copy ceiling: {ceiling['GBs']} GB/s")
+    same = same_size_copy(torch, bytes_per_launch)
+    log(f"copy of the dominant kernel's bytes per launch: hot {same['hot']['GBs']} GB/s, "
+        f"cold {same['cold']['GBs']} GB/s")
     breakdown = {Solver.kind_name(kk): dict(launches=v[0], ms=round(v[1], 3), kernel=names[kk],
                                             GBs=round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None)
                  for kk, v in sorted(tm_all.items(), key=lambda kv: -kv[1][1])}
@@ -454,7 +488,9 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(top),
                      "kernel": top, "classes": [Solver.kind_name(kk) for kk in funcs[top]["kinds"]],
                      "avg_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                     "launches": cnt, "frac_of_copy_ceiling": round(achieved / ceiling["GBs"], 4)},
+                     "launches": cnt, "frac_of_copy_ceiling": round(achieved / ceiling["GBs"], 4),
+                     "same_size_copy": same,
+                     "frac_of_same_size_copy": {m: round(achieved / same[m]["GBs"], 4) for m in ("hot", "cold")}},
         "kernel_functions_mixed": by_function,
         "kernel_breakdown_mixed": breakdown,
         "timed_solve_with_kernel_events_s": round(t_head, 6),

@@ -72,6 +72,36 @@ def test_hierarchy_bit_exact_with_oracle(case):
     assert abs(st.op_complexity - H.stats()["op_complexity"]) < 1e-12
 
 
+@pytest.mark.parametrize("which", ["channel3d_128_s3", "jitter3d_96_s3"])
+def test_hierarchy_bit_exact_with_oracle_at_full_size(which):
+    """The headline workload (128^3, s = 3, tanh-stretched) and a 96^3 jittered
+    grid with lognormal kappa: patterns and C/F splits bit for bit, values to
+    1e-12, on every level."""
+    from gen import config_problem
+    if which == "channel3d_128_s3":
+        p = config_problem(which)
+    else:
+        p = make_problem((96, 96, 96), s=3, seed=7, jitter=0.2, kappa="lognormal")
+    sv = _setup(p)
+    ctx = krylov.setup(p.A, p.img, amg.AMGOptions())
+    H = ctx["hier"]
+    assert sv.num_levels() == H.nlev >= 4
+    for lev in range(H.nlev):
+        e = sv.export_level(lev)
+        L = H.levels[lev]
+        assert np.array_equal(e["A"].indptr, L.A.indptr) and np.array_equal(e["A"].indices, L.A.indices)
+        assert np.abs(e["A"].data - L.A.data).max() <= 1e-12 * np.abs(L.A.data).max()
+        if L.C is not None:
+            assert np.array_equal(e["cf"], L.C)
+            for key in ("P", "G"):
+                M1, M2 = e[key], getattr(L, key)
+                assert np.array_equal(M1.indptr, M2.indptr) and np.array_equal(M1.indices, M2.indices)
+                assert np.abs(M1.data - M2.data).max() <= 1e-12 * np.abs(M2.data).max()
+            assert abs(e["omega"] - L.omega) <= 1e-10 * L.omega
+    sigma, iface = sv.export_outer()
+    assert np.array_equal(iface, ctx["interface"])
+
+
 def test_setup_rejects_bad_inputs():
     from paper_2407_05930_amd import Solver, MspError
     p = make_problem((8, 8), s=1, seed=2, y_stretch=1.5)
