@@ -102,7 +102,7 @@ struct Work {
     void* vt[kMaxLevels] = {};   // factored smoother (BF16-G variant)
     double* partial = nullptr;
     int nb_dot = 0;
-    int grid_op = 0, grid_upd = 0, grid_z = 0;   // PCG kernel grids (set by the first solve plan)
+    int grid_op = 0, grid_upd = 0, grid_z = 0, grid_p = 0;   // PCG kernel grids (set by the first solve plan)
     double* dense_part = nullptr;   // k-chunk partials of the dense coarsest solve
     void* dense_pack = nullptr;     // per-subsystem packed right-hand sides of the coarsest solves
     int dense_rows = 8;             // rows per wavefront of the per-subsystem coarsest solves (autotuned)
@@ -1200,6 +1200,7 @@ struct SolvePlan {
     hipStream_t st;
     int m, S, C, kl, O;
     int nbo = 0, nbu = 0, nbz = 0;   // grids of the operator, update and z-finish kernels (partial rows)
+    int nbp = 0;                     // grid of the rebuilding p update (mixed modes)
     int64_t nb, n;
     bool flexible, lrc_amg;
     bool x_pending = false;   // an x += alpha p step not yet applied
@@ -1252,6 +1253,7 @@ struct SolvePlan {
             nbo = w->grid_op;
             nbu = w->grid_upd;
             nbz = w->grid_z;
+            nbp = w->grid_p;
             return;
         }
         HIPCHECK(op_dot_grid(C, op_sliced(), nb, &nbo));
@@ -1264,9 +1266,14 @@ struct SolvePlan {
             if (c->U16) HIPCHECK((zfinish_grid<Bf16, Bf16>(C, lz, flexible, nb, &nbz)));
             else if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<Bf16, float>(C, lz, flexible, nb, &nbz)));
             else HIPCHECK((zfinish_grid<Bf16, double>(C, lz, flexible, nb, &nbz)));
+            if (c->U16) HIPCHECK((pupdate_rebuild_grid<Bf16, Bf16>(C, lz, nb, &nbp)));
+            else if (c->U32 || !c->d_U) HIPCHECK((pupdate_rebuild_grid<Bf16, float>(C, lz, nb, &nbp)));
+            else HIPCHECK((pupdate_rebuild_grid<Bf16, double>(C, lz, nb, &nbp)));
         } else if (s32) {
             if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<float, float>(C, lz, flexible, nb, &nbz)));
             else HIPCHECK((zfinish_grid<float, double>(C, lz, flexible, nb, &nbz)));
+            if (c->U32 || !c->d_U) HIPCHECK((pupdate_rebuild_grid<float, float>(C, lz, nb, &nbp)));
+            else HIPCHECK((pupdate_rebuild_grid<float, double>(C, lz, nb, &nbp)));
         } else {
             if (c->U32 || !c->d_U) HIPCHECK((zfinish_grid<double, float>(C, lz, flexible, nb, &nbz)));
             else HIPCHECK((zfinish_grid<double, double>(C, lz, flexible, nb, &nbz)));
@@ -1274,6 +1281,16 @@ struct SolvePlan {
         w->grid_op = nbo;
         w->grid_upd = nbu;
         w->grid_z = nbz;
+        w->grid_p = nbp;
+    }
+
+    // the V-cycle's level-0 output in the mixed modes (z is rebuilt from it, not stored)
+    const Bf16* cycle_out16() const {
+        return (amg(c) && c->o.precision == MSP_MIXED_BF16) ? static_cast<const Bf16*>(w->vs[0]) : nullptr;
+    }
+    const float* cycle_out32() const {
+        return (amg(c) && mixed(c) && c->o.precision != MSP_MIXED_BF16) ? static_cast<const float*>(w->vs[0])
+                                                                         : nullptr;
     }
 
     double vb() const { return 8.0 * nb * C; }   // bytes of one FP64 multivector pass
@@ -1345,27 +1362,29 @@ struct SolvePlan {
         const bool fq = flexible && !init;   // <q, z> for the flexible beta
         const double* qf = fq ? W.q : nullptr;
         double* pqz = fq ? W.pp2 : nullptr;
-        const double bytes = (s16 ? 2.0 : (s32 ? 4.0 : 8.0)) * nb * C + (init ? 3.0 : 2.0) * vb() +
-                             (fq ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0);
+        // the mixed modes store no z (the p update rebuilds it); the first call writes p = z
+        double* zs = (s16 || s32) ? nullptr : W.z;
+        const double bytes = (s16 ? 2.0 : (s32 ? 4.0 : 8.0)) * nb * C + (init ? 1.0 : 0.0) * vb() +
+                             (zs ? vb() : 0.0) + vb() + (fq ? vb() : 0.0) + (kl ? nb * S * kl * wu : 0.0);
         const void* U = lrc_amg ? c->d_U : nullptr;
         timed(c, KD_CAST, bytes, st, [&] {
             if (s16) {
                 if (c->U16)
-                    HIPCHECK((launch_zfinish<Bf16, Bf16>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const Bf16*>(U),
+                    HIPCHECK((launch_zfinish<Bf16, Bf16>(st, C, nbz, nb, s16, zs, W.r, static_cast<const Bf16*>(U),
                                                          c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz, c->gate)));
                 else if (c->U32 || !c->d_U)
-                    HIPCHECK((launch_zfinish<Bf16, float>(st, C, nbz, nb, s16, W.z, W.r, static_cast<const float*>(U),
+                    HIPCHECK((launch_zfinish<Bf16, float>(st, C, nbz, nb, s16, zs, W.r, static_cast<const float*>(U),
                                                           c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz, c->gate)));
                 else
-                    HIPCHECK((launch_zfinish<Bf16, double>(st, C, nbz, nb, s16, W.z, W.r,
+                    HIPCHECK((launch_zfinish<Bf16, double>(st, C, nbz, nb, s16, zs, W.r,
                                                            static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
                                                            W.pp1, z2, qf, pqz, c->gate)));
             } else if (s32) {
                 if (c->U32 || !c->d_U)
-                    HIPCHECK((launch_zfinish<float, float>(st, C, nbz, nb, s32, W.z, W.r, static_cast<const float*>(U),
+                    HIPCHECK((launch_zfinish<float, float>(st, C, nbz, nb, s32, zs, W.r, static_cast<const float*>(U),
                                                            c->d_lrc_W, S, kl, m, W.pp1, z2, qf, pqz, c->gate)));
                 else
-                    HIPCHECK((launch_zfinish<float, double>(st, C, nbz, nb, s32, W.z, W.r,
+                    HIPCHECK((launch_zfinish<float, double>(st, C, nbz, nb, s32, zs, W.r,
                                                             static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
                                                             W.pp1, z2, qf, pqz, c->gate)));
             } else {
@@ -1417,9 +1436,43 @@ struct SolvePlan {
     void half_b() {
         Work& W = *w;
         precond_dot(false);
-        timed(c, KD_PUPDATE, 5.0 * vb(), st,
-              [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, W.x, W.p, W.z, alpha, beta, active, c->gate != nullptr)); },
-              [&] { return "k_pcg_pupdate<" + std::to_string(C) + ">"; });
+        const Bf16* sb = cycle_out16();
+        const float* sf = cycle_out32();
+        if (!sb && !sf) {
+            timed(c, KD_PUPDATE, 5.0 * vb(), st,
+                  [&] { HIPCHECK(launch_pcg_pupdate(st, C, nb, W.x, W.p, W.z, alpha, beta, active, c->gate != nullptr)); },
+                  [&] { return "k_pcg_pupdate<" + std::to_string(C) + ">"; });
+        } else {
+            // z = s + U W rebuilt per row: s (and U) are read instead of a stored FP64 z
+            const void* U = lrc_amg ? c->d_U : nullptr;
+            const double bytes = 4.0 * vb() + (sb ? 2.0 : 4.0) * nb * C + (kl ? nb * S * kl * ubytes() : 0.0);
+            const bool g = c->gate != nullptr;
+            timed(c, KD_PUPDATE, bytes, st, [&] {
+                if (sb && c->U16)
+                    HIPCHECK((launch_pupdate_rebuild<Bf16, Bf16>(st, C, nbp, nb, W.x, W.p, sb, static_cast<const Bf16*>(U),
+                                                                 c->d_lrc_W, S, kl, m, alpha, beta, active, g)));
+                else if (sb && (c->U32 || !c->d_U))
+                    HIPCHECK((launch_pupdate_rebuild<Bf16, float>(st, C, nbp, nb, W.x, W.p, sb,
+                                                                  static_cast<const float*>(U), c->d_lrc_W, S, kl, m,
+                                                                  alpha, beta, active, g)));
+                else if (sb)
+                    HIPCHECK((launch_pupdate_rebuild<Bf16, double>(st, C, nbp, nb, W.x, W.p, sb,
+                                                                   static_cast<const double*>(U), c->d_lrc_W, S, kl, m,
+                                                                   alpha, beta, active, g)));
+                else if (c->U32 || !c->d_U)
+                    HIPCHECK((launch_pupdate_rebuild<float, float>(st, C, nbp, nb, W.x, W.p, sf,
+                                                                   static_cast<const float*>(U), c->d_lrc_W, S, kl, m,
+                                                                   alpha, beta, active, g)));
+                else
+                    HIPCHECK((launch_pupdate_rebuild<float, double>(st, C, nbp, nb, W.x, W.p, sf,
+                                                                    static_cast<const double*>(U), c->d_lrc_W, S, kl,
+                                                                    m, alpha, beta, active, g)));
+            }, [&] {
+                const char* tu = c->U16 ? "Bf16" : ((c->U32 || !c->d_U) ? "float" : "double");
+                return std::string("k_pupdate_rebuild<") + std::to_string(C) + ", " + (sb ? "Bf16" : "float") + ", " +
+                       (U && kl > 0 ? "true" : "false") + ", " + tu + ">";
+            });
+        }
         x_pending = false;
     }
 

@@ -269,7 +269,45 @@ __global__ __launch_bounds__(kBlock) void k_fin_check(int nb, int C, int init, i
 // (the expansion of the low-rank correction); partial[b, c] = sum r z and,
 // when FLEX, partial_qz[b, c] = sum q z (q = A p of this iteration: the
 // numerator of the flexible beta).
-// z2 != nullptr: z is also written there (the first search direction).
+// z of one row and lane: the V-cycle output s plus the low-rank correction
+// U_a W_a of the lane's subsystems (wl: W staged in LDS).  The z-finish kernel
+// and the rebuilding p update both form z through this function, so the two
+// agree bit for bit.
+template <int VW, typename TS, bool LRC, typename TU>
+__device__ __forceinline__ Pack<double, VW> z_lane(int64_t row, int64_t o, int lane, const TS* s,
+                                                   const TU* __restrict__ U, const double* wl, int S, int k, int m) {
+    Pack<double, VW> zv;
+    const Pack<TS, VW> sv = ld<TS, VW>(s + o);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) zv.e[e] = (double)to_acc(sv.e[e]);
+    if (LRC) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            const int col = lane * VW + e;
+            const int a = col / m, j = col % m;
+            if (a < S) {
+                const TU* u = U + row * (S * k) + a * k;
+                const double* w = wl + (a * k) * m + j;
+                double t2 = 0.0;
+                int t = 0;
+                for (; (k & 3) == 0 && t + 4 <= k; t += 4) {   // aligned 4-wide loads when k % 4 == 0
+                    const Pack<TU, 4> u4 = ld<TU, 4>(u + t);
+                    t2 += (double)to_acc(u4.e[0]) * w[t * m];
+                    t2 += (double)to_acc(u4.e[1]) * w[(t + 1) * m];
+                    t2 += (double)to_acc(u4.e[2]) * w[(t + 2) * m];
+                    t2 += (double)to_acc(u4.e[3]) * w[(t + 3) * m];
+                }
+                for (; t < k; ++t) t2 += (double)to_acc(u[t]) * w[t * m];
+                zv.e[e] += t2;
+            }
+        }
+    }
+    return zv;
+}
+
+// z == nullptr: z is not stored (the mixed modes, whose p update rebuilds it
+// with k_pupdate_rebuild).  z2 != nullptr: z is written there (the first
+// search direction).
 template <int C, typename TS, bool LRC, typename TU, bool FLEX>
 __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, double* z, const double* __restrict__ r,
                                                     const TU* __restrict__ U, const double* __restrict__ W, int S,
@@ -293,33 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
         const int64_t row = tile * RPB + slot;
         if (row >= n) continue;
         const int64_t o = row * C + lane * VW;
-        Pack<double, VW> zv;
-        const Pack<TS, VW> sv = ld<TS, VW>(s + o);
-#pragma unroll
-        for (int e = 0; e < VW; ++e) zv.e[e] = (double)to_acc(sv.e[e]);
-        if (LRC) {
-#pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                const int col = lane * VW + e;
-                const int a = col / m, j = col % m;
-                if (a < S) {
-                    const TU* u = U + row * (S * k) + a * k;
-                    const double* w = wl + (a * k) * m + j;
-                    double t2 = 0.0;
-                    int t = 0;
-                    for (; (k & 3) == 0 && t + 4 <= k; t += 4) {   // aligned 4-wide loads when k % 4 == 0
-                        const Pack<TU, 4> u4 = ld<TU, 4>(u + t);
-                        t2 += (double)to_acc(u4.e[0]) * w[t * m];
-                        t2 += (double)to_acc(u4.e[1]) * w[(t + 1) * m];
-                        t2 += (double)to_acc(u4.e[2]) * w[(t + 2) * m];
-                        t2 += (double)to_acc(u4.e[3]) * w[(t + 3) * m];
-                    }
-                    for (; t < k; ++t) t2 += (double)to_acc(u[t]) * w[t * m];
-                    zv.e[e] += t2;
-                }
-            }
-        }
-        st<double, VW>(z + o, zv);
+        const Pack<double, VW> zv = z_lane<VW, TS, LRC, TU>(row, o, lane, s, U, wl, S, k, m);
+        if (z) st<double, VW>(z + o, zv);
         if (z2) st<double, VW>(z2 + o, zv);
         const Pack<double, VW> rv = ld<double, VW>(r + o);
 #pragma unroll
@@ -332,6 +345,53 @@ __global__ __launch_bounds__(kBlock) void k_zfinish(int64_t n, const TS* s, doub
     }
     block_column_sums<C, VW>(acc, sm, partial + (int64_t)blockIdx.x * C);
     if (FLEX) block_column_sums<C, VW>(aqz, sm, partial_qz + (int64_t)blockIdx.x * C);
+}
+
+// x += alpha p (this iteration's x step; alpha = 0 on frozen columns), then
+// p = z + beta p on active columns, with z rebuilt from the V-cycle output s
+// and U W exactly as the z-finish kernel formed it (the mixed modes store no
+// z: s and U are read instead of the FP64 z).  Grid-stride over row tiles,
+// W staged in LDS once per block.
+template <int C, typename TS, bool LRC, typename TU>
+__global__ __launch_bounds__(kBlock) void k_pupdate_rebuild(int64_t n, double* __restrict__ x, double* __restrict__ p,
+                                                            const TS* __restrict__ s, const TU* __restrict__ U,
+                                                            const double* __restrict__ W, int S, int k, int m,
+                                                            const double* __restrict__ alpha,
+                                                            const double* __restrict__ beta,
+                                                            const int* __restrict__ active, int gated) {
+    if (alpha_gate_closed(alpha, gated != 0)) return;
+    constexpr int VW = DL<C>::VW, LPR = DL<C>::LPR, RPB = DL<C>::RPB;
+    __shared__ double wl[LRC ? 64 * 16 : 1];
+    const int slot = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+    const int64_t ntiles = (n + RPB - 1) / RPB;
+    if (LRC) {
+        for (int o = threadIdx.x; o < S * k * m; o += kBlock) wl[o] = W[o];
+        __syncthreads();
+    }
+    double al[VW], be[VW];
+    bool on[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+        const int c = lane * VW + e;
+        al[e] = alpha[c];
+        be[e] = beta[c];
+        on[e] = active[c] != 0;
+    }
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row = tile * RPB + slot;
+        if (row >= n) continue;
+        const int64_t o = row * C + lane * VW;
+        Pack<double, VW> pv = ld<double, VW>(p + o);
+        Pack<double, VW> xv = ld<double, VW>(x + o);
+        const Pack<double, VW> zv = z_lane<VW, TS, LRC, TU>(row, o, lane, s, U, wl, S, k, m);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            xv.e[e] += al[e] * pv.e[e];
+            if (on[e]) pv.e[e] = zv.e[e] + be[e] * pv.e[e];
+        }
+        st<double, VW>(x + o, xv);
+        st<double, VW>(p + o, pv);
+    }
 }
 
 // beta and rho = <r,z> on active columns; INIT: rho = <r,z> for every
@@ -442,6 +502,41 @@ template hipError_t zfinish_grid<float, double>(int, bool, bool, int64_t, int*);
 template hipError_t zfinish_grid<Bf16, float>(int, bool, bool, int64_t, int*);
 template hipError_t zfinish_grid<Bf16, double>(int, bool, bool, int64_t, int*);
 template hipError_t zfinish_grid<Bf16, Bf16>(int, bool, bool, int64_t, int*);
+
+template <typename TS, typename TU>
+hipError_t pupdate_rebuild_grid(int C, bool lrc, int64_t n, int* nb) {
+    MSP_DISPATCH_C(C, {
+        return lrc ? resident_grid<CC>(k_pupdate_rebuild<CC, TS, true, TU>, 0, n, nb)
+                   : resident_grid<CC>(k_pupdate_rebuild<CC, TS, false, TU>, 0, n, nb);
+    });
+    return hipErrorInvalidValue;
+}
+
+template <typename TS, typename TU>
+hipError_t launch_pupdate_rebuild(hipStream_t st, int C, int nb, int64_t n, double* x, double* p, const TS* s,
+                                  const TU* U, const double* W, int S, int k, int m, const double* alpha,
+                                  const double* beta, const int* active, bool gated) {
+    if (U && k > 0 && S * k * m > 64 * 16) return hipErrorInvalidValue;
+    MSP_DISPATCH_C(C, {
+        if (U && k > 0)
+            hipLaunchKernelGGL((k_pupdate_rebuild<CC, TS, true, TU>), dim3(nb), dim3(kBlock), 0, st, n, x, p, s, U, W,
+                               S, k, m, alpha, beta, active, gated ? 1 : 0);
+        else
+            hipLaunchKernelGGL((k_pupdate_rebuild<CC, TS, false, TU>), dim3(nb), dim3(kBlock), 0, st, n, x, p, s, U, W,
+                               S, k, m, alpha, beta, active, gated ? 1 : 0);
+    });
+    return hipGetLastError();
+}
+#define MSP_PUPDATE_INST(TS, TU)                                                                                   \
+    template hipError_t pupdate_rebuild_grid<TS, TU>(int, bool, int64_t, int*);                                     \
+    template hipError_t launch_pupdate_rebuild<TS, TU>(hipStream_t, int, int, int64_t, double*, double*, const TS*, \
+                                                       const TU*, const double*, int, int, int, const double*,      \
+                                                       const double*, const int*, bool);
+MSP_PUPDATE_INST(float, float)
+MSP_PUPDATE_INST(float, double)
+MSP_PUPDATE_INST(Bf16, float)
+MSP_PUPDATE_INST(Bf16, double)
+MSP_PUPDATE_INST(Bf16, Bf16)
 
 hipError_t launch_op_dot(hipStream_t st, int C, int nb, int64_t n, const int32_t* rp, const int32_t* ci,
                          const double* va, SellRef sl, OuterDiag sigma, int S, int m, const double* p, double* q,

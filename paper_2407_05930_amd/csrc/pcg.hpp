@@ -36,12 +36,23 @@ hipError_t launch_update_dots(hipStream_t st, int C, int nb, bool upd, int k, in
 hipError_t launch_fin_check(hipStream_t st, int C, int nb, bool init, int O, int m, const double* prr,
                             const double* plrc, const double* thr, const double* coef, int* active, int* iters,
                             int* flags, double* rnorm, double* W);
-// z2 != nullptr: z also written there (the first search direction p = z).
+// z == nullptr: z is not stored.  z2 != nullptr: z also written there (the
+// first search direction p = z).
 // q != nullptr (flexible beta): partial_qz also receives the partials of <q, z>.
 template <typename TS, typename TU>
 hipError_t launch_zfinish(hipStream_t st, int C, int nb, int64_t n, const TS* s, double* z, const double* r,
                           const TU* U, const double* W, int S, int k, int m, double* partial, double* z2 = nullptr,
                           const double* q = nullptr, double* partial_qz = nullptr, const int* gate = nullptr);
+// The p update of the mixed modes, which store no z: x += alpha p, then
+// p = z + beta p with z rebuilt from the V-cycle output s and U W (bit for bit
+// the z of launch_zfinish with the same s, U, W).  Grid-stride; nb from
+// pupdate_rebuild_grid.  S * k * m <= 1024 when U is given.
+template <typename TS, typename TU>
+hipError_t pupdate_rebuild_grid(int C, bool lrc, int64_t n, int* nb);
+template <typename TS, typename TU>
+hipError_t launch_pupdate_rebuild(hipStream_t st, int C, int nb, int64_t n, double* x, double* p, const TS* s,
+                                  const TU* U, const double* W, int S, int k, int m, const double* alpha,
+                                  const double* beta, const int* active, bool gated);
 // flex (non-initial calls): beta = -<q,z>/<p,q> from partial_qz and pq
 hipError_t launch_fin_beta(hipStream_t st, int C, int nb, bool init, bool flex, const double* partial,
                            const double* partial_qz, const int* active, const double* pq, double* rho, double* beta,

@@ -102,8 +102,11 @@ class Solver:
     # ------------------------------------------------------------------ solves
     def solve(self, b, stream=None):
         """Solve A x = b for a torch tensor b on the context's GPU, shape (n,)
-        or (n, m), float64.  Returns x with b's shape.  ``stream`` is a
-        torch.cuda.Stream (default: the current stream)."""
+        or (n, m), float64.  Returns x with b's shape.  The library takes and
+        writes n x m column-major arrays: a b already column-major (the
+        transpose of a contiguous (m, n) tensor) is passed without a copy, and
+        x is returned as the column-major view the library wrote.  ``stream``
+        is a torch.cuda.Stream (default: the current stream)."""
         import torch
         vec = b.dim() == 1
         B = b.reshape(self.n, -1)
@@ -119,7 +122,7 @@ class Solver:
         self.status = rc
         _warn_not_converged(rc, "Solver.solve")
         x = xt.t()
-        return x.reshape(-1) if vec else x.contiguous()
+        return x.reshape(-1) if vec else x
 
     def solve_host(self, b: np.ndarray) -> np.ndarray:
         vec = b.ndim == 1
@@ -324,7 +327,7 @@ class BatchSolver:
         st = stream if stream is not None else torch.cuda.current_stream(bs[0].device)
         self.status = check(lib.msp_batch_solve(self._h, ms, pb, px, ctypes.c_void_p(st.cuda_stream), self.stats))
         _warn_not_converged(self.status, "BatchSolver.solve")
-        return [x.t().reshape(-1) if vec else x.t().contiguous() for x, vec in zip(xts, shapes)]
+        return [x.t().reshape(-1) if vec else x.t() for x, vec in zip(xts, shapes)]
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
