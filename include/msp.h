@@ -131,6 +131,14 @@ typedef struct {
     int32_t coarse64;    /* mixed modes with MSP_PC_AMGR_SUB: 1 = the per-subsystem coarsest
                             inverses are read in FP64 (the V-cycle's vectors are converted at that
                             level), 0 = rounded to FP32 (default) */
+    int32_t nu1, nu2;    /* smoothing sweeps before and after the coarse correction on every level
+                            (Alg. 3): s = M y then nu1 - 1 sweeps s += M (y - A s); after the
+                            correction nu2 such sweeps.  1..8 and nu1 == nu2 (PCG needs a symmetric
+                            cycle; otherwise MSP_ERR_UNSUPPORTED).  Default 1, 1 */
+    int32_t true_residual;   /* 1: after the solve the library forms b - A x from x and b and reports
+                                ||b - A x|| / ||b|| per right-hand side in msp_stats.relres_true
+                                (two transforms, one operator product and one dot more); 0 (default):
+                                relres_true is -1 */
 } msp_opts;
 
 typedef struct {
@@ -148,12 +156,17 @@ typedef struct {
     double avg_nnzr;             /* nnz(A_1) / n_1 */
     double t_setup_s;
     double t_solve_s;
+    double relres_true[64];      /* per RHS with opts.true_residual = 1: ||b - A x|| / ||b|| formed
+                                    after the solve from the returned x; -1 otherwise */
+    double t_vcycle_s;           /* GPU time of the V-cycle's kernels in the last solve, summed from the
+                                    per-kernel event timers (msp_set_timing); -1 when none of the
+                                    V-cycle timers is on */
 } msp_stats;
 
 /* Fill *o with the defaults: FP64, AMGR, k = 0, d = 2, theta = 0.25,
    jacobi0 = 3, jacobi = 1, coarse_max = 2560, max_levels = 20,
    max_ratio = 0.8, tol = 1e-10, maxit = 1000, device = 0, seed = 240705930,
-   trunc0 = 0.05, coarse64 = 0. */
+   trunc0 = 0.05, coarse64 = 0, nu1 = nu2 = 1, true_residual = 0. */
 int msp_default_opts(msp_opts* o);
 
 /* Build a context from A and its symmetry map.  Validates the map

@@ -387,6 +387,8 @@ class Level:
 class Hierarchy:
     levels: List[Level]
     coarse_factor: tuple = None        # cho_factor of the coarsest matrix
+    nu1: int = 1                       # pre- and post-smoothing sweeps of Alg. 3
+    nu2: int = 1
 
     @property
     def nlev(self):
@@ -412,6 +414,8 @@ class AMGOptions:
     max_ratio: float = 0.8
     seed: int = 240705930
     mis_method: str = "rounds"
+    nu1: int = 1              # smoothing sweeps before and after the coarse correction (Alg. 3)
+    nu2: int = 1
 
 
 def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions,
@@ -456,22 +460,26 @@ def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions,
         lev += 1
     Ad = levels[-1].A.toarray()
     factor = sla.cho_factor(Ad, lower=True)
-    return Hierarchy(levels=levels, coarse_factor=factor)
+    return Hierarchy(levels=levels, coarse_factor=factor, nu1=opt.nu1, nu2=opt.nu2)
 
 
 def vcycle(H: Hierarchy, y: np.ndarray, lev: int = 0) -> np.ndarray:
-    """Alg. 3 with nu1 = nu2 = 1 and smoother M = omega G^T G:
-    s = M y; r = y - A s; h_c = V(R r); s += P h_c; s += M (y - A s).
+    """Alg. 3 with smoother M = omega G^T G and nu1 / nu2 sweeps (H.nu1,
+    H.nu2) on every level: s = M y, then nu1 - 1 times s += M (y - A s);
+    r = y - A s; h_c = V(R r); s += P h_c; then nu2 times s += M (y - A s).
     ``y`` may hold several columns."""
     if lev == H.nlev - 1:
         return sla.cho_solve(H.coarse_factor, y)
     L = H.levels[lev]
     GT = L.G.T
     s = L.omega * (GT @ (L.G @ y))
+    for _ in range(H.nu1 - 1):
+        s = s + L.omega * (GT @ (L.G @ (y - L.A @ s)))
     r = y - L.A @ s
     hc = vcycle(H, L.R @ r, lev + 1)
     s = s + L.P @ hc
-    s = s + L.omega * (GT @ (L.G @ (y - L.A @ s)))
+    for _ in range(H.nu2):
+        s = s + L.omega * (GT @ (L.G @ (y - L.A @ s)))
     return s
 
 
@@ -491,6 +499,8 @@ class SubHierarchy:
     share one sparsity pattern per level) and each subsystem's own values."""
     level0: Level
     subs: List[Hierarchy]          # per subsystem: levels 1.. (coarsest dense)
+    nu1: int = 1
+    nu2: int = 1
 
 
 def sub_level_values(A: sp.csr_matrix, shared: Level, steps: int, seed: int, level0: bool) -> Level:
@@ -526,8 +536,8 @@ def build_sub_hierarchy(hier: Hierarchy, sigma: np.ndarray, opt: AMGOptions) -> 
             levels.append(Lv)
             A = galerkin(A, Lv.P)
         fac = sla.cho_factor(levels[-1].A.toarray(), lower=True)
-        subs.append(Hierarchy(levels=levels, coarse_factor=fac))
-    return SubHierarchy(level0=L0, subs=subs)
+        subs.append(Hierarchy(levels=levels, coarse_factor=fac, nu1=opt.nu1, nu2=opt.nu2))
+    return SubHierarchy(level0=L0, subs=subs, nu1=opt.nu1, nu2=opt.nu2)
 
 
 def vcycle_sub(SH: SubHierarchy, Ahat_a: sp.csr_matrix, a: int, y: np.ndarray) -> np.ndarray:
@@ -537,8 +547,11 @@ def vcycle_sub(SH: SubHierarchy, Ahat_a: sp.csr_matrix, a: int, y: np.ndarray) -
     L = SH.level0
     GT = L.G.T
     s = L.omega * (GT @ (L.G @ y))
+    for _ in range(SH.nu1 - 1):
+        s = s + L.omega * (GT @ (L.G @ (y - Ahat_a @ s)))
     r = y - Ahat_a @ s
     hc = vcycle(SH.subs[a], L.R @ r, 0)
     s = s + L.P @ hc
-    s = s + L.omega * (GT @ (L.G @ (y - Ahat_a @ s)))
+    for _ in range(SH.nu2):
+        s = s + L.omega * (GT @ (L.G @ (y - Ahat_a @ s)))
     return s

@@ -53,14 +53,16 @@ class msp_opts(ctypes.Structure):
                 ("jacobi", ctypes.c_int32), ("coarse_max", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("max_ratio", ctypes.c_double), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("trunc0", ctypes.c_double),
-                ("coarse64", ctypes.c_int32)]
+                ("coarse64", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
+                ("true_residual", ctypes.c_int32)]
 
 
 class msp_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres_rec", ctypes.c_double * 64),
                 ("nlev", ctypes.c_int32), ("rows", ctypes.c_int64 * 32), ("nnz", ctypes.c_int64 * 32),
                 ("op_complexity", ctypes.c_double), ("c_rat", ctypes.c_double), ("avg_nnzr", ctypes.c_double),
-                ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
+                ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
+                ("relres_true", ctypes.c_double * 64), ("t_vcycle_s", ctypes.c_double)]
 
 
 class msp_faces(ctypes.Structure):

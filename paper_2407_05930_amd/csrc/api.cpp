@@ -119,7 +119,7 @@ struct Work {
     HostBufs own;             // pinned buffers this workspace allocated (freed with the context)
 };
 
-enum { SC_RR = 0, SC_RZ, SC_PQ, SC_RHO, SC_ALPHA, SC_BETA, SC_THR, SC_RNORM, SC_BN2, SC_COUNT };
+enum { SC_RR = 0, SC_RZ, SC_PQ, SC_RHO, SC_ALPHA, SC_BETA, SC_THR, SC_RNORM, SC_BN2, SC_TRUE, SC_COUNT };
 
 // Launch classes for the optional per-kernel timers (msp_set_timing).
 enum {
@@ -374,6 +374,20 @@ static void resolve_timers(msp_ctx* c) {
         c->tm.pool.push_back(p.e1);
     }
     c->tm.pending.clear();
+}
+
+// V-cycle kinds: the level products and the dense coarsest solve
+static bool is_vcycle_kind(int kind) { return kind >= KD_LEVEL || kind == KD_DENSE; }
+static bool vcycle_timed(const msp_ctx* c) {
+    for (int k = 0; k < KD_COUNT; ++k)
+        if (is_vcycle_kind(k) && c->tm.on[k]) return true;
+    return false;
+}
+static double vcycle_ms(const msp_ctx* c) {
+    double t = 0.0;
+    for (int k = 0; k < KD_COUNT; ++k)
+        if (is_vcycle_kind(k)) t += c->tm.ms[k];
+    return t;
 }
 
 // Algorithmic bytes of Y = alpha (M X) + beta Z: the matrix once, X once,
@@ -993,12 +1007,18 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     const DevOuter* sg = !c->sub ? nullptr : (l == 0 ? &c->dsig : (l == 1 ? &c->dsig1 : nullptr));
     const int m = w.m;
     smooth(y, TC(0));                                                      // pre-smooth from zero: s = M y
+    for (int i = 1; i < c->o.nu1; ++i) {                                   // further sweeps s += M (y - A s)
+        spmm<T>(c, kb + 0, st, C, L.A, s, r, y, TC(-1), TC(1), sg, S, m);
+        smooth(r, TC(1));
+    }
     spmm<T>(c, kb + 0, st, C, L.A, s, r, y, TC(-1), TC(1), sg, S, m);      // r = y - A s
     spmm<T>(c, kb + 3, st, C, L.R, r, yc, nullptr, TC(1), TC(0), nullptr, S, m);   // r_c = P^T r
     vcycle<T>(c, w, st, l + 1, yc, sc);                                    // coarse correction
     spmm<T>(c, kb + 4, st, C, L.P, sc, s, s, TC(1), TC(1), nullptr, S, m);  // s += P h_c
-    spmm<T>(c, kb + 0, st, C, L.A, s, r, y, TC(-1), TC(1), sg, S, m);      // post-smooth: s += M (y - A s)
-    smooth(r, TC(1));
+    for (int i = 0; i < c->o.nu2; ++i) {                                   // post-smooth: s += M (y - A s)
+        spmm<T>(c, kb + 0, st, C, L.A, s, r, y, TC(-1), TC(1), sg, S, m);
+        smooth(r, TC(1));
+    }
 }
 
 // out[c] = <X_c, Y_c> for the C columns of two n_b x C multivectors.
@@ -1201,6 +1221,9 @@ struct SolvePlan {
     int m, S, C, kl, O;
     int nbo = 0, nbu = 0, nbz = 0;   // grids of the operator, update and z-finish kernels (partial rows)
     int nbp = 0;                     // grid of the rebuilding p update (mixed modes)
+    const double* d_b0 = nullptr;    // the caller's right-hand sides (the true residual reads them again)
+    bool vc_on = false;              // some V-cycle timer is on: t_vcycle_s is reported
+    double vc_ms0 = 0.0;             // V-cycle timer total when this solve began
     int64_t nb, n;
     bool flexible, lrc_amg;
     bool x_pending = false;   // an x += alpha p step not yet applied
@@ -1408,6 +1431,9 @@ struct SolvePlan {
 
     void begin(const double* d_b) {
         Work& W = *w;
+        d_b0 = d_b;
+        vc_on = vcycle_timed(c);
+        vc_ms0 = vcycle_ms(c);
         HIPCHECK(launch_colnorm2(st, n, m, d_b, W.pp1, std::min<int64_t>(512, (n + 255) / 256), bn2));
         HIPCHECK(launch_thresholds(st, C, S, m, c->o.tol, bn2, thr));
         if (S * m < C) HIPCHECK(launch_fill<double>(st, nb * C, W.r, 0.0));   // padded columns (Q_s writes the rest)
@@ -1522,6 +1548,16 @@ struct SolvePlan {
             HIPCHECK(launch_qs_backward(st, S, nb, m, C, n, c->d_img, W.x, d_x, xp ? W.p : nullptr,
                                         xp ? alpha : nullptr));
         }, [&] { return "k_qs_backward<" + std::to_string(S) + ">"; });
+        const bool tr = c->o.true_residual != 0 && status != MSP_ERR_BREAKDOWN;
+        if (tr) {
+            // b - A x from the returned x: Q_s is orthogonal, so ||b - A x|| = ||bhat - Ahat xhat|| with
+            // bhat = Q_s b and xhat = Q_s x formed afresh (r, q, p are free once x is out)
+            HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_b0, W.r));
+            HIPCHECK(launch_qs_forward(st, S, nb, m, C, n, c->d_img, d_x, W.q));
+            HIPCHECK((launch_spmm<double, double>(st, C, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, W.q, W.p, W.r,
+                                                  -1.0, 1.0, c->dsig.d, S, m, 1, false, nullptr)));
+            dot(c, W, st, W.p, W.p, W.scal + SC_TRUE * 64);
+        }
         HIPCHECK(hipMemcpyAsync(W.h_iters, iters, 64 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipMemcpyAsync(W.h_scal, W.scal, SC_COUNT * 64 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipMemcpyAsync(W.h_flags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1542,6 +1578,16 @@ struct SolvePlan {
             const double bn = std::sqrt(W.h_scal[SC_BN2 * 64 + j]);
             R.relres_rec[j] = bn > 0 ? std::sqrt(s2) / bn : 0.0;
         }
+        for (int j = 0; j < 64; ++j) R.relres_true[j] = -1.0;
+        if (tr)
+            for (int j = 0; j < m && j < 64; ++j) {
+                double s2 = 0.0;
+                for (int a = 0; a < S; ++a) s2 += W.h_scal[SC_TRUE * 64 + a * m + j];
+                const double bn = std::sqrt(W.h_scal[SC_BN2 * 64 + j]);
+                R.relres_true[j] = bn > 0 ? std::sqrt(s2) / bn : 0.0;
+            }
+        R.t_vcycle_s = -1.0;
+        if (vc_on) R.t_vcycle_s = (vcycle_ms(c) - vc_ms0) * 1e-3;
         R.status = status;
         R.t_solve_s = seconds;
         if (out) *out = R;
@@ -1649,6 +1695,10 @@ static void check_opts(const msp_opts* o) {
     if (o->lrc_k > 16) throw Error(MSP_ERR_UNSUPPORTED, "low-rank correction rank above 16");
     if (o->coarse64 != 0 && o->coarse64 != 1) throw Error(MSP_ERR_ARG, "coarse64 must be 0 or 1");
     if (o->max_levels > msp::kMaxLevels) throw Error(MSP_ERR_UNSUPPORTED, "more than 32 levels");
+    if (o->nu1 < 1 || o->nu1 > 8 || o->nu2 < 1 || o->nu2 > 8) throw Error(MSP_ERR_ARG, "nu1 and nu2 must be in 1..8");
+    if (o->nu1 != o->nu2)
+        throw Error(MSP_ERR_UNSUPPORTED, "nu1 != nu2 makes the V-cycle non-symmetric, which PCG cannot take");
+    if (o->true_residual != 0 && o->true_residual != 1) throw Error(MSP_ERR_ARG, "true_residual must be 0 or 1");
 }
 
 // Host part of the setup: blocks, validation, hierarchy (no HIP calls).

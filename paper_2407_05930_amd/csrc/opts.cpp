@@ -23,5 +23,8 @@ extern "C" int msp_default_opts(msp_opts* o) {
     o->device = 0;
     o->seed = 240705930ull;
     o->coarse64 = 0;
+    o->nu1 = 1;
+    o->nu2 = 1;
+    o->true_residual = 0;
     return MSP_OK;
 }

@@ -447,3 +447,51 @@ def test_repeated_solve_is_bitwise_identical(prec):
     x1 = sv.solve(b)
     x2 = sv.solve(b)
     assert torch.equal(x1, x2)
+
+
+@pytest.mark.parametrize("pc", ["amgr", "amgr_sub"])
+def test_fp64_two_sweeps_match_oracle(pc):
+    """V(2,2) (nu1 = nu2 = 2 on every level, Alg. 3) against the oracle's cycle
+    with the same sweeps: equal iteration counts, x element-wise to 1e-9."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    p = make_problem((24, 16, 20), s=2, m=3, seed=23, y_stretch=1.5)
+    opt = amg.AMGOptions(coarse_max=40, nu1=2, nu2=2)
+    ctx = krylov.setup(p.A, p.img, opt, precond=pc)
+    ref = krylov.solve(ctx, p.b, tol=TOL)
+    sv = Solver(p.A, p.img, tol=TOL, pc=pc, coarse_max=40, nu1=2, nu2=2)
+    x = sv.solve(torch.from_numpy(p.b).cuda()).cpu().numpy()
+    one = Solver(p.A, p.img, tol=TOL, pc=pc, coarse_max=40)
+    one.solve(torch.from_numpy(p.b).cuda())
+    _say(pc, "V(2,2) iters", sv.last.iters, "oracle", int(ref.iters.max()), "V(1,1)", one.last.iters)
+    assert sv.last.iters == int(ref.iters.max())
+    assert sv.last.iters <= one.last.iters
+    _agree(x, ref.x)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_bf16"])
+def test_true_residual_and_vcycle_time_are_reported(prec):
+    """opts.true_residual = 1: relres_true equals ||b - A x|| / ||b|| formed on
+    the host from the returned x; t_vcycle_s is the V-cycle's share of the
+    solve when its timers are on, -1 when they are off."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    p = make_problem((24, 24, 24), s=3, m=3, seed=24, y_stretch=1.5)
+    sv = Solver(p.A, p.img, tol=1e-10, precision=prec, pc="amgr_sub", coarse_max=64, true_residual=1)
+    b = torch.from_numpy(p.b).cuda()
+    x = sv.solve(b).cpu().numpy()
+    ref = krylov.true_relres(p.A, x, p.b)
+    got = np.array(sv.last.relres_true[:3])
+    _say(prec, "relres_true", got, "host", ref, "recursive", list(sv.last.relres_rec[:3]))
+    assert np.all(np.abs(got - ref) <= 1e-3 * ref + 1e-15)
+    assert np.all(got <= 1.5e-10)
+    assert all(v == -1.0 for v in sv.last.relres_true[3:])
+    assert sv.last.t_vcycle_s == -1.0
+    sv.set_timing(True)
+    sv.solve(b)
+    t_v, t_s = sv.last.t_vcycle_s, sv.last.t_solve_s
+    _say(prec, "t_vcycle_s", t_v, "t_solve_s", t_s)
+    assert 0.0 < t_v < t_s
+    plain = Solver(p.A, p.img, tol=1e-10, precision=prec, pc="amgr_sub", coarse_max=64)
+    plain.solve(b)
+    assert all(v == -1.0 for v in plain.last.relres_true[:3])

@@ -102,6 +102,20 @@ def test_hierarchy_bit_exact_with_oracle_at_full_size(which):
     assert np.array_equal(iface, ctx["interface"])
 
 
+def test_smoothing_sweep_and_residual_options_are_validated():
+    from paper_2407_05930_amd import MspError, Solver
+    from paper_2407_05930_amd.solver import default_opts
+    o = default_opts()
+    assert (o.nu1, o.nu2, o.true_residual) == (1, 1, 0)
+    p = make_problem((8, 8), s=1, seed=2)
+    for kw, status in ((dict(nu1=2, nu2=1), -8), (dict(nu1=0, nu2=0), -1), (dict(nu1=9, nu2=9), -1),
+                       (dict(true_residual=2), -1)):
+        with pytest.raises(MspError) as e:
+            Solver(p.A, p.img, device=-1, **kw)
+        assert e.value.status == status, kw
+    Solver(p.A, p.img, device=-1, nu1=3, nu2=3)
+
+
 def test_setup_rejects_bad_inputs():
     from paper_2407_05930_amd import Solver, MspError
     p = make_problem((8, 8), s=1, seed=2, y_stretch=1.5)

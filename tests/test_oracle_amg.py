@@ -1,6 +1,7 @@
 """Pins of the multigrid-reduction part of the oracle (Sec. 3.2: Alg. 2,
 eqs. (3.13)-(3.15), Alg. 3) against invariants, special cases that reduce
 to textbook formulas, and brute force."""
+import dataclasses
 import itertools
 
 import numpy as np
@@ -438,3 +439,63 @@ def test_truncated_reduction_keeps_convergence():
         res[tr] = (int(r.iters.max()), ctx["hier"].levels[1].A.nnz)
     assert res[0.05][1] < res[0.0][1]
     assert res[0.05][0] <= res[0.0][0] + 1
+
+
+# ----------------------------------------------------------------- nu1 / nu2 sweeps (Alg. 3)
+
+def test_two_grid_with_two_sweeps_matches_error_propagation():
+    """Two levels, nu1 = nu2 = 2: I - V A = (I - M A)^2 (I - P A_c^{-1} P^T A) (I - M A)^2,
+    for the shared cycle and for the per-subsystem cycle."""
+    hier, sigma, Ahat, opt = _sub(coarse_max=200)
+    opt2 = dataclasses.replace(opt, nu1=2, nu2=2)
+    # shared cycle on A_inn with its interface
+    p = make_problem((12, 12, 12), s=3, seed=4)
+    Hb = symmetry.base_blocks(p.A, p.img)
+    Ainn, _ = symmetry.inner_outer(Hb)
+    iface = symmetry.interface_rows(Hb)
+    Hs = amg.build_hierarchy(Ainn.tocsr(), iface, opt2)
+    assert Hs.nlev == 2 and Hs.nu1 == 2
+    L0 = Hs.levels[0]
+    n = L0.A.shape[0]
+    I = np.eye(n)
+    Ad = L0.A.toarray()
+    P = L0.P.toarray()
+    M = L0.omega * L0.G.toarray().T @ L0.G.toarray()
+    V = np.column_stack([amg.vcycle(Hs, e) for e in I])
+    S = (I - M @ Ad) @ (I - M @ Ad)
+    E = S @ (I - P @ np.linalg.solve(P.T @ Ad @ P, P.T @ Ad)) @ S
+    assert np.abs((I - V @ Ad) - E).max() < 1e-10
+    # one sweep fewer on either side is a different operator
+    S1 = I - M @ Ad
+    assert np.abs((I - V @ Ad) - S1 @ (I - P @ np.linalg.solve(P.T @ Ad @ P, P.T @ Ad)) @ S).max() > 1e-3
+    SH = amg.build_sub_hierarchy(hier, sigma, opt2)
+    G = hier.levels[0].G.toarray()
+    Mh = hier.levels[0].omega * G.T @ G
+    Ph = hier.levels[0].P.toarray()
+    Ih = np.eye(Ph.shape[0])
+    for a in (0, 5):
+        Aa = Ahat[a].toarray()
+        Va = np.column_stack([amg.vcycle_sub(SH, Ahat[a], a, e) for e in Ih])
+        Sa = (Ih - Mh @ Aa) @ (Ih - Mh @ Aa)
+        Ea = Sa @ (Ih - Ph @ np.linalg.solve(Ph.T @ Aa @ Ph, Ph.T @ Aa)) @ Sa
+        assert np.abs((Ih - Va @ Aa) - Ea).max() < 1e-10
+
+
+def test_symmetric_sweeps_keep_the_cycle_symmetric_and_help_pcg():
+    """V(2,2) on three or more levels is symmetric positive definite, and PCG
+    needs no more iterations with it than with V(1,1)."""
+    A, iface = _inner((10, 10, 10))
+    opt1 = amg.AMGOptions(coarse_max=20)
+    opt2 = dataclasses.replace(opt1, nu1=2, nu2=2)
+    H1 = amg.build_hierarchy(A, iface, opt1)
+    H2 = amg.build_hierarchy(A, iface, opt2)
+    assert H2.nlev >= 3
+    I = np.eye(A.shape[0])
+    V = np.column_stack([amg.vcycle(H2, e) for e in I])
+    assert np.abs(V - V.T).max() <= 1e-12 * np.abs(V).max()
+    assert np.linalg.eigvalsh(0.5 * (V + V.T)).min() > 0
+    b = np.random.default_rng(3).standard_normal((A.shape[0], 1))
+    thr = 1e-10 * np.linalg.norm(b, axis=0)
+    r1 = krylov.pcg_columns(lambda X: A @ X, lambda R: amg.vcycle(H1, R), b, thr, 200)
+    r2 = krylov.pcg_columns(lambda X: A @ X, lambda R: amg.vcycle(H2, R), b, thr, 200)
+    assert r2.converged.all() and r2.iters.max() <= r1.iters.max()
