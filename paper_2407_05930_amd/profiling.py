@@ -4,6 +4,8 @@
     python -m paper_2407_05930_amd.profiling traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> <kernel name> <copy bytes> <out.md> <command...>
     python -m paper_2407_05930_amd.profiling counters <counter_collection.csv> <out.md> <command...>
+    python -m paper_2407_05930_amd.profiling vcycle <fetch.csv> <write.csv> <l2.csv> <copy bytes>
+        <bench.json> <out.md> <command...>
 
 ``window`` keeps the dispatches between the two int16 fill kernels that
 bench.py launches just before and just after the timed steps of the headline
@@ -162,6 +164,92 @@ def counters(path, out, command):
     open(out, "w").write("\n".join(lines) + "\n")
 
 
+VCYCLE_KERNELS = ("k_spmm", "k_sell", "k_pack_sets", "k_dense_sets", "k_dense_part", "k_dense_sum")
+
+
+def vcycle_order(nlev):
+    """Classes of one V(1,1) cycle's dispatches in launch order with the
+    explicit smoother: per level M, A, R on the way down, the two kernels of
+    the coarsest solve, then P, A, M on the way up."""
+    down = [f"L{l}.{k}" for l in range(nlev) for k in ("M", "A", "R")]
+    up = [f"L{l}.{k}" for l in reversed(range(nlev)) for k in ("P", "A", "M")]
+    return down + ["coarsest.1", "coarsest.2"] + up
+
+
+def _label_vcycles(inside):
+    """Label the dispatches of every V-cycle (a maximal run of V-cycle
+    kernels between PCG kernels) by class; runs of another length stay
+    unlabelled."""
+    out, run = [], []
+
+    def flush():
+        if run and (len(run) - 2) % 6 == 0 and len(run) >= 8:
+            for r, cls in zip(run, vcycle_order((len(run) - 2) // 6)):
+                out.append((cls, r))
+        run.clear()
+
+    for r in inside:
+        if short_name(r["Kernel_Name"]).startswith(VCYCLE_KERNELS):
+            run.append(r)
+        else:
+            flush()
+    flush()
+    return out
+
+
+def vcycle_classes(fetch_csv, write_csv, l2_csv, copy_bytes, bench_json, out, command):
+    """Per V-cycle class: calibrated FETCH/WRITE bytes per launch against the
+    bench's algorithmic bytes, and the L2 / L1 request counters."""
+    per = {}
+    factors = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv), (None, l2_csv)):
+        items, inside, found = _dispatches(path)
+        if counter:
+            copy = [r["values"][counter] for r in items if "copy" in r["Kernel_Name"].lower() and counter in r["values"]]
+            factors[counter] = copy_bytes / (max(copy) * 1024.0)
+        for cls, r in _label_vcycles(inside):
+            e = per.setdefault(cls, dict(kernel=short_name(r["Kernel_Name"]), n={}, sums={}))
+            for cn, v in r["values"].items():
+                if counter and cn == counter:
+                    v = v * 1024.0 * factors[counter]
+                e["sums"][cn] = e["sums"].get(cn, 0.0) + v
+                e["n"][cn] = e["n"].get(cn, 0) + 1
+    alg = {}
+    if bench_json:
+        d = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        for kind, v in d.get("kernel_breakdown_mixed", {}).items():
+            if v.get("GBs") and v.get("launches"):
+                alg[kind] = v["GBs"] * 1e9 * v["ms"] * 1e-3 / v["launches"]
+    avg = lambda e, cn: e["sums"][cn] / e["n"][cn] if cn in e["sums"] else float("nan")  # noqa: E731
+    lines = ["# V-cycle traffic and cache counters per class (timed headline solves)", "",
+             f"Command: `{command}`", "", f"Library source hash: `{source_hash()}`", "",
+             "Every dispatch of a V-cycle inside the bench's window markers is labelled by its position in the cycle "
+             "(per level M, A, R down; the coarsest solve's two kernels; P, A, M up). FETCH_SIZE and WRITE_SIZE are "
+             f"calibrated by a {copy_bytes:.0f}-byte device copy (factors {factors.get('FETCH_SIZE', 0):.4f}, "
+             f"{factors.get('WRITE_SIZE', 0):.4f}); 'alg' is bench.py's algorithmic bytes per launch of the class. "
+             "TCC_HIT / TCC_MISS count L2 requests (hit rate = hits / (hits + misses)); TCP_TCC_READ_REQ counts the "
+             "read requests the vector L1 caches send to L2.", "",
+             "| class | kernel | alg MB | fetch MB | write MB | (fetch+write)/alg | L2 hit % | L1->L2 reads (M) |",
+             "|---|---|---|---|---|---|---|---|"]
+    js = {}
+    for cls in sorted(per, key=lambda c: (c.startswith("coarsest"), c)):
+        e = per[cls]
+        f, w = avg(e, "FETCH_SIZE"), avg(e, "WRITE_SIZE")
+        h, m_ = avg(e, "TCC_HIT_sum"), avg(e, "TCC_MISS_sum")
+        rq = avg(e, "TCP_TCC_READ_REQ_sum")
+        # the coarsest solve's bytes are the second kernel's (the first packs the columns by subsystem)
+        key = {"coarsest.1": None, "coarsest.2": "dense_coarse"}.get(cls, cls)
+        a = alg.get(key) if key else None
+        ratio = (f + w) / a if a else float("nan")
+        hit = 100.0 * h / (h + m_) if h == h and m_ == m_ and h + m_ > 0 else float("nan")
+        lines.append(f"| {cls} | `{e['kernel']}` | {a / 1e6 if a else float('nan'):.1f} | {f / 1e6:.1f} | "
+                     f"{w / 1e6:.1f} | {ratio:.2f} | {hit:.0f} | {rq / 1e6:.2f} |")
+        js[cls] = dict(kernel=e["kernel"], alg_bytes=a, fetch_bytes=f, write_bytes=w, l2_hit_pct=hit,
+                       l1_l2_read_req=rq)
+    open(out, "w").write("\n".join(lines) + "\n")
+    json.dump(js, open(os.path.splitext(out)[0] + ".json", "w"), indent=1)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "window":
         window(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
@@ -169,5 +257,8 @@ if __name__ == "__main__":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), sys.argv[6], " ".join(sys.argv[7:]))
     elif sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    elif sys.argv[1] == "vcycle":
+        vcycle_classes(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), sys.argv[6], sys.argv[7],
+                       " ".join(sys.argv[8:]))
     else:
         raise SystemExit(__doc__)
