@@ -216,6 +216,83 @@ def bench_jitter(args, torch, np):
                        "unknowns": int(p.n), "preconditioner": args.pc}, "variants": out}
 
 
+def dominant_roofline(sv, b, steps, torch):
+    """Roofline of the dominant kernel function of a solve: the function with
+    the largest share of one fully instrumented solve, then its launches alone
+    bracketed by HIP events on the solve's stream over ``steps`` more solves."""
+    tm_all, names, funcs = kernel_breakdown(sv, b)
+    top = max(funcs, key=lambda f: funcs[f]["ms"])
+    for kind in funcs[top]["kinds"]:
+        sv.set_timing(True, kind)
+    for _ in range(steps):
+        sv.solve(b)
+    torch.cuda.synchronize()
+    live = sv.timing()
+    sv.set_timing(False)
+    sv.reset_timing()
+    cnt = sum(live[kd][0] for kd in funcs[top]["kinds"] if kd in live)
+    ms = sum(live[kd][1] for kd in funcs[top]["kinds"] if kd in live)
+    by = sum(live[kd][2] for kd in funcs[top]["kinds"] if kd in live)
+    avg_ms, per = ms / cnt, by / cnt
+    achieved = per / (avg_ms * 1e-3) / 1e9
+    same = same_size_copy(torch, per)
+    from paper_2407_05930_amd import Solver
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(top), "kernel": top,
+            "classes": [Solver.kind_name(kk) for kk in funcs[top]["kinds"]], "avg_ms": round(avg_ms, 5),
+            "algorithmic_bytes_per_launch": int(per), "launches": cnt, "same_size_copy": same,
+            "frac_of_same_size_copy": {m: round(achieved / same[m]["GBs"], 4) for m in ("hot", "cold")},
+            "kernel_functions": {f: dict(launches=v["launches"], ms=round(v["ms"], 3),
+                                         classes=[Solver.kind_name(kk) for kk in v["kinds"]])
+                                 for f, v in sorted(funcs.items(), key=lambda kv: -kv[1]["ms"])}}
+
+
+def bench_copies(args, torch, np):
+    """AMGR in the original basis on a domain made of copies (msp_setup_copies):
+    8 translated copies of a 64^3 box side by side, lognormal kappa repeated in
+    every copy, walls that differ between copies (the low axis-1 wall insulated
+    in odd copies and the far end wall), 4 right-hand sides: 2.1 M unknowns, the
+    headline's size, in a geometry Q_s cannot decouple.  FP64, FP32 and
+    bfloat16 V-cycle vectors; no low-rank correction."""
+    from gen import make_repeated_problem
+    from gen.problems import CONFIG_SEED0
+    from paper_2407_05930_amd import Solver
+    log("building workload copies3d_8x64")
+    p = make_repeated_problem((64, 64, 64), 8, m=4, seed=CONFIG_SEED0 + 5, walls="mixed")
+    b = device_columns(torch, p.b)
+    out = {}
+    x64 = None
+    svh = None
+    for prec in ("fp64", "mixed", "mixed_bf16"):
+        sv = Solver.from_copies(p.A, p.sub, tol=1e-10, precision=prec, **args.extra)
+        t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
+        xs = x.cpu().numpy()
+        rr = float(np.max(np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)))
+        out[prec] = dict(solve_s=round(t, 6), iters=sv.last.iters, true_relres=rr,
+                         setup_s=round(sv.stats.t_setup_s, 3))
+        if prec == "fp64":
+            x64 = xs
+        else:
+            out[prec]["rel_diff_vs_fp64"] = float(np.linalg.norm(xs - x64) / np.linalg.norm(x64))
+        log(f"  copies {prec}: {t * 1e3:.2f} ms, {sv.last.iters} its, relres {rr:.2e}")
+        if prec == "mixed_bf16":
+            svh = sv
+        else:
+            sv.close()
+    st = svh.stats
+    iface = svh.export_outer()[1]
+    roof = dominant_roofline(svh, b, args.steps, torch)
+    svh.close()
+    return {"metric": "solve time to 1e-10 rel-res, 8 translated copies of 64^3 with differing walls, 4 RHS",
+            "value": out["mixed_bf16"]["solve_s"], "unit": "s", "higher_is_better": False,
+            "dtype": "f64+f32+bf16",
+            "config": {"workload": "copies3d_8x64", "copy_grid": [64, 64, 64], "copies": 8, "rhs": 4,
+                       "unknowns": int(p.n), "preconditioner": "amgr (original basis, populated interface)",
+                       "interface_fraction": round(float(iface.mean()), 4),
+                       "levels": int(st.nlev), "op_complexity": round(st.op_complexity, 3)},
+            "variants": out, "roofline": roof}
+
+
 def bench_batch(args, torch, np):
     """64 uneven cubic Dirichlet systems (N in even 32..96, s in 1..3, m in
     1..8) solved as one batch: one launch of a captured graph whose
@@ -352,7 +429,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     extra = {} if args.trunc0 is None else {"trunc0": args.trunc0}
     args.extra = extra
-    other = {"jitter3d_192_s3": bench_jitter, "batch64": bench_batch, "adjoint3d_256_s3": bench_adjoint}
+    other = {"jitter3d_192_s3": bench_jitter, "batch64": bench_batch, "adjoint3d_256_s3": bench_adjoint,
+             "copies3d_8x64": bench_copies}
     if args.workload in other:
         res = other[args.workload](args, torch, np)
         res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "vs_baseline": None})

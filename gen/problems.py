@@ -467,55 +467,49 @@ def make_repeated_problem(N: Sequence[int], copies: int, m: int = 1, seed: int =
     n = n_b * copies
     kb = rng.lognormal(0.0, 1.0, size=n_b) if kappa == "lognormal" else np.ones(n_b)
 
-    def base_of(idx):            # full grid multi-index -> (copy, base multi-index)
-        a = idx[0] // N[0]
-        x0 = idx[0] % N[0]
-        if mirror and a % 2 == 1:
-            x0 = N[0] - 1 - x0
-        return a, (x0,) + tuple(idx[1:])
-
     strides_full = np.cumprod((1,) + full[:-1])     # axis 0 fastest
     strides_base = np.cumprod((1,) + N[:-1])
-    grid = np.stack(np.meshgrid(*[np.arange(v) for v in full], indexing="ij"), axis=-1).reshape(-1, D)
-    gidx = grid @ strides_full
-    order = np.argsort(gidx)
-    grid = grid[order]
-    copy_of = np.empty(n, dtype=np.int64)
-    base_idx = np.empty(n, dtype=np.int64)
-    for g in range(n):
-        a, bi = base_of(tuple(grid[g]))
-        copy_of[g] = a
-        base_idx[g] = int(np.dot(bi, strides_base))
+    g_all = np.arange(n, dtype=np.int64)
+    grid = np.stack([(g_all // strides_full[ax]) % full[ax] for ax in range(D)], axis=1)   # natural order
+    copy_of = grid[:, 0] // N[0]
+    x0 = grid[:, 0] % N[0]
+    if mirror:
+        x0 = np.where(copy_of % 2 == 1, N[0] - 1 - x0, x0)
+    base_idx = x0 * strides_base[0]
+    for ax in range(1, D):
+        base_idx = base_idx + grid[:, ax] * strides_base[ax]
     kap = kb[base_idx]
     rows, cols, vals = [], [], []
-    for g in range(n):
-        idx = grid[g]
-        face = np.zeros(2 * D)
-        for ax in range(D):
-            for side, step in ((0, -1), (1, 1)):
-                nb = idx.copy()
-                nb[ax] += step
-                f = 2 * ax + side
-                if nb[ax] < 0 or nb[ax] >= full[ax]:
-                    insulated = walls == "mixed" and (
-                        (ax == 1 and side == 0 and copy_of[g] % 2 == 1) or
-                        (ax == 0 and side == 1 and nb[ax] >= full[ax]))
-                    face[f] = 0.0 if insulated else 2.0 * kap[g]
-                    continue
-                h = int(np.dot(nb, strides_full))
-                t = 1.0 / (0.5 / kap[g] + 0.5 / kap[h])
-                face[f] = t
-                rows.append(g)
-                cols.append(h)
-                vals.append(-t)
-        pairs = [face[2 * ax] + face[2 * ax + 1] for ax in range(D)]
-        diag = pairs[0] + pairs[1]
-        if D == 3:
-            diag = diag + pairs[2]
-        rows.append(g)
-        cols.append(g)
-        vals.append(diag)
-    A = sp.csr_matrix((np.array(vals), (np.array(rows), np.array(cols))), shape=(n, n))
+    face = np.zeros((n, 2 * D))
+    for ax in range(D):
+        for side, step in ((0, -1), (1, 1)):
+            f = 2 * ax + side
+            nbc = grid[:, ax] + step
+            inside = (nbc >= 0) & (nbc < full[ax])
+            h = g_all + step * strides_full[ax]
+            gi, hi = g_all[inside], h[inside]
+            t = 1.0 / (0.5 / kap[gi] + 0.5 / kap[hi])
+            face[gi, f] = t
+            rows.append(gi)
+            cols.append(hi)
+            vals.append(-t)
+            out = ~inside
+            wall = 2.0 * kap[out]
+            if walls == "mixed":
+                if ax == 1 and side == 0:
+                    wall = np.where(copy_of[out] % 2 == 1, 0.0, wall)
+                if ax == 0 and side == 1:
+                    wall = np.zeros_like(wall)
+            face[out, f] = wall
+    pairs = [face[:, 2 * ax] + face[:, 2 * ax + 1] for ax in range(D)]
+    diag = pairs[0] + pairs[1]
+    if D == 3:
+        diag = diag + pairs[2]
+    rows.append(g_all)
+    cols.append(g_all)
+    vals.append(diag)
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
     A.sort_indices()
     sub = np.empty((n_b, copies), dtype=np.int64)
     sub[base_idx, copy_of] = np.arange(n)
