@@ -19,6 +19,10 @@ Modules
   lrc        Sec. 2.1/2.2: low-rank corrections (LRCFSAI(k), LRCAMG(k)),
              eigenpairs by Lanczos
   adjoint    gradient of 0.5||p - p*||^2 through the solve
+  copies     Sec. 3 / 3.2 in the original basis: AMGR for a domain made of
+             copies (interface of the copies, replicated Alg. 2 split)
+  amgs       Sec. 3.1: the Schur-complement AMG (eqs. (3.2)-(3.12)) on the
+             decoupled subsystems
 
 Pins: each function is checked in ``tests/test_oracle_*.py`` against closed
 forms, invariants, brute force or textbook routines.  Functions without
