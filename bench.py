@@ -293,6 +293,40 @@ def bench_copies(args, torch, np):
             "variants": out, "roofline": roof}
 
 
+def bench_amgs(args, torch, np):
+    """AMGS, the Schur-complement AMG of Sec. 3.1, on the headline problem
+    (128^3, s = 3, 4 RHS) with k low-rank corrections of the decoupled Schur
+    blocks, FP64: the symmetric form under PCG and the light form under
+    flexible CG, beside AMGR (per-subsystem cycle, FP64) on the same systems."""
+    from gen import config_problem
+    from paper_2407_05930_amd import Solver
+    log("building workload amgs3d_128_s3")
+    p = config_problem("channel3d_128_s3")
+    b = device_columns(torch, p.b)
+    out = {}
+    svh = None
+    for label, opts in (("amgs", dict(pc="amgs", amgs_light=0)), ("amgs_light", dict(pc="amgs", amgs_light=1)),
+                        ("amgr_sub", dict(pc="amgr_sub"))):
+        sv = Solver(p.A, p.img, tol=1e-10, precision="fp64", k=args.k, **opts)
+        t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
+        xs = x.cpu().numpy()
+        rr = float(np.max(np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)))
+        out[label] = dict(solve_s=round(t, 6), iters=sv.last.iters, true_relres=rr,
+                          setup_s=round(sv.stats.t_setup_s, 3))
+        log(f"  {label}: {t * 1e3:.2f} ms, {sv.last.iters} its, relres {rr:.2e}")
+        if label == "amgs":
+            svh = sv
+        else:
+            sv.close()
+    roof = dominant_roofline(svh, b, args.steps, torch)
+    svh.close()
+    return {"metric": "solve time to 1e-10 rel-res, 128^3 s=3, 4 RHS, AMGS (Schur-complement AMG), FP64",
+            "value": out["amgs"]["solve_s"], "unit": "s", "higher_is_better": False, "dtype": "f64",
+            "config": {"workload": "amgs3d_128_s3", "grid": list(p.N), "s": p.s, "rhs": int(p.b.shape[1]),
+                       "schur_lrc_k": args.k, "unknowns": int(p.n)},
+            "variants": out, "roofline": roof}
+
+
 def bench_batch(args, torch, np):
     """64 uneven cubic Dirichlet systems (N in even 32..96, s in 1..3, m in
     1..8) solved as one batch: one launch of a captured graph whose
@@ -430,7 +464,7 @@ def main():
     extra = {} if args.trunc0 is None else {"trunc0": args.trunc0}
     args.extra = extra
     other = {"jitter3d_192_s3": bench_jitter, "batch64": bench_batch, "adjoint3d_256_s3": bench_adjoint,
-             "copies3d_8x64": bench_copies}
+             "copies3d_8x64": bench_copies, "amgs3d_128_s3": bench_amgs}
     if args.workload in other:
         res = other[args.workload](args, torch, np)
         res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "vs_baseline": None})

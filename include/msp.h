@@ -81,7 +81,23 @@ enum { MSP_FP64 = 0, MSP_MIXED_FP32 = 1, MSP_MIXED_FP32_BF16G = 2, MSP_MIXED_BF1
      C/F splits and sparsity patterns (values per subsystem, so one SpMM pass
      still serves all columns); each has its own dense coarsest inverse.
      Optional LRCAMG(k) on top. */
-enum { MSP_PC_AMGR = 0, MSP_PC_FSAI = 1, MSP_PC_NONE = 2, MSP_PC_AMGR_SUB = 3 };
+/* MSP_PC_AMGS: the Schur-complement AMG of Sec. 3.1 on every decoupled
+     subsystem (eq. (3.12)), base cells ordered inner first (eq. (3.1)):
+     t = AMG_K r_I, q = r_G - B^T t, z_G = S_a^{-1} q, z_I = t - K^{-1} B z_G,
+     with K, B, C_1 the inner, inner-interface and interface blocks of A_inn,
+     AMG_K this library's hierarchy built on K (empty interface), K^{-1} in
+     the last step AMG_K again (symmetric; standard PCG) or, with
+     amgs_light = 1, G_K^T G_K (the FSAI of K; flexible CG, as the form is
+     not symmetric).  S_a^{-1} ~ G_S1^T G_S1 (the FSAI of
+     S_G1 = C_1 - B^T G_K^T G_K B, eqs. (3.4), (3.9)) plus, when lrc_k > 0,
+     lrc_k low-rank corrections per subsystem toward
+     S_AMG,a = C_1 + Sigma_a - B^T AMG_K B (eqs. (3.8), (3.11)).  FSAI
+     patterns: the lower triangle of the pattern of K_f^2 and of S_f^3,
+     M_f = M without the off-diagonal entries
+     |m_ij| < schur_tau sqrt(|m_ii m_jj|).  FP64
+     only (other precisions: MSP_ERR_UNSUPPORTED).  The hierarchy that
+     msp_num_levels / msp_export_level report is the one of K. */
+enum { MSP_PC_AMGR = 0, MSP_PC_FSAI = 1, MSP_PC_NONE = 2, MSP_PC_AMGR_SUB = 3, MSP_PC_AMGS = 4 };
 
 typedef struct msp_ctx msp_ctx;
 
@@ -135,6 +151,8 @@ typedef struct {
                             (Alg. 3): s = M y then nu1 - 1 sweeps s += M (y - A s); after the
                             correction nu2 such sweeps.  1..8 and nu1 == nu2 (PCG needs a symmetric
                             cycle; otherwise MSP_ERR_UNSUPPORTED).  Default 1, 1 */
+    int32_t amgs_light;      /* MSP_PC_AMGS: 1 = G_K^T G_K in the last step (flexible CG), 0 = AMG_K */
+    double schur_tau;        /* MSP_PC_AMGS: pre-filter of the FSAI patterns (default 0.01), >= 0 */
     int32_t true_residual;   /* 1: after the solve the library forms b - A x from x and b and reports
                                 ||b - A x|| / ||b|| per right-hand side in msp_stats.relres_true
                                 (two transforms, one operator product and one dot more); 0 (default):
@@ -166,7 +184,8 @@ typedef struct {
 /* Fill *o with the defaults: FP64, AMGR, k = 0, d = 2, theta = 0.25,
    jacobi0 = 3, jacobi = 1, coarse_max = 2560, max_levels = 20,
    max_ratio = 0.8, tol = 1e-10, maxit = 1000, device = 0, seed = 240705930,
-   trunc0 = 0.05, coarse64 = 0, nu1 = nu2 = 1, true_residual = 0. */
+   trunc0 = 0.05, coarse64 = 0, nu1 = nu2 = 1, amgs_light = 0, schur_tau = 0.01,
+   true_residual = 0. */
 int msp_default_opts(msp_opts* o);
 
 /* Build a context from A and its symmetry map.  Validates the map
@@ -248,8 +267,16 @@ int msp_export_level(const msp_ctx* c, int32_t lev, int8_t* cf, int64_t* A_rp, i
 int msp_export_sub_level(const msp_ctx* c, int32_t lev, int32_t a, double* A_v, double* P_v, double* G_v,
                          double* omega);
 /* Outer part: sigma[i * 2^s + a] (diagonal of A_out,a) and the interface
-   mask (1 for base cells coupled to another image). */
+   mask (1 for base cells coupled to another image).  With MSP_PC_AMGS both
+   are in the library's inner-first order of the base cells. */
 int msp_export_outer(const msp_ctx* c, double* sigma, int8_t* interface_mask);
+/* pc = MSP_PC_AMGS parity hook: which = 0 B (n_I x n_G), 1 C_1, 2 G_K
+   (n_I x n_I), 3 S_G1, 4 G_S1 (n_G x n_G), in the library's inner-first
+   order of the base cells (inner, then interface, each by increasing base
+   index).  Sizes are written to nrows, ncols, nnz; rp (nrows + 1), ci and v
+   (nnz) are filled when not NULL.  MSP_ERR_ARG for another pc or which. */
+int msp_export_amgs(const msp_ctx* c, int32_t which, int64_t* nrows, int64_t* ncols, int64_t* nnz, int64_t* rp,
+                    int32_t* ci, double* v);
 /* Low-rank corrections: number kept per subsystem (kept[a]) and the Ritz
    values found (ritz[a * k + t], k = lrc_k, ascending). */
 int msp_export_lrc(const msp_ctx* c, int32_t* kept, double* ritz);

@@ -31,7 +31,7 @@ STATUS = {
     -8: "MSP_ERR_UNSUPPORTED",
 }
 PRECISION = {"fp64": 0, "mixed": 1, "mixed_bf16g": 2, "mixed_bf16": 3}
-PC = {"amgr": 0, "fsai": 1, "none": 2, "amgr_sub": 3}
+PC = {"amgr": 0, "fsai": 1, "none": 2, "amgr_sub": 3, "amgs": 4}
 
 
 class msp_csr(ctypes.Structure):
@@ -54,7 +54,7 @@ class msp_opts(ctypes.Structure):
                 ("max_ratio", ctypes.c_double), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("trunc0", ctypes.c_double),
                 ("coarse64", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
-                ("true_residual", ctypes.c_int32)]
+                ("amgs_light", ctypes.c_int32), ("schur_tau", ctypes.c_double), ("true_residual", ctypes.c_int32)]
 
 
 class msp_stats(ctypes.Structure):
@@ -78,6 +78,8 @@ SIGNATURES = {
     "msp_default_opts": (ctypes.c_int, [_P(msp_opts)]),
     "msp_setup": (ctypes.c_int, [_P(msp_csr), _P(msp_symmap), _P(msp_opts), _P(_vp)]),
     "msp_setup_copies": (ctypes.c_int, [_P(msp_csr), _P(msp_copies), _P(msp_opts), _P(_vp)]),
+    "msp_export_amgs": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_int64),
+                                       _P(ctypes.c_int64), _vp, _vp, _vp]),
     "msp_solve_device": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _P(msp_stats)]),
     "msp_solve": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _P(msp_stats)]),
     "msp_solve_device_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _P(msp_stats)]),

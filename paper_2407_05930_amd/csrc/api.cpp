@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -103,6 +104,7 @@ struct Work {
     double* partial = nullptr;
     int nb_dot = 0;
     int grid_op = 0, grid_upd = 0, grid_z = 0, grid_p = 0;   // PCG kernel grids (set by the first solve plan)
+    double *amgs1 = nullptr, *amgs2 = nullptr;   // pc = AMGS: two n_b x C scratch multivectors
     double* dense_part = nullptr;   // k-chunk partials of the dense coarsest solve
     void* dense_pack = nullptr;     // per-subsystem packed right-hand sides of the coarsest solves
     int dense_rows = 8;             // rows per wavefront of the per-subsystem coarsest solves (autotuned)
@@ -132,6 +134,7 @@ enum {
     KD_DENSE = 6,     // coarsest-level dense solve
     KD_FSAI = 7,      // FSAI preconditioner products
     KD_LRC = 8,       // low-rank corrections
+    KD_AMGS = 9,      // AMGS: products with B, B^T and the FSAI factors of K and S_G1
     KD_LEVEL = 16,    // + 8 * level + {0: A, 1: G, 2: G^T, 3: R, 4: P}
     KD_COUNT = 16 + 8 * 20
 };
@@ -161,6 +164,10 @@ struct msp_ctx {
     msp::SubValues subv;      // per-subsystem values of levels >= 1 (pc = AMGR_SUB)
     bool sub = false;         // levels >= 1 and the coarsest solve are per subsystem
     msp::Csr Gf;              // FSAI of A_inn (pc = FSAI)
+    msp::AmgsParts am;        // pc = AMGS: blocks, FSAI factors (the AMG of K is `hier`)
+    msp::DevCsr dB, dBT, dC1, dGK, dGKT, dGS1, dGS1T;
+    msp::DevOuter dsigG;      // pc = AMGS: the outer diagonal on the interface rows
+    double* d_ones = nullptr; // 64 ones (column coefficients of a plain subtraction)
     msp_stats stats{};
     bool on_device = false;
     int device = -1;
@@ -875,6 +882,9 @@ static int vbytes(const msp_ctx* c) {
     return c->o.precision == MSP_FP64 ? 8 : (c->o.precision == MSP_MIXED_BF16 ? 2 : 4);
 }
 static bool amg(const msp_ctx* c) { return c->o.pc == MSP_PC_AMGR || c->o.pc == MSP_PC_AMGR_SUB; }
+static bool amgs(const msp_ctx* c) { return c->o.pc == MSP_PC_AMGS; }
+// a multigrid hierarchy is uploaded and cycled: A_inn's (AMGR) or K's (AMGS)
+static bool cycle(const msp_ctx* c) { return amg(c) || amgs(c); }
 
 // Carves the device arrays of a C-column workspace out of base (base ==
 // nullptr: offsets only); each array starts on a 256-byte boundary.  Returns
@@ -896,9 +906,13 @@ static size_t carve_work(const msp_ctx* c, int C, Work& w, char* base) {
     w.p = static_cast<double*>(take(vec));
     w.q = static_cast<double*>(take(vec));
     w.zold = static_cast<double*>(take(vec));
+    if (amgs(c)) {
+        w.amgs1 = static_cast<double*>(take(vec));
+        w.amgs2 = static_cast<double*>(take(vec));
+    }
     const size_t es = static_cast<size_t>(vbytes(c));
     const size_t L = c->hier.lev.size();
-    if (amg(c)) {
+    if (cycle(c)) {
         for (size_t l = 0; l < L; ++l) {
             const size_t n = static_cast<size_t>(c->hier.lev[l].A.nr);
             w.vy[l] = take(es * n * C);
@@ -954,7 +968,7 @@ static Work& work(msp_ctx* c, int C) {
     use_host_bufs(w, w.own);
     c->works[C] = std::move(wp);
     autotune_operator(c, w);
-    if (amg(c) && !c->dl.empty()) {
+    if (cycle(c) && !c->dl.empty()) {
         if (c->o.precision == MSP_MIXED_BF16) autotune_level_splits<Bf16>(c, w);
         else if (mixed(c)) autotune_level_splits<float>(c, w);
         else autotune_level_splits<double>(c, w);
@@ -1021,9 +1035,10 @@ static void vcycle(msp_ctx* c, Work& w, hipStream_t st, size_t l, const T* y, T*
     }
 }
 
-// out[c] = <X_c, Y_c> for the C columns of two n_b x C multivectors.
-static void dot(msp_ctx* c, Work& w, hipStream_t st, const double* X, const double* Y, double* out) {
-    const int64_t nb = c->sym.n_b;
+// out[c] = <X_c, Y_c> for the C columns of two rows x C multivectors (rows = n_b by default).
+static void dot(msp_ctx* c, Work& w, hipStream_t st, const double* X, const double* Y, double* out,
+                int64_t rows = -1) {
+    const int64_t nb = rows >= 0 ? rows : c->sym.n_b;
     const int C = w.C;
     timed(c, KD_DOT, 16.0 * nb * C, st,
           [&] { HIPCHECK(launch_dot<double>(st, C, nb, X, Y, w.partial, w.nb_dot, out)); },
@@ -1031,8 +1046,8 @@ static void dot(msp_ctx* c, Work& w, hipStream_t st, const double* X, const doub
 }
 
 // z += U_a diag(coef_a) U_a^T r_a for every subsystem a (low-rank corrections).
-static void lrc_apply(msp_ctx* c, Work& w, hipStream_t st, const double* r, double* z) {
-    const int64_t nb = c->sym.n_b;
+static void lrc_apply(msp_ctx* c, Work& w, hipStream_t st, const double* r, double* z, int64_t rows = -1) {
+    const int64_t nb = rows >= 0 ? rows : c->sym.n_b;
     const int S = 1 << c->sym.s, k = c->lrc_k;
     const double bytes = 2.0 * nb * S * k * (c->U32 ? 4.0 : 8.0) + 3.0 * 8.0 * nb * w.C;
     timed(c, KD_LRC, bytes, st, [&] {
@@ -1069,6 +1084,29 @@ static void precondition_base(msp_ctx* c, Work& w, hipStream_t st, const double*
             else run(0.0f);
         } else {
             vcycle<double>(c, w, st, 0, r, z);
+        }
+    } else if (amgs(c)) {
+        // eq. (3.12) with base cells ordered inner first: r = [r_I; r_G], z = [z_I; z_G]
+        const int64_t nI = c->am.nI, nG = nb - nI;
+        const double* rI = r;
+        const double* rG = r + nI * C;
+        double* zI = z;
+        double* zG = z + nI * C;
+        vcycle<double>(c, w, st, 0, rI, zI);                                         // t = AMG_K r_I (in z_I)
+        spmm<double>(c, KD_AMGS, st, C, c->dBT, zI, w.amgs1, rG, -1.0, 1.0);        // q = r_G - B^T t
+        spmm<double>(c, KD_AMGS, st, C, c->dGS1, w.amgs1, w.amgs2, nullptr, 1.0, 0.0);   // u = G_S1 q
+        if (c->d_U) {                                                                // u += V Theta V^T u
+            HIPCHECK(hipMemcpyAsync(w.amgs1, w.amgs2, sizeof(double) * nG * C, hipMemcpyDeviceToDevice, st));
+            lrc_apply(c, w, st, w.amgs1, w.amgs2, nG);
+        }
+        spmm<double>(c, KD_AMGS, st, C, c->dGS1T, w.amgs2, zG, nullptr, 1.0, 0.0);   // z_G = G_S1^T u
+        spmm<double>(c, KD_AMGS, st, C, c->dB, zG, w.amgs1, nullptr, 1.0, 0.0);     // v = B z_G
+        if (c->o.amgs_light) {                                                       // z_I = t - G_K^T G_K v
+            spmm<double>(c, KD_AMGS, st, C, c->dGK, w.amgs1, w.amgs2, nullptr, 1.0, 0.0);
+            spmm<double>(c, KD_AMGS, st, C, c->dGKT, w.amgs2, zI, zI, -1.0, 1.0);
+        } else {                                                                     // z_I = t - AMG_K v
+            vcycle<double>(c, w, st, 0, w.amgs1, w.amgs2);
+            HIPCHECK(launch_axpy_cols(st, nI * C, C, zI, w.amgs2, c->d_ones));
         }
     } else if (c->o.pc == MSP_PC_FSAI) {
         double* t = w.zold;   // scratch (the FSAI mode keeps no flexible copy)
@@ -1112,7 +1150,7 @@ static void upload_all(msp_ctx* c) {
     c->dAinn = upload_csr(c, c->sym.Ainn, false);
     c->dAinn.hpat = &c->sym.Ainn;   // the operator's sliced form is built from these (FP64 values)
     c->dAinn.hval = &c->sym.Ainn.v;
-    if (amg(c)) {
+    if (cycle(c)) {
         const int S = 1 << c->sym.s;
         c->dl.resize(c->hier.lev.size() - 1);
         for (size_t l = 0; l + 1 < c->hier.lev.size(); ++l) {
@@ -1197,6 +1235,22 @@ static void upload_all(msp_ctx* c) {
         c->dGf = upload_csr(c, c->Gf, false);
         c->dGfT = upload_csr(c, transpose(c->Gf), false);
     }
+    if (amgs(c)) {
+        const AmgsParts& A = c->am;
+        c->dB = upload_csr(c, A.B, false);
+        c->dBT = upload_csr(c, A.BT, false);
+        c->dC1 = upload_csr(c, A.C1, false);
+        c->dGK = upload_csr(c, A.GK, false);
+        c->dGKT = upload_csr(c, A.GKT, false);
+        c->dGS1 = upload_csr(c, A.GS1, false);
+        c->dGS1T = upload_csr(c, A.GS1T, false);
+        const int S = 1 << c->sym.s;
+        const int64_t nG = c->sym.n_b - A.nI;
+        std::vector<double> sg(c->sym.sigma.begin() + A.nI * S, c->sym.sigma.end());
+        c->dsigG = upload_outer(c, sg, nG, S);
+        std::vector<double> ones(64, 1.0);
+        c->d_ones = c->upload(ones.data(), 64);
+    }
     c->on_device = true;
 }
 
@@ -1268,7 +1322,7 @@ struct SolvePlan {
         active = w->iscal;
         iters = w->iscal + 64;
         flags = w->iscal + 128;
-        flexible = mixed(c) && amg(c);
+        flexible = (mixed(c) && amg(c)) || (amgs(c) && c->o.amgs_light);
         lrc_amg = c->d_U && amg(c);
         kl = lrc_amg ? c->lrc_k : 0;
         O = S * kl * m;
@@ -1656,6 +1710,7 @@ static void fill_stats(msp_ctx* c) {
 }
 
 void build_lrc(msp_ctx* c);   // low-rank corrections (below)
+void build_schur_lrc(msp_ctx* c);
 void fv_kappa_grad(msp_fv* f, const double* d_kap, int m, const double* d_lam, const double* d_p, double* d_grad,
                    hipStream_t st);   // fv.cpp
 
@@ -1687,7 +1742,11 @@ static int guarded(F&& f) {
 static void check_opts(const msp_opts* o) {
     if (!o) throw Error(MSP_ERR_ARG, "null options");
     if (o->precision < MSP_FP64 || o->precision > MSP_MIXED_BF16) throw Error(MSP_ERR_ARG, "precision");
-    if (o->pc < MSP_PC_AMGR || o->pc > MSP_PC_AMGR_SUB) throw Error(MSP_ERR_ARG, "pc");
+    if (o->pc < MSP_PC_AMGR || o->pc > MSP_PC_AMGS) throw Error(MSP_ERR_ARG, "pc");
+    if (o->amgs_light != 0 && o->amgs_light != 1) throw Error(MSP_ERR_ARG, "amgs_light must be 0 or 1");
+    if (!(o->schur_tau >= 0.0) || !std::isfinite(o->schur_tau)) throw Error(MSP_ERR_ARG, "schur_tau must be >= 0");
+    if (o->pc == MSP_PC_AMGS && o->precision != MSP_FP64)
+        throw Error(MSP_ERR_UNSUPPORTED, "AMGS runs in FP64 only");
     if (o->lrc_k < 0 || o->dist < 1 || o->jacobi0 < 1 || o->jacobi < 1 || o->coarse_max < 1 || o->max_levels < 1 ||
         !(o->theta >= 0.0) || !(o->tol > 0.0) || o->maxit < 0 || !(o->trunc0 >= 0.0 && o->trunc0 < 1.0))
         throw Error(MSP_ERR_ARG, "invalid option value");
@@ -1708,7 +1767,11 @@ static std::unique_ptr<msp_ctx> setup_host(const msp_csr* A, const msp_symmap* m
     c->device = o->device;
     c->lrc_k = o->lrc_k;
     c->sym = msp::extract_blocks(A, map);
-    if (o->pc == MSP_PC_AMGR || o->pc == MSP_PC_AMGR_SUB) {
+    if (o->pc == MSP_PC_AMGS) {
+        c->am = msp::build_amgs(c->sym, *o);   // reorders the base cells inner first
+        c->hier = std::move(c->am.HK);
+        c->am.HK = msp::HostHierarchy{};
+    } else if (o->pc == MSP_PC_AMGR || o->pc == MSP_PC_AMGR_SUB) {
         c->hier = msp::build_hierarchy(c->sym.Ainn, c->sym.iface, *o);
         if (o->pc == MSP_PC_AMGR_SUB && c->hier.lev.size() > 1) {
             c->subv = msp::build_sub_values(c->hier, c->sym.sigma, c->sym.iface, 1 << c->sym.s, *o);
@@ -1726,7 +1789,7 @@ static std::unique_ptr<msp_ctx> setup_host(const msp_csr* A, const msp_symmap* m
 // Host part of the setup for a domain made of copies: one subsystem holding the
 // whole matrix, level 0 split by the replicated populated interface.
 static std::unique_ptr<msp_ctx> setup_host_copies(const msp_csr* A, const msp_copies* map, const msp_opts* o) {
-    if (o->pc == MSP_PC_AMGR_SUB)
+    if (o->pc == MSP_PC_AMGR_SUB || o->pc == MSP_PC_AMGS)
         throw Error(MSP_ERR_ARG, "a domain of copies is solved in its own basis: use MSP_PC_AMGR");
     std::unique_ptr<msp_ctx> c(new msp_ctx());
     c->o = *o;
@@ -1753,7 +1816,8 @@ static void setup_device(msp_ctx* c) {
     msp::upload_all(c);
     HIPCHECK(msp::scratch_init());   // the allocation-free solve's workspace on this device
     msp::alloc_host_bufs(c->nohb);
-    if (c->lrc_k > 0) msp::build_lrc(c);
+    if (c->lrc_k > 0 && c->o.pc == MSP_PC_AMGS) msp::build_schur_lrc(c);
+    else if (c->lrc_k > 0) msp::build_lrc(c);
     HIPCHECK(hipDeviceSynchronize());
 }
 
@@ -1800,6 +1864,7 @@ static void batch_setup(int nsys, const msp_csr* A, const msp_symmap* maps, cons
     if (nsys <= 0 || !A || !maps || !out) throw Error(MSP_ERR_ARG, "bad batch arguments");
     check_opts(o);
     if (o->device < 0) throw Error(MSP_ERR_ARG, "batched solves need a device");
+    if (o->pc == MSP_PC_AMGS) throw Error(MSP_ERR_UNSUPPORTED, "batched solves with AMGS");
     std::unique_ptr<msp_batch> bt(new msp_batch());
     bt->sys.assign(nsys, nullptr);
     // host setups in parallel (each context is independent)
@@ -2102,6 +2167,29 @@ int msp_export_sub_level(const msp_ctx* c, int32_t lev, int32_t a, double* A_v, 
     return MSP_OK;
 }
 
+int msp_export_amgs(const msp_ctx* c, int32_t which, int64_t* nrows, int64_t* ncols, int64_t* nnz, int64_t* rp,
+                    int32_t* ci, double* v) {
+    return guarded([&]() -> int {
+        if (!c || c->o.pc != MSP_PC_AMGS) throw Error(MSP_ERR_ARG, "not an AMGS context");
+        const msp::Csr* M = nullptr;
+        switch (which) {
+            case 0: M = &c->am.B; break;
+            case 1: M = &c->am.C1; break;
+            case 2: M = &c->am.GK; break;
+            case 3: M = &c->am.SG1; break;
+            case 4: M = &c->am.GS1; break;
+            default: throw Error(MSP_ERR_ARG, "which must be 0..4");
+        }
+        if (nrows) *nrows = M->nr;
+        if (ncols) *ncols = M->nc;
+        if (nnz) *nnz = M->nnz();
+        if (rp) std::copy(M->rp.begin(), M->rp.end(), rp);
+        if (ci) std::copy(M->ci.begin(), M->ci.end(), ci);
+        if (v) std::copy(M->v.begin(), M->v.end(), v);
+        return MSP_OK;
+    });
+}
+
 int msp_export_outer(const msp_ctx* c, double* sigma, int8_t* iface) {
     if (!c) return MSP_ERR_ARG;
     if (sigma) std::copy(c->sym.sigma.begin(), c->sym.sigma.end(), sigma);
@@ -2236,15 +2324,20 @@ namespace msp {
 //         1/lam_t - 1, applied between the G and G^T products.
 // Start vector v_i = splitmix64(seed ^ i ^ 0x1CC)/2^64 - 1/2 (all subsystems),
 // max(4k, 40) steps (at most n_b).
-void build_lrc(msp_ctx* c) {
+// Lockstep Lanczos over the 2^s subsystems on n rows (one column per
+// subsystem), with full reorthogonalisation; the k smallest Ritz pairs below
+// one become the corrections U (n x S*k).  amg_form: op(v, B v) = M^{-1} B v
+// self-adjoint in the B inner product, coefficient 1 - lambda (LRCAMG);
+// otherwise op is symmetric in the Euclidean product, coefficient 1/lambda - 1
+// (LRCFSAI form).
+static void lanczos_corrections(msp_ctx* c, Work& w, int64_t n, bool amg_form,
+                                const std::function<void(const double*, double*)>& applyB,
+                                const std::function<void(const double*, const double*, double*)>& op) {
     const int S = 1 << c->sym.s;
     const int k = c->lrc_k;
-    const int64_t n = c->sym.n_b;
     const int K = static_cast<int>(std::min<int64_t>(std::max(4 * k, 40), n));
-    const int C = next_pow2(S);
-    const bool amg = msp::amg(c);
-    Work& w = work(c, C);
-    w.m = 1;
+    const int C = w.C;
+    const bool amg = amg_form;
     hipStream_t st = nullptr;
     const int64_t len = n * C;
     double* V = c->dalloc<double>(static_cast<int64_t>(K) * len);
@@ -2253,23 +2346,10 @@ void build_lrc(msp_ctx* c) {
     double* dvec = c->dalloc<double>(64);
     double* wv = w.x;    // w
     double* bw = w.q;    // B w
-    double* tmp = w.p;
     std::vector<double> h(64), hv(len);
 
-    auto applyB = [&](const double* x, double* y) {   // y = A_a x per column
-        spmm<double>(c, KD_OP, st, C, c->dAinn, x, y, nullptr, 1.0, 0.0, &c->dsig, S, 1);
-    };
-    auto op = [&](const double* v, const double* bv, double* out) {
-        if (amg) {
-            precondition_base(c, w, st, bv, out, false);
-        } else {
-            spmm<double>(c, KD_FSAI, st, C, c->dGfT, v, tmp, nullptr, 1.0, 0.0);
-            applyB(tmp, w.z);
-            spmm<double>(c, KD_FSAI, st, C, c->dGf, w.z, out, nullptr, 1.0, 0.0);
-        }
-    };
     auto coldots = [&](const double* X, const double* Y, double* out_host) {
-        dot(c, w, st, X, Y, dvec);
+        dot(c, w, st, X, Y, dvec, n);
         HIPCHECK(hipMemcpyAsync(out_host, dvec, C * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
     };
@@ -2304,7 +2384,7 @@ void build_lrc(msp_ctx* c) {
         // classical Gram-Schmidt, twice, against every basis vector so far
         for (int pass = 0; pass < 2; ++pass) {
             for (int i = 0; i <= j; ++i)
-                dot(c, w, st, wv, BV + static_cast<int64_t>(i) * len, hcoef + static_cast<int64_t>(i) * 64);
+                dot(c, w, st, wv, BV + static_cast<int64_t>(i) * len, hcoef + static_cast<int64_t>(i) * 64, n);
             for (int i = 0; i <= j; ++i)
                 HIPCHECK(launch_axpy_cols(st, len, C, wv, V + static_cast<int64_t>(i) * len,
                                           hcoef + static_cast<int64_t>(i) * 64));
@@ -2376,6 +2456,54 @@ void build_lrc(msp_ctx* c) {
     c->dfree(hcoef);
     if (amg) c->dfree(BV);
     c->dfree(V);
+}
+
+
+void build_lrc(msp_ctx* c) {
+    const int S = 1 << c->sym.s;
+    const int C = next_pow2(S);
+    const bool amg = msp::amg(c);
+    Work& w = work(c, C);
+    w.m = 1;
+    hipStream_t st = nullptr;
+    double* tmp = w.p;
+    auto applyB = [&](const double* x, double* y) {   // y = A_a x per column
+        spmm<double>(c, KD_OP, st, C, c->dAinn, x, y, nullptr, 1.0, 0.0, &c->dsig, S, 1);
+    };
+    auto op = [&](const double* v, const double* bv, double* out) {
+        if (amg) {
+            precondition_base(c, w, st, bv, out, false);
+        } else {
+            spmm<double>(c, KD_FSAI, st, C, c->dGfT, v, tmp, nullptr, 1.0, 0.0);
+            applyB(tmp, w.z);
+            spmm<double>(c, KD_FSAI, st, C, c->dGf, w.z, out, nullptr, 1.0, 0.0);
+        }
+    };
+    lanczos_corrections(c, w, c->sym.n_b, amg, applyB, op);
+}
+
+// Corrections of the decoupled Schur blocks for AMGS (eq. (3.11)): LRCFSAI of
+// G_S1 toward S_AMG,a = C_1 + Sigma_a - B^T AMG_K B on the interface rows.
+void build_schur_lrc(msp_ctx* c) {
+    const int S = 1 << c->sym.s;
+    const int C = next_pow2(S);
+    Work& w = work(c, C);
+    w.m = 1;
+    hipStream_t st = nullptr;
+    const int64_t nG = c->sym.n_b - c->am.nI;
+    double* tmp = w.p;
+    auto applyB = [&](const double* x, double* y) {   // y = S_AMG,a x per column
+        spmm<double>(c, KD_AMGS, st, C, c->dC1, x, y, nullptr, 1.0, 0.0, &c->dsigG, S, 1);
+        spmm<double>(c, KD_AMGS, st, C, c->dB, x, w.amgs1, nullptr, 1.0, 0.0);
+        vcycle<double>(c, w, st, 0, w.amgs1, w.amgs2);
+        spmm<double>(c, KD_AMGS, st, C, c->dBT, w.amgs2, y, y, -1.0, 1.0);
+    };
+    auto op = [&](const double* v, const double*, double* out) {   // G_S1 S_AMG,a G_S1^T v
+        spmm<double>(c, KD_AMGS, st, C, c->dGS1T, v, tmp, nullptr, 1.0, 0.0);
+        applyB(tmp, w.z);
+        spmm<double>(c, KD_AMGS, st, C, c->dGS1, w.z, out, nullptr, 1.0, 0.0);
+    };
+    lanczos_corrections(c, w, nG, false, applyB, op);
 }
 
 }  // namespace msp

@@ -815,6 +815,167 @@ HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface,
 
 static bool same_pattern(const Csr& X, const Csr& Y) { return X.rp == Y.rp && X.ci == Y.ci; }
 
+// ------------------------------------------------------------------ AMGS (Sec. 3.1)
+
+// Rows of M without the off-diagonal entries |m_ij| < tau sqrt(|m_ii m_jj|).
+static std::vector<std::vector<int32_t>> filtered_rows(const Csr& M, double tau) {
+    std::vector<double> d(M.nr, 0.0);
+    for (int64_t i = 0; i < M.nr; ++i)
+        for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k)
+            if (M.ci[k] == i) d[i] = std::fabs(M.v[k]);
+    std::vector<std::vector<int32_t>> rows(M.nr);
+    for (int64_t i = 0; i < M.nr; ++i)
+        for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k) {
+            const int32_t j = M.ci[k];
+            if (j == i || std::fabs(M.v[k]) >= tau * std::sqrt(d[i] * d[j])) rows[i].push_back(j);
+        }
+    return rows;
+}
+
+// FSAI of M on the lower triangle of the pattern of M_f^power (power >= 1):
+// the cells reachable from row i in at most `power` steps of the filtered graph.
+static Csr fsai_filtered_power(const Csr& M, double tau, int power) {
+    const std::vector<std::vector<int32_t>> P = filtered_rows(M, tau);
+    std::vector<std::vector<int32_t>> lower(M.nr);
+    std::vector<int64_t> mark(M.nr, -1);
+    std::vector<int32_t> front, next, reach;
+    for (int64_t i = 0; i < M.nr; ++i) {
+        reach.clear();
+        front.assign(1, static_cast<int32_t>(i));
+        mark[i] = i;
+        for (int step = 0; step < power; ++step) {
+            next.clear();
+            for (int32_t j : front)
+                for (int32_t l : P[j])
+                    if (mark[l] != i) {
+                        mark[l] = i;
+                        next.push_back(l);
+                        reach.push_back(l);
+                    }
+            front.swap(next);
+        }
+        for (int32_t l : reach)
+            if (l < i) lower[i].push_back(l);
+        std::sort(lower[i].begin(), lower[i].end());
+    }
+    return fsai_rows(M, lower);
+}
+
+// a X + b Y on the union pattern (rows sorted); sums that are exactly zero are dropped.
+static Csr add_csr(const Csr& X, double a, const Csr& Y, double b) {
+    Csr Z;
+    Z.nr = X.nr;
+    Z.nc = X.nc;
+    Z.rp.assign(Z.nr + 1, 0);
+    for (int64_t i = 0; i < X.nr; ++i) {
+        int64_t p = X.rp[i], q = Y.rp[i];
+        const int64_t pe = X.rp[i + 1], qe = Y.rp[i + 1];
+        while (p < pe || q < qe) {
+            int32_t j;
+            double v;
+            if (q >= qe || (p < pe && X.ci[p] < Y.ci[q])) {
+                j = X.ci[p];
+                v = a * X.v[p++];
+            } else if (p >= pe || Y.ci[q] < X.ci[p]) {
+                j = Y.ci[q];
+                v = b * Y.v[q++];
+            } else {
+                j = X.ci[p];
+                v = a * X.v[p++] + b * Y.v[q++];
+            }
+            if (v != 0.0) {
+                Z.ci.push_back(j);
+                Z.v.push_back(v);
+            }
+        }
+        Z.rp[i + 1] = static_cast<int64_t>(Z.ci.size());
+    }
+    return Z;
+}
+
+// Rows [r0, r1) and columns [c0, c1) of A, columns shifted by c0.
+static Csr block_of(const Csr& A, int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
+    Csr M;
+    M.nr = r1 - r0;
+    M.nc = c1 - c0;
+    M.rp.assign(M.nr + 1, 0);
+    for (int64_t i = r0; i < r1; ++i) {
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            if (A.ci[k] >= c0 && A.ci[k] < c1) {
+                M.ci.push_back(static_cast<int32_t>(A.ci[k] - c0));
+                M.v.push_back(A.v[k]);
+            }
+        M.rp[i - r0 + 1] = static_cast<int64_t>(M.ci.size());
+    }
+    return M;
+}
+
+AmgsParts build_amgs(SymParts& sym, const msp_opts& o) {
+    const int64_t nb = sym.n_b;
+    const int S = 1 << sym.s;
+    // inner cells first, interface cells after, each in increasing base index
+    std::vector<int64_t> perm;
+    perm.reserve(nb);
+    for (int64_t i = 0; i < nb; ++i)
+        if (!sym.iface[i]) perm.push_back(i);
+    const int64_t nI = static_cast<int64_t>(perm.size());
+    for (int64_t i = 0; i < nb; ++i)
+        if (sym.iface[i]) perm.push_back(i);
+    if (nI == 0 || nI == nb) throw Error(MSP_ERR_UNSUPPORTED, "AMGS needs both inner and interface cells");
+    std::vector<int32_t> pos(nb);
+    for (int64_t i = 0; i < nb; ++i) pos[perm[i]] = static_cast<int32_t>(i);
+    Csr A;
+    A.nr = A.nc = nb;
+    A.rp.assign(nb + 1, 0);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t i = 0; i < nb; ++i) {
+        const int64_t g = perm[i];
+        row.clear();
+        for (int64_t k = sym.Ainn.rp[g]; k < sym.Ainn.rp[g + 1]; ++k) row.emplace_back(pos[sym.Ainn.ci[k]], sym.Ainn.v[k]);
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) { return x.first < y.first; });
+        for (auto& e : row) {
+            A.ci.push_back(e.first);
+            A.v.push_back(e.second);
+        }
+        A.rp[i + 1] = static_cast<int64_t>(A.ci.size());
+    }
+    std::vector<double> sigma(sym.sigma.size());
+    std::vector<int64_t> img(sym.img.size());
+    std::vector<int8_t> iface(nb);
+    for (int64_t i = 0; i < nb; ++i) {
+        for (int a = 0; a < S; ++a) {
+            sigma[i * S + a] = sym.sigma[perm[i] * S + a];
+            img[i * S + a] = sym.img[perm[i] * S + a];
+        }
+        iface[i] = i >= nI ? 1 : 0;
+    }
+    sym.Ainn = std::move(A);
+    sym.sigma = std::move(sigma);
+    sym.img = std::move(img);
+    sym.iface = std::move(iface);
+
+    AmgsParts P;
+    P.nI = nI;
+    P.K = block_of(sym.Ainn, 0, nI, 0, nI);
+    P.B = block_of(sym.Ainn, 0, nI, nI, nb);
+    P.C1 = block_of(sym.Ainn, nI, nb, nI, nb);
+    P.BT = transpose(P.B);
+    const double tau = o.schur_tau;
+    P.GK = fsai_filtered_power(P.K, tau, 2);
+    P.GKT = transpose(P.GK);
+    const Csr W1 = spgemm(P.GK, P.B);
+    const Csr W2 = spgemm(P.GKT, W1);
+    const Csr X = spgemm(P.BT, W2);
+    Csr Xs = add_csr(X, 1.0, transpose(X), 1.0);   // (X + X^T) / 2: exactly symmetric
+    for (double& v : Xs.v) v *= 0.5;
+    P.SG1 = add_csr(P.C1, 1.0, Xs, -1.0);
+    P.GS1 = fsai_filtered_power(P.SG1, tau, 3);
+    P.GS1T = transpose(P.GS1);
+    P.HK = build_hierarchy(P.K, std::vector<int8_t>(nI, 0), o);
+    return P;
+}
+
 SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& sigma, const std::vector<int8_t>& iface,
                            int S, const msp_opts& o) {
     SubValues V;

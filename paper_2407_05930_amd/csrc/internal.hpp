@@ -89,6 +89,20 @@ std::vector<int8_t> reduction_split(const Csr& A, const std::vector<int8_t>& ifa
 // cf0: a level-0 split computed elsewhere, used instead of Alg. 2 on Ainn.
 HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o,
                               const std::vector<int8_t>* cf0 = nullptr);
+// AMGS, the Schur-complement AMG of Sec. 3.1, on the decoupled subsystems:
+// base cells reordered inner first (eq. (3.1)), so K = A_inn[0:nI, 0:nI],
+// B = A_inn[0:nI, nI:], C_1 = A_inn[nI:, nI:]; the AMG of K (HK); the FSAI of K
+// (GK, eq. (3.4)); S_G1 = C_1 - sym(B^T G_K^T G_K B) and its FSAI (GS1,
+// eq. (3.9)).  FSAI patterns: the lower triangle of the pattern of K_f^2 and
+// of S_f^3, M_f = M without the off-diagonal entries |m_ij| < tau sqrt(|m_ii m_jj|).
+struct AmgsParts {
+    int64_t nI = 0;
+    Csr K, B, BT, C1, GK, GKT, SG1, GS1, GS1T;
+    HostHierarchy HK;
+};
+// Reorders sym's base cells inner first (stable) and builds the parts.
+AmgsParts build_amgs(SymParts& sym, const msp_opts& o);
+
 // omega = 4/(3 lam), lam from 20 power iterations on G A G^T (seeded start).
 double damping(const Csr& A, const Csr& G, const Csr& GT, uint64_t seed);
 // Static FSAI on the full lower pattern of A (the stand-alone FSAI of A_inn).

@@ -25,6 +25,8 @@ extern "C" int msp_default_opts(msp_opts* o) {
     o->coarse64 = 0;
     o->nu1 = 1;
     o->nu2 = 1;
+    o->amgs_light = 0;
+    o->schur_tau = 0.01;
     o->true_residual = 0;
     return MSP_OK;
 }

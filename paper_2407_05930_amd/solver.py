@@ -206,6 +206,21 @@ class Solver:
                                    iface.ctypes.data_as(ctypes.c_void_p)))
         return sigma.reshape(self.n_b, S), iface.astype(bool)
 
+    def export_amgs(self, which: str):
+        """AMGS blocks and factors ("B", "C1", "GK", "SG1", "GS1") as scipy CSR,
+        in the library's inner-first order of the base cells."""
+        import scipy.sparse as sp
+        w = {"B": 0, "C1": 1, "GK": 2, "SG1": 3, "GS1": 4}[which]
+        nr, nc, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib.msp_export_amgs(self._ctx, w, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(nz), None, None,
+                                  None))
+        rp = np.zeros(nr.value + 1, np.int64)
+        ci = np.zeros(nz.value, np.int32)
+        v = np.zeros(nz.value)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        check(lib.msp_export_amgs(self._ctx, w, None, None, None, vp(rp), vp(ci), vp(v)))
+        return sp.csr_matrix((v, ci, rp), shape=(nr.value, nc.value))
+
     def export_lrc(self):
         S = 1 << self.s
         k = self.opts.lrc_k
@@ -217,7 +232,7 @@ class Solver:
 
     # ------------------------------------------------------------------ timers
     KIND_NAMES = {0: "operator", 1: "dot", 2: "update", 3: "p_update", 4: "qs", 5: "cast", 6: "dense_coarse",
-                  7: "fsai", 8: "lrc"}
+                  7: "fsai", 8: "lrc", 9: "amgs"}
 
     @staticmethod
     def kind_name(kind: int) -> str:
