@@ -227,14 +227,17 @@ def coarsen_standard(A: sp.csr_matrix, level: int, theta: float, seed: int,
 # interpolation, P = [W; I] (eq. (3.13))
 # ---------------------------------------------------------------------------
 
-def interpolation(A: sp.csr_matrix, C: np.ndarray, steps: int, trunc: float = 0.0) -> sp.csr_matrix:
+def interpolation(A: sp.csr_matrix, C: np.ndarray, steps: int, trunc: float = 0.0,
+                  keep_pattern: Optional[sp.csr_matrix] = None) -> sp.csr_matrix:
     """Jacobi-truncated ideal interpolation (parity reading of the cited long
     distance schemes): W1 = -D^{-1} A_FC, W_{t+1} = -D^{-1}(A_FC + O W_t) with
     D = diag(A_FF), O = A_FF - D, symbolic patterns.  With trunc > 0 every F
     row keeps only the weights with |w| >= trunc * max |w| of the row (the
-    others leave the pattern).  Each F row with nonzero sum is then rescaled
-    to rho_i = -sum_{l != i} a_il / a_ii.  Returns P (n x n_c), coarse
-    unknowns numbered by increasing fine index."""
+    others leave the pattern); with ``keep_pattern`` (an n x n_c matrix, the
+    P of an earlier setup) every F row keeps exactly the weights on that
+    pattern instead.  Each F row with nonzero sum is then rescaled to
+    rho_i = -sum_{l != i} a_il / a_ii.  Returns P (n x n_c), coarse unknowns
+    numbered by increasing fine index."""
     A = A.tocsr()
     n = A.shape[0]
     F = ~C
@@ -257,7 +260,15 @@ def interpolation(A: sp.csr_matrix, C: np.ndarray, steps: int, trunc: float = 0.
     for _ in range(steps - 1):
         inner = sym_add(AFC, sym_matmul(O, W))
         W = embed(-(Dinv @ inner), inner)
-    if trunc > 0.0:
+    if keep_pattern is not None:
+        Kp = keep_pattern.tocsr()[fidx].tocsr()
+        nrow = np.diff(W.indptr)
+        rows_w = np.repeat(np.arange(W.shape[0]), nrow)
+        rows_k = np.repeat(np.arange(Kp.shape[0]), np.diff(Kp.indptr))
+        keep = np.isin(rows_w * nc + W.indices, rows_k * nc + Kp.indices)
+        kept = np.bincount(rows_w[keep], minlength=W.shape[0])
+        W = sp.csr_matrix((W.data[keep], W.indices[keep], np.concatenate([[0], np.cumsum(kept)])), shape=W.shape)
+    elif trunc > 0.0:
         nrow = np.diff(W.indptr)
         rmax = np.zeros(W.shape[0])
         np.maximum.at(rmax, np.repeat(np.arange(W.shape[0]), nrow), np.abs(W.data))
