@@ -514,12 +514,14 @@ class SubHierarchy:
     nu2: int = 1
 
 
-def sub_level_values(A: sp.csr_matrix, shared: Level, steps: int, seed: int, level0: bool) -> Level:
+def sub_level_values(A: sp.csr_matrix, shared: Level, steps: int, seed: int, level0: bool,
+                     pattern: sp.csr_matrix | None = None) -> Level:
     """One level for a subsystem operator A with the shared level's C/F split
-    and FSAI pattern (from the strength of the shared operator)."""
+    and FSAI pattern (from the strength of the shared operator, or the given
+    lower-triangular ``pattern``: a kept one)."""
     n = A.shape[0]
     C = shared.C
-    S = strength(shared.A, AMGOptions.theta)
+    S = strength(shared.A, AMGOptions.theta) if pattern is None else pattern
     block = C.astype(np.int64) if level0 else np.zeros(n, dtype=np.int64)
     G = fsai(A, S, block)
     om = damping(A, G, seed)
@@ -529,9 +531,12 @@ def sub_level_values(A: sp.csr_matrix, shared: Level, steps: int, seed: int, lev
     return Level(A=A, C=C, P=P, R=R, G=G, omega=om)
 
 
-def build_sub_hierarchy(hier: Hierarchy, sigma: np.ndarray, opt: AMGOptions) -> SubHierarchy:
+def build_sub_hierarchy(hier: Hierarchy, sigma: np.ndarray, opt: AMGOptions,
+                        patterns: list | None = None) -> SubHierarchy:
     """sigma: (n_b, 2^s) outer diagonal.  hier: the shared AMGR hierarchy on
-    A_inn (provides level 0 and the C/F splits and patterns below)."""
+    A_inn (provides level 0 and the C/F splits and patterns below).
+    ``patterns[lev]``: a kept FSAI pattern for level lev (None: from the
+    strength of the shared level)."""
     L0 = hier.levels[0]
     cidx = np.flatnonzero(L0.C)
     subs = []
@@ -543,7 +548,8 @@ def build_sub_hierarchy(hier: Hierarchy, sigma: np.ndarray, opt: AMGOptions) -> 
             if lev == hier.nlev - 1:
                 levels.append(Level(A=A))
                 break
-            Lv = sub_level_values(A, hier.levels[lev], opt.jacobi, opt.seed, False)
+            Lv = sub_level_values(A, hier.levels[lev], opt.jacobi, opt.seed, False,
+                                  None if patterns is None else patterns[lev])
             levels.append(Lv)
             A = galerkin(A, Lv.P)
         fac = sla.cho_factor(levels[-1].A.toarray(), lower=True)

@@ -16,9 +16,9 @@ the same formulas as a fresh setup:
   * FSAI on the kept pattern (block FSAI at level 0, eq. (3.14)) and its
     damping; the Galerkin products (eq. (3.15)) on patterns that the
     unchanged sparsity reproduces;
-  * the per-subsystem levels (amg.build_sub_hierarchy already works on
-    shared patterns) and the low-rank corrections, as krylov.setup builds
-    them.
+  * the per-subsystem levels on the shared splits and interpolation
+    patterns and on the kept FSAI patterns, and the low-rank corrections, as
+    krylov.setup builds them.
 For a matrix whose fresh setup makes the same structural decisions (the same
 matrix, or one scaled by a positive constant: strength, MIS and truncation
 decisions are scale invariant) the re-setup equals the fresh setup.
@@ -74,7 +74,9 @@ def refresh(ctx: dict, A_new: sp.csr_matrix) -> dict:
     sub = None
     if precond == "amgr_sub" and hier.nlev > 1:
         sigma = np.stack([o.diagonal() for o in outs], axis=1)
-        sub = amg.build_sub_hierarchy(hier, sigma, opt)
+        # the subsystem levels keep the earlier setup's FSAI patterns too (a fresh
+        # setup takes them from the strength of the shared values)
+        sub = amg.build_sub_hierarchy(hier, sigma, opt, patterns=[L.G for L in ctx["hier"].levels])
     low = None
     k = 0 if ctx["lrc"] is None else max(len(r) for r in ctx["lrc"].ritz)
     if k > 0:

@@ -77,6 +77,12 @@ def test_refresh_for_a_new_coefficient_keeps_the_identities_and_solves():
         nz = ws != 0
         assert np.abs(ws[nz] - rho[fidx][nz]).max() <= 1e-12 * np.abs(rho).max()
         assert (L.G != ctx["hier"].levels[lev].G).nnz > 0            # values really changed
+    for S0, S1 in zip(ctx["sub"].subs, new["sub"].subs):        # kept FSAI patterns per subsystem
+        for L0, L1 in zip(S0.levels, S1.levels):
+            if L0.G is not None:
+                assert np.array_equal(L0.G.indptr, L1.G.indptr) and np.array_equal(L0.G.indices, L1.G.indices)
+                Gd, Ad = L1.G.toarray(), L1.A.toarray()
+                assert np.abs(np.diag(Gd @ Ad @ Gd.T) - 1).max() < 1e-12
     n = p1.n_b
     V = np.stack([amg.vcycle(H, e) for e in np.eye(n)], axis=1)
     assert np.abs(V - V.T).max() <= 1e-12 * np.abs(V).max()
