@@ -215,6 +215,27 @@ int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ct
    until msp_free. */
 int msp_setup_copies(const msp_csr* A, const msp_copies* map, const msp_opts* o, msp_ctx** out);
 
+/* Numeric re-setup on the device for a new matrix with the sparsity of the
+   setup matrix: d_val (device, rowptr[n] doubles) holds its values in the
+   caller's CSR order of the arrays msp_setup was given; positions that held
+   zeros then are ignored.  The structure of the setup is kept (the
+   interface, every level's C/F split, the smoother patterns, the reduction
+   level's truncated interpolation pattern); every value is recomputed on the
+   GPU with the setup's formulas: A_inn and the outer diagonal (Sec. 2), the
+   interpolation's Jacobi steps and row rescaling (eq. (3.13)), the FSAI
+   factors and their damping (eq. (3.14)), the Galerkin products (eq. (3.15))
+   as masked sparse products, the per-subsystem levels and the dense
+   coarsest inverses (Gauss-Jordan), then the low-rank corrections (Lanczos
+   on the device).  For the setup matrix itself, or a positive multiple of
+   it, the result is the fresh setup's.  Device work on hip_stream; returns
+   when done.  The first call builds the device-side structure (host work
+   proportional to the hierarchy's size, once).  The caller keeps symmetry
+   and the block structure of the map (not checked).  MSP_ERR_UNSUPPORTED for
+   MSP_PC_AMGS and MSP_MIXED_FP32_BF16G; MSP_ERR_NOT_SPD when an FSAI block of
+   the new matrix is not positive definite.  Sec. 6 names a device-side setup
+   as future work; this is its numeric part. */
+int msp_refresh(msp_ctx* c, const double* d_val, void* hip_stream);
+
 /* Solve for m right-hand sides held in device memory (d_b, d_x: n x m
    column-major FP64, on the context's device), enqueued on hip_stream (NULL
    = the default stream).  Returns when the solve has finished.

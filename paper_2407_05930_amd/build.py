@@ -32,6 +32,7 @@ SOURCES = [
     ("fv.cpp", []),
     ("kernels.hip", DEVICE),
     ("sell.hip", DEVICE),
+    ("refresh.hip", DEVICE),
     ("pcg.hip", DEVICE),
 ]
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <numeric>
 #include <array>
 #include <atomic>
 #include <chrono>
@@ -21,6 +22,7 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "pcg.hpp"
+#include "refresh.hpp"
 
 namespace msp {
 
@@ -123,6 +125,57 @@ struct Work {
 
 enum { SC_RR = 0, SC_RZ, SC_PQ, SC_RHO, SC_ALPHA, SC_BETA, SC_THR, SC_RNORM, SC_BN2, SC_TRUE, SC_COUNT };
 
+// Device structure of the numeric re-setup (built by the first msp_refresh).
+struct RfPat {
+    int32_t* rp = nullptr;
+    int32_t* ci = nullptr;
+    int64_t nr = 0, nnz = 0;
+};
+struct RfLevel {
+    int64_t n = 0, nf = 0;
+    RfPat A, G, GT, M, P, R, AP;     // A, M, P, R share the V-cycle matrices' patterns
+    std::vector<RfPat> W;            // Jacobi steps of the interpolation (F rows)
+    int32_t* fidx = nullptr;
+    int8_t* cf = nullptr;
+    int32_t* cnum = nullptr;
+    int32_t* fnum = nullptr;
+    int32_t* pmap = nullptr;         // P entry -> entry of the last Jacobi step (F rows)
+    int64_t* gt_src = nullptr;       // G^T entry -> G entry
+    int64_t* r_src = nullptr;        // R entry -> P entry
+    int64_t* woff = nullptr;         // FSAI workspace offsets
+    double* v0 = nullptr;            // normalised start vector of the damping's power iteration
+    double *a = nullptr, *g = nullptr, *gt = nullptr, *m = nullptr, *p = nullptr, *r = nullptr, *ap = nullptr;
+    std::vector<double*> w;
+    double* afc = nullptr;
+    int8_t* hasf = nullptr;
+    double omega = 0.0;
+};
+struct RefreshState {
+    int64_t* inn_src = nullptr;
+    int64_t* out_src = nullptr;
+    double* sigma = nullptr;                  // n_b x S
+    int64_t* dsig_src = nullptr;              // compact outer-diagonal values <- sigma entries
+    int64_t ndsig = 0;
+    int64_t* dsig1_src = nullptr;
+    int64_t ndsig1 = 0;
+    int64_t* s1_diag = nullptr;               // A_1 diagonal entries of the interface's coarse points
+    int64_t* s1_base = nullptr;               // and their base cells
+    int64_t ns1 = 0;
+    std::vector<RfLevel> lev;
+    double* work = nullptr;
+    double *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+    double* part = nullptr;
+    double* dots = nullptr;
+    int nbp = 256;
+    double *dense = nullptr, *rowk = nullptr, *colk = nullptr;
+    double* sets = nullptr;                   // coarsest operators of every subsystem, interleaved
+    double* gf = nullptr;                     // pc = FSAI: FSAI of A_inn and its transpose map
+    int64_t* gft_src = nullptr;
+    int64_t* gf_woff = nullptr;
+    RfPat gfp, gftp;
+    int* err = nullptr;
+};
+
 // Launch classes for the optional per-kernel timers (msp_set_timing).
 enum {
     KD_OP = 0,        // q = (A_inn + outer diagonal) p
@@ -197,6 +250,7 @@ struct msp_ctx {
     std::vector<int32_t> lrc_kept;
     std::vector<double> lrc_ritz;
     msp::Timers tm;
+    std::unique_ptr<msp::RefreshState> rf;   // numeric re-setup structure (first msp_refresh)
 
     ~msp_ctx() {
         if (on_device) {
@@ -1711,6 +1765,7 @@ static void fill_stats(msp_ctx* c) {
 
 void build_lrc(msp_ctx* c);   // low-rank corrections (below)
 void build_schur_lrc(msp_ctx* c);
+void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st);   // numeric re-setup (below)
 void fv_kappa_grad(msp_fv* f, const double* d_kap, int m, const double* d_lam, const double* d_p, double* d_grad,
                    hipStream_t st);   // fv.cpp
 
@@ -2059,6 +2114,15 @@ int msp_setup_copies(const msp_csr* A, const msp_copies* map, const msp_opts* o,
         const auto t1 = std::chrono::steady_clock::now();
         c->stats.t_setup_s = std::chrono::duration<double>(t1 - t0).count();
         *out = c.release();
+        return MSP_OK;
+    });
+}
+
+int msp_refresh(msp_ctx* c, const double* d_val, void* hip_stream) {
+    return guarded([&]() -> int {
+        if (!c) throw Error(MSP_ERR_ARG, "null context");
+        msp::refresh_device(c, d_val, static_cast<hipStream_t>(hip_stream));
+        msp::fill_stats(c);
         return MSP_OK;
     });
 }
@@ -2504,6 +2568,476 @@ void build_schur_lrc(msp_ctx* c) {
         spmm<double>(c, KD_AMGS, st, C, c->dGS1, w.z, out, nullptr, 1.0, 0.0);
     };
     lanczos_corrections(c, w, nG, false, applyB, op);
+}
+
+// ====================================================================== numeric re-setup on the device
+
+static RfPat upload_pat(msp_ctx* c, const Csr& M) {
+    if (M.nnz() >= (int64_t(1) << 31)) throw Error(MSP_ERR_UNSUPPORTED, "matrix too large for 32-bit indices");
+    RfPat P;
+    P.nr = M.nr;
+    P.nnz = M.nnz();
+    std::vector<int32_t> rp(M.nr + 1);
+    for (int64_t i = 0; i <= M.nr; ++i) rp[i] = static_cast<int32_t>(M.rp[i]);
+    P.rp = c->upload(rp.data(), M.nr + 1);
+    P.ci = c->upload(M.ci.data(), P.nnz);
+    return P;
+}
+
+static RfPat dev_pat(const DevCsr& D) {
+    RfPat P;
+    P.rp = D.rp;
+    P.ci = D.ci;
+    P.nr = D.nr;
+    P.nnz = D.nnz;
+    return P;
+}
+
+// FSAI workspace offsets of G's rows: k^2 + k doubles per row
+static int64_t* fsai_offsets(msp_ctx* c, const Csr& G, int64_t* total) {
+    std::vector<int64_t> off(G.nr + 1, 0);
+    for (int64_t i = 0; i < G.nr; ++i) {
+        const int64_t k = G.rp[i + 1] - G.rp[i];
+        off[i + 1] = off[i] + k * k + k;
+    }
+    *total = off[G.nr];
+    return c->upload(off.data(), G.nr + 1);
+}
+
+// Compact outer-diagonal values (upload_outer's layout) <- sigma entries
+static std::vector<int64_t> outer_sources(const std::vector<double>& dense, int64_t rows, int S,
+                                          const std::vector<int64_t>& base_of_row) {
+    std::vector<int64_t> src;
+    for (int64_t i = 0; i < rows; ++i) {
+        bool any = false;
+        for (int a = 0; a < S; ++a) any |= dense[i * S + a] != 0.0;
+        if (!any) continue;
+        for (int a = 0; a < S; ++a) src.push_back(base_of_row[i] * S + a);
+    }
+    return src;
+}
+
+static void refresh_build(msp_ctx* c) {
+    std::unique_ptr<RefreshState> R(new RefreshState());
+    const int S = 1 << c->sym.s;
+    const int64_t nb = c->sym.n_b;
+    if (static_cast<int64_t>(c->sym.inn_src.size()) != c->sym.Ainn.nnz())
+        throw Error(MSP_ERR_UNSUPPORTED, "no source map of the setup matrix");
+    R->inn_src = c->upload(c->sym.inn_src.data(), static_cast<int64_t>(c->sym.inn_src.size()));
+    if (S > 1) R->out_src = c->upload(c->sym.out_src.data(), static_cast<int64_t>(c->sym.out_src.size()));
+    R->sigma = c->dalloc<double>(nb * S);
+    {
+        std::vector<int64_t> ident(nb);
+        std::iota(ident.begin(), ident.end(), int64_t(0));
+        const std::vector<int64_t> ds = outer_sources(c->sym.sigma, nb, S, ident);
+        if (static_cast<int64_t>(ds.size()) != c->dsig.carried * S) throw Error(MSP_ERR_ARG, "outer diagonal layout");
+        R->ndsig = static_cast<int64_t>(ds.size());
+        if (R->ndsig) R->dsig_src = c->upload(ds.data(), R->ndsig);
+    }
+    R->err = c->dalloc<int>(1);
+    R->part = c->dalloc<double>(2 * R->nbp);
+    R->dots = c->dalloc<double>(2);
+    if (cycle(c)) {
+        const size_t L = c->hier.lev.size();
+        R->lev.resize(L);
+        int64_t work = 0, maxn = 0;
+        for (size_t l = 0; l < L; ++l) {
+            const HostLevel& H = c->hier.lev[l];
+            RfLevel& F = R->lev[l];
+            F.n = H.A.nr;
+            maxn = std::max(maxn, F.n);
+            F.A = l + 1 < L ? dev_pat(c->dl[l].A) : upload_pat(c, H.A);
+            F.a = c->dalloc<double>(H.A.nnz());
+            if (l + 1 == L) break;
+            const DevLevel& D = c->dl[l];
+            if (!D.M.rp) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup needs the explicit smoother");
+            F.G = upload_pat(c, H.G);
+            F.GT = upload_pat(c, H.GT);
+            const std::vector<int64_t> gts = transpose_map(H.G);
+            F.gt_src = c->upload(gts.data(), static_cast<int64_t>(gts.size()));
+            F.M = dev_pat(D.M);
+            F.P = dev_pat(D.P);
+            F.R = dev_pat(D.R);
+            const std::vector<int64_t> rs = transpose_map(H.P);
+            F.r_src = c->upload(rs.data(), static_cast<int64_t>(rs.size()));
+            const int steps = l == 0 ? c->o.jacobi0 : c->o.jacobi;
+            const std::vector<Csr> Ws = interpolation_patterns(H.A, H.cf, steps);
+            for (const Csr& W : Ws) {
+                F.W.push_back(upload_pat(c, W));
+                F.w.push_back(c->dalloc<double>(W.nnz()));
+            }
+            const Csr& WL = Ws.back();
+            F.nf = WL.nr;
+            F.afc = c->dalloc<double>(std::max<int64_t>(1, [&] {
+                int64_t mx = 0;
+                for (const Csr& W : Ws) mx = std::max(mx, W.nnz());
+                return mx;
+            }()));
+            F.hasf = c->dalloc<int8_t>(std::max<int64_t>(1, [&] {
+                int64_t mx = 0;
+                for (const Csr& W : Ws) mx = std::max(mx, W.nnz());
+                return mx;
+            }()));
+            std::vector<int32_t> fidx, cnum(F.n, -1), fnum(F.n, -1);
+            int32_t nc = 0, nf = 0;
+            for (int64_t i = 0; i < F.n; ++i) {
+                if (H.cf[i]) cnum[i] = nc++;
+                else {
+                    fnum[i] = nf++;
+                    fidx.push_back(static_cast<int32_t>(i));
+                }
+            }
+            std::vector<int32_t> pmap(H.P.nnz(), 0);
+            for (int64_t i = 0; i < F.n; ++i) {
+                if (H.cf[i]) continue;
+                const int32_t r = fnum[i];
+                for (int64_t e = H.P.rp[i]; e < H.P.rp[i + 1]; ++e) {
+                    const int32_t* b = WL.ci.data() + WL.rp[r];
+                    const int32_t* en = WL.ci.data() + WL.rp[r + 1];
+                    const int32_t* f = std::lower_bound(b, en, H.P.ci[e]);
+                    if (f == en || *f != H.P.ci[e]) throw Error(MSP_ERR_ARG, "interpolation pattern outside its steps");
+                    pmap[e] = static_cast<int32_t>(f - WL.ci.data());
+                }
+            }
+            F.pmap = c->upload(pmap.data(), static_cast<int64_t>(pmap.size()));
+            F.fidx = c->upload(fidx.data(), std::max<int64_t>(1, nf));
+            F.cnum = c->upload(cnum.data(), F.n);
+            F.fnum = c->upload(fnum.data(), F.n);
+            F.cf = c->upload(H.cf.data(), F.n);
+            F.AP = upload_pat(c, spgemm(H.A, H.P));
+            int64_t wk = 0;
+            F.woff = fsai_offsets(c, H.G, &wk);
+            work = std::max(work, wk);
+            std::vector<double> v0(F.n);
+            double nrm = 0.0;
+            for (int64_t i = 0; i < F.n; ++i) {
+                v0[i] = unit_centered(c->o.seed ^ static_cast<uint64_t>(i));
+                nrm += v0[i] * v0[i];
+            }
+            nrm = std::sqrt(nrm);
+            for (auto& x : v0) x /= nrm;
+            F.v0 = c->upload(v0.data(), F.n);
+            F.g = c->dalloc<double>(H.G.nnz());
+            F.gt = c->dalloc<double>(H.G.nnz());
+            F.m = c->dalloc<double>(H.M.nnz());
+            F.p = c->dalloc<double>(H.P.nnz());
+            F.r = c->dalloc<double>(H.P.nnz());
+            F.ap = c->dalloc<double>(F.AP.nnz);
+        }
+        R->work = c->dalloc<double>(std::max<int64_t>(1, work));
+        R->t1 = c->dalloc<double>(maxn);
+        R->t2 = c->dalloc<double>(maxn);
+        R->t3 = c->dalloc<double>(maxn);
+        const int64_t nL = c->hier.lev.back().A.nr;
+        const int Sd = c->sub ? S : 1;
+        R->dense = c->dalloc<double>(static_cast<int64_t>(Sd) * nL * nL);
+        R->rowk = c->dalloc<double>(static_cast<int64_t>(Sd) * nL);
+        R->colk = c->dalloc<double>(static_cast<int64_t>(Sd) * nL);
+        if (c->sub && L > 2) {
+            R->sets = c->dalloc<double>(c->hier.lev.back().A.nnz() * S);
+            // interface coarse points: their A_1 diagonal entries and base cells
+            const HostLevel& L0 = c->hier.lev[0];
+            const Csr& A1 = c->hier.lev[1].A;
+            std::vector<int64_t> diag, base, rowbase(A1.nr, -1);
+            int64_t j = 0;
+            for (int64_t i = 0; i < L0.A.nr; ++i) {
+                if (!L0.cf[i]) continue;
+                rowbase[j] = i;
+                if (c->sym.iface[i]) {
+                    const int32_t* b = A1.ci.data() + A1.rp[j];
+                    const int32_t* e = A1.ci.data() + A1.rp[j + 1];
+                    const int32_t* f = std::lower_bound(b, e, static_cast<int32_t>(j));
+                    if (f == e || *f != j) throw Error(MSP_ERR_ARG, "missing diagonal in the reduced operator");
+                    diag.push_back(f - A1.ci.data());
+                    base.push_back(i);
+                }
+                ++j;
+            }
+            R->ns1 = static_cast<int64_t>(diag.size());
+            if (R->ns1) {
+                R->s1_diag = c->upload(diag.data(), R->ns1);
+                R->s1_base = c->upload(base.data(), R->ns1);
+            }
+            // level-1 compact outer diagonal (upload_all's s1 layout)
+            std::vector<double> s1(static_cast<size_t>(A1.nr) * S, 0.0);
+            for (int64_t q = 0; q < A1.nr; ++q)
+                if (rowbase[q] >= 0 && c->sym.iface[rowbase[q]])
+                    for (int a = 0; a < S; ++a) s1[q * S + a] = c->sym.sigma[rowbase[q] * S + a];
+            const std::vector<int64_t> d1 = outer_sources(s1, A1.nr, S, rowbase);
+            if (static_cast<int64_t>(d1.size()) != c->dsig1.carried * S) throw Error(MSP_ERR_ARG, "level-1 outer layout");
+            R->ndsig1 = static_cast<int64_t>(d1.size());
+            if (R->ndsig1) R->dsig1_src = c->upload(d1.data(), R->ndsig1);
+        } else if (c->sub) {   // two levels: the coarsest operators are A_1,a themselves
+            R->sets = c->dalloc<double>(c->hier.lev.back().A.nnz() * S);
+            const HostLevel& L0 = c->hier.lev[0];
+            const Csr& A1 = c->hier.lev[1].A;
+            std::vector<int64_t> diag, base;
+            int64_t j = 0;
+            for (int64_t i = 0; i < L0.A.nr; ++i) {
+                if (!L0.cf[i]) continue;
+                if (c->sym.iface[i]) {
+                    const int32_t* b = A1.ci.data() + A1.rp[j];
+                    const int32_t* e = A1.ci.data() + A1.rp[j + 1];
+                    const int32_t* f = std::lower_bound(b, e, static_cast<int32_t>(j));
+                    if (f == e || *f != j) throw Error(MSP_ERR_ARG, "missing diagonal in the reduced operator");
+                    diag.push_back(f - A1.ci.data());
+                    base.push_back(i);
+                }
+                ++j;
+            }
+            R->ns1 = static_cast<int64_t>(diag.size());
+            if (R->ns1) {
+                R->s1_diag = c->upload(diag.data(), R->ns1);
+                R->s1_base = c->upload(base.data(), R->ns1);
+            }
+        }
+    } else if (c->o.pc == MSP_PC_FSAI) {
+        R->gfp = dev_pat(c->dGf);
+        R->gftp = dev_pat(c->dGfT);
+        const std::vector<int64_t> m = transpose_map(c->Gf);
+        R->gft_src = c->upload(m.data(), static_cast<int64_t>(m.size()));
+        int64_t wk = 0;
+        R->gf_woff = fsai_offsets(c, c->Gf, &wk);
+        R->work = c->dalloc<double>(std::max<int64_t>(1, wk));
+    }
+    c->rf = std::move(R);
+}
+
+// One level's FSAI, damping and explicit smoother from the values in F.a.
+static void refresh_smoother(RefreshState& R, RfLevel& F, hipStream_t st) {
+    HIPCHECK(launch_fsai(st, F.n, F.A.rp, F.A.ci, F.a, F.G.rp, F.G.ci, F.g, F.woff, R.work, R.err));
+    HIPCHECK(launch_gather(st, F.G.nnz, F.gt_src, F.g, F.gt));
+    // omega = 4 / (3 lambda), lambda from 20 power iterations on G A G^T
+    HIPCHECK(hipMemcpyAsync(R.t3, F.v0, sizeof(double) * F.n, hipMemcpyDeviceToDevice, st));
+    for (int it = 0; it < 20; ++it) {
+        HIPCHECK(launch_spmv(st, F.n, F.GT.rp, F.GT.ci, F.gt, R.t3, R.t1));
+        HIPCHECK(launch_spmv(st, F.n, F.A.rp, F.A.ci, F.a, R.t1, R.t2));
+        HIPCHECK(launch_spmv(st, F.n, F.G.rp, F.G.ci, F.g, R.t2, R.t1));
+        HIPCHECK(launch_power_dots(st, F.n, R.t3, R.t1, R.part, R.nbp, R.dots));
+        HIPCHECK(launch_normalise(st, F.n, R.t1, R.dots, R.t3));
+    }
+    double dots[2];
+    HIPCHECK(hipMemcpyAsync(dots, R.dots, sizeof(dots), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    F.omega = 4.0 / (3.0 * dots[0]);
+    HIPCHECK(launch_spgemm_masked(st, F.n, F.GT.rp, F.GT.ci, F.gt, F.G.rp, F.G.ci, F.g, F.M.rp, F.M.ci, F.m, R.err));
+    HIPCHECK(launch_scale(st, F.M.nnz, F.m, F.omega));
+}
+
+// Interpolation (the Jacobi steps, the kept pattern, the row rescaling), R, and next = R (A P).
+static void refresh_transfer(RefreshState& R, RfLevel& F, double* next, const RfPat& nextpat,
+                             hipStream_t st) {
+    for (size_t t = 0; t < F.W.size(); ++t) {
+        const bool first = t == 0;
+        HIPCHECK(launch_interp_step(st, F.nf, F.fidx, F.A.rp, F.A.ci, F.a, F.cf, F.cnum, F.fnum,
+                                    first ? nullptr : F.W[t - 1].rp, first ? nullptr : F.W[t - 1].ci,
+                                    first ? nullptr : F.w[t - 1], F.W[t].rp, F.W[t].ci, F.w[t], F.afc, F.hasf, R.err));
+    }
+    HIPCHECK(launch_interp_finish(st, F.n, F.cf, F.A.rp, F.A.ci, F.a, F.w.back(), F.P.rp, F.pmap, F.p));
+    HIPCHECK(launch_gather(st, F.R.nnz, F.r_src, F.p, F.r));
+    HIPCHECK(launch_spgemm_masked(st, F.n, F.A.rp, F.A.ci, F.a, F.P.rp, F.P.ci, F.p, F.AP.rp, F.AP.ci, F.ap, R.err));
+    HIPCHECK(launch_spgemm_masked(st, nextpat.nr, F.R.rp, F.R.ci, F.r, F.AP.rp, F.AP.ci, F.ap, nextpat.rp,
+                                  nextpat.ci, next, R.err));
+}
+
+// FP32 copy of a device matrix's values (mixed modes)
+static void refresh_f32(hipStream_t st, DevCsr& D) {
+    if (D.v32) HIPCHECK((launch_cast<float, double>(st, D.nnz * D.vs, D.v64, D.v32)));
+}
+
+void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
+    if (!d_val) throw Error(MSP_ERR_ARG, "null values");
+    if (!c->on_device) throw Error(MSP_ERR_ARG, "the context has no device setup");
+    if (c->o.pc == MSP_PC_AMGS) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup of AMGS");
+    if (c->o.precision == MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup of the BF16-G variant");
+    HIPCHECK(hipSetDevice(c->device));
+    if (!c->rf) refresh_build(c);
+    RefreshState& R = *c->rf;
+    const int S = 1 << c->sym.s;
+    const int64_t nb = c->sym.n_b;
+    HIPCHECK(hipMemsetAsync(R.err, 0, sizeof(int), st));
+    // A_inn (operator and level 0) and the outer diagonal from the caller's values
+    HIPCHECK(launch_gather(st, c->dAinn.nnz, R.inn_src, d_val, c->dAinn.v64));
+    HIPCHECK(launch_outer_sigma(st, nb, S, R.out_src, d_val, R.sigma));
+    if (R.ndsig) HIPCHECK(launch_gather(st, R.ndsig, R.dsig_src, R.sigma, const_cast<double*>(c->dsig.d.val)));
+    if (cycle(c)) {
+        const size_t L = R.lev.size();
+        HIPCHECK(hipMemcpyAsync(R.lev[0].a, c->dAinn.v64, sizeof(double) * c->dAinn.nnz, hipMemcpyDeviceToDevice,
+                                st));
+        // shared levels (with per-subsystem values below the reduction level the
+        // device applies only level 0 of them; the rest is mirrored on the host)
+        for (size_t l = 0; l + 1 < L; ++l) {
+            RfLevel& F = R.lev[l];
+            refresh_smoother(R, F, st);
+            refresh_transfer(R, F, R.lev[l + 1].a, R.lev[l + 1].A, st);
+            if (c->sub && l > 0) {
+                HostLevel& H = c->hier.lev[l];
+                auto mirror = [&](std::vector<double>& h, const double* d) {
+                    HIPCHECK(hipMemcpyAsync(h.data(), d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+                };
+                mirror(H.A.v, F.a);
+                mirror(H.G.v, F.g);
+                mirror(H.GT.v, F.gt);
+                mirror(H.M.v, F.m);
+                mirror(H.P.v, F.p);
+                mirror(H.R.v, F.r);
+                HIPCHECK(hipStreamSynchronize(st));
+                H.omega = F.omega;
+                continue;
+            }
+            DevLevel& D = c->dl[l];
+            D.omega = F.omega;
+            auto put = [&](DevCsr& M, const double* v) {
+                HIPCHECK(hipMemcpyAsync(M.v64, v, sizeof(double) * M.nnz, hipMemcpyDeviceToDevice, st));
+            };
+            put(D.A, F.a);
+            put(D.M, F.m);
+            put(D.P, F.p);
+            put(D.R, F.r);
+        }
+        const int64_t nL = c->hier.lev.back().A.nr;
+        if (c->sub) {   // host mirror of the shared coarsest matrix
+            std::vector<double>& h = c->hier.lev[L - 1].A.v;
+            HIPCHECK(hipMemcpyAsync(h.data(), R.lev[L - 1].a, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+        }
+        if (!c->sub) {
+            RfLevel& FL = R.lev[L - 1];
+            HIPCHECK(launch_dense_inverse(st, nL, 1, FL.A.rp, FL.A.ci, FL.a, R.dense, R.rowk, R.colk));
+            HIPCHECK(hipMemcpyAsync(c->d_cinv, R.dense, sizeof(double) * nL * nL, hipMemcpyDeviceToDevice, st));
+        } else {
+            // A_1 shared values and the level-1 outer diagonal (three or more levels)
+            if (L > 2)
+                HIPCHECK(hipMemcpyAsync(c->dl[1].A.v64, R.lev[1].a, sizeof(double) * c->dl[1].A.nnz,
+                                        hipMemcpyDeviceToDevice, st));
+            if (R.ndsig1)
+                HIPCHECK(launch_gather(st, R.ndsig1, R.dsig1_src, R.sigma, const_cast<double*>(c->dsig1.d.val)));
+            double* shared1 = c->dalloc<double>(R.lev[1].A.nnz);
+            HIPCHECK(hipMemcpyAsync(shared1, R.lev[1].a, sizeof(double) * R.lev[1].A.nnz, hipMemcpyDeviceToDevice, st));
+            for (int a = 0; a < S; ++a) {
+                HIPCHECK(hipMemcpyAsync(R.lev[1].a, shared1, sizeof(double) * R.lev[1].A.nnz, hipMemcpyDeviceToDevice,
+                                        st));
+                if (R.ns1) HIPCHECK(launch_add_sigma(st, R.ns1, R.s1_diag, R.s1_base, R.sigma, S, a, R.lev[1].a));
+                if (L > 2) {   // host mirror of A_1,a (the device applies A_1 and the outer diagonal)
+                    std::vector<double> h(R.lev[1].A.nnz);
+                    HIPCHECK(hipMemcpyAsync(h.data(), R.lev[1].a, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+                    HIPCHECK(hipStreamSynchronize(st));
+                    for (size_t k = 0; k < h.size(); ++k) c->subv.A[1][k * S + a] = h[k];
+                }
+                for (size_t l = 1; l + 1 < L; ++l) {
+                    RfLevel& F = R.lev[l];
+                    refresh_smoother(R, F, st);
+                    {   // host mirror of the subsystem's FSAI factor
+                        std::vector<double> h(F.G.nnz);
+                        HIPCHECK(hipMemcpyAsync(h.data(), F.g, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+                        HIPCHECK(hipStreamSynchronize(st));
+                        for (size_t k = 0; k < h.size(); ++k) c->subv.G[l][k * S + a] = h[k];
+                    }
+                    refresh_transfer(R, F, R.lev[l + 1].a, R.lev[l + 1].A, st);
+                    DevLevel& D = c->dl[l];
+                    c->subv.omega[l][a] = F.omega;
+                    HIPCHECK(launch_strided_copy(st, F.P.nnz, F.p, 1, 0, D.P.v64, S, a));
+                    HIPCHECK(launch_strided_copy(st, F.R.nnz, F.r, 1, 0, D.R.v64, S, a));
+                    HIPCHECK(launch_strided_copy(st, F.M.nnz, F.m, 1, 0, D.M.v64, S, a));
+                    if (l + 1 < L - 1)
+                        HIPCHECK(launch_strided_copy(st, R.lev[l + 1].A.nnz, R.lev[l + 1].a, 1, 0, c->dl[l + 1].A.v64, S,
+                                                     a));
+                }
+                HIPCHECK(launch_strided_copy(st, R.lev[L - 1].A.nnz, R.lev[L - 1].a, 1, 0, R.sets, S, a));
+            }
+            HIPCHECK(hipStreamSynchronize(st));
+            c->dfree(shared1);
+            const RfLevel& FL = R.lev[L - 1];
+            HIPCHECK(launch_dense_inverse(st, nL, S, FL.A.rp, FL.A.ci, R.sets, R.dense, R.rowk, R.colk));
+            if (c->d_cinv32) {
+                const int64_t ld = dense_sets_ld(nL, 4);
+                HIPCHECK(launch_dense_to_f32(st, S, nL, ld, R.dense, c->d_cinv32));
+            } else {
+                HIPCHECK(hipMemcpyAsync(c->d_cinv, R.dense, sizeof(double) * S * nL * nL, hipMemcpyDeviceToDevice, st));
+            }
+        }
+        // FP32 copies of the level matrices (mixed modes)
+        for (DevLevel& D : c->dl) {
+            refresh_f32(st, D.A);
+            refresh_f32(st, D.P);
+            refresh_f32(st, D.R);
+            refresh_f32(st, D.M);
+        }
+    } else if (c->o.pc == MSP_PC_FSAI) {
+        HIPCHECK(launch_fsai(st, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, R.gfp.rp, R.gfp.ci, c->dGf.v64, R.gf_woff,
+                             R.work, R.err));
+        HIPCHECK(launch_gather(st, R.gftp.nnz, R.gft_src, c->dGf.v64, c->dGfT.v64));
+    }
+    int err = 0;
+    HIPCHECK(hipMemcpyAsync(&err, R.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    if (err & 2) throw Error(MSP_ERR_NOT_SPD, "re-setup: an FSAI block of the new matrix is not positive definite");
+    if (err) throw Error(MSP_ERR_ARG, "re-setup: a product left its kept pattern");
+
+    // host mirror of every value (exports, sliced forms and the autotuner read it)
+    auto down = [&](std::vector<double>& h, const double* d, int64_t count) {
+        h.resize(count);
+        HIPCHECK(hipMemcpy(h.data(), d, sizeof(double) * count, hipMemcpyDeviceToHost));
+    };
+    down(c->sym.Ainn.v, c->dAinn.v64, c->dAinn.nnz);
+    down(c->sym.sigma, R.sigma, nb * S);
+    if (cycle(c)) {
+        const size_t L = R.lev.size();
+        for (size_t l = 0; l < L; ++l) {
+            HostLevel& H = c->hier.lev[l];
+            RfLevel& F = R.lev[l];
+            const bool shared = !c->sub || l == 0;   // per-subsystem mode mirrored levels >= 1 above
+            if (shared) down(H.A.v, F.a, H.A.nnz());
+            if (l + 1 == L) break;
+            if (!shared) continue;
+            down(H.G.v, F.g, H.G.nnz());
+            down(H.GT.v, F.gt, H.GT.nnz());
+            down(H.M.v, F.m, H.M.nnz());
+            down(H.P.v, F.p, H.P.nnz());
+            down(H.R.v, F.r, H.R.nnz());
+            H.omega = F.omega;
+        }
+        if (c->sub) {
+            for (size_t l = 1; l + 1 < L; ++l) {
+                const DevLevel& D = c->dl[l];
+                down(c->subv.P[l], D.P.v64, D.P.nnz * S);
+                down(c->subv.R[l], D.R.v64, D.R.nnz * S);
+                down(c->subv.M[l], D.M.v64, D.M.nnz * S);
+                if (l >= 2) down(c->subv.A[l], D.A.v64, D.A.nnz * S);
+            }
+            down(c->subv.A[L - 1], R.sets, c->hier.lev.back().A.nnz() * S);
+            down(c->subv.coarse_inv, R.dense, static_cast<int64_t>(S) * c->nL * c->nL);
+        } else {
+            down(c->hier.coarse_inv, R.dense, c->nL * c->nL);
+        }
+        // sliced forms carry copies of the values: rebuild the ones in use
+        for (DevLevel& D : c->dl)
+            for (DevCsr* M : {&D.A, &D.P, &D.R, &D.M})
+                for (int q = 0; q < kSellForms; ++q)
+                    if (M->sell[q].G) {
+                        const int G = M->sell[q].G;
+                        free_sell(c, M->sell[q]);
+                        build_sell(c, *M, G);
+                    }
+    } else if (c->o.pc == MSP_PC_FSAI) {
+        down(c->Gf.v, c->dGf.v64, c->dGf.nnz);
+    }
+    for (int q = 0; q < kSellForms; ++q)
+        if (c->dAinn.sell[q].G) {
+            const int G = c->dAinn.sell[q].G;
+            free_sell(c, c->dAinn.sell[q]);
+            build_sell(c, c->dAinn, G);
+        }
+    // low-rank corrections of the new operators
+    if (c->lrc_k > 0) {
+        for (void* q : {c->d_U, static_cast<void*>(c->d_lrc_coef), static_cast<void*>(c->d_lrc_part),
+                        static_cast<void*>(c->d_lrc_W)})
+            if (q) c->dfree(q);
+        c->d_U = nullptr;
+        c->d_lrc_coef = c->d_lrc_part = c->d_lrc_W = nullptr;
+        build_lrc(c);
+    }
+    HIPCHECK(hipDeviceSynchronize());
 }
 
 }  // namespace msp

@@ -52,6 +52,68 @@ Csr transpose(const Csr& A) {
     return T;   // rows of T come out sorted because rows of A are visited in order
 }
 
+std::vector<int64_t> transpose_map(const Csr& A) {
+    const int64_t nnz = A.nnz();
+    std::vector<int64_t> rp(A.nc + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) rp[A.ci[k] + 1]++;
+    for (int64_t i = 0; i < A.nc; ++i) rp[i + 1] += rp[i];
+    std::vector<int64_t> map(nnz);
+    for (int64_t i = 0; i < A.nr; ++i)
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) map[rp[A.ci[k]]++] = k;
+    return map;
+}
+
+std::vector<Csr> interpolation_patterns(const Csr& A, const std::vector<int8_t>& cf, int steps) {
+    const int64_t n = A.nr;
+    std::vector<int32_t> cnum(n, -1), fnum(n, -1);
+    int32_t nc = 0, nf = 0;
+    std::vector<int64_t> fidx;
+    for (int64_t i = 0; i < n; ++i) {
+        if (cf[i]) cnum[i] = nc++;
+        else {
+            fnum[i] = nf++;
+            fidx.push_back(i);
+        }
+    }
+    std::vector<Csr> out;
+    std::vector<int64_t> mark(nc, -1);
+    std::vector<int32_t> cols;
+    for (int t = 0; t < steps; ++t) {
+        const Csr* prev = t > 0 ? &out.back() : nullptr;
+        Csr W;
+        W.nr = nf;
+        W.nc = nc;
+        W.rp.assign(nf + 1, 0);
+        for (int32_t r = 0; r < nf; ++r) {
+            const int64_t i = fidx[r];
+            cols.clear();
+            for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                const int32_t c = A.ci[k];
+                if (c == i) continue;
+                if (cf[c]) {
+                    if (mark[cnum[c]] != r) {
+                        mark[cnum[c]] = r;
+                        cols.push_back(cnum[c]);
+                    }
+                } else if (prev) {
+                    const int32_t f = fnum[c];
+                    for (int64_t p = prev->rp[f]; p < prev->rp[f + 1]; ++p)
+                        if (mark[prev->ci[p]] != r) {
+                            mark[prev->ci[p]] = r;
+                            cols.push_back(prev->ci[p]);
+                        }
+                }
+            }
+            std::sort(cols.begin(), cols.end());
+            W.ci.insert(W.ci.end(), cols.begin(), cols.end());
+            W.rp[r + 1] = static_cast<int64_t>(W.ci.size());
+        }
+        std::fill(mark.begin(), mark.end(), -1);
+        out.push_back(std::move(W));
+    }
+    return out;
+}
+
 Csr spgemm(const Csr& A, const Csr& B) {
     Csr C;
     C.nr = A.nr;
@@ -96,8 +158,8 @@ static void spmv(const Csr& A, const double* x, double* y) {
 // ------------------------------------------------------------------ block extraction
 
 // Sorted, zero-free copy of the caller's matrix, checked for valid indices,
-// duplicates and exact symmetry.
-static Csr checked_copy(const msp_csr* A) {
+// duplicates and exact symmetry; src[k] = position of entry k in the caller's arrays.
+static Csr checked_copy(const msp_csr* A, std::vector<int64_t>* src = nullptr) {
     const int64_t n = A->n;
     if (n >= (int64_t(1) << 31)) throw Error(MSP_ERR_UNSUPPORTED, "n must fit in int32");
     const int64_t* rp = A->rowptr;
@@ -112,18 +174,23 @@ static Csr checked_copy(const msp_csr* A) {
     As.rp.assign(n + 1, 0);
     As.ci.reserve(nnz);
     As.v.reserve(nnz);
-    std::vector<std::pair<int32_t, double>> row;
+    std::vector<std::pair<int32_t, int64_t>> row;   // (column, caller position)
+    if (src) {
+        src->clear();
+        src->reserve(nnz);
+    }
     for (int64_t g = 0; g < n; ++g) {
         row.clear();
         for (int64_t k = rp[g]; k < rp[g + 1]; ++k)
-            if (A->val[k] != 0.0 || std::isnan(A->val[k])) row.emplace_back(A->col[k], A->val[k]);
+            if (A->val[k] != 0.0 || std::isnan(A->val[k])) row.emplace_back(A->col[k], k);
         std::sort(row.begin(), row.end(),
-                  [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) { return x.first < y.first; });
+                  [](const std::pair<int32_t, int64_t>& x, const std::pair<int32_t, int64_t>& y) { return x.first < y.first; });
         for (size_t q = 1; q < row.size(); ++q)
             if (row[q].first == row[q - 1].first) throw Error(MSP_ERR_ARG, "duplicate entry in a row");
         for (auto& e : row) {
             As.ci.push_back(e.first);
-            As.v.push_back(e.second);
+            As.v.push_back(A->val[e.second]);
+            if (src) src->push_back(e.second);
         }
         As.rp[g + 1] = static_cast<int64_t>(As.ci.size());
     }
@@ -150,7 +217,8 @@ SymParts extract_blocks(const msp_csr* A, const msp_symmap* map) {
     if (n <= 0 || map->n_b <= 0 || (map->n_b << s) != n)
         throw Error(MSP_ERR_ARG, "n must equal n_b * 2^s and be positive");
     const int64_t n_b = map->n_b;
-    const Csr As = checked_copy(A);
+    std::vector<int64_t> asrc;
+    const Csr As = checked_copy(A, &asrc);
 
     // map: permutation, inverse
     std::vector<int32_t> inv_i(n, -1);
@@ -173,13 +241,15 @@ SymParts extract_blocks(const msp_csr* A, const msp_symmap* map) {
     P.iface.assign(n_b, 0);
     P.Ainn.nr = P.Ainn.nc = n_b;
     P.Ainn.rp.assign(n_b + 1, 0);
-    struct Ent { int32_t j; int32_t l; double v; };
+    P.src_nnz = A->rowptr[n];
+    P.out_src.assign(static_cast<size_t>(n_b) * (S - 1), -1);
+    struct Ent { int32_t j; int32_t l; double v; int64_t src; };
     std::vector<Ent> canon, cur;
     auto row_entries = [&](int64_t g, int a, std::vector<Ent>& out) {
         out.clear();
         for (int64_t k = As.rp[g]; k < As.rp[g + 1]; ++k) {
             const int32_t h = As.ci[k];
-            out.push_back({a ^ inv_a[h], inv_i[h], As.v[k]});
+            out.push_back({a ^ inv_a[h], inv_i[h], As.v[k], asrc[k]});
         }
         std::sort(out.begin(), out.end(), [](const Ent& x, const Ent& y) {
             return x.j != y.j ? x.j < y.j : x.l < y.l;
@@ -202,11 +272,13 @@ SymParts extract_blocks(const msp_csr* A, const msp_symmap* map) {
             if (e.j == 0) {
                 P.Ainn.ci.push_back(e.l);
                 P.Ainn.v.push_back(e.v);
+                P.inn_src.push_back(e.src);
             } else {
                 if (e.l != i)
                     throw Error(MSP_ERR_UNSUPPORTED,
                                 "outer blocks H_j (j != 0) must be diagonal (two-point stencils)");
                 hdiag[e.j] = e.v;
+                P.out_src[static_cast<size_t>(i) * (S - 1) + (e.j - 1)] = e.src;
                 P.iface[i] = 1;
             }
         }
@@ -660,7 +732,8 @@ CopyParts extract_copies(const msp_csr* A, const msp_copies* map, const msp_opts
     CopyParts P;
     P.sym.s = 0;
     P.sym.n = P.sym.n_b = n;
-    P.sym.Ainn = checked_copy(A);
+    P.sym.Ainn = checked_copy(A, &P.sym.inn_src);
+    P.sym.src_nnz = A->rowptr[n];
     const Csr& As = P.sym.Ainn;
     std::vector<int32_t> copy_of(n, -1), base_of(n, -1);
     for (int64_t i = 0; i < n_b; ++i)

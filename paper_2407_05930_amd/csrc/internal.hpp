@@ -26,6 +26,12 @@ struct Csr {
 };
 
 Csr transpose(const Csr& A);
+// Entry p of transpose(A) is entry map[p] of A.
+std::vector<int64_t> transpose_map(const Csr& A);
+// Symbolic patterns of the interpolation's Jacobi steps W_1 .. W_steps (rows:
+// the F points in increasing order; columns: coarse numbers), as the
+// interpolation builds them before any truncation; values left empty.
+std::vector<Csr> interpolation_patterns(const Csr& A, const std::vector<int8_t>& cf, int steps);
 // Product with the structural pattern (explicit zeros kept); each value is
 // sum_k A_ik B_kj accumulated in increasing k (Gustavson order).
 Csr spgemm(const Csr& A, const Csr& B);
@@ -68,6 +74,11 @@ struct SymParts {
     std::vector<double> sigma;      // n_b * 2^s, diagonal of A_out,a
     std::vector<int8_t> iface;      // n_b
     std::vector<int64_t> img;       // n_b * 2^s
+    // where the values come from in the caller's CSR arrays (the numeric re-setup
+    // gathers a new matrix's values through these): A_inn entry k <- inn_src[k];
+    // outer coupling j of base cell i <- out_src[i * (2^s - 1) + j - 1] (-1: none)
+    std::vector<int64_t> inn_src, out_src;
+    int64_t src_nnz = 0;
 };
 
 SymParts extract_blocks(const msp_csr* A, const msp_symmap* map);

@@ -59,7 +59,7 @@ class Solver:
     indptr/indices/data) and the symmetry map ``img`` (n_b x 2^s, row of
     image a of base cell i); options as in ``msp_opts`` (``k`` = LRC rank,
     ``precision`` in {"fp64", "mixed", "mixed_bf16g", "mixed_bf16"}, ``pc`` in
-    {"amgr", "fsai", "none", "amgr_sub"}, ``device`` = -1 for a host-only setup)."""
+    {"amgr", "fsai", "none", "amgr_sub", "amgs"}, ``device`` = -1 for a host-only setup)."""
 
     def __init__(self, A, img, **opts):
         img = np.ascontiguousarray(img, dtype=np.int64)
@@ -98,6 +98,19 @@ class Solver:
                                    ctypes.byref(self._ctx)))
         self.last = _lib.msp_stats()
         return self
+
+    def refresh(self, values, stream=None):
+        """Numeric re-setup on the device (msp_refresh) for a matrix with the
+        setup matrix's sparsity: ``values`` are its nonzeros in the CSR order
+        of the matrix given at setup (a float64 CUDA tensor, or a host array
+        that is copied to the device first)."""
+        import torch
+        if not torch.is_tensor(values):
+            values = torch.from_numpy(np.ascontiguousarray(values, dtype=np.float64)).cuda()
+        if values.dtype != torch.float64 or not values.is_cuda or not values.is_contiguous():
+            raise ValueError("values must be a contiguous float64 CUDA tensor")
+        st = stream if stream is not None else torch.cuda.current_stream(values.device)
+        check(lib.msp_refresh(self._ctx, ctypes.c_void_p(values.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
 
     # ------------------------------------------------------------------ solves
     def solve(self, b, stream=None):

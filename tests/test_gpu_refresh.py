@@ -1,0 +1,277 @@
+"""GPU parity of the numeric re-setup on the device (msp_refresh) against the
+oracle's re-setup (oracle/refresh.py) and against fresh setups: every level's
+values, the dampings, the low-rank corrections and the solves that follow."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from gen import make_problem
+from oracle import amg, krylov, refresh
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-13
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cancel(P):
+    """sum |w| / |sum w| over P's rows: the factor by which the row rescaling
+    of eq. (3.13) amplifies rounding differences in the weights."""
+    W = abs(P)
+    return float((np.asarray(W.sum(axis=1)).ravel() /
+                  np.maximum(np.abs(np.asarray(P.sum(axis=1)).ravel()), 1e-300)).max())
+
+
+def _close(M1, M2, tol):
+    assert np.array_equal(M1.indptr, M2.indptr) and np.array_equal(M1.indices, M2.indices)
+    assert np.abs(M1.data - M2.data).max() <= tol * np.abs(M2.data).max()
+
+
+def _check_levels(sv, H, sub=None, base=1e-12):
+    """Library levels (shared, then per subsystem) against the oracle's
+    hierarchy H (and its subsystem hierarchies), patterns bit for bit."""
+    assert sv.num_levels() == H.nlev
+    amp = 1.0
+    shared = H.nlev if sub is None else 1
+    for lev in range(H.nlev):
+        if lev >= shared and lev > 0:
+            break
+        e = sv.export_level(lev)
+        L = H.levels[lev]
+        _close(e["A"], L.A, base * amp)
+        if L.C is not None:
+            assert np.array_equal(e["cf"], L.C)
+            amp = max(amp, _cancel(L.P))
+            _close(e["P"], L.P, base * amp)
+            _close(e["G"], L.G, base * amp)
+            assert abs(e["omega"] - L.omega) <= 1e-10 * L.omega
+    if sub is None:
+        return
+    for a, SH in enumerate(sub.subs):
+        amp_a = amp
+        for lev in range(1, H.nlev):
+            e = sv.export_sub_level(lev, a)
+            L = SH.levels[lev - 1]
+            _close(e["A"], L.A, base * amp_a)
+            if L.P is not None:
+                amp_a = max(amp_a, _cancel(L.P))
+                _close(e["P"], L.P, base * amp_a)
+                _close(e["G"], L.G, base * amp_a)
+                assert abs(e["omega"] - L.omega) <= 1e-10 * L.omega
+
+
+def _snapshot(sv, nlev, sub):
+    out = [sv.export_level(lev) for lev in range(nlev)]
+    if sub:
+        out += [sv.export_sub_level(lev, a) for a in range(sub) for lev in range(1, nlev)]
+    return out
+
+
+def _same(s1, s2, tol):
+    assert len(s1) == len(s2)
+    for e1, e2 in zip(s1, s2):
+        for key in ("A", "P", "G"):
+            if key in e2:
+                _close(e1[key], e2[key], tol)
+        assert abs(e1["omega"] - e2["omega"]) <= 1e-10 * max(abs(e2["omega"]), 1e-300)
+
+
+@pytest.mark.parametrize("pc,k", [("amgr", 0), ("amgr_sub", 0), ("amgr", 4), ("amgr_sub", 4)])
+def test_refresh_with_the_setup_values_reproduces_the_setup(pc, k):
+    """The re-setup from the setup matrix's own values gives the setup's
+    hierarchy again, and the solve afterwards takes the same iterations."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("refresh same values", pc, k)
+    p = make_problem((24, 20, 16), s=3, m=2, seed=31, y_stretch=1.5, kappa="lognormal")
+    opt = dict(coarse_max=48)
+    sv = Solver(p.A, p.img, tol=TOL, pc=pc, k=k, **opt)
+    nlev = sv.num_levels()
+    S = 8 if pc == "amgr_sub" else 0
+    before = _snapshot(sv, nlev, S)
+    kept0, ritz0 = sv.export_lrc() if k else (None, None)
+    b = torch.from_numpy(p.b).cuda()
+    x0 = sv.solve(b).cpu().numpy()
+    it0 = sv.last.iters
+    sv.refresh(torch.from_numpy(p.A.data).cuda())
+    torch.cuda.synchronize()
+    _same(_snapshot(sv, nlev, S), before, 1e-12)
+    if k:
+        kept, ritz = sv.export_lrc()
+        assert np.array_equal(kept, kept0)
+        assert np.abs(ritz - ritz0).max() <= 1e-8 * max(1.0, np.abs(ritz0).max())
+    x = sv.solve(b).cpu().numpy()
+    _say("its before", it0, "after", sv.last.iters)
+    assert abs(sv.last.iters - it0) <= (1 if k else 0)
+    assert np.linalg.norm(x - x0) <= 1e-9 * np.linalg.norm(x0)
+
+
+NEW_CASES = [
+    dict(name="amgr_s3", pc="amgr", k=0, N=(24, 20, 16), s=3, m=2, kw=dict(y_stretch=1.5)),
+    dict(name="amgr_sub_s3", pc="amgr_sub", k=0, N=(24, 20, 16), s=3, m=2, kw=dict(y_stretch=1.5)),
+    dict(name="amgr_s2_jitter", pc="amgr", k=0, N=(28, 24, 20), s=2, m=1, kw=dict(jitter=0.2)),
+    dict(name="amgr_sub_s2_lrc", pc="amgr_sub", k=4, N=(20, 16, 16), s=2, m=3, kw=dict(y_stretch=1.5)),
+    dict(name="amgr_s3_lrc", pc="amgr", k=8, N=(16, 16, 16), s=3, m=2, kw=dict(y_stretch=1.5)),
+    dict(name="amgr_2d_s1", pc="amgr", k=0, N=(64, 48), s=1, m=2, kw=dict()),
+]
+
+
+@pytest.mark.parametrize("case", NEW_CASES, ids=[c["name"] for c in NEW_CASES])
+def test_refresh_for_a_new_coefficient_matches_the_oracle(case):
+    """A new lognormal kappa on the same mesh: every level, damping and Ritz
+    value of the device re-setup equals the oracle's re-setup on the kept
+    structure, and the solve matches the oracle's (iterations equal, or within
+    one with low-rank corrections; x within 1e-9) and the direct solution."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("refresh new kappa", case["name"])
+    kw = dict(case["kw"], kappa="lognormal")
+    p0 = make_problem(case["N"], s=case["s"], m=case["m"], seed=41, **kw)
+    p1 = make_problem(case["N"], s=case["s"], m=case["m"], seed=42, **kw)
+    assert np.array_equal(p0.A.indices, p1.A.indices) and np.array_equal(p0.A.indptr, p1.A.indptr)
+    opt = dict(coarse_max=48)
+    pc, k = case["pc"], case["k"]
+    ctx0 = krylov.setup(p0.A, p0.img, amg.AMGOptions(**opt), precond=pc, k=k)
+    ctx1 = refresh.refresh(ctx0, p1.A)
+    ref = krylov.solve(ctx1, p1.b, tol=TOL)
+    sv = Solver(p0.A, p0.img, tol=TOL, pc=pc, k=k, **opt)
+    sv.refresh(torch.from_numpy(p1.A.data).cuda())
+    torch.cuda.synchronize()
+    _check_levels(sv, ctx1["hier"], ctx1["sub"])
+    if k:
+        kept, ritz = sv.export_lrc()
+        for a in range(1 << p1.s):
+            r_or = np.asarray(ctx1["lrc"].ritz[a])
+            assert np.abs(ritz[a][:r_or.size] - r_or).max() <= 1e-8 * max(1.0, np.abs(r_or).max())
+            assert kept[a] == ctx1["lrc"].U[a].shape[1]
+    x = sv.solve(torch.from_numpy(p1.b).cuda()).cpu().numpy()
+    _say("its gpu", sv.last.iters, "oracle", ref.iters.max())
+    assert abs(sv.last.iters - int(ref.iters.max())) <= (1 if k else 0)
+    xr = ref.x.reshape(p1.n, -1)
+    x = x.reshape(p1.n, -1)
+    assert np.linalg.norm(x - xr) <= 1e-9 * np.linalg.norm(xr)
+    assert np.all(np.abs(x - xr).max(axis=0) <= 1e-9 * np.abs(xr).max(axis=0))
+    lu = spla.splu(p1.A.tocsc())
+    xd = np.stack([lu.solve(p1.b.reshape(p1.n, -1)[:, j]) for j in range(xr.shape[1])], axis=1)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("pc", ["amgr", "amgr_sub"])
+def test_refresh_of_a_scaled_matrix_is_its_fresh_setup(pc):
+    """2A makes the fresh setup's structural decisions again (they are scale
+    invariant): the re-setup equals the library's fresh setup of 2A."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("refresh scaled", pc)
+    p = make_problem((20, 16, 16), s=3, m=1, seed=33, jitter=0.2, kappa="lognormal")
+    opt = dict(coarse_max=48)
+    A2 = (2.0 * p.A).tocsr()
+    sv = Solver(p.A, p.img, tol=TOL, pc=pc, **opt)
+    fresh = Solver(A2, p.img, tol=TOL, pc=pc, **opt)
+    nlev = fresh.num_levels()
+    S = 8 if pc == "amgr_sub" else 0
+    sv.refresh(torch.from_numpy(A2.data).cuda())
+    torch.cuda.synchronize()
+    _same(_snapshot(sv, nlev, S), _snapshot(fresh, nlev, S), 1e-12)
+    b = torch.from_numpy(p.b).cuda()
+    x1 = sv.solve(b).cpu().numpy()
+    it1 = sv.last.iters
+    x2 = fresh.solve(b).cpu().numpy()
+    assert it1 == fresh.last.iters
+    assert np.linalg.norm(x1 - x2) <= 1e-10 * np.linalg.norm(x2)
+
+
+def test_refresh_with_fsai_matches_the_oracle():
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("refresh fsai")
+    p0 = make_problem((20, 16, 16), s=3, m=2, seed=51, kappa="lognormal")
+    p1 = make_problem((20, 16, 16), s=3, m=2, seed=52, kappa="lognormal")
+    ctx = krylov.setup(p1.A, p1.img, precond="fsai")
+    ref = krylov.solve(ctx, p1.b, tol=TOL)
+    sv = Solver(p0.A, p0.img, tol=TOL, pc="fsai")
+    sv.refresh(torch.from_numpy(p1.A.data).cuda())
+    x = sv.solve(torch.from_numpy(p1.b).cuda()).cpu().numpy()
+    _say("fsai its gpu", sv.last.iters, "oracle", ref.iters.max())
+    assert sv.last.iters == int(ref.iters.max())
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("prec,pc", [("mixed", "amgr"), ("mixed_bf16", "amgr_sub"), ("mixed", "amgr_sub")])
+def test_refresh_in_mixed_precision_reaches_tolerance(prec, pc):
+    """The single- and half-precision copies of the values follow the
+    re-setup: after it, the mixed-precision solves reach the tolerance on the
+    new matrix and agree with the FP64 oracle's re-setup solve."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("refresh mixed", prec, pc)
+    p0 = make_problem((24, 24, 24), s=3, m=2, seed=61, y_stretch=1.5, kappa="lognormal")
+    p1 = make_problem((24, 24, 24), s=3, m=2, seed=62, y_stretch=1.5, kappa="lognormal")
+    opt = dict(coarse_max=64)
+    ctx1 = refresh.refresh(krylov.setup(p0.A, p0.img, amg.AMGOptions(**opt), precond=pc), p1.A)
+    ref = krylov.solve(ctx1, p1.b, tol=1e-12)
+    sv = Solver(p0.A, p0.img, tol=1e-10, precision=prec, pc=pc, **opt)
+    sv.refresh(torch.from_numpy(p1.A.data).cuda())
+    x = sv.solve(torch.from_numpy(p1.b).cuda()).cpu().numpy()
+    rr = krylov.true_relres(p1.A, x, p1.b)
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    _say("its", sv.last.iters, "oracle", ref.iters.max(), "relres", rr, "err", err)
+    assert np.all(rr <= 1.5e-10)
+    assert err <= 1e-7
+    assert sv.last.iters <= int(ref.iters.max()) + 3
+
+
+def test_refresh_of_a_domain_of_copies_solves_the_new_matrix():
+    """AMGR in the original basis (a domain of copies): the re-setup from the
+    setup values equals the setup, and for new values the solve reaches the
+    direct solution."""
+    torch = _torch()
+    from gen import make_repeated_problem
+    from paper_2407_05930_amd import Solver
+    _say("refresh copies")
+    p0 = make_repeated_problem((12, 10, 8), 3, m=1, seed=71, walls="mixed")
+    p1 = make_repeated_problem((12, 10, 8), 3, m=1, seed=72, walls="mixed")
+    assert np.array_equal(p0.A.indices, p1.A.indices) and not np.array_equal(p0.A.data, p1.A.data)
+    sv = Solver.from_copies(p0.A, p0.sub, tol=TOL, coarse_max=48)
+    nlev = sv.num_levels()
+    before = _snapshot(sv, nlev, 0)
+    sv.refresh(torch.from_numpy(p0.A.data).cuda())
+    torch.cuda.synchronize()
+    _same(_snapshot(sv, nlev, 0), before, 1e-12)
+    sv.refresh(torch.from_numpy(p1.A.data).cuda())
+    b = p1.b.reshape(p1.A.shape[0], -1)[:, 0].copy()
+    x = sv.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    xd = spla.splu(p1.A.tocsc()).solve(b)
+    _say("copies its", sv.last.iters)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+
+
+def test_refresh_rejects_what_it_does_not_rebuild():
+    torch = _torch()
+    from paper_2407_05930_amd import MspError, Solver
+    p = make_problem((12, 10, 8), s=2, m=1, seed=81)
+    v = torch.from_numpy(p.A.data).cuda()
+    for kw in (dict(pc="amgs"), dict(pc="amgr", precision="mixed_bf16g")):
+        _say("refresh rejects", kw)
+        sv = Solver(p.A, p.img, coarse_max=32, **kw)
+        with pytest.raises(MspError) as e:
+            sv.refresh(v)
+        assert e.value.status == -8
+    with pytest.raises(ValueError):
+        Solver(p.A, p.img, coarse_max=32).refresh(v.float())
+    host = Solver(p.A, p.img, coarse_max=32, device=-1)
+    with pytest.raises(MspError):
+        host.refresh(v)
