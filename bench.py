@@ -247,6 +247,44 @@ def dominant_roofline(sv, b, steps, torch):
                                  for f, v in sorted(funcs.items(), key=lambda kv: -kv[1]["ms"])}}
 
 
+def headline_resetup(args, torch, np, p, svm, k):
+    """Numeric re-setup on the device (msp_refresh) of the headline solver for
+    a lognormal coefficient on the same mesh, against a fresh host setup of
+    that matrix: time, iterations and true residual of the solve after it."""
+    from gen import make_problem
+    from gen.problems import CONFIG_SEED0
+    from paper_2407_05930_amd import Solver
+    log("re-setup for a lognormal kappa on the same mesh")
+    pk = make_problem(p.N, s=p.s, m=int(p.b.shape[1]), seed=CONFIG_SEED0 + 7, y_stretch=1.5, kappa="lognormal")
+    assert np.array_equal(pk.A.indices, p.A.indices) and np.array_equal(pk.A.indptr, p.A.indptr)
+    vals = torch.from_numpy(pk.A.data).cuda()
+    bk = device_columns(torch, pk.b)
+    t_rs = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        svm.refresh(vals)
+        torch.cuda.synchronize()
+        t_rs.append(time.perf_counter() - t0)
+    t_solve, x = timed_solves(svm, bk, args.steps, args.warmup, torch)
+    xs = x.cpu().numpy()
+    rr = float(np.max(np.linalg.norm(pk.b - pk.A @ xs, axis=0) / np.linalg.norm(pk.b, axis=0)))
+    its = svm.last.iters
+    fresh = Solver(pk.A, pk.img, tol=1e-10, precision=args.mixed, k=k, pc=args.pc, **args.extra)
+    t_fresh, _ = timed_solves(fresh, bk, args.steps, args.warmup, torch)
+    res = {"device_resetup_first_s": round(t_rs[0], 4), "device_resetup_s": round(min(t_rs[1:]), 4),
+           "host_setup_s": round(fresh.stats.t_setup_s, 3),
+           "solve_after_resetup_s": round(t_solve, 6), "iters_after_resetup": its, "true_relres_max": rr,
+           "fresh_setup_solve_s": round(t_fresh, 6), "iters_fresh_setup": fresh.last.iters,
+           "kappa": "lognormal(0, 1) per cell, same mesh",
+           "note": "first re-setup includes building its device structure; lrc_k corrections rebuilt each time"}
+    log(f"  re-setup {res['device_resetup_s'] * 1e3:.1f} ms (first {res['device_resetup_first_s'] * 1e3:.1f} ms), "
+        f"host setup {res['host_setup_s']:.2f} s; solve {t_solve * 1e3:.2f} ms, {its} its "
+        f"(fresh setup {t_fresh * 1e3:.2f} ms, {fresh.last.iters} its)")
+    fresh.close()
+    return res
+
+
 def bench_copies(args, torch, np):
     """AMGR in the original basis on a domain made of copies (msp_setup_copies):
     8 translated copies of a 64^3 box side by side, lognormal kappa repeated in
@@ -394,6 +432,7 @@ def bench_adjoint(args, torch, np):
     """256^3, s = 3, lognormal kappa: forward solve and adjoint (dL/df,
     dL/dkappa) through torch.autograd, FP64."""
     from gen import config_problem
+    from gen.problems import CONFIG_SEED0
     from paper_2407_05930_amd.adjoint import DifferentiablePoisson
     log("building workload adjoint3d_256_s3 (geometry only)")
     pr = config_problem("adjoint3d_256_s3", assemble=False)
@@ -417,12 +456,61 @@ def bench_adjoint(args, torch, np):
         if it >= args.warmup:
             times.append(time.perf_counter() - t0)
     t = sum(times) / len(times)
+    its_host = dp.solver.last.iters
+    loss_host = float(loss.item())
+    gk_host = float(kap.grad.norm().item())
+    # Per-kappa rebuild for an optimisation step: the host path (assembly and
+    # setup of a fresh solver) against the device re-setup on the first
+    # setup's structure (device assembly, then msp_refresh).  Kappa steps are
+    # lognormal perturbations exp(0.1 z) of the base field.
+    log("per-kappa rebuild: host assembly + setup")
+    rng = np.random.default_rng(CONFIG_SEED0 + 6)
+    steps_k = [torch.from_numpy(pr.kappa_base * np.exp(0.1 * rng.standard_normal(pr.n_b))).cuda()
+               for _ in range(3)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    host_dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-10, pc=args.pc, **args.extra)
+    host_dp.solver_for(steps_k[0])
+    torch.cuda.synchronize()
+    t_host_rebuild = time.perf_counter() - t0
+    kap0 = steps_k[0].clone().requires_grad_(True)
+    p0 = host_dp(f, kap0)
+    (0.5 * ((p0 - pst) ** 2).sum()).backward()
+    its_fresh = host_dp.solver.last.iters
+    g_fresh = kap0.grad.clone()
+    host_dp.solver.close()
+    host_dp.op.close()
+    del host_dp, p0
+    log("per-kappa rebuild: device assembly + re-setup")
+    dp.resetup = "device"
+    t_dev = []
+    for kk in steps_k:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dp.solver_for(kk)
+        torch.cuda.synchronize()
+        t_dev.append(time.perf_counter() - t0)
+        log(f"  re-setup {t_dev[-1]:.3f} s")
+    # back to the first step's kappa: its gradient against the fresh setup's
+    dp.solver_for(steps_k[0])
+    kap1 = steps_k[0].clone().requires_grad_(True)
+    p1 = dp(f, kap1)
+    (0.5 * ((p1 - pst) ** 2).sum()).backward()
+    its_dev = dp.solver.last.iters
+    g_rel = float((kap1.grad - g_fresh).norm().item() / g_fresh.norm().item())
+    resetup = {"host_assembly_and_setup_s": round(t_host_rebuild, 3),
+               "device_first_s": round(t_dev[0], 3),
+               "device_s": round(sum(t_dev[1:]) / len(t_dev[1:]), 4),
+               "iters_fresh_setup": its_fresh, "iters_device_resetup": its_dev,
+               "grad_kappa_rel_diff_vs_fresh_setup": g_rel,
+               "kappa_step": "kappa_base * exp(0.1 z), z ~ N(0, 1) per base cell",
+               "note": "device_first_s includes building the position map and the re-setup's device structure"}
     return {"metric": "forward + adjoint solve time, 256^3 s=3 lognormal kappa", "value": round(t, 6), "unit": "s",
             "higher_is_better": False, "dtype": "f64",
             "config": {"workload": "adjoint3d_256_s3", "grid": list(pr.N), "s": 3, "unknowns": int(pr.n),
                        "preconditioner": args.pc},
-            "iters": dp.solver.last.iters, "setup_s": round(t_setup, 2), "loss": float(loss.item()),
-            "grad_kappa_norm": float(kap.grad.norm().item()), "grad_f_norm": float(fr.grad.norm().item())}
+            "iters": its_host, "setup_s": round(t_setup, 2), "loss": loss_host,
+            "grad_kappa_norm": gk_host, "grad_f_norm": float(fr.grad.norm().item()), "resetup": resetup}
 
 
 def main():
@@ -628,6 +716,8 @@ def main():
             "true_relres_max": {kk: max(v["true_relres"]) for kk, v in other.items()},
             "mixed_vs_headline_rel_diff": rel(other["mixed"]["x"], res["mixed"]["x"]),
         }
+    if not args.no_compare:
+        out["resetup"] = headline_resetup(args, torch, np, p, svm, k)
     if not args.no_cpu_baseline and rank == 0:
         log("cpu baseline (oracle, same workload, preconditioner and k)")
         cb = cpu_baseline(p, k, args.pc, args.extra)

@@ -395,6 +395,16 @@ int msp_fv_nnz(const msp_fv* f, int64_t* nnz);
 /* Assemble the full n x n matrix for kappa_base (host, n_b) in the ordering of
    the map: rowptr (n + 1), col and val (nnz) are caller arrays; columns sorted. */
 int msp_fv_assemble(const msp_fv* f, const double* kappa_base, int64_t* rowptr, int32_t* col, double* val);
+/* The values of msp_fv_assemble's matrix computed on the device: d_kappa_base
+   (device, n_b doubles, positive: not checked) gives d_val (device,
+   msp_fv_nnz doubles) in msp_fv_assemble's positions, with its arithmetic
+   (equal values).  With msp_refresh this rebuilds a solver for a new kappa
+   without leaving the device.  Needs an operator created with device >= 0
+   (else MSP_ERR_ARG); the first call builds the position map on the host and
+   keeps it on the device (4 bytes per nonzero, plus one double per face and
+   per base cell) until msp_fv_free; MSP_ERR_UNSUPPORTED for 2^31 or more faces
+   or base cells.  Asynchronous on hip_stream. */
+int msp_fv_assemble_device(msp_fv* f, const double* d_kappa_base, double* d_val, void* hip_stream);
 /* d_grad[i] = dL/dkappa_i for base cell i (device arrays: kappa n_b; lambda and
    p n x m column-major; grad n_b), one thread per base cell gathering over its
    own faces (no atomics), enqueued on hip_stream. */

@@ -107,6 +107,7 @@ SIGNATURES = {
     "msp_fv_create": (ctypes.c_int, [_P(msp_faces), _P(msp_symmap), ctypes.c_int32, _P(_vp)]),
     "msp_fv_nnz": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "msp_fv_assemble": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "msp_fv_assemble_device": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "msp_fv_kappa_grad": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]),
     "msp_fv_free": (None, [_vp]),
     "msp_free": (None, [_vp]),

@@ -57,6 +57,26 @@ class FVOperator:
         check(lib.msp_fv_assemble(self._h, vp(kap), vp(rp), vp(ci), vp(va)))
         return sp.csr_matrix((va, ci, rp), shape=(self.n, self.n))
 
+    def nnz(self) -> int:
+        v = ctypes.c_int64()
+        check(lib.msp_fv_nnz(self._h, ctypes.byref(v)))
+        return v.value
+
+    def assemble_device(self, kappa, out=None, stream=None):
+        """The values of ``assemble``'s matrix for kappa (torch, n_b, on the
+        device), computed on the device in its positions: a float64 tensor of
+        nnz values (``out`` if given)."""
+        import torch
+        kap = kappa.detach().to(torch.float64).contiguous()
+        if out is None:
+            out = torch.empty(self.nnz(), dtype=torch.float64, device=kap.device)
+        if out.numel() != self.nnz() or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of nnz values")
+        st = stream if stream is not None else torch.cuda.current_stream(kap.device)
+        check(lib.msp_fv_assemble_device(self._h, ctypes.c_void_p(kap.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(st.cuda_stream)))
+        return out
+
     def kappa_grad(self, kappa, lam, p, stream=None):
         """dL/dkappa (torch, n_b) from lambda and p (torch, (n,) or (n, m))."""
         import torch
@@ -83,24 +103,45 @@ class FVOperator:
 
 
 class DifferentiablePoisson:
-    """Holds the operator and a solver for the last kappa seen."""
+    """Holds the operator and a solver for the last kappa seen.
 
-    def __init__(self, faces, img, device: int = 0, **solver_opts):
+    resetup = "host": every new kappa gets a fresh solver (host assembly and
+    setup).  resetup = "device": the first kappa sets the solver up on the
+    host; for later ones the matrix is assembled on the device and the
+    solver's values are recomputed there on the first setup's structure
+    (msp_fv_assemble_device, msp_refresh), which is much faster for the small
+    kappa steps of an optimisation.  A backward for a forward whose kappa
+    has since been replaced is then an error (the solver holds the new
+    values)."""
+
+    def __init__(self, faces, img, device: int = 0, resetup: str = "host", **solver_opts):
+        if resetup not in ("host", "device"):
+            raise ValueError("resetup must be 'host' or 'device'")
         self.op = FVOperator(faces, img, device)
         self.opts = dict(solver_opts, device=device)
+        self.resetup = resetup
         self._kappa = None
+        self._vals = None
         self.solver = None
+        self.version = 0
 
     def solver_for(self, kappa):
-        """The solver for this kappa (rebuilt when kappa changes).  The
-        previous solver is not closed here: an autograd graph recorded with
-        it may still need it for its backward solve, and it is freed when the
-        last reference goes."""
-        kap = kappa.detach().cpu().numpy()
-        if self._kappa is None or not np.array_equal(kap, self._kappa):
-            A = self.op.assemble(kap)
+        """The solver for this kappa (rebuilt when kappa changes).  With host
+        re-setups the previous solver is not closed here: an autograd graph
+        recorded with it may still need it for its backward solve, and it is
+        freed when the last reference goes."""
+        import torch
+        kap = kappa.detach().to(torch.float64)
+        if self._kappa is not None and self._kappa.device == kap.device and torch.equal(kap, self._kappa):
+            return self.solver
+        if self.resetup == "device" and self.solver is not None:
+            self._vals = self.op.assemble_device(kap, out=self._vals)
+            self.solver.refresh(self._vals)
+        else:
+            A = self.op.assemble(kap.cpu().numpy())
             self.solver = Solver(A, self.op.img, **self.opts)
-            self._kappa = kap.copy()
+        self.version += 1
+        self._kappa = kap.clone()
         return self.solver
 
     def __call__(self, f, kappa):
@@ -131,12 +172,16 @@ def _torch_function():
             p = _converged_solve(sv, f.contiguous(), "forward")
             ctx.dp = dp
             ctx.sv = sv
+            ctx.version = dp.version
             ctx.save_for_backward(p, kappa)
             return p
 
         @staticmethod
         def backward(ctx, g):
             p, kappa = ctx.saved_tensors
+            if ctx.sv is ctx.dp.solver and ctx.dp.version != ctx.version:
+                raise RuntimeError("the solver of this forward was re-set up for another kappa since: run the "
+                                   "backward first, or use resetup='host'")
             lam = _converged_solve(ctx.sv, g.contiguous(), "adjoint")
             gk = ctx.dp.op.kappa_grad(kappa, lam, p) if ctx.needs_input_grad[1] else None
             return lam, gk, None

@@ -45,6 +45,7 @@ struct DevSell {
     int32_t* ci = nullptr;   // column per slot, -1 for padding
     double* v64 = nullptr;   // values per slot (vs interleaved sets)
     float* v32 = nullptr;
+    int64_t* pos = nullptr;  // CSR entry per slot, -1 for padding (built by the first re-setup)
 };
 constexpr int kSellForms = 5;   // G = 1, 2, 4, 8, 16
 
@@ -169,6 +170,10 @@ struct RefreshState {
     int nbp = 256;
     double *dense = nullptr, *rowk = nullptr, *colk = nullptr;
     double* sets = nullptr;                   // coarsest operators of every subsystem, interleaved
+    double* shared1 = nullptr;                // per-subsystem mode: shared A_1 (without the outer diagonal)
+    double* sub_a1 = nullptr;                 // and A_1,a, the FSAI factors of every subsystem, interleaved
+    std::vector<double*> sub_g;
+    bool shared_stale = false;                // shared levels below the reduction level not recomputed yet
     double* gf = nullptr;                     // pc = FSAI: FSAI of A_inn and its transpose map
     int64_t* gft_src = nullptr;
     int64_t* gf_woff = nullptr;
@@ -251,6 +256,7 @@ struct msp_ctx {
     std::vector<double> lrc_ritz;
     msp::Timers tm;
     std::unique_ptr<msp::RefreshState> rf;   // numeric re-setup structure (first msp_refresh)
+    bool host_stale = false;                 // host copy of the values older than the device's (msp::sync_host)
 
     ~msp_ctx() {
         if (on_device) {
@@ -574,19 +580,14 @@ static int env_int(const char* name) {
     return (end && *end == 0 && x >= 0 && x < (1 << 20)) ? static_cast<int>(x) : -1;
 }
 
-// Sliced-ELL form of M with rows split into G virtual rows (layout in
-// sell.hip), built from the host pattern and values and uploaded with the
-// value type the context's V-cycle uses.
-static void build_sell(msp_ctx* c, DevCsr& M, int G) {
-    DevSell& F = M.sell[log2i(G)];
-    if (F.G == G) return;
-    if (!M.hpat || !M.hval) throw Error(MSP_ERR_ARG, "no host copy of the matrix for the sliced form");
-    const Csr& P = *M.hpat;
-    const std::vector<double>& V = *M.hval;
-    const int vs = M.vs;
+// Slot layout of the sliced-ELL form of pattern P with rows split into G
+// virtual rows (layout in sell.hip): per slice of 64 virtual rows its first
+// slot and width, and per slot the CSR entry it holds (-1: padding).
+static void sell_layout(const Csr& P, int G, std::vector<int64_t>& off, std::vector<int32_t>& wid,
+                        std::vector<int64_t>& pos) {
     const int64_t nv = P.nr * G, ns = (nv + 63) / 64;
-    std::vector<int64_t> off(static_cast<size_t>(ns) + 1, 0);
-    std::vector<int32_t> wid(static_cast<size_t>(ns), 0);
+    off.assign(static_cast<size_t>(ns) + 1, 0);
+    wid.assign(static_cast<size_t>(ns), 0);
     for (int64_t v = 0; v < nv; ++v) {
         const int64_t r = v / G, g = v % G;
         const int64_t len = P.rp[r + 1] - P.rp[r];
@@ -594,16 +595,39 @@ static void build_sell(msp_ctx* c, DevCsr& M, int G) {
         wid[v / 64] = std::max(wid[v / 64], static_cast<int32_t>(cnt));
     }
     for (int64_t q = 0; q < ns; ++q) off[q + 1] = off[q] + 64 * static_cast<int64_t>(wid[q]);
-    const int64_t slots = off[ns];
-    std::vector<int32_t> ci(static_cast<size_t>(slots), -1);
-    std::vector<double> val(static_cast<size_t>(slots) * vs, 0.0);
+    pos.assign(static_cast<size_t>(off[ns]), -1);
     for (int64_t r = 0; r < P.nr; ++r)
         for (int64_t j = 0; j < P.rp[r + 1] - P.rp[r]; ++j) {
             const int64_t v = r * G + j % G, k = j / G;
-            const int64_t q = off[v / 64] + 64 * k + v % 64;
-            ci[q] = P.ci[P.rp[r] + j];
-            for (int a = 0; a < vs; ++a) val[q * vs + a] = V[(P.rp[r] + j) * vs + a];
+            pos[off[v / 64] + 64 * k + v % 64] = P.rp[r] + j;
         }
+}
+
+void sync_host(msp_ctx* c);   // host copy of the values after a device re-setup (below)
+
+// Sliced-ELL form of M with rows split into G virtual rows, built from the
+// host pattern and values and uploaded with the value type the context's
+// V-cycle uses.
+static void build_sell(msp_ctx* c, DevCsr& M, int G) {
+    DevSell& F = M.sell[log2i(G)];
+    if (F.G == G) return;
+    if (!M.hpat || !M.hval) throw Error(MSP_ERR_ARG, "no host copy of the matrix for the sliced form");
+    sync_host(c);
+    const Csr& P = *M.hpat;
+    const std::vector<double>& V = *M.hval;
+    const int vs = M.vs;
+    std::vector<int64_t> off, pos;
+    std::vector<int32_t> wid;
+    sell_layout(P, G, off, wid, pos);
+    const int64_t ns = static_cast<int64_t>(wid.size()), slots = off[ns];
+    std::vector<int32_t> ci(static_cast<size_t>(slots), -1);
+    std::vector<double> val(static_cast<size_t>(slots) * vs, 0.0);
+    for (int64_t q = 0; q < slots; ++q) {
+        const int64_t p = pos[q];
+        if (p < 0) continue;
+        ci[q] = P.ci[p];
+        for (int a = 0; a < vs; ++a) val[q * vs + a] = V[p * vs + a];
+    }
     F.off = c->upload(off.data(), ns + 1);
     F.wid = c->upload(wid.data(), ns);
     F.ci = c->upload(ci.data(), slots);
@@ -617,9 +641,24 @@ static void build_sell(msp_ctx* c, DevCsr& M, int G) {
     F.G = G;
 }
 
+// New values of every sliced form of M from its device CSR values (FP64).
+static void refresh_sells(msp_ctx* c, DevCsr& M, hipStream_t st) {
+    for (int q = 0; q < kSellForms; ++q) {
+        DevSell& F = M.sell[q];
+        if (!F.G) continue;
+        if (!F.pos) {
+            std::vector<int64_t> off, pos;
+            std::vector<int32_t> wid;
+            sell_layout(*M.hpat, F.G, off, wid, pos);
+            F.pos = c->upload(pos.data(), static_cast<int64_t>(pos.size()));
+        }
+        HIPCHECK(launch_sell_values(st, F.slots, M.vs, F.pos, M.v64, M.f32 ? nullptr : F.v64, M.f32 ? F.v32 : nullptr));
+    }
+}
+
 static void free_sell(msp_ctx* c, DevSell& F) {
     for (void* q : {static_cast<void*>(F.off), static_cast<void*>(F.wid), static_cast<void*>(F.ci),
-                    static_cast<void*>(F.v64), static_cast<void*>(F.v32)})
+                    static_cast<void*>(F.v64), static_cast<void*>(F.v32), static_cast<void*>(F.pos)})
         if (q) c->dfree(q);
     F = DevSell();
 }
@@ -1768,6 +1807,7 @@ void build_schur_lrc(msp_ctx* c);
 void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st);   // numeric re-setup (below)
 void fv_kappa_grad(msp_fv* f, const double* d_kap, int m, const double* d_lam, const double* d_p, double* d_grad,
                    hipStream_t st);   // fv.cpp
+void fv_assemble_device(msp_fv* f, const double* d_kap, double* d_val, hipStream_t st);   // fv.cpp
 
 }  // namespace msp
 
@@ -2201,10 +2241,20 @@ static void copy_csr(const msp::Csr& M, int64_t* rp, int32_t* ci, double* v) {
     if (v) std::copy(M.v.begin(), M.v.end(), v);
 }
 
+// The host copy of the values is a cache of the device's after a re-setup:
+// exports fetch it first (blocking).
+static int synced(const msp_ctx* c) {
+    return guarded([&]() -> int {
+        msp::sync_host(const_cast<msp_ctx*>(c));
+        return MSP_OK;
+    });
+}
+
 int msp_export_level(const msp_ctx* c, int32_t lev, int8_t* cf, int64_t* A_rp, int32_t* A_ci, double* A_v,
                      int64_t* P_rp, int32_t* P_ci, double* P_v, int64_t* G_rp, int32_t* G_ci, double* G_v,
                      double* omega) {
     if (!c || lev < 0 || lev >= static_cast<int32_t>(c->hier.lev.size())) return MSP_ERR_ARG;
+    if (const int rc = synced(c)) return rc;
     const auto& L = c->hier.lev[lev];
     if (cf) std::copy(L.cf.begin(), L.cf.end(), cf);
     copy_csr(L.A, A_rp, A_ci, A_v);
@@ -2218,6 +2268,7 @@ int msp_export_sub_level(const msp_ctx* c, int32_t lev, int32_t a, double* A_v, 
                          double* omega) {
     if (!c || !c->sub || lev < 1 || lev >= static_cast<int32_t>(c->hier.lev.size()) || a < 0 || a >= c->subv.S)
         return MSP_ERR_ARG;
+    if (const int rc = synced(c)) return rc;
     const int S = c->subv.S;
     auto take = [&](const std::vector<double>& v, double* out) {
         if (!out) return;
@@ -2256,6 +2307,7 @@ int msp_export_amgs(const msp_ctx* c, int32_t which, int64_t* nrows, int64_t* nc
 
 int msp_export_outer(const msp_ctx* c, double* sigma, int8_t* iface) {
     if (!c) return MSP_ERR_ARG;
+    if (const int rc = synced(c)) return rc;
     if (sigma) std::copy(c->sym.sigma.begin(), c->sym.sigma.end(), sigma);
     if (iface) std::copy(c->sym.iface.begin(), c->sym.iface.end(), iface);
     return MSP_OK;
@@ -2355,6 +2407,14 @@ int msp_fv_assemble(const msp_fv* f, const double* kappa_base, int64_t* rowptr, 
     return guarded([&]() -> int {
         if (!f) throw Error(MSP_ERR_ARG, "null operator");
         msp::fv_assemble(f, kappa_base, rowptr, col, val);
+        return MSP_OK;
+    });
+}
+
+int msp_fv_assemble_device(msp_fv* f, const double* d_kappa_base, double* d_val, void* hip_stream) {
+    return guarded([&]() -> int {
+        if (!f) throw Error(MSP_ERR_ARG, "null operator");
+        msp::fv_assemble_device(f, d_kappa_base, d_val, static_cast<hipStream_t>(hip_stream));
         return MSP_OK;
     });
 }
@@ -2733,6 +2793,12 @@ static void refresh_build(msp_ctx* c) {
         R->dense = c->dalloc<double>(static_cast<int64_t>(Sd) * nL * nL);
         R->rowk = c->dalloc<double>(static_cast<int64_t>(Sd) * nL);
         R->colk = c->dalloc<double>(static_cast<int64_t>(Sd) * nL);
+        if (c->sub) {
+            R->shared1 = c->dalloc<double>(c->hier.lev[1].A.nnz());
+            R->sub_g.assign(L, nullptr);
+            for (size_t l = 1; l + 1 < L; ++l) R->sub_g[l] = c->dalloc<double>(c->hier.lev[l].G.nnz() * S);
+            if (L > 2) R->sub_a1 = c->dalloc<double>(c->hier.lev[1].A.nnz() * S);
+        }
         if (c->sub && L > 2) {
             R->sets = c->dalloc<double>(c->hier.lev.back().A.nnz() * S);
             // interface coarse points: their A_1 diagonal entries and base cells
@@ -2810,9 +2876,9 @@ static void refresh_smoother(RefreshState& R, RfLevel& F, hipStream_t st) {
     // omega = 4 / (3 lambda), lambda from 20 power iterations on G A G^T
     HIPCHECK(hipMemcpyAsync(R.t3, F.v0, sizeof(double) * F.n, hipMemcpyDeviceToDevice, st));
     for (int it = 0; it < 20; ++it) {
-        HIPCHECK(launch_spmv(st, F.n, F.GT.rp, F.GT.ci, F.gt, R.t3, R.t1));
-        HIPCHECK(launch_spmv(st, F.n, F.A.rp, F.A.ci, F.a, R.t1, R.t2));
-        HIPCHECK(launch_spmv(st, F.n, F.G.rp, F.G.ci, F.g, R.t2, R.t1));
+        HIPCHECK(launch_spmv(st, F.n, F.GT.rp, F.GT.ci, F.gt, R.t3, R.t1, F.GT.nnz));
+        HIPCHECK(launch_spmv(st, F.n, F.A.rp, F.A.ci, F.a, R.t1, R.t2, F.A.nnz));
+        HIPCHECK(launch_spmv(st, F.n, F.G.rp, F.G.ci, F.g, R.t2, R.t1, F.G.nnz));
         HIPCHECK(launch_power_dots(st, F.n, R.t3, R.t1, R.part, R.nbp, R.dots));
         HIPCHECK(launch_normalise(st, F.n, R.t1, R.dots, R.t3));
     }
@@ -2820,7 +2886,7 @@ static void refresh_smoother(RefreshState& R, RfLevel& F, hipStream_t st) {
     HIPCHECK(hipMemcpyAsync(dots, R.dots, sizeof(dots), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     F.omega = 4.0 / (3.0 * dots[0]);
-    HIPCHECK(launch_spgemm_masked(st, F.n, F.GT.rp, F.GT.ci, F.gt, F.G.rp, F.G.ci, F.g, F.M.rp, F.M.ci, F.m, R.err));
+    HIPCHECK(launch_spgemm_masked(st, F.n, F.M.nnz, F.GT.rp, F.GT.ci, F.gt, F.G.rp, F.G.ci, F.g, F.M.rp, F.M.ci, F.m));
     HIPCHECK(launch_scale(st, F.M.nnz, F.m, F.omega));
 }
 
@@ -2835,14 +2901,21 @@ static void refresh_transfer(RefreshState& R, RfLevel& F, double* next, const Rf
     }
     HIPCHECK(launch_interp_finish(st, F.n, F.cf, F.A.rp, F.A.ci, F.a, F.w.back(), F.P.rp, F.pmap, F.p));
     HIPCHECK(launch_gather(st, F.R.nnz, F.r_src, F.p, F.r));
-    HIPCHECK(launch_spgemm_masked(st, F.n, F.A.rp, F.A.ci, F.a, F.P.rp, F.P.ci, F.p, F.AP.rp, F.AP.ci, F.ap, R.err));
-    HIPCHECK(launch_spgemm_masked(st, nextpat.nr, F.R.rp, F.R.ci, F.r, F.AP.rp, F.AP.ci, F.ap, nextpat.rp,
-                                  nextpat.ci, next, R.err));
+    HIPCHECK(launch_spgemm_masked(st, F.n, F.AP.nnz, F.A.rp, F.A.ci, F.a, F.P.rp, F.P.ci, F.p, F.AP.rp, F.AP.ci, F.ap));
+    HIPCHECK(launch_spgemm_masked(st, nextpat.nr, nextpat.nnz, F.R.rp, F.R.ci, F.r, F.AP.rp, F.AP.ci, F.ap,
+                                  nextpat.rp, nextpat.ci, next));
 }
 
 // FP32 copy of a device matrix's values (mixed modes)
 static void refresh_f32(hipStream_t st, DevCsr& D) {
     if (D.v32) HIPCHECK((launch_cast<float, double>(st, D.nnz * D.vs, D.v64, D.v32)));
+}
+
+// One shared level's values (smoother, transfers, the next level's operator).
+static void refresh_shared_level(RefreshState& R, size_t l, hipStream_t st) {
+    RfLevel& F = R.lev[l];
+    refresh_smoother(R, F, st);
+    refresh_transfer(R, F, R.lev[l + 1].a, R.lev[l + 1].A, st);
 }
 
 void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
@@ -2864,27 +2937,13 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
         const size_t L = R.lev.size();
         HIPCHECK(hipMemcpyAsync(R.lev[0].a, c->dAinn.v64, sizeof(double) * c->dAinn.nnz, hipMemcpyDeviceToDevice,
                                 st));
-        // shared levels (with per-subsystem values below the reduction level the
-        // device applies only level 0 of them; the rest is mirrored on the host)
-        for (size_t l = 0; l + 1 < L; ++l) {
+        // shared levels: all of them for the shared cycle, the reduction level for
+        // the per-subsystem one (its shared levels below are recomputed only when
+        // the host copy is asked for)
+        const size_t shared_to = c->sub ? 1 : L - 1;
+        for (size_t l = 0; l < shared_to; ++l) {
             RfLevel& F = R.lev[l];
-            refresh_smoother(R, F, st);
-            refresh_transfer(R, F, R.lev[l + 1].a, R.lev[l + 1].A, st);
-            if (c->sub && l > 0) {
-                HostLevel& H = c->hier.lev[l];
-                auto mirror = [&](std::vector<double>& h, const double* d) {
-                    HIPCHECK(hipMemcpyAsync(h.data(), d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-                };
-                mirror(H.A.v, F.a);
-                mirror(H.G.v, F.g);
-                mirror(H.GT.v, F.gt);
-                mirror(H.M.v, F.m);
-                mirror(H.P.v, F.p);
-                mirror(H.R.v, F.r);
-                HIPCHECK(hipStreamSynchronize(st));
-                H.omega = F.omega;
-                continue;
-            }
+            refresh_shared_level(R, l, st);
             DevLevel& D = c->dl[l];
             D.omega = F.omega;
             auto put = [&](DevCsr& M, const double* v) {
@@ -2896,11 +2955,6 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
             put(D.R, F.r);
         }
         const int64_t nL = c->hier.lev.back().A.nr;
-        if (c->sub) {   // host mirror of the shared coarsest matrix
-            std::vector<double>& h = c->hier.lev[L - 1].A.v;
-            HIPCHECK(hipMemcpyAsync(h.data(), R.lev[L - 1].a, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-            HIPCHECK(hipStreamSynchronize(st));
-        }
         if (!c->sub) {
             RfLevel& FL = R.lev[L - 1];
             HIPCHECK(launch_dense_inverse(st, nL, 1, FL.A.rp, FL.A.ci, FL.a, R.dense, R.rowk, R.colk));
@@ -2912,27 +2966,16 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
                                         hipMemcpyDeviceToDevice, st));
             if (R.ndsig1)
                 HIPCHECK(launch_gather(st, R.ndsig1, R.dsig1_src, R.sigma, const_cast<double*>(c->dsig1.d.val)));
-            double* shared1 = c->dalloc<double>(R.lev[1].A.nnz);
-            HIPCHECK(hipMemcpyAsync(shared1, R.lev[1].a, sizeof(double) * R.lev[1].A.nnz, hipMemcpyDeviceToDevice, st));
+            const int64_t n1 = R.lev[1].A.nnz;
+            HIPCHECK(hipMemcpyAsync(R.shared1, R.lev[1].a, sizeof(double) * n1, hipMemcpyDeviceToDevice, st));
             for (int a = 0; a < S; ++a) {
-                HIPCHECK(hipMemcpyAsync(R.lev[1].a, shared1, sizeof(double) * R.lev[1].A.nnz, hipMemcpyDeviceToDevice,
-                                        st));
+                HIPCHECK(hipMemcpyAsync(R.lev[1].a, R.shared1, sizeof(double) * n1, hipMemcpyDeviceToDevice, st));
                 if (R.ns1) HIPCHECK(launch_add_sigma(st, R.ns1, R.s1_diag, R.s1_base, R.sigma, S, a, R.lev[1].a));
-                if (L > 2) {   // host mirror of A_1,a (the device applies A_1 and the outer diagonal)
-                    std::vector<double> h(R.lev[1].A.nnz);
-                    HIPCHECK(hipMemcpyAsync(h.data(), R.lev[1].a, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-                    HIPCHECK(hipStreamSynchronize(st));
-                    for (size_t k = 0; k < h.size(); ++k) c->subv.A[1][k * S + a] = h[k];
-                }
+                if (L > 2) HIPCHECK(launch_strided_copy(st, n1, R.lev[1].a, 1, 0, R.sub_a1, S, a));
                 for (size_t l = 1; l + 1 < L; ++l) {
                     RfLevel& F = R.lev[l];
                     refresh_smoother(R, F, st);
-                    {   // host mirror of the subsystem's FSAI factor
-                        std::vector<double> h(F.G.nnz);
-                        HIPCHECK(hipMemcpyAsync(h.data(), F.g, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-                        HIPCHECK(hipStreamSynchronize(st));
-                        for (size_t k = 0; k < h.size(); ++k) c->subv.G[l][k * S + a] = h[k];
-                    }
+                    HIPCHECK(launch_strided_copy(st, F.G.nnz, F.g, 1, 0, R.sub_g[l], S, a));
                     refresh_transfer(R, F, R.lev[l + 1].a, R.lev[l + 1].A, st);
                     DevLevel& D = c->dl[l];
                     c->subv.omega[l][a] = F.omega;
@@ -2945,8 +2988,6 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
                 }
                 HIPCHECK(launch_strided_copy(st, R.lev[L - 1].A.nnz, R.lev[L - 1].a, 1, 0, R.sets, S, a));
             }
-            HIPCHECK(hipStreamSynchronize(st));
-            c->dfree(shared1);
             const RfLevel& FL = R.lev[L - 1];
             HIPCHECK(launch_dense_inverse(st, nL, S, FL.A.rp, FL.A.ci, R.sets, R.dense, R.rowk, R.colk));
             if (c->d_cinv32) {
@@ -2956,78 +2997,25 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
                 HIPCHECK(hipMemcpyAsync(c->d_cinv, R.dense, sizeof(double) * S * nL * nL, hipMemcpyDeviceToDevice, st));
             }
         }
-        // FP32 copies of the level matrices (mixed modes)
-        for (DevLevel& D : c->dl) {
-            refresh_f32(st, D.A);
-            refresh_f32(st, D.P);
-            refresh_f32(st, D.R);
-            refresh_f32(st, D.M);
-        }
+        // FP32 copies of the level matrices (mixed modes) and the sliced forms in use
+        for (DevLevel& D : c->dl)
+            for (DevCsr* M : {&D.A, &D.P, &D.R, &D.M}) {
+                refresh_f32(st, *M);
+                refresh_sells(c, *M, st);
+            }
     } else if (c->o.pc == MSP_PC_FSAI) {
         HIPCHECK(launch_fsai(st, nb, c->dAinn.rp, c->dAinn.ci, c->dAinn.v64, R.gfp.rp, R.gfp.ci, c->dGf.v64, R.gf_woff,
                              R.work, R.err));
         HIPCHECK(launch_gather(st, R.gftp.nnz, R.gft_src, c->dGf.v64, c->dGfT.v64));
     }
+    refresh_sells(c, c->dAinn, st);
     int err = 0;
     HIPCHECK(hipMemcpyAsync(&err, R.err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
+    c->host_stale = true;   // the host copy is fetched when something reads it (sync_host)
+    R.shared_stale = c->sub;
     if (err & 2) throw Error(MSP_ERR_NOT_SPD, "re-setup: an FSAI block of the new matrix is not positive definite");
-    if (err) throw Error(MSP_ERR_ARG, "re-setup: a product left its kept pattern");
-
-    // host mirror of every value (exports, sliced forms and the autotuner read it)
-    auto down = [&](std::vector<double>& h, const double* d, int64_t count) {
-        h.resize(count);
-        HIPCHECK(hipMemcpy(h.data(), d, sizeof(double) * count, hipMemcpyDeviceToHost));
-    };
-    down(c->sym.Ainn.v, c->dAinn.v64, c->dAinn.nnz);
-    down(c->sym.sigma, R.sigma, nb * S);
-    if (cycle(c)) {
-        const size_t L = R.lev.size();
-        for (size_t l = 0; l < L; ++l) {
-            HostLevel& H = c->hier.lev[l];
-            RfLevel& F = R.lev[l];
-            const bool shared = !c->sub || l == 0;   // per-subsystem mode mirrored levels >= 1 above
-            if (shared) down(H.A.v, F.a, H.A.nnz());
-            if (l + 1 == L) break;
-            if (!shared) continue;
-            down(H.G.v, F.g, H.G.nnz());
-            down(H.GT.v, F.gt, H.GT.nnz());
-            down(H.M.v, F.m, H.M.nnz());
-            down(H.P.v, F.p, H.P.nnz());
-            down(H.R.v, F.r, H.R.nnz());
-            H.omega = F.omega;
-        }
-        if (c->sub) {
-            for (size_t l = 1; l + 1 < L; ++l) {
-                const DevLevel& D = c->dl[l];
-                down(c->subv.P[l], D.P.v64, D.P.nnz * S);
-                down(c->subv.R[l], D.R.v64, D.R.nnz * S);
-                down(c->subv.M[l], D.M.v64, D.M.nnz * S);
-                if (l >= 2) down(c->subv.A[l], D.A.v64, D.A.nnz * S);
-            }
-            down(c->subv.A[L - 1], R.sets, c->hier.lev.back().A.nnz() * S);
-            down(c->subv.coarse_inv, R.dense, static_cast<int64_t>(S) * c->nL * c->nL);
-        } else {
-            down(c->hier.coarse_inv, R.dense, c->nL * c->nL);
-        }
-        // sliced forms carry copies of the values: rebuild the ones in use
-        for (DevLevel& D : c->dl)
-            for (DevCsr* M : {&D.A, &D.P, &D.R, &D.M})
-                for (int q = 0; q < kSellForms; ++q)
-                    if (M->sell[q].G) {
-                        const int G = M->sell[q].G;
-                        free_sell(c, M->sell[q]);
-                        build_sell(c, *M, G);
-                    }
-    } else if (c->o.pc == MSP_PC_FSAI) {
-        down(c->Gf.v, c->dGf.v64, c->dGf.nnz);
-    }
-    for (int q = 0; q < kSellForms; ++q)
-        if (c->dAinn.sell[q].G) {
-            const int G = c->dAinn.sell[q].G;
-            free_sell(c, c->dAinn.sell[q]);
-            build_sell(c, c->dAinn, G);
-        }
+    if (err) throw Error(MSP_ERR_ARG, "re-setup: an interpolation weight left its kept pattern");
     // low-rank corrections of the new operators
     if (c->lrc_k > 0) {
         for (void* q : {c->d_U, static_cast<void*>(c->d_lrc_coef), static_cast<void*>(c->d_lrc_part),
@@ -3038,6 +3026,68 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
         build_lrc(c);
     }
     HIPCHECK(hipDeviceSynchronize());
+}
+
+// Host copy of every value after a device re-setup (exports, and sliced forms
+// the autotuner builds later, read it).  With per-subsystem values the shared
+// levels below the reduction level are recomputed here first: the solve does
+// not use them.
+void sync_host(msp_ctx* c) {
+    if (!c->host_stale || !c->rf) return;
+    RefreshState& R = *c->rf;
+    HIPCHECK(hipSetDevice(c->device));
+    hipStream_t st = nullptr;
+    const int S = 1 << c->sym.s;
+    const int64_t nb = c->sym.n_b;
+    auto down = [&](std::vector<double>& h, const double* d, int64_t count) {
+        h.resize(count);
+        HIPCHECK(hipMemcpy(h.data(), d, sizeof(double) * count, hipMemcpyDeviceToHost));
+    };
+    down(c->sym.Ainn.v, c->dAinn.v64, c->dAinn.nnz);
+    down(c->sym.sigma, R.sigma, nb * S);
+    if (cycle(c)) {
+        const size_t L = R.lev.size();
+        if (c->sub) {
+            // per-subsystem values first: the shared recomputation below reuses the level buffers
+            for (size_t l = 1; l + 1 < L; ++l) {
+                const DevLevel& D = c->dl[l];
+                down(c->subv.P[l], D.P.v64, D.P.nnz * S);
+                down(c->subv.R[l], D.R.v64, D.R.nnz * S);
+                down(c->subv.M[l], D.M.v64, D.M.nnz * S);
+                down(c->subv.G[l], R.sub_g[l], R.lev[l].G.nnz * S);
+                if (l >= 2) down(c->subv.A[l], D.A.v64, D.A.nnz * S);
+            }
+            if (L > 2) down(c->subv.A[1], R.sub_a1, R.lev[1].A.nnz * S);
+            down(c->subv.A[L - 1], R.sets, c->hier.lev.back().A.nnz() * S);
+            down(c->subv.coarse_inv, R.dense, static_cast<int64_t>(S) * c->nL * c->nL);
+            if (R.shared_stale) {
+                HIPCHECK(hipMemcpy(R.lev[1].a, R.shared1, sizeof(double) * R.lev[1].A.nnz, hipMemcpyDeviceToDevice));
+                for (size_t l = 1; l + 1 < L; ++l) {
+                    refresh_shared_level(R, l, st);
+                    c->hier.lev[l].omega = R.lev[l].omega;
+                }
+                HIPCHECK(hipStreamSynchronize(st));
+                R.shared_stale = false;
+            }
+        } else {
+            down(c->hier.coarse_inv, R.dense, c->nL * c->nL);
+        }
+        for (size_t l = 0; l < L; ++l) {
+            HostLevel& H = c->hier.lev[l];
+            const RfLevel& F = R.lev[l];
+            down(H.A.v, F.a, H.A.nnz());
+            if (l + 1 == L) break;
+            down(H.G.v, F.g, H.G.nnz());
+            down(H.GT.v, F.gt, H.GT.nnz());
+            down(H.M.v, F.m, H.M.nnz());
+            down(H.P.v, F.p, H.P.nnz());
+            down(H.R.v, F.r, H.R.nnz());
+            H.omega = F.omega;
+        }
+    } else if (c->o.pc == MSP_PC_FSAI) {
+        down(c->Gf.v, c->dGf.v64, c->dGf.nnz);
+    }
+    c->host_stale = false;
 }
 
 }  // namespace msp

@@ -10,6 +10,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "refresh.hpp"
 
 #define FVCHECK(expr)                                                                             \
     do {                                                                                          \
@@ -34,6 +35,12 @@ struct msp_fv {
     int32_t* d_cfi = nullptr;
     int8_t *d_kind = nullptr, *d_axis = nullptr;
     double *d_area = nullptr, *d_da = nullptr, *d_db = nullptr;
+    // device assembly: per position of the assembled matrix, the face whose -T
+    // it holds (>= 0) or the base cell whose diagonal it holds (-(i+1)); T per
+    // face and the diagonal per base cell as work arrays
+    int32_t* d_slot = nullptr;
+    int64_t nnz = 0;
+    double *d_T = nullptr, *d_diag = nullptr;
     ~msp_fv() {
         if (device >= 0) {
             (void)hipSetDevice(device);
@@ -179,6 +186,59 @@ void fv_assemble(const msp_fv* f, const double* kap, int64_t* rp, int32_t* ci, d
             }
         }
     std::copy(cnt.begin(), cnt.end(), rp);
+}
+
+// The positions of the host assembly, built once: each row of image a of base
+// cell i holds the diagonal and one entry per interior or mirror face of i,
+// sorted by column.
+static void fv_build_slots(msp_fv* f) {
+    if (f->nf >= (int64_t(1) << 31) || f->n_b >= (int64_t(1) << 31))
+        throw Error(MSP_ERR_UNSUPPORTED, "device assembly needs fewer than 2^31 faces and base cells");
+    const int S = f->S;
+    std::vector<int64_t> cnt(f->n + 1, 0);
+    for (int64_t i = 0; i < f->n_b; ++i) {
+        int64_t deg = 1;
+        for (int64_t e = f->cfp[i]; e < f->cfp[i + 1]; ++e) deg += f->kind[f->cfi[e]] != 1;
+        for (int a = 0; a < S; ++a) cnt[f->img[i * S + a] + 1] = deg;
+    }
+    for (int64_t g = 0; g < f->n; ++g) cnt[g + 1] += cnt[g];
+    std::vector<int32_t> slot(cnt[f->n]);
+    std::vector<std::pair<int32_t, int32_t>> row;
+    for (int64_t i = 0; i < f->n_b; ++i)
+        for (int a = 0; a < S; ++a) {
+            const int64_t g = f->img[i * S + a];
+            row.clear();
+            row.emplace_back(static_cast<int32_t>(g), static_cast<int32_t>(-(i + 1)));
+            for (int64_t e = f->cfp[i]; e < f->cfp[i + 1]; ++e) {
+                const int64_t q = f->cfi[e];
+                if (f->kind[q] == 0) {
+                    const int64_t o = f->ca[q] == i ? f->cb[q] : f->ca[q];
+                    row.emplace_back(static_cast<int32_t>(f->img[o * S + a]), static_cast<int32_t>(q));
+                } else if (f->kind[q] == 2) {
+                    row.emplace_back(static_cast<int32_t>(f->img[i * S + (a ^ (1 << f->axis[q]))]),
+                                     static_cast<int32_t>(q));
+                }
+            }
+            std::sort(row.begin(), row.end(),
+                      [](const std::pair<int32_t, int32_t>& x, const std::pair<int32_t, int32_t>& y) {
+                          return x.first < y.first;
+                      });
+            int64_t p = cnt[g];
+            for (auto& pr : row) slot[p++] = pr.second;
+        }
+    f->nnz = cnt[f->n];
+    f->d_slot = f->up(slot);
+    f->d_T = f->up(std::vector<double>(std::max<int64_t>(1, f->nf)));
+    f->d_diag = f->up(std::vector<double>(f->n_b));
+}
+
+void fv_assemble_device(msp_fv* f, const double* d_kap, double* d_val, hipStream_t st) {
+    if (f->device < 0) throw Error(MSP_ERR_ARG, "operator was created without a device");
+    if (!d_kap || !d_val) throw Error(MSP_ERR_ARG, "null array");
+    FVCHECK(hipSetDevice(f->device));
+    if (!f->d_slot) fv_build_slots(f);
+    FVCHECK(launch_fv_values(st, f->nf, f->n_b, f->nnz, f->d_ca, f->d_cb, f->d_kind, f->d_area, f->d_da, f->d_db,
+                             f->d_cfp, f->d_cfi, f->d_slot, d_kap, f->d_T, f->d_diag, d_val));
 }
 
 void fv_free(msp_fv* f) { delete f; }

@@ -220,30 +220,65 @@ __global__ __launch_bounds__(kRB) void k_fsai(int64_t n, const int32_t* __restri
 
 // C = A B on C's known pattern (Gustavson order: increasing k of A's row,
 // then B's row); alpha scales the result.
-__global__ __launch_bounds__(kRB) void k_spgemm_masked(int64_t nr, const int32_t* __restrict__ arp,
+// C = A B on C's kept pattern, one thread per nonzero of C: entry (i, c) sums
+// a_ik b_kc over the row of A in its order (the order in which a row-wise
+// product accumulates it), b_kc found by binary search in row k of B.  The
+// kept pattern is the symbolic product of the kept patterns, so every
+// product term has its slot.
+__global__ __launch_bounds__(kRB) void k_spgemm_masked(int64_t nr, int64_t nnz, const int32_t* __restrict__ arp,
                                                        const int32_t* __restrict__ aci,
                                                        const double* __restrict__ av,
                                                        const int32_t* __restrict__ brp,
                                                        const int32_t* __restrict__ bci,
                                                        const double* __restrict__ bv,
                                                        const int32_t* __restrict__ crp,
-                                                       const int32_t* __restrict__ cci, double* __restrict__ cv,
-                                                       int* __restrict__ err) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x;
-    if (i >= nr) return;
-    const int64_t cb = crp[i], ce = crp[i + 1];
-    for (int64_t p = cb; p < ce; ++p) cv[p] = 0.0;
-    for (int64_t k = arp[i]; k < arp[i + 1]; ++k) {
-        const int32_t j = aci[k];
-        const double a = av[k];
-        for (int64_t q = brp[j]; q < brp[j + 1]; ++q) {
-            const int64_t p = find_col(cci, cb, ce, bci[q]);
-            if (p < 0) {
-                atomicOr(err, 4);
-                continue;
-            }
-            cv[p] += a * bv[q];
+                                                       const int32_t* __restrict__ cci, double* __restrict__ cv) {
+    for (int64_t p = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; p < nnz;
+         p += static_cast<int64_t>(gridDim.x) * kRB) {
+        int64_t lo = 0, hi = nr;   // the row i with crp[i] <= p < crp[i + 1]
+        while (hi - lo > 1) {
+            const int64_t m = (lo + hi) >> 1;
+            if (crp[m] <= p) lo = m;
+            else hi = m;
         }
+        const int32_t c = cci[p];
+        double s = 0.0;
+        for (int64_t k = arp[lo]; k < arp[lo + 1]; ++k) {
+            const int32_t j = aci[k];
+            const int64_t q = find_col(bci, brp[j], brp[j + 1], c);
+            if (q >= 0) s += av[k] * bv[q];
+        }
+        cv[p] = s;
+    }
+}
+
+// one wavefront per row (rows with many entries); lanes stride over the row,
+// then a butterfly sum
+__global__ __launch_bounds__(kRB) void k_spmv_wave(int64_t n, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                   const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * (kRB / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;   // the whole wavefront leaves together
+    double s = 0.0;
+    for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += 64) s += v[k] * x[ci[k]];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) y[i] = s;
+}
+
+// values of a sliced-ELL form from its CSR values: slot q of set a holds entry
+// pos[q] of set a (pos < 0: padding, zero)
+__global__ __launch_bounds__(kRB) void k_sell_values(int64_t slots, int vs, const int64_t* __restrict__ pos,
+                                                     const double* __restrict__ v, double* __restrict__ out64,
+                                                     float* __restrict__ out32) {
+    const int64_t total = slots * vs;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; t < total;
+         t += static_cast<int64_t>(gridDim.x) * kRB) {
+        const int64_t q = t / vs, a = t - q * vs;
+        const int64_t p = pos[q];
+        const double x = p >= 0 ? v[p * vs + a] : 0.0;
+        if (out32) out32[t] = static_cast<float>(x);
+        else out64[t] = x;
     }
 }
 
@@ -345,6 +380,45 @@ __global__ __launch_bounds__(kRB) void k_gj_update(int64_t n, int S, int64_t k, 
     else x = (j == k) ? -(ci / p) : x - ci * (rj / p);
 }
 
+// Two-point-flux transmissibility of face q (interior: harmonic mean of the
+// two half-cell conductances; Dirichlet wall; mirror plane at half the
+// distance), the host assembly's arithmetic.
+__global__ __launch_bounds__(kRB) void k_fv_face_T(int64_t nf, const int64_t* __restrict__ ca,
+                                                   const int64_t* __restrict__ cb, const int8_t* __restrict__ kind,
+                                                   const double* __restrict__ area, const double* __restrict__ da,
+                                                   const double* __restrict__ db, const double* __restrict__ kap,
+                                                   double* __restrict__ T) {
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; q < nf;
+         q += static_cast<int64_t>(gridDim.x) * kRB) {
+        const double ka = kap[ca[q]];
+        const int K = kind[q];
+        T[q] = K == 0 ? area[q] / (da[q] / ka + db[q] / kap[cb[q]])
+                      : (K == 1 ? area[q] * ka / da[q] : area[q] * ka / (2.0 * da[q]));
+    }
+}
+
+// diagonal of base cell i: the sum of its faces' T in incidence order
+__global__ __launch_bounds__(kRB) void k_fv_diag(int64_t nb, const int64_t* __restrict__ cfp,
+                                                 const int32_t* __restrict__ cfi, const double* __restrict__ T,
+                                                 double* __restrict__ diag) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; i < nb;
+         i += static_cast<int64_t>(gridDim.x) * kRB) {
+        double s = 0.0;
+        for (int64_t e = cfp[i]; e < cfp[i + 1]; ++e) s += T[cfi[e]];
+        diag[i] = s;
+    }
+}
+
+__global__ __launch_bounds__(kRB) void k_fv_values(int64_t nnz, const int32_t* __restrict__ slot,
+                                                   const double* __restrict__ T, const double* __restrict__ diag,
+                                                   double* __restrict__ val) {
+    for (int64_t p = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; p < nnz;
+         p += static_cast<int64_t>(gridDim.x) * kRB) {
+        const int32_t c = slot[p];
+        val[p] = c >= 0 ? -T[c] : diag[-static_cast<int64_t>(c) - 1];
+    }
+}
+
 __global__ __launch_bounds__(kRB) void k_dense_to_f32(int64_t rows, int64_t n, int64_t ld,
                                                       const double* __restrict__ X, float* __restrict__ out) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x;
@@ -354,6 +428,17 @@ __global__ __launch_bounds__(kRB) void k_dense_to_f32(int64_t rows, int64_t n, i
 }
 
 }  // namespace
+
+hipError_t launch_fv_values(hipStream_t st, int64_t nf, int64_t nb, int64_t nnz, const int64_t* ca, const int64_t* cb,
+                            const int8_t* kind, const double* area, const double* da, const double* db,
+                            const int64_t* cfp, const int32_t* cfi, const int32_t* slot, const double* kap, double* T,
+                            double* diag, double* val) {
+    if (nf > 0)
+        hipLaunchKernelGGL(k_fv_face_T, dim3(grid_for(nf)), dim3(kRB), 0, st, nf, ca, cb, kind, area, da, db, kap, T);
+    hipLaunchKernelGGL(k_fv_diag, dim3(grid_for(nb)), dim3(kRB), 0, st, nb, cfp, cfi, T, diag);
+    hipLaunchKernelGGL(k_fv_values, dim3(grid_for(nnz)), dim3(kRB), 0, st, nnz, slot, T, diag, val);
+    return hipGetLastError();
+}
 
 hipError_t launch_dense_to_f32(hipStream_t st, int S, int64_t n, int64_t ld, const double* X, float* out) {
     const int64_t rows = static_cast<int64_t>(S) * n;
@@ -423,12 +508,12 @@ hipError_t launch_fsai(hipStream_t st, int64_t n, const int32_t* arp, const int3
     return hipGetLastError();
 }
 
-hipError_t launch_spgemm_masked(hipStream_t st, int64_t nr, const int32_t* arp, const int32_t* aci,
+hipError_t launch_spgemm_masked(hipStream_t st, int64_t nr, int64_t nnz, const int32_t* arp, const int32_t* aci,
                                 const double* av, const int32_t* brp, const int32_t* bci, const double* bv,
-                                const int32_t* crp, const int32_t* cci, double* cv, int* err) {
-    if (nr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spgemm_masked, dim3(static_cast<unsigned>((nr + kRB - 1) / kRB)), dim3(kRB), 0, st, nr,
-                       arp, aci, av, brp, bci, bv, crp, cci, cv, err);
+                                const int32_t* crp, const int32_t* cci, double* cv) {
+    if (nr <= 0 || nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spgemm_masked, dim3(grid_for(nnz)), dim3(kRB), 0, st, nr, nnz, arp, aci, av, brp, bci, bv,
+                       crp, cci, cv);
     return hipGetLastError();
 }
 
@@ -438,9 +523,21 @@ hipError_t launch_scale(hipStream_t st, int64_t n, double* v, double s) {
     return hipGetLastError();
 }
 
+hipError_t launch_sell_values(hipStream_t st, int64_t slots, int vs, const int64_t* pos, const double* v,
+                              double* out64, float* out32) {
+    if (slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sell_values, dim3(grid_for(slots * vs)), dim3(kRB), 0, st, slots, vs, pos, v, out64, out32);
+    return hipGetLastError();
+}
+
 hipError_t launch_spmv(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
-                       const double* x, double* y) {
+                       const double* x, double* y, int64_t nnz) {
     if (n <= 0) return hipSuccess;
+    if (nnz >= 32 * n) {   // long rows: a wavefront each
+        hipLaunchKernelGGL(k_spmv_wave, dim3(static_cast<unsigned>((n + kRB / 64 - 1) / (kRB / 64))), dim3(kRB), 0,
+                           st, n, rp, ci, v, x, y);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_spmv, dim3(static_cast<unsigned>((n + kRB - 1) / kRB)), dim3(kRB), 0, st, n, rp, ci, v, x,
                        y);
     return hipGetLastError();

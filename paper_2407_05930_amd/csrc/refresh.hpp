@@ -1,7 +1,7 @@
 // Launchers of the numeric re-setup kernels (refresh.hip).  Matrices are CSR
 // with int32 row pointers and columns; every launch is asynchronous on `st`;
-// `err` (device int) collects pattern misses (1: interpolation, 4: product)
-// and non-positive FSAI pivots (2).
+// `err` (device int) collects pattern misses of the interpolation (1) and
+// non-positive FSAI pivots (2).
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -37,13 +37,18 @@ hipError_t launch_interp_finish(hipStream_t st, int64_t n, const int8_t* cf, con
 hipError_t launch_fsai(hipStream_t st, int64_t n, const int32_t* arp, const int32_t* aci, const double* av,
                        const int32_t* grp, const int32_t* gci, double* gv, const int64_t* woff, double* work,
                        int* err);
-// C = A B on C's known pattern (nr rows)
-hipError_t launch_spgemm_masked(hipStream_t st, int64_t nr, const int32_t* arp, const int32_t* aci,
+// C = A B on C's kept pattern (nr rows, nnz entries), which holds every
+// product term (a symbolic product of the kept patterns)
+hipError_t launch_spgemm_masked(hipStream_t st, int64_t nr, int64_t nnz, const int32_t* arp, const int32_t* aci,
                                 const double* av, const int32_t* brp, const int32_t* bci, const double* bv,
-                                const int32_t* crp, const int32_t* cci, double* cv, int* err);
+                                const int32_t* crp, const int32_t* cci, double* cv);
 hipError_t launch_scale(hipStream_t st, int64_t n, double* v, double s);
+// y = M x (n rows, nnz entries: rows of 32 or more entries on average take a wavefront each)
 hipError_t launch_spmv(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci, const double* v,
-                       const double* x, double* y);
+                       const double* x, double* y, int64_t nnz);
+// values of a sliced-ELL form (slots x vs sets; FP32 if out32) from CSR values, pos: slot -> entry (-1: padding)
+hipError_t launch_sell_values(hipStream_t st, int64_t slots, int vs, const int64_t* pos, const double* v,
+                              double* out64, float* out32);
 // out[0] = v.w, out[1] = w.w (nb block partials in part, 2 * nb doubles)
 hipError_t launch_power_dots(hipStream_t st, int64_t n, const double* v, const double* w, double* part, int nb,
                              double* out);
@@ -56,5 +61,12 @@ hipError_t launch_dense_inverse(hipStream_t st, int64_t n, int S, const int32_t*
 
 // out (S * n rows of ld floats) = X (S * n rows of n doubles), padding zero
 hipError_t launch_dense_to_f32(hipStream_t st, int S, int64_t n, int64_t ld, const double* X, float* out);
+
+// finite-volume values on the device: T per face, the diagonal per base cell,
+// then val[p] = slot[p] >= 0 ? -T[slot[p]] : diag[-slot[p] - 1]
+hipError_t launch_fv_values(hipStream_t st, int64_t nf, int64_t nb, int64_t nnz, const int64_t* ca, const int64_t* cb,
+                            const int8_t* kind, const double* area, const double* da, const double* db,
+                            const int64_t* cfp, const int32_t* cfi, const int32_t* slot, const double* kap, double* T,
+                            double* diag, double* val);
 
 }  // namespace msp

@@ -101,3 +101,54 @@ def test_unconverged_solve_is_an_error_in_the_autograd_function():
     kap = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
     with pytest.raises(MspError, match="NOT_CONVERGED"):
         dp(f, kap)
+
+
+def test_device_assembly_equals_the_host_assembly():
+    """msp_fv_assemble_device: the same values in the same positions, bit for
+    bit (same arithmetic, same summation order), here for two kappa fields."""
+    torch = _torch()
+    from paper_2407_05930_amd.adjoint import FVOperator
+    pr = make_problem((20, 16, 12), s=3, m=1, seed=16, kappa="lognormal", jitter=0.2)
+    op = FVOperator(pr.faces, pr.img)
+    for kv in (pr.kappa_base, pr.kappa_base * np.exp(np.random.default_rng(2).standard_normal(pr.n_b))):
+        A = op.assemble(kv)
+        d = op.assemble_device(torch.from_numpy(kv).cuda()).cpu().numpy()
+        assert d.size == A.nnz
+        assert np.array_equal(d, A.data)
+    op.close()
+
+
+def test_device_resetup_in_an_optimisation_loop_matches_the_oracle():
+    """resetup = "device": kappa steps rebuild the solver on the device on
+    the first setup's structure; each step's loss and gradients equal the
+    oracle's for that kappa, and a backward for a forward whose kappa has
+    been replaced since is refused."""
+    torch = _torch()
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    pr = make_problem((24, 20, 16), s=3, m=1, seed=17, kappa="lognormal", with_target=True)
+    pstar = pr.p_target[:, None]
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-13, coarse_max=48, resetup="device")
+    f = torch.from_numpy(pr.b).cuda()
+    pst = torch.from_numpy(pstar).cuda()
+    kv = pr.kappa_base.copy()
+    rng = np.random.default_rng(3)
+    first = None
+    for step in range(3):
+        kap = torch.from_numpy(kv).cuda().requires_grad_(True)
+        p = dp(f, kap)
+        loss = 0.5 * ((p - pst) ** 2).sum()
+        loss.backward()
+        L, lam, g, p_ref = adjoint.loss_and_gradients(pr.faces, pr.img, kv, pr.b, pstar)
+        assert abs(loss.item() - L) <= 1e-9 * abs(L)
+        assert np.linalg.norm(p.detach().cpu().numpy() - p_ref) <= 1e-9 * np.linalg.norm(p_ref)
+        gk = kap.grad.cpu().numpy()
+        assert np.linalg.norm(gk - g) <= 1e-9 * np.linalg.norm(g)
+        if first is None:
+            first = dp.solver
+        assert dp.solver is first                     # re-set up in place, not rebuilt
+        kv = kv * np.exp(0.2 * rng.standard_normal(pr.n_b))
+    ka = torch.from_numpy(kv).cuda().requires_grad_(True)
+    loss_a = 0.5 * ((dp(f, ka) - pst) ** 2).sum()
+    dp(f, torch.from_numpy(kv * 1.5).cuda())           # replaces the solver's values
+    with pytest.raises(RuntimeError, match="re-set up"):
+        loss_a.backward()

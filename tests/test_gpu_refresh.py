@@ -275,3 +275,33 @@ def test_refresh_rejects_what_it_does_not_rebuild():
     host = Solver(p.A, p.img, coarse_max=32, device=-1)
     with pytest.raises(MspError):
         host.refresh(v)
+
+
+@pytest.mark.parametrize("pc", ["amgr", "amgr_sub"])
+def test_two_refreshes_then_a_new_column_count_and_exports(pc):
+    """The host copy of the values is fetched lazily: after two re-setups in a
+    row, a solve with a column count not seen before (its kernel choices are
+    tuned then, and sliced forms built from the host copy) and the exports
+    all see the second matrix, as the oracle's re-setup gives it."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("refresh twice", pc)
+    kw = dict(y_stretch=1.5, kappa="lognormal")
+    p0 = make_problem((24, 20, 16), s=3, m=2, seed=91, **kw)
+    p1 = make_problem((24, 20, 16), s=3, m=2, seed=92, **kw)
+    p2 = make_problem((24, 20, 16), s=3, m=5, seed=93, **kw)
+    opt = dict(coarse_max=48)
+    sv = Solver(p0.A, p0.img, tol=TOL, pc=pc, **opt)
+    sv.solve(torch.from_numpy(p0.b).cuda())
+    sv.refresh(torch.from_numpy(p1.A.data).cuda())
+    sv.refresh(torch.from_numpy(p2.A.data).cuda())
+    ctx2 = refresh.refresh(krylov.setup(p0.A, p0.img, amg.AMGOptions(**opt), precond=pc), p2.A)
+    ref = krylov.solve(ctx2, p2.b, tol=TOL)
+    x = sv.solve(torch.from_numpy(p2.b).cuda()).cpu().numpy()
+    _say("its gpu", sv.last.iters, "oracle", ref.iters.max())
+    assert sv.last.iters == int(ref.iters.max())
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _check_levels(sv, ctx2["hier"], ctx2["sub"])
+    sigma, _ = sv.export_outer()
+    for a in range(8):
+        assert np.abs(sigma[:, a] - ctx2["outs"][a].diagonal()).max() <= 1e-15 * np.abs(p2.A.data).max()
