@@ -18,6 +18,15 @@ listed with its reason in the design notes):
     (eq. (3.14)), damped by 4/(3 lambda_max(G A G^T));
   * reduced operator A_c = P^T A P (eq. (3.15)), symbolic pattern;
   * coarsest level: dense Cholesky.
+Options for the methods the experiments use (Sec. 5: an adaptive FSAI
+smoother with five entries per row, energy minimisation of the
+interpolation), which the paper cites without defining:
+  * afsai_nnz > 0: the FSAI pattern grown row by row by the greedy search of
+    adaptive FSAI (largest decrease of the row's quadratic form per added
+    entry), then the static FSAI on it;
+  * emin_steps > 0: every interpolation refined by projected, Jacobi-
+    preconditioned conjugate gradients on tr(P^T A P) with its pattern and
+    row sums fixed.
 """
 from __future__ import annotations
 
@@ -364,6 +373,120 @@ def fsai(A: sp.csr_matrix, S: sp.csr_matrix, block: np.ndarray) -> sp.csr_matrix
     return G
 
 
+# Scores within this relative distance of the best are ties (broken by the
+# smaller column), so that rounding differences between implementations do
+# not change the pattern.
+AFSAI_TIE = 1e-10
+
+
+def afsai_pattern(A: sp.csr_matrix, block: np.ndarray, nnz_max: int) -> sp.csr_matrix:
+    """Adaptive FSAI pattern (greedy pattern search of adaptive FSAI).  Row i
+    starts from P_i = {i}.  Each step takes the row g with g_i = 1 and support
+    P_i that minimises g^T A g, forms r = A g, and adds the candidate
+    j < i outside P_i with block_j == block_i and r_j != 0 whose score
+    r_j^2 / a_jj is largest: the decrease of g^T A g that a step along e_j
+    alone achieves, a lower bound of the decrease after re-minimising.  It
+    stops at nnz_max entries or when no candidate has a positive score.
+    Returns the lower pattern (diagonal included) as a CSR matrix of ones."""
+    A = A.tocsr()
+    A.sort_indices()
+    n = A.shape[0]
+    d = A.diagonal()
+    rows, cols = [], []
+    for i in range(n):
+        P = [i]
+        g = np.array([1.0])
+        while len(P) < nnz_max:
+            # r = A g over the rows of P in insertion order (A is symmetric)
+            seg_c = [A.indices[A.indptr[p]:A.indptr[p + 1]] for p in P]
+            seg_v = [A.data[A.indptr[p]:A.indptr[p + 1]] * gp for p, gp in zip(P, g)]
+            cc = np.concatenate(seg_c)
+            vv = np.concatenate(seg_v)
+            ok = (cc < i) & (block[cc] == block[i]) & ~np.isin(cc, P)
+            if not ok.any():
+                break
+            cand, inv = np.unique(cc[ok], return_inverse=True)
+            r = np.zeros(cand.size)
+            np.add.at(r, inv, vv[ok])
+            score = r * r / d[cand]
+            best = score.max()
+            if not best > 0.0:
+                break
+            P.append(int(cand[np.flatnonzero(score >= best * (1.0 - AFSAI_TIE))[0]]))
+            Q = np.array(P[1:])
+            y = np.linalg.solve(A[Q][:, Q].toarray(), -A[Q, i].toarray().ravel())
+            g = np.concatenate([[1.0], y])
+        rows.extend([i] * len(P))
+        cols.extend(P)
+    S = sp.csr_matrix((np.ones(len(rows)), (np.array(rows), np.array(cols))), shape=(n, n))
+    S.sort_indices()
+    return S
+
+
+def emin(A: sp.csr_matrix, C: np.ndarray, P: sp.csr_matrix, steps: int) -> sp.csr_matrix:
+    """Energy-minimising interpolation: minimise tr(P^T A P) over the F rows W
+    of P = [W; I] on W's pattern with every row sum of W kept (P keeps what it
+    gives for the coarse constant), by `steps` conjugate-gradient steps
+    started at W.  The objective's half gradient is A_FF W + A_FC on the
+    pattern; the constraint's tangent space is {D : every row of D sums to
+    0} (orthogonal projection: subtract the row mean over the row's pattern);
+    the preconditioner divides row f by a_ff, which maps that space to
+    itself."""
+    A = A.tocsr()
+    A.sort_indices()
+    n = A.shape[0]
+    fidx = np.flatnonzero(~C)
+    cidx = np.flatnonzero(C)
+    AF = A[fidx].tocsr()
+    AFF = AF[:, fidx].tocsr()
+    AFC = AF[:, cidx].tocsr()
+    W = P.tocsr()[fidx].tocsr()
+    W.sort_indices()
+    cnt = np.diff(W.indptr)
+    wr = np.repeat(np.arange(fidx.size), cnt)
+    wc = W.indices
+    dinv = 1.0 / AFF.diagonal()[wr]
+
+    def on_pattern(M):
+        M = M.tocsr()
+        M.sort_indices()
+        return lookup(M, wr, wc)
+
+    def project(v):
+        s = np.zeros(fidx.size)
+        np.add.at(s, wr, v)
+        return v - (s / np.maximum(cnt, 1))[wr]
+
+    def mat(v):
+        return sp.csr_matrix((v, wc, W.indptr), shape=W.shape)
+
+    w = W.data.copy()
+    r = -project(on_pattern(AFF @ mat(w) + AFC))
+    z = dinv * r
+    p = z.copy()
+    rz = float(r @ z)
+    for _ in range(steps):
+        if not rz > 0.0:
+            break
+        q = project(on_pattern(AFF @ mat(p)))
+        pq = float(p @ q)
+        if not pq > 0.0:
+            break
+        alpha = rz / pq
+        w = w + alpha * p
+        r = r - alpha * q
+        z = dinv * r
+        rz_new = float(r @ z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    Pn = P.tocsr().copy()
+    Pn.sort_indices()
+    frows = np.repeat(np.arange(n), np.diff(Pn.indptr))
+    isf = ~C[frows]
+    Pn.data[isf] = w        # F entries of P in fine-row order are W's entries in order
+    return Pn
+
+
 def damping(A: sp.csr_matrix, G: sp.csr_matrix, seed: int, iters: int = 20) -> float:
     """omega = 4 / (3 lam), lam from `iters` power iterations on G A G^T started
     at v_i = splitmix64(seed xor i)/2^64 - 1/2; lam is the Rayleigh quotient
@@ -427,6 +550,8 @@ class AMGOptions:
     mis_method: str = "rounds"
     nu1: int = 1              # smoothing sweeps before and after the coarse correction (Alg. 3)
     nu2: int = 1
+    afsai_nnz: int = 0        # > 0: adaptive FSAI pattern with at most this many entries per row
+    emin_steps: int = 0       # > 0: energy minimisation of every interpolation, this many CG steps
 
 
 def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions,
@@ -462,9 +587,11 @@ def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions,
         S = strength(A, opt.theta)
         block = C.astype(np.int64) if lev == 0 else np.zeros(n, dtype=np.int64)
         L.C = C
-        L.G = fsai(A, S, block)
+        L.G = fsai(A, afsai_pattern(A, block, opt.afsai_nnz) if opt.afsai_nnz > 0 else S, block)
         L.omega = damping(A, L.G, opt.seed)
         L.P = interpolation(A, C, steps, trunc)
+        if opt.emin_steps > 0:
+            L.P = emin(A, C, L.P, opt.emin_steps)
         L.R = L.P.T.tocsr()
         L.R.sort_indices()
         A = galerkin(A, L.P)
@@ -515,17 +642,19 @@ class SubHierarchy:
 
 
 def sub_level_values(A: sp.csr_matrix, shared: Level, steps: int, seed: int, level0: bool,
-                     pattern: sp.csr_matrix | None = None) -> Level:
+                     pattern: sp.csr_matrix | None = None, emin_steps: int = 0) -> Level:
     """One level for a subsystem operator A with the shared level's C/F split
-    and FSAI pattern (from the strength of the shared operator, or the given
-    lower-triangular ``pattern``: a kept one)."""
+    and FSAI pattern (the shared factor's, or the given lower-triangular
+    ``pattern``: a kept one)."""
     n = A.shape[0]
     C = shared.C
-    S = strength(shared.A, AMGOptions.theta) if pattern is None else pattern
+    S = shared.G if pattern is None else pattern
     block = C.astype(np.int64) if level0 else np.zeros(n, dtype=np.int64)
     G = fsai(A, S, block)
     om = damping(A, G, seed)
     P = interpolation(A, C, steps)
+    if emin_steps > 0:
+        P = emin(A, C, P, emin_steps)
     R = P.T.tocsr()
     R.sort_indices()
     return Level(A=A, C=C, P=P, R=R, G=G, omega=om)
@@ -549,7 +678,7 @@ def build_sub_hierarchy(hier: Hierarchy, sigma: np.ndarray, opt: AMGOptions,
                 levels.append(Level(A=A))
                 break
             Lv = sub_level_values(A, hier.levels[lev], opt.jacobi, opt.seed, False,
-                                  None if patterns is None else patterns[lev])
+                                  None if patterns is None else patterns[lev], opt.emin_steps)
             levels.append(Lv)
             A = galerkin(A, Lv.P)
         fac = sla.cho_factor(levels[-1].A.toarray(), lower=True)

@@ -70,6 +70,8 @@ def refresh(ctx: dict, A_new: sp.csr_matrix) -> dict:
         raise ValueError("interface differs from the earlier setup")
     if precond not in ("amgr", "amgr_sub"):
         raise ValueError(precond)
+    if opt.emin_steps > 0:
+        raise ValueError("the re-setup recomputes no energy minimisation")
     hier = refresh_hierarchy(ctx["hier"], Ainn, opt)
     sub = None
     if precond == "amgr_sub" and hier.nlev > 1:
