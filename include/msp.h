@@ -157,6 +157,18 @@ typedef struct {
                                 ||b - A x|| / ||b|| per right-hand side in msp_stats.relres_true
                                 (two transforms, one operator product and one dot more); 0 (default):
                                 relres_true is -1 */
+    int32_t afsai_nnz;       /* > 0: adaptive FSAI smoothers. Each row's lower pattern grows from the
+                                diagonal, one entry per step, to at most afsai_nnz entries. A step adds the
+                                candidate j < i (same F/C block at the reduction level) with the largest
+                                (A g)_j^2 / a_jj, g the row's current minimiser of g^T A g with g_i = 1.
+                                Scores within 1e-10 of the best tie to the smaller column. The static FSAI
+                                on that pattern follows. Sec. 5 uses an adaptive FSAI with five entries per
+                                row. 0 (default): static FSAI on the strong lower pattern. At most 64 */
+    int32_t emin_steps;      /* > 0: every interpolation is refined by this many Jacobi-preconditioned
+                                conjugate-gradient steps on tr(P^T A P), its pattern and row sums fixed
+                                (energy minimisation, which Sec. 5 applies). 0 (default): none. At most
+                                100. The device re-setup (msp_refresh) does not recompute it
+                                (MSP_ERR_UNSUPPORTED) */
 } msp_opts;
 
 typedef struct {
@@ -185,7 +197,7 @@ typedef struct {
    jacobi0 = 3, jacobi = 1, coarse_max = 2560, max_levels = 20,
    max_ratio = 0.8, tol = 1e-10, maxit = 1000, device = 0, seed = 240705930,
    trunc0 = 0.05, coarse64 = 0, nu1 = nu2 = 1, amgs_light = 0, schur_tau = 0.01,
-   true_residual = 0. */
+   true_residual = 0, afsai_nnz = 0, emin_steps = 0. */
 int msp_default_opts(msp_opts* o);
 
 /* Build a context from A and its symmetry map.  Validates the map

@@ -54,7 +54,8 @@ class msp_opts(ctypes.Structure):
                 ("max_ratio", ctypes.c_double), ("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("seed", ctypes.c_uint64), ("trunc0", ctypes.c_double),
                 ("coarse64", ctypes.c_int32), ("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32),
-                ("amgs_light", ctypes.c_int32), ("schur_tau", ctypes.c_double), ("true_residual", ctypes.c_int32)]
+                ("amgs_light", ctypes.c_int32), ("schur_tau", ctypes.c_double), ("true_residual", ctypes.c_int32),
+                ("afsai_nnz", ctypes.c_int32), ("emin_steps", ctypes.c_int32)]
 
 
 class msp_stats(ctypes.Structure):

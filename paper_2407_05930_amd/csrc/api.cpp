@@ -1853,6 +1853,10 @@ static void check_opts(const msp_opts* o) {
     if (o->nu1 != o->nu2)
         throw Error(MSP_ERR_UNSUPPORTED, "nu1 != nu2 makes the V-cycle non-symmetric, which PCG cannot take");
     if (o->true_residual != 0 && o->true_residual != 1) throw Error(MSP_ERR_ARG, "true_residual must be 0 or 1");
+    if (o->afsai_nnz < 0 || o->afsai_nnz > 64) throw Error(MSP_ERR_ARG, "afsai_nnz must be in 0..64");
+    if (o->emin_steps < 0 || o->emin_steps > 100) throw Error(MSP_ERR_ARG, "emin_steps must be in 0..100");
+    if (o->pc == MSP_PC_AMGS && (o->afsai_nnz > 0 || o->emin_steps > 0))
+        throw Error(MSP_ERR_UNSUPPORTED, "AMGS keeps its own FSAIs and the plain interpolation");
 }
 
 // Host part of the setup: blocks, validation, hierarchy (no HIP calls).
@@ -2923,6 +2927,7 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
     if (!c->on_device) throw Error(MSP_ERR_ARG, "the context has no device setup");
     if (c->o.pc == MSP_PC_AMGS) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup of AMGS");
     if (c->o.precision == MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup of the BF16-G variant");
+    if (c->o.emin_steps > 0) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup recomputes no energy minimisation");
     HIPCHECK(hipSetDevice(c->device));
     if (!c->rf) refresh_build(c);
     RefreshState& R = *c->rf;

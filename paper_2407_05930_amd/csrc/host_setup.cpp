@@ -595,6 +595,191 @@ Csr fsai_full_lower(const Csr& A) {
     return fsai_rows(A, lower);
 }
 
+// Adaptive FSAI pattern: row i grows from {i}.  Each step takes the row g
+// (g_i = 1, support P) minimising g^T A g, forms r = A g over the rows of P in
+// the order they joined (columns ascending within a row), and adds the
+// candidate j < i outside P (same block if `block`) with the largest
+// r_j^2 / a_jj; scores within kAfsaiTie of the best tie to the smaller column.
+// Stops at nnz_max entries or when no score is positive.  Returns the lower
+// neighbours of each row, ascending (the diagonal not included).
+static constexpr double kAfsaiTie = 1e-10;
+
+static std::vector<std::vector<int32_t>> afsai_lower(const Csr& A, const std::vector<int8_t>* block, int nnz_max) {
+    const int64_t n = A.nr;
+    std::vector<double> d(n);
+    for (int64_t i = 0; i < n; ++i) d[i] = lookup(A, i, static_cast<int32_t>(i));
+    std::vector<std::vector<int32_t>> lower(n);
+    std::vector<int64_t> stamp(n, -1);
+    std::vector<double> acc(n, 0.0);
+    std::vector<int32_t> P, cand;
+    std::vector<double> g, M, y;
+    int64_t tick = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        P.assign(1, static_cast<int32_t>(i));
+        g.assign(1, 1.0);
+        while (static_cast<int>(P.size()) < nnz_max) {
+            ++tick;
+            cand.clear();
+            for (size_t t = 0; t < P.size(); ++t) {
+                const int32_t p = P[t];
+                for (int64_t k = A.rp[p]; k < A.rp[p + 1]; ++k) {
+                    const int32_t j = A.ci[k];
+                    if (j >= i) break;   // columns ascending
+                    if (block && (*block)[j] != (*block)[i]) continue;
+                    if (std::find(P.begin(), P.end(), j) != P.end()) continue;
+                    if (stamp[j] != tick) {
+                        stamp[j] = tick;
+                        acc[j] = 0.0;
+                        cand.push_back(j);
+                    }
+                    acc[j] += A.v[k] * g[t];
+                }
+            }
+            if (cand.empty()) break;
+            double best = 0.0;
+            for (int32_t j : cand) best = std::max(best, acc[j] * acc[j] / d[j]);
+            if (!(best > 0.0)) break;
+            int32_t pick = -1;
+            for (int32_t j : cand)
+                if (acc[j] * acc[j] / d[j] >= best * (1.0 - kAfsaiTie) && (pick < 0 || j < pick)) pick = j;
+            P.push_back(pick);
+            // re-minimise: A[Q,Q] y = -A[Q,i], Q = P without i
+            const int q = static_cast<int>(P.size()) - 1;
+            M.assign(static_cast<size_t>(q) * q, 0.0);
+            y.assign(q, 0.0);
+            for (int a = 0; a < q; ++a) {
+                for (int b = 0; b < q; ++b) M[a * q + b] = lookup(A, P[a + 1], P[b + 1]);
+                y[a] = -lookup(A, P[a + 1], static_cast<int32_t>(i));
+            }
+            if (!cholesky(q, M.data())) throw Error(MSP_ERR_NOT_SPD, "adaptive FSAI: local matrix not SPD");
+            for (int a = 0; a < q; ++a) {   // L z = y, then L^T y = z
+                double s = y[a];
+                for (int b = 0; b < a; ++b) s -= M[a * q + b] * y[b];
+                y[a] = s / M[a * q + a];
+            }
+            for (int a = q - 1; a >= 0; --a) {
+                double s = y[a];
+                for (int b = a + 1; b < q; ++b) s -= M[b * q + a] * y[b];
+                y[a] = s / M[a * q + a];
+            }
+            g.assign(1, 1.0);
+            g.insert(g.end(), y.begin(), y.end());
+        }
+        lower[i].assign(P.begin() + 1, P.end());
+        std::sort(lower[i].begin(), lower[i].end());
+    }
+    return lower;
+}
+
+// Energy-minimising interpolation: the F rows W of P = [W; I] minimise
+// tr(P^T A P) on W's pattern with every row sum of W kept, by `steps`
+// conjugate-gradient steps from W.  Half gradient A_FF W + A_FC on the
+// pattern; projection onto the constraint's tangent space subtracts each
+// row's mean over its pattern; preconditioner: row f divided by a_ff.
+static void emin(const Csr& A, const std::vector<int8_t>& cf, Csr& P, int steps) {
+    const int64_t n = A.nr;
+    std::vector<int32_t> fnum(n, -1), cnum(n, -1), fidx;
+    int32_t nc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (cf[i]) cnum[i] = nc++;
+        else {
+            fnum[i] = static_cast<int32_t>(fidx.size());
+            fidx.push_back(static_cast<int32_t>(i));
+        }
+    }
+    const int64_t nf = static_cast<int64_t>(fidx.size());
+    // W: the F rows of P (entry positions of P kept in wpos)
+    std::vector<int64_t> wrp(nf + 1, 0), wpos;
+    std::vector<int32_t> wc;
+    for (int64_t f = 0; f < nf; ++f) {
+        const int32_t i = fidx[f];
+        for (int64_t k = P.rp[i]; k < P.rp[i + 1]; ++k) {
+            wc.push_back(P.ci[k]);
+            wpos.push_back(k);
+        }
+        wrp[f + 1] = static_cast<int64_t>(wc.size());
+    }
+    const int64_t m = wrp[nf];
+    std::vector<double> w(m), dinv(m);
+    for (int64_t e = 0; e < m; ++e) w[e] = P.v[wpos[e]];
+    for (int64_t f = 0; f < nf; ++f) {
+        const double dd = 1.0 / lookup(A, fidx[f], fidx[f]);
+        for (int64_t e = wrp[f]; e < wrp[f + 1]; ++e) dinv[e] = dd;
+    }
+    // slot of column c in row f of W (-1: off the pattern), through a dense row map
+    std::vector<int64_t> slot(nc, -1);
+    // out = A_FF x (+ A_FC if add_afc) on W's pattern, x on W's pattern
+    auto apply = [&](const std::vector<double>& x, bool add_afc, std::vector<double>& out) {
+        std::vector<double> prod(m, 0.0);
+        for (int64_t f = 0; f < nf; ++f) {
+            for (int64_t e = wrp[f]; e < wrp[f + 1]; ++e) slot[wc[e]] = e;
+            const int32_t i = fidx[f];
+            for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                const int32_t g = fnum[A.ci[k]];
+                if (g < 0) continue;
+                const double a = A.v[k];
+                for (int64_t e = wrp[g]; e < wrp[g + 1]; ++e) {
+                    const int64_t q = slot[wc[e]];
+                    if (q >= 0) prod[q] += a * x[e];
+                }
+            }
+            for (int64_t e = wrp[f]; e < wrp[f + 1]; ++e) {
+                double v = prod[e];
+                if (add_afc) {
+                    // A_FC entry (f, c): the coupling of fine row i to the coarse point numbered c
+                    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+                        if (cnum[A.ci[k]] == wc[e]) {
+                            v = v + A.v[k];
+                            break;
+                        }
+                }
+                out[e] = v;
+            }
+            for (int64_t e = wrp[f]; e < wrp[f + 1]; ++e) slot[wc[e]] = -1;
+        }
+    };
+    auto project = [&](std::vector<double>& v) {
+        for (int64_t f = 0; f < nf; ++f) {
+            const int64_t c = wrp[f + 1] - wrp[f];
+            if (c == 0) continue;
+            double s = 0.0;
+            for (int64_t e = wrp[f]; e < wrp[f + 1]; ++e) s += v[e];
+            const double mean = s / static_cast<double>(c);
+            for (int64_t e = wrp[f]; e < wrp[f + 1]; ++e) v[e] = v[e] - mean;
+        }
+    };
+    auto dot = [&](const std::vector<double>& a, const std::vector<double>& b) {
+        double s = 0.0;
+        for (int64_t e = 0; e < m; ++e) s += a[e] * b[e];
+        return s;
+    };
+    std::vector<double> r(m), z(m), p(m), q(m);
+    apply(w, true, r);
+    project(r);
+    for (auto& x : r) x = -x;
+    for (int64_t e = 0; e < m; ++e) z[e] = dinv[e] * r[e];
+    p = z;
+    double rz = dot(r, z);
+    for (int it = 0; it < steps; ++it) {
+        if (!(rz > 0.0)) break;
+        apply(p, false, q);
+        project(q);
+        const double pq = dot(p, q);
+        if (!(pq > 0.0)) break;
+        const double alpha = rz / pq;
+        for (int64_t e = 0; e < m; ++e) {
+            w[e] = w[e] + alpha * p[e];
+            r[e] = r[e] - alpha * q[e];
+        }
+        for (int64_t e = 0; e < m; ++e) z[e] = dinv[e] * r[e];
+        const double rz_new = dot(r, z);
+        const double beta = rz_new / rz;
+        for (int64_t e = 0; e < m; ++e) p[e] = z[e] + beta * p[e];
+        rz = rz_new;
+    }
+    for (int64_t e = 0; e < m; ++e) P.v[wpos[e]] = w[e];
+}
+
 // omega = 4 / (3 lam), lam = v^T G A G^T v after 20 power iterations from
 // v_i = splitmix64(seed xor i)/2^64 - 1/2 (normalised).
 double damping(const Csr& A, const Csr& G, const Csr& GT, uint64_t seed) {
@@ -861,19 +1046,25 @@ HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface,
             L.A = std::move(A);
             break;
         }
-        // smoother: FSAI on the strong lower pattern, block-diagonal F/C at level 0
+        // smoother: FSAI on the strong lower pattern (or an adaptive one), block-diagonal
+        // F/C at level 0
         std::vector<std::vector<int32_t>> lower(n);
-        for (int64_t i = 0; i < n; ++i)
-            for (int64_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
-                const int32_t j = S.ci[k];
-                if (j < i && (lev != 0 || cf[j] == cf[i])) lower[i].push_back(j);
-            }
+        if (o.afsai_nnz > 0) {
+            lower = afsai_lower(A, lev == 0 ? &cf : nullptr, o.afsai_nnz);
+        } else {
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
+                    const int32_t j = S.ci[k];
+                    if (j < i && (lev != 0 || cf[j] == cf[i])) lower[i].push_back(j);
+                }
+        }
         L.G = fsai_rows(A, lower);
         L.GT = transpose(L.G);
         L.omega = damping(A, L.G, L.GT, seed);
         L.M = spgemm(L.GT, L.G);
         for (double& v : L.M.v) v *= L.omega;
         L.P = interpolation(A, cf, lev == 0 ? o.jacobi0 : o.jacobi, lev == 0 ? o.trunc0 : 0.0);
+        if (o.emin_steps > 0) emin(A, cf, L.P, o.emin_steps);
         L.R = transpose(L.P);
         L.cf = std::move(cf);
         Csr AP = spgemm(A, L.P);
@@ -1104,6 +1295,7 @@ SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& si
             Csr GT = transpose(G);
             const double om = damping(A, G, GT, o.seed);
             Csr P = interpolation(A, Ls.cf, o.jacobi);
+            if (o.emin_steps > 0) emin(A, Ls.cf, P, o.emin_steps);
             Csr R = transpose(P);
             Csr M = spgemm(GT, G);
             for (double& v : M.v) v *= om;

@@ -28,5 +28,7 @@ extern "C" int msp_default_opts(msp_opts* o) {
     o->amgs_light = 0;
     o->schur_tau = 0.01;
     o->true_residual = 0;
+    o->afsai_nnz = 0;
+    o->emin_steps = 0;
     return MSP_OK;
 }
