@@ -167,8 +167,7 @@ typedef struct {
     int32_t emin_steps;      /* > 0: every interpolation is refined by this many Jacobi-preconditioned
                                 conjugate-gradient steps on tr(P^T A P), its pattern and row sums fixed
                                 (energy minimisation, which Sec. 5 applies). 0 (default): none. At most
-                                100. The device re-setup (msp_refresh) does not recompute it
-                                (MSP_ERR_UNSUPPORTED) */
+                                100. The device re-setup (msp_refresh) repeats it */
 } msp_opts;
 
 typedef struct {

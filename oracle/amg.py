@@ -385,40 +385,62 @@ def afsai_pattern(A: sp.csr_matrix, block: np.ndarray, nnz_max: int) -> sp.csr_m
     P_i that minimises g^T A g, forms r = A g, and adds the candidate
     j < i outside P_i with block_j == block_i and r_j != 0 whose score
     r_j^2 / a_jj is largest: the decrease of g^T A g that a step along e_j
-    alone achieves, a lower bound of the decrease after re-minimising.  It
-    stops at nnz_max entries or when no candidate has a positive score.
-    Returns the lower pattern (diagonal included) as a CSR matrix of ones."""
+    alone achieves, a lower bound of the decrease after re-minimising.  Scores
+    within AFSAI_TIE of the best tie to the smaller column.  A row stops at
+    nnz_max entries or when no candidate has a positive score.  All rows take
+    their steps together: r for every row is one sparse product (rows of the
+    current g's times A, A symmetric), and the rows still growing all hold
+    the same number of entries, so their re-minimisations are one batched
+    solve.  Returns the lower pattern (diagonal included) as a CSR matrix of
+    ones."""
     A = A.tocsr()
     A.sort_indices()
     n = A.shape[0]
     d = A.diagonal()
-    rows, cols = [], []
-    for i in range(n):
-        P = [i]
-        g = np.array([1.0])
-        while len(P) < nnz_max:
-            # r = A g over the rows of P in insertion order (A is symmetric)
-            seg_c = [A.indices[A.indptr[p]:A.indptr[p + 1]] for p in P]
-            seg_v = [A.data[A.indptr[p]:A.indptr[p + 1]] * gp for p, gp in zip(P, g)]
-            cc = np.concatenate(seg_c)
-            vv = np.concatenate(seg_v)
-            ok = (cc < i) & (block[cc] == block[i]) & ~np.isin(cc, P)
-            if not ok.any():
-                break
-            cand, inv = np.unique(cc[ok], return_inverse=True)
-            r = np.zeros(cand.size)
-            np.add.at(r, inv, vv[ok])
-            score = r * r / d[cand]
-            best = score.max()
-            if not best > 0.0:
-                break
-            P.append(int(cand[np.flatnonzero(score >= best * (1.0 - AFSAI_TIE))[0]]))
-            Q = np.array(P[1:])
-            y = np.linalg.solve(A[Q][:, Q].toarray(), -A[Q, i].toarray().ravel())
-            g = np.concatenate([[1.0], y])
-        rows.extend([i] * len(P))
-        cols.extend(P)
-    S = sp.csr_matrix((np.ones(len(rows)), (np.array(rows), np.array(cols))), shape=(n, n))
+    pat = np.full((n, max(nnz_max, 1)), -1, dtype=np.int64)    # entries in the order they joined
+    pat[:, 0] = np.arange(n)
+    g = np.zeros((n, max(nnz_max, 1)))
+    g[:, 0] = 1.0
+    active = np.arange(n)
+    for t in range(1, nnz_max):
+        if active.size == 0:
+            break
+        # r = (rows of g) A for the active rows
+        Gr = sp.csr_matrix((g[active, :t].ravel(), pat[active, :t].ravel(),
+                            np.arange(0, (active.size + 1) * t, t)), shape=(active.size, n))
+        R = (Gr @ A).tocsr()
+        R.sort_indices()
+        rr = np.repeat(np.arange(active.size), np.diff(R.indptr))
+        rows = active[rr]
+        cols = R.indices
+        inpat = np.zeros(cols.size, dtype=bool)
+        for q in range(t):
+            inpat |= pat[rows, q] == cols
+        ok = (cols < rows) & (block[cols] == block[rows]) & ~inpat & (R.data != 0.0)
+        score = np.where(ok, R.data * R.data / d[cols], -1.0)
+        best = np.full(active.size, -1.0)
+        np.maximum.at(best, rr, score)
+        pick = np.full(active.size, -1, dtype=np.int64)
+        take = ok & (score >= best[rr] * (1.0 - AFSAI_TIE)) & (best[rr] > 0.0)
+        # columns of a row are ascending: the first qualifying entry is the smallest column
+        first = np.flatnonzero(take)
+        first = first[np.concatenate([[True], rr[first][1:] != rr[first][:-1]])] if first.size else first
+        pick[rr[first]] = cols[first]
+        grow = pick >= 0
+        active = active[grow]
+        if active.size == 0:
+            break
+        pat[active, t] = pick[grow]
+        # re-minimise on Q = P \ {i}: A[Q, Q] y = -A[Q, i]
+        Q = pat[active, 1:t + 1]
+        M = lookup(A, np.repeat(Q, t, axis=1).ravel(), np.tile(Q, (1, t)).ravel()).reshape(-1, t, t)
+        rhs = -lookup(A, Q.ravel(), np.repeat(active, t)).reshape(-1, t)
+        y = np.linalg.solve(M, rhs[:, :, None])[:, :, 0]
+        g[active, 0] = 1.0
+        g[active, 1:t + 1] = y
+    keep = pat >= 0
+    S = sp.csr_matrix((np.ones(int(keep.sum())), (np.repeat(np.arange(n), keep.sum(axis=1)), pat[keep])),
+                      shape=(n, n))
     S.sort_indices()
     return S
 

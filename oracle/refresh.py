@@ -13,6 +13,7 @@ the same formulas as a fresh setup:
     patterns (which depend on the sparsity only), restricted at the reduction
     level to the kept pattern instead of the value-based truncation, then the
     row-sum rescaling (eq. (3.13));
+  * with energy minimisation, the same steps on every interpolation;
   * FSAI on the kept pattern (block FSAI at level 0, eq. (3.14)) and its
     damping; the Galerkin products (eq. (3.15)) on patterns that the
     unchanged sparsity reproduces;
@@ -53,6 +54,8 @@ def refresh_hierarchy(old: amg.Hierarchy, Ainn: sp.csr_matrix, opt: amg.AMGOptio
             L.P = amg.interpolation(A, L.C, opt.jacobi0, keep_pattern=Lo.P if opt.trunc0 > 0.0 else None)
         else:
             L.P = amg.interpolation(A, L.C, opt.jacobi)
+        if opt.emin_steps > 0:
+            L.P = amg.emin(A, L.C, L.P, opt.emin_steps)
         L.R = L.P.T.tocsr()
         L.R.sort_indices()
         A = amg.galerkin(A, L.P)
@@ -70,8 +73,6 @@ def refresh(ctx: dict, A_new: sp.csr_matrix) -> dict:
         raise ValueError("interface differs from the earlier setup")
     if precond not in ("amgr", "amgr_sub"):
         raise ValueError(precond)
-    if opt.emin_steps > 0:
-        raise ValueError("the re-setup recomputes no energy minimisation")
     hier = refresh_hierarchy(ctx["hier"], Ainn, opt)
     sub = None
     if precond == "amgr_sub" and hier.nlev > 1:

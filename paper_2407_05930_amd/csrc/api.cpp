@@ -174,6 +174,8 @@ struct RefreshState {
     double* sub_a1 = nullptr;                 // and A_1,a, the FSAI factors of every subsystem, interleaved
     std::vector<double*> sub_g;
     bool shared_stale = false;                // shared levels below the reduction level not recomputed yet
+    int emin_steps = 0;                       // energy minimisation of the interpolations (as the setup)
+    double* em[6] = {};                       // its work vectors over P's entries
     double* gf = nullptr;                     // pc = FSAI: FSAI of A_inn and its transpose map
     int64_t* gft_src = nullptr;
     int64_t* gf_woff = nullptr;
@@ -2789,6 +2791,12 @@ static void refresh_build(msp_ctx* c) {
             F.ap = c->dalloc<double>(F.AP.nnz);
         }
         R->work = c->dalloc<double>(std::max<int64_t>(1, work));
+        R->emin_steps = c->o.emin_steps;
+        if (R->emin_steps > 0) {
+            int64_t mp = 1;
+            for (size_t l = 0; l + 1 < L; ++l) mp = std::max(mp, c->hier.lev[l].P.nnz());
+            for (double*& e : R->em) e = c->dalloc<double>(mp);
+        }
         R->t1 = c->dalloc<double>(maxn);
         R->t2 = c->dalloc<double>(maxn);
         R->t3 = c->dalloc<double>(maxn);
@@ -2895,6 +2903,40 @@ static void refresh_smoother(RefreshState& R, RfLevel& F, hipStream_t st) {
 }
 
 // Interpolation (the Jacobi steps, the kept pattern, the row rescaling), R, and next = R (A P).
+// Energy minimisation of a level's interpolation, as the setup does it:
+// projected, Jacobi-preconditioned CG on tr(P^T A P) with P's pattern and row
+// sums fixed.  P's C rows are unit rows, so on the F rows the masked product
+// A P on P's pattern is A_FF W + A_FC (the half gradient), and with the C rows
+// zero (the search directions) it is A_FF D.
+static void refresh_emin(RefreshState& R, RfLevel& F, hipStream_t st) {
+    const int64_t m = F.P.nnz, n = F.n;
+    double *g = R.em[0], *r = R.em[1], *z = R.em[2], *p = R.em[3], *q = R.em[4], *dinv = R.em[5];
+    auto dot = [&](const double* a, const double* b) {
+        HIPCHECK(launch_power_dots(st, m, a, b, R.part, R.nbp, R.dots));
+        double h[2];
+        HIPCHECK(hipMemcpyAsync(h, R.dots, sizeof(h), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        return h[0];
+    };
+    HIPCHECK(launch_emin_dinv(st, n, F.A.rp, F.A.ci, F.a, F.P.rp, dinv));
+    HIPCHECK(launch_spgemm_masked(st, n, m, F.A.rp, F.A.ci, F.a, F.P.rp, F.P.ci, F.p, F.P.rp, F.P.ci, g));
+    HIPCHECK(launch_emin_project(st, n, F.P.rp, F.cf, g, -1.0, r));
+    HIPCHECK(launch_mul(st, m, dinv, r, z));
+    HIPCHECK(hipMemcpyAsync(p, z, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    double rz = dot(r, z);
+    for (int it = 0; it < R.emin_steps; ++it) {
+        if (!(rz > 0.0)) break;
+        HIPCHECK(launch_spgemm_masked(st, n, m, F.A.rp, F.A.ci, F.a, F.P.rp, F.P.ci, p, F.P.rp, F.P.ci, g));
+        HIPCHECK(launch_emin_project(st, n, F.P.rp, F.cf, g, 1.0, q));
+        const double pq = dot(p, q);
+        if (!(pq > 0.0)) break;
+        HIPCHECK(launch_emin_step(st, m, rz / pq, p, q, dinv, F.p, r, z));
+        const double rz_new = dot(r, z);
+        HIPCHECK(launch_emin_dir(st, m, rz_new / rz, z, p));
+        rz = rz_new;
+    }
+}
+
 static void refresh_transfer(RefreshState& R, RfLevel& F, double* next, const RfPat& nextpat,
                              hipStream_t st) {
     for (size_t t = 0; t < F.W.size(); ++t) {
@@ -2904,6 +2946,7 @@ static void refresh_transfer(RefreshState& R, RfLevel& F, double* next, const Rf
                                     first ? nullptr : F.w[t - 1], F.W[t].rp, F.W[t].ci, F.w[t], F.afc, F.hasf, R.err));
     }
     HIPCHECK(launch_interp_finish(st, F.n, F.cf, F.A.rp, F.A.ci, F.a, F.w.back(), F.P.rp, F.pmap, F.p));
+    if (R.emin_steps > 0) refresh_emin(R, F, st);
     HIPCHECK(launch_gather(st, F.R.nnz, F.r_src, F.p, F.r));
     HIPCHECK(launch_spgemm_masked(st, F.n, F.AP.nnz, F.A.rp, F.A.ci, F.a, F.P.rp, F.P.ci, F.p, F.AP.rp, F.AP.ci, F.ap));
     HIPCHECK(launch_spgemm_masked(st, nextpat.nr, nextpat.nnz, F.R.rp, F.R.ci, F.r, F.AP.rp, F.AP.ci, F.ap,
@@ -2927,7 +2970,6 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
     if (!c->on_device) throw Error(MSP_ERR_ARG, "the context has no device setup");
     if (c->o.pc == MSP_PC_AMGS) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup of AMGS");
     if (c->o.precision == MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup of the BF16-G variant");
-    if (c->o.emin_steps > 0) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup recomputes no energy minimisation");
     HIPCHECK(hipSetDevice(c->device));
     if (!c->rf) refresh_build(c);
     RefreshState& R = *c->rf;

@@ -282,6 +282,66 @@ __global__ __launch_bounds__(kRB) void k_sell_values(int64_t slots, int vs, cons
     }
 }
 
+// Energy minimisation of an interpolation P (n rows, C rows unit rows), one
+// thread per row.  Projection onto the row-sum constraint: on F rows v minus
+// its row mean (times sign), C rows zero.
+__global__ __launch_bounds__(kRB) void k_emin_project(int64_t n, const int32_t* __restrict__ rp,
+                                                      const int8_t* __restrict__ cf, const double* __restrict__ v,
+                                                      double sign, double* __restrict__ out) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRB) {
+        const int64_t b = rp[i], e = rp[i + 1];
+        if (cf[i]) {
+            for (int64_t k = b; k < e; ++k) out[k] = 0.0;
+            continue;
+        }
+        double s = 0.0;
+        for (int64_t k = b; k < e; ++k) s += v[k];
+        const double mean = e > b ? s / static_cast<double>(e - b) : 0.0;
+        for (int64_t k = b; k < e; ++k) out[k] = sign * (v[k] - mean);
+    }
+}
+
+// dinv[k] = 1 / a_ii for every entry k of row i of P
+__global__ __launch_bounds__(kRB) void k_emin_dinv(int64_t n, const int32_t* __restrict__ arp,
+                                                   const int32_t* __restrict__ aci, const double* __restrict__ av,
+                                                   const int32_t* __restrict__ prp, double* __restrict__ dinv) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRB) {
+        const double d = 1.0 / lookup(arp, aci, av, static_cast<int32_t>(i), static_cast<int32_t>(i));
+        for (int64_t k = prp[i]; k < prp[i + 1]; ++k) dinv[k] = d;
+    }
+}
+
+// w += alpha p, r -= alpha q, z = dinv r
+__global__ __launch_bounds__(kRB) void k_emin_step(int64_t m, double alpha, const double* __restrict__ p,
+                                                   const double* __restrict__ q, const double* __restrict__ dinv,
+                                                   double* __restrict__ w, double* __restrict__ r,
+                                                   double* __restrict__ z) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; k < m;
+         k += static_cast<int64_t>(gridDim.x) * kRB) {
+        w[k] = w[k] + alpha * p[k];
+        const double rn = r[k] - alpha * q[k];
+        r[k] = rn;
+        z[k] = dinv[k] * rn;
+    }
+}
+
+// p = z + beta p (beta = 0: p = z)
+__global__ __launch_bounds__(kRB) void k_emin_dir(int64_t m, double beta, const double* __restrict__ z,
+                                                  double* __restrict__ p) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; k < m;
+         k += static_cast<int64_t>(gridDim.x) * kRB)
+        p[k] = z[k] + beta * p[k];
+}
+
+__global__ __launch_bounds__(kRB) void k_mul(int64_t m, const double* __restrict__ a, const double* __restrict__ b,
+                                             double* __restrict__ out) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; k < m;
+         k += static_cast<int64_t>(gridDim.x) * kRB)
+        out[k] = a[k] * b[k];
+}
+
 __global__ __launch_bounds__(kRB) void k_scale(int64_t n, double* __restrict__ v, double s) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * kRB)
@@ -520,6 +580,39 @@ hipError_t launch_spgemm_masked(hipStream_t st, int64_t nr, int64_t nnz, const i
 hipError_t launch_scale(hipStream_t st, int64_t n, double* v, double s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(kRB), 0, st, n, v, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_emin_project(hipStream_t st, int64_t n, const int32_t* rp, const int8_t* cf, const double* v,
+                               double sign, double* out) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emin_project, dim3(grid_for(n)), dim3(kRB), 0, st, n, rp, cf, v, sign, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_emin_dinv(hipStream_t st, int64_t n, const int32_t* arp, const int32_t* aci, const double* av,
+                            const int32_t* prp, double* dinv) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emin_dinv, dim3(grid_for(n)), dim3(kRB), 0, st, n, arp, aci, av, prp, dinv);
+    return hipGetLastError();
+}
+
+hipError_t launch_emin_step(hipStream_t st, int64_t m, double alpha, const double* p, const double* q,
+                            const double* dinv, double* w, double* r, double* z) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emin_step, dim3(grid_for(m)), dim3(kRB), 0, st, m, alpha, p, q, dinv, w, r, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_emin_dir(hipStream_t st, int64_t m, double beta, const double* z, double* p) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emin_dir, dim3(grid_for(m)), dim3(kRB), 0, st, m, beta, z, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_mul(hipStream_t st, int64_t m, const double* a, const double* b, double* out) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mul, dim3(grid_for(m)), dim3(kRB), 0, st, m, a, b, out);
     return hipGetLastError();
 }
 

@@ -62,6 +62,21 @@ hipError_t launch_dense_inverse(hipStream_t st, int64_t n, int S, const int32_t*
 // out (S * n rows of ld floats) = X (S * n rows of n doubles), padding zero
 hipError_t launch_dense_to_f32(hipStream_t st, int S, int64_t n, int64_t ld, const double* X, float* out);
 
+// energy minimisation of an interpolation P (n rows; cf: C rows are unit rows, left alone):
+// out = sign * (v - row mean of v) on F rows, 0 on C rows
+hipError_t launch_emin_project(hipStream_t st, int64_t n, const int32_t* rp, const int8_t* cf, const double* v,
+                               double sign, double* out);
+// dinv[k] = 1 / a_ii for the entries k of row i of P
+hipError_t launch_emin_dinv(hipStream_t st, int64_t n, const int32_t* arp, const int32_t* aci, const double* av,
+                            const int32_t* prp, double* dinv);
+// w += alpha p, r -= alpha q, z = dinv r (m entries)
+hipError_t launch_emin_step(hipStream_t st, int64_t m, double alpha, const double* p, const double* q,
+                            const double* dinv, double* w, double* r, double* z);
+// p = z + beta p
+hipError_t launch_emin_dir(hipStream_t st, int64_t m, double beta, const double* z, double* p);
+// out = a * b elementwise
+hipError_t launch_mul(hipStream_t st, int64_t m, const double* a, const double* b, double* out);
+
 // finite-volume values on the device: T per face, the diagonal per base cell,
 // then val[p] = slot[p] >= 0 ? -T[slot[p]] : diag[-slot[p] - 1]
 hipError_t launch_fv_values(hipStream_t st, int64_t nf, int64_t nb, int64_t nnz, const int64_t* ca, const int64_t* cb,

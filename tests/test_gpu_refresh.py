@@ -89,15 +89,17 @@ def _same(s1, s2, tol):
         assert abs(e1["omega"] - e2["omega"]) <= 1e-10 * max(abs(e2["omega"]), 1e-300)
 
 
-@pytest.mark.parametrize("pc,k", [("amgr", 0), ("amgr_sub", 0), ("amgr", 4), ("amgr_sub", 4)])
-def test_refresh_with_the_setup_values_reproduces_the_setup(pc, k):
+@pytest.mark.parametrize("pc,k,f3", [("amgr", 0, False), ("amgr_sub", 0, False), ("amgr", 4, False),
+                                     ("amgr_sub", 4, False), ("amgr_sub", 4, True)])
+def test_refresh_with_the_setup_values_reproduces_the_setup(pc, k, f3):
     """The re-setup from the setup matrix's own values gives the setup's
-    hierarchy again, and the solve afterwards takes the same iterations."""
+    hierarchy again, and the solve afterwards takes the same iterations (also
+    with adaptive FSAI patterns and energy minimisation)."""
     torch = _torch()
     from paper_2407_05930_amd import Solver
-    _say("refresh same values", pc, k)
+    _say("refresh same values", pc, k, f3)
     p = make_problem((24, 20, 16), s=3, m=2, seed=31, y_stretch=1.5, kappa="lognormal")
-    opt = dict(coarse_max=48)
+    opt = dict(coarse_max=48, **(dict(afsai_nnz=5, emin_steps=4) if f3 else {}))
     sv = Solver(p.A, p.img, tol=TOL, pc=pc, k=k, **opt)
     nlev = sv.num_levels()
     S = 8 if pc == "amgr_sub" else 0

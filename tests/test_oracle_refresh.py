@@ -28,10 +28,17 @@ def _equal_hier(H1, H2):
     assert np.array_equal(H1.coarse_factor[0], H2.coarse_factor[0])
 
 
-@pytest.mark.parametrize("precond,k", [("amgr", 0), ("amgr_sub", 0), ("amgr_sub", 4)])
-def test_refresh_with_the_same_matrix_is_the_setup(precond, k):
+F3 = amg.AMGOptions(coarse_max=40, afsai_nnz=5, emin_steps=4)
+
+
+@pytest.mark.parametrize("precond,k,opt", [("amgr", 0, OPT), ("amgr_sub", 0, OPT), ("amgr_sub", 4, OPT),
+                                           ("amgr", 0, F3), ("amgr_sub", 4, F3)])
+def test_refresh_with_the_same_matrix_is_the_setup(precond, k, opt):
+    """With adaptive FSAI and energy minimisation too: the kept adaptive
+    patterns are the ones the setup chose, and the minimisation repeats the
+    setup's steps from the same start."""
     p = make_problem((16, 14, 12), s=2, seed=3, y_stretch=1.5, kappa="lognormal")
-    ctx = krylov.setup(p.A, p.img, OPT, precond=precond, k=k)
+    ctx = krylov.setup(p.A, p.img, opt, precond=precond, k=k)
     new = refresh.refresh(ctx, p.A)
     _equal_hier(new["hier"], ctx["hier"])
     if ctx["sub"] is not None:
@@ -42,11 +49,14 @@ def test_refresh_with_the_same_matrix_is_the_setup(precond, k):
             assert np.array_equal(r1, r2)
 
 
-def test_refresh_of_a_scaled_matrix_is_its_fresh_setup():
+@pytest.mark.parametrize("opt", [OPT, F3])
+def test_refresh_of_a_scaled_matrix_is_its_fresh_setup(opt):
+    """Scaling by 2 is exact: the adaptive FSAI scores and the energy
+    minimisation's gradients double, its step lengths do not change."""
     p = make_problem((14, 12, 10), s=1, seed=4, jitter=0.2, kappa="lognormal")
-    ctx = krylov.setup(p.A, p.img, OPT, precond="amgr_sub")
+    ctx = krylov.setup(p.A, p.img, opt, precond="amgr_sub")
     A2 = (2.0 * p.A).tocsr()
-    fresh = krylov.setup(A2, p.img, OPT, precond="amgr_sub")
+    fresh = krylov.setup(A2, p.img, opt, precond="amgr_sub")
     new = refresh.refresh(ctx, A2)
     _equal_hier(new["hier"], fresh["hier"])
     for S1, S2 in zip(new["sub"].subs, fresh["sub"].subs):
