@@ -212,7 +212,7 @@ def bench_jitter(args, torch, np):
         sv.close()
     return {"metric": "solve time to 1e-10 rel-res, 192^3 jittered s=3, k=16", "value": out["mixed_bf16g"]["solve_s"],
             "unit": "s", "higher_is_better": False, "dtype": "f64+f32+bf16",
-            "config": {"workload": "jitter3d_192_s3", "grid": list(p.N), "s": 3, "rhs": 1, "lrc_k": args.k,
+            "config": {"workload": "jitter3d_192_s3", "afsai_nnz": args.afsai, "emin_steps": args.emin, "grid": list(p.N), "s": 3, "rhs": 1, "lrc_k": args.k,
                        "unknowns": int(p.n), "preconditioner": args.pc}, "variants": out}
 
 
@@ -324,7 +324,7 @@ def bench_copies(args, torch, np):
     return {"metric": "solve time to 1e-10 rel-res, 8 translated copies of 64^3 with differing walls, 4 RHS",
             "value": out["mixed_bf16"]["solve_s"], "unit": "s", "higher_is_better": False,
             "dtype": "f64+f32+bf16",
-            "config": {"workload": "copies3d_8x64", "copy_grid": [64, 64, 64], "copies": 8, "rhs": 4,
+            "config": {"workload": "copies3d_8x64", "afsai_nnz": args.afsai, "emin_steps": args.emin, "copy_grid": [64, 64, 64], "copies": 8, "rhs": 4,
                        "unknowns": int(p.n), "preconditioner": "amgr (original basis, populated interface)",
                        "interface_fraction": round(float(iface.mean()), 4),
                        "levels": int(st.nlev), "op_complexity": round(st.op_complexity, 3)},
@@ -419,7 +419,7 @@ def bench_batch(args, torch, np):
         sv.close()
     return {"metric": "batched solve time to 1e-10 rel-res, 64 uneven systems", "value": head["solve_s"], "unit": "s",
             "higher_is_better": False, "dtype": "f64+f32",
-            "config": {"workload": "batch64", "systems": len(probs), "unknowns": int(sum(pr.n for pr in probs)),
+            "config": {"workload": "batch64", "afsai_nnz": args.afsai, "emin_steps": args.emin, "systems": len(probs), "unknowns": int(sum(pr.n for pr in probs)),
                        "rhs_total": int(sum(pr.b.shape[1] for pr in probs)), "preconditioner": args.pc,
                        "precision": PRECISION_NOTE["mixed"]},
             **{k: v for k, v in head.items() if k != "solve_s"},
@@ -507,7 +507,7 @@ def bench_adjoint(args, torch, np):
                "note": "device_first_s includes building the position map and the re-setup's device structure"}
     return {"metric": "forward + adjoint solve time, 256^3 s=3 lognormal kappa", "value": round(t, 6), "unit": "s",
             "higher_is_better": False, "dtype": "f64",
-            "config": {"workload": "adjoint3d_256_s3", "grid": list(pr.N), "s": 3, "unknowns": int(pr.n),
+            "config": {"workload": "adjoint3d_256_s3", "afsai_nnz": args.afsai, "emin_steps": args.emin, "grid": list(pr.N), "s": 3, "unknowns": int(pr.n),
                        "preconditioner": args.pc},
             "iters": its_host, "setup_s": round(t_setup, 2), "loss": loss_host,
             "grad_kappa_norm": gk_host, "grad_f_norm": float(fr.grad.norm().item()), "resetup": resetup}
@@ -526,6 +526,11 @@ def main():
     ap.add_argument("--mixed", default="mixed_bf16", choices=["mixed", "mixed_bf16"],
                     help="mixed-precision variant of the headline: V-cycle multivectors in bfloat16 (default) or "
                          "FP32; the other one is timed beside it")
+    ap.add_argument("--afsai", type=int, default=5,
+                    help="adaptive FSAI smoothers with at most this many entries per row, as in the paper's "
+                         "experiments (0: static FSAI on the strong lower pattern)")
+    ap.add_argument("--emin", type=int, default=4,
+                    help="energy-minimisation steps on every interpolation (0: none)")
     ap.add_argument("--trunc0", type=float, default=None,
                     help="reduction-level interpolation truncation (library default when omitted)")
     ap.add_argument("--no-compare", action="store_true",
@@ -549,7 +554,9 @@ def main():
     from paper_2407_05930_amd import Solver
 
     rank = int(os.environ.get("RANK", "0"))
-    extra = {} if args.trunc0 is None else {"trunc0": args.trunc0}
+    extra = {"afsai_nnz": args.afsai, "emin_steps": args.emin}
+    if args.trunc0 is not None:
+        extra["trunc0"] = args.trunc0
     args.extra = extra
     other = {"jitter3d_192_s3": bench_jitter, "batch64": bench_batch, "adjoint3d_256_s3": bench_adjoint,
              "copies3d_8x64": bench_copies, "amgs3d_128_s3": bench_amgs}
@@ -677,7 +684,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(p.N), "s": p.s, "rhs": int(p.b.shape[1]),
                    "subsystem_columns": int((1 << p.s) * p.b.shape[1]), "lrc_k": k, "tol": 1e-10,
-                   "preconditioner": args.pc,
+                   "preconditioner": args.pc, "afsai_nnz": args.afsai, "emin_steps": args.emin,
                    "precision": PRECISION_NOTE[head], "unknowns": int(p.n)},
         "other_mixed_variant": {"precision": PRECISION_NOTE[alt], "solve_s": round(res["alt"]["t"], 6),
                                 "iters": res["alt"]["iters"], "true_relres_max": max(res["alt"]["true_relres"]),

@@ -61,17 +61,21 @@ def _check_ritz(sv, ctx, S):
         assert kept[a] == ctx["lrc"].U[a].shape[1]
 
 
-def test_headline_workload_fp64_matches_oracle():
+@pytest.mark.parametrize("f3", [False, True], ids=["static_fsai", "afsai5_emin4"])
+def test_headline_workload_fp64_matches_oracle(f3):
     """The headline workload at its full size (128^3, y stretched, s = 3,
     4 right-hand sides: 32 columns) with the per-subsystem cycle in FP64,
-    without low-rank corrections (they change no iteration count there)."""
+    without low-rank corrections (they change no iteration count there);
+    also with the adaptive FSAI smoothers and energy-minimised interpolation
+    that the headline measurement uses."""
     _torch()
     p = config_problem("channel3d_128_s3")
-    _say("oracle setup 128^3")
-    ctx = krylov.setup(p.A, p.img, amg.AMGOptions(), precond="amgr_sub")
+    opt = dict(afsai_nnz=5, emin_steps=4) if f3 else {}
+    _say("oracle setup 128^3", opt)
+    ctx = krylov.setup(p.A, p.img, amg.AMGOptions(**opt), precond="amgr_sub")
     ref = krylov.solve(ctx, p.b, tol=TOL)
     _say("oracle iterations", int(ref.iters.max()))
-    sv, x = _solve_gpu(p, tol=TOL, pc="amgr_sub")
+    sv, x = _solve_gpu(p, tol=TOL, pc="amgr_sub", **opt)
     _say("gpu iterations", sv.last.iters)
     assert sv.num_levels() == ref.hierarchy.nlev
     assert sv.last.iters == int(ref.iters.max())
