@@ -307,3 +307,28 @@ def test_two_refreshes_then_a_new_column_count_and_exports(pc):
     sigma, _ = sv.export_outer()
     for a in range(8):
         assert np.abs(sigma[:, a] - ctx2["outs"][a].diagonal()).max() <= 1e-15 * np.abs(p2.A.data).max()
+
+
+@pytest.mark.parametrize("f3", [False, True], ids=["static_fsai", "afsai5_emin4"])
+def test_refresh_of_a_deep_hierarchy_matches_the_oracle(f3):
+    """Five or more levels (a small coarsest size): every level of every
+    subsystem after the device re-setup equals the oracle's re-setup, and so
+    do the iteration counts."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("refresh deep", f3)
+    kw = dict(y_stretch=1.5, kappa="lognormal")
+    p0 = make_problem((32, 28, 24), s=3, m=1, seed=95, **kw)
+    p1 = make_problem((32, 28, 24), s=3, m=1, seed=96, **kw)
+    opt = dict(coarse_max=12, **(dict(afsai_nnz=5, emin_steps=4) if f3 else {}))
+    ctx0 = krylov.setup(p0.A, p0.img, amg.AMGOptions(**opt), precond="amgr_sub")
+    assert ctx0["hier"].nlev >= 5
+    ctx1 = refresh.refresh(ctx0, p1.A)
+    ref = krylov.solve(ctx1, p1.b, tol=TOL)
+    sv = Solver(p0.A, p0.img, tol=TOL, pc="amgr_sub", **opt)
+    sv.refresh(torch.from_numpy(p1.A.data).cuda())
+    _check_levels(sv, ctx1["hier"], ctx1["sub"])
+    x = sv.solve(torch.from_numpy(p1.b).cuda()).cpu().numpy()
+    _say("levels", sv.num_levels(), "its gpu", sv.last.iters, "oracle", ref.iters.max())
+    assert sv.last.iters == int(ref.iters.max())
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
