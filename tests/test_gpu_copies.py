@@ -41,6 +41,10 @@ CASES = [
     dict(name="2d_repeated5_m2", N=(24, 20), copies=5, mirror=False, walls="dirichlet", m=2, opt=dict(coarse_max=40)),
     dict(name="32cube_x4_mixed_m4", N=(32, 32, 32), copies=4, mirror=False, walls="mixed", m=4, opt=dict()),
     dict(name="48cube_x4_mirrored_m2", N=(48, 48, 48), copies=4, mirror=True, walls="mixed", m=2, opt=dict()),
+    dict(name="repeated4_mixed_m3_afsai_emin", N=(8, 7, 6), copies=4, mirror=False, walls="mixed", m=3,
+         opt=dict(coarse_max=40, afsai_nnz=5, emin_steps=4)),
+    dict(name="32cube_x4_mixed_m4_afsai_emin", N=(32, 32, 32), copies=4, mirror=False, walls="mixed", m=4,
+         opt=dict(afsai_nnz=5, emin_steps=4)),
 ]
 
 

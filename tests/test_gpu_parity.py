@@ -239,15 +239,18 @@ def test_batched_systems_match_oracle_one_by_one():
     bm.close()
 
 
-def test_batch_workload_fp32_vcycle_full_size():
+@pytest.mark.parametrize("f3", [False, True], ids=["static_fsai", "afsai5_emin4"])
+def test_batch_workload_fp32_vcycle_full_size(f3):
     """The batched workload itself: 64 uneven systems (N in even 32..96,
     s in 1..3, m in 1..8) with the FP32 V-cycle and FP64 PCG in one batch:
     every system reaches a true relative residual of 1e-10, and the four
-    smallest are within 1e-7 of their FP64 oracle solutions."""
+    smallest are within 1e-7 of their FP64 oracle solutions (also with the
+    adaptive FSAI and energy minimisation the bench uses)."""
     torch = _torch()
     from paper_2407_05930_amd import BatchSolver
     probs = batch_problems(64)
-    bs = BatchSolver([(p.A, p.img) for p in probs], tol=1e-10, pc="amgr_sub", precision="mixed")
+    opt = dict(afsai_nnz=5, emin_steps=4) if f3 else {}
+    bs = BatchSolver([(p.A, p.img) for p in probs], tol=1e-10, pc="amgr_sub", precision="mixed", **opt)
     b_in = [torch.from_numpy(p.b).cuda() for p in probs]
     bs.solve(b_in)
     xs = bs.solve(b_in)
@@ -258,7 +261,7 @@ def test_batch_workload_fp32_vcycle_full_size():
     _say("batch64 worst true relres", worst)
     assert worst <= 1.5e-10
     for i in sorted(range(len(probs)), key=lambda j: probs[j].n)[:4]:
-        ctx = krylov.setup(probs[i].A, probs[i].img, amg.AMGOptions(), precond="amgr_sub")
+        ctx = krylov.setup(probs[i].A, probs[i].img, amg.AMGOptions(**opt), precond="amgr_sub")
         ref = krylov.solve(ctx, probs[i].b, tol=1e-12)
         _say("batch64 system", i, "N", probs[i].N, "s", probs[i].s)
         _agree(xh[i], ref.x, 1e-7)

@@ -17,8 +17,11 @@ CASES = [
     dict(N=(24, 20), copies=5, mirror=False, walls="dirichlet", opt=dict(coarse_max=40)),
     dict(N=(16, 12, 10), copies=3, mirror=True, walls="dirichlet", opt=dict(coarse_max=64, dist=3, jacobi0=2)),
     dict(N=(24, 20, 16), copies=4, mirror=False, walls="mixed", opt=dict()),
+    dict(N=(8, 7, 6), copies=4, mirror=False, walls="mixed", opt=dict(coarse_max=40, afsai_nnz=5, emin_steps=4)),
+    dict(N=(10, 9, 7), copies=2, mirror=True, walls="mixed", opt=dict(coarse_max=40, afsai_nnz=5, emin_steps=4)),
 ]
-IDS = ["repeated4_mixed", "mirrored2_mixed", "2d_repeated5", "mirrored3_d3", "repeated4_default"]
+IDS = ["repeated4_mixed", "mirrored2_mixed", "2d_repeated5", "mirrored3_d3", "repeated4_default",
+       "repeated4_mixed_afsai_emin", "mirrored2_mixed_afsai_emin"]
 
 
 def _setup(p, **kw):
