@@ -243,7 +243,9 @@ int msp_setup_copies(const msp_csr* A, const msp_copies* map, const msp_opts* o,
    proportional to the hierarchy's size, once).  The caller keeps symmetry
    and the block structure of the map (not checked).  MSP_ERR_UNSUPPORTED for
    MSP_PC_AMGS and MSP_MIXED_FP32_BF16G; MSP_ERR_NOT_SPD when an FSAI block of
-   the new matrix is not positive definite.  Sec. 6 names a device-side setup
+   the new matrix is not positive definite.  After any error part way the
+   context's values are invalid: solves return MSP_ERR_ARG until a re-setup
+   succeeds.  Sec. 6 names a device-side setup
    as future work; this is its numeric part. */
 int msp_refresh(msp_ctx* c, const double* d_val, void* hip_stream);
 

@@ -259,6 +259,7 @@ struct msp_ctx {
     msp::Timers tm;
     std::unique_ptr<msp::RefreshState> rf;   // numeric re-setup structure (first msp_refresh)
     bool host_stale = false;                 // host copy of the values older than the device's (msp::sync_host)
+    bool values_invalid = false;             // a re-setup failed part way: no solve until one succeeds
 
     ~msp_ctx() {
         if (on_device) {
@@ -1747,6 +1748,8 @@ struct SolvePlan {
 static int solve_device(msp_ctx* c, int m, const double* d_b, double* d_x, hipStream_t st, msp_stats* out,
                         Work* noalloc = nullptr) {
     if (!d_b || !d_x) throw Error(MSP_ERR_ARG, "need device arrays");
+    if (c->values_invalid)
+        throw Error(MSP_ERR_ARG, "the last re-setup failed: the values are invalid until msp_refresh succeeds");
     SolvePlan P(c, m, st, noalloc);
     struct SeqKeep {   // the published-flag sequence of the context's shared host buffers
         msp_ctx* c;
@@ -2973,6 +2976,7 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
     HIPCHECK(hipSetDevice(c->device));
     if (!c->rf) refresh_build(c);
     RefreshState& R = *c->rf;
+    c->values_invalid = true;   // until this re-setup completes
     const int S = 1 << c->sym.s;
     const int64_t nb = c->sym.n_b;
     HIPCHECK(hipMemsetAsync(R.err, 0, sizeof(int), st));
@@ -3073,6 +3077,7 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
         build_lrc(c);
     }
     HIPCHECK(hipDeviceSynchronize());
+    c->values_invalid = false;
 }
 
 // Host copy of every value after a device re-setup (exports, and sliced forms

@@ -218,8 +218,6 @@ __global__ __launch_bounds__(kRB) void k_fsai(int64_t n, const int32_t* __restri
     for (int p = 0; p < k; ++p) gv[gb + p] = g[p] * sc;
 }
 
-// C = A B on C's known pattern (Gustavson order: increasing k of A's row,
-// then B's row); alpha scales the result.
 // C = A B on C's kept pattern, one thread per nonzero of C: entry (i, c) sums
 // a_ik b_kc over the row of A in its order (the order in which a row-wise
 // product accumulates it), b_kc found by binary search in row k of B.  The

@@ -332,3 +332,22 @@ def test_refresh_of_a_deep_hierarchy_matches_the_oracle(f3):
     _say("levels", sv.num_levels(), "its gpu", sv.last.iters, "oracle", ref.iters.max())
     assert sv.last.iters == int(ref.iters.max())
     assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_refresh_of_a_matrix_that_is_not_positive_definite_is_refused():
+    """Negated values make every FSAI pivot non-positive: the row kernels
+    flag it and finish, and msp_refresh returns MSP_ERR_NOT_SPD."""
+    torch = _torch()
+    from paper_2407_05930_amd import MspError, Solver
+    _say("refresh not SPD")
+    p = make_problem((12, 10, 8), s=2, m=1, seed=97)
+    sv = Solver(p.A, p.img, coarse_max=32, pc="amgr_sub")
+    with pytest.raises(MspError) as e:
+        sv.refresh(torch.from_numpy(-p.A.data).cuda())
+    assert e.value.status == -7
+    with pytest.raises(MspError) as e:                # no solve on the half-updated values
+        sv.solve(torch.from_numpy(p.b).cuda())
+    assert e.value.status == -1
+    sv.refresh(torch.from_numpy(p.A.data).cuda())     # a successful re-setup makes it usable again
+    x = sv.solve(torch.from_numpy(p.b).cuda()).cpu().numpy()
+    assert np.all(krylov.true_relres(p.A, x, p.b) <= 1e-9)
