@@ -190,6 +190,11 @@ typedef struct {
     double t_vcycle_s;           /* GPU time of the V-cycle's kernels in the last solve, summed from the
                                     per-kernel event timers (msp_set_timing); -1 when none of the
                                     V-cycle timers is on */
+    int64_t split_drift;         /* after msp_refresh: the points of the reduction level whose C/F decision
+                                    a fresh setup of the new matrix would take differently (Alg. 2 redone on
+                                    the device: strength, distance-d independent set under the same
+                                    priorities); 0 when the kept structure is the fresh one. -1 before any
+                                    re-setup, for domains of copies and for d > 3 */
 } msp_stats;
 
 /* Fill *o with the defaults: FP64, AMGR, k = 0, d = 2, theta = 0.25,

@@ -112,18 +112,22 @@ class DifferentiablePoisson:
     (msp_fv_assemble_device, msp_refresh), which is much faster for the small
     kappa steps of an optimisation.  A backward for a forward whose kappa
     has since been replaced is then an error (the solver holds the new
-    values)."""
+    values).  With ``max_split_drift`` (a fraction of the base cells), a
+    device re-setup whose reduction-level split a fresh setup would change on
+    more cells than that (msp_stats.split_drift) is followed by a fresh host
+    setup for the same kappa, which restores the iteration count."""
 
-    def __init__(self, faces, img, device: int = 0, resetup: str = "host", **solver_opts):
+    def __init__(self, faces, img, device: int = 0, resetup: str = "host", max_split_drift=None, **solver_opts):
         if resetup not in ("host", "device"):
             raise ValueError("resetup must be 'host' or 'device'")
         self.op = FVOperator(faces, img, device)
         self.opts = dict(solver_opts, device=device)
         self.resetup = resetup
+        self.max_split_drift = max_split_drift
+        self.fresh_setups = 0
         self._kappa = None
         self._vals = None
         self.solver = None
-        self.version = 0
 
     def solver_for(self, kappa):
         """The solver for this kappa (rebuilt when kappa changes).  With host
@@ -134,13 +138,16 @@ class DifferentiablePoisson:
         kap = kappa.detach().to(torch.float64)
         if self._kappa is not None and self._kappa.device == kap.device and torch.equal(kap, self._kappa):
             return self.solver
+        fresh = True
         if self.resetup == "device" and self.solver is not None:
             self._vals = self.op.assemble_device(kap, out=self._vals)
             self.solver.refresh(self._vals)
-        else:
+            drift = self.solver.stats.split_drift
+            fresh = self.max_split_drift is not None and drift > self.max_split_drift * self.op.n_b
+        if fresh:
             A = self.op.assemble(kap.cpu().numpy())
             self.solver = Solver(A, self.op.img, **self.opts)
-        self.version += 1
+            self.fresh_setups += 1
         self._kappa = kap.clone()
         return self.solver
 
@@ -172,14 +179,14 @@ def _torch_function():
             p = _converged_solve(sv, f.contiguous(), "forward")
             ctx.dp = dp
             ctx.sv = sv
-            ctx.version = dp.version
+            ctx.version = sv.version
             ctx.save_for_backward(p, kappa)
             return p
 
         @staticmethod
         def backward(ctx, g):
             p, kappa = ctx.saved_tensors
-            if ctx.sv is ctx.dp.solver and ctx.dp.version != ctx.version:
+            if ctx.sv.version != ctx.version:
                 raise RuntimeError("the solver of this forward was re-set up for another kappa since: run the "
                                    "backward first, or use resetup='host'")
             lam = _converged_solve(ctx.sv, g.contiguous(), "adjoint")

@@ -174,6 +174,13 @@ struct RefreshState {
     double* sub_a1 = nullptr;                 // and A_1,a, the FSAI factors of every subsystem, interleaved
     std::vector<double*> sub_g;
     bool shared_stale = false;                // shared levels below the reduction level not recomputed yet
+    // the reduction level's split for the new values (Alg. 2 on the device), compared with the kept one
+    bool split_check = false;
+    int64_t* tmap0 = nullptr;                 // entry (i, j) of A_inn -> entry (j, i)
+    uint64_t* pri0 = nullptr;                 // priorities of the independent set
+    int8_t *smask0 = nullptr, *tmask0 = nullptr, *state0 = nullptr, *state_init = nullptr, *cf0 = nullptr;
+    int* left = nullptr;
+    unsigned long long* diff = nullptr;
     int emin_steps = 0;                       // energy minimisation of the interpolations (as the setup)
     double* em[6] = {};                       // its work vectors over P's entries
     double* gf = nullptr;                     // pc = FSAI: FSAI of A_inn and its transpose map
@@ -260,6 +267,7 @@ struct msp_ctx {
     std::unique_ptr<msp::RefreshState> rf;   // numeric re-setup structure (first msp_refresh)
     bool host_stale = false;                 // host copy of the values older than the device's (msp::sync_host)
     bool values_invalid = false;             // a re-setup failed part way: no solve until one succeeds
+    bool copies = false;                     // a domain of copies (level-0 split replicated, not Alg. 2 on A_inn)
 
     ~msp_ctx() {
         if (on_device) {
@@ -1887,6 +1895,7 @@ static std::unique_ptr<msp_ctx> setup_host(const msp_csr* A, const msp_symmap* m
         if (o->pc == MSP_PC_FSAI) c->Gf = msp::fsai_full_lower(c->sym.Ainn);
     }
     msp::fill_stats(c.get());
+    c->stats.split_drift = -1;
     return c;
 }
 
@@ -1901,6 +1910,7 @@ static std::unique_ptr<msp_ctx> setup_host_copies(const msp_csr* A, const msp_co
     c->lrc_k = o->lrc_k;
     msp::CopyParts parts = msp::extract_copies(A, map, *o);
     c->sym = std::move(parts.sym);
+    c->copies = true;
     if (o->pc == MSP_PC_AMGR) {
         c->hier = msp::build_hierarchy(c->sym.Ainn, c->sym.iface, *o, &parts.cf0);
     } else {
@@ -1909,6 +1919,7 @@ static std::unique_ptr<msp_ctx> setup_host_copies(const msp_csr* A, const msp_co
         if (o->pc == MSP_PC_FSAI) c->Gf = msp::fsai_full_lower(c->sym.Ainn);
     }
     msp::fill_stats(c.get());
+    c->stats.split_drift = -1;
     return c;
 }
 
@@ -2704,6 +2715,27 @@ static void refresh_build(msp_ctx* c) {
         if (R->ndsig) R->dsig_src = c->upload(ds.data(), R->ndsig);
     }
     R->err = c->dalloc<int>(1);
+    // Alg. 2 redone for the new values (not for a domain of copies, whose split is replicated)
+    if (cycle(c) && !c->copies && c->o.dist <= 3 && c->o.pc != MSP_PC_AMGS) {
+        const Csr& A = c->sym.Ainn;
+        const std::vector<int64_t> tm = transpose_map(A);   // A_inn's pattern is symmetric
+        R->tmap0 = c->upload(tm.data(), static_cast<int64_t>(tm.size()));
+        std::vector<uint64_t> pri(nb);
+        std::vector<int8_t> st0(nb);
+        for (int64_t i = 0; i < nb; ++i) {
+            pri[i] = splitmix64(c->o.seed ^ static_cast<uint64_t>(i));
+            st0[i] = c->sym.iface[i] ? 3 : 0;
+        }
+        R->pri0 = c->upload(pri.data(), nb);
+        R->state_init = c->upload(st0.data(), nb);
+        R->cf0 = c->upload(c->hier.lev[0].cf.data(), nb);
+        R->smask0 = c->dalloc<int8_t>(A.nnz());
+        R->tmask0 = c->dalloc<int8_t>(A.nnz());
+        R->state0 = c->dalloc<int8_t>(nb);
+        R->left = c->dalloc<int>(1);
+        R->diff = c->dalloc<unsigned long long>(1);
+        R->split_check = true;
+    }
     R->part = c->dalloc<double>(2 * R->nbp);
     R->dots = c->dalloc<double>(2);
     if (cycle(c)) {
@@ -2984,6 +3016,29 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
     HIPCHECK(launch_gather(st, c->dAinn.nnz, R.inn_src, d_val, c->dAinn.v64));
     HIPCHECK(launch_outer_sigma(st, nb, S, R.out_src, d_val, R.sigma));
     if (R.ndsig) HIPCHECK(launch_gather(st, R.ndsig, R.dsig_src, R.sigma, const_cast<double*>(c->dsig.d.val)));
+    c->stats.split_drift = -1;
+    if (R.split_check) {   // the split a fresh setup would take for these values, against the kept one
+        const DevCsr& D = c->dAinn;
+        HIPCHECK(launch_split_strength(st, nb, D.nnz, D.rp, D.ci, D.v64, c->o.theta, R.tmap0, R.smask0, R.tmask0));
+        HIPCHECK(hipMemcpyAsync(R.state0, R.state_init, nb, hipMemcpyDeviceToDevice, st));
+        bool done = false;
+        for (int round = 0; round < 4096 && !done; ++round) {
+            HIPCHECK(hipMemsetAsync(R.left, 0, sizeof(int), st));
+            HIPCHECK(launch_mis_round(st, nb, c->o.dist, D.rp, D.ci, R.tmask0, R.pri0, R.state0, R.left));
+            int left = 0;
+            HIPCHECK(hipMemcpyAsync(&left, R.left, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            done = left == 0;
+        }
+        if (done) {
+            unsigned long long diff = 0;
+            HIPCHECK(hipMemsetAsync(R.diff, 0, sizeof(diff), st));
+            HIPCHECK(launch_split_diff(st, nb, R.state0, R.cf0, R.diff));
+            HIPCHECK(hipMemcpyAsync(&diff, R.diff, sizeof(diff), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            c->stats.split_drift = static_cast<int64_t>(diff);
+        }
+    }
     if (cycle(c)) {
         const size_t L = R.lev.size();
         HIPCHECK(hipMemcpyAsync(R.lev[0].a, c->dAinn.v64, sizeof(double) * c->dAinn.nnz, hipMemcpyDeviceToDevice,

@@ -250,6 +250,100 @@ __global__ __launch_bounds__(kRB) void k_spgemm_masked(int64_t nr, int64_t nnz, 
     }
 }
 
+// Split of the reduction level that a fresh setup would take (Alg. 2): the
+// strength of connection marks entry (i, j), j != i, when -a_ij >= theta * max_{l != i}(-a_il) (no entry
+// when that maximum is <= 0); T is its symmetric closure.
+__global__ __launch_bounds__(kRB) void k_strength(int64_t n, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                  double theta, int8_t* __restrict__ smask) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRB) {
+        double mx = -INFINITY;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] != i) mx = fmax(mx, -v[k]);
+        const double thr = theta * mx;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            smask[k] = (mx > 0.0 && ci[k] != i && -v[k] >= thr) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kRB) void k_symmetric_mask(int64_t nnz, const int64_t* __restrict__ tmap,
+                                                        const int8_t* __restrict__ smask,
+                                                        int8_t* __restrict__ tmask) {
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; k < nnz;
+         k += static_cast<int64_t>(gridDim.x) * kRB)
+        tmask[k] = (smask[k] | smask[tmap[k]]) ? 1 : 0;
+}
+
+constexpr int8_t kUndecided = 0, kIn = 1, kOut = 2, kNotCandidate = 3;
+
+// Does a node y within d <= 3 hops of u (through candidates, along T) satisfy
+// pred(y)?  u itself is not visited.
+template <typename Pred>
+__device__ bool any_within(int64_t u, int d, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const int8_t* __restrict__ tmask, const int8_t* __restrict__ state, Pred pred) {
+    for (int64_t k1 = rp[u]; k1 < rp[u + 1]; ++k1) {
+        if (!tmask[k1]) continue;
+        const int32_t y1 = ci[k1];
+        if (state[y1] == kNotCandidate) continue;
+        if (y1 != u && pred(y1)) return true;
+        if (d < 2) continue;
+        for (int64_t k2 = rp[y1]; k2 < rp[y1 + 1]; ++k2) {
+            if (!tmask[k2]) continue;
+            const int32_t y2 = ci[k2];
+            if (y2 == u || state[y2] == kNotCandidate) continue;
+            if (pred(y2)) return true;
+            if (d < 3) continue;
+            for (int64_t k3 = rp[y2]; k3 < rp[y2 + 1]; ++k3) {
+                if (!tmask[k3]) continue;
+                const int32_t y3 = ci[k3];
+                if (y3 == u || state[y3] == kNotCandidate) continue;
+                if (pred(y3)) return true;
+            }
+        }
+    }
+    return false;
+}
+
+// One round: an undecided candidate joins when no candidate within d hops
+// that is not out has a higher priority (writing "in" in place is harmless:
+// in and undecided both count as not out).
+__global__ __launch_bounds__(kRB) void k_mis_select(int64_t n, int d, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const int8_t* __restrict__ tmask,
+                                                    const uint64_t* __restrict__ pri, int8_t* __restrict__ state) {
+    for (int64_t u = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * kRB) {
+        if (state[u] != kUndecided) continue;
+        const uint64_t pu = pri[u];
+        const bool beaten = any_within(u, d, rp, ci, tmask, state,
+                                       [&](int32_t y) { return state[y] != kOut && pri[y] > pu; });
+        if (!beaten) state[u] = kIn;
+    }
+}
+
+// Undecided candidates with a member within d hops leave; counts the rest.
+__global__ __launch_bounds__(kRB) void k_mis_remove(int64_t n, int d, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const int8_t* __restrict__ tmask,
+                                                    int8_t* __restrict__ state, int* __restrict__ left) {
+    for (int64_t u = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; u < n;
+         u += static_cast<int64_t>(gridDim.x) * kRB) {
+        if (state[u] != kUndecided) continue;
+        if (any_within(u, d, rp, ci, tmask, state, [&](int32_t y) { return state[y] == kIn; })) state[u] = kOut;
+        else atomicAdd(left, 1);
+    }
+}
+
+// number of points whose decision (C: member or not a candidate) differs from cf
+__global__ __launch_bounds__(kRB) void k_split_diff(int64_t n, const int8_t* __restrict__ state,
+                                                    const int8_t* __restrict__ cf,
+                                                    unsigned long long* __restrict__ count) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kRB) {
+        const int8_t c = (state[i] == kIn || state[i] == kNotCandidate) ? 1 : 0;
+        if (c != (cf[i] ? 1 : 0)) atomicAdd(count, 1ull);
+    }
+}
+
 // one wavefront per row (rows with many entries); lanes stride over the row,
 // then a butterfly sum
 __global__ __launch_bounds__(kRB) void k_spmv_wave(int64_t n, const int32_t* __restrict__ rp,
@@ -578,6 +672,29 @@ hipError_t launch_spgemm_masked(hipStream_t st, int64_t nr, int64_t nnz, const i
 hipError_t launch_scale(hipStream_t st, int64_t n, double* v, double s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(kRB), 0, st, n, v, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_strength(hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                                 const double* v, double theta, const int64_t* tmap, int8_t* smask, int8_t* tmask) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_strength, dim3(grid_for(n)), dim3(kRB), 0, st, n, rp, ci, v, theta, smask);
+    hipLaunchKernelGGL(k_symmetric_mask, dim3(grid_for(nnz)), dim3(kRB), 0, st, nnz, tmap, smask, tmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_mis_round(hipStream_t st, int64_t n, int d, const int32_t* rp, const int32_t* ci,
+                            const int8_t* tmask, const uint64_t* pri, int8_t* state, int* left) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mis_select, dim3(grid_for(n)), dim3(kRB), 0, st, n, d, rp, ci, tmask, pri, state);
+    hipLaunchKernelGGL(k_mis_remove, dim3(grid_for(n)), dim3(kRB), 0, st, n, d, rp, ci, tmask, state, left);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_diff(hipStream_t st, int64_t n, const int8_t* state, const int8_t* cf,
+                             unsigned long long* count) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_diff, dim3(grid_for(n)), dim3(kRB), 0, st, n, state, cf, count);
     return hipGetLastError();
 }
 

@@ -77,6 +77,18 @@ hipError_t launch_emin_dir(hipStream_t st, int64_t m, double beta, const double*
 // out = a * b elementwise
 hipError_t launch_mul(hipStream_t st, int64_t m, const double* a, const double* b, double* out);
 
+// Split of the reduction level for new values (Alg. 2): strength mask of every entry of A (smask) and its
+// symmetric closure (tmask; tmap: entry (i, j) -> entry (j, i))
+hipError_t launch_split_strength(hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                                 const double* v, double theta, const int64_t* tmap, int8_t* smask, int8_t* tmask);
+// one round of the distance-d (d <= 3) maximal independent set under priorities pri over the candidates
+// (state: 0 undecided, 1 in, 2 out, 3 not a candidate); *left += undecided candidates after the round
+hipError_t launch_mis_round(hipStream_t st, int64_t n, int d, const int32_t* rp, const int32_t* ci,
+                            const int8_t* tmask, const uint64_t* pri, int8_t* state, int* left);
+// *count += points whose C/F decision (in or not a candidate: C) differs from cf
+hipError_t launch_split_diff(hipStream_t st, int64_t n, const int8_t* state, const int8_t* cf,
+                             unsigned long long* count);
+
 // finite-volume values on the device: T per face, the diagonal per base cell,
 // then val[p] = slot[p] >= 0 ? -T[slot[p]] : diag[-slot[p] - 1]
 hipError_t launch_fv_values(hipStream_t st, int64_t nf, int64_t nb, int64_t nnz, const int64_t* ca, const int64_t* cb,

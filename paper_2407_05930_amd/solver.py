@@ -77,6 +77,7 @@ class Solver:
         check(lib.msp_setup(ctypes.byref(csr), ctypes.byref(smap), ctypes.byref(self.opts),
                             ctypes.byref(self._ctx)))
         self.last = _lib.msp_stats()
+        self.version = 0   # incremented by every refresh
 
     @classmethod
     def from_copies(cls, A, sub, **opts):
@@ -97,6 +98,7 @@ class Solver:
         check(lib.msp_setup_copies(ctypes.byref(csr), ctypes.byref(cmap), ctypes.byref(self.opts),
                                    ctypes.byref(self._ctx)))
         self.last = _lib.msp_stats()
+        self.version = 0   # incremented by every refresh
         return self
 
     def refresh(self, values, stream=None):
@@ -110,6 +112,7 @@ class Solver:
         if values.dtype != torch.float64 or not values.is_cuda or not values.is_contiguous():
             raise ValueError("values must be a contiguous float64 CUDA tensor")
         st = stream if stream is not None else torch.cuda.current_stream(values.device)
+        self.version += 1
         check(lib.msp_refresh(self._ctx, ctypes.c_void_p(values.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
 
     # ------------------------------------------------------------------ solves

@@ -152,3 +152,31 @@ def test_device_resetup_in_an_optimisation_loop_matches_the_oracle():
     dp(f, torch.from_numpy(kv * 1.5).cuda())           # replaces the solver's values
     with pytest.raises(RuntimeError, match="re-set up"):
         loss_a.backward()
+
+
+def test_device_resetup_falls_back_to_a_fresh_setup_when_the_split_moves():
+    """max_split_drift = 0: a kappa step that moves the reduction level's split
+    (reported by the device re-setup) gets a fresh host setup instead, and
+    its loss and gradient are those of the oracle."""
+    torch = _torch()
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    pr = make_problem((24, 20, 16), s=3, m=1, seed=18, kappa="lognormal", y_stretch=1.5, with_target=True)
+    pstar = pr.p_target[:, None]
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-13, coarse_max=48, resetup="device", max_split_drift=0.0)
+    f = torch.from_numpy(pr.b).cuda()
+    pst = torch.from_numpy(pstar).cuda()
+    k0 = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
+    loss0 = 0.5 * ((dp(f, k0) - pst) ** 2).sum()      # a graph recorded with the first solver
+    first = dp.solver
+    assert dp.fresh_setups == 1
+    k1 = pr.kappa_base * np.exp(0.5 * np.random.default_rng(4).standard_normal(pr.n_b))
+    kap = torch.from_numpy(k1).cuda().requires_grad_(True)
+    loss = 0.5 * ((dp(f, kap) - pst) ** 2).sum()
+    assert first.stats.split_drift > 0
+    assert dp.fresh_setups == 2 and dp.solver is not first
+    loss.backward()
+    L, lam, g, p_ref = adjoint.loss_and_gradients(pr.faces, pr.img, k1, pr.b, pstar)
+    assert abs(loss.item() - L) <= 1e-9 * abs(L)
+    assert np.linalg.norm(kap.grad.cpu().numpy() - g) <= 1e-9 * np.linalg.norm(g)
+    with pytest.raises(RuntimeError, match="re-set up"):   # the first solver holds the new values now
+        loss0.backward()

@@ -351,3 +351,53 @@ def test_refresh_of_a_matrix_that_is_not_positive_definite_is_refused():
     sv.refresh(torch.from_numpy(p.A.data).cuda())     # a successful re-setup makes it usable again
     x = sv.solve(torch.from_numpy(p.b).cuda()).cpu().numpy()
     assert np.all(krylov.true_relres(p.A, x, p.b) <= 1e-9)
+
+
+# "moves": the new kappa changes the split (True), leaves it (False), or either
+# (None: on the uniform grid the lognormal kappa leaves every connection strong,
+# and at distance 1 this draw moves no decision)
+SPLIT_CASES = [
+    dict(name="s3_d2", N=(24, 20, 16), s=3, kw=dict(y_stretch=1.5), dist=2, moves=True),
+    dict(name="s2_d3_jitter", N=(28, 24, 20), s=2, kw=dict(jitter=0.2), dist=3, moves=True),
+    dict(name="s3_d1_jitter", N=(20, 16, 16), s=3, kw=dict(jitter=0.2), dist=1, moves=None),
+    dict(name="2d_s1_d2", N=(64, 48), s=1, kw=dict(), dist=2, moves=None),
+]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=[c["name"] for c in SPLIT_CASES])
+def test_refresh_reports_how_far_the_kept_split_is_from_a_fresh_one(case):
+    """msp_stats.split_drift: the device redoes Alg. 2 for the new values
+    (strength, distance-d independent set under the setup's priorities) and
+    counts the points whose C/F decision differs from the kept split.  Zero
+    for the setup values and for 2A; for a new kappa exactly the points where
+    a fresh host setup's split differs."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("split drift", case["name"])
+    kw = dict(case["kw"], kappa="lognormal")
+    p0 = make_problem(case["N"], s=case["s"], m=1, seed=98, **kw)
+    p1 = make_problem(case["N"], s=case["s"], m=1, seed=99, **kw)
+    opt = dict(coarse_max=48, dist=case["dist"])
+    sv = Solver(p0.A, p0.img, pc="amgr_sub", **opt)
+    assert sv.stats.split_drift == -1
+    sv.refresh(torch.from_numpy(p0.A.data).cuda())
+    assert sv.stats.split_drift == 0
+    sv.refresh(torch.from_numpy(2.0 * p0.A.data).cuda())
+    assert sv.stats.split_drift == 0
+    sv.refresh(torch.from_numpy(p1.A.data).cuda())
+    fresh = Solver(p1.A, p1.img, device=-1, pc="amgr_sub", **opt)
+    want = int(np.sum(fresh.export_level(0)["cf"] != sv.export_level(0)["cf"]))
+    _say("drift", sv.stats.split_drift, "fresh host split differs at", want, "of", p1.n_b)
+    assert sv.stats.split_drift == want
+    if case["moves"] is not None:
+        assert (want > 0) == case["moves"]
+
+
+def test_split_drift_is_not_reported_for_domains_of_copies():
+    torch = _torch()
+    from gen import make_repeated_problem
+    from paper_2407_05930_amd import Solver
+    p = make_repeated_problem((8, 7, 6), 3, m=1, seed=100, walls="mixed")
+    sv = Solver.from_copies(p.A, p.sub, coarse_max=40)
+    sv.refresh(torch.from_numpy(p.A.data).cuda())
+    assert sv.stats.split_drift == -1
