@@ -112,19 +112,28 @@ class DifferentiablePoisson:
     (msp_fv_assemble_device, msp_refresh), which is much faster for the small
     kappa steps of an optimisation.  A backward for a forward whose kappa
     has since been replaced is then an error (the solver holds the new
-    values).  With ``max_split_drift`` (a fraction of the base cells), a
-    device re-setup whose reduction-level split a fresh setup would change on
-    more cells than that (msp_stats.split_drift) is followed by a fresh host
-    setup for the same kappa, which restores the iteration count."""
+    values).  Two policies bound what the kept structure costs:
+    ``max_split_drift`` (a fraction of the base cells): a device re-setup
+    whose reduction-level split a fresh setup would change on more cells than
+    that (msp_stats.split_drift) is followed at once by a fresh host setup for
+    the same kappa; ``max_iteration_growth`` (a ratio): once a solve on a
+    re-set-up solver takes more than that times the iterations of the first
+    solve after the last fresh setup, the next kappa gets a fresh host setup
+    (the coarser levels and the kept interpolation patterns can cost
+    iterations while the reduction level's split stays)."""
 
-    def __init__(self, faces, img, device: int = 0, resetup: str = "host", max_split_drift=None, **solver_opts):
+    def __init__(self, faces, img, device: int = 0, resetup: str = "host", max_split_drift=None,
+                 max_iteration_growth=None, **solver_opts):
         if resetup not in ("host", "device"):
             raise ValueError("resetup must be 'host' or 'device'")
         self.op = FVOperator(faces, img, device)
         self.opts = dict(solver_opts, device=device)
         self.resetup = resetup
         self.max_split_drift = max_split_drift
+        self.max_iteration_growth = max_iteration_growth
         self.fresh_setups = 0
+        self._fresh_iters = None   # iterations of the first solve after the last fresh setup
+        self._grown = False
         self._kappa = None
         self._vals = None
         self.solver = None
@@ -139,7 +148,7 @@ class DifferentiablePoisson:
         if self._kappa is not None and self._kappa.device == kap.device and torch.equal(kap, self._kappa):
             return self.solver
         fresh = True
-        if self.resetup == "device" and self.solver is not None:
+        if self.resetup == "device" and self.solver is not None and not self._grown:
             self._vals = self.op.assemble_device(kap, out=self._vals)
             self.solver.refresh(self._vals)
             drift = self.solver.stats.split_drift
@@ -148,11 +157,24 @@ class DifferentiablePoisson:
             A = self.op.assemble(kap.cpu().numpy())
             self.solver = Solver(A, self.op.img, **self.opts)
             self.fresh_setups += 1
+            self._fresh_iters = None
+            self._grown = False
         self._kappa = kap.clone()
         return self.solver
 
     def __call__(self, f, kappa):
         return PoissonSolve.apply(f, kappa, self)
+
+    def _observe(self, sv):
+        """Iteration count of a solve with the current solver (the growth policy)."""
+        if sv is not self.solver:
+            return
+        its = sv.last.iters
+        if self._fresh_iters is None and sv.version == 0:
+            self._fresh_iters = its
+        elif (self.max_iteration_growth is not None and self._fresh_iters is not None and sv.version > 0
+              and its > self.max_iteration_growth * self._fresh_iters):
+            self._grown = True
 
 
 def _converged_solve(sv, rhs, what):
@@ -177,6 +199,7 @@ def _torch_function():
         def forward(ctx, f, kappa, dp):
             sv = dp.solver_for(kappa)
             p = _converged_solve(sv, f.contiguous(), "forward")
+            dp._observe(sv)
             ctx.dp = dp
             ctx.sv = sv
             ctx.version = sv.version

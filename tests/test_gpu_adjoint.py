@@ -180,3 +180,31 @@ def test_device_resetup_falls_back_to_a_fresh_setup_when_the_split_moves():
     assert np.linalg.norm(kap.grad.cpu().numpy() - g) <= 1e-9 * np.linalg.norm(g)
     with pytest.raises(RuntimeError, match="re-set up"):   # the first solver holds the new values now
         loss0.backward()
+
+
+def test_device_resetup_falls_back_when_the_iterations_grow():
+    """max_iteration_growth: once a solve on a re-set-up solver takes more
+    than the ratio times the iterations after the last fresh setup, the next
+    kappa gets a fresh host setup (ratio 0.5 forces it here), and the
+    gradients stay the oracle's."""
+    torch = _torch()
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    pr = make_problem((20, 16, 16), s=3, m=1, seed=19, kappa="lognormal", with_target=True)
+    pstar = pr.p_target[:, None]
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-13, coarse_max=48, resetup="device",
+                               max_iteration_growth=0.5)
+    f = torch.from_numpy(pr.b).cuda()
+    pst = torch.from_numpy(pstar).cuda()
+    rng = np.random.default_rng(6)
+    kv = pr.kappa_base.copy()
+    setups = []
+    for step in range(4):
+        kap = torch.from_numpy(kv).cuda().requires_grad_(True)
+        loss = 0.5 * ((dp(f, kap) - pst) ** 2).sum()
+        loss.backward()
+        setups.append(dp.fresh_setups)
+        L, lam, g, _ = adjoint.loss_and_gradients(pr.faces, pr.img, kv, pr.b, pstar)
+        assert np.linalg.norm(kap.grad.cpu().numpy() - g) <= 1e-9 * np.linalg.norm(g)
+        kv = kv * np.exp(0.1 * rng.standard_normal(pr.n_b))
+    # fresh, re-set up (grows past 0.5x), fresh, re-set up
+    assert setups == [1, 1, 2, 2], setups
