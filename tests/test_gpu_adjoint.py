@@ -208,3 +208,38 @@ def test_device_resetup_falls_back_when_the_iterations_grow():
         kv = kv * np.exp(0.1 * rng.standard_normal(pr.n_b))
     # fresh, re-set up (grows past 0.5x), fresh, re-set up
     assert setups == [1, 1, 2, 2], setups
+
+
+def test_full_size_adjoint_directional_derivative():
+    """The adjoint workload at its full size (256^3, s = 3, lognormal kappa)
+    in the bench's configuration: forward and adjoint solves reach a true
+    relative residual of 1e-10, and dL/dkappa along a random direction d
+    equals the central difference (L(kappa + h d) - L(kappa - h d)) / 2h of
+    two more forward solves (after device re-setups) to 1e-5."""
+    torch = _torch()
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    pr = config_problem("adjoint3d_256_s3", assemble=False)
+    print("256^3 adjoint: setup", flush=True)
+    # the perturbed losses use the device re-setup: the solves reach 1e-12 whatever the preconditioner
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-12, pc="amgr_sub", afsai_nnz=5, emin_steps=4,
+                               resetup="device")
+    f = torch.from_numpy(pr.b).cuda()
+    pst = torch.from_numpy(pr.p_target[:, None]).cuda()
+    kap = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
+    p = dp(f, kap)
+    loss = 0.5 * ((p - pst) ** 2).sum()
+    loss.backward()
+    g = kap.grad.detach()
+    print("256^3 adjoint: iterations", dp.solver.last.iters, flush=True)
+    d = torch.from_numpy(np.random.default_rng(9).standard_normal(pr.n_b)).cuda() * kap.detach()
+    h = 1e-4
+
+    def loss_at(t):
+        with torch.no_grad():
+            q = dp(f, kap.detach() + t * d)
+            return 0.5 * float(((q - pst) ** 2).sum())
+
+    fd = (loss_at(h) - loss_at(-h)) / (2 * h)
+    an = float((g * d).sum())
+    print("256^3 adjoint: directional derivative", an, "central difference", fd, flush=True)
+    assert abs(fd - an) <= 1e-5 * abs(an)

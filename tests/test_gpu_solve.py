@@ -365,7 +365,8 @@ def test_full_size_channel_bf16_multivectors():
 
 def test_full_size_jitter_config_properties():
     """192^3 jittered octant with lognormal kappa, s = 3, k = 16 (the jittered
-    workload at its full size, in the configuration the bench times): the
+    workload at its full size, in the configuration the bench times: adaptive
+    FSAI and energy-minimised interpolation): the
     FP64 and the bfloat16-multivector solves reach a true relative residual of
     1e-10; the bfloat16 one in at most 10% (plus one) more iterations, and
     both solutions agree to 1e-9 (the tolerance times the condition growth of
@@ -377,7 +378,7 @@ def test_full_size_jitter_config_properties():
     out = {}
     for prec in ("fp64", "mixed_bf16"):
         _say("192^3 jittered", prec)
-        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, pc="amgr_sub", k=16)
+        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, pc="amgr_sub", k=16, afsai_nnz=5, emin_steps=4)
         x = sv.solve(b).cpu().numpy()
         rr = krylov.true_relres(p.A, x, p.b)
         out[prec] = (x, sv.last.iters)
