@@ -267,6 +267,7 @@ def headline_resetup(args, torch, np, p, svm, k):
         torch.cuda.synchronize()
         t_rs.append(time.perf_counter() - t0)
     drift = int(svm.stats.split_drift)
+    drift1 = int(svm.stats.split_drift1)
     t_solve, x = timed_solves(svm, bk, args.steps, args.warmup, torch)
     xs = x.cpu().numpy()
     rr = float(np.max(np.linalg.norm(pk.b - pk.A @ xs, axis=0) / np.linalg.norm(pk.b, axis=0)))
@@ -277,6 +278,7 @@ def headline_resetup(args, torch, np, p, svm, k):
            "host_setup_s": round(fresh.stats.t_setup_s, 3),
            "solve_after_resetup_s": round(t_solve, 6), "iters_after_resetup": its, "true_relres_max": rr,
            "split_drift": drift, "base_cells": int(p.n_b),
+           "split_drift_level1": drift1, "level1_points": int(svm.stats.rows[1]),
            "fresh_setup_solve_s": round(t_fresh, 6), "iters_fresh_setup": fresh.last.iters,
            "kappa": "lognormal(0, 1) per cell, same mesh",
            "note": "first re-setup includes building its device structure; lrc_k corrections rebuilt each time"}
@@ -487,6 +489,7 @@ def bench_adjoint(args, torch, np):
     dp.resetup = "device"
     t_dev = []
     drift = []
+    drift1 = []
     for kk in steps_k:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -494,7 +497,9 @@ def bench_adjoint(args, torch, np):
         torch.cuda.synchronize()
         t_dev.append(time.perf_counter() - t0)
         drift.append(int(dp.solver.stats.split_drift))
-        log(f"  re-setup {t_dev[-1]:.3f} s, split drift {drift[-1]} of {pr.n_b} base cells")
+        drift1.append(int(dp.solver.stats.split_drift1))
+        log(f"  re-setup {t_dev[-1]:.3f} s, split drift {drift[-1]} of {pr.n_b} base cells, "
+            f"level 1: {drift1[-1]} of {dp.solver.stats.rows[1]}")
     # back to the first step's kappa: its gradient against the fresh setup's
     dp.solver_for(steps_k[0])
     kap1 = steps_k[0].clone().requires_grad_(True)
@@ -507,6 +512,7 @@ def bench_adjoint(args, torch, np):
                "device_s": round(sum(t_dev[1:]) / len(t_dev[1:]), 4),
                "iters_fresh_setup": its_fresh, "iters_device_resetup": its_dev,
                "split_drift_per_step": drift, "base_cells": int(pr.n_b),
+               "split_drift_level1_per_step": drift1, "level1_points": int(dp.solver.stats.rows[1]),
                "grad_kappa_rel_diff_vs_fresh_setup": g_rel,
                "kappa_step": "kappa_base * exp(0.1 z), z ~ N(0, 1) per base cell",
                "note": "device_first_s includes building the position map and the re-setup's device structure"}

@@ -195,6 +195,11 @@ typedef struct {
                                     the device: strength, distance-d independent set under the same
                                     priorities); 0 when the kept structure is the fresh one. -1 before any
                                     re-setup, for domains of copies and for d > 3 */
+    int64_t split_drift1;        /* after msp_refresh: the same count for level 1 (the standard split of
+                                    the new shared A_1: strength, distance-1 independent set with the
+                                    strong-dependant count, then the hash, as priority), against the kept
+                                    level-1 split; -1 before any re-setup and for hierarchies of fewer than
+                                    three levels */
 } msp_stats;
 
 /* Fill *o with the defaults: FP64, AMGR, k = 0, d = 2, theta = 0.25,

@@ -64,7 +64,7 @@ class msp_stats(ctypes.Structure):
                 ("op_complexity", ctypes.c_double), ("c_rat", ctypes.c_double), ("avg_nnzr", ctypes.c_double),
                 ("t_setup_s", ctypes.c_double), ("t_solve_s", ctypes.c_double),
                 ("relres_true", ctypes.c_double * 64), ("t_vcycle_s", ctypes.c_double),
-                ("split_drift", ctypes.c_int64)]
+                ("split_drift", ctypes.c_int64), ("split_drift1", ctypes.c_int64)]
 
 
 class msp_faces(ctypes.Structure):

@@ -112,24 +112,28 @@ class DifferentiablePoisson:
     (msp_fv_assemble_device, msp_refresh), which is much faster for the small
     kappa steps of an optimisation.  A backward for a forward whose kappa
     has since been replaced is then an error (the solver holds the new
-    values).  Two policies bound what the kept structure costs:
+    values).  Three policies bound what the kept structure costs:
     ``max_split_drift`` (a fraction of the base cells): a device re-setup
     whose reduction-level split a fresh setup would change on more cells than
     that (msp_stats.split_drift) is followed at once by a fresh host setup for
-    the same kappa; ``max_iteration_growth`` (a ratio): once a solve on a
+    the same kappa; ``max_split_drift1`` (a fraction of the level-1 points):
+    the same for level 1's split of the new A_1 (msp_stats.split_drift1),
+    which moves long before the reduction level's does;
+    ``max_iteration_growth`` (a ratio): once a solve on a
     re-set-up solver takes more than that times the iterations of the first
     solve after the last fresh setup, the next kappa gets a fresh host setup
     (the coarser levels and the kept interpolation patterns can cost
     iterations while the reduction level's split stays)."""
 
     def __init__(self, faces, img, device: int = 0, resetup: str = "host", max_split_drift=None,
-                 max_iteration_growth=None, **solver_opts):
+                 max_iteration_growth=None, max_split_drift1=None, **solver_opts):
         if resetup not in ("host", "device"):
             raise ValueError("resetup must be 'host' or 'device'")
         self.op = FVOperator(faces, img, device)
         self.opts = dict(solver_opts, device=device)
         self.resetup = resetup
         self.max_split_drift = max_split_drift
+        self.max_split_drift1 = max_split_drift1
         self.max_iteration_growth = max_iteration_growth
         self.fresh_setups = 0
         self._fresh_iters = None   # iterations of the first solve after the last fresh setup
@@ -151,8 +155,10 @@ class DifferentiablePoisson:
         if self.resetup == "device" and self.solver is not None and not self._grown:
             self._vals = self.op.assemble_device(kap, out=self._vals)
             self.solver.refresh(self._vals)
-            drift = self.solver.stats.split_drift
-            fresh = self.max_split_drift is not None and drift > self.max_split_drift * self.op.n_b
+            st = self.solver.stats
+            fresh = ((self.max_split_drift is not None and st.split_drift > self.max_split_drift * self.op.n_b)
+                     or (self.max_split_drift1 is not None and st.nlev > 2
+                         and st.split_drift1 > self.max_split_drift1 * st.rows[1]))
         if fresh:
             A = self.op.assemble(kap.cpu().numpy())
             self.solver = Solver(A, self.op.img, **self.opts)

@@ -151,6 +151,15 @@ struct RfLevel {
     int8_t* hasf = nullptr;
     double omega = 0.0;
 };
+struct SplitCheck {              // one level's split redone on the device for new values
+    bool on = false;
+    int d = 1;                       // independent-set distance
+    RfPat A;                         // the level's operator pattern (symmetric)
+    int64_t* tmap = nullptr;         // entry (i, j) -> entry (j, i)
+    uint64_t* pri = nullptr;         // hash priorities
+    int32_t* lam = nullptr;          // strong dependants (levels below the reduction; nullptr at level 0)
+    int8_t *smask = nullptr, *tmask = nullptr, *state = nullptr, *state_init = nullptr, *cf = nullptr;
+};
 struct RefreshState {
     int64_t* inn_src = nullptr;
     int64_t* out_src = nullptr;
@@ -174,11 +183,8 @@ struct RefreshState {
     double* sub_a1 = nullptr;                 // and A_1,a, the FSAI factors of every subsystem, interleaved
     std::vector<double*> sub_g;
     bool shared_stale = false;                // shared levels below the reduction level not recomputed yet
-    // the reduction level's split for the new values (Alg. 2 on the device), compared with the kept one
-    bool split_check = false;
-    int64_t* tmap0 = nullptr;                 // entry (i, j) of A_inn -> entry (j, i)
-    uint64_t* pri0 = nullptr;                 // priorities of the independent set
-    int8_t *smask0 = nullptr, *tmask0 = nullptr, *state0 = nullptr, *state_init = nullptr, *cf0 = nullptr;
+    // the splits of levels 0 and 1 for the new values, compared with the kept ones
+    SplitCheck sc0, sc1;
     int* left = nullptr;
     unsigned long long* diff = nullptr;
     int emin_steps = 0;                       // energy minimisation of the interpolations (as the setup)
@@ -1896,6 +1902,7 @@ static std::unique_ptr<msp_ctx> setup_host(const msp_csr* A, const msp_symmap* m
     }
     msp::fill_stats(c.get());
     c->stats.split_drift = -1;
+    c->stats.split_drift1 = -1;
     return c;
 }
 
@@ -1920,6 +1927,7 @@ static std::unique_ptr<msp_ctx> setup_host_copies(const msp_csr* A, const msp_co
     }
     msp::fill_stats(c.get());
     c->stats.split_drift = -1;
+    c->stats.split_drift1 = -1;
     return c;
 }
 
@@ -2715,26 +2723,43 @@ static void refresh_build(msp_ctx* c) {
         if (R->ndsig) R->dsig_src = c->upload(ds.data(), R->ndsig);
     }
     R->err = c->dalloc<int>(1);
-    // Alg. 2 redone for the new values (not for a domain of copies, whose split is replicated)
-    if (cycle(c) && !c->copies && c->o.dist <= 3 && c->o.pc != MSP_PC_AMGS) {
-        const Csr& A = c->sym.Ainn;
-        const std::vector<int64_t> tm = transpose_map(A);   // A_inn's pattern is symmetric
-        R->tmap0 = c->upload(tm.data(), static_cast<int64_t>(tm.size()));
-        std::vector<uint64_t> pri(nb);
-        std::vector<int8_t> st0(nb);
-        for (int64_t i = 0; i < nb; ++i) {
-            pri[i] = splitmix64(c->o.seed ^ static_cast<uint64_t>(i));
-            st0[i] = c->sym.iface[i] ? 3 : 0;
+    // Alg. 2 redone for the new values (not for a domain of copies, whose split is replicated);
+    // level 1's standard split (priorities: strong dependants, then hash) as well
+    auto make_check = [&](SplitCheck& K, const Csr& A, const RfPat& pat, int d, uint64_t lev_bits,
+                          const std::vector<int8_t>& cand, const std::vector<int8_t>& cf, bool pmis) {
+        const int64_t n = A.nr;
+        const std::vector<int64_t> tm = transpose_map(A);   // operator patterns here are symmetric
+        std::vector<uint64_t> pri(n);
+        std::vector<int8_t> st0(n);
+        for (int64_t i = 0; i < n; ++i) {
+            pri[i] = splitmix64(c->o.seed ^ lev_bits ^ static_cast<uint64_t>(i));
+            st0[i] = cand[i] ? 0 : 3;
         }
-        R->pri0 = c->upload(pri.data(), nb);
-        R->state_init = c->upload(st0.data(), nb);
-        R->cf0 = c->upload(c->hier.lev[0].cf.data(), nb);
-        R->smask0 = c->dalloc<int8_t>(A.nnz());
-        R->tmask0 = c->dalloc<int8_t>(A.nnz());
-        R->state0 = c->dalloc<int8_t>(nb);
+        K.A = pat;
+        K.d = d;
+        K.tmap = c->upload(tm.data(), static_cast<int64_t>(tm.size()));
+        K.pri = c->upload(pri.data(), n);
+        K.state_init = c->upload(st0.data(), n);
+        K.cf = c->upload(cf.data(), n);
+        K.smask = c->dalloc<int8_t>(A.nnz());
+        K.tmask = c->dalloc<int8_t>(A.nnz());
+        K.state = c->dalloc<int8_t>(n);
+        if (pmis) K.lam = c->dalloc<int32_t>(n);
+        K.on = true;
+    };
+    if (cycle(c) && c->o.pc != MSP_PC_AMGS) {
         R->left = c->dalloc<int>(1);
         R->diff = c->dalloc<unsigned long long>(1);
-        R->split_check = true;
+        if (!c->copies && c->o.dist <= 3) {
+            std::vector<int8_t> cand(nb);
+            for (int64_t i = 0; i < nb; ++i) cand[i] = c->sym.iface[i] ? 0 : 1;
+            make_check(R->sc0, c->sym.Ainn, dev_pat(c->dAinn), c->o.dist, 0, cand, c->hier.lev[0].cf, false);
+        }
+        if (c->hier.lev.size() > 2) {
+            const HostLevel& H1 = c->hier.lev[1];
+            make_check(R->sc1, H1.A, dev_pat(c->dl[1].A), 1, uint64_t(1) << 40, std::vector<int8_t>(H1.A.nr, 1),
+                       H1.cf, true);
+        }
     }
     R->part = c->dalloc<double>(2 * R->nbp);
     R->dots = c->dalloc<double>(2);
@@ -2993,6 +3018,36 @@ static void refresh_f32(hipStream_t st, DevCsr& D) {
     if (D.v32) HIPCHECK((launch_cast<float, double>(st, D.nnz * D.vs, D.v64, D.v32)));
 }
 
+// Points of a level whose C/F decision a fresh setup of these values would
+// take differently (the strength of connection, then the distance-d
+// independent set in rounds); -1 when the check is off or did not finish.
+static int64_t split_drift(RefreshState& R, SplitCheck& K, const double* v, double theta, hipStream_t st) {
+    if (!K.on) return -1;
+    const int64_t n = K.A.nr;
+    HIPCHECK(launch_split_strength(st, n, K.A.nnz, K.A.rp, K.A.ci, v, theta, K.tmap, K.smask, K.tmask));
+    if (K.lam) {
+        HIPCHECK(hipMemsetAsync(K.lam, 0, sizeof(int32_t) * n, st));
+        HIPCHECK(launch_strong_dependants(st, n, K.A.rp, K.A.ci, K.smask, K.lam));
+    }
+    HIPCHECK(hipMemcpyAsync(K.state, K.state_init, n, hipMemcpyDeviceToDevice, st));
+    for (int round = 0; round < 4096; ++round) {
+        HIPCHECK(hipMemsetAsync(R.left, 0, sizeof(int), st));
+        HIPCHECK(launch_mis_round(st, n, K.d, K.A.rp, K.A.ci, K.tmask, K.lam, K.pri, K.state, R.left));
+        int left = 0;
+        HIPCHECK(hipMemcpyAsync(&left, R.left, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        if (left == 0) {
+            unsigned long long diff = 0;
+            HIPCHECK(hipMemsetAsync(R.diff, 0, sizeof(diff), st));
+            HIPCHECK(launch_split_diff(st, n, K.state, K.cf, R.diff));
+            HIPCHECK(hipMemcpyAsync(&diff, R.diff, sizeof(diff), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            return static_cast<int64_t>(diff);
+        }
+    }
+    return -1;
+}
+
 // One shared level's values (smoother, transfers, the next level's operator).
 static void refresh_shared_level(RefreshState& R, size_t l, hipStream_t st) {
     RfLevel& F = R.lev[l];
@@ -3016,29 +3071,8 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
     HIPCHECK(launch_gather(st, c->dAinn.nnz, R.inn_src, d_val, c->dAinn.v64));
     HIPCHECK(launch_outer_sigma(st, nb, S, R.out_src, d_val, R.sigma));
     if (R.ndsig) HIPCHECK(launch_gather(st, R.ndsig, R.dsig_src, R.sigma, const_cast<double*>(c->dsig.d.val)));
-    c->stats.split_drift = -1;
-    if (R.split_check) {   // the split a fresh setup would take for these values, against the kept one
-        const DevCsr& D = c->dAinn;
-        HIPCHECK(launch_split_strength(st, nb, D.nnz, D.rp, D.ci, D.v64, c->o.theta, R.tmap0, R.smask0, R.tmask0));
-        HIPCHECK(hipMemcpyAsync(R.state0, R.state_init, nb, hipMemcpyDeviceToDevice, st));
-        bool done = false;
-        for (int round = 0; round < 4096 && !done; ++round) {
-            HIPCHECK(hipMemsetAsync(R.left, 0, sizeof(int), st));
-            HIPCHECK(launch_mis_round(st, nb, c->o.dist, D.rp, D.ci, R.tmask0, R.pri0, R.state0, R.left));
-            int left = 0;
-            HIPCHECK(hipMemcpyAsync(&left, R.left, sizeof(int), hipMemcpyDeviceToHost, st));
-            HIPCHECK(hipStreamSynchronize(st));
-            done = left == 0;
-        }
-        if (done) {
-            unsigned long long diff = 0;
-            HIPCHECK(hipMemsetAsync(R.diff, 0, sizeof(diff), st));
-            HIPCHECK(launch_split_diff(st, nb, R.state0, R.cf0, R.diff));
-            HIPCHECK(hipMemcpyAsync(&diff, R.diff, sizeof(diff), hipMemcpyDeviceToHost, st));
-            HIPCHECK(hipStreamSynchronize(st));
-            c->stats.split_drift = static_cast<int64_t>(diff);
-        }
-    }
+    c->stats.split_drift = split_drift(R, R.sc0, c->dAinn.v64, c->o.theta, st);
+    c->stats.split_drift1 = -1;
     if (cycle(c)) {
         const size_t L = R.lev.size();
         HIPCHECK(hipMemcpyAsync(R.lev[0].a, c->dAinn.v64, sizeof(double) * c->dAinn.nnz, hipMemcpyDeviceToDevice,
@@ -3060,6 +3094,9 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
             put(D.P, F.p);
             put(D.R, F.r);
         }
+        // level 1's split for the shared A_1 of these values (per-subsystem mode: before the
+        // subsystems overwrite that buffer)
+        c->stats.split_drift1 = split_drift(R, R.sc1, R.lev[1].a, c->o.theta, st);
         const int64_t nL = c->hier.lev.back().A.nr;
         if (!c->sub) {
             RfLevel& FL = R.lev[L - 1];

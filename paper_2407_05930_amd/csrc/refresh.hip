@@ -307,18 +307,35 @@ __device__ bool any_within(int64_t u, int d, const int32_t* __restrict__ rp, con
 
 // One round: an undecided candidate joins when no candidate within d hops
 // that is not out has a higher priority (writing "in" in place is harmless:
-// in and undecided both count as not out).
+// in and undecided both count as not out).  Priority: lam first (when given,
+// the number of strong dependants), then pri.
 __global__ __launch_bounds__(kRB) void k_mis_select(int64_t n, int d, const int32_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci, const int8_t* __restrict__ tmask,
-                                                    const uint64_t* __restrict__ pri, int8_t* __restrict__ state) {
+                                                    const int32_t* __restrict__ lam, const uint64_t* __restrict__ pri,
+                                                    int8_t* __restrict__ state) {
     for (int64_t u = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; u < n;
          u += static_cast<int64_t>(gridDim.x) * kRB) {
         if (state[u] != kUndecided) continue;
         const uint64_t pu = pri[u];
-        const bool beaten = any_within(u, d, rp, ci, tmask, state,
-                                       [&](int32_t y) { return state[y] != kOut && pri[y] > pu; });
+        const int32_t lu = lam ? lam[u] : 0;
+        const bool beaten = any_within(u, d, rp, ci, tmask, state, [&](int32_t y) {
+            if (state[y] == kOut) return false;
+            const int32_t ly = lam ? lam[y] : 0;
+            return ly > lu || (ly == lu && pri[y] > pu);
+        });
         if (!beaten) state[u] = kIn;
     }
+}
+
+// lam[i] = number of rows j whose strong set holds i
+__global__ __launch_bounds__(kRB) void k_strong_dependants(int64_t n, const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const int8_t* __restrict__ smask,
+                                                           int32_t* __restrict__ lam) {
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * kRB + threadIdx.x; j < n;
+         j += static_cast<int64_t>(gridDim.x) * kRB)
+        for (int64_t k = rp[j]; k < rp[j + 1]; ++k)
+            if (smask[k]) atomicAdd(&lam[ci[k]], 1);
 }
 
 // Undecided candidates with a member within d hops leave; counts the rest.
@@ -683,10 +700,17 @@ hipError_t launch_split_strength(hipStream_t st, int64_t n, int64_t nnz, const i
     return hipGetLastError();
 }
 
-hipError_t launch_mis_round(hipStream_t st, int64_t n, int d, const int32_t* rp, const int32_t* ci,
-                            const int8_t* tmask, const uint64_t* pri, int8_t* state, int* left) {
+hipError_t launch_strong_dependants(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci,
+                                   const int8_t* smask, int32_t* lam) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mis_select, dim3(grid_for(n)), dim3(kRB), 0, st, n, d, rp, ci, tmask, pri, state);
+    hipLaunchKernelGGL(k_strong_dependants, dim3(grid_for(n)), dim3(kRB), 0, st, n, rp, ci, smask, lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_mis_round(hipStream_t st, int64_t n, int d, const int32_t* rp, const int32_t* ci,
+                            const int8_t* tmask, const int32_t* lam, const uint64_t* pri, int8_t* state, int* left) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mis_select, dim3(grid_for(n)), dim3(kRB), 0, st, n, d, rp, ci, tmask, lam, pri, state);
     hipLaunchKernelGGL(k_mis_remove, dim3(grid_for(n)), dim3(kRB), 0, st, n, d, rp, ci, tmask, state, left);
     return hipGetLastError();
 }

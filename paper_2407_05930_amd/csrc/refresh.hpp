@@ -81,10 +81,14 @@ hipError_t launch_mul(hipStream_t st, int64_t m, const double* a, const double* 
 // symmetric closure (tmask; tmap: entry (i, j) -> entry (j, i))
 hipError_t launch_split_strength(hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
                                  const double* v, double theta, const int64_t* tmap, int8_t* smask, int8_t* tmask);
-// one round of the distance-d (d <= 3) maximal independent set under priorities pri over the candidates
-// (state: 0 undecided, 1 in, 2 out, 3 not a candidate); *left += undecided candidates after the round
+// one round of the distance-d (d <= 3) maximal independent set under the priorities (lam, then pri; lam may
+// be nullptr) over the candidates (state: 0 undecided, 1 in, 2 out, 3 not a candidate); *left += undecided
+// candidates after the round
 hipError_t launch_mis_round(hipStream_t st, int64_t n, int d, const int32_t* rp, const int32_t* ci,
-                            const int8_t* tmask, const uint64_t* pri, int8_t* state, int* left);
+                            const int8_t* tmask, const int32_t* lam, const uint64_t* pri, int8_t* state, int* left);
+// lam[i] += number of rows whose strong set (smask) holds i
+hipError_t launch_strong_dependants(hipStream_t st, int64_t n, const int32_t* rp, const int32_t* ci,
+                                   const int8_t* smask, int32_t* lam);
 // *count += points whose C/F decision (in or not a candidate: C) differs from cf
 hipError_t launch_split_diff(hipStream_t st, int64_t n, const int8_t* state, const int8_t* cf,
                              unsigned long long* count);

@@ -182,6 +182,32 @@ def test_device_resetup_falls_back_to_a_fresh_setup_when_the_split_moves():
         loss0.backward()
 
 
+def test_device_resetup_falls_back_when_the_level_one_split_moves():
+    """max_split_drift1 = 0 (and no bound on the reduction level): a small
+    kappa step that moves level 1's split gets a fresh host setup, with the
+    oracle's loss and gradient."""
+    torch = _torch()
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    pr = make_problem((24, 20, 16), s=3, m=1, seed=21, kappa="lognormal", y_stretch=1.5, with_target=True)
+    pstar = pr.p_target[:, None]
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-13, coarse_max=48, resetup="device", max_split_drift1=0.0)
+    f = torch.from_numpy(pr.b).cuda()
+    pst = torch.from_numpy(pstar).cuda()
+    dp(f, torch.from_numpy(pr.kappa_base).cuda())
+    first = dp.solver
+    assert dp.fresh_setups == 1 and first.num_levels() >= 3
+    k1 = pr.kappa_base * np.exp(0.05 * np.random.default_rng(7).standard_normal(pr.n_b))
+    kap = torch.from_numpy(k1).cuda().requires_grad_(True)
+    loss = 0.5 * ((dp(f, kap) - pst) ** 2).sum()
+    print("drift", first.stats.split_drift, "level 1", first.stats.split_drift1, flush=True)
+    assert first.stats.split_drift1 > 0
+    assert dp.fresh_setups == 2 and dp.solver is not first
+    loss.backward()
+    L, lam, g, _ = adjoint.loss_and_gradients(pr.faces, pr.img, k1, pr.b, pstar)
+    assert abs(loss.item() - L) <= 1e-9 * abs(L)
+    assert np.linalg.norm(kap.grad.cpu().numpy() - g) <= 1e-9 * np.linalg.norm(g)
+
+
 def test_device_resetup_falls_back_when_the_iterations_grow():
     """max_iteration_growth: once a solve on a re-set-up solver takes more
     than the ratio times the iterations after the last fresh setup, the next

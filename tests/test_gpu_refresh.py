@@ -393,6 +393,51 @@ def test_refresh_reports_how_far_the_kept_split_is_from_a_fresh_one(case):
         assert (want > 0) == case["moves"]
 
 
+@pytest.mark.parametrize("pc", ["amgr", "amgr_sub"])
+@pytest.mark.parametrize("f3", [False, True], ids=["static", "afsai_emin"])
+def test_refresh_reports_the_level_one_split_drift(pc, f3):
+    """msp_stats.split_drift1: the device redoes the standard split of the
+    new shared A_1 (strength, distance-1 independent set with the number of
+    strong dependants, then the hash, as priority) and counts the points
+    whose decision differs from the kept level-1 split; the count must equal
+    the oracle's standard coarsening of the exported A_1 against the kept
+    split.  Zero for the setup values and for 2A."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("level-1 drift", pc, f3)
+    kw = dict(y_stretch=1.5, kappa="lognormal")
+    p0 = make_problem((28, 24, 20), s=2, m=1, seed=101, **kw)
+    p1 = make_problem((28, 24, 20), s=2, m=1, seed=102, **kw)
+    opt = dict(coarse_max=48)
+    if f3:
+        opt.update(afsai_nnz=5, emin_steps=4)
+    sv = Solver(p0.A, p0.img, pc=pc, **opt)
+    assert sv.num_levels() >= 3
+    assert sv.stats.split_drift1 == -1
+    sv.refresh(torch.from_numpy(p0.A.data).cuda())
+    assert sv.stats.split_drift1 == 0
+    sv.refresh(torch.from_numpy(2.0 * p0.A.data).cuda())
+    assert sv.stats.split_drift1 == 0
+    sv.refresh(torch.from_numpy(p1.A.data).cuda())
+    e1 = sv.export_level(1)
+    o = amg.AMGOptions()
+    C1 = amg.coarsen_standard(e1["A"], 1, o.theta, o.seed)
+    want = int(np.sum(C1 != e1["cf"].astype(bool)))
+    _say("level-1 drift", sv.stats.split_drift1, "oracle", want, "of", e1["A"].shape[0])
+    assert sv.stats.split_drift1 == want
+    assert want > 0
+
+
+def test_level_one_drift_is_not_reported_for_two_levels():
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    p = make_problem((12, 10, 8), s=2, m=1, seed=103)
+    sv = Solver(p.A, p.img, coarse_max=200, pc="amgr_sub")
+    assert sv.num_levels() == 2
+    sv.refresh(torch.from_numpy(p.A.data).cuda())
+    assert sv.stats.split_drift == 0 and sv.stats.split_drift1 == -1
+
+
 def test_split_drift_is_not_reported_for_domains_of_copies():
     torch = _torch()
     from gen import make_repeated_problem
