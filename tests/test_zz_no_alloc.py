@@ -96,3 +96,27 @@ def test_noalloc_solve_rejects_a_workspace_beyond_the_array():
     assert rc0 == 0
     assert np.all(krylov.true_relres(p.A, x0, p.b) <= 1.5e-10)
     sv.close()
+
+
+def test_noalloc_solve_after_a_device_resetup():
+    """After msp_refresh to a new coefficient the allocation-free solve
+    equals the ordinary one bit for bit (FP64), and after a refused
+    re-setup it refuses to solve as the ordinary call does."""
+    torch = _torch()
+    from paper_2407_05930_amd import MspError, Solver, _lib
+    lib = _lib.lib
+    kw = dict(y_stretch=1.5, kappa="lognormal")
+    p0 = make_problem((20, 16, 16), s=3, m=2, seed=54, **kw)
+    p1 = make_problem((20, 16, 16), s=3, m=2, seed=55, **kw)
+    sv = Solver(p0.A, p0.img, tol=1e-12, pc="amgr_sub", coarse_max=48, k=4)
+    sv.refresh(torch.from_numpy(p1.A.data).cuda())
+    rc0, x0, st0 = _call(lib.msp_solve_device, sv, p1.b, torch)
+    rc1, x1, st1 = _call(lib.msp_solve_device_noalloc, sv, p1.b, torch)
+    assert rc0 == 0 and rc1 == 0, lib.msp_last_error()
+    assert st1.iters == st0.iters and np.array_equal(x1, x0)
+    assert np.all(krylov.true_relres(p1.A, x1, p1.b) <= 1e-11)
+    with pytest.raises(MspError):
+        sv.refresh(torch.from_numpy(-p1.A.data).cuda())
+    rc, _, _ = _call(lib.msp_solve_device_noalloc, sv, p1.b, torch)
+    assert rc == -1
+    sv.close()
