@@ -259,6 +259,23 @@ int msp_setup_copies(const msp_csr* A, const msp_copies* map, const msp_opts* o,
    as future work; this is its numeric part. */
 int msp_refresh(msp_ctx* c, const double* d_val, void* hip_stream);
 
+/* A new context whose reduction level (level 0 of the AMGR hierarchy, Sec. 3.2:
+   the Alg. 2 split, the interpolation P = [W; I] of eq. (3.13), the smoother of
+   eq. (3.14)) is c's as it stands, values included -- after msp_refresh the
+   re-set-up ones, fetched from the device -- and whose levels below it are built
+   afresh on the host from c's level-1 operator (eq. (3.15)), as msp_setup builds
+   them: standard splits, smoother and interpolation patterns, Galerkin products,
+   per-subsystem values, coarsest inverses; then uploaded to c's device with new
+   low-rank corrections. For re-set-up contexts whose coarser splits have moved
+   (msp_stats.split_drift1) and cost iterations; it skips the reduction level's
+   split and products but repeats the rest of the host setup, per-subsystem
+   values included. c stays valid and unchanged (its values are only fetched);
+   *out owns its own memory until msp_free. AMGR and
+   per-subsystem AMGR contexts of two or more levels, domains of copies included;
+   MSP_ERR_UNSUPPORTED for other preconditioners, MSP_ERR_ARG after a failed
+   re-setup of c or for a null argument. */
+int msp_rebuild_below(msp_ctx* c, msp_ctx** out);
+
 /* Solve for m right-hand sides held in device memory (d_b, d_x: n x m
    column-major FP64, on the context's device), enqueued on hip_stream (NULL
    = the default stream).  Returns when the solve has finished.

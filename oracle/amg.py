@@ -584,10 +584,24 @@ def build_hierarchy(Ainn: sp.csr_matrix, interface: np.ndarray, opt: AMGOptions,
     operator, the last level is solved densely.  ``coarse0``: a level-0
     coarse set computed elsewhere (the populated interface of a domain of
     copies), used instead of Alg. 2 on this matrix."""
-    levels = []
     A = Ainn.tocsr()
     A.sort_indices()
-    lev = 0
+    return _levels_from([], A, 0, interface, opt, coarse0)
+
+
+def build_hierarchy_below(H: Hierarchy, opt: AMGOptions) -> Hierarchy:
+    """H's reduction level as it is (split, patterns, values), and every level
+    below it built afresh from H's level-1 operator exactly as build_hierarchy
+    builds the levels below the reduction level."""
+    if H.nlev < 2:
+        raise ValueError("no level below the reduction level")
+    return _levels_from([H.levels[0]], H.levels[1].A, 1, None, opt, None)
+
+
+def _levels_from(levels: list, A: sp.csr_matrix, lev: int, interface, opt: AMGOptions,
+                 coarse0: Optional[np.ndarray]) -> Hierarchy:
+    """The loop of build_hierarchy from level ``lev`` (operator A) down,
+    appended to ``levels``."""
     while True:
         L = Level(A=A)
         levels.append(L)

@@ -23,6 +23,11 @@ the same formulas as a fresh setup:
 For a matrix whose fresh setup makes the same structural decisions (the same
 matrix, or one scaled by a positive constant: strength, MIS and truncation
 decisions are scale invariant) the re-setup equals the fresh setup.
+
+rebuild_below keeps a context's reduction level as it stands and builds every
+level below it afresh from its level-1 operator (the remedy when the kept
+coarser splits cost iterations); when the kept reduction level is also what a
+fresh setup would build, the result is the fresh setup.
 """
 from __future__ import annotations
 
@@ -80,13 +85,35 @@ def refresh(ctx: dict, A_new: sp.csr_matrix) -> dict:
         # the subsystem levels keep the earlier setup's FSAI patterns too (a fresh
         # setup takes them from the strength of the shared values)
         sub = amg.build_sub_hierarchy(hier, sigma, opt, patterns=[L.G for L in ctx["hier"].levels])
-    low = None
-    k = 0 if ctx["lrc"] is None else max(len(r) for r in ctx["lrc"].ritz)
-    if k > 0:
-        if sub is None:
-            low = lrcmod.build_lrcamg(hier, Ainn, outs, k, opt.seed)
-        else:
-            Ahat = [(Ainn + o).tocsr() for o in outs]
-            low = lrcmod.build_lrcamg(hier, Ainn, outs, k, opt.seed,
-                                      apply_Minv=lambda a, x: amg.vcycle_sub(sub, Ahat[a], a, x))
+    low = _corrections(ctx, hier, sub, Ainn, outs)
     return dict(ctx, H=H, Ainn=Ainn, outs=outs, interface=iface, hier=hier, sub=sub, lrc=low)
+
+
+def _corrections(ctx: dict, hier, sub, Ainn, outs):
+    """LRCAMG corrections of the rank ctx was set up with, for a new hierarchy."""
+    opt = ctx["opt"]
+    k = 0 if ctx["lrc"] is None else max(len(r) for r in ctx["lrc"].ritz)
+    if k == 0:
+        return None
+    if sub is None:
+        return lrcmod.build_lrcamg(hier, Ainn, outs, k, opt.seed)
+    Ahat = [(Ainn + o).tocsr() for o in outs]
+    return lrcmod.build_lrcamg(hier, Ainn, outs, k, opt.seed,
+                               apply_Minv=lambda a, x: amg.vcycle_sub(sub, Ahat[a], a, x))
+
+
+def rebuild_below(ctx: dict) -> dict:
+    """ctx with its reduction level kept as it stands (split, patterns and
+    values) and every level below it built afresh from its level-1 operator,
+    as krylov.setup builds them: fresh standard splits, patterns and
+    per-subsystem values, then new low-rank corrections."""
+    opt, precond = ctx["opt"], ctx["precond"]
+    if precond not in ("amgr", "amgr_sub"):
+        raise ValueError(precond)
+    hier = amg.build_hierarchy_below(ctx["hier"], opt)
+    sub = None
+    if precond == "amgr_sub":
+        sigma = np.stack([o.diagonal() for o in ctx["outs"]], axis=1)
+        sub = amg.build_sub_hierarchy(hier, sigma, opt)
+    low = _corrections(ctx, hier, sub, ctx["Ainn"], ctx["outs"])
+    return dict(ctx, hier=hier, sub=sub, lrc=low)

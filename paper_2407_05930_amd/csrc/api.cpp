@@ -1931,6 +1931,32 @@ static std::unique_ptr<msp_ctx> setup_host_copies(const msp_csr* A, const msp_co
     return c;
 }
 
+// Host part of a rebuild below the reduction level: the blocks and the reduction
+// level of `old` with its current values (after a device re-setup: fetched), every
+// level below built afresh from its level-1 operator, per-subsystem values too.
+static std::unique_ptr<msp_ctx> setup_host_below(msp_ctx* old) {
+    if (old->values_invalid) throw Error(MSP_ERR_ARG, "the context's values are invalid (a re-setup failed)");
+    if (old->o.pc != MSP_PC_AMGR && old->o.pc != MSP_PC_AMGR_SUB)
+        throw Error(MSP_ERR_UNSUPPORTED, "a rebuild below the reduction level needs an AMGR context");
+    if (old->hier.lev.size() < 2) throw Error(MSP_ERR_ARG, "the hierarchy has no level below the reduction level");
+    if (old->on_device) msp::sync_host(old);
+    std::unique_ptr<msp_ctx> c(new msp_ctx());
+    c->o = old->o;
+    c->device = old->device;
+    c->lrc_k = old->lrc_k;
+    c->sym = old->sym;
+    c->copies = old->copies;
+    c->hier = msp::build_hierarchy_below(old->hier, c->o);
+    if (old->sub) {
+        c->subv = msp::build_sub_values(c->hier, c->sym.sigma, c->sym.iface, 1 << c->sym.s, c->o);
+        c->sub = true;
+    }
+    msp::fill_stats(c.get());
+    c->stats.split_drift = -1;
+    c->stats.split_drift1 = -1;
+    return c;
+}
+
 // Device part: upload and low-rank corrections.
 static void setup_device(msp_ctx* c) {
     int ndev = 0;
@@ -2167,6 +2193,21 @@ int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ct
         const auto t1 = std::chrono::steady_clock::now();
         c->stats.t_setup_s = std::chrono::duration<double>(t1 - t0).count();
         *out = c.release();
+        return MSP_OK;
+    });
+}
+
+int msp_rebuild_below(msp_ctx* c, msp_ctx** out) {
+    return guarded([&]() -> int {
+        if (!out) throw Error(MSP_ERR_ARG, "null output");
+        *out = nullptr;
+        if (!c) throw Error(MSP_ERR_ARG, "null context");
+        const auto t0 = std::chrono::steady_clock::now();
+        std::unique_ptr<msp_ctx> n = setup_host_below(c);
+        if (n->o.device >= 0) setup_device(n.get());
+        const auto t1 = std::chrono::steady_clock::now();
+        n->stats.t_setup_s = std::chrono::duration<double>(t1 - t0).count();
+        *out = n.release();
         return MSP_OK;
     });
 }

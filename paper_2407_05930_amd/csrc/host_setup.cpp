@@ -1003,11 +1003,9 @@ std::vector<int8_t> reduction_split(const Csr& A, const std::vector<int8_t>& ifa
     return reduction_split(strength(A, o.theta), A.nr, iface, o);
 }
 
-HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o,
-                              const std::vector<int8_t>* cf0) {
-    HostHierarchy H;
-    Csr A = Ainn;
-    int lev = 0;
+// Levels from `lev` down, appended to H, starting from the operator A of that level.
+static void build_levels(HostHierarchy& H, Csr A, int lev, const std::vector<int8_t>& iface, const msp_opts& o,
+                         const std::vector<int8_t>* cf0) {
     const uint64_t seed = o.seed;
     while (true) {
         H.lev.emplace_back();
@@ -1074,6 +1072,20 @@ HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface,
         ++lev;
     }
     H.coarse_inv = dense_inverse(H.lev.back().A);
+}
+
+HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o,
+                              const std::vector<int8_t>* cf0) {
+    HostHierarchy H;
+    build_levels(H, Ainn, 0, iface, o, cf0);
+    return H;
+}
+
+HostHierarchy build_hierarchy_below(const HostHierarchy& old, const msp_opts& o) {
+    if (old.lev.size() < 2) throw Error(MSP_ERR_ARG, "no level below the reduction level");
+    HostHierarchy H;
+    H.lev.push_back(old.lev[0]);
+    build_levels(H, old.lev[1].A, 1, std::vector<int8_t>(), o, nullptr);
     return H;
 }
 

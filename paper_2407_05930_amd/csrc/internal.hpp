@@ -100,6 +100,9 @@ std::vector<int8_t> reduction_split(const Csr& A, const std::vector<int8_t>& ifa
 // cf0: a level-0 split computed elsewhere, used instead of Alg. 2 on Ainn.
 HostHierarchy build_hierarchy(const Csr& Ainn, const std::vector<int8_t>& iface, const msp_opts& o,
                               const std::vector<int8_t>* cf0 = nullptr);
+// The reduction level of `old` as it is (split, patterns and values), every level
+// below it built afresh from old's level-1 operator, as build_hierarchy builds them.
+HostHierarchy build_hierarchy_below(const HostHierarchy& old, const msp_opts& o);
 // AMGS, the Schur-complement AMG of Sec. 3.1, on the decoupled subsystems:
 // base cells reordered inner first (eq. (3.1)), so K = A_inn[0:nI, 0:nI],
 // B = A_inn[0:nI, nI:], C_1 = A_inn[nI:, nI:]; the AMG of K (HK); the FSAI of K

@@ -115,6 +115,18 @@ class Solver:
         self.version += 1
         check(lib.msp_refresh(self._ctx, ctypes.c_void_p(values.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
 
+    def rebuild_below(self):
+        """Rebuild every level below the reduction level on the host from the
+        current level-1 operator (msp_rebuild_below): for a solver whose
+        re-setups have moved the coarser splits (``stats.split_drift1``).  The
+        reduction level, with its current values, is kept; the solver then
+        holds the new context (``version`` is incremented, as by refresh)."""
+        new = ctypes.c_void_p()
+        check(lib.msp_rebuild_below(self._ctx, ctypes.byref(new)))
+        lib.msp_free(self._ctx)
+        self._ctx = new
+        self.version += 1
+
     # ------------------------------------------------------------------ solves
     def solve(self, b, stream=None):
         """Solve A x = b for a torch tensor b on the context's GPU, shape (n,)

@@ -446,3 +446,41 @@ def test_split_drift_is_not_reported_for_domains_of_copies():
     sv = Solver.from_copies(p.A, p.sub, coarse_max=40)
     sv.refresh(torch.from_numpy(p.A.data).cuda())
     assert sv.stats.split_drift == -1
+
+
+@pytest.mark.parametrize("pc,k,f3", [("amgr", 0, False), ("amgr_sub", 0, False), ("amgr_sub", 4, True)])
+def test_rebuild_below_after_a_refresh_matches_the_oracle(pc, k, f3):
+    """Device re-setup for a new kappa, then msp_rebuild_below: the reduction
+    level is the re-set-up one and every level below is built afresh from its
+    A_1, as the oracle's rebuild_below of its re-setup does (patterns and
+    splits bit for bit, values to the tolerance of the re-setup tests); the
+    solve then has the oracle's iteration count with x within 1e-9, and a
+    re-setup with the same values finds level 1's split where the rebuild put
+    it (split_drift1 = 0)."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("rebuild below", pc, k, f3)
+    kw = dict(y_stretch=1.5, kappa="lognormal")
+    p0 = make_problem((28, 24, 20), s=2, m=1, seed=101, **kw)
+    p1 = make_problem((28, 24, 20), s=2, m=1, seed=102, **kw)
+    opt = dict(coarse_max=48)
+    if f3:
+        opt.update(afsai_nnz=5, emin_steps=4)
+    sv = Solver(p0.A, p0.img, tol=TOL, pc=pc, k=k, **opt)
+    vals = torch.from_numpy(p1.A.data).cuda()
+    sv.refresh(vals)
+    assert sv.stats.split_drift1 > 0
+    sv.rebuild_below()
+    assert sv.stats.split_drift == -1 and sv.stats.split_drift1 == -1
+    ctx0 = krylov.setup(p0.A, p0.img, amg.AMGOptions(**opt), precond=pc, k=k)
+    ref = refresh.rebuild_below(refresh.refresh(ctx0, p1.A))
+    _check_levels(sv, ref["hier"], ref["sub"], base=1e-11)
+    x = sv.solve(torch.from_numpy(p1.b).cuda()).cpu().numpy()
+    r = krylov.solve(ref, p1.b, tol=TOL)
+    _say("its gpu", sv.last.iters, "oracle", r.iters.max())
+    assert abs(sv.last.iters - int(r.iters.max())) <= (1 if k else 0)
+    assert np.linalg.norm(x - r.x) <= 1e-9 * np.linalg.norm(r.x)
+    sv.refresh(vals)
+    assert sv.stats.split_drift1 == 0
+    x2 = sv.solve(torch.from_numpy(p1.b).cuda()).cpu().numpy()
+    assert np.linalg.norm(x2 - r.x) <= 1e-9 * np.linalg.norm(r.x)
