@@ -118,22 +118,30 @@ class DifferentiablePoisson:
     that (msp_stats.split_drift) is followed at once by a fresh host setup for
     the same kappa; ``max_split_drift1`` (a fraction of the level-1 points):
     the same for level 1's split of the new A_1 (msp_stats.split_drift1),
-    which moves long before the reduction level's does;
-    ``max_iteration_growth`` (a ratio): once a solve on a
+    which moves long before the reduction level's does (with
+    ``drift1_action="rebuild_below"`` the solver keeps its re-set-up reduction
+    level and rebuilds the levels below it on the host, msp_rebuild_below,
+    instead of a fresh setup); ``max_iteration_growth`` (a ratio): once a solve on a
     re-set-up solver takes more than that times the iterations of the first
     solve after the last fresh setup, the next kappa gets a fresh host setup
     (the coarser levels and the kept interpolation patterns can cost
     iterations while the reduction level's split stays)."""
 
     def __init__(self, faces, img, device: int = 0, resetup: str = "host", max_split_drift=None,
-                 max_iteration_growth=None, max_split_drift1=None, **solver_opts):
+                 max_iteration_growth=None, max_split_drift1=None, drift1_action: str = "fresh",
+                 **solver_opts):
         if resetup not in ("host", "device"):
             raise ValueError("resetup must be 'host' or 'device'")
+        if drift1_action not in ("fresh", "rebuild_below"):
+            raise ValueError("drift1_action must be 'fresh' or 'rebuild_below'")
         self.op = FVOperator(faces, img, device)
         self.opts = dict(solver_opts, device=device)
         self.resetup = resetup
         self.max_split_drift = max_split_drift
         self.max_split_drift1 = max_split_drift1
+        self.drift1_action = drift1_action
+        self.rebuilds = 0
+        self._base_version = 0     # solver version of the last fresh setup or rebuild
         self.max_iteration_growth = max_iteration_growth
         self.fresh_setups = 0
         self._fresh_iters = None   # iterations of the first solve after the last fresh setup
@@ -156,14 +164,22 @@ class DifferentiablePoisson:
             self._vals = self.op.assemble_device(kap, out=self._vals)
             self.solver.refresh(self._vals)
             st = self.solver.stats
-            fresh = ((self.max_split_drift is not None and st.split_drift > self.max_split_drift * self.op.n_b)
-                     or (self.max_split_drift1 is not None and st.nlev > 2
-                         and st.split_drift1 > self.max_split_drift1 * st.rows[1]))
+            over0 = self.max_split_drift is not None and st.split_drift > self.max_split_drift * self.op.n_b
+            over1 = (self.max_split_drift1 is not None and st.nlev > 2
+                     and st.split_drift1 > self.max_split_drift1 * st.rows[1])
+            fresh = over0 or over1
+            if over1 and not over0 and self.drift1_action == "rebuild_below":
+                self.solver.rebuild_below()
+                self.rebuilds += 1
+                self._fresh_iters = None
+                self._base_version = self.solver.version
+                fresh = False
         if fresh:
             A = self.op.assemble(kap.cpu().numpy())
             self.solver = Solver(A, self.op.img, **self.opts)
             self.fresh_setups += 1
             self._fresh_iters = None
+            self._base_version = 0
             self._grown = False
         self._kappa = kap.clone()
         return self.solver
@@ -176,9 +192,10 @@ class DifferentiablePoisson:
         if sv is not self.solver:
             return
         its = sv.last.iters
-        if self._fresh_iters is None and sv.version == 0:
+        if self._fresh_iters is None and sv.version == self._base_version:
             self._fresh_iters = its
-        elif (self.max_iteration_growth is not None and self._fresh_iters is not None and sv.version > 0
+        elif (self.max_iteration_growth is not None and self._fresh_iters is not None
+              and sv.version > self._base_version
               and its > self.max_iteration_growth * self._fresh_iters):
             self._grown = True
 

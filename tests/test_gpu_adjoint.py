@@ -208,6 +208,34 @@ def test_device_resetup_falls_back_when_the_level_one_split_moves():
     assert np.linalg.norm(kap.grad.cpu().numpy() - g) <= 1e-9 * np.linalg.norm(g)
 
 
+def test_level_one_drift_can_rebuild_below_instead_of_a_fresh_setup():
+    """drift1_action = "rebuild_below": the same kappa step keeps the solver
+    (re-set-up reduction level) and rebuilds the levels below it; loss and
+    gradient are the oracle's, and a graph recorded before the rebuild is
+    refused its backward."""
+    torch = _torch()
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    pr = make_problem((24, 20, 16), s=3, m=1, seed=21, kappa="lognormal", y_stretch=1.5, with_target=True)
+    pstar = pr.p_target[:, None]
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-13, coarse_max=48, resetup="device", max_split_drift1=0.0,
+                               drift1_action="rebuild_below")
+    f = torch.from_numpy(pr.b).cuda()
+    pst = torch.from_numpy(pstar).cuda()
+    k0 = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
+    loss0 = 0.5 * ((dp(f, k0) - pst) ** 2).sum()
+    first = dp.solver
+    k1 = pr.kappa_base * np.exp(0.05 * np.random.default_rng(7).standard_normal(pr.n_b))
+    kap = torch.from_numpy(k1).cuda().requires_grad_(True)
+    loss = 0.5 * ((dp(f, kap) - pst) ** 2).sum()
+    assert dp.fresh_setups == 1 and dp.rebuilds == 1 and dp.solver is first
+    loss.backward()
+    L, lam, g, _ = adjoint.loss_and_gradients(pr.faces, pr.img, k1, pr.b, pstar)
+    assert abs(loss.item() - L) <= 1e-9 * abs(L)
+    assert np.linalg.norm(kap.grad.cpu().numpy() - g) <= 1e-9 * np.linalg.norm(g)
+    with pytest.raises(RuntimeError, match="re-set up"):
+        loss0.backward()
+
+
 def test_device_resetup_falls_back_when_the_iterations_grow():
     """max_iteration_growth: once a solve on a re-set-up solver takes more
     than the ratio times the iterations after the last fresh setup, the next
