@@ -5,8 +5,12 @@
 // compiled without floating-point contraction so that each decision is one
 // IEEE multiply followed by an exact comparison.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <numeric>
 #include <thread>
 #include <utility>
@@ -29,6 +33,76 @@ double unit_centered(uint64_t x) {
 }
 
 static int popcount_parity(uint32_t x) { return __builtin_popcount(x) & 1; }
+
+// ------------------------------------------------------------------ row-parallel loops
+
+// Threads a row loop may use: at most 16 (MSP_SETUP_THREADS overrides, 1..64);
+// inside the per-subsystem workers, their share of that.
+static thread_local int t_share = 0;
+
+static int setup_threads() {
+    if (t_share > 0) return t_share;
+    static const int all = [] {
+        const char* v = std::getenv("MSP_SETUP_THREADS");
+        const int e = v ? std::atoi(v) : 0;
+        if (e > 0) return std::min(e, 64);
+        return static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    }();
+    return all;
+}
+
+// fn(lo, hi, chunk) over contiguous row ranges [lo, hi) covering [0, n), chunk =
+// 0 .. chunks-1 in row order; returns the number of chunks.  Every row is
+// computed by one thread with the serial loop's arithmetic, so the results do not
+// depend on the thread count.  The first exception of any chunk is rethrown.
+template <typename F>
+static int parallel_rows(int64_t n, F&& fn, int64_t grain = 2048) {
+    const int nt = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(setup_threads(), n / grain)));
+    if (nt == 1) {
+        fn(int64_t(0), n, 0);
+        return 1;
+    }
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> err(nt);
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            try {
+                fn(n * t / nt, n * (t + 1) / nt, t);
+            } catch (...) {
+                err[t] = std::current_exception();
+            }
+        });
+    for (auto& x : th) x.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+    return nt;
+}
+
+// Row pieces of a CSR matrix computed per chunk, then concatenated in row order.
+struct CsrPiece {
+    std::vector<int64_t> len;
+    std::vector<int32_t> ci;
+    std::vector<double> v;
+};
+
+static void join_pieces(Csr& C, std::vector<CsrPiece>& pc, int chunks) {
+    C.rp.assign(C.nr + 1, 0);
+    int64_t r = 0, nnz = 0;
+    for (int t = 0; t < chunks; ++t) nnz += static_cast<int64_t>(pc[t].ci.size());
+    C.ci.clear();
+    C.v.clear();
+    C.ci.reserve(nnz);
+    C.v.reserve(nnz);
+    for (int t = 0; t < chunks; ++t) {
+        for (int64_t l : pc[t].len) {
+            C.rp[r + 1] = C.rp[r] + l;
+            ++r;
+        }
+        C.ci.insert(C.ci.end(), pc[t].ci.begin(), pc[t].ci.end());
+        C.v.insert(C.v.end(), pc[t].v.begin(), pc[t].v.end());
+        CsrPiece().len.swap(pc[t].len);
+    }
+}
 
 // ------------------------------------------------------------------ sparse kernels
 
@@ -118,41 +192,47 @@ Csr spgemm(const Csr& A, const Csr& B) {
     Csr C;
     C.nr = A.nr;
     C.nc = B.nc;
-    C.rp.assign(C.nr + 1, 0);
-    std::vector<int64_t> mark(B.nc, -1);
-    std::vector<double> acc(B.nc, 0.0);
-    std::vector<int32_t> cols;
-    for (int64_t i = 0; i < A.nr; ++i) {
-        cols.clear();
-        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-            const int32_t j = A.ci[k];
-            const double a = A.v[k];
-            for (int64_t q = B.rp[j]; q < B.rp[j + 1]; ++q) {
-                const int32_t c = B.ci[q];
-                if (mark[c] != i) {
-                    mark[c] = i;
-                    acc[c] = 0.0;
-                    cols.push_back(c);
+    std::vector<CsrPiece> pc(64);
+    const int chunks = parallel_rows(A.nr, [&](int64_t lo, int64_t hi, int t) {
+        CsrPiece& out = pc[t];
+        std::vector<int64_t> mark(B.nc, -1);
+        std::vector<double> acc(B.nc, 0.0);
+        std::vector<int32_t> cols;
+        for (int64_t i = lo; i < hi; ++i) {
+            cols.clear();
+            for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                const int32_t j = A.ci[k];
+                const double a = A.v[k];
+                for (int64_t q = B.rp[j]; q < B.rp[j + 1]; ++q) {
+                    const int32_t c = B.ci[q];
+                    if (mark[c] != i) {
+                        mark[c] = i;
+                        acc[c] = 0.0;
+                        cols.push_back(c);
+                    }
+                    acc[c] += a * B.v[q];
                 }
-                acc[c] += a * B.v[q];
             }
+            std::sort(cols.begin(), cols.end());
+            for (int32_t c : cols) {
+                out.ci.push_back(c);
+                out.v.push_back(acc[c]);
+            }
+            out.len.push_back(static_cast<int64_t>(cols.size()));
         }
-        std::sort(cols.begin(), cols.end());
-        for (int32_t c : cols) {
-            C.ci.push_back(c);
-            C.v.push_back(acc[c]);
-        }
-        C.rp[i + 1] = static_cast<int64_t>(C.ci.size());
-    }
+    });
+    join_pieces(C, pc, chunks);
     return C;
 }
 
 static void spmv(const Csr& A, const double* x, double* y) {
-    for (int64_t i = 0; i < A.nr; ++i) {
-        double s = 0.0;
-        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * x[A.ci[k]];
-        y[i] = s;
-    }
+    parallel_rows(A.nr, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i) {
+            double s = 0.0;
+            for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * x[A.ci[k]];
+            y[i] = s;
+        }
+    });
 }
 
 // ------------------------------------------------------------------ block extraction
@@ -558,10 +638,12 @@ static double lookup(const Csr& A, int64_t i, int32_t j) {
 static Csr fsai_rows(const Csr& A, const std::vector<std::vector<int32_t>>& lower) {
     Csr G;
     G.nr = G.nc = A.nr;
-    G.rp.assign(A.nr + 1, 0);
+    std::vector<CsrPiece> pc(64);
+    const int chunks = parallel_rows(A.nr, [&](int64_t lo, int64_t hi, int t) {
+    CsrPiece& out = pc[t];
     std::vector<double> M, g;
     std::vector<int32_t> J;
-    for (int64_t i = 0; i < A.nr; ++i) {
+    for (int64_t i = lo; i < hi; ++i) {
         J = lower[i];
         J.push_back(static_cast<int32_t>(i));
         const int k = static_cast<int>(J.size());
@@ -579,11 +661,13 @@ static Csr fsai_rows(const Csr& A, const std::vector<std::vector<int32_t>>& lowe
         }
         const double sc = 1.0 / std::sqrt(g[k - 1]);
         for (int p = 0; p < k; ++p) {
-            G.ci.push_back(J[p]);
-            G.v.push_back(g[p] * sc);
+            out.ci.push_back(J[p]);
+            out.v.push_back(g[p] * sc);
         }
-        G.rp[i + 1] = static_cast<int64_t>(G.ci.size());
+        out.len.push_back(k);
     }
+    }, 256);
+    join_pieces(G, pc, chunks);
     return G;
 }
 
@@ -609,12 +693,13 @@ static std::vector<std::vector<int32_t>> afsai_lower(const Csr& A, const std::ve
     std::vector<double> d(n);
     for (int64_t i = 0; i < n; ++i) d[i] = lookup(A, i, static_cast<int32_t>(i));
     std::vector<std::vector<int32_t>> lower(n);
+    parallel_rows(n, [&](int64_t lo, int64_t hi, int) {
     std::vector<int64_t> stamp(n, -1);
     std::vector<double> acc(n, 0.0);
     std::vector<int32_t> P, cand;
     std::vector<double> g, M, y;
     int64_t tick = 0;
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = lo; i < hi; ++i) {
         P.assign(1, static_cast<int32_t>(i));
         g.assign(1, 1.0);
         while (static_cast<int>(P.size()) < nnz_max) {
@@ -668,6 +753,7 @@ static std::vector<std::vector<int32_t>> afsai_lower(const Csr& A, const std::ve
         lower[i].assign(P.begin() + 1, P.end());
         std::sort(lower[i].begin(), lower[i].end());
     }
+    }, 256);
     return lower;
 }
 
@@ -706,12 +792,13 @@ static void emin(const Csr& A, const std::vector<int8_t>& cf, Csr& P, int steps)
         const double dd = 1.0 / lookup(A, fidx[f], fidx[f]);
         for (int64_t e = wrp[f]; e < wrp[f + 1]; ++e) dinv[e] = dd;
     }
-    // slot of column c in row f of W (-1: off the pattern), through a dense row map
-    std::vector<int64_t> slot(nc, -1);
     // out = A_FF x (+ A_FC if add_afc) on W's pattern, x on W's pattern
     auto apply = [&](const std::vector<double>& x, bool add_afc, std::vector<double>& out) {
         std::vector<double> prod(m, 0.0);
-        for (int64_t f = 0; f < nf; ++f) {
+        parallel_rows(nf, [&](int64_t lo, int64_t hi, int) {
+        // slot of column c in row f of W (-1: off the pattern), through a dense row map
+        std::vector<int64_t> slot(nc, -1);
+        for (int64_t f = lo; f < hi; ++f) {
             for (int64_t e = wrp[f]; e < wrp[f + 1]; ++e) slot[wc[e]] = e;
             const int32_t i = fidx[f];
             for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
@@ -737,6 +824,7 @@ static void emin(const Csr& A, const std::vector<int8_t>& cf, Csr& P, int steps)
             }
             for (int64_t e = wrp[f]; e < wrp[f + 1]; ++e) slot[wc[e]] = -1;
         }
+        }, 64);
     };
     auto project = [&](std::vector<double>& v) {
         for (int64_t f = 0; f < nf; ++f) {
@@ -873,7 +961,7 @@ static std::vector<double> dense_inverse(const Csr& Ac) {
     std::vector<int64_t> coff(nc + 1, 0);
     for (int64_t c = 0; c < nc; ++c) coff[c + 1] = coff[c] + (nc - c);
     std::vector<double> Li(coff[nc]);
-    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const unsigned nth = static_cast<unsigned>(setup_threads());
     auto parallel = [&](auto&& body) {
         std::vector<std::thread> th;
         for (unsigned t = 0; t < nth; ++t)
@@ -1007,6 +1095,16 @@ std::vector<int8_t> reduction_split(const Csr& A, const std::vector<int8_t>& ifa
 static void build_levels(HostHierarchy& H, Csr A, int lev, const std::vector<int8_t>& iface, const msp_opts& o,
                          const std::vector<int8_t>* cf0) {
     const uint64_t seed = o.seed;
+    // MSP_SETUP_LOG set (non-empty, not "0"): seconds per setup phase and level to stderr
+    const char* logv = std::getenv("MSP_SETUP_LOG");
+    const bool log = logv && *logv && std::strcmp(logv, "0") != 0;
+    auto clk = std::chrono::steady_clock::now();
+    auto lap = [&](const char* what, int l) {
+        if (!log) return;
+        const auto t = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "msp setup: level %d %s %.3f s\n", l, what, std::chrono::duration<double>(t - clk).count());
+        clk = t;
+    };
     while (true) {
         H.lev.emplace_back();
         HostLevel& L = H.lev.back();
@@ -1038,6 +1136,7 @@ static void build_levels(HostHierarchy& H, Csr A, int lev, const std::vector<int
             });
             cf = mis_scan(T, std::vector<int8_t>(n, 1), order, 1);
         }
+        lap("split", lev);
         int64_t nc = 0;
         for (int64_t i = 0; i < n; ++i) nc += cf[i];
         if (nc == 0 || static_cast<double>(nc) > o.max_ratio * static_cast<double>(n)) {
@@ -1056,17 +1155,23 @@ static void build_levels(HostHierarchy& H, Csr A, int lev, const std::vector<int
                     if (j < i && (lev != 0 || cf[j] == cf[i])) lower[i].push_back(j);
                 }
         }
+        lap("smoother pattern", lev);
         L.G = fsai_rows(A, lower);
         L.GT = transpose(L.G);
+        lap("fsai", lev);
         L.omega = damping(A, L.G, L.GT, seed);
         L.M = spgemm(L.GT, L.G);
         for (double& v : L.M.v) v *= L.omega;
+        lap("damping and M", lev);
         L.P = interpolation(A, cf, lev == 0 ? o.jacobi0 : o.jacobi, lev == 0 ? o.trunc0 : 0.0);
+        lap("interpolation", lev);
         if (o.emin_steps > 0) emin(A, cf, L.P, o.emin_steps);
+        lap("energy minimisation", lev);
         L.R = transpose(L.P);
         L.cf = std::move(cf);
         Csr AP = spgemm(A, L.P);
         Csr Ac = spgemm(L.R, AP);
+        lap("galerkin", lev);
         L.A = std::move(A);
         A = std::move(Ac);
         ++lev;
@@ -1326,10 +1431,13 @@ SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& si
         const std::vector<double> inv = dense_inverse(A);
         std::copy(inv.begin(), inv.end(), V.coarse_inv.begin() + static_cast<size_t>(a) * nL * nL);
     };
+    const auto t0 = std::chrono::steady_clock::now();
     std::vector<std::thread> th;
     std::vector<int> codes(S, MSP_OK);
+    const int share = std::max(1, setup_threads() / S);   // row loops inside a subsystem's worker
     for (int a = 0; a < S; ++a)
         th.emplace_back([&, a]() {
+            t_share = share;
             try {
                 one(a);
             } catch (const Error& e) {
@@ -1340,6 +1448,10 @@ SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& si
     for (auto& t : th) t.join();
     for (int a = 0; a < S; ++a)
         if (codes[a] != MSP_OK) throw Error(codes[a], "subsystem " + std::to_string(a) + ": " + errs[a]);
+    const char* logv = std::getenv("MSP_SETUP_LOG");
+    if (logv && *logv && std::strcmp(logv, "0") != 0)
+        std::fprintf(stderr, "msp setup: per-subsystem values of levels >= 1 %.3f s\n",
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     return V;
 }
 
