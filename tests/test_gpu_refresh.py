@@ -484,3 +484,46 @@ def test_rebuild_below_after_a_refresh_matches_the_oracle(pc, k, f3):
     assert sv.stats.split_drift1 == 0
     x2 = sv.solve(torch.from_numpy(p1.b).cuda()).cpu().numpy()
     assert np.linalg.norm(x2 - r.x) <= 1e-9 * np.linalg.norm(r.x)
+
+
+def test_rebuild_below_of_copies_and_in_mixed_precision():
+    """The rebuild after a re-setup for a domain of copies (FP64: the direct
+    solution to 1e-9) and for a bfloat16-multivector solver with low-rank
+    corrections (the FP64 oracle's rebuild solution to 1e-7, true residual
+    to the tolerance); both find level 1's split unmoved on a second
+    re-setup with the same values."""
+    torch = _torch()
+    from gen import make_repeated_problem
+    from paper_2407_05930_amd import Solver
+    _say("rebuild copies")
+    p0 = make_repeated_problem((12, 10, 8), 3, m=1, seed=71, walls="mixed")
+    p1 = make_repeated_problem((12, 10, 8), 3, m=1, seed=72, walls="mixed")
+    sv = Solver.from_copies(p0.A, p0.sub, tol=TOL, coarse_max=48)
+    assert sv.num_levels() >= 3
+    vals = torch.from_numpy(p1.A.data).cuda()
+    sv.refresh(vals)
+    sv.rebuild_below()
+    b = p1.b.reshape(p1.A.shape[0], -1)[:, 0].copy()
+    x = sv.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    xd = spla.splu(p1.A.tocsc()).solve(b)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+    sv.refresh(vals)
+    assert sv.stats.split_drift1 == 0
+    sv.close()
+    _say("rebuild mixed_bf16")
+    kw = dict(y_stretch=1.5, kappa="lognormal")
+    q0 = make_problem((28, 24, 20), s=3, m=2, seed=103, **kw)
+    q1 = make_problem((28, 24, 20), s=3, m=2, seed=104, **kw)
+    opt = dict(coarse_max=48, afsai_nnz=5, emin_steps=4)
+    sm = Solver(q0.A, q0.img, tol=1e-10, pc="amgr_sub", k=4, precision="mixed_bf16", **opt)
+    vq = torch.from_numpy(q1.A.data).cuda()
+    sm.refresh(vq)
+    sm.rebuild_below()
+    y = sm.solve(torch.from_numpy(q1.b).cuda()).cpu().numpy()
+    ref = krylov.solve(refresh.rebuild_below(refresh.refresh(
+        krylov.setup(q0.A, q0.img, amg.AMGOptions(**opt), precond="amgr_sub"), q1.A)), q1.b, tol=1e-12)
+    _say("its", sm.last.iters, "oracle (k = 0)", ref.iters.max())
+    assert np.all(krylov.true_relres(q1.A, y, q1.b) <= 1.5e-10)
+    assert np.linalg.norm(y - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+    sm.refresh(vq)
+    assert sm.stats.split_drift1 == 0
