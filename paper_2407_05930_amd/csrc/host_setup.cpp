@@ -150,15 +150,17 @@ std::vector<Csr> interpolation_patterns(const Csr& A, const std::vector<int8_t>&
         }
     }
     std::vector<Csr> out;
-    std::vector<int64_t> mark(nc, -1);
-    std::vector<int32_t> cols;
     for (int t = 0; t < steps; ++t) {
         const Csr* prev = t > 0 ? &out.back() : nullptr;
         Csr W;
         W.nr = nf;
         W.nc = nc;
-        W.rp.assign(nf + 1, 0);
-        for (int32_t r = 0; r < nf; ++r) {
+        std::vector<CsrPiece> pc(64);
+        const int chunks = parallel_rows(nf, [&](int64_t lo, int64_t hi, int tc) {
+        CsrPiece& piece = pc[tc];
+        std::vector<int64_t> mark(nc, -1);
+        std::vector<int32_t> cols;
+        for (int64_t r = lo; r < hi; ++r) {
             const int64_t i = fidx[r];
             cols.clear();
             for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
@@ -179,10 +181,12 @@ std::vector<Csr> interpolation_patterns(const Csr& A, const std::vector<int8_t>&
                 }
             }
             std::sort(cols.begin(), cols.end());
-            W.ci.insert(W.ci.end(), cols.begin(), cols.end());
-            W.rp[r + 1] = static_cast<int64_t>(W.ci.size());
+            piece.ci.insert(piece.ci.end(), cols.begin(), cols.end());
+            piece.len.push_back(static_cast<int64_t>(cols.size()));
         }
-        std::fill(mark.begin(), mark.end(), -1);
+        });
+        join_pieces(W, pc, chunks);
+        W.v.clear();
         out.push_back(std::move(W));
     }
     return out;
@@ -487,12 +491,14 @@ static Csr interpolation(const Csr& A, const std::vector<int8_t>& cf, int steps,
         Csr Wn;
         Wn.nr = nf;
         Wn.nc = nc;
-        Wn.rp.assign(nf + 1, 0);
+        std::vector<CsrPiece> pc(64);
+        const int chunks = parallel_rows(nf, [&](int64_t lo, int64_t hi, int tc) {
+        CsrPiece& piece = pc[tc];
         std::vector<int64_t> mark(nc, -1);
         std::vector<double> acc(nc, 0.0), afc(nc, 0.0);
         std::vector<int8_t> has_afc(nc, 0), has_acc(nc, 0);
         std::vector<int32_t> cols;
-        for (int32_t r = 0; r < nf; ++r) {
+        for (int64_t r = lo; r < hi; ++r) {
             const int64_t i = fidx[r];
             cols.clear();
             double dii = 0.0;
@@ -537,11 +543,13 @@ static Csr interpolation(const Csr& A, const std::vector<int8_t>& cf, int steps,
                 if (has_afc[q] && has_acc[q]) t = afc[q] + acc[q];
                 else if (has_afc[q]) t = afc[q];
                 else t = acc[q];
-                Wn.ci.push_back(q);
-                Wn.v.push_back(-(dinv * t));
+                piece.ci.push_back(q);
+                piece.v.push_back(-(dinv * t));
             }
-            Wn.rp[r + 1] = static_cast<int64_t>(Wn.ci.size());
+            piece.len.push_back(static_cast<int64_t>(cols.size()));
         }
+        });
+        join_pieces(Wn, pc, chunks);
         return Wn;
     };
     W = build_step(nullptr);
