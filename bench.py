@@ -40,15 +40,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_solves(sv, b, steps, warmup, torch):
+def timed_solves(sv, b, steps, warmup, torch, markers=False):
+    """Mean time of `steps` solves after `warmup` untimed ones; with markers, the
+    window fills bracket the timed solves (for profiling.py window)."""
     for _ in range(warmup):
         sv.solve(b)
     torch.cuda.synchronize()
+    if markers:
+        window_marker(torch)
     t0 = time.perf_counter()
     for _ in range(steps):
         x = sv.solve(b)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if markers:
+        window_marker(torch)
+        torch.cuda.synchronize()
     return (t1 - t0) / steps, x
 
 
@@ -148,7 +155,8 @@ def device_columns(torch, a):
 def window_marker(torch):
     """A tiny int16 fill launched just before and just after the timed steps of
     the headline solve, so that a kernel trace of this command can be cut to
-    exactly those steps (profiling.py window)."""
+    exactly those steps (profiling.py window).  The other workloads place them
+    around their bfloat16-multivector solves."""
     torch.empty(1, dtype=torch.int16, device="cuda").fill_(7)
 
 
@@ -195,12 +203,13 @@ def bench_jitter(args, torch, np):
     from gen import config_problem
     from paper_2407_05930_amd import Solver
     log("building workload jitter3d_192_s3")
+    k = 16 if args.k is None else args.k
     p = config_problem("jitter3d_192_s3")
     b = device_columns(torch, p.b)
     out = {}
     for prec in ("fp64", "mixed", "mixed_bf16g", "mixed_bf16"):
-        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=args.k, pc=args.pc, **args.extra)
-        t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
+        sv = Solver(p.A, p.img, tol=1e-10, precision=prec, k=k, pc=args.pc, **args.extra)
+        t, x = timed_solves(sv, b, args.steps, args.warmup, torch, markers=prec == "mixed_bf16")
         xs = x.cpu().numpy()
         rr = float(np.max(np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)))
         out[prec] = dict(solve_s=round(t, 6), iters=sv.last.iters, true_relres=rr, setup_s=round(sv.stats.t_setup_s, 3))
@@ -210,9 +219,9 @@ def bench_jitter(args, torch, np):
             out[prec]["rel_diff_vs_fp64"] = float(np.linalg.norm(xs - x64) / np.linalg.norm(x64))
         log(f"  {prec}: {t * 1e3:.2f} ms, {sv.last.iters} its, relres {rr:.2e}")
         sv.close()
-    return {"metric": "solve time to 1e-10 rel-res, 192^3 jittered s=3, k=16", "value": out["mixed_bf16g"]["solve_s"],
+    return {"metric": f"solve time to 1e-10 rel-res, 192^3 jittered s=3, k={k}", "value": out["mixed_bf16g"]["solve_s"],
             "unit": "s", "higher_is_better": False, "dtype": "f64+f32+bf16",
-            "config": {"workload": "jitter3d_192_s3", "afsai_nnz": args.afsai, "emin_steps": args.emin, "grid": list(p.N), "s": 3, "rhs": 1, "lrc_k": args.k,
+            "config": {"workload": "jitter3d_192_s3", "afsai_nnz": args.afsai, "emin_steps": args.emin, "grid": list(p.N), "s": 3, "rhs": 1, "lrc_k": k,
                        "unknowns": int(p.n), "preconditioner": args.pc}, "variants": out}
 
 
@@ -307,7 +316,7 @@ def bench_copies(args, torch, np):
     svh = None
     for prec in ("fp64", "mixed", "mixed_bf16"):
         sv = Solver.from_copies(p.A, p.sub, tol=1e-10, precision=prec, **args.extra)
-        t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
+        t, x = timed_solves(sv, b, args.steps, args.warmup, torch, markers=prec == "mixed_bf16")
         xs = x.cpu().numpy()
         rr = float(np.max(np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)))
         out[prec] = dict(solve_s=round(t, 6), iters=sv.last.iters, true_relres=rr,
@@ -349,7 +358,7 @@ def bench_amgs(args, torch, np):
     svh = None
     for label, opts in (("amgs", dict(pc="amgs", amgs_light=0)), ("amgs_light", dict(pc="amgs", amgs_light=1)),
                         ("amgr_sub", dict(pc="amgr_sub"))):
-        sv = Solver(p.A, p.img, tol=1e-10, precision="fp64", k=args.k, **opts)
+        sv = Solver(p.A, p.img, tol=1e-10, precision="fp64", k=8 if args.k is None else args.k, **opts)
         t, x = timed_solves(sv, b, args.steps, args.warmup, torch)
         xs = x.cpu().numpy()
         rr = float(np.max(np.linalg.norm(p.b - p.A @ xs, axis=0) / np.linalg.norm(p.b, axis=0)))
@@ -365,7 +374,7 @@ def bench_amgs(args, torch, np):
     return {"metric": "solve time to 1e-10 rel-res, 128^3 s=3, 4 RHS, AMGS (Schur-complement AMG), FP64",
             "value": out["amgs"]["solve_s"], "unit": "s", "higher_is_better": False, "dtype": "f64",
             "config": {"workload": "amgs3d_128_s3", "grid": list(p.N), "s": p.s, "rhs": int(p.b.shape[1]),
-                       "schur_lrc_k": args.k, "unknowns": int(p.n)},
+                       "schur_lrc_k": 8 if args.k is None else args.k, "unknowns": int(p.n)},
             "variants": out, "roofline": roof}
 
 
@@ -545,7 +554,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="channel3d_128_s3")
-    ap.add_argument("--k", type=int, default=8, help="low-rank correction rank per subsystem")
+    ap.add_argument("--k", type=int, default=None,
+                    help="low-rank correction rank per subsystem (default: 16 for jitter3d_192_s3, else 8)")
     ap.add_argument("--pc", default="amgr_sub", choices=["amgr", "amgr_sub"],
                     help="AMGR per subsystem below the shared reduction level (default), or the AMGR "
                          "hierarchy of A_inn shared by every subsystem")
@@ -602,7 +612,7 @@ def main():
     log(f"building workload {args.workload}")
     p = config_problem(args.workload)
     b = device_columns(torch, p.b)
-    k = args.k
+    k = 8 if args.k is None else args.k
     head = args.mixed   # the mixed-precision variant reported as the headline
     alt = "mixed" if head == "mixed_bf16" else "mixed_bf16"
 

@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the committed profile notes.
 
-    python -m paper_2407_05930_amd.profiling window <kernel_trace.csv> <out.md> <command...>
+    python -m paper_2407_05930_amd.profiling window <kernel_trace.csv> <out.md> [--what=<title>] <command...>
     python -m paper_2407_05930_amd.profiling traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> <kernel name> <copy bytes> <out.md> <command...>
     python -m paper_2407_05930_amd.profiling counters <counter_collection.csv> <out.md> <command...>
@@ -68,7 +68,7 @@ def _in_window(rows, order_key):
     return [r for r in rows[marks[0] + 1:marks[-1]] if MARKER not in r["Kernel_Name"]], True
 
 
-def window(path, out, command):
+def window(path, out, command, what="the timed headline solves"):
     rows = list(csv.DictReader(open(path)))
     rows, found = _in_window(rows, lambda r: int(r["Start_Timestamp"]))
     per = {}
@@ -79,7 +79,7 @@ def window(path, out, command):
         e[1] += d
     total = sum(v[1] for v in per.values()) or 1
     span = (int(rows[-1]["End_Timestamp"]) - int(rows[0]["Start_Timestamp"])) if rows else 0
-    lines = ["# rocprofv3 kernel statistics of the timed headline solves", "", f"Command: `{command}`", "",
+    lines = [f"# rocprofv3 kernel statistics of {what}", "", f"Command: `{command}`", "",
              f"Library source hash: `{source_hash()}`", "",
              ("Only the dispatches between the two int16 fill markers that bench.py launches around its timed steps "
               "are counted (no setup, autotuning or Lanczos kernels)." if found else
@@ -252,7 +252,10 @@ def vcycle_classes(fetch_csv, write_csv, l2_csv, copy_bytes, bench_json, out, co
 
 if __name__ == "__main__":
     if sys.argv[1] == "window":
-        window(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        if sys.argv[4].startswith("--what="):
+            window(sys.argv[2], sys.argv[3], " ".join(sys.argv[5:]), sys.argv[4][len("--what="):])
+        else:
+            window(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), sys.argv[6], " ".join(sys.argv[7:]))
     elif sys.argv[1] == "counters":
