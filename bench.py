@@ -156,7 +156,8 @@ def window_marker(torch):
     """A tiny int16 fill launched just before and just after the timed steps of
     the headline solve, so that a kernel trace of this command can be cut to
     exactly those steps (profiling.py window).  The other workloads place them
-    around their bfloat16-multivector solves."""
+    around their bfloat16-multivector solves (the adjoint: its timed forward and
+    backward passes)."""
     torch.empty(1, dtype=torch.int16, device="cuda").fill_(7)
 
 
@@ -461,6 +462,8 @@ def bench_adjoint(args, torch, np):
         kap.grad = None
         fr = f.clone().requires_grad_(True)
         torch.cuda.synchronize()
+        if it == args.warmup:
+            window_marker(torch)
         t0 = time.perf_counter()
         p = dp(fr, kap)
         loss = 0.5 * ((p - pst) ** 2).sum()
@@ -468,6 +471,8 @@ def bench_adjoint(args, torch, np):
         torch.cuda.synchronize()
         if it >= args.warmup:
             times.append(time.perf_counter() - t0)
+    window_marker(torch)
+    torch.cuda.synchronize()
     t = sum(times) / len(times)
     its_host = dp.solver.last.iters
     loss_host = float(loss.item())
