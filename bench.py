@@ -475,6 +475,29 @@ def bench_adjoint(args, torch, np):
     torch.cuda.synchronize()
     t = sum(times) / len(times)
     its_host = dp.solver.last.iters
+    g64 = kap.grad.clone()
+    # the same passes with the bfloat16-multivector V-cycle under the FP64 PCG
+    log("forward + adjoint with the bfloat16-multivector V-cycle")
+    dpm = DifferentiablePoisson(pr.faces, pr.img, tol=1e-10, pc=args.pc, precision="mixed_bf16", **args.extra)
+    dpm.solver_for(kap)
+    tm = []
+    for it in range(args.warmup + args.steps):
+        kap.grad = None
+        fm = f.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pm = dpm(fm, kap)
+        (0.5 * ((pm - pst) ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            tm.append(time.perf_counter() - t0)
+    mixed = {"value_s": round(sum(tm) / len(tm), 6), "iters": dpm.solver.last.iters,
+             "grad_kappa_rel_diff_vs_fp64": float((kap.grad - g64).norm().item() / g64.norm().item())}
+    log(f"  mixed_bf16: {mixed['value_s'] * 1e3:.1f} ms, {mixed['iters']} its")
+    dpm.solver.close()
+    dpm.op.close()
+    del dpm, pm
+    kap.grad = g64
     loss_host = float(loss.item())
     gk_host = float(kap.grad.norm().item())
     # Per-kappa rebuild for an optimisation step: the host path (assembly and
@@ -550,7 +573,8 @@ def bench_adjoint(args, torch, np):
             "config": {"workload": "adjoint3d_256_s3", "afsai_nnz": args.afsai, "emin_steps": args.emin, "grid": list(pr.N), "s": 3, "unknowns": int(pr.n),
                        "preconditioner": args.pc},
             "iters": its_host, "setup_s": round(t_setup, 2), "loss": loss_host,
-            "grad_kappa_norm": gk_host, "grad_f_norm": float(fr.grad.norm().item()), "resetup": resetup}
+            "grad_kappa_norm": gk_host, "grad_f_norm": float(fr.grad.norm().item()), "resetup": resetup,
+            "mixed_bf16_vcycle": mixed}
 
 
 def main():

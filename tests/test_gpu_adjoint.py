@@ -37,6 +37,28 @@ def test_adjoint_gradient_matches_oracle(N, s, m):
     assert np.linalg.norm(gk - g) <= 1e-9 * np.linalg.norm(g)
 
 
+@pytest.mark.parametrize("prec", ["mixed", "mixed_bf16"])
+def test_adjoint_gradient_with_a_mixed_precision_cycle(prec):
+    """The FP64 outer PCG with an FP32-arithmetic V-cycle (FP32 or bfloat16
+    multivectors) as preconditioner: both solves reach the tolerance in the
+    true residual, so loss and gradients match the oracle's to 1e-9."""
+    torch = _torch()
+    from paper_2407_05930_amd.adjoint import DifferentiablePoisson
+    pr = make_problem((32, 32, 32), s=3, m=1, seed=13, kappa="lognormal", with_target=True)
+    pstar = pr.p_target[:, None]
+    L, lam, g, p_ref = adjoint.loss_and_gradients(pr.faces, pr.img, pr.kappa_base, pr.b, pstar)
+    dp = DifferentiablePoisson(pr.faces, pr.img, tol=1e-12, coarse_max=64, precision=prec, afsai_nnz=5,
+                               emin_steps=4)
+    f = torch.from_numpy(pr.b).cuda().requires_grad_(True)
+    kap = torch.from_numpy(pr.kappa_base).cuda().requires_grad_(True)
+    p = dp(f, kap)
+    loss = 0.5 * ((p - torch.from_numpy(pstar).cuda()) ** 2).sum()
+    loss.backward()
+    assert abs(loss.item() - L) <= 1e-9 * abs(L)
+    assert np.linalg.norm(f.grad.cpu().numpy() - lam) <= 1e-9 * np.linalg.norm(lam)
+    assert np.linalg.norm(kap.grad.cpu().numpy() - g) <= 1e-9 * np.linalg.norm(g)
+
+
 def test_adjoint_gradient_central_difference_on_gpu():
     """Finite differences of the GPU loss for a few base cells (32^3, s = 3)."""
     torch = _torch()
