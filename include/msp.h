@@ -265,16 +265,22 @@ int msp_refresh(msp_ctx* c, const double* d_val, void* hip_stream);
    re-set-up ones, fetched from the device -- and whose levels below it are built
    afresh on the host from c's level-1 operator (eq. (3.15)), as msp_setup builds
    them: standard splits, smoother and interpolation patterns, Galerkin products,
-   per-subsystem values, coarsest inverses; then uploaded to c's device with new
-   low-rank corrections. For re-set-up contexts whose coarser splits have moved
-   (msp_stats.split_drift1) and cost iterations; it skips the reduction level's
-   split and products but repeats the rest of the host setup, per-subsystem
-   values included. c stays valid and unchanged (its values are only fetched);
-   *out owns its own memory until msp_free. AMGR and
-   per-subsystem AMGR contexts of two or more levels, domains of copies included;
-   MSP_ERR_UNSUPPORTED for other preconditioners, MSP_ERR_ARG after a failed
-   re-setup of c or for a null argument. */
-int msp_rebuild_below(msp_ctx* c, msp_ctx** out);
+   coarsest inverses. For re-set-up contexts whose coarser splits have moved
+   (msp_stats.split_drift1) and cost iterations.
+   d_val NULL: the per-subsystem values are computed on the host too, then the
+   context is uploaded with new low-rank corrections (c's device; none for a
+   host-only c). d_val non-NULL: the device values of the matrix c was last set
+   up or re-set up for (msp_refresh's d_val, CSR order of the setup matrix, FP64);
+   the new context is uploaded and re-set up from them on the device
+   (msp_refresh: every value, the per-subsystem ones and the corrections
+   included), work enqueued on hip_stream, the call returning when it is done;
+   the host then skips the per-subsystem values, the costly part of the rebuild.
+   c stays valid and unchanged (its values are only fetched); *out owns its own
+   memory until msp_free. AMGR and per-subsystem AMGR contexts of two or more
+   levels, domains of copies included; MSP_ERR_UNSUPPORTED for other
+   preconditioners and for d_val with the BF16-G variant, MSP_ERR_ARG after a
+   failed re-setup of c, for d_val with a host-only c or a null argument. */
+int msp_rebuild_below(msp_ctx* c, const double* d_val, void* hip_stream, msp_ctx** out);
 
 /* Solve for m right-hand sides held in device memory (d_b, d_x: n x m
    column-major FP64, on the context's device), enqueued on hip_stream (NULL

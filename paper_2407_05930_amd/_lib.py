@@ -81,7 +81,7 @@ SIGNATURES = {
     "msp_setup": (ctypes.c_int, [_P(msp_csr), _P(msp_symmap), _P(msp_opts), _P(_vp)]),
     "msp_setup_copies": (ctypes.c_int, [_P(msp_csr), _P(msp_copies), _P(msp_opts), _P(_vp)]),
     "msp_refresh": (ctypes.c_int, [_vp, _vp, _vp]),
-    "msp_rebuild_below": (ctypes.c_int, [_vp, _P(_vp)]),
+    "msp_rebuild_below": (ctypes.c_int, [_vp, _vp, _vp, _P(_vp)]),
     "msp_export_amgs": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_int64),
                                        _P(ctypes.c_int64), _vp, _vp, _vp]),
     "msp_solve_device": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _P(msp_stats)]),

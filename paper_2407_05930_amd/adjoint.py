@@ -169,7 +169,7 @@ class DifferentiablePoisson:
                      and st.split_drift1 > self.max_split_drift1 * st.rows[1])
             fresh = over0 or over1
             if over1 and not over0 and self.drift1_action == "rebuild_below":
-                self.solver.rebuild_below()
+                self.solver.rebuild_below(self._vals)
                 self.rebuilds += 1
                 self._fresh_iters = None
                 self._base_version = self.solver.version

@@ -1933,8 +1933,9 @@ static std::unique_ptr<msp_ctx> setup_host_copies(const msp_csr* A, const msp_co
 
 // Host part of a rebuild below the reduction level: the blocks and the reduction
 // level of `old` with its current values (after a device re-setup: fetched), every
-// level below built afresh from its level-1 operator, per-subsystem values too.
-static std::unique_ptr<msp_ctx> setup_host_below(msp_ctx* old) {
+// level below built afresh from its level-1 operator; the per-subsystem values too,
+// or (sub_later) the shared ones in their place, for a device re-setup to replace.
+static std::unique_ptr<msp_ctx> setup_host_below(msp_ctx* old, bool sub_later) {
     if (old->values_invalid) throw Error(MSP_ERR_ARG, "the context's values are invalid (a re-setup failed)");
     if (old->o.pc != MSP_PC_AMGR && old->o.pc != MSP_PC_AMGR_SUB)
         throw Error(MSP_ERR_UNSUPPORTED, "a rebuild below the reduction level needs an AMGR context");
@@ -1948,7 +1949,8 @@ static std::unique_ptr<msp_ctx> setup_host_below(msp_ctx* old) {
     c->copies = old->copies;
     c->hier = msp::build_hierarchy_below(old->hier, c->o);
     if (old->sub) {
-        c->subv = msp::build_sub_values(c->hier, c->sym.sigma, c->sym.iface, 1 << c->sym.s, c->o);
+        c->subv = sub_later ? msp::replicated_sub_values(c->hier, 1 << c->sym.s)
+                            : msp::build_sub_values(c->hier, c->sym.sigma, c->sym.iface, 1 << c->sym.s, c->o);
         c->sub = true;
     }
     msp::fill_stats(c.get());
@@ -2197,14 +2199,28 @@ int msp_setup(const msp_csr* A, const msp_symmap* map, const msp_opts* o, msp_ct
     });
 }
 
-int msp_rebuild_below(msp_ctx* c, msp_ctx** out) {
+int msp_rebuild_below(msp_ctx* c, const double* d_val, void* hip_stream, msp_ctx** out) {
     return guarded([&]() -> int {
         if (!out) throw Error(MSP_ERR_ARG, "null output");
         *out = nullptr;
         if (!c) throw Error(MSP_ERR_ARG, "null context");
+        if (d_val && !c->on_device) throw Error(MSP_ERR_ARG, "device values for a context without a device");
+        if (d_val && c->o.precision == MSP_MIXED_FP32_BF16G)
+            throw Error(MSP_ERR_UNSUPPORTED, "the re-setup of the BF16-G variant");
         const auto t0 = std::chrono::steady_clock::now();
-        std::unique_ptr<msp_ctx> n = setup_host_below(c);
-        if (n->o.device >= 0) setup_device(n.get());
+        std::unique_ptr<msp_ctx> n = setup_host_below(c, d_val != nullptr);
+        if (n->o.device >= 0 && d_val) {
+            // upload without corrections; the device re-setup then computes every value
+            // (per-subsystem ones included) and the corrections from the caller's matrix
+            const int k = n->lrc_k;
+            n->lrc_k = 0;
+            setup_device(n.get());
+            n->lrc_k = k;
+            msp::refresh_device(n.get(), d_val, static_cast<hipStream_t>(hip_stream));
+            msp::fill_stats(n.get());
+        } else if (n->o.device >= 0) {
+            setup_device(n.get());
+        }
         const auto t1 = std::chrono::steady_clock::now();
         n->stats.t_setup_s = std::chrono::duration<double>(t1 - t0).count();
         *out = n.release();

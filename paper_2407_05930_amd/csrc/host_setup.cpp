@@ -1365,6 +1365,39 @@ AmgsParts build_amgs(SymParts& sym, const msp_opts& o) {
     return P;
 }
 
+SubValues replicated_sub_values(const HostHierarchy& H, int S) {
+    SubValues V;
+    V.S = S;
+    const int L = static_cast<int>(H.lev.size());
+    if (L < 2) return V;
+    auto rep = [S](const std::vector<double>& v) {
+        std::vector<double> out(v.size() * S);
+        for (size_t k = 0; k < v.size(); ++k)
+            for (int a = 0; a < S; ++a) out[k * S + a] = v[k];
+        return out;
+    };
+    V.A.assign(L, {});
+    V.P.assign(L, {});
+    V.R.assign(L, {});
+    V.M.assign(L, {});
+    V.G.assign(L, {});
+    V.omega.assign(L, std::vector<double>(S, 0.0));
+    for (int l = 1; l < L; ++l) {
+        V.A[l] = rep(H.lev[l].A.v);
+        if (l + 1 < L) {
+            V.P[l] = rep(H.lev[l].P.v);
+            V.R[l] = rep(H.lev[l].R.v);
+            V.M[l] = rep(H.lev[l].M.v);
+            V.G[l] = rep(H.lev[l].G.v);
+            V.omega[l].assign(S, H.lev[l].omega);
+        }
+    }
+    const size_t nn = H.coarse_inv.size();
+    V.coarse_inv.resize(nn * S);
+    for (int a = 0; a < S; ++a) std::copy(H.coarse_inv.begin(), H.coarse_inv.end(), V.coarse_inv.begin() + a * nn);
+    return V;
+}
+
 SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& sigma, const std::vector<int8_t>& iface,
                            int S, const msp_opts& o) {
     SubValues V;

@@ -65,6 +65,9 @@ struct SubValues {
 // standard levels with the shared splits and patterns.
 SubValues build_sub_values(const HostHierarchy& H, const std::vector<double>& sigma,
                            const std::vector<int8_t>& iface, int S, const msp_opts& o);
+// Every subsystem holding the shared levels' values (the layout of build_sub_values):
+// storage for values that a device re-setup computes afterwards.
+SubValues replicated_sub_values(const HostHierarchy& H, int S);
 
 // Result of block extraction (Sec. 2).
 struct SymParts {

@@ -115,14 +115,24 @@ class Solver:
         self.version += 1
         check(lib.msp_refresh(self._ctx, ctypes.c_void_p(values.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
 
-    def rebuild_below(self):
+    def rebuild_below(self, values=None, stream=None):
         """Rebuild every level below the reduction level on the host from the
         current level-1 operator (msp_rebuild_below): for a solver whose
         re-setups have moved the coarser splits (``stats.split_drift1``).  The
         reduction level, with its current values, is kept; the solver then
-        holds the new context (``version`` is incremented, as by refresh)."""
+        holds the new context (``version`` is incremented, as by refresh).
+        ``values``: the float64 CUDA tensor of the last refresh (or of the
+        setup matrix), from which the device computes the per-subsystem
+        values and the corrections instead of the host."""
         new = ctypes.c_void_p()
-        check(lib.msp_rebuild_below(self._ctx, ctypes.byref(new)))
+        vp, sp = None, None
+        if values is not None:
+            import torch
+            if values.dtype != torch.float64 or not values.is_cuda or not values.is_contiguous():
+                raise ValueError("values must be a contiguous float64 CUDA tensor")
+            st = stream if stream is not None else torch.cuda.current_stream(values.device)
+            vp, sp = ctypes.c_void_p(values.data_ptr()), ctypes.c_void_p(st.cuda_stream)
+        check(lib.msp_rebuild_below(self._ctx, vp, sp, ctypes.byref(new)))
         lib.msp_free(self._ctx)
         self._ctx = new
         self.version += 1

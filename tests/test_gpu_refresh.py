@@ -448,18 +448,21 @@ def test_split_drift_is_not_reported_for_domains_of_copies():
     assert sv.stats.split_drift == -1
 
 
-@pytest.mark.parametrize("pc,k,f3", [("amgr", 0, False), ("amgr_sub", 0, False), ("amgr_sub", 4, True)])
-def test_rebuild_below_after_a_refresh_matches_the_oracle(pc, k, f3):
+@pytest.mark.parametrize("pc,k,f3,dev", [("amgr", 0, False, False), ("amgr_sub", 0, False, False),
+                                         ("amgr_sub", 4, True, False), ("amgr_sub", 0, False, True),
+                                         ("amgr_sub", 4, True, True)])
+def test_rebuild_below_after_a_refresh_matches_the_oracle(pc, k, f3, dev):
     """Device re-setup for a new kappa, then msp_rebuild_below: the reduction
     level is the re-set-up one and every level below is built afresh from its
     A_1, as the oracle's rebuild_below of its re-setup does (patterns and
     splits bit for bit, values to the tolerance of the re-setup tests); the
     solve then has the oracle's iteration count with x within 1e-9, and a
     re-setup with the same values finds level 1's split where the rebuild put
-    it (split_drift1 = 0)."""
+    it (split_drift1 = 0).  dev: the per-subsystem values and corrections are
+    computed by a device re-setup from the matrix values instead of the host."""
     torch = _torch()
     from paper_2407_05930_amd import Solver
-    _say("rebuild below", pc, k, f3)
+    _say("rebuild below", pc, k, f3, dev)
     kw = dict(y_stretch=1.5, kappa="lognormal")
     p0 = make_problem((28, 24, 20), s=2, m=1, seed=101, **kw)
     p1 = make_problem((28, 24, 20), s=2, m=1, seed=102, **kw)
@@ -470,8 +473,11 @@ def test_rebuild_below_after_a_refresh_matches_the_oracle(pc, k, f3):
     vals = torch.from_numpy(p1.A.data).cuda()
     sv.refresh(vals)
     assert sv.stats.split_drift1 > 0
-    sv.rebuild_below()
-    assert sv.stats.split_drift == -1 and sv.stats.split_drift1 == -1
+    sv.rebuild_below(vals if dev else None)
+    if dev:
+        assert sv.stats.split_drift1 == 0     # the rebuilt split is that of these values
+    else:
+        assert sv.stats.split_drift == -1 and sv.stats.split_drift1 == -1
     ctx0 = krylov.setup(p0.A, p0.img, amg.AMGOptions(**opt), precond=pc, k=k)
     ref = refresh.rebuild_below(refresh.refresh(ctx0, p1.A))
     _check_levels(sv, ref["hier"], ref["sub"], base=1e-11)
@@ -518,7 +524,7 @@ def test_rebuild_below_of_copies_and_in_mixed_precision():
     sm = Solver(q0.A, q0.img, tol=1e-10, pc="amgr_sub", k=4, precision="mixed_bf16", **opt)
     vq = torch.from_numpy(q1.A.data).cuda()
     sm.refresh(vq)
-    sm.rebuild_below()
+    sm.rebuild_below(vq)
     y = sm.solve(torch.from_numpy(q1.b).cuda()).cpu().numpy()
     ref = krylov.solve(refresh.rebuild_below(refresh.refresh(
         krylov.setup(q0.A, q0.img, amg.AMGOptions(**opt), precond="amgr_sub"), q1.A)), q1.b, tol=1e-12)

@@ -62,6 +62,17 @@ def test_rebuild_of_a_domain_of_copies_reproduces_it():
     _identical(e0, _exports(sv, False))
 
 
+def test_rebuild_with_device_values_needs_a_device_context():
+    import ctypes
+    from paper_2407_05930_amd import Solver, _lib
+    p = make_problem((12, 10, 8), s=2, m=1, seed=66)
+    sv = Solver(p.A, p.img, device=-1, coarse_max=32)
+    out = ctypes.c_void_p()
+    assert _lib.lib.msp_rebuild_below(sv._ctx, ctypes.c_void_p(16), None, ctypes.byref(out)) == -1
+    assert "device" in _lib.lib.msp_last_error().decode() and not out.value
+    assert _lib.lib.msp_rebuild_below(sv._ctx, None, None, None) == -1
+
+
 def test_rebuild_rejects_what_it_cannot_rebuild():
     from paper_2407_05930_amd import MspError, Solver
     p = make_problem((12, 10, 8), s=2, m=1, seed=65)
