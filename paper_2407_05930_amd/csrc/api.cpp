@@ -2763,6 +2763,17 @@ static std::vector<int64_t> outer_sources(const std::vector<double>& dense, int6
 }
 
 static void refresh_build(msp_ctx* c) {
+    // MSP_SETUP_LOG set (non-empty, not "0"): seconds per phase to stderr
+    const char* logv = std::getenv("MSP_SETUP_LOG");
+    const bool tlog = logv && *logv && std::strcmp(logv, "0") != 0;
+    auto clk = std::chrono::steady_clock::now();
+    auto lap = [&](const char* what, long l) {
+        if (!tlog) return;
+        const auto t = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "msp re-setup structure: %s %ld %.3f s\n", what, l,
+                     std::chrono::duration<double>(t - clk).count());
+        clk = t;
+    };
     std::unique_ptr<RefreshState> R(new RefreshState());
     const int S = 1 << c->sym.s;
     const int64_t nb = c->sym.n_b;
@@ -2818,6 +2829,7 @@ static void refresh_build(msp_ctx* c) {
                        H1.cf, true);
         }
     }
+    lap("sources and split checks", -1);
     R->part = c->dalloc<double>(2 * R->nbp);
     R->dots = c->dalloc<double>(2);
     if (cycle(c)) {
@@ -2843,8 +2855,10 @@ static void refresh_build(msp_ctx* c) {
             F.R = dev_pat(D.R);
             const std::vector<int64_t> rs = transpose_map(H.P);
             F.r_src = c->upload(rs.data(), static_cast<int64_t>(rs.size()));
+            lap("patterns and transposes, level", static_cast<long>(l));
             const int steps = l == 0 ? c->o.jacobi0 : c->o.jacobi;
             const std::vector<Csr> Ws = interpolation_patterns(H.A, H.cf, steps);
+            lap("interpolation patterns, level", static_cast<long>(l));
             for (const Csr& W : Ws) {
                 F.W.push_back(upload_pat(c, W));
                 F.w.push_back(c->dalloc<double>(W.nnz()));
@@ -2887,9 +2901,12 @@ static void refresh_build(msp_ctx* c) {
             F.cnum = c->upload(cnum.data(), F.n);
             F.fnum = c->upload(fnum.data(), F.n);
             F.cf = c->upload(H.cf.data(), F.n);
+            lap("interpolation maps, level", static_cast<long>(l));
             F.AP = upload_pat(c, spgemm(H.A, H.P));
+            lap("AP pattern, level", static_cast<long>(l));
             int64_t wk = 0;
             F.woff = fsai_offsets(c, H.G, &wk);
+            lap("FSAI offsets, level", static_cast<long>(l));
             work = std::max(work, wk);
             std::vector<double> v0(F.n);
             double nrm = 0.0;
@@ -2995,6 +3012,7 @@ static void refresh_build(msp_ctx* c) {
         R->gf_woff = fsai_offsets(c, c->Gf, &wk);
         R->work = c->dalloc<double>(std::max<int64_t>(1, wk));
     }
+    lap("rest", -1);
     c->rf = std::move(R);
 }
 
@@ -3118,7 +3136,18 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
     if (c->o.pc == MSP_PC_AMGS) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup of AMGS");
     if (c->o.precision == MSP_MIXED_FP32_BF16G) throw Error(MSP_ERR_UNSUPPORTED, "the re-setup of the BF16-G variant");
     HIPCHECK(hipSetDevice(c->device));
+    const char* logv = std::getenv("MSP_SETUP_LOG");
+    const bool tlog = logv && *logv && std::strcmp(logv, "0") != 0;
+    auto clk = std::chrono::steady_clock::now();
+    auto lap = [&](const char* what) {
+        if (!tlog) return;
+        HIPCHECK(hipStreamSynchronize(st));
+        const auto t = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "msp re-setup: %s %.3f s\n", what, std::chrono::duration<double>(t - clk).count());
+        clk = t;
+    };
     if (!c->rf) refresh_build(c);
+    lap("structure");
     RefreshState& R = *c->rf;
     c->values_invalid = true;   // until this re-setup completes
     const int S = 1 << c->sym.s;
@@ -3197,6 +3226,7 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
                 HIPCHECK(hipMemcpyAsync(c->d_cinv, R.dense, sizeof(double) * S * nL * nL, hipMemcpyDeviceToDevice, st));
             }
         }
+        lap("levels");
         // FP32 copies of the level matrices (mixed modes) and the sliced forms in use
         for (DevLevel& D : c->dl)
             for (DevCsr* M : {&D.A, &D.P, &D.R, &D.M}) {
@@ -3209,6 +3239,7 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
         HIPCHECK(launch_gather(st, R.gftp.nnz, R.gft_src, c->dGf.v64, c->dGfT.v64));
     }
     refresh_sells(c, c->dAinn, st);
+    lap("copies and sliced forms");
     int err = 0;
     HIPCHECK(hipMemcpyAsync(&err, R.err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
@@ -3224,6 +3255,7 @@ void refresh_device(msp_ctx* c, const double* d_val, hipStream_t st) {
         c->d_U = nullptr;
         c->d_lrc_coef = c->d_lrc_part = c->d_lrc_W = nullptr;
         build_lrc(c);
+        lap("corrections");
     }
     HIPCHECK(hipDeviceSynchronize());
     c->values_invalid = false;
