@@ -62,6 +62,20 @@ def test_rebuild_of_a_domain_of_copies_reproduces_it():
     _identical(e0, _exports(sv, False))
 
 
+@pytest.mark.parametrize("pc", ["amgr", "amgr_sub"])
+def test_rebuild_of_a_two_level_setup_reproduces_it(pc):
+    """With two levels the level below the reduction level is the coarsest
+    one, which the rebuild only recomputes (its dense inverses too)."""
+    from paper_2407_05930_amd import Solver
+    p = make_problem((12, 10, 8), s=2, m=1, seed=67, kappa="lognormal")
+    sv = Solver(p.A, p.img, device=-1, pc=pc, coarse_max=200)
+    assert sv.num_levels() == 2
+    e0 = _exports(sv, pc == "amgr_sub")
+    sv.rebuild_below()
+    assert sv.num_levels() == 2
+    _identical(e0, _exports(sv, pc == "amgr_sub"))
+
+
 def test_rebuild_with_device_values_needs_a_device_context():
     import ctypes
     from paper_2407_05930_amd import Solver, _lib
