@@ -533,3 +533,25 @@ def test_rebuild_below_of_copies_and_in_mixed_precision():
     assert np.linalg.norm(y - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
     sm.refresh(vq)
     assert sm.stats.split_drift1 == 0
+
+
+@pytest.mark.parametrize("dev", [False, True])
+def test_rebuild_below_of_a_two_level_hierarchy(dev):
+    """Two levels: the rebuild only recomputes the coarsest operators and
+    their inverses; the solve after a re-setup and a rebuild reaches the
+    direct solution."""
+    torch = _torch()
+    from paper_2407_05930_amd import Solver
+    _say("rebuild two levels", dev)
+    kw = dict(kappa="lognormal")
+    p0 = make_problem((12, 10, 8), s=2, m=1, seed=105, **kw)
+    p1 = make_problem((12, 10, 8), s=2, m=1, seed=106, **kw)
+    sv = Solver(p0.A, p0.img, tol=TOL, pc="amgr_sub", coarse_max=200, k=2)
+    assert sv.num_levels() == 2
+    vals = torch.from_numpy(p1.A.data).cuda()
+    sv.refresh(vals)
+    sv.rebuild_below(vals if dev else None)
+    assert sv.num_levels() == 2
+    x = sv.solve(torch.from_numpy(p1.b).cuda()).cpu().numpy()
+    xd = spla.splu(p1.A.tocsc()).solve(p1.b)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
